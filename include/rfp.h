@@ -1,0 +1,145 @@
+/*
+ * rfp.h -- C ABI of the MI355X (gfx950) library for Cholesky factorization,
+ * solution and inversion of a symmetric positive definite matrix held in
+ * Rectangular Full Packed Format (Gustavson, Wasniewski, Dongarra, Langou,
+ * "Rectangular Full Packed Format for Cholesky's Algorithm: Factorization,
+ * Solution and Inversion").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - RFP array (arf): n(n+1)/2 entries, device memory, in one of the eight
+ *    layouts selected by TRANSR ('N' or 'T') and UPLO ('L' or 'U'), exactly
+ *    as defined in Section 2 and drawn in Figures 4-6 (the parity of n is the
+ *    third selector).  Characters are case-insensitive.
+ *  - Full matrices and right-hand sides are column-major device arrays with a
+ *    leading dimension (lda, ldb >= max(1, n)).
+ *  - All sizes are int64_t.  n = 0 (or nrhs = 0) returns 0 immediately.
+ *  - Ownership: the caller allocates and owns every array.  The handle owns
+ *    only scratch memory (leaf inverses, split-K partial sums, low-precision
+ *    copies), grown on demand; a grow waits for the device to go idle.
+ *  - Streams: work is enqueued on `stream` (NULL = the default stream) and the
+ *    call returns without waiting, except where a routine says otherwise.
+ *    One handle must not be used by two streams or threads at once.
+ *  - Return value: 0 on success; -i when argument i (counted in the paper's
+ *    argument order for that routine, given with each routine) is illegal,
+ *    in which case nothing is enqueued; RFP_ERR_HANDLE for a bad handle;
+ *    RFP_ERR_RUNTIME when the HIP runtime reports an error.
+ *  - Numerical status (INFO) is written to a device int so that no call has
+ *    to synchronise; read it after the stream has finished.
+ */
+#ifndef RFP_MI355X_H
+#define RFP_MI355X_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RFP_ERR_HANDLE (-101)
+#define RFP_ERR_RUNTIME (-102)
+
+typedef struct rfp_context* rfp_handle_t;
+
+/* Create a handle bound to HIP device `device` (scratch memory is allocated
+ * lazily on that device).  Returns 0, -1 (h is NULL), -2 (bad device) or
+ * RFP_ERR_RUNTIME. */
+int rfp_create(rfp_handle_t* h, int device);
+
+/* Release the handle and its scratch memory (waits for the device). */
+int rfp_destroy(rfp_handle_t h);
+
+/* TRTTF (the paper's table of LAPACK 3.2 RFP routines, "Conv. from TR to
+ * TF"): copy the UPLO triangle of the full n x n matrix a (column-major,
+ * lda >= max(1,n)) into the RFP array arf of layout (transr, uplo).  The other
+ * triangle of a is not read.  Argument order: TRANSR=1, UPLO=2, N=3, A=4,
+ * LDA=5, ARF=6. */
+int rfp_dtrttf(rfp_handle_t h, char transr, char uplo, int64_t n, const double* a, int64_t lda, double* arf,
+               hipStream_t stream);
+
+/* TFTTR ("Conv. from TF to TR"): copy the RFP array into the UPLO triangle of
+ * the full matrix a; the other triangle of a is left untouched.  Argument
+ * order: TRANSR=1, UPLO=2, N=3, ARF=4, A=5, LDA=6. */
+int rfp_dtfttr(rfp_handle_t h, char transr, char uplo, int64_t n, const double* arf, double* a, int64_t lda,
+               hipStream_t stream);
+
+/* PFTRF (Section 3, Figure 4 "Cholesky Factorization Algorithm"): A = L L^T
+ * (UPLO='L') or A = U^T U (UPLO='U'); the factor overwrites arf in the same
+ * layout.  *info (device int) becomes 0 on success or p > 0 when the leading
+ * minor of order p (in the order of A) is not positive definite; the
+ * factorization then stops and arf is partly overwritten.  Argument order:
+ * TRANSR=1, UPLO=2, N=3, A=4, INFO=5. */
+int rfp_dpftrf(rfp_handle_t h, char transr, char uplo, int64_t n, double* arf, int* info, hipStream_t stream);
+
+/* PFTRS (Section 4, Figure 4 "Cholesky Solution Algorithm"): solve A X = B
+ * with the PFTRF factor in arf; X overwrites b (n x nrhs, column-major,
+ * ldb >= max(1,n)).  arf is only read.  Argument order: TRANSR=1, UPLO=2,
+ * N=3, NR=4, A=5, B=6, LDB=7. */
+int rfp_dpftrs(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, const double* arf, double* b,
+               int64_t ldb, hipStream_t stream);
+
+/* PFTRI (Section 5, Figure 4 "Cholesky Inversion Algorithm"): from the PFTRF
+ * factor, overwrite arf with the same triangle of A^{-1} in the same layout
+ * (W = L^{-1} by TRTRI/TRMM on the three blocks, then W^T W by LAUUM, SYRK and
+ * TRMM).  *info (device int) becomes 0, or i > 0 when the factor's diagonal
+ * entry i is exactly zero.  Argument order: TRANSR=1, UPLO=2, N=3, A=4,
+ * INFO=5. */
+int rfp_dpftri(rfp_handle_t h, char transr, char uplo, int64_t n, double* arf, int* info, hipStream_t stream);
+
+/* Single-precision counterparts (SPFTRF / SPFTRS / STRTTF / STFTTR in the
+ * paper's routine table); same arguments and semantics with float arrays. */
+int rfp_strttf(rfp_handle_t h, char transr, char uplo, int64_t n, const float* a, int64_t lda, float* arf,
+               hipStream_t stream);
+int rfp_stfttr(rfp_handle_t h, char transr, char uplo, int64_t n, const float* arf, float* a, int64_t lda,
+               hipStream_t stream);
+int rfp_spftrf(rfp_handle_t h, char transr, char uplo, int64_t n, float* arf, int* info, hipStream_t stream);
+int rfp_spftrs(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, const float* arf, float* b,
+               int64_t ldb, hipStream_t stream);
+int rfp_spftri(rfp_handle_t h, char transr, char uplo, int64_t n, float* arf, int* info, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Plan introspection (host only, touches no device).
+ * The drivers are the paper's 2 x 2 block algorithms (Figure 3, Sections 3-5)
+ * applied recursively; rfp_plan records the sequence of primitives that
+ * rfp_dpftrf ('F'), rfp_dpftrs ('S') or rfp_dpftri ('I') would enqueue for
+ * the given arguments, without launching anything, so that the block
+ * algebra, the views into the RFP rectangle and the aliasing rules can be
+ * checked on a machine without a GPU.  Each record names views as (buffer,
+ * element offset, row stride, column stride) with buffer one of the
+ * RFP_PLAN_BUF_* values.  Primitive semantics:
+ *   RFP_PLAN_GEMM: C(m x n) = alpha * A(m x k) * B(n x k)^T + beta * C, with
+ *     A and B masked by tri_a / tri_b (0 none, 1 lower i >= j, 2 upper
+ *     i <= j, 3 strictly lower, 4 strictly upper, in the operand's own
+ *     indices) and, when c_lower, only C's lower triangle computed.
+ *   RFP_PLAN_POTRF_LEAF: Cholesky of the lower triangle of a (order m); the
+ *     leaf's inverse goes to view b (row-major NB x NB); INFO base info_base.
+ *   RFP_PLAN_TRTRI_LEAF: in-place inverse of the lower triangle of a.
+ *   RFP_PLAN_TRTRI_LEAVES: inverses of all 64-row diagonal blocks of the lower
+ *     triangular a (order m) into consecutive NB x NB row-major blocks at b.
+ *   RFP_PLAN_LAUUM_LEAF: lower triangle of W^T W in place (order m).
+ * *count receives the number of records (even beyond cap).  Returns 0, -1 for
+ * an unknown routine, -8 for bad output arguments, or the routine's own
+ * argument error code. */
+enum {
+    RFP_PLAN_GEMM = 1,
+    RFP_PLAN_POTRF_LEAF = 2,
+    RFP_PLAN_TRTRI_LEAF = 3,
+    RFP_PLAN_TRTRI_LEAVES = 4,
+    RFP_PLAN_LAUUM_LEAF = 5
+};
+enum { RFP_PLAN_BUF_ARF = 0, RFP_PLAN_BUF_B = 1, RFP_PLAN_BUF_WORK = 2, RFP_PLAN_BUF_INFO = 3 };
+typedef struct {
+    int32_t kind, tri_a, tri_b, c_lower;
+    int64_t m, n, k;
+    double alpha, beta;
+    int64_t a[4], b[4], c[4]; /* buffer (-1: unused), offset, row stride, column stride */
+    int64_t info_base;
+} rfp_plan_op;
+int rfp_plan(char routine, char transr, char uplo, int64_t n, int64_t nrhs, int64_t ldb, rfp_plan_op* ops,
+             int64_t cap, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RFP_MI355X_H */

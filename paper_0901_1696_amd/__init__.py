@@ -1,0 +1,213 @@
+"""Python binding of the MI355X RFP Cholesky library (``librfp.so``).
+
+Argument marshalling only: every routine forwards torch device tensors (their
+data pointers) and the current HIP stream to the C ABI declared in
+``include/rfp.h``; all arithmetic happens in the library's HIP kernels.  There
+is no fallback path: if the library is not built, loading fails loudly.
+
+Array conventions (as in the C ABI):
+  * RFP arrays: 1-D contiguous tensors of at least n(n+1)/2 entries.
+  * Full matrices and right-hand sides: column-major, i.e. a 2-D tensor with
+    ``stride(0) == 1`` (e.g. ``x.t().contiguous().t()``), leading dimension
+    ``stride(1)``; a contiguous 1-D tensor is one column.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librfp.so")
+
+RFP_ERR_HANDLE = -101
+RFP_ERR_RUNTIME = -102
+LAYOUTS = [(t, u) for t in "NT" for u in "LU"]
+
+_lib = None
+
+
+class RfpError(RuntimeError):
+    def __init__(self, routine, code):
+        self.code = code
+        what = {RFP_ERR_HANDLE: "bad handle", RFP_ERR_RUNTIME: "HIP runtime error"}.get(
+            code, f"illegal argument {-code}" if code < 0 else f"status {code}")
+        super().__init__(f"{routine}: {what} (return code {code})")
+
+
+_i64 = ctypes.c_int64
+_chr = ctypes.c_char
+_vp = ctypes.c_void_p
+_int = ctypes.c_int
+
+_SIGS = {
+    "rfp_create": [ctypes.POINTER(_vp), _int],
+    "rfp_destroy": [_vp],
+    "rfp_dtrttf": [_vp, _chr, _chr, _i64, _vp, _i64, _vp, _vp],
+    "rfp_dtfttr": [_vp, _chr, _chr, _i64, _vp, _vp, _i64, _vp],
+    "rfp_dpftrf": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
+    "rfp_dpftrs": [_vp, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp],
+    "rfp_dpftri": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
+    "rfp_strttf": [_vp, _chr, _chr, _i64, _vp, _i64, _vp, _vp],
+    "rfp_stfttr": [_vp, _chr, _chr, _i64, _vp, _vp, _i64, _vp],
+    "rfp_spftrf": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
+    "rfp_spftrs": [_vp, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp],
+    "rfp_spftri": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
+    "rfp_plan": [_chr, _chr, _chr, _i64, _i64, _i64, _vp, _i64, ctypes.POINTER(_i64)],
+}
+
+PLAN_GEMM, PLAN_POTRF_LEAF, PLAN_TRTRI_LEAF, PLAN_TRTRI_LEAVES, PLAN_LAUUM_LEAF = 1, 2, 3, 4, 5
+PLAN_BUF_ARF, PLAN_BUF_B, PLAN_BUF_WORK = 0, 1, 2
+
+
+class PlanOp(ctypes.Structure):
+    """One record of ``rfp_plan`` (layout of ``rfp_plan_op`` in include/rfp.h)."""
+    _fields_ = [("kind", ctypes.c_int32), ("tri_a", ctypes.c_int32), ("tri_b", ctypes.c_int32),
+                ("c_lower", ctypes.c_int32), ("m", _i64), ("n", _i64), ("k", _i64),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("a", _i64 * 4), ("b", _i64 * 4), ("c", _i64 * 4), ("info_base", _i64)]
+
+
+def exported_symbols():
+    """Names the C ABI exports (the declarations of include/rfp.h)."""
+    return list(_SIGS)
+
+
+def lib():
+    """Load ``librfp.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_0901_1696_amd.build` "
+                               "(or __graft_entry__.build()) first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = _int
+        _lib = L
+    return _lib
+
+
+def nt(n):
+    return n * (n + 1) // 2
+
+
+def _c(ch):
+    return ch.encode() if isinstance(ch, str) else ch
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _colmajor(x, name):
+    """(pointer, leading dimension, ncols) of a column-major tensor."""
+    if x.dim() == 1:
+        if not x.is_contiguous():
+            raise ValueError(f"{name}: 1-D tensor must be contiguous")
+        return x.data_ptr(), max(1, x.shape[0]), 1
+    if x.dim() != 2 or (x.stride(0) != 1 and x.shape[0] > 1):
+        raise ValueError(f"{name}: expected a column-major 2-D tensor (stride(0) == 1)")
+    return x.data_ptr(), max(1, x.stride(1) if x.shape[1] > 1 else x.shape[0]), x.shape[1]
+
+
+def _check(routine, code):
+    if code != 0:
+        raise RfpError(routine, code)
+
+
+class Handle:
+    """Owns an ``rfp_handle_t`` (scratch memory on one device)."""
+
+    def __init__(self, device=0):
+        h = _vp()
+        _check("rfp_create", lib().rfp_create(ctypes.byref(h), int(device)))
+        self._h = h
+        self.device = device
+
+    @property
+    def value(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().rfp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rfp_plan(routine, transr, uplo, n, nrhs=0, ldb=None):
+    """Primitive sequence of PFTRF ('F'), PFTRS ('S') or PFTRI ('I'), recorded
+    on the host without touching a device (see include/rfp.h)."""
+    ldb = max(1, n) if ldb is None else ldb
+    count = _i64(0)
+    rc = lib().rfp_plan(_c(routine), _c(transr), _c(uplo), n, nrhs, ldb, None, 0, ctypes.byref(count))
+    if rc != 0:
+        raise RfpError("rfp_plan", rc)
+    ops = (PlanOp * max(1, count.value))()
+    rc = lib().rfp_plan(_c(routine), _c(transr), _c(uplo), n, nrhs, ldb, ops, count.value, ctypes.byref(count))
+    if rc != 0:
+        raise RfpError("rfp_plan", rc)
+    return list(ops)[:count.value]
+
+
+def rfp_dtrttf(h, transr, uplo, n, a, arf, stream=None):
+    pa, lda, _ = _colmajor(a, "a")
+    _check("rfp_dtrttf", lib().rfp_dtrttf(h.value, _c(transr), _c(uplo), n, pa, lda, _ptr(arf), _stream(stream)))
+
+
+def rfp_dtfttr(h, transr, uplo, n, arf, a, stream=None):
+    pa, lda, _ = _colmajor(a, "a")
+    _check("rfp_dtfttr", lib().rfp_dtfttr(h.value, _c(transr), _c(uplo), n, _ptr(arf), pa, lda, _stream(stream)))
+
+
+def rfp_dpftrf(h, transr, uplo, n, arf, info, stream=None):
+    _check("rfp_dpftrf", lib().rfp_dpftrf(h.value, _c(transr), _c(uplo), n, _ptr(arf), _ptr(info),
+                                          _stream(stream)))
+
+
+def rfp_dpftrs(h, transr, uplo, n, arf, b, stream=None):
+    pb, ldb, nrhs = _colmajor(b, "b")
+    _check("rfp_dpftrs", lib().rfp_dpftrs(h.value, _c(transr), _c(uplo), n, nrhs, _ptr(arf), pb, ldb,
+                                          _stream(stream)))
+
+
+def rfp_dpftri(h, transr, uplo, n, arf, info, stream=None):
+    _check("rfp_dpftri", lib().rfp_dpftri(h.value, _c(transr), _c(uplo), n, _ptr(arf), _ptr(info),
+                                          _stream(stream)))
+
+
+def rfp_strttf(h, transr, uplo, n, a, arf, stream=None):
+    pa, lda, _ = _colmajor(a, "a")
+    _check("rfp_strttf", lib().rfp_strttf(h.value, _c(transr), _c(uplo), n, pa, lda, _ptr(arf), _stream(stream)))
+
+
+def rfp_stfttr(h, transr, uplo, n, arf, a, stream=None):
+    pa, lda, _ = _colmajor(a, "a")
+    _check("rfp_stfttr", lib().rfp_stfttr(h.value, _c(transr), _c(uplo), n, _ptr(arf), pa, lda, _stream(stream)))
+
+
+def rfp_spftrf(h, transr, uplo, n, arf, info, stream=None):
+    _check("rfp_spftrf", lib().rfp_spftrf(h.value, _c(transr), _c(uplo), n, _ptr(arf), _ptr(info),
+                                          _stream(stream)))
+
+
+def rfp_spftrs(h, transr, uplo, n, arf, b, stream=None):
+    pb, ldb, nrhs = _colmajor(b, "b")
+    _check("rfp_spftrs", lib().rfp_spftrs(h.value, _c(transr), _c(uplo), n, nrhs, _ptr(arf), pb, ldb,
+                                          _stream(stream)))
+
+
+def rfp_spftri(h, transr, uplo, n, arf, info, stream=None):
+    _check("rfp_spftri", lib().rfp_spftri(h.value, _c(transr), _c(uplo), n, _ptr(arf), _ptr(info),
+                                          _stream(stream)))

@@ -1,0 +1,219 @@
+// Diagonal-block ("leaf") kernels of the recursive RFP algorithms: Cholesky
+// (POTRF, Section 3), triangular inverse (TRTRI, Section 5 stage 2) and the
+// triangular product W^T W (LAUUM, Section 5 stage 3) on blocks of order at
+// most NB = 64.  One wavefront handles one block; rows or columns live in
+// lanes and the block is broadcast through LDS, so the only synchronisation
+// is within the wavefront.  Every store back into the RFP array is masked to
+// the block's own lower triangle: the other triangle of a diagonal block is
+// the other diagonal block's data.
+#include "rfp_common.h"
+
+namespace rfp {
+
+// Cholesky of one leaf.  Lane i holds row i of the block in registers; at step
+// j the pivot column is published in LDS and every lane updates its row:
+// l_jj = sqrt(a_jj), l_ij = a_ij / l_jj, a_ik -= l_ij l_kj (k > j).
+// Then W = L^{-1} by forward substitution, lane c building column c, and W is
+// stored row-major (W(r, c) at winv[r * NB + c]) for the panel TRSM.
+template <typename T>
+__global__ __launch_bounds__(64) void potrf_leaf_kernel(Mat<T> A, int nb, T* winv, int* info, int64_t info_base)
+{
+    if (info && *info) return;
+    const int i = threadIdx.x;
+    __shared__ T col[NB];
+    __shared__ T Ls[NB][NB + 1];
+    __shared__ T rdiag[NB];
+
+    T a[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) a[j] = (i < nb && j <= i) ? A.at(i, j) : (i == j ? T(1) : T(0));
+
+    int fail = 0;
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        T d = T(1);
+        if (j < nb && !fail) {
+            col[i] = a[j];
+            __syncthreads();
+            d = col[j];
+            if (!(d > T(0))) fail = j + 1;
+        }
+        if (j < nb && !fail) {
+            const T l = sqrt(d);
+            const T rl = T(1) / l;
+            const T lij = (i > j) ? a[j] * rl : (i == j ? l : T(0));
+            a[j] = lij;
+            const T t = lij * rl;
+#pragma unroll
+            for (int k = j + 1; k < NB; k++) a[k] -= t * col[k];
+            __syncthreads();
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (fail) {
+        if (i == 0) *info = (int)(info_base + fail);
+        return;
+    }
+    if (i < nb) {
+#pragma unroll
+        for (int j = 0; j < NB; j++)
+            if (j <= i) A.at(i, j) = a[j];
+    }
+    if (!winv) return;
+#pragma unroll
+    for (int j = 0; j < NB; j++) Ls[i][j] = (j <= i) ? a[j] : T(0);
+    __syncthreads();
+    rdiag[i] = T(1) / Ls[i][i];
+    __syncthreads();
+    // lane c: column c of W, rows r = 0..NB-1
+    const int c = i;
+    T w[NB];
+#pragma unroll
+    for (int r = 0; r < NB; r++) {
+        T s = (r == c) ? T(1) : T(0);
+#pragma unroll
+        for (int q = 0; q < r; q++) s -= Ls[r][q] * w[q];
+        w[r] = s * rdiag[r];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int r = 0; r < NB; r++) winv[r * NB + c] = w[r];
+}
+
+// Forward substitution for W = L^{-1} of a block already in LDS; lane c
+// returns column c.  Diagonal entries are inverted once per row.
+template <typename T>
+__device__ __forceinline__ void inv_columns(const T (*Ls)[NB + 1], const T* rdiag, int c, T* w)
+{
+#pragma unroll
+    for (int r = 0; r < NB; r++) {
+        T s = (r == c) ? T(1) : T(0);
+#pragma unroll
+        for (int q = 0; q < r; q++) s -= Ls[r][q] * w[q];
+        w[r] = s * rdiag[r];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// In-place inverse of one lower-triangular leaf (PFTRI stage 2).
+template <typename T>
+__global__ __launch_bounds__(64) void trtri_leaf_kernel(Mat<T> A, int nb, int* info, int64_t info_base)
+{
+    if (info && *info) return;
+    const int i = threadIdx.x;
+    __shared__ T Ls[NB][NB + 1];
+    __shared__ T rdiag[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) Ls[i][j] = (i < nb && j <= i) ? A.at(i, j) : (i == j ? T(1) : T(0));
+    __syncthreads();
+    // first exactly-zero diagonal entry (uniform decision)
+    for (int r = 0; r < nb; r++) {
+        if (Ls[r][r] == T(0)) {
+            if (i == 0) *info = (int)(info_base + r + 1);
+            return;
+        }
+    }
+    rdiag[i] = T(1) / Ls[i][i];
+    __syncthreads();
+    T w[NB];
+    inv_columns<T>(Ls, rdiag, i, w);
+    __syncthreads();
+    // lane c holds column c of W; transpose through LDS, then lane i stores row i
+#pragma unroll
+    for (int r = 0; r < NB; r++) Ls[r][i] = w[r];
+    __syncthreads();
+    if (i < nb) {
+#pragma unroll
+        for (int j = 0; j < NB; j++)
+            if (j <= i) A.at(i, j) = Ls[i][j];
+    }
+}
+
+// Out-of-place inverses of all leaves of a lower-triangular matrix of order n
+// (one wavefront per leaf, blockIdx.x = leaf).  Used by PFTRS.
+template <typename T>
+__global__ __launch_bounds__(64) void trtri_leaves_kernel(Mat<const T> A, int64_t n, T* winv)
+{
+    const int64_t b = blockIdx.x;
+    const int64_t o = b * NB;
+    const int nb = (int)((n - o) < NB ? (n - o) : NB);
+    const int i = threadIdx.x;
+    __shared__ T Ls[NB][NB + 1];
+    __shared__ T rdiag[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++)
+        Ls[i][j] = (i < nb && j <= i) ? A.at(o + i, o + j) : (i == j ? T(1) : T(0));
+    __syncthreads();
+    rdiag[i] = T(1) / Ls[i][i];
+    __syncthreads();
+    T w[NB];
+    inv_columns<T>(Ls, rdiag, i, w);
+    T* out = winv + b * NB * NB;
+#pragma unroll
+    for (int r = 0; r < NB; r++) out[r * NB + i] = w[r];
+}
+
+// In-place lower triangle of W^T W for one leaf: (W^T W)(r, c) =
+// sum_{k >= r} W(k, r) W(k, c) for r >= c; lane c keeps column c of W.
+template <typename T>
+__global__ __launch_bounds__(64) void lauum_leaf_kernel(Mat<T> A, int nb, const int* info)
+{
+    if (info && *info) return;
+    const int i = threadIdx.x;
+    __shared__ T Ls[NB][NB + 1];
+#pragma unroll
+    for (int j = 0; j < NB; j++) Ls[i][j] = (i < nb && j <= i) ? A.at(i, j) : T(0);
+    __syncthreads();
+    const int c = i;
+    T w[NB];
+#pragma unroll
+    for (int k = 0; k < NB; k++) w[k] = Ls[k][c];
+#pragma unroll
+    for (int r = 0; r < NB; r++) {
+        T acc = 0;
+#pragma unroll
+        for (int k = r; k < NB; k++) acc += Ls[k][r] * w[k];
+        if (r >= c && r < nb) A.at(r, c) = acc;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <typename T>
+hipError_t potrf_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info_base)
+{
+    hipLaunchKernelGGL((potrf_leaf_kernel<T>), dim3(1), dim3(64), 0, ex.stream, A, nb, winv, ex.info, info_base);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t trtri_leaf(const Exec& ex, Mat<T> A, int nb, int64_t info_base)
+{
+    hipLaunchKernelGGL((trtri_leaf_kernel<T>), dim3(1), dim3(64), 0, ex.stream, A, nb, ex.info, info_base);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t trtri_leaves(const Exec& ex, Mat<const T> A, int64_t n, T* winv)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t nl = (n + NB - 1) / NB;
+    hipLaunchKernelGGL((trtri_leaves_kernel<T>), dim3((unsigned)nl), dim3(64), 0, ex.stream, A, n, winv);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t lauum_leaf(const Exec& ex, Mat<T> A, int nb)
+{
+    hipLaunchKernelGGL((lauum_leaf_kernel<T>), dim3(1), dim3(64), 0, ex.stream, A, nb, (const int*)ex.info);
+    return hipGetLastError();
+}
+
+#define RFP_LEAF_INST(T)                                                               \
+    template hipError_t potrf_leaf<T>(const Exec&, Mat<T>, int, T*, int64_t);          \
+    template hipError_t trtri_leaf<T>(const Exec&, Mat<T>, int, int64_t);              \
+    template hipError_t trtri_leaves<T>(const Exec&, Mat<const T>, int64_t, T*);       \
+    template hipError_t lauum_leaf<T>(const Exec&, Mat<T>, int);
+RFP_LEAF_INST(double)
+RFP_LEAF_INST(float)
+
+}  // namespace rfp

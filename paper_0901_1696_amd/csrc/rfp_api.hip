@@ -1,0 +1,617 @@
+// Drivers and C ABI of the MI355X RFP Cholesky library.
+//
+// The paper's simple related partition algorithm (Figure 3) splits the RFP
+// array into T1 (A11), S (A21) and T2 (A22) and runs four full-format steps.
+// Here the same 2 x 2 partition is applied recursively: the top level is the
+// RFP split itself, and every step on T1 or T2 (POTRF, TRSM, TRTRI, TRMM,
+// LAUUM) splits its triangle again at a multiple of NB until the diagonal
+// blocks fit one wavefront.  All off-diagonal work therefore lands in large
+// GEMM-shaped products on the matrix cores, with the operands read in place
+// from the RFP rectangle through strided views.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "rfp.h"
+#include "rfp_common.h"
+
+struct rfp_context {
+    int device;
+    void* splitk;
+    size_t splitk_bytes;
+    void* inv;
+    size_t inv_bytes;
+};
+
+namespace rfp {
+
+static int upc(char c) { return (c >= 'a' && c <= 'z') ? c - 'a' + 'A' : c; }
+
+// Layout descriptor (Section 2, Figures 4-6).  With n1 = ceil(n/2) columns
+// for TRANSR='N' the rectangle AR has LDAR = n (odd n) or n + 1 (even n)
+// rows.  For UPLO='L' the first diagonal block has order ceil(n/2): its lower
+// triangle sits in the first columns of AR (one row down when n is even, to
+// make room for the diagonal of A22), A21 sits under it, and A22's lower
+// triangle is stored transposed in the upper part of the top square, shifted
+// one column right when n is odd.  For UPLO='U' the first diagonal block has
+// order floor(n/2): A12 occupies the top rows of AR, A22's upper triangle
+// follows in the same columns, and A11's upper triangle is stored transposed
+// below it.  TRANSR='T' stores AR^T with leading dimension n1, which swaps the
+// row and column strides of every block.
+bool rfp_blocks(char transr, char uplo, int64_t n, RfpBlocks* o)
+{
+    const int t = upc(transr), u = upc(uplo);
+    if ((t != 'N' && t != 'T') || (u != 'L' && u != 'U') || n < 0) return false;
+    const bool odd = (n & 1) != 0;
+    const int64_t ldar = odd ? n : n + 1;
+    const int64_t cols = (n + 1) / 2;
+    const int64_t sr = (t == 'N') ? 1 : cols;   // stride of one AR row step
+    const int64_t sc = (t == 'N') ? ldar : 1;   // stride of one AR column step
+    const int64_t extra = odd ? 0 : 1;           // the extra top row of even n
+    o->n = n;
+    // each block: AR position (row, col) of its (0,0) and whether its row
+    // index runs down AR rows (true) or along AR columns (false)
+    int64_t r11, c11, r21, c21, r22, c22;
+    bool d11, d21, d22;
+    if (u == 'L') {
+        o->m1 = (n + 1) / 2;
+        o->m2 = n - o->m1;
+        r11 = extra; c11 = 0; d11 = true;
+        r21 = o->m1 + extra; c21 = 0; d21 = true;
+        r22 = 0; c22 = 1 - extra; d22 = false;
+    } else {
+        o->m1 = n / 2;
+        o->m2 = n - o->m1;
+        r11 = o->m2 + extra; c11 = 0; d11 = true;
+        r21 = 0; c21 = 0; d21 = false;
+        r22 = o->m1; c22 = 0; d22 = false;
+    }
+    auto put = [&](int64_t r, int64_t c, bool down, int64_t* off, int64_t* rs, int64_t* cs) {
+        *off = r * sr + c * sc;
+        *rs = down ? sr : sc;
+        *cs = down ? sc : sr;
+    };
+    put(r11, c11, d11, &o->off11, &o->rs11, &o->cs11);
+    put(r21, c21, d21, &o->off21, &o->rs21, &o->cs21);
+    put(r22, c22, d22, &o->off22, &o->rs22, &o->cs22);
+    return true;
+}
+
+static inline int64_t nleaves(int64_t n) { return (n + NB - 1) / NB; }
+
+// Plan recording: when a Run has a recorder, the drivers append one record
+// per primitive (GEMM or leaf kernel) instead of launching it.  Pointers are
+// then symbolic: each buffer gets a fixed fake base, and a record stores
+// (buffer, element offset, strides).
+static constexpr uint64_t PLAN_BASE_SHIFT = 44;
+struct PlanRec {
+    rfp_plan_op* ops;
+    int64_t cap, count;
+    size_t esize;
+};
+static void plan_view(const void* p, int64_t rs, int64_t cs, size_t esize, int64_t* out)
+{
+    const uint64_t a = (uint64_t)(uintptr_t)p;
+    const uint64_t buf = a >> PLAN_BASE_SHIFT;
+    out[0] = (int64_t)buf - 1;
+    out[1] = (int64_t)((a - (buf << PLAN_BASE_SHIFT)) / esize);
+    out[2] = rs;
+    out[3] = cs;
+}
+
+template <typename T>
+struct Run {
+    Exec ex;
+    hipError_t err = hipSuccess;
+    PlanRec* rec = nullptr;
+    void chk(hipError_t e)
+    {
+        if (e != hipSuccess && err == hipSuccess) err = e;
+    }
+    rfp_plan_op* next(int kind)
+    {
+        if (rec->count >= rec->cap) {
+            rec->count++;
+            return nullptr;
+        }
+        rfp_plan_op* o = &rec->ops[rec->count++];
+        std::memset(o, 0, sizeof(*o));
+        o->kind = kind;
+        o->a[0] = o->b[0] = o->c[0] = -1;
+        return o;
+    }
+    void mm(int64_t m, int64_t n, int64_t k, T alpha, Mat<const T> A, int ta, Mat<const T> B, int tb, T beta,
+            Mat<T> C, bool lower = false)
+    {
+        if (rec) {
+            if (rfp_plan_op* o = next(RFP_PLAN_GEMM)) {
+                o->m = m; o->n = n; o->k = k;
+                o->alpha = (double)alpha; o->beta = (double)beta;
+                o->tri_a = ta; o->tri_b = tb; o->c_lower = lower ? 1 : 0;
+                plan_view(A.p, A.rs, A.cs, sizeof(T), o->a);
+                plan_view(B.p, B.rs, B.cs, sizeof(T), o->b);
+                plan_view(C.p, C.rs, C.cs, sizeof(T), o->c);
+            }
+            return;
+        }
+        chk(gemm<T>(ex, m, n, k, alpha, A, ta, B, tb, beta, C, lower));
+    }
+    void leaf(int kind, Mat<const T> A, int64_t nb, const T* w, int64_t info_base)
+    {
+        if (rfp_plan_op* o = next(kind)) {
+            o->m = nb;
+            o->info_base = info_base;
+            plan_view(A.p, A.rs, A.cs, sizeof(T), o->a);
+            if (w) plan_view(w, NB, 1, sizeof(T), o->b);
+        }
+    }
+
+    // ---------------------------------------------------------- factorization
+    // B (m x n) <- B L^{-T}; L lower of order n whose leaf inverses are in winv.
+    void trsm_rlt(int64_t m, int64_t n, Mat<T> B, Mat<const T> L, const T* winv)
+    {
+        if (m <= 0 || n <= 0) return;
+        if (n <= NB) {
+            mm(m, n, n, T(1), B, TRI_NONE, Mat<const T>{winv, NB, 1}, TRI_LOWER, T(0), B);
+            return;
+        }
+        const int64_t n1 = rec_split(n), n2 = n - n1;
+        trsm_rlt(m, n1, B, L, winv);
+        mm(m, n2, n1, T(-1), B, TRI_NONE, L.sub(n1, 0), TRI_NONE, T(1), B.sub(0, n1));
+        trsm_rlt(m, n2, B.sub(0, n1), L.sub(n1, n1), winv + nleaves(n1) * NB * NB);
+    }
+
+    // Cholesky of the lower triangle of A (order n); goff is the position of
+    // A's first row in the whole matrix, for INFO.
+    void potrf_rec(int64_t n, Mat<T> A, int64_t goff, T* winv)
+    {
+        if (n <= 0) return;
+        if (n <= NB) {
+            if (rec) leaf(RFP_PLAN_POTRF_LEAF, A, n, winv, goff);
+            else chk(potrf_leaf<T>(ex, A, (int)n, winv, goff));
+            return;
+        }
+        const int64_t n1 = rec_split(n), n2 = n - n1;
+        potrf_rec(n1, A, goff, winv);
+        trsm_rlt(n2, n1, A.sub(n1, 0), A, winv);
+        mm(n2, n2, n1, T(-1), A.sub(n1, 0), TRI_NONE, A.sub(n1, 0), TRI_NONE, T(1), A.sub(n1, n1), true);
+        potrf_rec(n2, A.sub(n1, n1), goff + n1, winv + nleaves(n1) * NB * NB);
+    }
+
+    // ---------------------------------------------------------------- solve
+    // B (n x r) <- L^{-1} B
+    void trsm_lln(int64_t n, int64_t r, Mat<const T> L, Mat<T> B, const T* winv)
+    {
+        if (n <= 0 || r <= 0) return;
+        if (n <= NB) {
+            mm(n, r, n, T(1), Mat<const T>{winv, NB, 1}, TRI_LOWER, Mat<T>(B).tr(), TRI_NONE, T(0), B);
+            return;
+        }
+        const int64_t n1 = rec_split(n), n2 = n - n1;
+        trsm_lln(n1, r, L, B, winv);
+        mm(n2, r, n1, T(-1), L.sub(n1, 0), TRI_NONE, B.tr(), TRI_NONE, T(1), B.sub(n1, 0));
+        trsm_lln(n2, r, L.sub(n1, n1), B.sub(n1, 0), winv + nleaves(n1) * NB * NB);
+    }
+    // B (n x r) <- L^{-T} B
+    void leaves_inv(Mat<const T> A, int64_t n, T* winv)
+    {
+        if (rec) leaf(RFP_PLAN_TRTRI_LEAVES, A, n, winv, 0);
+        else chk(trtri_leaves<T>(ex, A, n, winv));
+    }
+    void setinfo(int* p)
+    {
+        if (!rec) chk(set_int(ex.stream, p, 0));
+    }
+    void trsm_llt(int64_t n, int64_t r, Mat<const T> L, Mat<T> B, const T* winv)
+    {
+        if (n <= 0 || r <= 0) return;
+        if (n <= NB) {
+            mm(n, r, n, T(1), Mat<const T>{winv, 1, NB}, TRI_UPPER, B.tr(), TRI_NONE, T(0), B);
+            return;
+        }
+        const int64_t n1 = rec_split(n), n2 = n - n1;
+        trsm_llt(n2, r, L.sub(n1, n1), B.sub(n1, 0), winv + nleaves(n1) * NB * NB);
+        mm(n1, r, n2, T(-1), L.sub(n1, 0).tr(), TRI_NONE, B.sub(n1, 0).tr(), TRI_NONE, T(1), B);
+        trsm_llt(n1, r, L, B, winv);
+    }
+
+    // ------------------------------------------------------------ inversion
+    // B (m x n) <- alpha B W, W lower of order n
+    void trmm_rl(int64_t m, int64_t n, Mat<T> B, Mat<const T> W, T alpha)
+    {
+        if (m <= 0 || n <= 0) return;
+        if (n <= NB) {
+            mm(m, n, n, alpha, B, TRI_NONE, W.tr(), TRI_UPPER, T(0), B);
+            return;
+        }
+        const int64_t n1 = rec_split(n), n2 = n - n1;
+        trmm_rl(m, n1, B, W, alpha);
+        mm(m, n1, n2, alpha, B.sub(0, n1), TRI_NONE, W.sub(n1, 0).tr(), TRI_NONE, T(1), B);
+        trmm_rl(m, n2, B.sub(0, n1), W.sub(n1, n1), alpha);
+    }
+    // B (m x n) <- W B, W lower of order m
+    void trmm_ll(int64_t m, int64_t n, Mat<const T> W, Mat<T> B)
+    {
+        if (m <= 0 || n <= 0) return;
+        if (m <= NB) {
+            mm(m, n, m, T(1), W, TRI_LOWER, B.tr(), TRI_NONE, T(0), B);
+            return;
+        }
+        const int64_t m1 = rec_split(m), m2 = m - m1;
+        trmm_ll(m2, n, W.sub(m1, m1), B.sub(m1, 0));
+        mm(m2, n, m1, T(1), W.sub(m1, 0), TRI_NONE, B.tr(), TRI_NONE, T(1), B.sub(m1, 0));
+        trmm_ll(m1, n, W, B);
+    }
+    // B (m x n) <- W^T B, W lower of order m
+    void trmm_llt(int64_t m, int64_t n, Mat<const T> W, Mat<T> B)
+    {
+        if (m <= 0 || n <= 0) return;
+        if (m <= NB) {
+            mm(m, n, m, T(1), W.tr(), TRI_UPPER, B.tr(), TRI_NONE, T(0), B);
+            return;
+        }
+        const int64_t m1 = rec_split(m), m2 = m - m1;
+        trmm_llt(m1, n, W, B);
+        mm(m1, n, m2, T(1), W.sub(m1, 0).tr(), TRI_NONE, B.sub(m1, 0).tr(), TRI_NONE, T(1), B);
+        trmm_llt(m2, n, W.sub(m1, m1), B.sub(m1, 0));
+    }
+    // in-place inverse of the lower triangle of A (order n)
+    void trtri_rec(int64_t n, Mat<T> A, int64_t goff)
+    {
+        if (n <= 0) return;
+        if (n <= NB) {
+            if (rec) leaf(RFP_PLAN_TRTRI_LEAF, A, n, nullptr, goff);
+            else chk(trtri_leaf<T>(ex, A, (int)n, goff));
+            return;
+        }
+        const int64_t n1 = rec_split(n), n2 = n - n1;
+        trtri_rec(n1, A, goff);
+        trmm_rl(n2, n1, A.sub(n1, 0), A, T(-1));
+        trtri_rec(n2, A.sub(n1, n1), goff + n1);
+        trmm_ll(n2, n1, A.sub(n1, n1), A.sub(n1, 0));
+    }
+    // lower triangle of W^T W in place (order n)
+    void lauum_rec(int64_t n, Mat<T> W)
+    {
+        if (n <= 0) return;
+        if (n <= NB) {
+            if (rec) leaf(RFP_PLAN_LAUUM_LEAF, W, n, nullptr, 0);
+            else chk(lauum_leaf<T>(ex, W, (int)n));
+            return;
+        }
+        const int64_t n1 = rec_split(n), n2 = n - n1;
+        lauum_rec(n1, W);
+        mm(n1, n1, n2, T(1), W.sub(n1, 0).tr(), TRI_NONE, W.sub(n1, 0).tr(), TRI_NONE, T(1), W, true);
+        trmm_llt(n2, n1, W.sub(n1, n1), W.sub(n1, 0));
+        lauum_rec(n2, W.sub(n1, n1));
+    }
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (dev < 0) return;  // plan recording: no device involved
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+static hipError_t ensure(void** p, size_t* have, size_t need)
+{
+    if (need <= *have) return hipSuccess;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+    need = (need + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1);
+    e = hipMalloc(p, need);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    *have = need;
+    return hipSuccess;
+}
+
+static constexpr size_t SPLITK_BYTES = size_t(128) << 20;
+
+static hipError_t prepare(rfp_context* h, size_t inv_need)
+{
+    hipError_t e = ensure(&h->splitk, &h->splitk_bytes, SPLITK_BYTES);
+    if (e != hipSuccess) return e;
+    return ensure(&h->inv, &h->inv_bytes, inv_need);
+}
+
+template <typename T>
+static Run<T> make_run(rfp_context* h, hipStream_t s, int* info)
+{
+    Run<T> r;
+    r.ex.stream = s;
+    r.ex.info = info;
+    r.ex.splitk_ws = h->splitk;
+    r.ex.splitk_bytes = h->splitk_bytes;
+    return r;
+}
+
+static inline bool bad_tr(char c) { return upc(c) != 'N' && upc(c) != 'T'; }
+static inline bool bad_ul(char c) { return upc(c) != 'L' && upc(c) != 'U'; }
+
+template <typename T>
+static int trttf_impl(rfp_context* h, char transr, char uplo, int64_t n, const T* a, int64_t lda, T* arf,
+                      hipStream_t s, bool to_rfp)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (bad_tr(transr)) return -1;
+    if (bad_ul(uplo)) return -2;
+    if (n < 0) return -3;
+    if (n == 0) return 0;
+    // argument positions differ: TRTTF (.., A=4, LDA=5, ARF=6); TFTTR (.., ARF=4, A=5, LDA=6)
+    if (to_rfp) {
+        if (!a) return -4;
+        if (lda < std::max<int64_t>(1, n)) return -5;
+        if (!arf) return -6;
+    } else {
+        if (!arf) return -4;
+        if (!a) return -5;
+        if (lda < std::max<int64_t>(1, n)) return -6;
+    }
+    DeviceGuard g(h->device);
+    RfpBlocks b;
+    rfp_blocks(transr, uplo, n, &b);
+    RfpView<T> v = rfp_view(b, arf);
+    // canonical lower view of the full matrix: the UPLO triangle read as lower
+    Mat<T> F = (upc(uplo) == 'L') ? Mat<T>{(T*)a, 1, lda} : Mat<T>{(T*)a, lda, 1};
+    hipError_t e;
+    if (to_rfp) {
+        e = copy2d<T, T>(s, v.t1, F, b.m1, b.m1, true);
+        if (e == hipSuccess) e = copy2d<T, T>(s, v.s, F.sub(b.m1, 0), b.m2, b.m1, false);
+        if (e == hipSuccess) e = copy2d<T, T>(s, v.t2, F.sub(b.m1, b.m1), b.m2, b.m2, true);
+    } else {
+        e = copy2d<T, T>(s, F, v.t1, b.m1, b.m1, true);
+        if (e == hipSuccess) e = copy2d<T, T>(s, F.sub(b.m1, 0), v.s, b.m2, b.m1, false);
+        if (e == hipSuccess) e = copy2d<T, T>(s, F.sub(b.m1, b.m1), v.t2, b.m2, b.m2, true);
+    }
+    return e == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+// Fake buffer bases used while recording a plan (buffer id + 1 in the high bits).
+template <typename T>
+static T* plan_base(int buf)
+{
+    return (T*)(uintptr_t)((uint64_t)(buf + 1) << PLAN_BASE_SHIFT);
+}
+
+template <typename T>
+static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf, int* info, hipStream_t s,
+                      PlanRec* rec = nullptr)
+{
+    if (!h && !rec) return RFP_ERR_HANDLE;
+    if (bad_tr(transr)) return -1;
+    if (bad_ul(uplo)) return -2;
+    if (n < 0) return -3;
+    if (n > 0 && !arf) return -4;
+    if (!info) return -5;
+    RfpBlocks b;
+    rfp_blocks(transr, uplo, n, &b);
+    const int64_t lv = std::max(nleaves(b.m1), nleaves(b.m2));
+    Run<T> r;
+    T* winv;
+    DeviceGuard g(rec ? -1 : h->device);
+    if (rec) {
+        r.rec = rec;
+        winv = plan_base<T>(RFP_PLAN_BUF_WORK);
+    } else {
+        if (n == 0) return set_int(s, info, 0) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+        if (prepare(h, size_t(lv) * NB * NB * sizeof(T)) != hipSuccess) return RFP_ERR_RUNTIME;
+        r = make_run<T>(h, s, info);
+        winv = (T*)h->inv;
+    }
+    RfpView<T> v = rfp_view(b, arf);
+    r.setinfo(info);
+    // step 1: L11 = chol(A11)              (Figure 4, factorization step 1)
+    r.potrf_rec(b.m1, v.t1, 0, winv);
+    // step 2: L21 = A21 L11^{-T}           (step 2, TRSM)
+    r.trsm_rlt(b.m2, b.m1, v.s, v.t1, winv);
+    // step 3: A22 <- A22 - L21 L21^T       (step 3, SYRK on T2's triangle)
+    r.mm(b.m2, b.m2, b.m1, T(-1), v.s, TRI_NONE, v.s, TRI_NONE, T(1), v.t2, true);
+    // step 4: L22 = chol(A22), INFO offset by m1
+    r.potrf_rec(b.m2, v.t2, b.m1, winv);
+    return r.err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+template <typename T>
+static int pftrs_impl(rfp_context* h, char transr, char uplo, int64_t n, int64_t nrhs, const T* arf, T* bp,
+                      int64_t ldb, hipStream_t s, PlanRec* rec = nullptr)
+{
+    if (!h && !rec) return RFP_ERR_HANDLE;
+    if (bad_tr(transr)) return -1;
+    if (bad_ul(uplo)) return -2;
+    if (n < 0) return -3;
+    if (nrhs < 0) return -4;
+    if (n > 0 && !arf) return -5;
+    if (n > 0 && nrhs > 0 && !bp) return -6;
+    if (ldb < std::max<int64_t>(1, n)) return -7;
+    if (n == 0 || nrhs == 0) return 0;
+    RfpBlocks b;
+    rfp_blocks(transr, uplo, n, &b);
+    const int64_t l1 = nleaves(b.m1), l2 = nleaves(b.m2);
+    Run<T> r;
+    T* w1;
+    DeviceGuard g(rec ? -1 : h->device);
+    if (rec) {
+        r.rec = rec;
+        w1 = plan_base<T>(RFP_PLAN_BUF_WORK);
+    } else {
+        if (prepare(h, size_t(l1 + l2) * NB * NB * sizeof(T)) != hipSuccess) return RFP_ERR_RUNTIME;
+        r = make_run<T>(h, s, nullptr);
+        w1 = (T*)h->inv;
+    }
+    T* w2 = w1 + l1 * NB * NB;
+    RfpView<const T> v = rfp_view(b, arf);
+    r.leaves_inv(v.t1, b.m1, w1);
+    r.leaves_inv(v.t2, b.m2, w2);
+    Mat<T> B1{bp, 1, ldb};
+    Mat<T> B2 = B1.sub(b.m1, 0);
+    // L Y = B: Y1 = L11^{-1} B1; B2 -= L21 Y1; Y2 = L22^{-1} B2   (Figure 4, solution)
+    r.trsm_lln(b.m1, nrhs, v.t1, B1, w1);
+    r.mm(b.m2, nrhs, b.m1, T(-1), v.s, TRI_NONE, Mat<T>(B1).tr(), TRI_NONE, T(1), B2);
+    r.trsm_lln(b.m2, nrhs, v.t2, B2, w2);
+    // L^T X = Y: X2 = L22^{-T} Y2; Y1 -= L21^T X2; X1 = L11^{-T} Y1
+    r.trsm_llt(b.m2, nrhs, v.t2, B2, w2);
+    r.mm(b.m1, nrhs, b.m2, T(-1), v.s.tr(), TRI_NONE, Mat<T>(B2).tr(), TRI_NONE, T(1), B1);
+    r.trsm_llt(b.m1, nrhs, v.t1, B1, w1);
+    return r.err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+template <typename T>
+static int pftri_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf, int* info, hipStream_t s,
+                      PlanRec* rec = nullptr)
+{
+    if (!h && !rec) return RFP_ERR_HANDLE;
+    if (bad_tr(transr)) return -1;
+    if (bad_ul(uplo)) return -2;
+    if (n < 0) return -3;
+    if (n > 0 && !arf) return -4;
+    if (!info) return -5;
+    RfpBlocks b;
+    rfp_blocks(transr, uplo, n, &b);
+    Run<T> r;
+    DeviceGuard g(rec ? -1 : h->device);
+    if (rec) {
+        r.rec = rec;
+    } else {
+        if (n == 0) return set_int(s, info, 0) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+        if (prepare(h, 0) != hipSuccess) return RFP_ERR_RUNTIME;
+        r = make_run<T>(h, s, info);
+    }
+    RfpView<T> v = rfp_view(b, arf);
+    r.setinfo(info);
+    // stage 2 (TFTRI): W11 = L11^{-1}; S <- -S W11; W22 = L22^{-1}; S <- W22 S
+    r.trtri_rec(b.m1, v.t1, 0);
+    r.trmm_rl(b.m2, b.m1, v.s, v.t1, T(-1));
+    r.trtri_rec(b.m2, v.t2, b.m1);
+    r.trmm_ll(b.m2, b.m1, v.t2, v.s);
+    // stage 3: T1 <- W11^T W11 + W21^T W21; S <- W22^T W21; T2 <- W22^T W22
+    r.lauum_rec(b.m1, v.t1);
+    r.mm(b.m1, b.m1, b.m2, T(1), v.s.tr(), TRI_NONE, v.s.tr(), TRI_NONE, T(1), v.t1, true);
+    r.trmm_llt(b.m2, b.m1, v.t2, v.s);
+    r.lauum_rec(b.m2, v.t2);
+    return r.err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+}  // namespace rfp
+
+using namespace rfp;
+
+extern "C" {
+
+int rfp_create(rfp_handle_t* h, int device)
+{
+    if (!h) return -1;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return -2;
+    rfp_context* c = (rfp_context*)std::calloc(1, sizeof(rfp_context));
+    if (!c) return RFP_ERR_RUNTIME;
+    c->device = device;
+    *h = c;
+    return 0;
+}
+
+int rfp_destroy(rfp_handle_t h)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    {
+        DeviceGuard g(h->device);
+        (void)hipDeviceSynchronize();
+        if (h->splitk) (void)hipFree(h->splitk);
+        if (h->inv) (void)hipFree(h->inv);
+    }
+    std::free(h);
+    return 0;
+}
+
+int rfp_dtrttf(rfp_handle_t h, char transr, char uplo, int64_t n, const double* a, int64_t lda, double* arf,
+               hipStream_t stream)
+{
+    return trttf_impl<double>(h, transr, uplo, n, a, lda, arf, stream, true);
+}
+
+int rfp_dtfttr(rfp_handle_t h, char transr, char uplo, int64_t n, const double* arf, double* a, int64_t lda,
+               hipStream_t stream)
+{
+    return trttf_impl<double>(h, transr, uplo, n, a, lda, (double*)arf, stream, false);
+}
+
+int rfp_dpftrf(rfp_handle_t h, char transr, char uplo, int64_t n, double* arf, int* info, hipStream_t stream)
+{
+    return pftrf_impl<double>(h, transr, uplo, n, arf, info, stream);
+}
+
+int rfp_dpftrs(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, const double* arf, double* b,
+               int64_t ldb, hipStream_t stream)
+{
+    return pftrs_impl<double>(h, transr, uplo, n, nrhs, arf, b, ldb, stream);
+}
+
+int rfp_dpftri(rfp_handle_t h, char transr, char uplo, int64_t n, double* arf, int* info, hipStream_t stream)
+{
+    return pftri_impl<double>(h, transr, uplo, n, arf, info, stream);
+}
+
+int rfp_strttf(rfp_handle_t h, char transr, char uplo, int64_t n, const float* a, int64_t lda, float* arf,
+               hipStream_t stream)
+{
+    return trttf_impl<float>(h, transr, uplo, n, a, lda, arf, stream, true);
+}
+
+int rfp_stfttr(rfp_handle_t h, char transr, char uplo, int64_t n, const float* arf, float* a, int64_t lda,
+               hipStream_t stream)
+{
+    return trttf_impl<float>(h, transr, uplo, n, a, lda, (float*)arf, stream, false);
+}
+
+int rfp_spftrf(rfp_handle_t h, char transr, char uplo, int64_t n, float* arf, int* info, hipStream_t stream)
+{
+    return pftrf_impl<float>(h, transr, uplo, n, arf, info, stream);
+}
+
+int rfp_spftrs(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, const float* arf, float* b,
+               int64_t ldb, hipStream_t stream)
+{
+    return pftrs_impl<float>(h, transr, uplo, n, nrhs, arf, b, ldb, stream);
+}
+
+int rfp_spftri(rfp_handle_t h, char transr, char uplo, int64_t n, float* arf, int* info, hipStream_t stream)
+{
+    return pftri_impl<float>(h, transr, uplo, n, arf, info, stream);
+}
+
+int rfp_plan(char routine, char transr, char uplo, int64_t n, int64_t nrhs, int64_t ldb, rfp_plan_op* ops,
+             int64_t cap, int64_t* count)
+{
+    if (!count || cap < 0 || (cap > 0 && !ops)) return -8;
+    PlanRec rec{ops, cap, 0, sizeof(double)};
+    double* arf = plan_base<double>(RFP_PLAN_BUF_ARF);
+    double* b = plan_base<double>(RFP_PLAN_BUF_B);
+    int* info = (int*)plan_base<int>(RFP_PLAN_BUF_INFO);
+    int rc;
+    switch (upc(routine)) {
+        case 'F': rc = pftrf_impl<double>(nullptr, transr, uplo, n, arf, info, nullptr, &rec); break;
+        case 'S': rc = pftrs_impl<double>(nullptr, transr, uplo, n, nrhs, arf, b, ldb, nullptr, &rec); break;
+        case 'I': rc = pftri_impl<double>(nullptr, transr, uplo, n, arf, info, nullptr, &rec); break;
+        default: return -1;
+    }
+    *count = rec.count;
+    return rc;
+}
+
+}  // extern "C"

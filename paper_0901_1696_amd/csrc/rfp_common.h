@@ -1,0 +1,116 @@
+// Internal header of the MI355X RFP library: strided views, the RFP block
+// descriptor for the eight layouts, and the launchers the drivers call.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rfp {
+
+// A strided 2-D view: element (i, j) lives at p[i * rs + j * cs].  Every view
+// the library builds has one unit stride (rs == 1: rows contiguous, i.e. the
+// column-major orientation; cs == 1: the row-major orientation).
+template <typename T>
+struct Mat {
+    T* p;
+    int64_t rs, cs;
+    __host__ __device__ T& at(int64_t i, int64_t j) const { return p[i * rs + j * cs]; }
+    __host__ __device__ Mat sub(int64_t i, int64_t j) const { return Mat{p + i * rs + j * cs, rs, cs}; }
+    __host__ __device__ Mat tr() const { return Mat{p, cs, rs}; }
+    __host__ __device__ operator Mat<const T>() const { return Mat<const T>{p, rs, cs}; }
+};
+
+// Operand masks: which entries of an operand (in its own (row, col) indices)
+// are read; everything else is taken as zero.  Triangular operands of the
+// RFP format must be masked because the complementary triangle of a diagonal
+// block holds the other diagonal block's live data.
+enum TriMask { TRI_NONE = 0, TRI_LOWER = 1, TRI_UPPER = 2, TRI_SLOWER = 3, TRI_SUPPER = 4 };
+
+// The three blocks of an RFP array seen as the blocks of the lower-triangular
+// (canonical) matrix: L11 (m1 x m1, lower), L21 (m2 x m1), L22 (m2 x m2, lower).
+// For UPLO='U' the array holds U = L^T, i.e. the same numbers, so the lower
+// view of every layout addresses the stored copy of each element.
+struct RfpBlocks {
+    int64_t n, m1, m2;
+    int64_t off11, rs11, cs11;
+    int64_t off21, rs21, cs21;
+    int64_t off22, rs22, cs22;
+};
+
+// Layout descriptor of the eight RFP layouts (Section 2 and Figures 4-6).
+// Returns false for an illegal TRANSR / UPLO character or n < 0.
+bool rfp_blocks(char transr, char uplo, int64_t n, RfpBlocks* out);
+
+template <typename T>
+struct RfpView {
+    int64_t n, m1, m2;
+    Mat<T> t1, s, t2;  // L11, L21, L22
+};
+
+template <typename T>
+inline RfpView<T> rfp_view(const RfpBlocks& b, T* arf)
+{
+    RfpView<T> v;
+    v.n = b.n;
+    v.m1 = b.m1;
+    v.m2 = b.m2;
+    v.t1 = Mat<T>{arf + b.off11, b.rs11, b.cs11};
+    v.s = Mat<T>{arf + b.off21, b.rs21, b.cs21};
+    v.t2 = Mat<T>{arf + b.off22, b.rs22, b.cs22};
+    return v;
+}
+
+// Leaf order of the recursive algorithms: diagonal blocks of at most NB
+// rows are handled by one wavefront each.
+constexpr int NB = 64;
+
+// Splits of the recursion are multiples of NB measured from the root, so the
+// leaves of every sub-problem coincide with the leaves of its root.
+inline int64_t rec_split(int64_t n)
+{
+    int64_t nblk = (n + NB - 1) / NB;
+    return ((nblk + 1) / 2) * NB;
+}
+
+// Per-call execution context.
+struct Exec {
+    hipStream_t stream;
+    int* info;          // device; kernels of a factorization exit early when *info != 0
+    void* splitk_ws;    // split-K partial sums
+    size_t splitk_bytes;
+};
+
+// C(m x n) = alpha * A(m x k) * B(n x k)^T + beta * C.
+// A(i, kk) = A.at(i, kk) masked by triA; B(j, kk) = B.at(j, kk) masked by triB.
+// c_lower: only the lower triangle (i >= j) of C is computed and written.
+// C may alias A when n fits one column tile, or alias B when m fits one row
+// tile (the in-place triangular products of the leaves).
+template <typename T>
+hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<const T> A, int triA,
+                Mat<const T> B, int triB, T beta, Mat<T> C, bool c_lower);
+
+// Leaf kernels (order nb <= NB, one wavefront per block).
+// potrf: in-place Cholesky of the lower triangle of A; writes L^{-1} (NB x NB,
+// column-major, zero above the diagonal) to winv; *info = info_base + j + 1 on
+// the first non-positive pivot j.
+template <typename T>
+hipError_t potrf_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info_base);
+// trtri: in-place inverse of the lower triangle of A.  info as above for an
+// exactly zero diagonal entry.
+template <typename T>
+hipError_t trtri_leaf(const Exec& ex, Mat<T> A, int nb, int64_t info_base);
+// Batched out-of-place inverses of every NB-leaf of a lower-triangular matrix
+// of order n: winv[b] = (diagonal block b)^{-1}.
+template <typename T>
+hipError_t trtri_leaves(const Exec& ex, Mat<const T> A, int64_t n, T* winv);
+// lauum: lower triangle of W^T W, in place.
+template <typename T>
+hipError_t lauum_leaf(const Exec& ex, Mat<T> A, int nb);
+
+// 2-D strided copy dst = src (m x n), optionally only the lower triangle.
+template <typename Td, typename Ts>
+hipError_t copy2d(hipStream_t s, Mat<Td> dst, Mat<const Ts> src, int64_t m, int64_t n, bool lower);
+
+// Small utility kernels.
+hipError_t set_int(hipStream_t s, int* p, int v);
+
+}  // namespace rfp

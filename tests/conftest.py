@@ -9,3 +9,10 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running case")
+    # Load what is built; build only what is missing (the oracle and librfp.so).
+    from oracle import build as obuild
+    if not os.path.exists(obuild.LIB):
+        obuild.build()
+    from paper_0901_1696_amd import build as rbuild
+    if not os.path.exists(rbuild.LIB):
+        rbuild.build()

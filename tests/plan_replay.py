@@ -1,0 +1,139 @@
+"""Host-side replay of the GPU library's recorded plans (test support).
+
+``rfp_plan`` lists the primitives (masked strided GEMMs and diagonal-block
+leaf operations) the drivers would launch.  This module executes each one in
+NumPy with the documented semantics and checks, for every access, that
+
+  * the view stays inside its buffer (no out-of-bounds address on the GPU);
+  * reads of a masked operand touch only its triangle;
+  * an output that overlaps an input is one of the two in-place forms the
+    GEMM kernel supports (C and A the same view with all columns in one
+    128-wide tile, or B the transpose view of C with all rows in one tile),
+    and overlaps nothing else.
+
+The replay gives the same result as the GPU up to rounding; the tests compare
+it with the oracle, which checks the block algebra of all eight layouts.
+"""
+import numpy as np
+
+import paper_0901_1696_amd as rfp
+
+NB = 64
+TILE = 128
+
+
+class PlanError(AssertionError):
+    pass
+
+
+def _idx(view, rows, cols):
+    buf, off, rs, cs = view
+    i = np.arange(rows)[:, None]
+    j = np.arange(cols)[None, :]
+    return buf, off + i * rs + j * cs
+
+
+def _mask(tri, rows, cols):
+    i = np.arange(rows)[:, None]
+    j = np.arange(cols)[None, :]
+    return {0: np.ones((rows, cols), bool), 1: i >= j, 2: i <= j, 3: i > j, 4: i < j}[tri]
+
+
+class Replayer:
+    def __init__(self, bufs):
+        self.bufs = bufs  # {buffer id: 1-D float64 array}
+        self.nops = 0
+
+    def _check(self, buf, idx, mask, what):
+        if buf not in self.bufs:
+            raise PlanError(f"{what}: unknown buffer {buf}")
+        sel = idx[mask]
+        if sel.size and (sel.min() < 0 or sel.max() >= self.bufs[buf].size):
+            raise PlanError(f"{what}: index range [{sel.min()}, {sel.max()}] outside buffer {buf} "
+                            f"of size {self.bufs[buf].size}")
+
+    def read(self, view, rows, cols, tri, what):
+        buf, idx = _idx(view, rows, cols)
+        mask = _mask(tri, rows, cols)
+        self._check(buf, idx, mask, what)
+        out = np.zeros((rows, cols))
+        out[mask] = self.bufs[buf][idx[mask]]
+        return out, (buf, set(idx[mask].ravel().tolist()))
+
+    def write(self, view, val, mask, what):
+        rows, cols = val.shape
+        buf, idx = _idx(view, rows, cols)
+        self._check(buf, idx, mask, what)
+        self.bufs[buf][idx[mask]] = val[mask]
+        return buf, set(idx[mask].ravel().tolist())
+
+    def gemm(self, op):
+        m, n, k = op.m, op.n, op.k
+        A, ra = self.read(tuple(op.a), m, k, op.tri_a, "gemm A")
+        B, rb = self.read(tuple(op.b), n, k, op.tri_b, "gemm B")
+        cmask = _mask(1 if op.c_lower else 0, m, n)
+        cbuf, cidx = _idx(tuple(op.c), m, n)
+        self._check(cbuf, cidx, cmask, "gemm C")
+        wset = set(cidx[cmask].ravel().tolist())
+        # aliasing rules of the kernel
+        if ra[0] == cbuf and ra[1] & wset:
+            if not (tuple(op.a) == tuple(op.c) and n <= TILE and op.beta == 0):
+                raise PlanError(f"gemm: C overlaps A outside the supported in-place form {list(op.a)} {list(op.c)}")
+        if rb[0] == cbuf and rb[1] & wset:
+            cb, co, crs, ccs = tuple(op.c)
+            if not (tuple(op.b) == (cb, co, ccs, crs) and m <= TILE and op.beta == 0):
+                raise PlanError(f"gemm: C overlaps B outside the supported in-place form {list(op.b)} {list(op.c)}")
+        C = np.zeros((m, n))
+        if op.beta != 0:
+            C[cmask] = self.bufs[cbuf][cidx[cmask]]
+        R = op.alpha * (A @ B.T) + (op.beta * C if op.beta != 0 else 0.0)
+        self.write(tuple(op.c), R, cmask, "gemm C")
+
+    def leaf(self, op):
+        nb = op.m
+        low = _mask(1, nb, nb)
+        X, _ = self.read(tuple(op.a), nb, nb, 1, "leaf A")
+        if op.kind == rfp.PLAN_POTRF_LEAF:
+            L = np.linalg.cholesky(X + np.tril(X, -1).T)
+            self.write(tuple(op.a), L, low, "potrf leaf")
+            W = np.eye(NB)
+            W[:nb, :nb] = np.linalg.inv(L)
+            self.write(tuple(op.b), W, np.ones((NB, NB), bool), "potrf leaf winv")
+        elif op.kind == rfp.PLAN_TRTRI_LEAF:
+            self.write(tuple(op.a), np.tril(np.linalg.inv(X)), low, "trtri leaf")
+        elif op.kind == rfp.PLAN_LAUUM_LEAF:
+            W = np.tril(X)
+            self.write(tuple(op.a), W.T @ W, low, "lauum leaf")
+        else:
+            raise PlanError(f"unknown leaf kind {op.kind}")
+
+    def leaves(self, op):
+        n = op.m
+        A, _ = self.read(tuple(op.a), n, n, 1, "trtri leaves A")
+        wb, woff, _, _ = tuple(op.b)
+        for b in range((n + NB - 1) // NB):
+            o = b * NB
+            nb = min(NB, n - o)
+            W = np.eye(NB)
+            W[:nb, :nb] = np.linalg.inv(np.tril(A[o:o + nb, o:o + nb]))
+            self.write((wb, woff + b * NB * NB, NB, 1), W, np.ones((NB, NB), bool), "trtri leaves out")
+
+    def run(self, ops):
+        for op in ops:
+            self.nops += 1
+            if op.kind == rfp.PLAN_GEMM:
+                self.gemm(op)
+            elif op.kind == rfp.PLAN_TRTRI_LEAVES:
+                self.leaves(op)
+            else:
+                self.leaf(op)
+
+
+def work_size(routine, uplo, n):
+    """Scratch the library allocates for the leaf inverses of each routine:
+    PFTRF reuses one set sized for the larger diagonal block, PFTRS keeps the
+    inverses of both T1 and T2, PFTRI needs none."""
+    m1 = (n + 1) // 2 if uplo == "L" else n // 2
+    m2 = n - m1
+    nl = lambda m: (m + NB - 1) // NB
+    return {"F": max(nl(m1), nl(m2)), "S": nl(m1) + nl(m2), "I": 0}[routine] * NB * NB

@@ -1,0 +1,85 @@
+"""CPU checks of the GPU library's host logic: the recorded plans of PFTRF,
+PFTRS and PFTRI for all eight layouts, replayed primitive by primitive in
+NumPy (with bounds, mask and aliasing checks), must reproduce the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_0901_1696_amd as rfp
+import synth
+from plan_replay import Replayer, work_size
+
+SIZES = [1, 2, 3, 5, 63, 64, 65, 127, 128, 129, 130, 192, 200, 255, 256, 257, 300, 513]
+LAYOUTS = oracle.LAYOUTS
+
+
+def _bufs(routine, uplo, n, arf, b=None):
+    bufs = {0: arf, 2: np.full(work_size(routine, uplo, n), np.nan)}
+    if b is not None:
+        bufs[1] = b
+    return bufs
+
+
+@pytest.mark.parametrize("transr,uplo", LAYOUTS)
+@pytest.mark.parametrize("n", SIZES)
+def test_pftrf_plan(transr, uplo, n):
+    A, _ = synth.spd(n, seed=n)
+    arf = oracle.trttf(transr, uplo, A)
+    want, info = oracle.pftrf(transr, uplo, n, arf)
+    assert info == 0
+    got = arf.copy()
+    Replayer(_bufs("F", uplo, n, got)).run(rfp.rfp_plan("F", transr, uplo, n))
+    assert oracle.rel_fro(got, want) <= 1e-13 * max(n, 1)
+
+
+@pytest.mark.parametrize("transr,uplo", LAYOUTS)
+@pytest.mark.parametrize("n", SIZES)
+def test_pftrs_plan(transr, uplo, n):
+    nrhs = 3
+    A, B = synth.spd(n, nrhs=nrhs, seed=n + 1)
+    f, _ = oracle.pftrf(transr, uplo, n, oracle.trttf(transr, uplo, A))
+    want = oracle.pftrs(transr, uplo, n, f, B)
+    ldb = n + 5
+    bflat = np.full(ldb * nrhs, np.nan)
+    for c in range(nrhs):
+        bflat[c * ldb:c * ldb + n] = B[:, c]
+    Replayer(_bufs("S", uplo, n, f.copy(), bflat)).run(rfp.rfp_plan("S", transr, uplo, n, nrhs, ldb))
+    got = np.stack([bflat[c * ldb:c * ldb + n] for c in range(nrhs)], axis=1)
+    assert oracle.rel_fro(got, want) <= 1e-13 * max(n, 1)
+    # rows beyond n in each column are never touched
+    for c in range(nrhs):
+        assert np.all(np.isnan(bflat[c * ldb + n:(c + 1) * ldb]))
+
+
+@pytest.mark.parametrize("transr,uplo", LAYOUTS)
+@pytest.mark.parametrize("n", SIZES)
+def test_pftri_plan(transr, uplo, n):
+    A, _ = synth.spd(n, seed=n + 2)
+    f, _ = oracle.pftrf(transr, uplo, n, oracle.trttf(transr, uplo, A))
+    want, info = oracle.pftri(transr, uplo, n, f)
+    assert info == 0
+    got = f.copy()
+    Replayer(_bufs("I", uplo, n, got)).run(rfp.rfp_plan("I", transr, uplo, n))
+    assert oracle.rel_fro(got, want) <= 1e-13 * max(n, 1)
+
+
+def test_plan_argument_errors():
+    with pytest.raises(rfp.RfpError):
+        rfp.rfp_plan("F", "X", "L", 5)
+    with pytest.raises(rfp.RfpError):
+        rfp.rfp_plan("S", "N", "L", 5, nrhs=1, ldb=3)
+    with pytest.raises(rfp.RfpError):
+        rfp.rfp_plan("Q", "N", "L", 5)
+
+
+def test_plan_leaf_counts():
+    """The recursion reaches diagonal blocks of at most 64 rows, aligned on
+    64-row boundaries of T1 and T2, one leaf per block."""
+    for n in [100, 1001, 4097]:
+        for t, u in LAYOUTS:
+            ops = rfp.rfp_plan("F", t, u, n)
+            leaves = [o for o in ops if o.kind == rfp.PLAN_POTRF_LEAF]
+            m1 = (n + 1) // 2 if u == "L" else n // 2
+            m2 = n - m1
+            assert len(leaves) == -(-m1 // 64) + -(-m2 // 64)
+            assert all(o.m <= 64 for o in leaves)
