@@ -20,6 +20,10 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct Mfma;
+// Operand layout of both 16x16x4 instructions: lane l supplies A(l % 16, l / 16)
+// and B(l / 16, l % 16).  Result layout differs (measured on gfx950): lane l,
+// register r holds D(row, l % 16) with row = l/16 + 4r for FP64 and
+// row = 4(l/16) + r for FP32.
 template <>
 struct Mfma<double> {
     typedef v4d acc;
@@ -27,6 +31,7 @@ struct Mfma<double> {
     {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 template <>
 struct Mfma<float> {
@@ -35,6 +40,7 @@ struct Mfma<float> {
     {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
 constexpr int BM = 128, BN = 128, BK = 16, NTH = 256;
@@ -182,8 +188,8 @@ __global__ __launch_bounds__(NTH) void gemm_kernel(GemmParams<T> p)
     }
 
     // accumulator (a, b)[r] holds C(row, col) with
-    // row = wm*64 + a*16 + 4*(lane/16) + r, col = wn*64 + b*16 + lane%16
-    const int rbase = 4 * (lane >> 4), cl = lane & 15;
+    // row = wm*64 + a*16 + Mfma<T>::row(lane, r), col = wn*64 + b*16 + lane%16
+    const int cl = lane & 15;
     if (p.W) {
         T* W = p.W + (int64_t)blockIdx.z * m * n;
 #pragma unroll
@@ -193,7 +199,7 @@ __global__ __launch_bounds__(NTH) void gemm_kernel(GemmParams<T> p)
                 const int64_t j = j0 + wn * 64 + b * 16 + cl;
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const int64_t i = i0 + wm * 64 + a * 16 + rbase + r;
+                    const int64_t i = i0 + wm * 64 + a * 16 + Mfma<T>::row(lane, r);
                     if (i < m && j < n) W[j * m + i] = acc[a][b][r];
                 }
             }
@@ -206,7 +212,7 @@ __global__ __launch_bounds__(NTH) void gemm_kernel(GemmParams<T> p)
             const int64_t j = j0 + wn * 64 + b * 16 + cl;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int64_t i = i0 + wm * 64 + a * 16 + rbase + r;
+                const int64_t i = i0 + wm * 64 + a * 16 + Mfma<T>::row(lane, r);
                 if (i < m && j < n && (!p.c_lower || i >= j)) {
                     T* c = CMC ? &p.C[i + j * p.ldc] : &p.C[i * p.ldc + j];
                     T v = p.alpha * acc[a][b][r];
