@@ -99,6 +99,24 @@ int rfp_spftrs(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, 
 int rfp_spftri(rfp_handle_t h, char transr, char uplo, int64_t n, float* arf, int* info, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Kernel timing (introspection, used by the benchmark for its roofline).
+ * While enabled, every kernel the handle's calls launch is bracketed by a pair
+ * of HIP events on the call's stream.  rfp_profile_read waits for the device,
+ * folds the finished pairs into one entry per kernel (the kernel's demangled
+ * name as rocprofv3 prints it: launches, summed event time, summed
+ * algorithmic flops and bytes of those launches), and resets the totals
+ * once every entry fits in out (so a first call with cap = 0 only sizes).
+ * *count receives the number of kernels (even beyond cap).  Returns 0,
+ * RFP_ERR_HANDLE, -4 for bad output arguments or RFP_ERR_RUNTIME. */
+typedef struct {
+    char name[160];
+    int64_t launches;
+    double total_ms, flops, bytes;
+} rfp_profile_entry;
+int rfp_profile_enable(rfp_handle_t h, int on);
+int rfp_profile_read(rfp_handle_t h, rfp_profile_entry* out, int cap, int* count);
+
+/* ------------------------------------------------------------------------
  * Plan introspection (host only, touches no device).
  * The drivers are the paper's 2 x 2 block algorithms (Figure 3, Sections 3-5)
  * applied recursively; rfp_plan records the sequence of primitives that

@@ -51,7 +51,15 @@ _SIGS = {
     "rfp_spftrs": [_vp, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp],
     "rfp_spftri": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_plan": [_chr, _chr, _chr, _i64, _i64, _i64, _vp, _i64, ctypes.POINTER(_i64)],
+    "rfp_profile_enable": [_vp, _int],
+    "rfp_profile_read": [_vp, _vp, _int, ctypes.POINTER(_int)],
 }
+
+
+class ProfileEntry(ctypes.Structure):
+    """Layout of ``rfp_profile_entry`` (include/rfp.h)."""
+    _fields_ = [("name", ctypes.c_char * 160), ("launches", _i64), ("total_ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 PLAN_GEMM, PLAN_POTRF_LEAF, PLAN_TRTRI_LEAF, PLAN_TRTRI_LEAVES, PLAN_LAUUM_LEAF = 1, 2, 3, 4, 5
 PLAN_BUF_ARF, PLAN_BUF_B, PLAN_BUF_WORK = 0, 1, 2
@@ -144,6 +152,20 @@ class Handle:
             self.close()
         except Exception:
             pass
+
+
+def rfp_profile_enable(h, on=True):
+    _check("rfp_profile_enable", lib().rfp_profile_enable(h.value, 1 if on else 0))
+
+
+def rfp_profile_read(h):
+    """{kernel name: dict(launches, total_ms, flops, bytes)}; waits for the device and resets."""
+    count = _int(0)
+    _check("rfp_profile_read", lib().rfp_profile_read(h.value, None, 0, ctypes.byref(count)))
+    buf = (ProfileEntry * max(1, count.value))()
+    _check("rfp_profile_read", lib().rfp_profile_read(h.value, buf, count.value, ctypes.byref(count)))
+    return {e.name.decode(): dict(launches=e.launches, total_ms=e.total_ms, flops=e.flops, bytes=e.bytes)
+            for e in list(buf)[:count.value]}
 
 
 def rfp_plan(routine, transr, uplo, n, nrhs=0, ldb=None):

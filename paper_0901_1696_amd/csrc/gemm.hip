@@ -11,6 +11,8 @@
 // of 16 x 16 held in accumulation registers.  K advances in slabs of 16
 // staged through LDS (double buffered, one barrier per slab); the next slab's
 // global loads are issued before the current slab's MFMAs.
+#include <cstdio>
+
 #include "rfp_common.h"
 
 namespace rfp {
@@ -43,8 +45,8 @@ struct Mfma<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-constexpr int BM = 128, BN = 128, BK = 16, NTH = 256;
-constexpr int LPAD = 1;  // LDS row padding (elements)
+constexpr int BK = 16, NTH = 256;
+constexpr int KP = BK + 2;  // LDS row pitch (elements): k-contiguous rows, 16-byte aligned, conflict-free
 
 template <typename T>
 struct GemmParams {
@@ -58,43 +60,83 @@ struct GemmParams {
     T alpha, beta;
     int triA, triB;
     int c_lower;
-    int tiles_m;
+    int tiles_m, tiles_n;
     int64_t kchunk;
     T* W;  // split-K partials, [split][n][m], or null
     const int* info;
 };
 
-__device__ __forceinline__ bool keep(int tri, int64_t i, int64_t j)
+// A mask keeps (i, kk) when lo <= kk - i <= hi.
+struct Band {
+    int64_t lo, hi;
+};
+__device__ __forceinline__ Band band_of(int tri)
 {
+    const int64_t BIG = (int64_t)1 << 62;
     switch (tri) {
-        case TRI_LOWER: return i >= j;
-        case TRI_UPPER: return i <= j;
-        case TRI_SLOWER: return i > j;
-        case TRI_SUPPER: return i < j;
-        default: return true;
+        case TRI_LOWER: return Band{-BIG, 0};
+        case TRI_UPPER: return Band{0, BIG};
+        case TRI_SLOWER: return Band{-BIG, -1};
+        case TRI_SUPPER: return Band{1, BIG};
+        default: return Band{-BIG, BIG};
     }
 }
 
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    typedef double __attribute__((ext_vector_type(2))) type;
+};
+template <>
+struct Vec2<float> {
+    typedef float __attribute__((ext_vector_type(2))) type;
+};
+
+// Map the launch index to a tile.  Workgroups are dealt round-robin to the
+// eight XCDs, so consecutive launch indices are first regrouped into one
+// contiguous range per XCD (each XCD has its own L2); within that order,
+// tiles go column-group by column-group, GROUP tile rows at a time, so the
+// tiles resident at once share A row panels and B column panels.
+constexpr int NXCD = 8, GROUP = 8;
+__device__ __forceinline__ int xcd_remap(int bid, int total)
+{
+    const int per = total / NXCD, rem = total % NXCD;
+    const int x = bid % NXCD, q = bid / NXCD;
+    return x * per + (x < rem ? x : rem) + q;
+}
+
+// One tile of C per workgroup: four waves in a 2 x 2 grid, each owning
+// WMB x WNB MFMA blocks of 16 x 16, so the tile is (32 WMB) x (32 WNB).
 // AMC: A's row index is contiguous (column-major A); else A's k index is.
 // BNC: B's row index (the n index of C) is contiguous; else its k index is.
 // CMC: C's row index is contiguous.
-template <typename T, bool AMC, bool BNC, bool CMC>
-__global__ __launch_bounds__(NTH) void gemm_kernel(GemmParams<T> p)
+template <typename T, bool AMC, bool BNC, bool CMC, int WMB, int WNB>
+__global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(GemmParams<T> p)
 {
+    constexpr int BM = 32 * WMB, BN = 32 * WNB;
     if (p.info && *p.info) return;
 
     int64_t ti, tj;
-    const int bid = blockIdx.x;
-    if (p.c_lower) {
-        // bid enumerates the lower triangle of tiles row by row
-        int r = (int)((sqrtf(8.0f * (float)bid + 1.0f) - 1.0f) * 0.5f);
-        while ((r + 1) * (r + 2) / 2 <= bid) r++;
-        while (r * (r + 1) / 2 > bid) r--;
-        ti = r;
-        tj = bid - r * (r + 1) / 2;
-    } else {
-        ti = bid % p.tiles_m;
-        tj = bid / p.tiles_m;
+    {
+        const int total = p.c_lower ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
+        const int bid = xcd_remap((int)blockIdx.x, total);
+        if (p.c_lower) {
+            // lower triangle of tiles, row by row
+            int r = (int)((sqrtf(8.0f * (float)bid + 1.0f) - 1.0f) * 0.5f);
+            while ((r + 1) * (r + 2) / 2 <= bid) r++;
+            while (r * (r + 1) / 2 > bid) r--;
+            ti = r;
+            tj = bid - r * (r + 1) / 2;
+        } else {
+            const int per_group = GROUP * p.tiles_n;
+            const int g = bid / per_group;
+            const int first = g * GROUP;
+            const int rows = (p.tiles_m - first) < GROUP ? (p.tiles_m - first) : GROUP;
+            const int in = bid - g * per_group;
+            ti = first + in % rows;
+            tj = in / rows;
+        }
     }
     const int64_t i0 = ti * BM, j0 = tj * BN;
     const int64_t m = p.m, n = p.n;
@@ -107,15 +149,15 @@ __global__ __launch_bounds__(NTH) void gemm_kernel(GemmParams<T> p)
     if (p.triB == TRI_LOWER || p.triB == TRI_SLOWER) ke = ke < j0 + BN ? ke : j0 + BN;
     if (p.triB == TRI_UPPER || p.triB == TRI_SUPPER) kb = kb > j0 ? kb : j0;
 
-    __shared__ T As[2][BK][BM + LPAD];
-    __shared__ T Bs[2][BK][BN + LPAD];
+    __shared__ __attribute__((aligned(16))) T As[2][BM][KP];
+    __shared__ __attribute__((aligned(16))) T Bs[2][BN][KP];
 
     const int t = threadIdx.x;
     const int lane = t & 63, w = t >> 6;
     const int wm = w & 1, wn = w >> 1;
 
     constexpr int EA = BM * BK / NTH;  // elements of each operand tile per thread
-    // per-thread coordinates inside a tile
+    constexpr int EB = BN * BK / NTH;
     const int a_i = AMC ? (t % BM) : (t / BK);
     const int a_k = AMC ? (t / BM) : (t % BK);
     const int b_j = BNC ? (t % BN) : (t / BK);
@@ -123,96 +165,181 @@ __global__ __launch_bounds__(NTH) void gemm_kernel(GemmParams<T> p)
     constexpr int A_STEP = AMC ? NTH / BM : NTH / BK;  // along k (AMC) or i
     constexpr int B_STEP = BNC ? NTH / BN : NTH / BK;
 
-    T ra[EA], rb[EA];
+    const Band ba = band_of(p.triA), bb = band_of(p.triB);
+    const int64_t kmax = p.k > 0 ? p.k - 1 : 0;
+    const bool a_nomask = p.triA == TRI_NONE, b_nomask = p.triB == TRI_NONE;
+    // Per-thread row pointers: rows are clamped into the operand once (a valid
+    // address even for the rows past the edge of a ragged tile, which are
+    // zeroed after the load), and the k position advances by pointer arithmetic.
+    int64_t a_row[AMC ? 1 : EA], b_row[BNC ? 1 : EB];
+    uint32_t a_valid = 0, b_valid = 0;
+#pragma unroll
+    for (int r = 0; r < (AMC ? 1 : EA); r++) {
+        const int64_t i = i0 + a_i + (AMC ? 0 : r * A_STEP);
+        a_row[r] = i < m ? i : m - 1;
+        a_valid |= (i < m ? 1u : 0u) << r;
+    }
+#pragma unroll
+    for (int r = 0; r < (BNC ? 1 : EB); r++) {
+        const int64_t j = j0 + b_j + (BNC ? 0 : r * B_STEP);
+        b_row[r] = j < n ? j : n - 1;
+        b_valid |= (j < n ? 1u : 0u) << r;
+    }
+    const bool a_all_rows = i0 + BM <= m, b_all_rows = j0 + BN <= n;
 
-    auto load = [&](int64_t k0) {
+    T ra[EA], rb[EB];
+
+    // Full slab [k0, k0 + BK) inside [kb, ke): no k bounds to test.
+    auto load_fast = [&](int64_t k0) {
 #pragma unroll
         for (int r = 0; r < EA; r++) {
-            int64_t i = i0 + (AMC ? a_i : a_i + r * A_STEP);
-            int64_t kk = k0 + (AMC ? a_k + r * A_STEP : a_k);
-            bool ok = i < m && kk < ke && keep(p.triA, i, kk);
-            ra[r] = ok ? (AMC ? p.A[i + kk * p.lda] : p.A[i * p.lda + kk]) : T(0);
+            const int64_t kk = k0 + a_k + (AMC ? r * A_STEP : 0);
+            ra[r] = AMC ? p.A[a_row[0] + kk * p.lda] : p.A[a_row[r] * p.lda + kk];
         }
 #pragma unroll
+        for (int r = 0; r < EB; r++) {
+            const int64_t kk = k0 + b_k + (BNC ? r * B_STEP : 0);
+            rb[r] = BNC ? p.B[b_row[0] + kk * p.ldb] : p.B[b_row[r] * p.ldb + kk];
+        }
+        if (!a_all_rows || !a_nomask) {
+#pragma unroll
+            for (int r = 0; r < EA; r++) {
+                const int64_t i = i0 + a_i + (AMC ? 0 : r * A_STEP);
+                const int64_t d = k0 + a_k + (AMC ? r * A_STEP : 0) - i;
+                const bool ok = ((a_valid >> (AMC ? 0 : r)) & 1u) && d >= ba.lo && d <= ba.hi;
+                ra[r] = ok ? ra[r] : T(0);
+            }
+        }
+        if (!b_all_rows || !b_nomask) {
+#pragma unroll
+            for (int r = 0; r < EB; r++) {
+                const int64_t j = j0 + b_j + (BNC ? 0 : r * B_STEP);
+                const int64_t d = k0 + b_k + (BNC ? r * B_STEP : 0) - j;
+                const bool ok = ((b_valid >> (BNC ? 0 : r)) & 1u) && d >= bb.lo && d <= bb.hi;
+                rb[r] = ok ? rb[r] : T(0);
+            }
+        }
+    };
+    // Ragged last slab: k clamped into the operand, entries at or past ke zeroed.
+    auto load_tail = [&](int64_t k0) {
+#pragma unroll
         for (int r = 0; r < EA; r++) {
-            int64_t j = j0 + (BNC ? b_j : b_j + r * B_STEP);
-            int64_t kk = k0 + (BNC ? b_k + r * B_STEP : b_k);
-            bool ok = j < n && kk < ke && keep(p.triB, j, kk);
-            rb[r] = ok ? (BNC ? p.B[j + kk * p.ldb] : p.B[j * p.ldb + kk]) : T(0);
+            const int64_t i = i0 + a_i + (AMC ? 0 : r * A_STEP);
+            const int64_t kk = k0 + a_k + (AMC ? r * A_STEP : 0);
+            const int64_t kc = kk < kmax ? kk : kmax;
+            const T v = AMC ? p.A[a_row[0] + kc * p.lda] : p.A[a_row[r] * p.lda + kc];
+            const int64_t d = kk - i;
+            const bool ok = ((a_valid >> (AMC ? 0 : r)) & 1u) && kk < ke && d >= ba.lo && d <= ba.hi;
+            ra[r] = ok ? v : T(0);
+        }
+#pragma unroll
+        for (int r = 0; r < EB; r++) {
+            const int64_t j = j0 + b_j + (BNC ? 0 : r * B_STEP);
+            const int64_t kk = k0 + b_k + (BNC ? r * B_STEP : 0);
+            const int64_t kc = kk < kmax ? kk : kmax;
+            const T v = BNC ? p.B[b_row[0] + kc * p.ldb] : p.B[b_row[r] * p.ldb + kc];
+            const int64_t d = kk - j;
+            const bool ok = ((b_valid >> (BNC ? 0 : r)) & 1u) && kk < ke && d >= bb.lo && d <= bb.hi;
+            rb[r] = ok ? v : T(0);
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int r = 0; r < EA; r++) {
-            if (AMC) As[buf][a_k + r * A_STEP][a_i] = ra[r];
-            else As[buf][a_k][a_i + r * A_STEP] = ra[r];
+            if (AMC) As[buf][a_i][a_k + r * A_STEP] = ra[r];
+            else As[buf][a_i + r * A_STEP][a_k] = ra[r];
         }
 #pragma unroll
-        for (int r = 0; r < EA; r++) {
-            if (BNC) Bs[buf][b_k + r * B_STEP][b_j] = rb[r];
-            else Bs[buf][b_k][b_j + r * B_STEP] = rb[r];
+        for (int r = 0; r < EB; r++) {
+            if (BNC) Bs[buf][b_j][b_k + r * B_STEP] = rb[r];
+            else Bs[buf][b_j + r * B_STEP][b_k] = rb[r];
         }
     };
 
     typedef typename Mfma<T>::acc acc_t;
-    acc_t acc[4][4];
+    typedef typename Vec2<T>::type v2_t;
+    acc_t acc[WMB][WNB];
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+    for (int a = 0; a < WMB; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++) acc[a][b] = acc_t{0, 0, 0, 0};
+        for (int b = 0; b < WNB; b++) acc[a][b] = acc_t{0, 0, 0, 0};
 
-    const int64_t nslab = ke > kb ? (ke - kb + BK - 1) / BK : 0;
+    // Each ds_read_b128 brings two k values (2g, 2g+1 of an 8-wide k group,
+    // g = lane / 16) for two MFMA k-steps; A and B use the same assignment, so
+    // every k of the group is summed exactly once.
+    const int lrow = lane & 15, lk = 2 * (lane >> 4);
+    auto compute = [&](int buf) {
+#pragma unroll
+        for (int kg = 0; kg < BK; kg += 8) {
+            v2_t af[WMB], bf[WNB];
+#pragma unroll
+            for (int x = 0; x < WMB; x++)
+                af[x] = *reinterpret_cast<const v2_t*>(&As[buf][wm * (BM / 2) + x * 16 + lrow][kg + lk]);
+#pragma unroll
+            for (int x = 0; x < WNB; x++)
+                bf[x] = *reinterpret_cast<const v2_t*>(&Bs[buf][wn * (BN / 2) + x * 16 + lrow][kg + lk]);
+#pragma unroll
+            for (int a = 0; a < WMB; a++)
+#pragma unroll
+                for (int b = 0; b < WNB; b++) acc[a][b] = Mfma<T>::op(af[a].x, bf[b].x, acc[a][b]);
+#pragma unroll
+            for (int a = 0; a < WMB; a++)
+#pragma unroll
+                for (int b = 0; b < WNB; b++) acc[a][b] = Mfma<T>::op(af[a].y, bf[b].y, acc[a][b]);
+        }
+    };
+
+    const int64_t span = ke > kb ? ke - kb : 0;
+    const int64_t nfull = span / BK, nslab = (span + BK - 1) / BK;
     if (nslab > 0) {
-        load(kb);
+        if (nfull > 0) load_fast(kb);
+        else load_tail(kb);
         store(0);
         __syncthreads();
-        for (int64_t s = 0; s < nslab; s++) {
-            const int buf = (int)(s & 1);
-            if (s + 1 < nslab) load(kb + (s + 1) * BK);
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 4) {
-                T af[4], bf[4];
-                const int kr = kk + (lane >> 4);
-#pragma unroll
-                for (int x = 0; x < 4; x++) af[x] = As[buf][kr][wm * 64 + x * 16 + (lane & 15)];
-#pragma unroll
-                for (int x = 0; x < 4; x++) bf[x] = Bs[buf][kr][wn * 64 + x * 16 + (lane & 15)];
-#pragma unroll
-                for (int a = 0; a < 4; a++)
-#pragma unroll
-                    for (int b = 0; b < 4; b++) acc[a][b] = Mfma<T>::op(af[a], bf[b], acc[a][b]);
-            }
-            if (s + 1 < nslab) store(buf ^ 1);
+        int64_t s = 0;
+        // steady state: the slab being prefetched is a full one
+        for (; s + 1 < nfull; s++) {
+            load_fast(kb + (s + 1) * BK);
+            compute((int)(s & 1));
+            store((int)((s + 1) & 1));
             __syncthreads();
         }
+        if (s + 1 < nslab) {  // a ragged slab follows the last full one
+            load_tail(kb + (s + 1) * BK);
+            compute((int)(s & 1));
+            store((int)((s + 1) & 1));
+            __syncthreads();
+            s++;
+        }
+        compute((int)(s & 1));
     }
 
     // accumulator (a, b)[r] holds C(row, col) with
-    // row = wm*64 + a*16 + Mfma<T>::row(lane, r), col = wn*64 + b*16 + lane%16
+    // row = wm*BM/2 + a*16 + Mfma<T>::row(lane, r), col = wn*BN/2 + b*16 + lane%16
     const int cl = lane & 15;
     if (p.W) {
         T* W = p.W + (int64_t)blockIdx.z * m * n;
 #pragma unroll
-        for (int a = 0; a < 4; a++)
+        for (int a = 0; a < WMB; a++)
 #pragma unroll
-            for (int b = 0; b < 4; b++) {
-                const int64_t j = j0 + wn * 64 + b * 16 + cl;
+            for (int b = 0; b < WNB; b++) {
+                const int64_t j = j0 + wn * (BN / 2) + b * 16 + cl;
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const int64_t i = i0 + wm * 64 + a * 16 + Mfma<T>::row(lane, r);
+                    const int64_t i = i0 + wm * (BM / 2) + a * 16 + Mfma<T>::row(lane, r);
                     if (i < m && j < n) W[j * m + i] = acc[a][b][r];
                 }
             }
         return;
     }
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+    for (int a = 0; a < WMB; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++) {
-            const int64_t j = j0 + wn * 64 + b * 16 + cl;
+        for (int b = 0; b < WNB; b++) {
+            const int64_t j = j0 + wn * (BN / 2) + b * 16 + cl;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int64_t i = i0 + wm * 64 + a * 16 + Mfma<T>::row(lane, r);
+                const int64_t i = i0 + wm * (BM / 2) + a * 16 + Mfma<T>::row(lane, r);
                 if (i < m && j < n && (!p.c_lower || i >= j)) {
                     T* c = CMC ? &p.C[i + j * p.ldc] : &p.C[i * p.ldc + j];
                     T v = p.alpha * acc[a][b][r];
@@ -243,10 +370,117 @@ __global__ __launch_bounds__(256) void splitk_reduce(GemmParams<T> p, int nsplit
     *c = v;
 }
 
-template <typename T, bool AMC, bool BNC, bool CMC>
-static void launch(const GemmParams<T>& p, dim3 grid, hipStream_t s)
+template <typename T>
+static constexpr const char* tname() { return sizeof(T) == 8 ? "double" : "float"; }
+
+// Demangled kernel names as rocprofv3 prints them.
+template <typename T, bool AMC, bool BNC, bool CMC, int WMB, int WNB>
+static const char* kname()
 {
-    hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC>), grid, dim3(NTH), 0, s, p);
+    static char buf[112];
+    if (!buf[0])
+        snprintf(buf, sizeof buf, "rfp::gemm_kernel<%s, %s, %s, %s, %d, %d>(rfp::GemmParams<%s>)", tname<T>(),
+                 AMC ? "true" : "false", BNC ? "true" : "false", CMC ? "true" : "false", WMB, WNB, tname<T>());
+    return buf;
+}
+
+// Algorithmic work of one launch: multiply-adds over the entries of C that
+// are computed and the k-range each one needs once triangular operands are
+// taken into account (zero entries of a masked operand are not work).
+static double tri_pairs(int tri, int64_t rows, int64_t k)
+{
+    // number of kept (row, kk) pairs of an operand of `rows` x `k` under mask tri
+    auto lower = [](int64_t r, int64_t c, int64_t d) {  // #(i,j): i - j >= d
+        double s = 0;
+        for (int64_t i = 0; i < r; i++) {
+            int64_t hi = i - d + 1;
+            s += hi <= 0 ? 0 : (double)(hi < c ? hi : c);
+        }
+        return s;
+    };
+    switch (tri) {
+        case TRI_LOWER: return lower(rows, k, 0);
+        case TRI_SLOWER: return lower(rows, k, 1);
+        case TRI_UPPER: return (double)rows * k - lower(rows, k, 1);
+        case TRI_SUPPER: return (double)rows * k - lower(rows, k, 0);
+        default: return (double)rows * k;
+    }
+}
+
+template <typename T>
+static double gemm_flops(const GemmParams<T>& p)
+{
+    double cells = p.c_lower ? 0.5 * (double)p.m * (double)(p.m + 1) : (double)p.m * (double)p.n;
+    double kfrac = 1.0;
+    if (p.k > 0) {
+        if (p.triA) kfrac *= tri_pairs(p.triA, p.m, p.k) / ((double)p.m * p.k);
+        if (p.triB) kfrac *= tri_pairs(p.triB, p.n, p.k) / ((double)p.n * p.k);
+    }
+    return 2.0 * cells * (double)p.k * kfrac;
+}
+
+template <typename T>
+static double gemm_bytes(const GemmParams<T>& p)
+{
+    double cells = p.c_lower ? 0.5 * (double)p.m * (double)(p.m + 1) : (double)p.m * (double)p.n;
+    return sizeof(T) * ((double)p.m * p.k + (double)p.n * p.k + cells * (p.beta != T(0) ? 2.0 : 1.0));
+}
+
+template <typename T, bool AMC, bool BNC, bool CMC>
+static void launch(const GemmParams<T>& p, dim3 grid, int tile, const Exec& ex)
+{
+    switch (tile) {
+        case 0: {
+            ProfScope ps(ex, kname<T, AMC, BNC, CMC, 4, 4>(), gemm_flops(p), gemm_bytes(p));
+            hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC, 4, 4>), grid, dim3(NTH), 0, ex.stream, p);
+        } break;
+        case 1: {
+            ProfScope ps(ex, kname<T, AMC, BNC, CMC, 2, 4>(), gemm_flops(p), gemm_bytes(p));
+            hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC, 2, 4>), grid, dim3(NTH), 0, ex.stream, p);
+        } break;
+        case 2: {
+            ProfScope ps(ex, kname<T, AMC, BNC, CMC, 4, 2>(), gemm_flops(p), gemm_bytes(p));
+            hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC, 4, 2>), grid, dim3(NTH), 0, ex.stream, p);
+        } break;
+        default: {
+            ProfScope ps(ex, kname<T, AMC, BNC, CMC, 2, 2>(), gemm_flops(p), gemm_bytes(p));
+            hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC, 2, 2>), grid, dim3(NTH), 0, ex.stream, p);
+        } break;
+    }
+}
+
+// Tile shapes (BM x BN): 0 = 128 x 128, 1 = 64 x 128, 2 = 128 x 64, 3 = 64 x 64.
+static const int TILE_BM[4] = {128, 64, 128, 64};
+static const int TILE_BN[4] = {128, 128, 64, 64};
+
+// Pick the largest tile that still gives the chip enough workgroups.  A
+// dimension of at most 128 is always covered by a single tile, which keeps the
+// in-place products (C aliasing A or B over that dimension) race-free.
+static int pick_tile(int64_t m, int64_t n, bool c_lower, int64_t* tm, int64_t* tn)
+{
+    const int64_t want = 512;  // two workgroups per CU on 256 CUs
+    int best = -1;
+    int64_t best_tiles = -1;
+    for (int t = 0; t < 4; t++) {
+        const int bm = TILE_BM[t], bn = TILE_BN[t];
+        if (c_lower && bm != bn) continue;
+        if (m <= 128 && bm < m) continue;
+        if (n <= 128 && bn < n) continue;
+        const int64_t a = (m + bm - 1) / bm, b = (n + bn - 1) / bn;
+        const int64_t tiles = c_lower ? a * (a + 1) / 2 : a * b;
+        if (tiles >= want) {
+            best = t;
+            best_tiles = tiles;
+            break;
+        }
+        if (tiles > best_tiles) {
+            best = t;
+            best_tiles = tiles;
+        }
+    }
+    *tm = (m + TILE_BM[best] - 1) / TILE_BM[best];
+    *tn = (n + TILE_BN[best] - 1) / TILE_BN[best];
+    return best;
 }
 
 template <typename T>
@@ -277,9 +511,11 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
     p.triB = triB;
     p.c_lower = c_lower ? 1 : 0;
     p.info = ex.info;
-    const int64_t tm = (m + BM - 1) / BM, tn = (n + BN - 1) / BN;
+    int64_t tm, tn;
+    const int tile = pick_tile(m, n, c_lower, &tm, &tn);
     const int64_t ntiles = c_lower ? tm * (tm + 1) / 2 : tm * tn;
     p.tiles_m = (int)tm;
+    p.tiles_n = (int)tn;
 
     // split K when the tile grid cannot fill the chip and K is long
     int64_t nsplit = 1;
@@ -303,18 +539,24 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
     dim3 grid((unsigned)ntiles, 1, (unsigned)nsplit);
     const int sel = (amc ? 4 : 0) | (bnc ? 2 : 0) | (cmc ? 1 : 0);
     switch (sel) {
-        case 0: launch<T, false, false, false>(p, grid, ex.stream); break;
-        case 1: launch<T, false, false, true>(p, grid, ex.stream); break;
-        case 2: launch<T, false, true, false>(p, grid, ex.stream); break;
-        case 3: launch<T, false, true, true>(p, grid, ex.stream); break;
-        case 4: launch<T, true, false, false>(p, grid, ex.stream); break;
-        case 5: launch<T, true, false, true>(p, grid, ex.stream); break;
-        case 6: launch<T, true, true, false>(p, grid, ex.stream); break;
-        default: launch<T, true, true, true>(p, grid, ex.stream); break;
+        case 0: launch<T, false, false, false>(p, grid, tile, ex); break;
+        case 1: launch<T, false, false, true>(p, grid, tile, ex); break;
+        case 2: launch<T, false, true, false>(p, grid, tile, ex); break;
+        case 3: launch<T, false, true, true>(p, grid, tile, ex); break;
+        case 4: launch<T, true, false, false>(p, grid, tile, ex); break;
+        case 5: launch<T, true, false, true>(p, grid, tile, ex); break;
+        case 6: launch<T, true, true, false>(p, grid, tile, ex); break;
+        default: launch<T, true, true, true>(p, grid, tile, ex); break;
     }
     if (nsplit > 1) {
         const int64_t total = m * n;
         dim3 g((unsigned)((total + 255) / 256));
+        static char rn[2][80];
+        const int ci = cmc ? 1 : 0;
+        if (!rn[ci][0])
+            snprintf(rn[ci], sizeof rn[ci], "rfp::splitk_reduce<%s, %s>(rfp::GemmParams<%s>, int)", tname<T>(),
+                     cmc ? "true" : "false", tname<T>());
+        ProfScope ps(ex, rn[ci], (double)nsplit * total, sizeof(T) * (double)(nsplit + 1) * total);
         if (cmc) hipLaunchKernelGGL((splitk_reduce<T, true>), g, dim3(256), 0, ex.stream, p, (int)nsplit);
         else hipLaunchKernelGGL((splitk_reduce<T, false>), g, dim3(256), 0, ex.stream, p, (int)nsplit);
     }

@@ -6,6 +6,8 @@
 // is within the wavefront.  Every store back into the RFP array is masked to
 // the block's own lower triangle: the other triangle of a diagonal block is
 // the other diagonal block's data.
+#include <cstdio>
+
 #include "rfp_common.h"
 
 namespace rfp {
@@ -179,8 +181,20 @@ __global__ __launch_bounds__(64) void lauum_leaf_kernel(Mat<T> A, int nb, const 
 }
 
 template <typename T>
+static const char* lname(const char* kern, const char* args)
+{
+    // demangled name as rocprofv3 prints it, e.g. "rfp::potrf_leaf_kernel<double>(...)"
+    static thread_local char buf[160];
+    snprintf(buf, sizeof buf, "rfp::%s<%s>(%s)", kern, sizeof(T) == 8 ? "double" : "float", args);
+    return buf;
+}
+
+template <typename T>
 hipError_t potrf_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info_base)
 {
+    ProfScope ps(ex, lname<T>("potrf_leaf_kernel", sizeof(T) == 8 ? "rfp::Mat<double>, int, double*, int*, long"
+                                                                  : "rfp::Mat<float>, int, float*, int*, long"),
+                 (double)nb * nb * nb / 3.0 + (double)nb * nb * nb / 3.0, sizeof(T) * (double)nb * nb * 1.5);
     hipLaunchKernelGGL((potrf_leaf_kernel<T>), dim3(1), dim3(64), 0, ex.stream, A, nb, winv, ex.info, info_base);
     return hipGetLastError();
 }
@@ -188,6 +202,9 @@ hipError_t potrf_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info_ba
 template <typename T>
 hipError_t trtri_leaf(const Exec& ex, Mat<T> A, int nb, int64_t info_base)
 {
+    ProfScope ps(ex, lname<T>("trtri_leaf_kernel", sizeof(T) == 8 ? "rfp::Mat<double>, int, int*, long"
+                                                                  : "rfp::Mat<float>, int, int*, long"),
+                 (double)nb * nb * nb / 3.0, sizeof(T) * (double)nb * nb);
     hipLaunchKernelGGL((trtri_leaf_kernel<T>), dim3(1), dim3(64), 0, ex.stream, A, nb, ex.info, info_base);
     return hipGetLastError();
 }
@@ -197,6 +214,9 @@ hipError_t trtri_leaves(const Exec& ex, Mat<const T> A, int64_t n, T* winv)
 {
     if (n <= 0) return hipSuccess;
     const int64_t nl = (n + NB - 1) / NB;
+    ProfScope ps(ex, lname<T>("trtri_leaves_kernel", sizeof(T) == 8 ? "rfp::Mat<double const>, long, double*"
+                                                                    : "rfp::Mat<float const>, long, float*"),
+                 (double)nl * NB * NB * NB / 3.0, sizeof(T) * (double)nl * NB * NB * 1.5);
     hipLaunchKernelGGL((trtri_leaves_kernel<T>), dim3((unsigned)nl), dim3(64), 0, ex.stream, A, n, winv);
     return hipGetLastError();
 }
@@ -204,6 +224,9 @@ hipError_t trtri_leaves(const Exec& ex, Mat<const T> A, int64_t n, T* winv)
 template <typename T>
 hipError_t lauum_leaf(const Exec& ex, Mat<T> A, int nb)
 {
+    ProfScope ps(ex, lname<T>("lauum_leaf_kernel", sizeof(T) == 8 ? "rfp::Mat<double>, int, int const*"
+                                                                  : "rfp::Mat<float>, int, int const*"),
+                 (double)nb * nb * nb / 3.0, sizeof(T) * (double)nb * nb);
     hipLaunchKernelGGL((lauum_leaf_kernel<T>), dim3(1), dim3(64), 0, ex.stream, A, nb, (const int*)ex.info);
     return hipGetLastError();
 }

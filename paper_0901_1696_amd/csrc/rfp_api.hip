@@ -13,9 +13,90 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <string>
+#include <vector>
 
 #include "rfp.h"
 #include "rfp_common.h"
+
+namespace rfp {
+
+// Per-launch event timing.  Event pairs come from a pool; when the pool is
+// used up the finished pairs are folded into per-kernel totals (this waits
+// for the last recorded launch).
+struct Profiler {
+    struct Rec {
+        std::string name;
+        int ev;
+        double flops, bytes;
+    };
+    struct Agg {
+        int64_t launches = 0;
+        double ms = 0, flops = 0, bytes = 0;
+    };
+    static constexpr int POOL_PAIRS = 16384;
+    std::vector<hipEvent_t> pool;
+    std::vector<Rec> pending;
+    std::map<std::string, Agg> agg;
+    int used = 0;
+    hipError_t err = hipSuccess;
+
+    int begin(const char* name, double flops, double bytes, hipStream_t s)
+    {
+        if (used == POOL_PAIRS) fold();
+        if ((int)pool.size() < 2 * (used + 1)) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+                err = hipErrorOutOfMemory;
+                return -1;
+            }
+            pool.push_back(a);
+            pool.push_back(b);
+        }
+        const int ev = 2 * used++;
+        pending.push_back(Rec{name, ev, flops, bytes});
+        (void)hipEventRecord(pool[ev], s);
+        return ev;
+    }
+    void end(int ev, hipStream_t s)
+    {
+        if (ev >= 0) (void)hipEventRecord(pool[ev + 1], s);
+    }
+    void fold()
+    {
+        for (const Rec& r : pending) {
+            float ms = 0;
+            if (hipEventSynchronize(pool[r.ev + 1]) != hipSuccess ||
+                hipEventElapsedTime(&ms, pool[r.ev], pool[r.ev + 1]) != hipSuccess)
+                err = hipErrorUnknown;
+            Agg& a = agg[r.name];
+            a.launches++;
+            a.ms += ms;
+            a.flops += r.flops;
+            a.bytes += r.bytes;
+        }
+        pending.clear();
+        used = 0;
+    }
+    ~Profiler()
+    {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+ProfScope::ProfScope(const Exec& ex, const char* name, double flops, double bytes)
+    : p(ex.prof), slot(-1), stream(ex.stream)
+{
+    if (p) slot = p->begin(name, flops, bytes, stream);
+}
+
+ProfScope::~ProfScope()
+{
+    if (p) p->end(slot, stream);
+}
+
+}  // namespace rfp
 
 struct rfp_context {
     int device;
@@ -23,6 +104,7 @@ struct rfp_context {
     size_t splitk_bytes;
     void* inv;
     size_t inv_bytes;
+    rfp::Profiler* prof;
 };
 
 namespace rfp {
@@ -339,6 +421,7 @@ static Run<T> make_run(rfp_context* h, hipStream_t s, int* info)
     r.ex.info = info;
     r.ex.splitk_ws = h->splitk;
     r.ex.splitk_bytes = h->splitk_bytes;
+    r.ex.prof = h->prof;
     return r;
 }
 
@@ -534,9 +617,54 @@ int rfp_destroy(rfp_handle_t h)
         (void)hipDeviceSynchronize();
         if (h->splitk) (void)hipFree(h->splitk);
         if (h->inv) (void)hipFree(h->inv);
+        delete h->prof;
     }
     std::free(h);
     return 0;
+}
+
+int rfp_profile_enable(rfp_handle_t h, int on)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    DeviceGuard g(h->device);
+    if (on && !h->prof) h->prof = new Profiler();
+    if (!on && h->prof) {
+        (void)hipDeviceSynchronize();
+        delete h->prof;
+        h->prof = nullptr;
+    }
+    return 0;
+}
+
+int rfp_profile_read(rfp_handle_t h, rfp_profile_entry* out, int cap, int* count)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (!count || cap < 0 || (cap > 0 && !out)) return -4;
+    *count = 0;
+    if (!h->prof) return 0;
+    DeviceGuard g(h->device);
+    Profiler* p = h->prof;
+    p->fold();
+    int i = 0;
+    for (const auto& kv : p->agg) {
+        if (i < cap) {
+            rfp_profile_entry* e = &out[i];
+            std::memset(e, 0, sizeof(*e));
+            std::strncpy(e->name, kv.first.c_str(), sizeof(e->name) - 1);
+            e->launches = kv.second.launches;
+            e->total_ms = kv.second.ms;
+            e->flops = kv.second.flops;
+            e->bytes = kv.second.bytes;
+        }
+        i++;
+    }
+    *count = i;
+    const hipError_t err = p->err;
+    if (i <= cap) {  // everything delivered: start new totals
+        p->agg.clear();
+        p->err = hipSuccess;
+    }
+    return err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
 int rfp_dtrttf(rfp_handle_t h, char transr, char uplo, int64_t n, const double* a, int64_t lda, double* arf,

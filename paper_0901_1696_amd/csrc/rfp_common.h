@@ -71,12 +71,26 @@ inline int64_t rec_split(int64_t n)
     return ((nblk + 1) / 2) * NB;
 }
 
+struct Profiler;
+
 // Per-call execution context.
 struct Exec {
     hipStream_t stream;
     int* info;          // device; kernels of a factorization exit early when *info != 0
     void* splitk_ws;    // split-K partial sums
     size_t splitk_bytes;
+    Profiler* prof;     // optional per-launch event timing
+};
+
+// Brackets one kernel launch with HIP events on the launch stream when
+// profiling is enabled; `name` is the kernel's demangled name, `flops` and
+// `bytes` its algorithmic work for this launch.
+struct ProfScope {
+    Profiler* p;
+    int slot;
+    hipStream_t stream;
+    ProfScope(const Exec& ex, const char* name, double flops, double bytes);
+    ~ProfScope();
 };
 
 // C(m x n) = alpha * A(m x k) * B(n x k)^T + beta * C.
@@ -90,7 +104,7 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
 
 // Leaf kernels (order nb <= NB, one wavefront per block).
 // potrf: in-place Cholesky of the lower triangle of A; writes L^{-1} (NB x NB,
-// column-major, zero above the diagonal) to winv; *info = info_base + j + 1 on
+// row-major, zero above the diagonal, identity-padded) to winv; *info = info_base + j + 1 on
 // the first non-positive pivot j.
 template <typename T>
 hipError_t potrf_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info_base);
