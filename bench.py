@@ -66,7 +66,7 @@ def traffic_for(kernel_name):
     return rec.get("kernels", {}).get(kernel_name, {}).get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(n=6000, nrhs=128):
+def cpu_baseline(n=12000, nrhs=128):
     """The oracle (definition-path PFTRF + PFTRS) on the host, bounded sample."""
     import numpy as np
     import oracle
@@ -102,7 +102,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pftri", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        nel = args.calibrate_copy // 8
+        src = torch.rand(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": nel * 8, "calibrate_copy_bytes_written": nel * 8,
+                          "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built.",
               file=sys.stderr)
