@@ -131,7 +131,8 @@ int rfp_profile_read(rfp_handle_t h, rfp_profile_entry* out, int cap, int* count
  *     i <= j, 3 strictly lower, 4 strictly upper, in the operand's own
  *     indices) and, when c_lower, only C's lower triangle computed.
  *   RFP_PLAN_POTRF_LEAF: Cholesky of the lower triangle of a (order m); the
- *     leaf's inverse goes to view b (row-major NB x NB); INFO base info_base.
+ *     leaf's inverse goes to view b (row-major, block order = b's row stride);
+ *     INFO base info_base.
  *   RFP_PLAN_TRTRI_LEAF: in-place inverse of the lower triangle of a.
  *   RFP_PLAN_TRTRI_LEAVES: inverses of all 64-row diagonal blocks of the lower
  *     triangular a (order m) into consecutive NB x NB row-major blocks at b.
@@ -149,6 +150,7 @@ enum {
 enum { RFP_PLAN_BUF_ARF = 0, RFP_PLAN_BUF_B = 1, RFP_PLAN_BUF_WORK = 2, RFP_PLAN_BUF_INFO = 3 };
 typedef struct {
     int32_t kind, tri_a, tri_b, c_lower;
+    int32_t inplace, reserved; /* GEMM: C aliases A or B (one tile spans the aliased dimension) */
     int64_t m, n, k;
     double alpha, beta;
     int64_t a[4], b[4], c[4]; /* buffer (-1: unused), offset, row stride, column stride */

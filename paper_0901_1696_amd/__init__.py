@@ -68,7 +68,8 @@ PLAN_BUF_ARF, PLAN_BUF_B, PLAN_BUF_WORK = 0, 1, 2
 class PlanOp(ctypes.Structure):
     """One record of ``rfp_plan`` (layout of ``rfp_plan_op`` in include/rfp.h)."""
     _fields_ = [("kind", ctypes.c_int32), ("tri_a", ctypes.c_int32), ("tri_b", ctypes.c_int32),
-                ("c_lower", ctypes.c_int32), ("m", _i64), ("n", _i64), ("k", _i64),
+                ("c_lower", ctypes.c_int32), ("inplace", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("m", _i64), ("n", _i64), ("k", _i64),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("a", _i64 * 4), ("b", _i64 * 4), ("c", _i64 * 4), ("info_base", _i64)]
 

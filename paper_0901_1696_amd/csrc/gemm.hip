@@ -453,10 +453,10 @@ static void launch(const GemmParams<T>& p, dim3 grid, int tile, const Exec& ex)
 static const int TILE_BM[4] = {128, 64, 128, 64};
 static const int TILE_BN[4] = {128, 128, 64, 64};
 
-// Pick the largest tile that still gives the chip enough workgroups.  A
-// dimension of at most 128 is always covered by a single tile, which keeps the
-// in-place products (C aliasing A or B over that dimension) race-free.
-static int pick_tile(int64_t m, int64_t n, bool c_lower, int64_t* tm, int64_t* tn)
+// Pick the largest tile that still gives the chip enough workgroups.  For an
+// in-place product a dimension of at most 128 is covered by a single tile, so
+// each workgroup owns whole rows (C aliasing A) or columns (C aliasing B).
+static int pick_tile(int64_t m, int64_t n, bool c_lower, bool inplace, int64_t* tm, int64_t* tn)
 {
     const int64_t want = 512;  // two workgroups per CU on 256 CUs
     int best = -1;
@@ -464,8 +464,8 @@ static int pick_tile(int64_t m, int64_t n, bool c_lower, int64_t* tm, int64_t* t
     for (int t = 0; t < 4; t++) {
         const int bm = TILE_BM[t], bn = TILE_BN[t];
         if (c_lower && bm != bn) continue;
-        if (m <= 128 && bm < m) continue;
-        if (n <= 128 && bn < n) continue;
+        if (inplace && m <= 128 && bm < m) continue;
+        if (inplace && n <= 128 && bn < n) continue;
         const int64_t a = (m + bm - 1) / bm, b = (n + bn - 1) / bn;
         const int64_t tiles = c_lower ? a * (a + 1) / 2 : a * b;
         if (tiles >= want) {
@@ -485,9 +485,10 @@ static int pick_tile(int64_t m, int64_t n, bool c_lower, int64_t* tm, int64_t* t
 
 template <typename T>
 hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<const T> A, int triA,
-                Mat<const T> B, int triB, T beta, Mat<T> C, bool c_lower)
+                Mat<const T> B, int triB, T beta, Mat<T> C, bool c_lower, bool inplace)
 {
     if (m <= 0 || n <= 0) return hipSuccess;
+    if (inplace && m > 128 && n > 128) return hipErrorInvalidValue;
     if (c_lower && m != n) return hipErrorInvalidValue;
     GemmParams<T> p{};
     p.m = m;
@@ -512,7 +513,7 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
     p.c_lower = c_lower ? 1 : 0;
     p.info = ex.info;
     int64_t tm, tn;
-    const int tile = pick_tile(m, n, c_lower, &tm, &tn);
+    const int tile = pick_tile(m, n, c_lower, inplace, &tm, &tn);
     const int64_t ntiles = c_lower ? tm * (tm + 1) / 2 : tm * tn;
     p.tiles_m = (int)tm;
     p.tiles_n = (int)tn;
@@ -564,8 +565,8 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
 }
 
 template hipError_t gemm<double>(const Exec&, int64_t, int64_t, int64_t, double, Mat<const double>, int,
-                                 Mat<const double>, int, double, Mat<double>, bool);
+                                 Mat<const double>, int, double, Mat<double>, bool, bool);
 template hipError_t gemm<float>(const Exec&, int64_t, int64_t, int64_t, float, Mat<const float>, int,
-                                Mat<const float>, int, float, Mat<float>, bool);
+                                Mat<const float>, int, float, Mat<float>, bool, bool);
 
 }  // namespace rfp

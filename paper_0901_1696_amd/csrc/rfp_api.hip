@@ -4,8 +4,9 @@
 // array into T1 (A11), S (A21) and T2 (A22) and runs four full-format steps.
 // Here the same 2 x 2 partition is applied recursively: the top level is the
 // RFP split itself, and every step on T1 or T2 (POTRF, TRSM, TRTRI, TRMM,
-// LAUUM) splits its triangle again at a multiple of NB until the diagonal
-// blocks fit one wavefront.  All off-diagonal work therefore lands in large
+// LAUUM) splits its triangle again at a multiple of the leaf order until the
+// diagonal blocks fit one fused workgroup (factorization, 128) or one
+// wavefront (solve and inversion, 64).  All off-diagonal work therefore lands in large
 // GEMM-shaped products on the matrix cores, with the operands read in place
 // from the RFP rectangle through strided views.
 #include <hip/hip_runtime.h>
@@ -161,7 +162,7 @@ bool rfp_blocks(char transr, char uplo, int64_t n, RfpBlocks* o)
     return true;
 }
 
-static inline int64_t nleaves(int64_t n) { return (n + NB - 1) / NB; }
+static inline int64_t nleaves(int64_t n, int nb) { return (n + nb - 1) / nb; }
 
 // Plan recording: when a Run has a recorder, the drivers append one record
 // per primitive (GEMM or leaf kernel) instead of launching it.  Pointers are
@@ -188,6 +189,7 @@ struct Run {
     Exec ex;
     hipError_t err = hipSuccess;
     PlanRec* rec = nullptr;
+    int nb = NB;  // leaf order of this call's recursion
     void chk(hipError_t e)
     {
         if (e != hipSuccess && err == hipSuccess) err = e;
@@ -205,11 +207,12 @@ struct Run {
         return o;
     }
     void mm(int64_t m, int64_t n, int64_t k, T alpha, Mat<const T> A, int ta, Mat<const T> B, int tb, T beta,
-            Mat<T> C, bool lower = false)
+            Mat<T> C, bool lower = false, bool inplace = false)
     {
         if (rec) {
             if (rfp_plan_op* o = next(RFP_PLAN_GEMM)) {
                 o->m = m; o->n = n; o->k = k;
+                o->inplace = inplace ? 1 : 0;
                 o->alpha = (double)alpha; o->beta = (double)beta;
                 o->tri_a = ta; o->tri_b = tb; o->c_lower = lower ? 1 : 0;
                 plan_view(A.p, A.rs, A.cs, sizeof(T), o->a);
@@ -218,15 +221,15 @@ struct Run {
             }
             return;
         }
-        chk(gemm<T>(ex, m, n, k, alpha, A, ta, B, tb, beta, C, lower));
+        chk(gemm<T>(ex, m, n, k, alpha, A, ta, B, tb, beta, C, lower, inplace));
     }
-    void leaf(int kind, Mat<const T> A, int64_t nb, const T* w, int64_t info_base)
+    void leaf(int kind, Mat<const T> A, int64_t order, const T* w, int64_t info_base)
     {
         if (rfp_plan_op* o = next(kind)) {
-            o->m = nb;
+            o->m = order;
             o->info_base = info_base;
             plan_view(A.p, A.rs, A.cs, sizeof(T), o->a);
-            if (w) plan_view(w, NB, 1, sizeof(T), o->b);
+            if (w) plan_view(w, nb, 1, sizeof(T), o->b);
         }
     }
 
@@ -235,14 +238,14 @@ struct Run {
     void trsm_rlt(int64_t m, int64_t n, Mat<T> B, Mat<const T> L, const T* winv)
     {
         if (m <= 0 || n <= 0) return;
-        if (n <= NB) {
-            mm(m, n, n, T(1), B, TRI_NONE, Mat<const T>{winv, NB, 1}, TRI_LOWER, T(0), B);
+        if (n <= nb) {
+            mm(m, n, n, T(1), B, TRI_NONE, Mat<const T>{winv, nb, 1}, TRI_LOWER, T(0), B, false, true);
             return;
         }
-        const int64_t n1 = rec_split(n), n2 = n - n1;
+        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
         trsm_rlt(m, n1, B, L, winv);
         mm(m, n2, n1, T(-1), B, TRI_NONE, L.sub(n1, 0), TRI_NONE, T(1), B.sub(0, n1));
-        trsm_rlt(m, n2, B.sub(0, n1), L.sub(n1, n1), winv + nleaves(n1) * NB * NB);
+        trsm_rlt(m, n2, B.sub(0, n1), L.sub(n1, n1), winv + nleaves(n1, nb) * nb * nb);
     }
 
     // Cholesky of the lower triangle of A (order n); goff is the position of
@@ -250,16 +253,17 @@ struct Run {
     void potrf_rec(int64_t n, Mat<T> A, int64_t goff, T* winv)
     {
         if (n <= 0) return;
-        if (n <= NB) {
+        if (n <= nb) {
             if (rec) leaf(RFP_PLAN_POTRF_LEAF, A, n, winv, goff);
+            else if (nb == NB2) chk(potrf128_leaf<T>(ex, A, (int)n, winv, goff));
             else chk(potrf_leaf<T>(ex, A, (int)n, winv, goff));
             return;
         }
-        const int64_t n1 = rec_split(n), n2 = n - n1;
+        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
         potrf_rec(n1, A, goff, winv);
         trsm_rlt(n2, n1, A.sub(n1, 0), A, winv);
         mm(n2, n2, n1, T(-1), A.sub(n1, 0), TRI_NONE, A.sub(n1, 0), TRI_NONE, T(1), A.sub(n1, n1), true);
-        potrf_rec(n2, A.sub(n1, n1), goff + n1, winv + nleaves(n1) * NB * NB);
+        potrf_rec(n2, A.sub(n1, n1), goff + n1, winv + nleaves(n1, nb) * nb * nb);
     }
 
     // ---------------------------------------------------------------- solve
@@ -267,14 +271,14 @@ struct Run {
     void trsm_lln(int64_t n, int64_t r, Mat<const T> L, Mat<T> B, const T* winv)
     {
         if (n <= 0 || r <= 0) return;
-        if (n <= NB) {
-            mm(n, r, n, T(1), Mat<const T>{winv, NB, 1}, TRI_LOWER, Mat<T>(B).tr(), TRI_NONE, T(0), B);
+        if (n <= nb) {
+            mm(n, r, n, T(1), Mat<const T>{winv, nb, 1}, TRI_LOWER, Mat<T>(B).tr(), TRI_NONE, T(0), B, false, true);
             return;
         }
-        const int64_t n1 = rec_split(n), n2 = n - n1;
+        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
         trsm_lln(n1, r, L, B, winv);
         mm(n2, r, n1, T(-1), L.sub(n1, 0), TRI_NONE, B.tr(), TRI_NONE, T(1), B.sub(n1, 0));
-        trsm_lln(n2, r, L.sub(n1, n1), B.sub(n1, 0), winv + nleaves(n1) * NB * NB);
+        trsm_lln(n2, r, L.sub(n1, n1), B.sub(n1, 0), winv + nleaves(n1, nb) * nb * nb);
     }
     // B (n x r) <- L^{-T} B
     void leaves_inv(Mat<const T> A, int64_t n, T* winv)
@@ -289,12 +293,12 @@ struct Run {
     void trsm_llt(int64_t n, int64_t r, Mat<const T> L, Mat<T> B, const T* winv)
     {
         if (n <= 0 || r <= 0) return;
-        if (n <= NB) {
-            mm(n, r, n, T(1), Mat<const T>{winv, 1, NB}, TRI_UPPER, B.tr(), TRI_NONE, T(0), B);
+        if (n <= nb) {
+            mm(n, r, n, T(1), Mat<const T>{winv, 1, nb}, TRI_UPPER, B.tr(), TRI_NONE, T(0), B, false, true);
             return;
         }
-        const int64_t n1 = rec_split(n), n2 = n - n1;
-        trsm_llt(n2, r, L.sub(n1, n1), B.sub(n1, 0), winv + nleaves(n1) * NB * NB);
+        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
+        trsm_llt(n2, r, L.sub(n1, n1), B.sub(n1, 0), winv + nleaves(n1, nb) * nb * nb);
         mm(n1, r, n2, T(-1), L.sub(n1, 0).tr(), TRI_NONE, B.sub(n1, 0).tr(), TRI_NONE, T(1), B);
         trsm_llt(n1, r, L, B, winv);
     }
@@ -304,11 +308,11 @@ struct Run {
     void trmm_rl(int64_t m, int64_t n, Mat<T> B, Mat<const T> W, T alpha)
     {
         if (m <= 0 || n <= 0) return;
-        if (n <= NB) {
-            mm(m, n, n, alpha, B, TRI_NONE, W.tr(), TRI_UPPER, T(0), B);
+        if (n <= nb) {
+            mm(m, n, n, alpha, B, TRI_NONE, W.tr(), TRI_UPPER, T(0), B, false, true);
             return;
         }
-        const int64_t n1 = rec_split(n), n2 = n - n1;
+        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
         trmm_rl(m, n1, B, W, alpha);
         mm(m, n1, n2, alpha, B.sub(0, n1), TRI_NONE, W.sub(n1, 0).tr(), TRI_NONE, T(1), B);
         trmm_rl(m, n2, B.sub(0, n1), W.sub(n1, n1), alpha);
@@ -317,11 +321,11 @@ struct Run {
     void trmm_ll(int64_t m, int64_t n, Mat<const T> W, Mat<T> B)
     {
         if (m <= 0 || n <= 0) return;
-        if (m <= NB) {
-            mm(m, n, m, T(1), W, TRI_LOWER, B.tr(), TRI_NONE, T(0), B);
+        if (m <= nb) {
+            mm(m, n, m, T(1), W, TRI_LOWER, B.tr(), TRI_NONE, T(0), B, false, true);
             return;
         }
-        const int64_t m1 = rec_split(m), m2 = m - m1;
+        const int64_t m1 = rec_split(m, nb), m2 = m - m1;
         trmm_ll(m2, n, W.sub(m1, m1), B.sub(m1, 0));
         mm(m2, n, m1, T(1), W.sub(m1, 0), TRI_NONE, B.tr(), TRI_NONE, T(1), B.sub(m1, 0));
         trmm_ll(m1, n, W, B);
@@ -330,11 +334,11 @@ struct Run {
     void trmm_llt(int64_t m, int64_t n, Mat<const T> W, Mat<T> B)
     {
         if (m <= 0 || n <= 0) return;
-        if (m <= NB) {
-            mm(m, n, m, T(1), W.tr(), TRI_UPPER, B.tr(), TRI_NONE, T(0), B);
+        if (m <= nb) {
+            mm(m, n, m, T(1), W.tr(), TRI_UPPER, B.tr(), TRI_NONE, T(0), B, false, true);
             return;
         }
-        const int64_t m1 = rec_split(m), m2 = m - m1;
+        const int64_t m1 = rec_split(m, nb), m2 = m - m1;
         trmm_llt(m1, n, W, B);
         mm(m1, n, m2, T(1), W.sub(m1, 0).tr(), TRI_NONE, B.sub(m1, 0).tr(), TRI_NONE, T(1), B);
         trmm_llt(m2, n, W.sub(m1, m1), B.sub(m1, 0));
@@ -343,12 +347,12 @@ struct Run {
     void trtri_rec(int64_t n, Mat<T> A, int64_t goff)
     {
         if (n <= 0) return;
-        if (n <= NB) {
+        if (n <= nb) {
             if (rec) leaf(RFP_PLAN_TRTRI_LEAF, A, n, nullptr, goff);
             else chk(trtri_leaf<T>(ex, A, (int)n, goff));
             return;
         }
-        const int64_t n1 = rec_split(n), n2 = n - n1;
+        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
         trtri_rec(n1, A, goff);
         trmm_rl(n2, n1, A.sub(n1, 0), A, T(-1));
         trtri_rec(n2, A.sub(n1, n1), goff + n1);
@@ -358,12 +362,12 @@ struct Run {
     void lauum_rec(int64_t n, Mat<T> W)
     {
         if (n <= 0) return;
-        if (n <= NB) {
+        if (n <= nb) {
             if (rec) leaf(RFP_PLAN_LAUUM_LEAF, W, n, nullptr, 0);
             else chk(lauum_leaf<T>(ex, W, (int)n));
             return;
         }
-        const int64_t n1 = rec_split(n), n2 = n - n1;
+        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
         lauum_rec(n1, W);
         mm(n1, n1, n2, T(1), W.sub(n1, 0).tr(), TRI_NONE, W.sub(n1, 0).tr(), TRI_NONE, T(1), W, true);
         trmm_llt(n2, n1, W.sub(n1, n1), W.sub(n1, 0));
@@ -485,7 +489,7 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     if (!info) return -5;
     RfpBlocks b;
     rfp_blocks(transr, uplo, n, &b);
-    const int64_t lv = std::max(nleaves(b.m1), nleaves(b.m2));
+    const int64_t lv = std::max(nleaves(b.m1, NB2), nleaves(b.m2, NB2));
     Run<T> r;
     T* winv;
     DeviceGuard g(rec ? -1 : h->device);
@@ -494,10 +498,11 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
         winv = plan_base<T>(RFP_PLAN_BUF_WORK);
     } else {
         if (n == 0) return set_int(s, info, 0) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
-        if (prepare(h, size_t(lv) * NB * NB * sizeof(T)) != hipSuccess) return RFP_ERR_RUNTIME;
+        if (prepare(h, size_t(lv) * NB2 * NB2 * sizeof(T)) != hipSuccess) return RFP_ERR_RUNTIME;
         r = make_run<T>(h, s, info);
         winv = (T*)h->inv;
     }
+    r.nb = NB2;
     RfpView<T> v = rfp_view(b, arf);
     r.setinfo(info);
     // step 1: L11 = chol(A11)              (Figure 4, factorization step 1)
@@ -526,7 +531,7 @@ static int pftrs_impl(rfp_context* h, char transr, char uplo, int64_t n, int64_t
     if (n == 0 || nrhs == 0) return 0;
     RfpBlocks b;
     rfp_blocks(transr, uplo, n, &b);
-    const int64_t l1 = nleaves(b.m1), l2 = nleaves(b.m2);
+    const int64_t l1 = nleaves(b.m1, NB), l2 = nleaves(b.m2, NB);
     Run<T> r;
     T* w1;
     DeviceGuard g(rec ? -1 : h->device);

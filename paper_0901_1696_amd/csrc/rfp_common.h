@@ -59,16 +59,18 @@ inline RfpView<T> rfp_view(const RfpBlocks& b, T* arf)
     return v;
 }
 
-// Leaf order of the recursive algorithms: diagonal blocks of at most NB
-// rows are handled by one wavefront each.
+// Leaf orders of the recursive algorithms: diagonal blocks of at most NB rows
+// are handled by one wavefront (solve, inversion), of at most NB2 rows by one
+// fused workgroup (factorization).
 constexpr int NB = 64;
+constexpr int NB2 = 128;
 
-// Splits of the recursion are multiples of NB measured from the root, so the
-// leaves of every sub-problem coincide with the leaves of its root.
-inline int64_t rec_split(int64_t n)
+// Splits of the recursion are multiples of the leaf order measured from the
+// root, so the leaves of every sub-problem coincide with the leaves of its root.
+inline int64_t rec_split(int64_t n, int nb)
 {
-    int64_t nblk = (n + NB - 1) / NB;
-    return ((nblk + 1) / 2) * NB;
+    int64_t nblk = (n + nb - 1) / nb;
+    return ((nblk + 1) / 2) * nb;
 }
 
 struct Profiler;
@@ -96,11 +98,12 @@ struct ProfScope {
 // C(m x n) = alpha * A(m x k) * B(n x k)^T + beta * C.
 // A(i, kk) = A.at(i, kk) masked by triA; B(j, kk) = B.at(j, kk) masked by triB.
 // c_lower: only the lower triangle (i >= j) of C is computed and written.
-// C may alias A when n fits one column tile, or alias B when m fits one row
-// tile (the in-place triangular products of the leaves).
+// inplace: C aliases A (then n <= 128) or B (then m <= 128); the aliased
+// dimension is then kept inside one tile, which makes the in-place triangular
+// products of the leaves race-free.
 template <typename T>
 hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<const T> A, int triA,
-                Mat<const T> B, int triB, T beta, Mat<T> C, bool c_lower);
+                Mat<const T> B, int triB, T beta, Mat<T> C, bool c_lower, bool inplace = false);
 
 // Leaf kernels (order nb <= NB, one wavefront per block).
 // potrf: in-place Cholesky of the lower triangle of A; writes L^{-1} (NB x NB,
@@ -119,6 +122,11 @@ hipError_t trtri_leaves(const Exec& ex, Mat<const T> A, int64_t n, T* winv);
 // lauum: lower triangle of W^T W, in place.
 template <typename T>
 hipError_t lauum_leaf(const Exec& ex, Mat<T> A, int nb);
+// Fused Cholesky of a diagonal block of order nb <= NB2 with the inverse of
+// its factor (NB2 x NB2, row-major, zero above the diagonal, identity-padded)
+// written to winv; INFO as for potrf_leaf.
+template <typename T>
+hipError_t potrf128_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info_base);
 
 // 2-D strided copy dst = src (m x n), optionally only the lower triangle.
 template <typename Td, typename Ts>

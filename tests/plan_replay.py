@@ -75,13 +75,14 @@ class Replayer:
         cbuf, cidx = _idx(tuple(op.c), m, n)
         self._check(cbuf, cidx, cmask, "gemm C")
         wset = set(cidx[cmask].ravel().tolist())
-        # aliasing rules of the kernel
+        # aliasing rules of the kernel: an overlap must be declared in-place and
+        # be one of the two supported forms
         if ra[0] == cbuf and ra[1] & wset:
-            if not (tuple(op.a) == tuple(op.c) and n <= TILE and op.beta == 0):
+            if not (op.inplace and tuple(op.a) == tuple(op.c) and n <= TILE and op.beta == 0):
                 raise PlanError(f"gemm: C overlaps A outside the supported in-place form {list(op.a)} {list(op.c)}")
         if rb[0] == cbuf and rb[1] & wset:
             cb, co, crs, ccs = tuple(op.c)
-            if not (tuple(op.b) == (cb, co, ccs, crs) and m <= TILE and op.beta == 0):
+            if not (op.inplace and tuple(op.b) == (cb, co, ccs, crs) and m <= TILE and op.beta == 0):
                 raise PlanError(f"gemm: C overlaps B outside the supported in-place form {list(op.b)} {list(op.c)}")
         C = np.zeros((m, n))
         if op.beta != 0:
@@ -96,9 +97,10 @@ class Replayer:
         if op.kind == rfp.PLAN_POTRF_LEAF:
             L = np.linalg.cholesky(X + np.tril(X, -1).T)
             self.write(tuple(op.a), L, low, "potrf leaf")
-            W = np.eye(NB)
+            bs = op.b[2]  # block order of the inverse (its row stride)
+            W = np.eye(bs)
             W[:nb, :nb] = np.linalg.inv(L)
-            self.write(tuple(op.b), W, np.ones((NB, NB), bool), "potrf leaf winv")
+            self.write(tuple(op.b), W, np.ones((bs, bs), bool), "potrf leaf winv")
         elif op.kind == rfp.PLAN_TRTRI_LEAF:
             self.write(tuple(op.a), np.tril(np.linalg.inv(X)), low, "trtri leaf")
         elif op.kind == rfp.PLAN_LAUUM_LEAF:
@@ -129,11 +131,16 @@ class Replayer:
                 self.leaf(op)
 
 
+NB2 = 128
+
+
 def work_size(routine, uplo, n):
     """Scratch the library allocates for the leaf inverses of each routine:
-    PFTRF reuses one set sized for the larger diagonal block, PFTRS keeps the
-    inverses of both T1 and T2, PFTRI needs none."""
+    PFTRF reuses one set of 128-blocks sized for the larger diagonal block,
+    PFTRS keeps the 64-block inverses of both T1 and T2, PFTRI needs none."""
     m1 = (n + 1) // 2 if uplo == "L" else n // 2
     m2 = n - m1
-    nl = lambda m: (m + NB - 1) // NB
-    return {"F": max(nl(m1), nl(m2)), "S": nl(m1) + nl(m2), "I": 0}[routine] * NB * NB
+    nl = lambda m, b: (m + b - 1) // b
+    if routine == "F":
+        return max(nl(m1, NB2), nl(m2, NB2)) * NB2 * NB2
+    return {"S": nl(m1, NB) + nl(m2, NB), "I": 0}[routine] * NB * NB

@@ -73,13 +73,17 @@ def test_plan_argument_errors():
 
 
 def test_plan_leaf_counts():
-    """The recursion reaches diagonal blocks of at most 64 rows, aligned on
-    64-row boundaries of T1 and T2, one leaf per block."""
+    """The factorization recursion reaches diagonal blocks of at most 128 rows
+    (the solve and inversion ones 64), aligned from the start of T1 and T2,
+    one leaf per block."""
     for n in [100, 1001, 4097]:
         for t, u in LAYOUTS:
-            ops = rfp.rfp_plan("F", t, u, n)
-            leaves = [o for o in ops if o.kind == rfp.PLAN_POTRF_LEAF]
             m1 = (n + 1) // 2 if u == "L" else n // 2
             m2 = n - m1
+            ops = rfp.rfp_plan("F", t, u, n)
+            leaves = [o for o in ops if o.kind == rfp.PLAN_POTRF_LEAF]
+            assert len(leaves) == -(-m1 // 128) + -(-m2 // 128)
+            assert all(o.m <= 128 for o in leaves)
+            ops = rfp.rfp_plan("I", t, u, n)
+            leaves = [o for o in ops if o.kind == rfp.PLAN_TRTRI_LEAF]
             assert len(leaves) == -(-m1 // 64) + -(-m2 // 64)
-            assert all(o.m <= 64 for o in leaves)
