@@ -59,7 +59,8 @@ struct GemmParams {
     int64_t ldc;
     T alpha, beta;
     int triA, triB;
-    int c_lower;
+    int c_lower;   // write only C(i, j) with i >= j
+    int tri_enum;  // square lower output: the grid enumerates lower tiles only
     int tiles_m, tiles_n;
     int64_t kchunk;
     T* W;  // split-K partials, [split][n][m], or null
@@ -119,9 +120,9 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
 
     int64_t ti, tj;
     {
-        const int total = p.c_lower ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
+        const int total = p.tri_enum ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
         const int bid = xcd_remap((int)blockIdx.x, total);
-        if (p.c_lower) {
+        if (p.tri_enum) {
             // lower triangle of tiles, row by row
             int r = (int)((sqrtf(8.0f * (float)bid + 1.0f) - 1.0f) * 0.5f);
             while ((r + 1) * (r + 2) / 2 <= bid) r++;
@@ -140,6 +141,7 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
     }
     const int64_t i0 = ti * BM, j0 = tj * BN;
     const int64_t m = p.m, n = p.n;
+    if (p.c_lower && j0 >= i0 + BM) return;  // tile entirely above the diagonal
 
     int64_t kb = (int64_t)blockIdx.z * p.kchunk;
     int64_t ke = kb + p.kchunk < p.k ? kb + p.kchunk : p.k;
@@ -408,9 +410,16 @@ static double tri_pairs(int tri, int64_t rows, int64_t k)
 }
 
 template <typename T>
+static double out_cells(const GemmParams<T>& p)
+{
+    // entries of C computed: all, or those with i >= j (m >= n)
+    return p.c_lower ? (double)p.m * p.n - 0.5 * (double)p.n * (double)(p.n - 1) : (double)p.m * (double)p.n;
+}
+
+template <typename T>
 static double gemm_flops(const GemmParams<T>& p)
 {
-    double cells = p.c_lower ? 0.5 * (double)p.m * (double)(p.m + 1) : (double)p.m * (double)p.n;
+    double cells = out_cells(p);
     double kfrac = 1.0;
     if (p.k > 0) {
         if (p.triA) kfrac *= tri_pairs(p.triA, p.m, p.k) / ((double)p.m * p.k);
@@ -422,7 +431,7 @@ static double gemm_flops(const GemmParams<T>& p)
 template <typename T>
 static double gemm_bytes(const GemmParams<T>& p)
 {
-    double cells = p.c_lower ? 0.5 * (double)p.m * (double)(p.m + 1) : (double)p.m * (double)p.n;
+    double cells = out_cells(p);
     return sizeof(T) * ((double)p.m * p.k + (double)p.n * p.k + cells * (p.beta != T(0) ? 2.0 : 1.0));
 }
 
@@ -463,11 +472,11 @@ static int pick_tile(int64_t m, int64_t n, bool c_lower, bool inplace, int64_t* 
     int64_t best_tiles = -1;
     for (int t = 0; t < 4; t++) {
         const int bm = TILE_BM[t], bn = TILE_BN[t];
-        if (c_lower && bm != bn) continue;
+        if (c_lower && m == n && bm != bn) continue;
         if (inplace && m <= 128 && bm < m) continue;
         if (inplace && n <= 128 && bn < n) continue;
         const int64_t a = (m + bm - 1) / bm, b = (n + bn - 1) / bn;
-        const int64_t tiles = c_lower ? a * (a + 1) / 2 : a * b;
+        const int64_t tiles = (c_lower && m == n) ? a * (a + 1) / 2 : a * b;
         if (tiles >= want) {
             best = t;
             best_tiles = tiles;
@@ -483,13 +492,27 @@ static int pick_tile(int64_t m, int64_t n, bool c_lower, bool inplace, int64_t* 
     return best;
 }
 
+hipError_t gemm_validate(int64_t m, int64_t n, int64_t a_rs, int64_t a_cs, int64_t b_rs, int64_t b_cs,
+                         int64_t c_rs, int64_t c_cs, bool c_lower, bool inplace)
+{
+    if (m <= 0 || n <= 0) return hipSuccess;
+    if (inplace && m > 128 && n > 128) return hipErrorInvalidValue;
+    if (c_lower && m < n) return hipErrorInvalidValue;
+    if (a_rs != 1 && a_cs != 1) return hipErrorInvalidValue;
+    if (b_rs != 1 && b_cs != 1) return hipErrorInvalidValue;
+    if (c_rs != 1 && c_cs != 1) return hipErrorInvalidValue;
+    return hipSuccess;
+}
+
 template <typename T>
 hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<const T> A, int triA,
                 Mat<const T> B, int triB, T beta, Mat<T> C, bool c_lower, bool inplace)
 {
     if (m <= 0 || n <= 0) return hipSuccess;
-    if (inplace && m > 128 && n > 128) return hipErrorInvalidValue;
-    if (c_lower && m != n) return hipErrorInvalidValue;
+    {
+        const hipError_t v = gemm_validate(m, n, A.rs, A.cs, B.rs, B.cs, C.rs, C.cs, c_lower, inplace);
+        if (v != hipSuccess) return v;
+    }
     GemmParams<T> p{};
     p.m = m;
     p.n = n;
@@ -514,7 +537,8 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
     p.info = ex.info;
     int64_t tm, tn;
     const int tile = pick_tile(m, n, c_lower, inplace, &tm, &tn);
-    const int64_t ntiles = c_lower ? tm * (tm + 1) / 2 : tm * tn;
+    p.tri_enum = (c_lower && m == n) ? 1 : 0;
+    const int64_t ntiles = p.tri_enum ? tm * (tm + 1) / 2 : tm * tn;
     p.tiles_m = (int)tm;
     p.tiles_n = (int)tn;
 

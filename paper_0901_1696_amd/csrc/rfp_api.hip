@@ -106,6 +106,9 @@ struct rfp_context {
     void* inv;
     size_t inv_bytes;
     rfp::Profiler* prof;
+    hipStream_t aux;      // second stream for the lookahead factorization (default priority)
+    hipEvent_t ev[64];    // ring of ordering events between the two streams
+    int nev, evi;
 };
 
 namespace rfp {
@@ -186,7 +189,11 @@ static void plan_view(const void* p, int64_t rs, int64_t cs, size_t esize, int64
 
 template <typename T>
 struct Run {
-    Exec ex;
+    Exec ex;             // the caller's stream: the critical path
+    Exec ex2;            // auxiliary stream (bulk trailing updates), when available
+    hipEvent_t* evs = nullptr;
+    int nev = 0, *evi = nullptr;
+    bool on_aux = false;  // route the next GEMMs to ex2
     hipError_t err = hipSuccess;
     PlanRec* rec = nullptr;
     int nb = NB;  // leaf order of this call's recursion
@@ -210,9 +217,11 @@ struct Run {
             Mat<T> C, bool lower = false, bool inplace = false)
     {
         if (rec) {
+            chk(gemm_validate(m, n, A.rs, A.cs, B.rs, B.cs, C.rs, C.cs, lower, inplace));
             if (rfp_plan_op* o = next(RFP_PLAN_GEMM)) {
                 o->m = m; o->n = n; o->k = k;
                 o->inplace = inplace ? 1 : 0;
+                o->stream = on_aux ? 1 : 0;
                 o->alpha = (double)alpha; o->beta = (double)beta;
                 o->tri_a = ta; o->tri_b = tb; o->c_lower = lower ? 1 : 0;
                 plan_view(A.p, A.rs, A.cs, sizeof(T), o->a);
@@ -221,7 +230,82 @@ struct Run {
             }
             return;
         }
-        chk(gemm<T>(ex, m, n, k, alpha, A, ta, B, tb, beta, C, lower, inplace));
+        chk(gemm<T>(on_aux ? ex2 : ex, m, n, k, alpha, A, ta, B, tb, beta, C, lower, inplace));
+    }
+    // Stream ordering.  Stream 0 is the caller's, stream 1 the auxiliary one.
+    // While recording a plan the two streams are virtual and every record and
+    // wait is logged, so the host replay can check the schedule for races.
+    int plan_events = 0;
+    bool two_streams() const { return rec || (evs && ex2.stream != nullptr); }
+    hipEvent_t record(int stream)
+    {
+        if (rec) {
+            if (rfp_plan_op* o = next(RFP_PLAN_RECORD)) {
+                o->stream = stream;
+                o->m = plan_events;
+            }
+            return (hipEvent_t)(uintptr_t)(++plan_events);
+        }
+        if (!two_streams()) return nullptr;
+        hipEvent_t ev = evs[(*evi)++ % nev];
+        chk(hipEventRecord(ev, stream ? ex2.stream : ex.stream));
+        return ev;
+    }
+    void wait(int stream, hipEvent_t ev)
+    {
+        if (!ev) return;
+        if (rec) {
+            if (rfp_plan_op* o = next(RFP_PLAN_WAIT)) {
+                o->stream = stream;
+                o->m = (int64_t)(uintptr_t)ev - 1;
+            }
+            return;
+        }
+        chk(hipStreamWaitEvent(stream ? ex2.stream : ex.stream, ev, 0));
+    }
+    void leaf_potrf(int64_t order, Mat<T> A, int64_t goff, T* winv)
+    {
+        if (rec) leaf(RFP_PLAN_POTRF_LEAF, A, order, winv, goff);
+        else if (nb == NB2) chk(potrf128_leaf<T>(ex, A, (int)order, winv, goff));
+        else chk(potrf_leaf<T>(ex, A, (int)order, winv, goff));
+    }
+
+    // Right-looking blocked Cholesky of the lower triangle of A (order n) in
+    // diagonal blocks of nb, with one step of lookahead: after the panel of
+    // step k, the critical stream updates only block column k + 1 and factors
+    // its diagonal block while the auxiliary stream applies step k's update
+    // to the rest of the trailing matrix.  Step k + 1's update of block
+    // column k + 2 waits for that bulk update (both write it).
+    void potrf_la(int64_t n, Mat<T> A, int64_t goff, T* winv)
+    {
+        if (n <= 0) return;
+        const int64_t b = nb;
+        const int64_t K = nleaves(n, nb);
+        leaf_potrf(std::min<int64_t>(b, n), A, goff, winv);
+        hipEvent_t bulk_prev = nullptr;
+        for (int64_t k = 0; k + 1 < K; k++) {
+            const int64_t o = k * b, bk = b, o1 = o + bk;
+            const int64_t b1 = std::min<int64_t>(b, n - o1), o2 = o1 + b1;
+            // panel: L(o1:, block k) = A(o1:, block k) W_k^T, in place
+            mm(n - o1, bk, bk, T(1), A.sub(o1, o), TRI_NONE, Mat<const T>{winv + k * b * b, nb, 1}, TRI_LOWER,
+               T(0), A.sub(o1, o), false, true);
+            hipEvent_t panel_done = record(0);
+            // lookahead: block column k + 1 (lower part of its diagonal tile), then its leaf
+            wait(0, bulk_prev);
+            mm(n - o1, b1, bk, T(-1), A.sub(o1, o), TRI_NONE, A.sub(o1, o), TRI_NONE, T(1), A.sub(o1, o1), true);
+            leaf_potrf(b1, A.sub(o1, o1), goff + o1, winv + (k + 1) * b * b);
+            // bulk: columns beyond block k + 1
+            bulk_prev = nullptr;
+            if (o2 < n) {
+                wait(1, panel_done);
+                on_aux = two_streams();
+                mm(n - o2, n - o2, bk, T(-1), A.sub(o2, o), TRI_NONE, A.sub(o2, o), TRI_NONE, T(1), A.sub(o2, o2),
+                   true);
+                on_aux = false;
+                bulk_prev = record(1);
+            }
+        }
+        wait(0, bulk_prev);
     }
     void leaf(int kind, Mat<const T> A, int64_t order, const T* w, int64_t info_base)
     {
@@ -414,6 +498,15 @@ static hipError_t prepare(rfp_context* h, size_t inv_need)
 {
     hipError_t e = ensure(&h->splitk, &h->splitk_bytes, SPLITK_BYTES);
     if (e != hipSuccess) return e;
+    if (!h->aux) {
+        e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        for (int i = 0; i < 64; i++) {
+            e = hipEventCreateWithFlags(&h->ev[i], hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+            h->nev = i + 1;
+        }
+    }
     return ensure(&h->inv, &h->inv_bytes, inv_need);
 }
 
@@ -426,6 +519,11 @@ static Run<T> make_run(rfp_context* h, hipStream_t s, int* info)
     r.ex.splitk_ws = h->splitk;
     r.ex.splitk_bytes = h->splitk_bytes;
     r.ex.prof = h->prof;
+    r.ex2 = r.ex;
+    r.ex2.stream = h->aux;
+    r.evs = h->nev ? h->ev : nullptr;
+    r.nev = h->nev;
+    r.evi = &h->evi;
     return r;
 }
 
@@ -506,13 +604,13 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     RfpView<T> v = rfp_view(b, arf);
     r.setinfo(info);
     // step 1: L11 = chol(A11)              (Figure 4, factorization step 1)
-    r.potrf_rec(b.m1, v.t1, 0, winv);
+    r.potrf_la(b.m1, v.t1, 0, winv);
     // step 2: L21 = A21 L11^{-T}           (step 2, TRSM)
     r.trsm_rlt(b.m2, b.m1, v.s, v.t1, winv);
     // step 3: A22 <- A22 - L21 L21^T       (step 3, SYRK on T2's triangle)
     r.mm(b.m2, b.m2, b.m1, T(-1), v.s, TRI_NONE, v.s, TRI_NONE, T(1), v.t2, true);
     // step 4: L22 = chol(A22), INFO offset by m1
-    r.potrf_rec(b.m2, v.t2, b.m1, winv);
+    r.potrf_la(b.m2, v.t2, b.m1, winv);
     return r.err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
@@ -622,6 +720,8 @@ int rfp_destroy(rfp_handle_t h)
         (void)hipDeviceSynchronize();
         if (h->splitk) (void)hipFree(h->splitk);
         if (h->inv) (void)hipFree(h->inv);
+        for (int i = 0; i < h->nev; i++) (void)hipEventDestroy(h->ev[i]);
+        if (h->aux) (void)hipStreamDestroy(h->aux);
         delete h->prof;
     }
     std::free(h);

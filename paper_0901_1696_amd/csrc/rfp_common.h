@@ -97,10 +97,13 @@ struct ProfScope {
 
 // C(m x n) = alpha * A(m x k) * B(n x k)^T + beta * C.
 // A(i, kk) = A.at(i, kk) masked by triA; B(j, kk) = B.at(j, kk) masked by triB.
-// c_lower: only the lower triangle (i >= j) of C is computed and written.
+// c_lower: only the entries i >= j of C are computed and written (m >= n).
 // inplace: C aliases A (then n <= 128) or B (then m <= 128); the aliased
 // dimension is then kept inside one tile, which makes the in-place triangular
 // products of the leaves race-free.
+// Argument checks shared by the launch and by plan recording.
+hipError_t gemm_validate(int64_t m, int64_t n, int64_t a_rs, int64_t a_cs, int64_t b_rs, int64_t b_cs,
+                         int64_t c_rs, int64_t c_cs, bool c_lower, bool inplace);
 template <typename T>
 hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<const T> A, int triA,
                 Mat<const T> B, int triB, T beta, Mat<T> C, bool c_lower, bool inplace = false);

@@ -9,7 +9,10 @@ NumPy with the documented semantics and checks, for every access, that
   * an output that overlaps an input is one of the two in-place forms the
     GEMM kernel supports (C and A the same view with all columns in one
     128-wide tile, or B the transpose view of C with all rows in one tile),
-    and overlaps nothing else.
+    and overlaps nothing else;
+  * the two-stream schedule is race-free: ops on different streams that the
+    recorded events do not order (vector clocks) touch disjoint data, or only
+    read the same data.
 
 The replay gives the same result as the GPU up to rounding; the tests compare
 it with the oracle, which checks the block algebra of all eight layouts.
@@ -43,6 +46,10 @@ class Replayer:
     def __init__(self, bufs):
         self.bufs = bufs  # {buffer id: 1-D float64 array}
         self.nops = 0
+        self.vc = {0: [0, 0], 1: [0, 0]}  # vector clock of each stream
+        self.events = {}
+        self.log = []  # (stream, clock, reads, writes) per compute op
+        self._r, self._w = [], []
 
     def _check(self, buf, idx, mask, what):
         if buf not in self.bufs:
@@ -58,14 +65,18 @@ class Replayer:
         self._check(buf, idx, mask, what)
         out = np.zeros((rows, cols))
         out[mask] = self.bufs[buf][idx[mask]]
-        return out, (buf, set(idx[mask].ravel().tolist()))
+        sel = set(idx[mask].ravel().tolist())
+        self._r.append((buf, sel))
+        return out, (buf, sel)
 
     def write(self, view, val, mask, what):
         rows, cols = val.shape
         buf, idx = _idx(view, rows, cols)
         self._check(buf, idx, mask, what)
         self.bufs[buf][idx[mask]] = val[mask]
-        return buf, set(idx[mask].ravel().tolist())
+        sel = set(idx[mask].ravel().tolist())
+        self._w.append((buf, sel))
+        return buf, sel
 
     def gemm(self, op):
         m, n, k = op.m, op.n, op.k
@@ -123,12 +134,42 @@ class Replayer:
     def run(self, ops):
         for op in ops:
             self.nops += 1
+            if op.kind == rfp.PLAN_RECORD:
+                self.events[op.m] = list(self.vc[op.stream])
+                continue
+            if op.kind == rfp.PLAN_WAIT:
+                ev = self.events[op.m]
+                self.vc[op.stream] = [max(a, b) for a, b in zip(self.vc[op.stream], ev)]
+                continue
+            self._r, self._w = [], []
             if op.kind == rfp.PLAN_GEMM:
                 self.gemm(op)
             elif op.kind == rfp.PLAN_TRTRI_LEAVES:
                 self.leaves(op)
             else:
                 self.leaf(op)
+            s = op.stream
+            self.vc[s][s] += 1
+            self.log.append((s, list(self.vc[s]), self._r, self._w))
+        self.check_races()
+
+    def check_races(self):
+        def merge(lst):
+            out = {}
+            for buf, sel in lst:
+                out.setdefault(buf, set()).update(sel)
+            return out
+        ops = [(s, vc, merge(r), merge(w)) for s, vc, r, w in self.log]
+        a_ops = [o for o in ops if o[0] == 0]
+        b_ops = [o for o in ops if o[0] == 1]
+        for sa, va, ra, wa in a_ops:
+            for sb, vb, rb, wb in b_ops:
+                if va[0] <= vb[0] or vb[1] <= va[1]:
+                    continue  # ordered by the events
+                for buf in set(wa) | set(wb):
+                    if (wa.get(buf, set()) & (rb.get(buf, set()) | wb.get(buf, set()))) or \
+                       (wb.get(buf, set()) & ra.get(buf, set())):
+                        raise PlanError(f"race between unordered ops on streams 0 and 1 (buffer {buf})")
 
 
 NB2 = 128

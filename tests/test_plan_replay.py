@@ -63,6 +63,22 @@ def test_pftri_plan(transr, uplo, n):
     assert oracle.rel_fro(got, want) <= 1e-13 * max(n, 1)
 
 
+def test_two_stream_schedule_is_checked():
+    """The factorization uses the auxiliary stream; the replay's race check is
+    active (a schedule without the bulk-update wait is flagged)."""
+    ops = rfp.rfp_plan("F", "N", "L", 1001)
+    assert any(o.stream == 1 for o in ops)
+    assert any(o.kind == rfp.PLAN_WAIT for o in ops)
+    n = 1001
+    A, _ = synth.spd(n, seed=9)
+    arf = oracle.trttf("N", "L", A)
+    # drop the waits of the critical stream: the next block column's update
+    # then races with the previous step's bulk update
+    broken = [o for o in ops if not (o.kind == rfp.PLAN_WAIT and o.stream == 0)]
+    with pytest.raises(AssertionError):
+        Replayer(_bufs("F", "L", n, arf.copy())).run(broken)
+
+
 def test_plan_argument_errors():
     with pytest.raises(rfp.RfpError):
         rfp.rfp_plan("F", "X", "L", 5)
