@@ -137,6 +137,11 @@ int rfp_profile_read(rfp_handle_t h, rfp_profile_entry* out, int cap, int* count
  *   RFP_PLAN_TRTRI_LEAVES: inverses of all 64-row diagonal blocks of the lower
  *     triangular a (order m) into consecutive NB x NB row-major blocks at b.
  *   RFP_PLAN_LAUUM_LEAF: lower triangle of W^T W in place (order m).
+ *   RFP_PLAN_BLOCK_SOLVE: tri_a 0: L Y = B (forward), 1: L^T X = B
+ *     (backward), in place in d (m + k rows, n columns), with L the lower
+ *     factor held as a = L11 (order m), b = L21 (k x m), c = L22 (order k);
+ *     w holds the inverses of the 64-row diagonal blocks of L11 then of L22,
+ *     consecutive NB x NB row-major blocks (as RFP_PLAN_TRTRI_LEAVES writes).
  *   RFP_PLAN_RECORD / RFP_PLAN_WAIT: event m is recorded on / waited for by
  *     stream `stream` (0: the caller's stream, 1: the handle's auxiliary
  *     stream).  Every other record carries the stream it runs on; work on one
@@ -151,7 +156,8 @@ enum {
     RFP_PLAN_TRTRI_LEAVES = 4,
     RFP_PLAN_LAUUM_LEAF = 5,
     RFP_PLAN_RECORD = 6,
-    RFP_PLAN_WAIT = 7
+    RFP_PLAN_WAIT = 7,
+    RFP_PLAN_BLOCK_SOLVE = 8
 };
 enum { RFP_PLAN_BUF_ARF = 0, RFP_PLAN_BUF_B = 1, RFP_PLAN_BUF_WORK = 2, RFP_PLAN_BUF_INFO = 3 };
 typedef struct {
@@ -162,6 +168,7 @@ typedef struct {
     double alpha, beta;
     int64_t a[4], b[4], c[4]; /* buffer (-1: unused), offset, row stride, column stride */
     int64_t info_base;
+    int64_t d[4], w[4];       /* RFP_PLAN_BLOCK_SOLVE: right-hand sides and block inverses */
 } rfp_plan_op;
 int rfp_plan(char routine, char transr, char uplo, int64_t n, int64_t nrhs, int64_t ldb, rfp_plan_op* ops,
              int64_t cap, int64_t* count);

@@ -62,7 +62,7 @@ class ProfileEntry(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 PLAN_GEMM, PLAN_POTRF_LEAF, PLAN_TRTRI_LEAF, PLAN_TRTRI_LEAVES, PLAN_LAUUM_LEAF = 1, 2, 3, 4, 5
-PLAN_RECORD, PLAN_WAIT = 6, 7
+PLAN_RECORD, PLAN_WAIT, PLAN_BLOCK_SOLVE = 6, 7, 8
 PLAN_BUF_ARF, PLAN_BUF_B, PLAN_BUF_WORK = 0, 1, 2
 
 
@@ -72,7 +72,8 @@ class PlanOp(ctypes.Structure):
                 ("c_lower", ctypes.c_int32), ("inplace", ctypes.c_int32), ("stream", ctypes.c_int32),
                 ("m", _i64), ("n", _i64), ("k", _i64),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
-                ("a", _i64 * 4), ("b", _i64 * 4), ("c", _i64 * 4), ("info_base", _i64)]
+                ("a", _i64 * 4), ("b", _i64 * 4), ("c", _i64 * 4), ("info_base", _i64),
+                ("d", _i64 * 4), ("w", _i64 * 4)]
 
 
 def exported_symbols():

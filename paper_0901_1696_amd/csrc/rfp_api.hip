@@ -109,6 +109,9 @@ struct rfp_context {
     hipStream_t aux;      // second stream for the lookahead factorization (default priority)
     hipEvent_t ev[64];    // ring of ordering events between the two streams
     int nev, evi;
+    int* flags;           // ready flags of the fused triangular solves
+    size_t flags_bytes;
+    int epoch;            // last epoch handed to a fused solve
 };
 
 namespace rfp {
@@ -210,7 +213,7 @@ struct Run {
         rfp_plan_op* o = &rec->ops[rec->count++];
         std::memset(o, 0, sizeof(*o));
         o->kind = kind;
-        o->a[0] = o->b[0] = o->c[0] = -1;
+        o->a[0] = o->b[0] = o->c[0] = o->d[0] = o->w[0] = -1;
         return o;
     }
     void mm(int64_t m, int64_t n, int64_t k, T alpha, Mat<const T> A, int ta, Mat<const T> B, int tb, T beta,
@@ -262,6 +265,24 @@ struct Run {
             return;
         }
         chk(hipStreamWaitEvent(stream ? ex2.stream : ex.stream, ev, 0));
+    }
+    // Fused triangular solve with the whole factor (see block_solve).
+    int* flags = nullptr;
+    void solve(bool forward, const RfpView<const T>& v, const T* winv, Mat<T> B, int64_t nrhs, int epoch)
+    {
+        if (rec) {
+            if (rfp_plan_op* o = next(RFP_PLAN_BLOCK_SOLVE)) {
+                o->tri_a = forward ? 0 : 1;
+                o->m = v.m1; o->n = nrhs; o->k = v.m2;
+                plan_view(v.t1.p, v.t1.rs, v.t1.cs, sizeof(T), o->a);
+                plan_view(v.s.p, v.s.rs, v.s.cs, sizeof(T), o->b);
+                plan_view(v.t2.p, v.t2.rs, v.t2.cs, sizeof(T), o->c);
+                plan_view(B.p, B.rs, B.cs, sizeof(T), o->d);
+                plan_view(winv, NB, 1, sizeof(T), o->w);
+            }
+            return;
+        }
+        chk(block_solve<T>(ex, forward, v.t1, v.s, v.t2, v.m1, v.m2, winv, B.p, B.cs, nrhs, flags, epoch));
     }
     void leaf_potrf(int64_t order, Mat<T> A, int64_t goff, T* winv)
     {
@@ -332,39 +353,8 @@ struct Run {
         trsm_rlt(m, n2, B.sub(0, n1), L.sub(n1, n1), winv + nleaves(n1, nb) * nb * nb);
     }
 
-    // Cholesky of the lower triangle of A (order n); goff is the position of
-    // A's first row in the whole matrix, for INFO.
-    void potrf_rec(int64_t n, Mat<T> A, int64_t goff, T* winv)
-    {
-        if (n <= 0) return;
-        if (n <= nb) {
-            if (rec) leaf(RFP_PLAN_POTRF_LEAF, A, n, winv, goff);
-            else if (nb == NB2) chk(potrf128_leaf<T>(ex, A, (int)n, winv, goff));
-            else chk(potrf_leaf<T>(ex, A, (int)n, winv, goff));
-            return;
-        }
-        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
-        potrf_rec(n1, A, goff, winv);
-        trsm_rlt(n2, n1, A.sub(n1, 0), A, winv);
-        mm(n2, n2, n1, T(-1), A.sub(n1, 0), TRI_NONE, A.sub(n1, 0), TRI_NONE, T(1), A.sub(n1, n1), true);
-        potrf_rec(n2, A.sub(n1, n1), goff + n1, winv + nleaves(n1, nb) * nb * nb);
-    }
 
     // ---------------------------------------------------------------- solve
-    // B (n x r) <- L^{-1} B
-    void trsm_lln(int64_t n, int64_t r, Mat<const T> L, Mat<T> B, const T* winv)
-    {
-        if (n <= 0 || r <= 0) return;
-        if (n <= nb) {
-            mm(n, r, n, T(1), Mat<const T>{winv, nb, 1}, TRI_LOWER, Mat<T>(B).tr(), TRI_NONE, T(0), B, false, true);
-            return;
-        }
-        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
-        trsm_lln(n1, r, L, B, winv);
-        mm(n2, r, n1, T(-1), L.sub(n1, 0), TRI_NONE, B.tr(), TRI_NONE, T(1), B.sub(n1, 0));
-        trsm_lln(n2, r, L.sub(n1, n1), B.sub(n1, 0), winv + nleaves(n1, nb) * nb * nb);
-    }
-    // B (n x r) <- L^{-T} B
     void leaves_inv(Mat<const T> A, int64_t n, T* winv)
     {
         if (rec) leaf(RFP_PLAN_TRTRI_LEAVES, A, n, winv, 0);
@@ -373,18 +363,6 @@ struct Run {
     void setinfo(int* p)
     {
         if (!rec) chk(set_int(ex.stream, p, 0));
-    }
-    void trsm_llt(int64_t n, int64_t r, Mat<const T> L, Mat<T> B, const T* winv)
-    {
-        if (n <= 0 || r <= 0) return;
-        if (n <= nb) {
-            mm(n, r, n, T(1), Mat<const T>{winv, 1, nb}, TRI_UPPER, B.tr(), TRI_NONE, T(0), B, false, true);
-            return;
-        }
-        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
-        trsm_llt(n2, r, L.sub(n1, n1), B.sub(n1, 0), winv + nleaves(n1, nb) * nb * nb);
-        mm(n1, r, n2, T(-1), L.sub(n1, 0).tr(), TRI_NONE, B.sub(n1, 0).tr(), TRI_NONE, T(1), B);
-        trsm_llt(n1, r, L, B, winv);
     }
 
     // ------------------------------------------------------------ inversion
@@ -510,6 +488,28 @@ static hipError_t prepare(rfp_context* h, size_t inv_need)
     return ensure(&h->inv, &h->inv_bytes, inv_need);
 }
 
+// Ready flags for the fused solves: grown on demand and cleared once when
+// allocated; launches then tell stale flags apart by their epoch.
+static hipError_t prepare_flags(rfp_context* h, int64_t count)
+{
+    const size_t need = size_t(count) * sizeof(int);
+    if (need <= h->flags_bytes) return hipSuccess;
+    hipError_t e = ensure((void**)&h->flags, &h->flags_bytes, need);
+    if (e == hipSuccess) e = hipMemset(h->flags, 0, h->flags_bytes);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    h->epoch = 0;
+    return e;
+}
+
+static int next_epoch(rfp_context* h, hipStream_t s)
+{
+    if (h->epoch >= (1 << 30)) {
+        (void)fill_int(s, h->flags, (int64_t)(h->flags_bytes / sizeof(int)), 0);
+        h->epoch = 0;
+    }
+    return ++h->epoch;
+}
+
 template <typename T>
 static Run<T> make_run(rfp_context* h, hipStream_t s, int* info)
 {
@@ -632,29 +632,31 @@ static int pftrs_impl(rfp_context* h, char transr, char uplo, int64_t n, int64_t
     const int64_t l1 = nleaves(b.m1, NB), l2 = nleaves(b.m2, NB);
     Run<T> r;
     T* w1;
+    int e_fwd = 1, e_bwd = 2;
     DeviceGuard g(rec ? -1 : h->device);
     if (rec) {
         r.rec = rec;
         w1 = plan_base<T>(RFP_PLAN_BUF_WORK);
     } else {
         if (prepare(h, size_t(l1 + l2) * NB * NB * sizeof(T)) != hipSuccess) return RFP_ERR_RUNTIME;
+        if (prepare_flags(h, block_solve_flags(b.m1, b.m2, nrhs)) != hipSuccess) return RFP_ERR_RUNTIME;
         r = make_run<T>(h, s, nullptr);
+        r.flags = h->flags;
+        e_fwd = next_epoch(h, s);
+        e_bwd = next_epoch(h, s);
         w1 = (T*)h->inv;
     }
     T* w2 = w1 + l1 * NB * NB;
     RfpView<const T> v = rfp_view(b, arf);
+    // inverses of the 64-row diagonal blocks of L11 and L22, consecutive
     r.leaves_inv(v.t1, b.m1, w1);
     r.leaves_inv(v.t2, b.m2, w2);
-    Mat<T> B1{bp, 1, ldb};
-    Mat<T> B2 = B1.sub(b.m1, 0);
-    // L Y = B: Y1 = L11^{-1} B1; B2 -= L21 Y1; Y2 = L22^{-1} B2   (Figure 4, solution)
-    r.trsm_lln(b.m1, nrhs, v.t1, B1, w1);
-    r.mm(b.m2, nrhs, b.m1, T(-1), v.s, TRI_NONE, Mat<T>(B1).tr(), TRI_NONE, T(1), B2);
-    r.trsm_lln(b.m2, nrhs, v.t2, B2, w2);
-    // L^T X = Y: X2 = L22^{-T} Y2; Y1 -= L21^T X2; X1 = L11^{-T} Y1
-    r.trsm_llt(b.m2, nrhs, v.t2, B2, w2);
-    r.mm(b.m1, nrhs, b.m2, T(-1), v.s.tr(), TRI_NONE, Mat<T>(B2).tr(), TRI_NONE, T(1), B1);
-    r.trsm_llt(b.m1, nrhs, v.t1, B1, w1);
+    Mat<T> B{bp, 1, ldb};
+    // L Y = B, then L^T X = Y (Figure 4, solution): the 2 x 2 block steps
+    // (Y1 = L11^{-1} B1, B2 -= L21 Y1, Y2 = L22^{-1} B2 and back) run as one
+    // blocked substitution per direction over all diagonal blocks of L11 and L22
+    r.solve(true, v, w1, B, nrhs, e_fwd);
+    r.solve(false, v, w1, B, nrhs, e_bwd);
     return r.err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
@@ -720,6 +722,7 @@ int rfp_destroy(rfp_handle_t h)
         (void)hipDeviceSynchronize();
         if (h->splitk) (void)hipFree(h->splitk);
         if (h->inv) (void)hipFree(h->inv);
+        if (h->flags) (void)hipFree(h->flags);
         for (int i = 0; i < h->nev; i++) (void)hipEventDestroy(h->ev[i]);
         if (h->aux) (void)hipStreamDestroy(h->aux);
         delete h->prof;

@@ -131,6 +131,20 @@ hipError_t lauum_leaf(const Exec& ex, Mat<T> A, int nb);
 template <typename T>
 hipError_t potrf128_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info_base);
 
+// Fused blocked triangular solve with the whole factor of an RFP matrix
+// (Section 4): forward L Y = B, else L^T X = B, over the views L11 (order m1),
+// L21 (m2 x m1) and L22 (order m2), in one launch.  winv holds the inverses
+// of the 64-row diagonal blocks, those of L11 then those of L22, each NB x NB
+// row-major (as trtri_leaves writes them).  b (m1 + m2 rows, nrhs columns,
+// column-major, leading dimension ldb) is overwritten by the solution.  flags
+// (block_solve_flags ints) are ready flags compared with epoch: every launch
+// on the same flags needs an epoch none of them holds.
+template <typename T>
+hipError_t block_solve(const Exec& ex, bool forward, Mat<const T> t1, Mat<const T> s, Mat<const T> t2, int64_t m1,
+                       int64_t m2, const T* winv, T* b, int64_t ldb, int64_t nrhs, int* flags, int epoch);
+int64_t block_solve_flags(int64_t m1, int64_t m2, int64_t nrhs);
+hipError_t fill_int(hipStream_t s, int* p, int64_t n, int v);
+
 // 2-D strided copy dst = src (m x n), optionally only the lower triangle.
 template <typename Td, typename Ts>
 hipError_t copy2d(hipStream_t s, Mat<Td> dst, Mat<const Ts> src, int64_t m, int64_t n, bool lower);

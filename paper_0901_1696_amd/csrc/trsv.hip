@@ -1,0 +1,380 @@
+// Fused blocked triangular solves for PFTRS (Section 4): L Y = B and
+// L^T X = Y over the whole lower factor held in RFP, one launch each.
+//
+// The factor is cut into 64-row block rows: those of T1 (L11) first, then
+// those of T2 (L22).  A block (k, j) below the diagonal lies in T1, in S (L21)
+// or in T2, and never straddles two of them.  One workgroup owns block row k
+// and one slice of right-hand-side columns.  Forward, it accumulates
+// B_k - sum_{j<k} L_kj Y_j on MFMA, taking each Y_j as soon as block row j
+// has published it (one ready flag per block row and slice), then forms
+// Y_k = W_k (B_k - ...) with W_k the inverse of the diagonal block, stores Y_k
+// over B_k and raises its flag.  Backward runs the block rows from the bottom
+// with the blocks of L^T and W_k^T.
+//
+// Workgroups are numbered in dependency order and only ever wait for lower
+// numbers.  Dispatch is in order on every XCD, so the lowest unfinished
+// workgroup is always resident with all its inputs published: every wait
+// ends.  The waits are bounded spins all the same; a workgroup whose wait
+// runs out writes NaN into its block of the solution (and still raises its
+// flag, so that no other workgroup is held).
+//
+// Flags hold an epoch number that the host advances on every launch, so the
+// flag array is never cleared between calls.
+#include <cstdio>
+#include <cstdlib>
+
+#include "rfp_common.h"
+
+namespace rfp {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MT;
+template <>
+struct MT<double> {
+    typedef v4d acc;
+    static __device__ __forceinline__ acc op(double a, double b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct MT<float> {
+    typedef v4f acc;
+    static __device__ __forceinline__ acc op(float a, float b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+constexpr int BS = NB;     // rows per block row
+constexpr int P = BS + 4;  // LDS row pitch
+
+}  // namespace
+
+template <typename T>
+struct SolveArgs {
+    Mat<const T> t1, s, t2;  // L11, L21, L22
+    int64_t m1, m2;
+    int nb1, nb2;            // block rows in T1 and T2
+    const T* w;              // diagonal-block inverses, nb1 + nb2 blocks of BS x BS row-major
+    T* b;                    // right-hand sides, column-major
+    int64_t ldb, nrhs;
+    int nslices;             // slices of 16 * NCB columns
+    int* flags;              // [block row][slice]
+    int epoch;
+    int spin_limit;
+};
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ void block_rows(const SolveArgs<T>& a, int k, int64_t* r0, int* cnt)
+{
+    const int64_t o = k < a.nb1 ? (int64_t)k * BS : (int64_t)(k - a.nb1) * BS;
+    const int64_t len = k < a.nb1 ? a.m1 : a.m2;
+    *r0 = k < a.nb1 ? o : a.m1 + o;
+    *cnt = (int)(len - o < BS ? len - o : BS);
+}
+
+// Element (i, kk) of the block that block row k applies for dependency j:
+// L(r0 + i, rj + kk) forward, L(rj + kk, r0 + i) backward.  Returns its
+// address and the strides along i and kk.
+template <typename T, bool FWD>
+__device__ __forceinline__ const T* dep_block(const SolveArgs<T>& a, int k, int64_t r0, int j, int64_t rj,
+                                              int64_t* si, int64_t* sk)
+{
+    const int rowb = FWD ? k : j, colb = FWD ? j : k;      // block (row, col) of L
+    const int64_t gr = FWD ? r0 : rj, gc = FWD ? rj : r0;  // its first element in L
+    Mat<const T> M;
+    int64_t rr, cc;
+    if (rowb < a.nb1) {
+        M = a.t1; rr = gr; cc = gc;
+    } else if (colb < a.nb1) {
+        M = a.s; rr = gr - a.m1; cc = gc;
+    } else {
+        M = a.t2; rr = gr - a.m1; cc = gc - a.m1;
+    }
+    *si = FWD ? M.rs : M.cs;
+    *sk = FWD ? M.cs : M.rs;
+    return M.p + rr * M.rs + cc * M.cs;
+}
+
+}  // namespace
+
+// Workgroup b -> (position q in dependency order, slice s).  The slices of
+// one block row share an XCD (consecutive workgroups go to consecutive XCDs),
+// so its factor block is fetched from HBM once per XCD; for a fixed slice the
+// numbering still rises with q, which keeps every wait on an earlier
+// workgroup.  The grid is padded to whole groups of XCD_COUNT block rows.
+constexpr int XCD_COUNT = 8;
+
+template <typename T, int NCB, bool FWD>
+__global__ __launch_bounds__(256) void block_solve_kernel(SolveArgs<T> a)
+{
+    constexpr int CS = 16 * NCB;
+    constexpr int LPT = BS * BS / 256;  // factor-block elements per thread
+    constexpr int YPT = CS * BS / 256;  // solution-block elements per thread
+    __shared__ __attribute__((aligned(16))) T Ls[BS][P];  // L block or W, Ls[i][kk]
+    __shared__ __attribute__((aligned(16))) T Ys[CS][P];  // solved rows, Ys[column][row]
+
+    const int nblk = a.nb1 + a.nb2;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int grp = blockIdx.x / (XCD_COUNT * a.nslices), rem = blockIdx.x % (XCD_COUNT * a.nslices);
+    const int slice = rem / XCD_COUNT;
+    const int q = grp * XCD_COUNT + rem % XCD_COUNT;
+    if (q >= nblk) return;  // padding of the last group: nobody waits for it
+    const int k = FWD ? q : nblk - 1 - q;
+    const int64_t c0 = (int64_t)slice * CS;
+    int64_t r0;
+    int cnt;
+    block_rows(a, k, &r0, &cnt);
+
+    // the diagonal block's inverse, needed last: fetch it now
+    const T* wk = a.w + (int64_t)k * BS * BS;
+    T wreg[LPT];
+#pragma unroll
+    for (int e = 0; e < LPT; e++) {
+        const int idx = t + 256 * e, i = idx / BS, kk = idx % BS;
+        wreg[e] = (i < cnt && kk < cnt) ? (FWD ? wk[i * BS + kk] : wk[kk * BS + i]) : T(0);
+    }
+
+    typedef typename MT<T>::acc acc_t;
+    acc_t acc[NCB];
+    // B_k in the MFMA result layout: wave w holds rows 16w .. 16w + 15
+#pragma unroll
+    for (int cb = 0; cb < NCB; cb++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int i = 16 * w + MT<T>::row(lane, e);
+            const int64_t c = c0 + cb * 16 + r;
+            acc[cb][e] = (i < cnt && c < a.nrhs) ? a.b[(r0 + i) + c * a.ldb] : T(0);
+        }
+
+    // factor block of dependency d into registers (all loads in flight at once);
+    // the thread's element e is (i, kk) = (idx % BS, idx / BS) when i runs along
+    // the unit stride, else (idx / BS, idx % BS), idx = t + 256 e
+    T lreg[LPT];
+    bool i_fast = true;
+    auto fetch_l = [&](int d) {
+        const int j = FWD ? d : nblk - 1 - d;
+        int64_t rj, si, sk;
+        int cntj;
+        block_rows(a, j, &rj, &cntj);
+        const T* lp = dep_block<T, FWD>(a, k, r0, j, rj, &si, &sk);
+        i_fast = si == 1;
+#pragma unroll
+        for (int e = 0; e < LPT; e++) {
+            const int idx = t + 256 * e;
+            const int i = i_fast ? idx % BS : idx / BS, kk = i_fast ? idx / BS : idx % BS;
+            lreg[e] = (i < cnt && kk < cntj) ? lp[i * si + kk * sk] : T(0);
+        }
+    };
+    if (q > 0) fetch_l(0);
+
+    // Readiness is learnt in batches: wave 0 reads the flags of up to 64
+    // upcoming dependencies at once and one acquire covers every dependency
+    // found published, so a workgroup far behind the front pays one fence
+    // per batch rather than one per block.
+    bool ok = true;
+    int ready = 0;  // dependencies 0 .. ready-1 are known to be published
+    __shared__ int ready_sh;
+    for (int d = 0; d < q; d++) {
+        const int j = FWD ? d : nblk - 1 - d;
+        int64_t rj;
+        int cntj;
+        block_rows(a, j, &rj, &cntj);
+#pragma unroll
+        for (int e = 0; e < LPT; e++) {
+            const int idx = t + 256 * e;
+            const int i = i_fast ? idx % BS : idx / BS, kk = i_fast ? idx / BS : idx % BS;
+            Ls[i][kk] = lreg[e];
+        }
+        if (d >= ready) {
+            if (w == 0) {
+                const int dd = d + lane;
+                const int jj = FWD ? dd : nblk - 1 - dd;
+                const int* f = a.flags + (int64_t)jj * a.nslices + slice;
+                int spins = 0, avail = 0;
+                for (;;) {
+                    const bool rdy =
+                        dd < q && __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == a.epoch;
+                    const uint64_t m = __ballot(rdy);
+                    avail = ~m ? __builtin_ctzll(~m) : 64;  // published run starting at d
+                    if (avail > 0 || spins > a.spin_limit) break;
+                    spins++;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (lane == 0) ready_sh = avail > 0 ? d + avail : -1;
+            }
+            __syncthreads();
+            ready = ready_sh;
+            if (ready < 0) {
+                ok = false;
+                break;
+            }
+        }
+        T yreg[YPT];
+#pragma unroll
+        for (int e = 0; e < YPT; e++) {
+            const int idx = t + 256 * e, kk = idx % BS, c = idx / BS;
+            yreg[e] = (kk < cntj && c0 + c < a.nrhs) ? a.b[(rj + kk) + (c0 + c) * a.ldb] : T(0);
+        }
+        if (d + 1 < q) fetch_l(d + 1);  // overlaps this step's products
+#pragma unroll
+        for (int e = 0; e < YPT; e++) {
+            const int idx = t + 256 * e;
+            Ys[idx / BS][idx % BS] = yreg[e];
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < BS; kk += 4) {
+            const T av = -Ls[16 * w + r][kk + g];
+#pragma unroll
+            for (int cb = 0; cb < NCB; cb++) acc[cb] = MT<T>::op(av, Ys[cb * 16 + r][kk + g], acc[cb]);
+        }
+        __syncthreads();
+    }
+
+    // X_k = W_k acc (forward) or W_k^T acc (backward)
+#pragma unroll
+    for (int e = 0; e < LPT; e++) {
+        const int idx = t + 256 * e;
+        Ls[idx / BS][idx % BS] = wreg[e];
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCB; cb++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) Ys[cb * 16 + r][16 * w + MT<T>::row(lane, e)] = acc[cb][e];
+    __syncthreads();
+    acc_t out[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; cb++) out[cb] = acc_t{0, 0, 0, 0};
+#pragma unroll 4
+    for (int kk = 0; kk < BS; kk += 4) {
+        const T av = Ls[16 * w + r][kk + g];
+#pragma unroll
+        for (int cb = 0; cb < NCB; cb++) out[cb] = MT<T>::op(av, Ys[cb * 16 + r][kk + g], out[cb]);
+    }
+    const T nan = T(__builtin_nan(""));
+#pragma unroll
+    for (int cb = 0; cb < NCB; cb++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int i = 16 * w + MT<T>::row(lane, e);
+            const int64_t c = c0 + cb * 16 + r;
+            if (i < cnt && c < a.nrhs) a.b[(r0 + i) + c * a.ldb] = ok ? out[cb][e] : nan;
+        }
+    // publish: every thread's stores have reached L2, then one release at
+    // device scope (write-back of L2) before the flag
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (t == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(a.flags + (int64_t)k * a.nslices + slice, a.epoch, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void fill_int_kernel(int* p, int64_t n, int v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+int64_t block_solve_flags(int64_t m1, int64_t m2, int64_t nrhs)
+{
+    const int64_t nblk = (m1 + BS - 1) / BS + (m2 + BS - 1) / BS;
+    return nblk * ((nrhs + 15) / 16);  // slices are at least 16 columns wide
+}
+
+hipError_t fill_int(hipStream_t s, int* p, int64_t n, int v)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+template <typename T, int NCB>
+static hipError_t launch_solve(const Exec& ex, bool forward, const SolveArgs<T>& a, int nblk)
+{
+    static char names[2][2][112];
+    const int ti = sizeof(T) == 8 ? 0 : 1, di = forward ? 0 : 1;
+    char* nm = names[ti][di];
+    if (!nm[0]) {
+        const char* tn = ti ? "float" : "double";
+        snprintf(nm, sizeof names[ti][di], "void rfp::block_solve_kernel<%s, %d, %s>(rfp::SolveArgs<%s>)", tn, NCB,
+                 forward ? "true" : "false", tn);
+    }
+    const double mtot = (double)(a.m1 + a.m2);
+    ProfScope ps(ex, nm, mtot * mtot * (double)a.nrhs,
+                 sizeof(T) * (mtot * mtot / 2 * a.nslices + 2.0 * mtot * (double)a.nrhs));
+    const int groups = (nblk + XCD_COUNT - 1) / XCD_COUNT;
+    const dim3 grid((unsigned)(groups * XCD_COUNT * a.nslices));
+    if (forward) hipLaunchKernelGGL((block_solve_kernel<T, NCB, true>), grid, dim3(256), 0, ex.stream, a);
+    else hipLaunchKernelGGL((block_solve_kernel<T, NCB, false>), grid, dim3(256), 0, ex.stream, a);
+    return hipGetLastError();
+}
+
+// Slice width in 16-column blocks: narrow slices shorten each block row's
+// chain of dependent steps, wide ones read the factor fewer times.
+// RFP_SOLVE_COLS (16, 32, 64 or 128) overrides the choice.
+int block_solve_width(int64_t nrhs)
+{
+    static int forced = -1;
+    if (forced < 0) {
+        const char* e = getenv("RFP_SOLVE_COLS");
+        const int v = e ? atoi(e) : 0;
+        forced = (v == 16 || v == 32 || v == 64 || v == 128) ? v / 16 : 0;
+    }
+    if (forced) return forced;
+    // measured at n = 20000: 16-column slices up to 64 right-hand sides,
+    // 32-column slices beyond (the factor is then re-read nrhs / 32 times)
+    return nrhs <= 64 ? 1 : 2;
+}
+
+template <typename T>
+hipError_t block_solve(const Exec& ex, bool forward, Mat<const T> t1, Mat<const T> s, Mat<const T> t2, int64_t m1,
+                       int64_t m2, const T* winv, T* b, int64_t ldb, int64_t nrhs, int* flags, int epoch)
+{
+    SolveArgs<T> a;
+    a.t1 = t1;
+    a.s = s;
+    a.t2 = t2;
+    a.m1 = m1;
+    a.m2 = m2;
+    a.nb1 = (int)((m1 + BS - 1) / BS);
+    a.nb2 = (int)((m2 + BS - 1) / BS);
+    a.w = winv;
+    a.b = b;
+    a.ldb = ldb;
+    a.nrhs = nrhs;
+    a.flags = flags;
+    a.epoch = epoch;
+    a.spin_limit = 1 << 24;
+    const int nblk = a.nb1 + a.nb2;
+    if (nblk == 0 || nrhs <= 0) return hipSuccess;
+    const int ncb = block_solve_width(nrhs);
+    a.nslices = (int)((nrhs + 16 * ncb - 1) / (16 * ncb));
+    switch (ncb) {
+        case 1: return launch_solve<T, 1>(ex, forward, a, nblk);
+        case 2: return launch_solve<T, 2>(ex, forward, a, nblk);
+        case 4: return launch_solve<T, 4>(ex, forward, a, nblk);
+        default: return launch_solve<T, 8>(ex, forward, a, nblk);
+    }
+}
+
+template hipError_t block_solve<double>(const Exec&, bool, Mat<const double>, Mat<const double>, Mat<const double>,
+                                        int64_t, int64_t, const double*, double*, int64_t, int64_t, int*, int);
+template hipError_t block_solve<float>(const Exec&, bool, Mat<const float>, Mat<const float>, Mat<const float>,
+                                       int64_t, int64_t, const float*, float*, int64_t, int64_t, int*, int);
+
+}  // namespace rfp

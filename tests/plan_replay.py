@@ -131,6 +131,35 @@ class Replayer:
             W[:nb, :nb] = np.linalg.inv(np.tril(A[o:o + nb, o:o + nb]))
             self.write((wb, woff + b * NB * NB, NB, 1), W, np.ones((NB, NB), bool), "trtri leaves out")
 
+    def block_solve(self, op):
+        """Blocked substitution with the whole factor, block row by block row
+        in the kernel's dependency order, through the stored block inverses."""
+        m1, m2, r = op.m, op.k, op.n
+        n = m1 + m2
+        L = np.zeros((n, n))
+        L[:m1, :m1], _ = self.read(tuple(op.a), m1, m1, 1, "solve L11")
+        L[m1:, :m1], _ = self.read(tuple(op.b), m2, m1, 0, "solve L21")
+        L[m1:, m1:], _ = self.read(tuple(op.c), m2, m2, 1, "solve L22")
+        X, _ = self.read(tuple(op.d), n, r, 0, "solve B")
+        blocks = [(o, min(NB, m1 - o)) for o in range(0, m1, NB)] + \
+                 [(m1 + o, min(NB, m2 - o)) for o in range(0, m2, NB)]
+        wb, woff, _, _ = tuple(op.w)
+        forward = op.tri_a == 0
+        order = range(len(blocks)) if forward else range(len(blocks) - 1, -1, -1)
+        done = []
+        for kb in order:
+            o, c = blocks[kb]
+            W, _ = self.read((wb, woff + kb * NB * NB, NB, 1), NB, NB, 0, "solve W")
+            W = W[:c, :c] if forward else W[:c, :c].T
+            acc = X[o:o + c].copy()
+            for jb in done:
+                oj, cj = blocks[jb]
+                blk = L[o:o + c, oj:oj + cj] if forward else L[oj:oj + cj, o:o + c].T
+                acc -= blk @ X[oj:oj + cj]
+            X[o:o + c] = W @ acc
+            done.append(kb)
+        self.write(tuple(op.d), X, np.ones((n, r), bool), "solve X")
+
     def run(self, ops):
         for op in ops:
             self.nops += 1
@@ -146,6 +175,8 @@ class Replayer:
                 self.gemm(op)
             elif op.kind == rfp.PLAN_TRTRI_LEAVES:
                 self.leaves(op)
+            elif op.kind == rfp.PLAN_BLOCK_SOLVE:
+                self.block_solve(op)
             else:
                 self.leaf(op)
             s = op.stream

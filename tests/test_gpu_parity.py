@@ -97,6 +97,41 @@ def test_pftrs_random(h, transr, uplo, n):
     assert np.all(got[n:] == 7.0)
 
 
+@pytest.mark.parametrize("transr,uplo", [("N", "L"), ("T", "U"), ("N", "U"), ("T", "L")])
+@pytest.mark.parametrize("nrhs", [1, 16, 17, 33, 64, 65, 128, 130, 300])
+def test_pftrs_slice_widths(h, transr, uplo, nrhs):
+    """Right-hand-side slices of 16, 32, 64 and 128 columns, ragged last
+    slices, over a factor with ragged 64-row blocks in both triangles."""
+    n = 333
+    A, B = synth.spd(n, nrhs=nrhs, seed=nrhs + 4)
+    f, _ = oracle.pftrf(transr, uplo, n, oracle.trttf(transr, uplo, A))
+    want = oracle.pftrs(transr, uplo, n, f, B)
+    ldb = n + 3
+    Bp = np.full((ldb, nrhs), -3.0)
+    Bp[:n] = B
+    bd = dev_colmajor(Bp)
+    rfp.rfp_dpftrs(h, transr, uplo, n, dev(f), bd)
+    got = host_colmajor(bd)
+    assert oracle.rel_fro(got[:n], want) <= tol(n)
+    assert np.all(got[n:] == -3.0)
+
+
+def test_pftrs_repeated_calls_reuse_flags(h):
+    """Back-to-back solves on one handle with growing and shrinking shapes
+    (the ready flags are reused across launches by epoch, never cleared)."""
+    cases = [(700, 3, "N", "L"), (1001, 140, "T", "U"), (130, 1, "N", "U"), (1001, 140, "T", "U"),
+             (65, 20, "T", "L")]
+    outs = []
+    for n, nrhs, t, u in cases:
+        A, B = synth.spd(n, nrhs=nrhs, seed=n + nrhs)
+        f, _ = oracle.pftrf(t, u, n, oracle.trttf(t, u, A))
+        bd = dev_colmajor(B)
+        rfp.rfp_dpftrs(h, t, u, n, dev(f), bd)
+        outs.append((bd, oracle.pftrs(t, u, n, f, B), n))
+    for bd, want, n in outs:
+        assert oracle.rel_fro(host_colmajor(bd), want) <= tol(n)
+
+
 @pytest.mark.parametrize("transr,uplo", LAYOUTS)
 @pytest.mark.parametrize("n", [1, 2, 64, 65, 129, 300])
 def test_pftrs_min_matrix_integer_exact(h, transr, uplo, n):

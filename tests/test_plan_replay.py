@@ -103,3 +103,14 @@ def test_plan_leaf_counts():
             ops = rfp.rfp_plan("I", t, u, n)
             leaves = [o for o in ops if o.kind == rfp.PLAN_TRTRI_LEAF]
             assert len(leaves) == -(-m1 // 64) + -(-m2 // 64)
+
+
+def test_pftrs_plan_is_two_fused_solves():
+    """PFTRS is the diagonal-block inverses of L11 and L22 followed by one
+    blocked substitution per direction over the whole factor."""
+    for t, u in LAYOUTS:
+        ops = rfp.rfp_plan("S", t, u, 1001, 7, 1003)
+        assert [o.kind for o in ops] == [rfp.PLAN_TRTRI_LEAVES] * 2 + [rfp.PLAN_BLOCK_SOLVE] * 2
+        assert [o.tri_a for o in ops[2:]] == [0, 1]
+        assert all(o.stream == 0 for o in ops)
+        assert tuple(ops[2].d) == (rfp.PLAN_BUF_B, 0, 1, 1003)
