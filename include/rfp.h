@@ -99,6 +99,55 @@ int rfp_spftrs(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, 
 int rfp_spftri(rfp_handle_t h, char transr, char uplo, int64_t n, float* arf, int* info, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Mixed precision with iterative refinement (not in the paper: the FP32
+ * counterparts above are the paper's; the refinement follows the classical
+ * mixed-precision iterative refinement of a Cholesky solve, as in LAPACK's
+ * DSPOSV, over the RFP format).
+ */
+enum { RFP_PREC_FP32 = 0, RFP_PREC_FP16 = 1, RFP_PREC_BF16 = 2 };
+
+/* Scaled cast: s[i] = 1/sqrt(a_ii) when scale != 0 (else 1), and
+ * arf32 = (float)(((a_ij * s_i) * s_j) * mu) on every stored entry, in the
+ * same RFP layout (so diag(s) A diag(s) has a unit diagonal before mu).  Each
+ * product is rounded in FP64 in that order, then rounded once to FP32.  A
+ * diagonal entry that is not positive gives s_i = NaN.  s is a device array of
+ * n doubles.  Argument order: TRANSR=1, UPLO=2, N=3, ARF=4, SCALE=5, MU=6
+ * (positive, finite), S=7, ARF32=8. */
+int rfp_dpfcast_s(rfp_handle_t h, char transr, char uplo, int64_t n, const double* arf, int scale, double mu,
+                  double* s, float* arf32, hipStream_t stream);
+
+/* LANSF (the paper's routine table, "Norm"): *out (device double) = the norm
+ * of the symmetric matrix held in arf: 'M' max |a_ij|, '1', 'O' or 'I' the
+ * one-norm (= infinity-norm), 'F' or 'E' Frobenius.  The one-norm and
+ * Frobenius sums are accumulated with atomics (order not fixed).  Argument
+ * order: NORM=1, TRANSR=2, UPLO=3, N=4, A=5, OUT=6. */
+int rfp_dlansf(rfp_handle_t h, char norm, char transr, char uplo, int64_t n, const double* arf, double* out,
+               hipStream_t stream);
+
+/* Solve A X = B for the FP64 SPD matrix in arf (left untouched) by a
+ * low-precision Cholesky factor and FP64 iterative refinement:
+ *   As = rfp_dpfcast_s(A, scale = 1, mu = 1) in FP32; Ls = PFTRF(As) with the
+ *   updates in precision fprec (RFP_PREC_FP32: FP32 MFMA);
+ *   X = 0, R = B; repeat: X += D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2} R (solve in
+ *   FP32, update in FP64); R = B - A X (FP64, from arf); until the normwise
+ *   backward error max_c ||R_c||_inf / (||A||_inf ||X_c||_inf + ||B_c||_inf)
+ *   is <= tol.
+ * Falls back to the FP64 PFTRF + PFTRS on a copy of A when the low-precision
+ * factor is not positive definite, when an iteration fails to cut the
+ * backward error below 0.9 times the previous one, or after max_iter sweeps.
+ * Host outputs: *iter = number of sweeps when refinement converged, or the
+ * fall-back reason: -1 max_iter reached, -2 stalled, -3 low-precision factor
+ * not positive definite; *info = the FP64 PFTRF INFO of a fall-back (0
+ * otherwise).  X (n x nrhs, ldx) receives the solution; b is only read.
+ * The call synchronises with `stream` once per sweep (to read the backward
+ * error) and returns when the solution is complete.  Argument order:
+ * FPREC=1, TRANSR=2, UPLO=3, N=4, NRHS=5, A=6, B=7, LDB=8, X=9, LDX=10,
+ * TOL=11 (positive), MAX_ITER=12 (>= 1), ITER=13, INFO=14. */
+int rfp_dpfsv_ir(rfp_handle_t h, int fprec, char transr, char uplo, int64_t n, int64_t nrhs, const double* arf,
+                 const double* b, int64_t ldb, double* x, int64_t ldx, double tol, int max_iter, int* iter, int* info,
+                 hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Kernel timing (introspection, used by the benchmark for its roofline).
  * While enabled, every kernel the handle's calls launch is bracketed by a pair
  * of HIP events on the call's stream.  rfp_profile_read waits for the device,

@@ -32,6 +32,7 @@ def lib():
 _i64 = ctypes.c_longlong
 _chr = ctypes.c_char
 _dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
 
 
 def _declare(L):
@@ -63,6 +64,11 @@ def _declare(L):
     L.orc_norm_inf.restype = ctypes.c_double
     L.orc_norm_inf.argtypes = [_chr, _chr, _i64, _dp]
     L.orc_backward_error.restype = ctypes.c_double
+    L.orc_norm_max.argtypes = [_chr, _chr, _i64, _dp]
+    L.orc_norm_max.restype = ctypes.c_double
+    L.orc_norm_fro.argtypes = [_chr, _chr, _i64, _dp]
+    L.orc_norm_fro.restype = ctypes.c_double
+    L.orc_pfcast_s.argtypes = [_chr, _chr, _i64, _dp, ctypes.c_int, ctypes.c_double, _dp, _vp]
     L.orc_backward_error.argtypes = [_chr, _chr, _i64, _i64, _dp, _dp, _i64, _dp, _i64]
     L.orc_factor_residual.restype = ctypes.c_double
     L.orc_factor_residual.argtypes = [_chr, _chr, _i64, _dp, _dp]
@@ -175,6 +181,26 @@ def pftri(transr, uplo, n, arf_factor):
 def norm_inf(transr, uplo, n, arf):
     arf = np.ascontiguousarray(arf, dtype=np.float64)
     return lib().orc_norm_inf(_c(transr), _c(uplo), n, _p(arf))
+
+
+def norm_max(transr, uplo, n, arf):
+    arf = np.ascontiguousarray(arf, dtype=np.float64)
+    return lib().orc_norm_max(_c(transr), _c(uplo), n, _p(arf))
+
+
+def norm_fro(transr, uplo, n, arf):
+    arf = np.ascontiguousarray(arf, dtype=np.float64)
+    return lib().orc_norm_fro(_c(transr), _c(uplo), n, _p(arf))
+
+
+def pfcast_s(transr, uplo, n, arf, scale=True, mu=1.0):
+    """(s, arf32): diagonal scaling vector and the scaled FP32 RFP copy."""
+    arf = np.ascontiguousarray(arf, dtype=np.float64)
+    s = np.empty(n)
+    out = np.zeros(arf.size, dtype=np.float32)
+    lib().orc_pfcast_s(_c(transr), _c(uplo), n, _p(arf), 1 if scale else 0, float(mu), _p(s),
+                       out.ctypes.data_as(_vp))
+    return s, out
 
 
 def backward_error(transr, uplo, n, arf_a, b, x):

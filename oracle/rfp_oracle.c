@@ -411,6 +411,52 @@ double orc_norm_inf(char transr, char uplo, i64 n, const double *arf)
     return (double)best;
 }
 
+/* max |a_ij| and the Frobenius norm of the symmetric matrix held in RFP
+ * (the LANSF norms of the paper's routine table), by visiting every (i, j). */
+double orc_norm_max(char transr, char uplo, i64 n, const double *arf)
+{
+    double best = 0.0;
+    for (i64 i = 0; i < n; i++)
+        for (i64 j = 0; j < n; j++) {
+            double v = fabs(sym_at(transr, uplo, n, arf, i, j));
+            if (v > best) best = v;
+        }
+    return best;
+}
+
+double orc_norm_fro(char transr, char uplo, i64 n, const double *arf)
+{
+    long double s = 0.0L;
+    for (i64 i = 0; i < n; i++)
+        for (i64 j = 0; j < n; j++) {
+            long double v = (long double)sym_at(transr, uplo, n, arf, i, j);
+            s += v * v;
+        }
+    return (double)sqrtl(s);
+}
+
+/* Scaled cast of the mixed-precision solve (not part of the paper; the
+ * scaling D^{-1/2} A D^{-1/2} with D = diag(A) is the classical symmetric
+ * equilibration): s_i = 1 / sqrt(a_ii) when scale is set (NaN for a
+ * non-positive a_ii), else 1; then every stored entry becomes
+ * (float)(((a_ij * s_i) * s_j) * mu) with i >= j, each product rounded in
+ * binary64 in that order. */
+void orc_pfcast_s(char transr, char uplo, i64 n, const double *arf, int scale, double mu, double *s, float *out)
+{
+    for (i64 i = 0; i < n; i++) {
+        double d = sym_at(transr, uplo, n, arf, i, i);
+        s[i] = scale ? (d > 0.0 ? 1.0 / sqrt(d) : NAN) : 1.0;
+    }
+    for (i64 j = 0; j < n; j++)
+        for (i64 i = j; i < n; i++) {
+            i64 p = orc_rfp_pos(transr, uplo, n, i, j);
+            double v = arf[p] * s[i];
+            v = v * s[j];
+            v = v * mu;
+            out[p] = (float)v;
+        }
+}
+
 /* Normwise backward error of a solve, max over columns:
  *   eta = ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf).
  * A is the original matrix in RFP; residuals accumulate in long double. */

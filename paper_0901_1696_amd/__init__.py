@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "librfp.so")
 RFP_ERR_HANDLE = -101
 RFP_ERR_RUNTIME = -102
 LAYOUTS = [(t, u) for t in "NT" for u in "LU"]
+PREC_FP32, PREC_FP16, PREC_BF16 = 0, 1, 2
 
 _lib = None
 
@@ -50,6 +51,10 @@ _SIGS = {
     "rfp_spftrf": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_spftrs": [_vp, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp],
     "rfp_spftri": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
+    "rfp_dpfcast_s": [_vp, _chr, _chr, _i64, _vp, _int, ctypes.c_double, _vp, _vp, _vp],
+    "rfp_dlansf": [_vp, _chr, _chr, _chr, _i64, _vp, _vp, _vp],
+    "rfp_dpfsv_ir": [_vp, _int, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp, _i64, ctypes.c_double, _int,
+                     ctypes.POINTER(_int), ctypes.POINTER(_int), _vp],
     "rfp_plan": [_chr, _chr, _chr, _i64, _i64, _i64, _vp, _i64, ctypes.POINTER(_i64)],
     "rfp_profile_enable": [_vp, _int],
     "rfp_profile_read": [_vp, _vp, _int, ctypes.POINTER(_int)],
@@ -236,3 +241,26 @@ def rfp_spftrs(h, transr, uplo, n, arf, b, stream=None):
 def rfp_spftri(h, transr, uplo, n, arf, info, stream=None):
     _check("rfp_spftri", lib().rfp_spftri(h.value, _c(transr), _c(uplo), n, _ptr(arf), _ptr(info),
                                           _stream(stream)))
+
+
+def rfp_dpfcast_s(h, transr, uplo, n, arf, scale, mu, s, arf32, stream=None):
+    _check("rfp_dpfcast_s", lib().rfp_dpfcast_s(h.value, _c(transr), _c(uplo), n, _ptr(arf), int(scale), float(mu),
+                                                _ptr(s), _ptr(arf32), _stream(stream)))
+
+
+def rfp_dlansf(h, norm, transr, uplo, n, arf, out, stream=None):
+    _check("rfp_dlansf", lib().rfp_dlansf(h.value, _c(norm), _c(transr), _c(uplo), n, _ptr(arf), _ptr(out),
+                                          _stream(stream)))
+
+
+def rfp_dpfsv_ir(h, fprec, transr, uplo, n, arf, b, x, tol=1e-14, max_iter=50, stream=None):
+    """Mixed-precision solve with FP64 refinement; returns (iter, info) (host ints)."""
+    pb, ldb, nrhs = _colmajor(b, "b")
+    px, ldx, nx = _colmajor(x, "x")
+    if nx != nrhs:
+        raise ValueError("x and b must have the same number of columns")
+    it, info = _int(0), _int(0)
+    _check("rfp_dpfsv_ir", lib().rfp_dpfsv_ir(h.value, int(fprec), _c(transr), _c(uplo), n, nrhs, _ptr(arf), pb, ldb,
+                                              px, ldx, float(tol), int(max_iter), ctypes.byref(it),
+                                              ctypes.byref(info), _stream(stream)))
+    return it.value, info.value

@@ -1,0 +1,293 @@
+// Kernels of the mixed-precision solve with iterative refinement: the
+// scaled cast of the FP64 RFP matrix to an FP32 RFP workspace, norms of a
+// symmetric matrix held in RFP, and the elementwise steps of a refinement
+// sweep (scaled cast of the residual, FP64 update of the solution, column
+// maxima for the backward error).
+//
+// Every RFP kernel walks the three blocks T1, S and T2 through their
+// canonical lower views; each view has one unit stride, and the 64 x 64 tile
+// of a workgroup is read with the fast thread index along it.
+#include <cstdio>
+
+#include "rfp_common.h"
+
+namespace rfp {
+
+namespace {
+constexpr int TT = 64;  // tile edge of the RFP block kernels
+}
+
+// s[i] = 1 / sqrt(a_ii) (scale != 0) or 1; NaN for a diagonal entry that is
+// not positive, so that the scaled matrix cannot be factored.
+__global__ void diag_scale_kernel(Mat<const double> t1, int64_t m1, Mat<const double> t2, int64_t m2, int scale,
+                                  double* s)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m1 + m2) return;
+    const double d = i < m1 ? t1.at(i, i) : t2.at(i - m1, i - m1);
+    double v = 1.0;
+    if (scale) v = d > 0.0 ? 1.0 / sqrt(d) : __builtin_nan("");
+    s[i] = v;
+}
+
+// dst(i, j) = (float)(((src(i, j) * sr[i]) * sc[j]) * mu) over an m x n block
+// (lower triangle only if lower); src and dst have the same strides.
+__global__ __launch_bounds__(256) void cast_block_kernel(Mat<const double> src, Mat<float> dst, int64_t m, int64_t n,
+                                                         int lower, const double* sr, const double* sc, double mu,
+                                                         int64_t tiles_m)
+{
+    const int64_t ti = blockIdx.x % tiles_m, tj = blockIdx.x / tiles_m;
+    const int64_t i0 = ti * TT, j0 = tj * TT;
+    if (lower && j0 > i0 + TT - 1) return;
+    const int t = threadIdx.x, fast = t % TT, slow = t / TT;
+    const bool rows = src.rs == 1;
+#pragma unroll 4
+    for (int r = 0; r < TT / 4; r++) {
+        const int li = rows ? fast : slow + 4 * r;
+        const int lj = rows ? slow + 4 * r : fast;
+        const int64_t i = i0 + li, j = j0 + lj;
+        if (i < m && j < n && (!lower || i >= j)) {
+            double v = src.at(i, j) * sr[i];
+            v = v * sc[j];
+            v = v * mu;
+            dst.at(i, j) = (float)v;
+        }
+    }
+}
+
+hipError_t pf_cast_scale(hipStream_t st, const RfpView<const double>& a, const RfpView<float>& o, int scale, double mu,
+                         double* s)
+{
+    const int64_t n = a.m1 + a.m2;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(diag_scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a.t1, a.m1, a.t2, a.m2,
+                       scale, s);
+    auto blk = [&](Mat<const double> src, Mat<float> dst, int64_t m, int64_t nn, bool lower, const double* sr,
+                   const double* sc) {
+        if (m <= 0 || nn <= 0) return;
+        const int64_t tm = (m + TT - 1) / TT, tn = (nn + TT - 1) / TT;
+        hipLaunchKernelGGL(cast_block_kernel, dim3((unsigned)(tm * tn)), dim3(256), 0, st, src, dst, m, nn,
+                           lower ? 1 : 0, sr, sc, mu, tm);
+    };
+    blk(a.t1, o.t1, a.m1, a.m1, true, s, s);
+    blk(a.s, o.s, a.m2, a.m1, false, s + a.m1, s);
+    blk(a.t2, o.t2, a.m2, a.m2, true, s + a.m1, s + a.m1);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- norms
+// Per 64 x 64 tile of a block with global row / column offsets gi0 / gj0
+// (symmetric matrix: an off-diagonal stored entry also stands for its mirror):
+//   rowsum[g] += |a| for both rows it belongs to, maxabs = max |a|,
+//   sumsq += a^2 (twice off the diagonal).
+__device__ __forceinline__ void atomic_max_nonneg(double* p, double v)
+{
+    // non-negative doubles order like their bit patterns
+    atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ __launch_bounds__(256) void sym_norm_kernel(Mat<const double> a, int64_t m, int64_t n, int lower,
+                                                       int64_t gi0, int64_t gj0, int64_t tiles_m, double* rowsum,
+                                                       double* maxabs, double* sumsq)
+{
+    __shared__ double rs[TT], cs[TT];
+    __shared__ double red[256];
+    __shared__ double redm[256];
+    const int64_t ti = blockIdx.x % tiles_m, tj = blockIdx.x / tiles_m;
+    const int64_t i0 = ti * TT, j0 = tj * TT;
+    if (lower && j0 > i0 + TT - 1) return;
+    const int t = threadIdx.x, fast = t % TT, slow = t / TT;
+    if (t < TT) rs[t] = cs[t] = 0.0;
+    __syncthreads();
+    const bool rows = a.rs == 1;
+    double sq = 0.0, mx = 0.0;
+    for (int r = 0; r < TT / 4; r++) {
+        const int li = rows ? fast : slow + 4 * r;
+        const int lj = rows ? slow + 4 * r : fast;
+        const int64_t i = i0 + li, j = j0 + lj;
+        if (i < m && j < n && (!lower || i >= j)) {
+            const double v = fabs(a.at(i, j));
+            const bool diag = gi0 + i == gj0 + j;
+            atomicAdd(&rs[li], v);
+            if (!diag) atomicAdd(&cs[lj], v);
+            sq += diag ? v * v : 2.0 * v * v;
+            mx = v > mx ? v : mx;
+        }
+    }
+    red[t] = sq;
+    redm[t] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            red[t] += red[t + w];
+            redm[t] = redm[t] > redm[t + w] ? redm[t] : redm[t + w];
+        }
+        __syncthreads();
+    }
+    if (t < TT) {
+        if (i0 + t < m && rs[t] != 0.0) atomicAdd(&rowsum[gi0 + i0 + t], rs[t]);
+        if (j0 + t < n && cs[t] != 0.0) atomicAdd(&rowsum[gj0 + j0 + t], cs[t]);
+    }
+    if (t == 0) {
+        atomicAdd(sumsq, red[0]);
+        atomic_max_nonneg(maxabs, redm[0]);
+    }
+}
+
+__global__ void fill_double_kernel(double* p, int64_t n, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t fill_double(hipStream_t s, double* p, int64_t n, double v)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_double_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// out = max_i v[i] (non-negative entries), one workgroup
+__global__ __launch_bounds__(256) void max_reduce_kernel(const double* v, int64_t n, double* out)
+{
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) m = v[i] > m ? v[i] : m;
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + w] ? red[threadIdx.x]
+                                                                                          : red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void norm_finish_kernel(int which, const double* inf, const double* maxabs, const double* sumsq,
+                                   double* out)
+{
+    if (threadIdx.x != 0) return;
+    *out = which == 0 ? *maxabs : which == 1 ? *inf : sqrt(*sumsq);
+}
+
+// work: n + 3 doubles.  which: 0 max-abs, 1 one/infinity norm, 2 Frobenius.
+hipError_t pf_norm(hipStream_t st, const RfpView<const double>& a, int which, double* work, double* out)
+{
+    const int64_t n = a.m1 + a.m2;
+    double* rowsum = work;
+    double* inf = work + n;
+    double* maxabs = work + n + 1;
+    double* sumsq = work + n + 2;
+    hipError_t e = fill_double(st, work, n + 3, 0.0);
+    if (e != hipSuccess) return e;
+    auto blk = [&](Mat<const double> v, int64_t m, int64_t nn, bool lower, int64_t gi0, int64_t gj0) {
+        if (m <= 0 || nn <= 0) return;
+        const int64_t tm = (m + TT - 1) / TT, tn = (nn + TT - 1) / TT;
+        hipLaunchKernelGGL(sym_norm_kernel, dim3((unsigned)(tm * tn)), dim3(256), 0, st, v, m, nn, lower ? 1 : 0,
+                           gi0, gj0, tm, rowsum, maxabs, sumsq);
+    };
+    blk(a.t1, a.m1, a.m1, true, 0, 0);
+    blk(a.s, a.m2, a.m1, false, a.m1, 0);
+    blk(a.t2, a.m2, a.m2, true, a.m1, a.m1);
+    if (n > 0) hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, st, rowsum, n, inf);
+    hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(64), 0, st, which, inf, maxabs, sumsq, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- refinement sweep
+// out(i, c) = (float)(s[i] * r(i, c))
+__global__ void ir_scale_cast_kernel(const double* r, int64_t ldr, const double* s, float* out, int64_t ldo, int64_t n,
+                                     int64_t nrhs)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (i < n && c < nrhs) out[i + c * ldo] = (float)(s[i] * r[i + c * ldr]);
+}
+
+// x(i, c) += (double)d(i, c) * s[i] * mu
+__global__ void ir_update_kernel(double* x, int64_t ldx, const double* s, double mu, const float* d, int64_t ldd,
+                                 int64_t n, int64_t nrhs)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (i < n && c < nrhs) x[i + c * ldx] += ((double)d[i + c * ldd] * s[i]) * mu;
+}
+
+// out[c] = max_i |v(i, c)|, one workgroup per column
+__global__ __launch_bounds__(256) void colmax_kernel(const double* v, int64_t ld, int64_t n, double* out)
+{
+    __shared__ double red[256];
+    const int64_t c = blockIdx.x;
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double a = fabs(v[i + c * ld]);
+        m = (a > m || a != a) ? a : m;  // a NaN wins
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double a = red[threadIdx.x], b = red[threadIdx.x + w];
+            red[threadIdx.x] = (b > a || b != b) ? b : a;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = red[0];
+}
+
+// eta = max_c rmax[c] / (anorm * xmax[c] + bmax[c])  (normwise backward error)
+__global__ __launch_bounds__(256) void eta_kernel(const double* rmax, const double* xmax, const double* bmax,
+                                                  const double* anorm, int64_t nrhs, double* eta)
+{
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int64_t c = threadIdx.x; c < nrhs; c += 256) {
+        const double den = *anorm * xmax[c] + bmax[c];
+        const double e = den > 0.0 ? rmax[c] / den : (rmax[c] > 0.0 ? __builtin_inf() : 0.0);
+        m = (e > m || e != e) ? e : m;
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double a = red[threadIdx.x], b = red[threadIdx.x + w];
+            red[threadIdx.x] = (b > a || b != b) ? b : a;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *eta = red[0];
+}
+
+hipError_t ir_scale_cast(hipStream_t st, const double* r, int64_t ldr, const double* s, float* out, int64_t ldo,
+                         int64_t n, int64_t nrhs)
+{
+    if (n <= 0 || nrhs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ir_scale_cast_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, r,
+                       ldr, s, out, ldo, n, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t ir_update(hipStream_t st, double* x, int64_t ldx, const double* s, double mu, const float* d, int64_t ldd,
+                     int64_t n, int64_t nrhs)
+{
+    if (n <= 0 || nrhs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ir_update_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, x, ldx,
+                       s, mu, d, ldd, n, nrhs);
+    return hipGetLastError();
+}
+
+hipError_t col_max(hipStream_t st, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out)
+{
+    if (nrhs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)nrhs), dim3(256), 0, st, v, ld, n, out);
+    return hipGetLastError();
+}
+
+hipError_t backward_error(hipStream_t st, const double* rmax, const double* xmax, const double* bmax,
+                          const double* anorm, int64_t nrhs, double* eta)
+{
+    hipLaunchKernelGGL(eta_kernel, dim3(1), dim3(256), 0, st, rmax, xmax, bmax, anorm, nrhs, eta);
+    return hipGetLastError();
+}
+
+}  // namespace rfp

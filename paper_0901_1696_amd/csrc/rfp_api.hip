@@ -19,6 +19,9 @@
 #include <vector>
 
 #include "rfp.h"
+#include <cstdio>
+#include <cstdlib>
+
 #include "rfp_common.h"
 
 namespace rfp {
@@ -112,6 +115,8 @@ struct rfp_context {
     int* flags;           // ready flags of the fused triangular solves
     size_t flags_bytes;
     int epoch;            // last epoch handed to a fused solve
+    void* ir;             // mixed-precision solve workspace
+    size_t ir_bytes;
 };
 
 namespace rfp {
@@ -696,6 +701,189 @@ static int pftri_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     return r.err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
+// ------------------------------------------------ mixed precision + IR
+// Workspace carve-up of the refinement driver (256-byte aligned pieces).
+struct IrSpace {
+    float* a32;            // scaled FP32 copy of the matrix, same RFP layout
+    double* s;             // diagonal scaling D^{-1/2}
+    double* r;             // residual, n x nrhs, leading dimension n
+    float* r32;            // scaled residual / correction in FP32
+    double *bmax, *rmax, *xmax, *anorm, *eta, *normwork;
+    int* info;
+    size_t bytes;
+};
+static IrSpace ir_space(void* base, int64_t n, int64_t nrhs)
+{
+    IrSpace w;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return (char*)base + o;
+    };
+    w.a32 = (float*)take(sizeof(float) * (size_t)(n * (n + 1) / 2));
+    w.s = (double*)take(sizeof(double) * (size_t)n);
+    w.r = (double*)take(sizeof(double) * (size_t)(n * nrhs));
+    w.r32 = (float*)take(sizeof(float) * (size_t)(n * nrhs));
+    w.bmax = (double*)take(sizeof(double) * (size_t)nrhs);
+    w.rmax = (double*)take(sizeof(double) * (size_t)nrhs);
+    w.xmax = (double*)take(sizeof(double) * (size_t)nrhs);
+    w.anorm = (double*)take(sizeof(double));
+    w.eta = (double*)take(sizeof(double));
+    w.normwork = (double*)take(sizeof(double) * (size_t)(n + 3));
+    w.info = (int*)take(sizeof(int));
+    w.bytes = off;
+    return w;
+}
+
+// R = B - A X with A symmetric in RFP (FP64): per block row of the 2 x 2
+// partition, the lower triangle of each diagonal block, its strictly lower
+// part transposed, and S or S^T.
+static hipError_t rfp_residual(const Exec& ex, const RfpView<const double>& v, const double* b, int64_t ldb,
+                               const double* x, int64_t ldx, double* r, int64_t nrhs)
+{
+    const int64_t n = v.m1 + v.m2, m1 = v.m1, m2 = v.m2;
+    hipError_t e = copy2d<double, double>(ex.stream, Mat<double>{r, 1, n}, Mat<const double>{b, 1, ldb}, n, nrhs,
+                                          false);
+    if (e != hipSuccess) return e;
+    Mat<const double> X1{x, 1, ldx}, X2 = X1.sub(m1, 0);
+    Mat<double> R1{r, 1, n}, R2 = R1.sub(m1, 0);
+    const double m1d = -1.0, one = 1.0;
+    hipError_t es[6] = {
+        gemm<double>(ex, m1, nrhs, m1, m1d, v.t1, TRI_LOWER, X1.tr(), TRI_NONE, one, R1, false),
+        gemm<double>(ex, m1, nrhs, m1, m1d, v.t1.tr(), TRI_SUPPER, X1.tr(), TRI_NONE, one, R1, false),
+        m2 > 0 ? gemm<double>(ex, m1, nrhs, m2, m1d, v.s.tr(), TRI_NONE, X2.tr(), TRI_NONE, one, R1, false)
+               : hipSuccess,
+        m2 > 0 ? gemm<double>(ex, m2, nrhs, m1, m1d, v.s, TRI_NONE, X1.tr(), TRI_NONE, one, R2, false) : hipSuccess,
+        m2 > 0 ? gemm<double>(ex, m2, nrhs, m2, m1d, v.t2, TRI_LOWER, X2.tr(), TRI_NONE, one, R2, false)
+               : hipSuccess,
+        m2 > 0 ? gemm<double>(ex, m2, nrhs, m2, m1d, v.t2.tr(), TRI_SUPPER, X2.tr(), TRI_NONE, one, R2, false)
+               : hipSuccess};
+    for (hipError_t q : es)
+        if (q != hipSuccess) return q;
+    return hipSuccess;
+}
+
+// Host copy of a few device words (the refinement decisions): one sync.
+template <typename V>
+static hipError_t fetch(hipStream_t s, const V* d, V* h)
+{
+    hipError_t e = hipMemcpyAsync(h, d, sizeof(V), hipMemcpyDeviceToHost, s);
+    return e == hipSuccess ? hipStreamSynchronize(s) : e;
+}
+
+// RFP_IR_TRACE=1 prints the backward error of every refinement sweep to stderr.
+static bool ir_trace()
+{
+    static int on = -1;
+    if (on < 0) {
+        const char* e = getenv("RFP_IR_TRACE");
+        on = (e && e[0] == '1') ? 1 : 0;
+    }
+    return on == 1;
+}
+
+static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64_t n, int64_t nrhs, const double* arf,
+                        const double* b, int64_t ldb, double* x, int64_t ldx, double tol, int max_iter, int* iter,
+                        int* info, hipStream_t st)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (fprec != RFP_PREC_FP32) return -1;
+    if (bad_tr(transr)) return -2;
+    if (bad_ul(uplo)) return -3;
+    if (n < 0) return -4;
+    if (nrhs < 0) return -5;
+    if (n > 0 && !arf) return -6;
+    if (n > 0 && nrhs > 0 && !b) return -7;
+    if (ldb < std::max<int64_t>(1, n)) return -8;
+    if (n > 0 && nrhs > 0 && !x) return -9;
+    if (ldx < std::max<int64_t>(1, n)) return -10;
+    if (!(tol > 0.0)) return -11;
+    if (max_iter < 1) return -12;
+    if (!iter) return -13;
+    if (!info) return -14;
+    *iter = 0;
+    *info = 0;
+    if (n == 0 || nrhs == 0) return 0;
+    DeviceGuard g(h->device);
+    const IrSpace probe = ir_space(nullptr, n, nrhs);
+    if (ensure(&h->ir, &h->ir_bytes, probe.bytes) != hipSuccess) return RFP_ERR_RUNTIME;
+    IrSpace w = ir_space(h->ir, n, nrhs);
+    RfpBlocks blk;
+    rfp_blocks(transr, uplo, n, &blk);
+    RfpView<const double> v = rfp_view(blk, arf);
+    RfpView<float> v32 = rfp_view(blk, w.a32);
+    Exec ex{};
+    ex.stream = st;
+    ex.prof = h->prof;
+    const double mu = 1.0;
+    hipError_t e = hipSuccess;
+    auto ok = [&](hipError_t q) {
+        if (q != hipSuccess && e == hipSuccess) e = q;
+        return e == hipSuccess;
+    };
+    // scaled low-precision copy, its factor, and the norms that stay fixed
+    ok(pf_cast_scale(st, v, v32, 1, mu, w.s));
+    ok(pf_norm(st, v, 1, w.normwork, w.anorm));
+    ok(col_max(st, b, ldb, n, nrhs, w.bmax));
+    if (!ok(hipGetLastError())) return RFP_ERR_RUNTIME;
+    int rc = pftrf_impl<float>(h, transr, uplo, n, w.a32, w.info, st);
+    if (rc != 0) return rc;
+    int linfo = 0;
+    if (!ok(fetch(st, w.info, &linfo))) return RFP_ERR_RUNTIME;
+    int code = 0;  // 0 converged, else the fallback reason
+    if (linfo != 0) code = -3;
+    if (code == 0) {
+        ex.splitk_ws = h->splitk;
+        ex.splitk_bytes = h->splitk_bytes;
+        // x = 0, r = b; then sweeps of  x += mu D^{-1/2} (L L^T)^{-1} D^{-1/2} r,  r = b - A x
+        ok(copy2d<double, double>(st, Mat<double>{w.r, 1, n}, Mat<const double>{b, 1, ldb}, n, nrhs, false));
+        for (int64_t c = 0; c < nrhs; c++) ok(fill_double(st, x + c * ldx, n, 0.0));
+        double prev = 0.0;
+        code = -1;
+        for (int it = 1; it <= max_iter; it++) {
+            ok(ir_scale_cast(st, w.r, n, w.s, w.r32, n, n, nrhs));
+            if (e != hipSuccess) return RFP_ERR_RUNTIME;
+            rc = pftrs_impl<float>(h, transr, uplo, n, nrhs, w.a32, w.r32, n, st);
+            if (rc != 0) return rc;
+            ok(ir_update(st, x, ldx, w.s, mu, w.r32, n, n, nrhs));
+            ok(rfp_residual(ex, v, b, ldb, x, ldx, w.r, nrhs));
+            ok(col_max(st, w.r, n, n, nrhs, w.rmax));
+            ok(col_max(st, x, ldx, n, nrhs, w.xmax));
+            ok(backward_error(st, w.rmax, w.xmax, w.bmax, w.anorm, nrhs, w.eta));
+            double eta = 0.0;
+            if (!ok(fetch(st, w.eta, &eta))) return RFP_ERR_RUNTIME;
+            if (ir_trace()) fprintf(stderr, "rfp_dpfsv_ir: sweep %d backward error %.3e\n", it, eta);
+            if (eta <= tol) {
+                code = it;
+                break;
+            }
+            // stalled: the backward error no longer falls by a useful factor
+            if (it > 1 && !(eta < 0.9 * prev)) {
+                code = -2;
+                break;
+            }
+            prev = eta;
+        }
+    }
+    *iter = code;
+    if (code > 0) return 0;
+    // fall-back: FP64 factor of a copy of A, then the FP64 solve
+    void* a64 = nullptr;
+    if (hipMalloc(&a64, sizeof(double) * (size_t)(n * (n + 1) / 2)) != hipSuccess) return RFP_ERR_RUNTIME;
+    ok(hipMemcpyAsync(a64, arf, sizeof(double) * (size_t)(n * (n + 1) / 2), hipMemcpyDeviceToDevice, st));
+    rc = pftrf_impl<double>(h, transr, uplo, n, (double*)a64, w.info, st);
+    if (rc == 0) ok(fetch(st, w.info, info));
+    if (rc == 0 && e == hipSuccess && *info == 0) {
+        ok(copy2d<double, double>(st, Mat<double>{x, 1, ldx}, Mat<const double>{b, 1, ldb}, n, nrhs, false));
+        rc = pftrs_impl<double>(h, transr, uplo, n, nrhs, (const double*)a64, x, ldx, st);
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(a64);
+    if (rc != 0) return rc;
+    return e == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
 }  // namespace rfp
 
 using namespace rfp;
@@ -723,6 +911,7 @@ int rfp_destroy(rfp_handle_t h)
         if (h->splitk) (void)hipFree(h->splitk);
         if (h->inv) (void)hipFree(h->inv);
         if (h->flags) (void)hipFree(h->flags);
+        if (h->ir) (void)hipFree(h->ir);
         for (int i = 0; i < h->nev; i++) (void)hipEventDestroy(h->ev[i]);
         if (h->aux) (void)hipStreamDestroy(h->aux);
         delete h->prof;
@@ -848,6 +1037,54 @@ int rfp_plan(char routine, char transr, char uplo, int64_t n, int64_t nrhs, int6
     }
     *count = rec.count;
     return rc;
+}
+
+int rfp_dpfcast_s(rfp_handle_t h, char transr, char uplo, int64_t n, const double* arf, int scale, double mu,
+                  double* s, float* arf32, hipStream_t stream)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (bad_tr(transr)) return -1;
+    if (bad_ul(uplo)) return -2;
+    if (n < 0) return -3;
+    if (n > 0 && !arf) return -4;
+    if (!(mu > 0.0) || mu > 1e300) return -6;
+    if (n > 0 && !s) return -7;
+    if (n > 0 && !arf32) return -8;
+    if (n == 0) return 0;
+    DeviceGuard g(h->device);
+    RfpBlocks b;
+    rfp_blocks(transr, uplo, n, &b);
+    return pf_cast_scale(stream, rfp_view(b, arf), rfp_view(b, arf32), scale, mu, s) == hipSuccess ? 0
+                                                                                                 : RFP_ERR_RUNTIME;
+}
+
+int rfp_dlansf(rfp_handle_t h, char norm, char transr, char uplo, int64_t n, const double* arf, double* out,
+               hipStream_t stream)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    const int c = upc(norm);
+    const int which = c == 'M' ? 0 : (c == '1' || c == 'O' || c == 'I') ? 1 : (c == 'F' || c == 'E') ? 2 : -1;
+    if (which < 0) return -1;
+    if (bad_tr(transr)) return -2;
+    if (bad_ul(uplo)) return -3;
+    if (n < 0) return -4;
+    if (n > 0 && !arf) return -5;
+    if (!out) return -6;
+    DeviceGuard g(h->device);
+    if (n == 0) return fill_double(stream, out, 1, 0.0) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+    // the norm's scratch lives in the refinement workspace
+    const size_t need = sizeof(double) * (size_t)(n + 3);
+    if (ensure(&h->ir, &h->ir_bytes, need) != hipSuccess) return RFP_ERR_RUNTIME;
+    RfpBlocks b;
+    rfp_blocks(transr, uplo, n, &b);
+    return pf_norm(stream, rfp_view(b, arf), which, (double*)h->ir, out) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+int rfp_dpfsv_ir(rfp_handle_t h, int fprec, char transr, char uplo, int64_t n, int64_t nrhs, const double* arf,
+                 const double* b, int64_t ldb, double* x, int64_t ldx, double tol, int max_iter, int* iter, int* info,
+                 hipStream_t stream)
+{
+    return pfsv_ir_impl(h, fprec, transr, uplo, n, nrhs, arf, b, ldb, x, ldx, tol, max_iter, iter, info, stream);
 }
 
 }  // extern "C"

@@ -145,6 +145,23 @@ hipError_t block_solve(const Exec& ex, bool forward, Mat<const T> t1, Mat<const 
 int64_t block_solve_flags(int64_t m1, int64_t m2, int64_t nrhs);
 hipError_t fill_int(hipStream_t s, int* p, int64_t n, int v);
 
+// Mixed-precision building blocks.
+// s[i] = 1/sqrt(a_ii) (scale) or 1, then o = (float)(((a_ij s_i) s_j) mu) on
+// every stored entry, o in the same RFP layout as a.
+hipError_t pf_cast_scale(hipStream_t st, const RfpView<const double>& a, const RfpView<float>& o, int scale, double mu,
+                         double* s);
+// Norm of the symmetric matrix held in a: which = 0 max |a_ij|, 1 one- (=
+// infinity-) norm, 2 Frobenius; work holds n + 3 doubles; *out on the device.
+hipError_t pf_norm(hipStream_t st, const RfpView<const double>& a, int which, double* work, double* out);
+hipError_t fill_double(hipStream_t s, double* p, int64_t n, double v);
+hipError_t ir_scale_cast(hipStream_t st, const double* r, int64_t ldr, const double* s, float* out, int64_t ldo,
+                         int64_t n, int64_t nrhs);
+hipError_t ir_update(hipStream_t st, double* x, int64_t ldx, const double* s, double mu, const float* d, int64_t ldd,
+                     int64_t n, int64_t nrhs);
+hipError_t col_max(hipStream_t st, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out);
+hipError_t backward_error(hipStream_t st, const double* rmax, const double* xmax, const double* bmax,
+                          const double* anorm, int64_t nrhs, double* eta);
+
 // 2-D strided copy dst = src (m x n), optionally only the lower triangle.
 template <typename Td, typename Ts>
 hipError_t copy2d(hipStream_t s, Mat<Td> dst, Mat<const Ts> src, int64_t m, int64_t n, bool lower);
