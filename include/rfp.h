@@ -127,14 +127,19 @@ int rfp_dlansf(rfp_handle_t h, char norm, char transr, char uplo, int64_t n, con
 /* Solve A X = B for the FP64 SPD matrix in arf (left untouched) by a
  * low-precision Cholesky factor and FP64 iterative refinement:
  *   As = rfp_dpfcast_s(A, scale = 1, mu = 1) in FP32; Ls = PFTRF(As) with the
- *   updates in precision fprec (RFP_PREC_FP32: FP32 MFMA);
- *   X = 0, R = B; repeat: X += D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2} R (solve in
- *   FP32, update in FP64); R = B - A X (FP64, from arf); until the normwise
- *   backward error max_c ||R_c||_inf / (||A||_inf ||X_c||_inf + ||B_c||_inf)
- *   is <= tol.
+ *   updates in precision fprec (RFP_PREC_FP32: FP32 MFMA); the preconditioner
+ *   is M^{-1} = D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2} (solves in FP32).
+ *   X = 0, R = B; each sweep corrects X from R in FP64, then R = B - A X
+ *   (FP64, from arf), until the normwise backward error
+ *   max_c ||R_c||_inf / (||A||_inf ||X_c||_inf + ||B_c||_inf) is <= tol.
+ *   A sweep is X += M^{-1} R (classical refinement) until one fails to cut
+ *   the backward error fourfold; later sweeps run 8 steps of conjugate
+ *   gradients on A D = R preconditioned by M^{-1}, in FP64 (refinement with a
+ *   CG inner solver), which converges where kappa(A) u_low is not small.
  * Falls back to the FP64 PFTRF + PFTRS on a copy of A when the low-precision
- * factor is not positive definite, when an iteration fails to cut the
- * backward error below 0.9 times the previous one, or after max_iter sweeps.
+ * factor is not positive definite, when a conjugate-gradient sweep fails to
+ * cut the backward error below 0.9 times the previous one, or after max_iter
+ * sweeps.
  * Host outputs: *iter = number of sweeps when refinement converged, or the
  * fall-back reason: -1 max_iter reached, -2 stalled, -3 low-precision factor
  * not positive definite; *info = the FP64 PFTRF INFO of a fall-back (0

@@ -204,13 +204,58 @@ __global__ void ir_scale_cast_kernel(const double* r, int64_t ldr, const double*
     if (i < n && c < nrhs) out[i + c * ldo] = (float)(s[i] * r[i + c * ldr]);
 }
 
-// x(i, c) += (double)d(i, c) * s[i] * mu
+// x(i, c) += (double)d(i, c) * s[i] * mu   (or x = ..., accumulate == 0)
 __global__ void ir_update_kernel(double* x, int64_t ldx, const double* s, double mu, const float* d, int64_t ldd,
-                                 int64_t n, int64_t nrhs)
+                                 int64_t n, int64_t nrhs, int accumulate)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t c = blockIdx.y;
-    if (i < n && c < nrhs) x[i + c * ldx] += ((double)d[i + c * ldd] * s[i]) * mu;
+    if (i < n && c < nrhs) {
+        const double v = ((double)d[i + c * ldd] * s[i]) * mu;
+        x[i + c * ldx] = accumulate ? x[i + c * ldx] + v : v;
+    }
+}
+
+// out[c] = sum_i u(i, c) v(i, c), one workgroup per column (fixed order)
+__global__ __launch_bounds__(256) void col_dot_kernel(const double* u, const double* v, int64_t ld, int64_t n,
+                                                      double* out)
+{
+    __shared__ double red[256];
+    const int64_t c = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) acc += u[i + c * ld] * v[i + c * ld];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = red[0];
+}
+
+// alpha_c = rz[c] / pq[c] (0 when pq[c] = 0); d += alpha p; r -= alpha q
+__global__ void pcg_step_kernel(double* d, int64_t ldd, double* r, const double* p, const double* q, const double* rz,
+                                const double* pq, int64_t ld, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (i >= n) return;
+    const double a = pq[c] != 0.0 ? rz[c] / pq[c] : 0.0;
+    const int64_t o = i + c * ld;
+    d[i + c * ldd] += a * p[o];
+    r[o] -= a * q[o];
+}
+
+// beta_c = rz_new[c] / rz_old[c] (0 when rz_old[c] = 0); p = z + beta p
+__global__ void pcg_dir_kernel(double* p, const double* z, const double* rz_new, const double* rz_old, int64_t ld,
+                               int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (i >= n) return;
+    const double b = rz_old[c] != 0.0 ? rz_new[c] / rz_old[c] : 0.0;
+    const int64_t o = i + c * ld;
+    p[o] = z[o] + b * p[o];
 }
 
 // out[c] = max_i |v(i, c)|, one workgroup per column
@@ -268,11 +313,36 @@ hipError_t ir_scale_cast(hipStream_t st, const double* r, int64_t ldr, const dou
 }
 
 hipError_t ir_update(hipStream_t st, double* x, int64_t ldx, const double* s, double mu, const float* d, int64_t ldd,
-                     int64_t n, int64_t nrhs)
+                     int64_t n, int64_t nrhs, bool accumulate)
 {
     if (n <= 0 || nrhs <= 0) return hipSuccess;
     hipLaunchKernelGGL(ir_update_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, x, ldx,
-                       s, mu, d, ldd, n, nrhs);
+                       s, mu, d, ldd, n, nrhs, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t col_dot(hipStream_t st, const double* u, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out)
+{
+    if (nrhs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(col_dot_kernel, dim3((unsigned)nrhs), dim3(256), 0, st, u, v, ld, n, out);
+    return hipGetLastError();
+}
+
+hipError_t pcg_step(hipStream_t st, double* d, int64_t ldd, double* r, const double* p, const double* q,
+                    const double* rz, const double* pq, int64_t ld, int64_t n, int64_t nrhs)
+{
+    if (n <= 0 || nrhs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pcg_step_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, d, ldd, r,
+                       p, q, rz, pq, ld, n);
+    return hipGetLastError();
+}
+
+hipError_t pcg_dir(hipStream_t st, double* p, const double* z, const double* rz_new, const double* rz_old, int64_t ld,
+                   int64_t n, int64_t nrhs)
+{
+    if (n <= 0 || nrhs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pcg_dir_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, p, z,
+                       rz_new, rz_old, ld, n);
     return hipGetLastError();
 }
 

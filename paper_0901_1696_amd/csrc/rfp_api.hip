@@ -709,6 +709,9 @@ struct IrSpace {
     double* r;             // residual, n x nrhs, leading dimension n
     float* r32;            // scaled residual / correction in FP32
     double *bmax, *rmax, *xmax, *anorm, *eta, *normwork;
+    double *cr, *cz, *cp, *cq;  // conjugate-gradient vectors, n x nrhs each
+    double *rz0, *rz1, *pq;     // their per-column scalars
+    double* symm;               // partial products of A X
     int* info;
     size_t bytes;
 };
@@ -731,37 +734,27 @@ static IrSpace ir_space(void* base, int64_t n, int64_t nrhs)
     w.anorm = (double*)take(sizeof(double));
     w.eta = (double*)take(sizeof(double));
     w.normwork = (double*)take(sizeof(double) * (size_t)(n + 3));
+    w.cr = (double*)take(sizeof(double) * (size_t)(n * nrhs));
+    w.cz = (double*)take(sizeof(double) * (size_t)(n * nrhs));
+    w.cp = (double*)take(sizeof(double) * (size_t)(n * nrhs));
+    w.cq = (double*)take(sizeof(double) * (size_t)(n * nrhs));
+    w.rz0 = (double*)take(sizeof(double) * (size_t)nrhs);
+    w.rz1 = (double*)take(sizeof(double) * (size_t)nrhs);
+    w.pq = (double*)take(sizeof(double) * (size_t)nrhs);
+    w.symm = (double*)take(symm_thin_workspace((n + 1) / 2, n / 2));
     w.info = (int*)take(sizeof(int));
     w.bytes = off;
     return w;
 }
 
-// R = B - A X with A symmetric in RFP (FP64): per block row of the 2 x 2
-// partition, the lower triangle of each diagonal block, its strictly lower
-// part transposed, and S or S^T.
+// R = B - A X
 static hipError_t rfp_residual(const Exec& ex, const RfpView<const double>& v, const double* b, int64_t ldb,
-                               const double* x, int64_t ldx, double* r, int64_t nrhs)
+                               const double* x, int64_t ldx, double* r, int64_t nrhs, double* ws)
 {
-    const int64_t n = v.m1 + v.m2, m1 = v.m1, m2 = v.m2;
+    const int64_t n = v.m1 + v.m2;
     hipError_t e = copy2d<double, double>(ex.stream, Mat<double>{r, 1, n}, Mat<const double>{b, 1, ldb}, n, nrhs,
                                           false);
-    if (e != hipSuccess) return e;
-    Mat<const double> X1{x, 1, ldx}, X2 = X1.sub(m1, 0);
-    Mat<double> R1{r, 1, n}, R2 = R1.sub(m1, 0);
-    const double m1d = -1.0, one = 1.0;
-    hipError_t es[6] = {
-        gemm<double>(ex, m1, nrhs, m1, m1d, v.t1, TRI_LOWER, X1.tr(), TRI_NONE, one, R1, false),
-        gemm<double>(ex, m1, nrhs, m1, m1d, v.t1.tr(), TRI_SUPPER, X1.tr(), TRI_NONE, one, R1, false),
-        m2 > 0 ? gemm<double>(ex, m1, nrhs, m2, m1d, v.s.tr(), TRI_NONE, X2.tr(), TRI_NONE, one, R1, false)
-               : hipSuccess,
-        m2 > 0 ? gemm<double>(ex, m2, nrhs, m1, m1d, v.s, TRI_NONE, X1.tr(), TRI_NONE, one, R2, false) : hipSuccess,
-        m2 > 0 ? gemm<double>(ex, m2, nrhs, m2, m1d, v.t2, TRI_LOWER, X2.tr(), TRI_NONE, one, R2, false)
-               : hipSuccess,
-        m2 > 0 ? gemm<double>(ex, m2, nrhs, m2, m1d, v.t2.tr(), TRI_SUPPER, X2.tr(), TRI_NONE, one, R2, false)
-               : hipSuccess};
-    for (hipError_t q : es)
-        if (q != hipSuccess) return q;
-    return hipSuccess;
+    return e != hipSuccess ? e : symm_thin(ex, v, x, ldx, -1.0, 1.0, r, n, nrhs, ws);
 }
 
 // Host copy of a few device words (the refinement decisions): one sync.
@@ -836,30 +829,65 @@ static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64
     if (code == 0) {
         ex.splitk_ws = h->splitk;
         ex.splitk_bytes = h->splitk_bytes;
-        // x = 0, r = b; then sweeps of  x += mu D^{-1/2} (L L^T)^{-1} D^{-1/2} r,  r = b - A x
+        // M^{-1} = mu D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2}: the low-precision
+        // preconditioner, applied as a scaled cast, two FP32 triangular
+        // solves and an FP64 rescale into z (or added to z)
+        auto prec = [&](const double* v_in, double* z, int64_t ldz, bool accumulate) {
+            ok(ir_scale_cast(st, v_in, n, w.s, w.r32, n, n, nrhs));
+            if (e != hipSuccess) return false;
+            if (pftrs_impl<float>(h, transr, uplo, n, nrhs, w.a32, w.r32, n, st) != 0) return false;
+            return ok(ir_update(st, z, ldz, w.s, mu, w.r32, n, n, nrhs, accumulate));
+        };
+        // k steps of conjugate gradients on A d = r from d = 0, preconditioned
+        // by M^{-1}, with d added straight into x (FP64 throughout)
+        auto pcg = [&](int k) {
+            ok(copy2d<double, double>(st, Mat<double>{w.cr, 1, n}, Mat<const double>{w.r, 1, n}, n, nrhs, false));
+            if (!prec(w.cr, w.cz, n, false)) return false;
+            ok(copy2d<double, double>(st, Mat<double>{w.cp, 1, n}, Mat<const double>{w.cz, 1, n}, n, nrhs, false));
+            ok(col_dot(st, w.cr, w.cz, n, n, nrhs, w.rz0));
+            double *rz = w.rz0, *rzn = w.rz1;
+            for (int i = 0; i < k && e == hipSuccess; i++) {
+                ok(symm_thin(ex, v, w.cp, n, 1.0, 0.0, w.cq, n, nrhs, w.symm));
+                ok(col_dot(st, w.cp, w.cq, n, n, nrhs, w.pq));
+                ok(pcg_step(st, x, ldx, w.cr, w.cp, w.cq, rz, w.pq, n, n, nrhs));
+                if (i + 1 == k) break;
+                if (!prec(w.cr, w.cz, n, false)) return false;
+                ok(col_dot(st, w.cr, w.cz, n, n, nrhs, rzn));
+                ok(pcg_dir(st, w.cp, w.cz, rzn, rz, n, n, nrhs));
+                std::swap(rz, rzn);
+            }
+            return e == hipSuccess;
+        };
+        // x = 0, r = b; each sweep corrects x from r, then r = b - A x in FP64.
+        // A sweep first applies M^{-1} once (classical refinement); once that
+        // stops cutting the backward error by 4x per sweep, sweeps run
+        // PCG_STEPS preconditioned conjugate-gradient steps instead.
+        constexpr int PCG_STEPS = 8;
         ok(copy2d<double, double>(st, Mat<double>{w.r, 1, n}, Mat<const double>{b, 1, ldb}, n, nrhs, false));
         for (int64_t c = 0; c < nrhs; c++) ok(fill_double(st, x + c * ldx, n, 0.0));
         double prev = 0.0;
+        bool use_pcg = false;
         code = -1;
         for (int it = 1; it <= max_iter; it++) {
-            ok(ir_scale_cast(st, w.r, n, w.s, w.r32, n, n, nrhs));
-            if (e != hipSuccess) return RFP_ERR_RUNTIME;
-            rc = pftrs_impl<float>(h, transr, uplo, n, nrhs, w.a32, w.r32, n, st);
-            if (rc != 0) return rc;
-            ok(ir_update(st, x, ldx, w.s, mu, w.r32, n, n, nrhs));
-            ok(rfp_residual(ex, v, b, ldb, x, ldx, w.r, nrhs));
+            const bool swept_pcg = use_pcg;
+            const bool good = swept_pcg ? pcg(PCG_STEPS) : prec(w.r, x, ldx, true);
+            if (!good) return RFP_ERR_RUNTIME;
+            ok(rfp_residual(ex, v, b, ldb, x, ldx, w.r, nrhs, w.symm));
             ok(col_max(st, w.r, n, n, nrhs, w.rmax));
             ok(col_max(st, x, ldx, n, nrhs, w.xmax));
             ok(backward_error(st, w.rmax, w.xmax, w.bmax, w.anorm, nrhs, w.eta));
             double eta = 0.0;
             if (!ok(fetch(st, w.eta, &eta))) return RFP_ERR_RUNTIME;
-            if (ir_trace()) fprintf(stderr, "rfp_dpfsv_ir: sweep %d backward error %.3e\n", it, eta);
+            if (ir_trace())
+                fprintf(stderr, "rfp_dpfsv_ir: sweep %d (%s) backward error %.3e\n", it, swept_pcg ? "pcg" : "ir",
+                        eta);
             if (eta <= tol) {
                 code = it;
                 break;
             }
-            // stalled: the backward error no longer falls by a useful factor
-            if (it > 1 && !(eta < 0.9 * prev)) {
+            if (it > 1 && !swept_pcg && !(eta < 0.25 * prev)) use_pcg = true;
+            // stalled: a conjugate-gradient sweep no longer cuts the backward error
+            if (it > 1 && swept_pcg && !(eta < 0.9 * prev)) {
                 code = -2;
                 break;
             }

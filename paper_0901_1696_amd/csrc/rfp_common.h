@@ -154,10 +154,20 @@ hipError_t pf_cast_scale(hipStream_t st, const RfpView<const double>& a, const R
 // infinity-) norm, 2 Frobenius; work holds n + 3 doubles; *out on the device.
 hipError_t pf_norm(hipStream_t st, const RfpView<const double>& a, int which, double* work, double* out);
 hipError_t fill_double(hipStream_t s, double* p, int64_t n, double v);
+// Y = beta Y + alpha A X, A symmetric in RFP (FP64), X and Y n x nrhs
+// column-major; ws holds symm_thin_workspace(m1, m2) bytes.
+size_t symm_thin_workspace(int64_t m1, int64_t m2);
+hipError_t symm_thin(const Exec& ex, const RfpView<const double>& v, const double* x, int64_t ldx, double alpha,
+                     double beta, double* y, int64_t ldy, int64_t nrhs, double* ws);
 hipError_t ir_scale_cast(hipStream_t st, const double* r, int64_t ldr, const double* s, float* out, int64_t ldo,
                          int64_t n, int64_t nrhs);
 hipError_t ir_update(hipStream_t st, double* x, int64_t ldx, const double* s, double mu, const float* d, int64_t ldd,
-                     int64_t n, int64_t nrhs);
+                     int64_t n, int64_t nrhs, bool accumulate);
+hipError_t col_dot(hipStream_t st, const double* u, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out);
+hipError_t pcg_step(hipStream_t st, double* d, int64_t ldd, double* r, const double* p, const double* q,
+                    const double* rz, const double* pq, int64_t ld, int64_t n, int64_t nrhs);
+hipError_t pcg_dir(hipStream_t st, double* p, const double* z, const double* rz_new, const double* rz_old, int64_t ld,
+                   int64_t n, int64_t nrhs);
 hipError_t col_max(hipStream_t st, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out);
 hipError_t backward_error(hipStream_t st, const double* rmax, const double* xmax, const double* bmax,
                           const double* anorm, int64_t nrhs, double* eta);
