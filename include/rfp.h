@@ -106,6 +106,15 @@ int rfp_spftri(rfp_handle_t h, char transr, char uplo, int64_t n, float* arf, in
  */
 enum { RFP_PREC_FP32 = 0, RFP_PREC_FP16 = 1, RFP_PREC_BF16 = 2 };
 
+/* PFTRF on an FP32 RFP array with the bulk trailing updates (the GEMM, SYRK
+ * and TRSM-update products of every step, not the diagonal-block leaves and
+ * their in-place panel products) computed with operands rounded to fprec:
+ * RFP_PREC_FP32 (same as rfp_spftrf), RFP_PREC_FP16 or RFP_PREC_BF16, with
+ * FP32 accumulation on the matrix cores.  Argument order: FPREC=1, TRANSR=2,
+ * UPLO=3, N=4, A=5, INFO=6. */
+int rfp_spftrf_mp(rfp_handle_t h, int fprec, char transr, char uplo, int64_t n, float* arf, int* info,
+                  hipStream_t stream);
+
 /* Scaled cast: s[i] = 1/sqrt(a_ii) when scale != 0 (else 1), and
  * arf32 = (float)(((a_ij * s_i) * s_j) * mu) on every stored entry, in the
  * same RFP layout (so diag(s) A diag(s) has a unit diagonal before mu).  Each
@@ -127,7 +136,7 @@ int rfp_dlansf(rfp_handle_t h, char norm, char transr, char uplo, int64_t n, con
 /* Solve A X = B for the FP64 SPD matrix in arf (left untouched) by a
  * low-precision Cholesky factor and FP64 iterative refinement:
  *   As = rfp_dpfcast_s(A, scale = 1, mu = 1) in FP32; Ls = PFTRF(As) with the
- *   updates in precision fprec (RFP_PREC_FP32: FP32 MFMA); the preconditioner
+ *   updates in precision fprec (as rfp_spftrf_mp); the preconditioner
  *   is M^{-1} = D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2} (solves in FP32).
  *   X = 0, R = B; each sweep corrects X from R in FP64, then R = B - A X
  *   (FP64, from arf), until the normwise backward error

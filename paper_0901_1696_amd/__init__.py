@@ -51,6 +51,7 @@ _SIGS = {
     "rfp_spftrf": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_spftrs": [_vp, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp],
     "rfp_spftri": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
+    "rfp_spftrf_mp": [_vp, _int, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_dpfcast_s": [_vp, _chr, _chr, _i64, _vp, _int, ctypes.c_double, _vp, _vp, _vp],
     "rfp_dlansf": [_vp, _chr, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_dpfsv_ir": [_vp, _int, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp, _i64, ctypes.c_double, _int,
@@ -241,6 +242,11 @@ def rfp_spftrs(h, transr, uplo, n, arf, b, stream=None):
 def rfp_spftri(h, transr, uplo, n, arf, info, stream=None):
     _check("rfp_spftri", lib().rfp_spftri(h.value, _c(transr), _c(uplo), n, _ptr(arf), _ptr(info),
                                           _stream(stream)))
+
+
+def rfp_spftrf_mp(h, fprec, transr, uplo, n, arf, info, stream=None):
+    _check("rfp_spftrf_mp", lib().rfp_spftrf_mp(h.value, int(fprec), _c(transr), _c(uplo), n, _ptr(arf), _ptr(info),
+                                                _stream(stream)))
 
 
 def rfp_dpfcast_s(h, transr, uplo, n, arf, scale, mu, s, arf32, stream=None):

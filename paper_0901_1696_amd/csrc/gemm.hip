@@ -12,6 +12,7 @@
 // staged through LDS (double buffered, one barrier per slab); the next slab's
 // global loads are issued before the current slab's MFMAs.
 #include <cstdio>
+#include <type_traits>
 
 #include "rfp_common.h"
 
@@ -47,6 +48,44 @@ struct Mfma<float> {
 
 constexpr int BK = 16, NTH = 256;
 constexpr int KP = BK + 2;  // LDS row pitch (elements): k-contiguous rows, 16-byte aligned, conflict-free
+
+// Low-precision operand modes of the FP32 GEMM (LP): 0 FP32 MFMA; 1 operands
+// rounded to FP16 and 2 to BF16 when staged in LDS, products on the
+// 16x16x16 MFMA with FP32 accumulation.  The 16x16x16 instructions take four
+// consecutive k values per lane: lane l supplies A(l % 16, 4 (l / 16) + j)
+// and B(4 (l / 16) + j, l % 16), j = 0..3; the result layout is the FP32 one.
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+template <typename T, int LP>
+struct Lds {
+    typedef T type;
+    static constexpr int pitch = KP;
+};
+template <>
+struct Lds<float, 1> {
+    typedef _Float16 type;
+    static constexpr int pitch = BK + 4;  // 40-byte rows: 8-byte aligned k groups
+};
+template <>
+struct Lds<float, 2> {
+    typedef short type;  // BF16 bit pattern
+    static constexpr int pitch = BK + 4;
+};
+// FP32 -> BF16, round to nearest even (a NaN stays a quiet NaN)
+__device__ __forceinline__ short f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (short)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+template <int LP, typename T>
+__device__ __forceinline__ typename Lds<T, LP>::type to_lds(T v)
+{
+    if constexpr (LP == 1) return (_Float16)v;
+    else if constexpr (LP == 2) return f32_to_bf16(v);
+    else return v;  // native precision: no conversion
+}
 
 template <typename T>
 struct GemmParams {
@@ -112,7 +151,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int total)
 // AMC: A's row index is contiguous (column-major A); else A's k index is.
 // BNC: B's row index (the n index of C) is contiguous; else its k index is.
 // CMC: C's row index is contiguous.
-template <typename T, bool AMC, bool BNC, bool CMC, int WMB, int WNB>
+template <typename T, bool AMC, bool BNC, bool CMC, int WMB, int WNB, int LP = 0>
 __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(GemmParams<T> p)
 {
     constexpr int BM = 32 * WMB, BN = 32 * WNB;
@@ -151,8 +190,10 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
     if (p.triB == TRI_LOWER || p.triB == TRI_SLOWER) ke = ke < j0 + BN ? ke : j0 + BN;
     if (p.triB == TRI_UPPER || p.triB == TRI_SUPPER) kb = kb > j0 ? kb : j0;
 
-    __shared__ __attribute__((aligned(16))) T As[2][BM][KP];
-    __shared__ __attribute__((aligned(16))) T Bs[2][BN][KP];
+    typedef typename Lds<T, LP>::type LT;
+    constexpr int KPL = Lds<T, LP>::pitch;
+    __shared__ __attribute__((aligned(16))) LT As[2][BM][KPL];
+    __shared__ __attribute__((aligned(16))) LT Bs[2][BN][KPL];
 
     const int t = threadIdx.x;
     const int lane = t & 63, w = t >> 6;
@@ -248,13 +289,13 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
     auto store = [&](int buf) {
 #pragma unroll
         for (int r = 0; r < EA; r++) {
-            if (AMC) As[buf][a_i][a_k + r * A_STEP] = ra[r];
-            else As[buf][a_i + r * A_STEP][a_k] = ra[r];
+            if (AMC) As[buf][a_i][a_k + r * A_STEP] = to_lds<LP>(ra[r]);
+            else As[buf][a_i + r * A_STEP][a_k] = to_lds<LP>(ra[r]);
         }
 #pragma unroll
         for (int r = 0; r < EB; r++) {
-            if (BNC) Bs[buf][b_j][b_k + r * B_STEP] = rb[r];
-            else Bs[buf][b_j + r * B_STEP][b_k] = rb[r];
+            if (BNC) Bs[buf][b_j][b_k + r * B_STEP] = to_lds<LP>(rb[r]);
+            else Bs[buf][b_j + r * B_STEP][b_k] = to_lds<LP>(rb[r]);
         }
     };
 
@@ -271,6 +312,27 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
     // every k of the group is summed exactly once.
     const int lrow = lane & 15, lk = 2 * (lane >> 4);
     auto compute = [&](int buf) {
+        if constexpr (LP != 0) {
+            typedef typename std::conditional<LP == 1, v4h, v4s>::type v4l;
+            const int lk4 = 4 * (lane >> 4);
+            v4l af[WMB], bf[WNB];
+#pragma unroll
+            for (int x = 0; x < WMB; x++)
+                af[x] = *reinterpret_cast<const v4l*>(&As[buf][wm * (BM / 2) + x * 16 + lrow][lk4]);
+#pragma unroll
+            for (int x = 0; x < WNB; x++)
+                bf[x] = *reinterpret_cast<const v4l*>(&Bs[buf][wn * (BN / 2) + x * 16 + lrow][lk4]);
+#pragma unroll
+            for (int a = 0; a < WMB; a++)
+#pragma unroll
+                for (int b = 0; b < WNB; b++) {
+                    if constexpr (LP == 1)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16f16(af[a], bf[b], acc[a][b], 0, 0, 0);
+                    else
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bf[b], acc[a][b], 0, 0, 0);
+                }
+            return;
+        } else {
 #pragma unroll
         for (int kg = 0; kg < BK; kg += 8) {
             v2_t af[WMB], bf[WNB];
@@ -288,6 +350,7 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
             for (int a = 0; a < WMB; a++)
 #pragma unroll
                 for (int b = 0; b < WNB; b++) acc[a][b] = Mfma<T>::op(af[a].y, bf[b].y, acc[a][b]);
+        }
         }
     };
 
@@ -376,13 +439,16 @@ template <typename T>
 static constexpr const char* tname() { return sizeof(T) == 8 ? "double" : "float"; }
 
 // Demangled kernel names as rocprofv3 prints them.
-template <typename T, bool AMC, bool BNC, bool CMC, int WMB, int WNB>
+template <typename T, bool AMC, bool BNC, bool CMC, int WMB, int WNB, int LP = 0>
 static const char* kname()
 {
     static char buf[112];
-    if (!buf[0])
-        snprintf(buf, sizeof buf, "rfp::gemm_kernel<%s, %s, %s, %s, %d, %d>(rfp::GemmParams<%s>)", tname<T>(),
-                 AMC ? "true" : "false", BNC ? "true" : "false", CMC ? "true" : "false", WMB, WNB, tname<T>());
+    if (!buf[0]) {
+        char lp[8] = "";
+        if (LP) snprintf(lp, sizeof lp, ", %d", LP);
+        snprintf(buf, sizeof buf, "rfp::gemm_kernel<%s, %s, %s, %s, %d, %d%s>(rfp::GemmParams<%s>)", tname<T>(),
+                 AMC ? "true" : "false", BNC ? "true" : "false", CMC ? "true" : "false", WMB, WNB, lp, tname<T>());
+    }
     return buf;
 }
 
@@ -436,8 +502,28 @@ static double gemm_bytes(const GemmParams<T>& p)
 }
 
 template <typename T, bool AMC, bool BNC, bool CMC>
-static void launch(const GemmParams<T>& p, dim3 grid, int tile, const Exec& ex)
+static void launch(const GemmParams<T>& p, dim3 grid, int tile, const Exec& ex, int lp)
 {
+    if constexpr (sizeof(T) == 4) {
+        // low-precision operand kernels: square tiles only (128 or 64)
+        if (lp == 1 || lp == 2) {
+            const bool big = tile == 0;
+            if (lp == 1 && big) {
+                ProfScope ps(ex, kname<T, AMC, BNC, CMC, 4, 4, 1>(), gemm_flops(p), gemm_bytes(p));
+                hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC, 4, 4, 1>), grid, dim3(NTH), 0, ex.stream, p);
+            } else if (lp == 1) {
+                ProfScope ps(ex, kname<T, AMC, BNC, CMC, 2, 2, 1>(), gemm_flops(p), gemm_bytes(p));
+                hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC, 2, 2, 1>), grid, dim3(NTH), 0, ex.stream, p);
+            } else if (big) {
+                ProfScope ps(ex, kname<T, AMC, BNC, CMC, 4, 4, 2>(), gemm_flops(p), gemm_bytes(p));
+                hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC, 4, 4, 2>), grid, dim3(NTH), 0, ex.stream, p);
+            } else {
+                ProfScope ps(ex, kname<T, AMC, BNC, CMC, 2, 2, 2>(), gemm_flops(p), gemm_bytes(p));
+                hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC, 2, 2, 2>), grid, dim3(NTH), 0, ex.stream, p);
+            }
+            return;
+        }
+    }
     switch (tile) {
         case 0: {
             ProfScope ps(ex, kname<T, AMC, BNC, CMC, 4, 4>(), gemm_flops(p), gemm_bytes(p));
@@ -465,13 +551,15 @@ static const int TILE_BN[4] = {128, 128, 64, 64};
 // Pick the largest tile that still gives the chip enough workgroups.  For an
 // in-place product a dimension of at most 128 is covered by a single tile, so
 // each workgroup owns whole rows (C aliasing A) or columns (C aliasing B).
-static int pick_tile(int64_t m, int64_t n, bool c_lower, bool inplace, int64_t* tm, int64_t* tn)
+static int pick_tile(int64_t m, int64_t n, bool c_lower, bool inplace, int64_t* tm, int64_t* tn,
+                     bool square_only = false)
 {
     const int64_t want = 512;  // two workgroups per CU on 256 CUs
     int best = -1;
     int64_t best_tiles = -1;
     for (int t = 0; t < 4; t++) {
         const int bm = TILE_BM[t], bn = TILE_BN[t];
+        if (square_only && bm != bn) continue;
         if (c_lower && m == n && bm != bn) continue;
         if (inplace && m <= 128 && bm < m) continue;
         if (inplace && n <= 128 && bn < n) continue;
@@ -536,7 +624,10 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
     p.c_lower = c_lower ? 1 : 0;
     p.info = ex.info;
     int64_t tm, tn;
-    const int tile = pick_tile(m, n, c_lower, inplace, &tm, &tn);
+    // low-precision operands for the bulk updates only: in-place products
+    // (the leaf-level panel solves) stay in FP32
+    const int lp = (sizeof(T) == 4 && !inplace) ? ex.lowp : 0;
+    const int tile = pick_tile(m, n, c_lower, inplace, &tm, &tn, lp != 0);
     p.tri_enum = (c_lower && m == n) ? 1 : 0;
     const int64_t ntiles = p.tri_enum ? tm * (tm + 1) / 2 : tm * tn;
     p.tiles_m = (int)tm;
@@ -564,14 +655,14 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
     dim3 grid((unsigned)ntiles, 1, (unsigned)nsplit);
     const int sel = (amc ? 4 : 0) | (bnc ? 2 : 0) | (cmc ? 1 : 0);
     switch (sel) {
-        case 0: launch<T, false, false, false>(p, grid, tile, ex); break;
-        case 1: launch<T, false, false, true>(p, grid, tile, ex); break;
-        case 2: launch<T, false, true, false>(p, grid, tile, ex); break;
-        case 3: launch<T, false, true, true>(p, grid, tile, ex); break;
-        case 4: launch<T, true, false, false>(p, grid, tile, ex); break;
-        case 5: launch<T, true, false, true>(p, grid, tile, ex); break;
-        case 6: launch<T, true, true, false>(p, grid, tile, ex); break;
-        default: launch<T, true, true, true>(p, grid, tile, ex); break;
+        case 0: launch<T, false, false, false>(p, grid, tile, ex, lp); break;
+        case 1: launch<T, false, false, true>(p, grid, tile, ex, lp); break;
+        case 2: launch<T, false, true, false>(p, grid, tile, ex, lp); break;
+        case 3: launch<T, false, true, true>(p, grid, tile, ex, lp); break;
+        case 4: launch<T, true, false, false>(p, grid, tile, ex, lp); break;
+        case 5: launch<T, true, false, true>(p, grid, tile, ex, lp); break;
+        case 6: launch<T, true, true, false>(p, grid, tile, ex, lp); break;
+        default: launch<T, true, true, true>(p, grid, tile, ex, lp); break;
     }
     if (nsplit > 1) {
         const int64_t total = m * n;

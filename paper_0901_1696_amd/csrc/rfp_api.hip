@@ -582,7 +582,7 @@ static T* plan_base(int buf)
 
 template <typename T>
 static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf, int* info, hipStream_t s,
-                      PlanRec* rec = nullptr)
+                      PlanRec* rec = nullptr, int lowp = 0)
 {
     if (!h && !rec) return RFP_ERR_HANDLE;
     if (bad_tr(transr)) return -1;
@@ -603,6 +603,7 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
         if (n == 0) return set_int(s, info, 0) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
         if (prepare(h, size_t(lv) * NB2 * NB2 * sizeof(T)) != hipSuccess) return RFP_ERR_RUNTIME;
         r = make_run<T>(h, s, info);
+        r.ex.lowp = r.ex2.lowp = lowp;
         winv = (T*)h->inv;
     }
     r.nb = NB2;
@@ -781,7 +782,7 @@ static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64
                         int* info, hipStream_t st)
 {
     if (!h) return RFP_ERR_HANDLE;
-    if (fprec != RFP_PREC_FP32) return -1;
+    if (fprec != RFP_PREC_FP32 && fprec != RFP_PREC_FP16 && fprec != RFP_PREC_BF16) return -1;
     if (bad_tr(transr)) return -2;
     if (bad_ul(uplo)) return -3;
     if (n < 0) return -4;
@@ -820,7 +821,7 @@ static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64
     ok(pf_norm(st, v, 1, w.normwork, w.anorm));
     ok(col_max(st, b, ldb, n, nrhs, w.bmax));
     if (!ok(hipGetLastError())) return RFP_ERR_RUNTIME;
-    int rc = pftrf_impl<float>(h, transr, uplo, n, w.a32, w.info, st);
+    int rc = pftrf_impl<float>(h, transr, uplo, n, w.a32, w.info, st, nullptr, fprec);
     if (rc != 0) return rc;
     int linfo = 0;
     if (!ok(fetch(st, w.info, &linfo))) return RFP_ERR_RUNTIME;
@@ -1106,6 +1107,15 @@ int rfp_dlansf(rfp_handle_t h, char norm, char transr, char uplo, int64_t n, con
     RfpBlocks b;
     rfp_blocks(transr, uplo, n, &b);
     return pf_norm(stream, rfp_view(b, arf), which, (double*)h->ir, out) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+int rfp_spftrf_mp(rfp_handle_t h, int fprec, char transr, char uplo, int64_t n, float* arf, int* info,
+                  hipStream_t stream)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (fprec != RFP_PREC_FP32 && fprec != RFP_PREC_FP16 && fprec != RFP_PREC_BF16) return -1;
+    const int rc = pftrf_impl<float>(h, transr, uplo, n, arf, info, stream, nullptr, fprec);
+    return rc < 0 && rc > -100 ? rc - 1 : rc;  // argument positions shift by the leading FPREC
 }
 
 int rfp_dpfsv_ir(rfp_handle_t h, int fprec, char transr, char uplo, int64_t n, int64_t nrhs, const double* arf,

@@ -82,6 +82,7 @@ struct Exec {
     void* splitk_ws;    // split-K partial sums
     size_t splitk_bytes;
     Profiler* prof;     // optional per-launch event timing
+    int lowp = 0;       // FP32 GEMMs: 0 FP32 operands, 1 FP16, 2 BF16 (not for in-place products)
 };
 
 // Brackets one kernel launch with HIP events on the launch stream when

@@ -118,3 +118,46 @@ def test_ir_argument_errors(h):
         assert e.value.code == code
     # n = 0 and nrhs = 0 return at once
     assert rfp.rfp_dpfsv_ir(h, rfp.PREC_FP32, "N", "L", 0, d, b[:0], x[:0]) == (0, 0)
+
+
+@pytest.mark.parametrize("fprec", [rfp.PREC_FP32, rfp.PREC_FP16, rfp.PREC_BF16])
+@pytest.mark.parametrize("transr,uplo", LAYOUTS)
+@pytest.mark.parametrize("n", [1, 65, 300, 700])
+def test_low_precision_factor_min_matrix_exact(h, fprec, transr, uplo, n):
+    """Min matrix: the factor is all ones, so every operand rounded to FP16 or
+    BF16 is exact and the low-precision factor is exact too."""
+    A = synth.min_matrix(n)
+    arf = torch.from_numpy(oracle.trttf(transr, uplo, A).astype(np.float32)).cuda()
+    info = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    rfp.rfp_spftrf_mp(h, fprec, transr, uplo, n, arf, info)
+    ones = np.tril(np.ones((n, n))) if uplo == "L" else np.triu(np.ones((n, n)))
+    assert int(host(info)[0]) == 0
+    assert np.array_equal(host(arf), oracle.trttf(transr, uplo, ones).astype(np.float32))
+
+
+@pytest.mark.parametrize("fprec,bound", [(rfp.PREC_FP32, 2e-6), (rfp.PREC_FP16, 2e-3), (rfp.PREC_BF16, 2e-2)])
+@pytest.mark.parametrize("transr,uplo", [("N", "L"), ("T", "U")])
+def test_low_precision_factor_residual(h, fprec, bound, transr, uplo):
+    """||L L^T - A|| / ||A|| of the low-precision factor is of the order of the
+    operand precision (parity unpinned beyond that: the factor is not unique
+    at this precision)."""
+    n = 700
+    A, _ = synth.spd(n, seed=12)
+    arf64 = oracle.trttf(transr, uplo, A)
+    arf = torch.from_numpy(arf64.astype(np.float32)).cuda()
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rfp.rfp_spftrf_mp(h, fprec, transr, uplo, n, arf, info)
+    assert int(host(info)[0]) == 0
+    res = oracle.factor_residual(transr, uplo, n, arf64, host(arf).astype(np.float64))
+    assert res <= bound
+
+
+@pytest.mark.parametrize("fprec", [rfp.PREC_FP16, rfp.PREC_BF16])
+@pytest.mark.parametrize("n,kappa", [(300, 1e2), (1001, 1e3)])
+def test_ir_half_precision_updates(h, fprec, n, kappa):
+    nrhs = 2
+    A, B, arf = _ir_case(n, kappa, nrhs, seed=n + 17)
+    x = dev_colmajor(np.zeros((n, nrhs)))
+    it, info = rfp.rfp_dpfsv_ir(h, fprec, "N", "L", n, dev(arf), dev_colmajor(B), x, tol=1e-14, max_iter=60)
+    assert info == 0 and it > 0, f"code {it}"
+    assert oracle.backward_error("N", "L", n, arf, B, host_colmajor(x)) <= 1e-14
