@@ -104,7 +104,7 @@ int rfp_spftri(rfp_handle_t h, char transr, char uplo, int64_t n, float* arf, in
  * mixed-precision iterative refinement of a Cholesky solve, as in LAPACK's
  * DSPOSV, over the RFP format).
  */
-enum { RFP_PREC_FP32 = 0, RFP_PREC_FP16 = 1, RFP_PREC_BF16 = 2 };
+enum { RFP_PREC_FP32 = 0, RFP_PREC_FP16 = 1, RFP_PREC_BF16 = 2, RFP_PREC_FP64 = 3 };
 
 /* PFTRF on an FP32 RFP array with the bulk trailing updates (the GEMM, SYRK
  * and TRSM-update products of every step, not the diagonal-block leaves and
@@ -160,6 +160,45 @@ int rfp_dlansf(rfp_handle_t h, char norm, char transr, char uplo, int64_t n, con
 int rfp_dpfsv_ir(rfp_handle_t h, int fprec, char transr, char uplo, int64_t n, int64_t nrhs, const double* arf,
                  const double* b, int64_t ldb, double* x, int64_t ldx, double tol, int max_iter, int* iter, int* info,
                  hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched small systems (not in the paper): many SPD systems of order
+ * n <= 256, each in its own RFP layout, solved in one persistent launch.
+ * Each workgroup takes systems from a work counter and runs the paper's
+ * factorization (Section 3), solution (Section 4) and, if asked, inversion
+ * (Section 5) for one system at a time, all inside the workgroup.
+ */
+typedef struct {
+    int64_t n;       /* order, 0 <= n <= 256 */
+    int64_t arf_off; /* element offset of the system's RFP array in arf_pool */
+    int64_t b_off;   /* element offset of its first right-hand side in b_pool */
+    int64_t ldb;     /* leading dimension of its right-hand sides (>= max(1, n)) */
+    int64_t nrhs;    /* number of right-hand sides (>= 0) */
+    char transr, uplo;
+    char pad[6];
+} rfp_sys_t;
+
+/* Solve every system of the batch.  sys (device, batch entries) describes
+ * the systems; arf_pool and b_pool (device) hold their RFP arrays and
+ * right-hand sides, which X overwrites.  mode:
+ *   RFP_PREC_FP64: PFTRF in place, then PFTRS (the factor stays in arf);
+ *   RFP_PREC_FP32: FP32 factor of diag(A)^{-1/2} A diag(A)^{-1/2} and FP64
+ *     refinement against the untouched FP64 matrix until the normwise
+ *     backward error is <= tol (at most max_iter sweeps; a sweep that fails to
+ *     halve it counts as stalled); on failure the FP64 path runs on arf.
+ * With do_pftri != 0, arf ends as the RFP array of A^{-1} (PFTRI after an
+ * FP64 factor, in both modes).  Device outputs per system: info[i] = 0 or the
+ * FP64 PFTRF INFO (first non-positive pivot, 1-based); iter[i] = 0 (FP64
+ * mode), the number of refinement sweeps, or -1 (max_iter), -2 (stalled),
+ * -3 (FP32 factor not positive definite) when the FP64 path was taken; a
+ * system with n > 256 or a bad layout character gets info[i] = -1 and is not
+ * touched.  No host synchronisation or allocation happens once the handle's
+ * workspace has been sized by an earlier call, so the call can be captured
+ * in a HIP graph.  Argument order: MODE=1, BATCH=2, SYS=3, ARF_POOL=4,
+ * B_POOL=5, DO_PFTRI=6, TOL=7, MAX_ITER=8, INFO=9, ITER=10. */
+int rfp_dpfsv_batched(rfp_handle_t h, int mode, int64_t batch, const rfp_sys_t* sys, double* arf_pool,
+                      double* b_pool, int do_pftri, double tol, int max_iter, int* info, int* iter,
+                      hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Kernel timing (introspection, used by the benchmark for its roofline).

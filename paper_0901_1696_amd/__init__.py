@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "librfp.so")
 RFP_ERR_HANDLE = -101
 RFP_ERR_RUNTIME = -102
 LAYOUTS = [(t, u) for t in "NT" for u in "LU"]
-PREC_FP32, PREC_FP16, PREC_BF16 = 0, 1, 2
+PREC_FP32, PREC_FP16, PREC_BF16, PREC_FP64 = 0, 1, 2, 3
 
 _lib = None
 
@@ -54,6 +54,7 @@ _SIGS = {
     "rfp_spftrf_mp": [_vp, _int, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_dpfcast_s": [_vp, _chr, _chr, _i64, _vp, _int, ctypes.c_double, _vp, _vp, _vp],
     "rfp_dlansf": [_vp, _chr, _chr, _chr, _i64, _vp, _vp, _vp],
+    "rfp_dpfsv_batched": [_vp, _int, _i64, _vp, _vp, _vp, _int, ctypes.c_double, _int, _vp, _vp, _vp],
     "rfp_dpfsv_ir": [_vp, _int, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp, _i64, ctypes.c_double, _int,
                      ctypes.POINTER(_int), ctypes.POINTER(_int), _vp],
     "rfp_plan": [_chr, _chr, _chr, _i64, _i64, _i64, _vp, _i64, ctypes.POINTER(_i64)],
@@ -270,3 +271,25 @@ def rfp_dpfsv_ir(h, fprec, transr, uplo, n, arf, b, x, tol=1e-14, max_iter=50, s
                                               px, ldx, float(tol), int(max_iter), ctypes.byref(it),
                                               ctypes.byref(info), _stream(stream)))
     return it.value, info.value
+
+
+class SysDesc(ctypes.Structure):
+    """Layout of ``rfp_sys_t`` (include/rfp.h): one system of a batch."""
+    _fields_ = [("n", _i64), ("arf_off", _i64), ("b_off", _i64), ("ldb", _i64), ("nrhs", _i64),
+                ("transr", ctypes.c_char), ("uplo", ctypes.c_char), ("pad", ctypes.c_char * 6)]
+
+
+def sys_table(systems):
+    """Bytes of an ``rfp_sys_t`` array from (n, arf_off, b_off, ldb, nrhs, transr, uplo) tuples."""
+    arr = (SysDesc * max(1, len(systems)))()
+    for k, (n, ao, bo, ldb, nr, t, u) in enumerate(systems):
+        arr[k] = SysDesc(n, ao, bo, ldb, nr, _c(t), _c(u), b"")
+    return bytes(arr)[:ctypes.sizeof(SysDesc) * len(systems)]
+
+
+def rfp_dpfsv_batched(h, mode, batch, sys, arf_pool, b_pool, info, iter, do_pftri=False, tol=1e-14, max_iter=20,
+                      stream=None):
+    """sys: device tensor holding the ``rfp_sys_t`` table (e.g. a uint8 tensor from :func:`sys_table`)."""
+    _check("rfp_dpfsv_batched", lib().rfp_dpfsv_batched(h.value, int(mode), int(batch), _ptr(sys), _ptr(arf_pool),
+                                                        _ptr(b_pool), 1 if do_pftri else 0, float(tol), int(max_iter),
+                                                        _ptr(info), _ptr(iter), _stream(stream)))

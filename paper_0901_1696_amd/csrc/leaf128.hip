@@ -1,317 +1,17 @@
-// Fused Cholesky of one diagonal block of order <= 128 (the leaf of the
-// factorization recursion, Section 3's block equations applied inside the
-// block) and the inverse of its factor, for the panel TRSM that follows.
-//
-// One 256-thread workgroup keeps the whole block in LDS (128 x 130 elements,
-// rows k-contiguous).  For each 32-column block column:
-//   1. one wavefront factors the 32 x 32 diagonal block (row per lane, the
-//      pivot column broadcast through LDS) and inverts it;
-//   2. all four wavefronts solve the panel below with MFMA, X = A_p W^T;
-//   3. all four wavefronts update the trailing lower triangle, A -= X X^T.
-// The factor is stored back (masked to the block's own lower triangle), then
-// W = L^{-1} is formed in place, block column by block column from the right:
-// W_RR is already inverted, so W_Rj = -(W_RR L_Rj) W_jj.
+// Leaf kernel of the blocked factorization: one workgroup factors a diagonal
+// block of order <= 128 and inverts its factor (potrf128_block).
 #include <cstdio>
 
-#include "rfp_common.h"
-
-#ifndef RFP_LEAF_STAMP
-#define RFP_LEAF_STAMP(k)
-#endif
+#include "leaf128.h"
 
 namespace rfp {
-
-namespace {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct M16;
-template <>
-struct M16<double> {
-    typedef v4d acc;
-    static __device__ __forceinline__ acc op(double a, double b, acc c)
-    {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-};
-template <>
-struct M16<float> {
-    typedef v4f acc;
-    static __device__ __forceinline__ acc op(float a, float b, acc c)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
-
-constexpr int N = 128, LP = N + 2, D = 32, DP = D + 2;
-
-__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
-
-// acc(16 x 16) += sum_k X(xr + i, xk + k) * Y(yr + j, yk + k), k < K (multiple of 4),
-// X and Y rows k-contiguous in LDS with pitch P.  Lane l supplies k = kk + l/16.
-template <typename T, int P>
-__device__ __forceinline__ void mma_rows(typename M16<T>::acc& acc, const T (*X)[P], int xr, int xk,
-                                         const T (*Y)[P], int yr, int yk, int K, int lane)
-{
-    const int r = lane & 15, g = lane >> 4;
-    for (int kk = 0; kk < K; kk += 4)
-        acc = M16<T>::op(X[xr + r][xk + kk + g], Y[yr + r][yk + kk + g], acc);
-}
-
-// Cholesky of the 32 x 32 diagonal block at (o, o) of the LDS matrix by one
-// wavefront, left-looking: lane i < 32 owns row i; column j is
-// l_ij = (a_ij - sum_{k<j} l_ik l_jk) / l_jj with the pivot taken from lane j.
-// Returns 0, or j + 1 for the first pivot that is not positive (uniform).
-template <typename T>
-__device__ __forceinline__ int chol32(T (*L)[LP], int o, int lane)
-{
-    const int i = lane;
-    for (int j = 0; j < D; j++) {
-        T v = T(0);
-        if (i >= j && i < D) {
-            // independent partial sums keep several LDS loads in flight
-            T p0 = 0, p1 = 0, p2 = 0, p3 = 0;
-            int k = 0;
-            for (; k + 4 <= j; k += 4) {
-                p0 += L[o + i][o + k] * L[o + j][o + k];
-                p1 += L[o + i][o + k + 1] * L[o + j][o + k + 1];
-                p2 += L[o + i][o + k + 2] * L[o + j][o + k + 2];
-                p3 += L[o + i][o + k + 3] * L[o + j][o + k + 3];
-            }
-            for (; k < j; k++) p0 += L[o + i][o + k] * L[o + j][o + k];
-            v = L[o + i][o + j] - ((p0 + p1) + (p2 + p3));
-        }
-        const T d = __shfl(v, j);
-        if (!(d > T(0))) return j + 1;
-        const T l = sqrt(d);
-        if (i > j && i < D) L[o + i][o + j] = v / l;
-        if (i == j) L[o + j][o + j] = l;
-        wave_sync();
-    }
-    return 0;
-}
-
-// Inverse of the lower-triangular 32 x 32 block at (o, o): lane c < 32 forms
-// column c by forward substitution, W(r, c) = (delta_rc - sum_{c<=q<r} L(r, q)
-// W(q, c)) / L(r, r), directly in Wd (row-major; zero above the diagonal).
-// Each lane reads only its own column of Wd.
-template <typename T>
-__device__ __forceinline__ void inv32(T (*L)[LP], int o, T (*Wd)[DP], T* rdg, int lane)
-{
-    if (lane < D) rdg[lane] = T(1) / L[o + lane][o + lane];
-    wave_sync();
-    const int c = lane;
-    if (c < D) {
-        for (int r = 0; r < D; r++) {
-            T p0 = 0, p1 = 0, p2 = 0, p3 = 0;
-            int q = c;
-            for (; q + 4 <= r; q += 4) {
-                p0 += L[o + r][o + q] * Wd[q][c];
-                p1 += L[o + r][o + q + 1] * Wd[q + 1][c];
-                p2 += L[o + r][o + q + 2] * Wd[q + 2][c];
-                p3 += L[o + r][o + q + 3] * Wd[q + 3][c];
-            }
-            for (; q < r; q++) p0 += L[o + r][o + q] * Wd[q][c];
-            const T s = ((r == c) ? T(1) : T(0)) - ((p0 + p1) + (p2 + p3));
-            Wd[r][c] = (r >= c) ? s * rdg[r] : T(0);
-        }
-    }
-    wave_sync();
-}
-
-}  // namespace
 
 template <typename T>
 __global__ __launch_bounds__(256) void potrf128_kernel(Mat<T> A, int nb, T* winv, int* info, int64_t info_base)
 {
     if (info && *info) return;
-    __shared__ __attribute__((aligned(16))) T L[N][LP];
-    __shared__ __attribute__((aligned(16))) T Wd[D][DP];  // Wd[r][c] = (L_jj^{-1})(r, c)
-    __shared__ T rdg[D];
-    __shared__ int fail;
-
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    if (t == 0) fail = 0;
-    const bool colmajor = A.rs == 1;
-#pragma unroll 16
-    for (int it = 0; it < N * N / 256; it++) {
-        const int idx = t + it * 256;
-        const int i = colmajor ? idx % N : idx / N;
-        const int j = colmajor ? idx / N : idx % N;
-        T v = (i == j) ? T(1) : T(0);
-        if (i < nb && j <= i) v = A.at(i, j);
-        L[i][j] = v;
-    }
-    __syncthreads();
-    RFP_LEAF_STAMP(0);
-
-    const int nblk = (nb + D - 1) / D;
-    typedef typename M16<T>::acc acc_t;
-
-    // factor the 32 x 32 diagonal block at offset o (wavefront 0) and leave
-    // its inverse in Wd; a failing pivot is recorded in `fail`
-    // (the inverse of each diagonal block is also parked in its final place in
-    // winv, where the inversion phase picks it up again)
-    auto diag = [&](int o, bool factor) {
-        if (factor) {
-            if (w == 0) {
-                const int f = chol32<T>(L, o, lane);
-                if (f) {
-                    if (lane == 0) fail = o + f;
-                    return;
-                }
-                RFP_LEAF_STAMP(16 + 3 * (o / D));
-                inv32<T>(L, o, Wd, rdg, lane);
-                RFP_LEAF_STAMP(17 + 3 * (o / D));
-                if (winv && lane < D) {
-                    for (int r = 0; r < D; r++) winv[(o + r) * N + o + lane] = Wd[r][lane];
-                }
-            }
-        } else {
-            for (int idx = t; idx < D * D; idx += 256) Wd[idx / D][idx % D] = winv[(o + idx / D) * N + o + idx % D];
-        }
-    };
-
-    // ---------------------------------------------------------------- factor
-    for (int kb = 0; kb < nblk; kb++) {
-        const int o = kb * D;
-        diag(o, true);
-        __syncthreads();
-        RFP_LEAF_STAMP(1 + 3 * kb);
-        if (fail) break;
-        const int r0 = o + D, nrb = (N - r0) / 16;  // 16-row blocks below
-        // panel: X(i, c) = sum_k L(i, o + k) W(c, k), i.e. X = A_p W^T; a wave
-        // owns whole row blocks, so reading and overwriting them is race-free
-        for (int rb = w; rb < nrb; rb += 4) {
-            acc_t x0 = acc_t{0, 0, 0, 0}, x1 = acc_t{0, 0, 0, 0};
-            {
-                const int r = lane & 15, g = lane >> 4;
-#pragma unroll
-                for (int kk = 0; kk < D; kk += 4) {
-                    const T av = L[r0 + rb * 16 + r][o + kk + g];
-                    x0 = M16<T>::op(av, Wd[r][kk + g], x0);
-                    x1 = M16<T>::op(av, Wd[16 + r][kk + g], x1);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const int i = r0 + rb * 16 + M16<T>::row(lane, q);
-                L[i][o + (lane & 15)] = x0[q];
-                L[i][o + 16 + (lane & 15)] = x1[q];
-            }
-        }
-        __syncthreads();
-        RFP_LEAF_STAMP(2 + 3 * kb);
-        // trailing update of the lower triangle of 16 x 16 blocks below/right
-        const int nt = nrb * (nrb + 1) / 2;
-        for (int b = w; b < nt; b += 4) {
-            int bi = 0;
-            while ((bi + 1) * (bi + 2) / 2 <= b) bi++;
-            const int bj = b - bi * (bi + 1) / 2;
-            acc_t s = acc_t{0, 0, 0, 0};
-            mma_rows<T, LP>(s, L, r0 + bi * 16, o, L, r0 + bj * 16, o, D, lane);
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const int i = bi * 16 + M16<T>::row(lane, q), j = bj * 16 + (lane & 15);
-                if (i >= j) L[r0 + i][r0 + j] -= s[q];
-            }
-        }
-        __syncthreads();
-        RFP_LEAF_STAMP(3 + 3 * kb);
-    }
-    if (fail) {
-        if (t == 0) *info = (int)(info_base + fail);
-        return;
-    }
-    // store the factor: its own lower triangle only
-#pragma unroll 16
-    for (int idx = t; idx < N * N; idx += 256) {
-        const int i = colmajor ? idx % N : idx / N;
-        const int j = colmajor ? idx / N : idx % N;
-        if (i < nb && j <= i) A.at(i, j) = L[i][j];
-    }
-    RFP_LEAF_STAMP(13);
-    if (!winv) return;
-
-    // --------------------------------------------------------------- inverse
-    for (int kb = nblk - 1; kb >= 0; kb--) {
-        const int o = kb * D;
-        __syncthreads();
-        diag(o, false);  // Wd = L_jj^{-1}, as parked in winv by the factor phase
-        __syncthreads();
-        const int r0 = o + D, nrb = (N - r0) / 16;
-        // T = W_RR L_Rj  (W_RR already in place, lower triangular).  A wave owns
-        // the row blocks w and w + 4 (at most six row blocks exist).
-        acc_t tacc[2][2];
-#pragma unroll
-        for (int q2 = 0; q2 < 2; q2++) {
-            const int rb = w + 4 * q2;
-            tacc[q2][0] = acc_t{0, 0, 0, 0};
-            tacc[q2][1] = acc_t{0, 0, 0, 0};
-            if (rb < nrb) {
-                const int r = lane & 15, g = lane >> 4;
-                const int kend = (rb + 1) * 16;  // W_RR(i, k) = 0 for k > i
-                for (int kk = 0; kk < kend; kk += 4) {
-                    const T av = L[r0 + rb * 16 + r][r0 + kk + g];
-                    tacc[q2][0] = M16<T>::op(av, L[r0 + kk + g][o + r], tacc[q2][0]);
-                    tacc[q2][1] = M16<T>::op(av, L[r0 + kk + g][o + 16 + r], tacc[q2][1]);
-                }
-            }
-        }
-        __syncthreads();  // every wave has read L_Rj
-#pragma unroll
-        for (int q2 = 0; q2 < 2; q2++) {
-            const int rb = w + 4 * q2;
-            if (rb < nrb) {
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int i = r0 + rb * 16 + M16<T>::row(lane, q);
-                    L[i][o + (lane & 15)] = tacc[q2][0][q];
-                    L[i][o + 16 + (lane & 15)] = tacc[q2][1][q];
-                }
-            }
-        }
-        // W_Rj = -T W_jj, in place on the wave's own rows
-#pragma unroll
-        for (int q2 = 0; q2 < 2; q2++) {
-            const int rb = w + 4 * q2;
-            if (rb < nrb) {
-                acc_t y0 = acc_t{0, 0, 0, 0}, y1 = acc_t{0, 0, 0, 0};
-                const int r = lane & 15, g = lane >> 4;
-                wave_sync();
-#pragma unroll
-                for (int kk = 0; kk < D; kk += 4) {
-                    const T av = L[r0 + rb * 16 + r][o + kk + g];
-                    y0 = M16<T>::op(av, Wd[kk + g][r], y0);
-                    y1 = M16<T>::op(av, Wd[kk + g][16 + r], y1);
-                }
-                wave_sync();
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int i = r0 + rb * 16 + M16<T>::row(lane, q);
-                    L[i][o + (lane & 15)] = -y0[q];
-                    L[i][o + 16 + (lane & 15)] = -y1[q];
-                }
-            }
-        }
-        // the diagonal block becomes its inverse
-        if (w == 0 && lane < D) {
-#pragma unroll
-            for (int r = 0; r < D; r++)
-                if (r >= lane) L[o + r][o + lane] = Wd[r][lane];
-        }
-    }
-    __syncthreads();
-    RFP_LEAF_STAMP(14);
-    // W row-major into winv (zero above the diagonal, identity on padding)
-    for (int idx = t; idx < N * N; idx += 256) {
-        const int i = idx / N, j = idx % N;
-        winv[idx] = (j <= i) ? L[i][j] : T(0);
-    }
+    __shared__ Leaf128Smem<T> sm;
+    (void)potrf128_block<T>(sm, A, nb, winv, info, info_base);
 }
 
 template <typename T>

@@ -117,61 +117,14 @@ struct rfp_context {
     int epoch;            // last epoch handed to a fused solve
     void* ir;             // mixed-precision solve workspace
     size_t ir_bytes;
+    void* bat;            // batched-solver scratch (work counter + per-workgroup scratch)
+    size_t bat_bytes;
+    int cus;              // compute units of the device
 };
 
 namespace rfp {
 
 static int upc(char c) { return (c >= 'a' && c <= 'z') ? c - 'a' + 'A' : c; }
-
-// Layout descriptor (Section 2, Figures 4-6).  With n1 = ceil(n/2) columns
-// for TRANSR='N' the rectangle AR has LDAR = n (odd n) or n + 1 (even n)
-// rows.  For UPLO='L' the first diagonal block has order ceil(n/2): its lower
-// triangle sits in the first columns of AR (one row down when n is even, to
-// make room for the diagonal of A22), A21 sits under it, and A22's lower
-// triangle is stored transposed in the upper part of the top square, shifted
-// one column right when n is odd.  For UPLO='U' the first diagonal block has
-// order floor(n/2): A12 occupies the top rows of AR, A22's upper triangle
-// follows in the same columns, and A11's upper triangle is stored transposed
-// below it.  TRANSR='T' stores AR^T with leading dimension n1, which swaps the
-// row and column strides of every block.
-bool rfp_blocks(char transr, char uplo, int64_t n, RfpBlocks* o)
-{
-    const int t = upc(transr), u = upc(uplo);
-    if ((t != 'N' && t != 'T') || (u != 'L' && u != 'U') || n < 0) return false;
-    const bool odd = (n & 1) != 0;
-    const int64_t ldar = odd ? n : n + 1;
-    const int64_t cols = (n + 1) / 2;
-    const int64_t sr = (t == 'N') ? 1 : cols;   // stride of one AR row step
-    const int64_t sc = (t == 'N') ? ldar : 1;   // stride of one AR column step
-    const int64_t extra = odd ? 0 : 1;           // the extra top row of even n
-    o->n = n;
-    // each block: AR position (row, col) of its (0,0) and whether its row
-    // index runs down AR rows (true) or along AR columns (false)
-    int64_t r11, c11, r21, c21, r22, c22;
-    bool d11, d21, d22;
-    if (u == 'L') {
-        o->m1 = (n + 1) / 2;
-        o->m2 = n - o->m1;
-        r11 = extra; c11 = 0; d11 = true;
-        r21 = o->m1 + extra; c21 = 0; d21 = true;
-        r22 = 0; c22 = 1 - extra; d22 = false;
-    } else {
-        o->m1 = n / 2;
-        o->m2 = n - o->m1;
-        r11 = o->m2 + extra; c11 = 0; d11 = true;
-        r21 = 0; c21 = 0; d21 = false;
-        r22 = o->m1; c22 = 0; d22 = false;
-    }
-    auto put = [&](int64_t r, int64_t c, bool down, int64_t* off, int64_t* rs, int64_t* cs) {
-        *off = r * sr + c * sc;
-        *rs = down ? sr : sc;
-        *cs = down ? sc : sr;
-    };
-    put(r11, c11, d11, &o->off11, &o->rs11, &o->cs11);
-    put(r21, c21, d21, &o->off21, &o->rs21, &o->cs21);
-    put(r22, c22, d22, &o->off22, &o->rs22, &o->cs22);
-    return true;
-}
 
 static inline int64_t nleaves(int64_t n, int nb) { return (n + nb - 1) / nb; }
 
@@ -927,6 +880,8 @@ int rfp_create(rfp_handle_t* h, int device)
     rfp_context* c = (rfp_context*)std::calloc(1, sizeof(rfp_context));
     if (!c) return RFP_ERR_RUNTIME;
     c->device = device;
+    if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->cus <= 0)
+        c->cus = 256;
     *h = c;
     return 0;
 }
@@ -941,6 +896,7 @@ int rfp_destroy(rfp_handle_t h)
         if (h->inv) (void)hipFree(h->inv);
         if (h->flags) (void)hipFree(h->flags);
         if (h->ir) (void)hipFree(h->ir);
+        if (h->bat) (void)hipFree(h->bat);
         for (int i = 0; i < h->nev; i++) (void)hipEventDestroy(h->ev[i]);
         if (h->aux) (void)hipStreamDestroy(h->aux);
         delete h->prof;
@@ -1123,6 +1079,34 @@ int rfp_dpfsv_ir(rfp_handle_t h, int fprec, char transr, char uplo, int64_t n, i
                  hipStream_t stream)
 {
     return pfsv_ir_impl(h, fprec, transr, uplo, n, nrhs, arf, b, ldb, x, ldx, tol, max_iter, iter, info, stream);
+}
+
+int rfp_dpfsv_batched(rfp_handle_t h, int mode, int64_t batch, const rfp_sys_t* sys, double* arf_pool,
+                      double* b_pool, int do_pftri, double tol, int max_iter, int* info, int* iter,
+                      hipStream_t stream)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (mode != RFP_PREC_FP64 && mode != RFP_PREC_FP32) return -1;
+    if (batch < 0) return -2;
+    if (batch == 0) return 0;
+    if (!sys) return -3;
+    if (!arf_pool) return -4;
+    if (!b_pool) return -5;
+    if (mode == RFP_PREC_FP32 && !(tol > 0.0)) return -7;
+    if (mode == RFP_PREC_FP32 && max_iter < 1) return -8;
+    if (!info) return -9;
+    if (!iter) return -10;
+    DeviceGuard g(h->device);
+    const int wgs = (int)std::min<int64_t>(batch, h->cus);  // one resident workgroup per CU (LDS-bound)
+    const size_t need = 256 + batched_scratch_bytes(wgs);
+    if (ensure(&h->bat, &h->bat_bytes, need) != hipSuccess) return RFP_ERR_RUNTIME;
+    Exec ex{};
+    ex.stream = stream;
+    ex.prof = h->prof;
+    const hipError_t e = batched_solve(ex, sys, batch, arf_pool, b_pool, mode == RFP_PREC_FP32 ? 1 : 0,
+                                       do_pftri ? 1 : 0, tol, max_iter, info, iter, (int*)h->bat,
+                                       (char*)h->bat + 256, wgs);
+    return e == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
 }  // extern "C"

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rfp.h"
+
 namespace rfp {
 
 // A strided 2-D view: element (i, j) lives at p[i * rs + j * cs].  Every view
@@ -36,9 +38,58 @@ struct RfpBlocks {
     int64_t off22, rs22, cs22;
 };
 
-// Layout descriptor of the eight RFP layouts (Section 2 and Figures 4-6).
 // Returns false for an illegal TRANSR / UPLO character or n < 0.
-bool rfp_blocks(char transr, char uplo, int64_t n, RfpBlocks* out);
+// Layout descriptor (Section 2, Figures 4-6).  With n1 = ceil(n/2) columns
+// for TRANSR='N' the rectangle AR has LDAR = n (odd n) or n + 1 (even n)
+// rows.  For UPLO='L' the first diagonal block has order ceil(n/2): its lower
+// triangle sits in the first columns of AR (one row down when n is even, to
+// make room for the diagonal of A22), A21 sits under it, and A22's lower
+// triangle is stored transposed in the upper part of the top square, shifted
+// one column right when n is odd.  For UPLO='U' the first diagonal block has
+// order floor(n/2): A12 occupies the top rows of AR, A22's upper triangle
+// follows in the same columns, and A11's upper triangle is stored transposed
+// below it.  TRANSR='T' stores AR^T with leading dimension n1, which swaps the
+// row and column strides of every block.
+__host__ __device__ inline bool rfp_blocks(char transr, char uplo, int64_t n, RfpBlocks* o)
+{
+    const int t = (transr >= 'a' && transr <= 'z') ? transr - 'a' + 'A' : transr;
+    const int u = (uplo >= 'a' && uplo <= 'z') ? uplo - 'a' + 'A' : uplo;
+    if ((t != 'N' && t != 'T') || (u != 'L' && u != 'U') || n < 0) return false;
+    const bool odd = (n & 1) != 0;
+    const int64_t ldar = odd ? n : n + 1;
+    const int64_t cols = (n + 1) / 2;
+    const int64_t sr = (t == 'N') ? 1 : cols;   // stride of one AR row step
+    const int64_t sc = (t == 'N') ? ldar : 1;   // stride of one AR column step
+    const int64_t extra = odd ? 0 : 1;           // the extra top row of even n
+    o->n = n;
+    // each block: AR position (row, col) of its (0,0) and whether its row
+    // index runs down AR rows (true) or along AR columns (false)
+    int64_t r11, c11, r21, c21, r22, c22;
+    bool d11, d21, d22;
+    if (u == 'L') {
+        o->m1 = (n + 1) / 2;
+        o->m2 = n - o->m1;
+        r11 = extra; c11 = 0; d11 = true;
+        r21 = o->m1 + extra; c21 = 0; d21 = true;
+        r22 = 0; c22 = 1 - extra; d22 = false;
+    } else {
+        o->m1 = n / 2;
+        o->m2 = n - o->m1;
+        r11 = o->m2 + extra; c11 = 0; d11 = true;
+        r21 = 0; c21 = 0; d21 = false;
+        r22 = o->m1; c22 = 0; d22 = false;
+    }
+    auto put = [&](int64_t r, int64_t c, bool down, int64_t* off, int64_t* rs, int64_t* cs) {
+        *off = r * sr + c * sc;
+        *rs = down ? sr : sc;
+        *cs = down ? sc : sr;
+    };
+    put(r11, c11, d11, &o->off11, &o->rs11, &o->cs11);
+    put(r21, c21, d21, &o->off21, &o->rs21, &o->cs21);
+    put(r22, c22, d22, &o->off22, &o->rs22, &o->cs22);
+    return true;
+}
+
 
 template <typename T>
 struct RfpView {
@@ -47,7 +98,7 @@ struct RfpView {
 };
 
 template <typename T>
-inline RfpView<T> rfp_view(const RfpBlocks& b, T* arf)
+__host__ __device__ inline RfpView<T> rfp_view(const RfpBlocks& b, T* arf)
 {
     RfpView<T> v;
     v.n = b.n;
@@ -172,6 +223,13 @@ hipError_t pcg_dir(hipStream_t st, double* p, const double* z, const double* rz_
 hipError_t col_max(hipStream_t st, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out);
 hipError_t backward_error(hipStream_t st, const double* rmax, const double* xmax, const double* bmax,
                           const double* anorm, int64_t nrhs, double* eta);
+
+// Batched small systems (n <= 256): one persistent launch; scratch holds
+// batched_scratch_bytes(wgs) bytes, counter one int.
+size_t batched_scratch_bytes(int wgs);
+hipError_t batched_solve(const Exec& ex, const rfp_sys_t* sys, int64_t batch, double* arf, double* b, int mode,
+                         int pftri, double tol, int max_iter, int* info, int* iter, int* counter, char* scratch,
+                         int wgs);
 
 // 2-D strided copy dst = src (m x n), optionally only the lower triangle.
 template <typename Td, typename Ts>
