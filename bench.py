@@ -13,7 +13,18 @@ Also reported on the same JSON line:
                 launches inside the timed region, against the FP64 MFMA peak;
   cpu_baseline  the CPU oracle timed on a bounded sample on the host cores;
   pftri         PFTRI GFLOP/s (nominal 2 n^3 / 3) on the same matrices;
-  accuracy      worst normwise backward error of the solves, all layouts.
+  accuracy      worst normwise backward error of the solves, all layouts;
+  mixed         n = 40000 (TRANSR=N, UPLO=L), nrhs = 16, A = M M^T / k + alpha I
+                with M n x k (k = n/2) and alpha for cond ~1e3 and ~1e6: the
+                FP64 PFTRF+PFTRS time against the low-precision factor with
+                FP64 refinement (FP16, BF16 and FP32 factors tried; the fastest
+                that reaches the FP64 path's backward error bound of 1e-14),
+                each backward error measured with the dense FP64 A;
+  batched       20000 systems, n uniform in [16, 256], random layout, nrhs
+                uniform in [1, 8], A_i = M_i M_i^T / n_i + I: one persistent
+                launch in FP64 and with FP32 factors + FP64 refinement, with
+                and without PFTRI, against the single-system routines launched
+                one system at a time (timed on the first 300 systems).
 """
 import argparse
 import hashlib
@@ -91,6 +102,158 @@ def cpu_baseline(n=12000, nrhs=128):
                       f"matrix of the same recipe, nrhs={nrhs}; {dt:.1f} s"}
 
 
+def backward_error_dense(A, B, X):
+    """max over columns ||B - A X||_inf / (||A||_inf ||X||_inf + ||B||_inf), FP64 on the GPU."""
+    R = B - A @ X
+    anorm = A.abs().sum(dim=1).max()
+    return (R.abs().amax(dim=0) / (anorm * X.abs().amax(dim=0) + B.abs().amax(dim=0))).max().item()
+
+
+def bench_mixed(h, n, nrhs=16, kappas=(1e3, 1e6), reps=2):
+    """FP64 PFTRF+PFTRS vs low-precision factor + FP64 refinement at equal backward error."""
+    import torch
+    import paper_0901_1696_amd as rfp
+    import synth
+
+    k = n // 2
+    dev = torch.device("cuda:0")
+    log(f"[bench] mixed: generating n={n}, k={k}")
+    G, B = synth.spd_device(n, k=k, alpha=0.0, nrhs=nrhs, seed=n + 3, device=dev)  # M M^T / k
+    arf = torch.empty(rfp.nt(n), dtype=torch.float64, device=dev)
+    work = torch.empty_like(arf)
+    x = torch.empty((nrhs, n), dtype=torch.float64, device=dev).t()
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = {"n": n, "nrhs": nrhs, "layout": "NL", "tol": 1e-14, "cases": []}
+    diag = torch.arange(n, device=dev)
+    alpha_prev = 0.0
+    for kappa in kappas:
+        alpha = synth.cond_alpha(n, k, kappa)
+        G[diag, diag] += alpha - alpha_prev
+        alpha_prev = alpha
+        rfp.rfp_dtrttf(h, "N", "L", n, G, arf)
+        torch.cuda.synchronize()
+
+        def fp64():
+            work.copy_(arf)
+            x.copy_(B)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rfp.rfp_dpftrf(h, "N", "L", n, work, info)
+            rfp.rfp_dpftrs(h, "N", "L", n, work, x)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+
+        fp64()
+        t64 = min(fp64() for _ in range(reps))
+        eta64 = backward_error_dense(G, B, x)
+        case = {"kappa": kappa, "fp64_ms": round(t64 * 1e3, 2), "fp64_backward_error": eta64,
+                "fp64_gflops": round((flops_trf(n) + flops_trs(n, nrhs)) / t64 / 1e9, 1)}
+        best = None
+        for prec, name in [(rfp.PREC_FP16, "fp16"), (rfp.PREC_BF16, "bf16"), (rfp.PREC_FP32, "fp32")]:
+            def mixed():
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                it, inf = rfp.rfp_dpfsv_ir(h, prec, "N", "L", n, arf, B, x, tol=1e-14, max_iter=40)
+                torch.cuda.synchronize()
+                return time.perf_counter() - t0, it, inf
+            mixed()
+            runs = [mixed() for _ in range(reps)]
+            tm, it, inf = min(runs)
+            eta = backward_error_dense(G, B, x)
+            rec = {"factor": name, "ms": round(tm * 1e3, 2), "sweeps_or_fallback": it, "backward_error": eta}
+            case.setdefault("tried", []).append(rec)
+            log(f"[bench] mixed kappa={kappa:g} {name}: {tm*1e3:.1f} ms, code {it}, eta {eta:.2e}")
+            if it > 0 and eta <= 1e-14 and (best is None or tm < best[0]):
+                best = (tm, name, it, eta)
+        if best is not None:
+            case.update({"mixed_ms": round(best[0] * 1e3, 2), "mixed_factor": best[1], "sweeps": best[2],
+                         "mixed_backward_error": best[3], "speedup_vs_fp64": round(t64 / best[0], 3),
+                         "mixed_gflops_nominal": round((flops_trf(n) + flops_trs(n, nrhs)) / best[0] / 1e9, 1)})
+        out["cases"].append(case)
+        log(f"[bench] mixed kappa={kappa:g}: fp64 {t64*1e3:.1f} ms, best {best}")
+    del G, B, arf, work, x
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_batched(h, count=20000, seed=4, one_at_a_time=300, reps=3):
+    """Persistent batched launch vs the single-system routines one system at a time."""
+    import numpy as np
+    import torch
+    import paper_0901_1696_amd as rfp
+    import synth
+
+    dev = torch.device("cuda:0")
+    ns, lays, nrs = synth.batch_sizes(count, 16, 256, 1, 8, seed=seed)
+    systems, ao, bo = [], 0, 0
+    for n, li, nr in zip(ns, lays, nrs):
+        n, nr = int(n), int(nr)
+        t, u = rfp.LAYOUTS[int(li)]
+        systems.append((n, ao, bo, n, nr, t, u))
+        ao += rfp.nt(n)
+        bo += n * nr
+    log(f"[bench] batched: generating {count} systems ({ao * 8 / 1e9:.2f} GB RFP)")
+    arf = torch.empty(ao, dtype=torch.float64, device=dev)
+    b = torch.empty(bo, dtype=torch.float64, device=dev)
+    g = synth.rng(seed + 1)
+    for (n, a0, b0, ldb, nr, t, u) in systems:
+        M = torch.from_numpy(g.standard_normal((n, n))).to(dev)
+        A = (M @ M.t()) / n
+        A.diagonal().add_(1.0)
+        rfp.rfp_dtrttf(h, t, u, n, A.t(), arf[a0:a0 + rfp.nt(n)])
+        b[b0:b0 + n * nr] = torch.from_numpy(g.standard_normal(n * nr)).to(dev)
+    table = torch.frombuffer(bytearray(rfp.sys_table(systems)), dtype=torch.uint8).to(dev)
+    info = torch.zeros(count, dtype=torch.int32, device=dev)
+    it = torch.zeros_like(info)
+    fl_f = sum(flops_trf(s[0]) for s in systems)
+    fl_s = sum(flops_trs(s[0], s[4]) for s in systems)
+    fl_i = sum(flops_tri(s[0]) for s in systems)
+    a1, b1 = arf.clone(), b.clone()
+    out = {"systems": count, "n_range": [16, 256], "nrhs_range": [1, 8], "rfp_gb": round(ao * 8 / 1e9, 3),
+           "nominal_gflop": {"pftrf": round(fl_f / 1e9, 2), "pftrs": round(fl_s / 1e9, 2),
+                             "pftri": round(fl_i / 1e9, 2)}, "runs": []}
+    for mode, name in [(rfp.PREC_FP64, "fp64"), (rfp.PREC_FP32, "fp32_factor+fp64_ir")]:
+        for pftri in (False, True):
+            def run():
+                a1.copy_(arf)
+                b1.copy_(b)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rfp.rfp_dpfsv_batched(h, mode, count, table, a1, b1, info, it, do_pftri=pftri)
+                torch.cuda.synchronize()
+                return time.perf_counter() - t0
+            run()
+            tm = min(run() for _ in range(reps))
+            fl = fl_f + fl_s + (fl_i if pftri else 0.0)
+            bad = int((info != 0).sum().item())
+            rec = {"mode": name, "pftri": pftri, "ms": round(tm * 1e3, 2), "gflops": round(fl / tm / 1e9, 1),
+                   "info_nonzero": bad, "max_sweeps": int(it.max().item()), "min_code": int(it.min().item())}
+            out["runs"].append(rec)
+            log(f"[bench] batched {rec}")
+    # the same work through the single-system routines, one system at a time
+    a1.copy_(arf)
+    b1.copy_(b)
+    inf1 = torch.zeros(1, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (n, a0, b0, ldb, nr, t, u) in systems[:one_at_a_time]:
+        av = a1[a0:a0 + rfp.nt(n)]
+        bv = b1[b0:b0 + n * nr].view(nr, n).t()
+        rfp.rfp_dpftrf(h, t, u, n, av, inf1)
+        rfp.rfp_dpftrs(h, t, u, n, av, bv)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter() - t0
+    proj = t1 * count / one_at_a_time
+    fp64 = out["runs"][0]["ms"]
+    out["one_at_a_time_fp64"] = {"systems_timed": one_at_a_time, "ms": round(t1 * 1e3, 2),
+                                 "projected_ms_all": round(proj * 1e3, 1),
+                                 "batched_speedup": round(proj * 1e3 / fp64, 1)}
+    log(f"[bench] batched one-at-a-time {out['one_at_a_time_fp64']}")
+    del arf, b, a1, b1
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +265,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pftri", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--mixed-n", type=int, default=40000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -202,16 +368,13 @@ def main():
     # ---- accuracy of every (n, layout) solve (independent check with torch)
     accuracy = None
     if not args.no_check:
-        worst = 0.0
+        worst, per = 0.0, {}
         for n, t, u in combos:
             run_one(n, t, u)
-            X = bwork[:n]
-            A, B = dense[n], rhs[n]
-            R = B - A @ X
-            anorm = A.abs().sum(dim=1).max()
-            eta = (R.abs().amax(dim=0) / (anorm * X.abs().amax(dim=0) + B.abs().amax(dim=0))).max().item()
+            eta = backward_error_dense(dense[n], rhs[n], bwork[:n])
+            per[f"{t}{u}{n}"] = eta
             worst = max(worst, eta)
-        accuracy = {"max_backward_error": worst, "layouts_checked": len(combos)}
+        accuracy = {"max_backward_error": worst, "layouts_checked": len(combos), "per_layout": per}
         log(f"[bench] worst backward error {worst:.3e}")
 
     # ---- PFTRI (event timed, after its own PFTRF)
@@ -236,6 +399,11 @@ def main():
                  "ms_per_call": round(tot_ms / len(combos), 3)}
         log(f"[bench] PFTRI {pftri}")
 
+    del pristine, rhs, dense, work, bwork
+    torch.cuda.empty_cache()
+    mixed = None if args.no_mixed else bench_mixed(h, args.mixed_n)
+    batched = None if args.no_batched else bench_batched(h)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample")
@@ -250,6 +418,7 @@ def main():
                    + ",".join(t + u for t, u in layouts) + f", nrhs={nrhs}, A=M M^T/n+I (seeded N(0,1))",
                    "n": sizes, "layouts": [t + u for t, u in layouts], "nrhs": nrhs},
         "roofline": roofline, "cpu_baseline": cpu, "pftri": pftri, "accuracy": accuracy,
+        "mixed": mixed, "batched": batched,
         "kernels": kernel_table,
         "paper_context": "PFTRF 90.7-93.0 GFLOP/s at n=20000 on a 16-core Intel Tigerton with MKL "
                          "(paper's zootfac_vendor table); another machine, not the target",

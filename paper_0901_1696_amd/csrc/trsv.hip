@@ -19,7 +19,9 @@
 // flag, so that no other workgroup is held).
 //
 // Flags hold an epoch number that the host advances on every launch, so the
-// flag array is never cleared between calls.
+// flag array is never cleared between calls.  Solved rows travel between
+// workgroups (and XCDs) through device-scope atomic stores and loads ordered
+// by the flags' release / acquire, never through plain cached accesses.
 #include <cstdio>
 #include <cstdlib>
 
@@ -222,11 +224,18 @@ __global__ __launch_bounds__(256) void block_solve_kernel(SolveArgs<T> a)
                 break;
             }
         }
+        // Rows solved by other workgroups are read with device-scope loads:
+        // when block rows share cache lines (an unaligned m1 or ldb), this
+        // workgroup's own first read of B_k may have cached a neighbour's
+        // unsolved rows, and a plain load could be served that stale copy.
         T yreg[YPT];
 #pragma unroll
         for (int e = 0; e < YPT; e++) {
             const int idx = t + 256 * e, kk = idx % BS, c = idx / BS;
-            yreg[e] = (kk < cntj && c0 + c < a.nrhs) ? a.b[(rj + kk) + (c0 + c) * a.ldb] : T(0);
+            yreg[e] = (kk < cntj && c0 + c < a.nrhs)
+                          ? __hip_atomic_load(&a.b[(rj + kk) + (c0 + c) * a.ldb], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)
+                          : T(0);
         }
         if (d + 1 < q) fetch_l(d + 1);  // overlaps this step's products
 #pragma unroll
@@ -271,17 +280,17 @@ __global__ __launch_bounds__(256) void block_solve_kernel(SolveArgs<T> a)
         for (int e = 0; e < 4; e++) {
             const int i = 16 * w + MT<T>::row(lane, e);
             const int64_t c = c0 + cb * 16 + r;
-            if (i < cnt && c < a.nrhs) a.b[(r0 + i) + c * a.ldb] = ok ? out[cb][e] : nan;
+            if (i < cnt && c < a.nrhs)
+                __hip_atomic_store(&a.b[(r0 + i) + c * a.ldb], ok ? out[cb][e] : nan, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
-    // publish: every thread's stores have reached L2, then one release at
-    // device scope (write-back of L2) before the flag
+    // publish: every wavefront waits for its device-scope stores to complete,
+    // then one thread raises the flag with a release store
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (t == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(a.flags + (int64_t)k * a.nslices + slice, a.epoch, __ATOMIC_RELAXED,
+    if (t == 0)
+        __hip_atomic_store(a.flags + (int64_t)k * a.nslices + slice, a.epoch, __ATOMIC_RELEASE,
                            __HIP_MEMORY_SCOPE_AGENT);
-    }
 }
 
 __global__ void fill_int_kernel(int* p, int64_t n, int v)

@@ -250,3 +250,28 @@ def test_cfg1_n1001_full_path(h):
     rfp.rfp_dpftri(h, "N", "L", n, ad, info)
     assert read_info(info) == 0
     assert oracle.rel_fro(host(ad), inv_or) <= tol(n)
+
+
+@pytest.mark.parametrize("n", [8001, 8000])
+def test_pftrs_large_backward_error_all_layouts(h, n):
+    """Full-size behaviour of the fused solve, checked by a property that holds
+    at any size: the normwise backward error of the PFTRF + PFTRS solution,
+    from the dense FP64 matrix on the GPU.  Odd n puts block rows across
+    cache-line boundaries of B, where solved rows written by one workgroup
+    share lines with rows another workgroup read earlier; repeated calls."""
+    A, B = synth.spd_device(n, nrhs=130, seed=n, device="cuda")
+    anorm = A.abs().sum(dim=1).max()
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for t, u in LAYOUTS:
+        arf = torch.empty(rfp.nt(n), dtype=torch.float64, device="cuda")
+        rfp.rfp_dtrttf(h, t, u, n, A, arf)
+        rfp.rfp_dpftrf(h, t, u, n, arf, info)
+        assert read_info(info) == 0
+        for nrhs in (1, 16, 33, 130):
+            for _ in range(2):
+                X = B[:, :nrhs].clone()  # column-major copy (B itself stays the right-hand side)
+                assert X.stride(0) == 1 and X.data_ptr() != B.data_ptr()
+                rfp.rfp_dpftrs(h, t, u, n, arf, X)
+                R = B[:, :nrhs] - A @ X
+                eta = (R.abs().amax(0) / (anorm * X.abs().amax(0) + B[:, :nrhs].abs().amax(0))).max().item()
+                assert eta <= 1e-14, (t, u, nrhs, eta)
