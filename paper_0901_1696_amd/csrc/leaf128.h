@@ -46,7 +46,11 @@ struct M16<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-constexpr int N = 128, LP = N + 2, D = 32, DP = D + 2;
+// D: width of the block columns whose diagonal blocks are factored and
+// inverted by one wavefront (16 or 32; the sequential work per leaf grows
+// with D, the MFMA panel and trailing work does not).
+constexpr int N = 128, LP = N + 2, D = 16, DP = D + 2;
+constexpr bool TWO_HALVES = D > 16;
 
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
@@ -61,67 +65,75 @@ __device__ __forceinline__ void mma_rows(typename M16<T>::acc& acc, const T (*X)
         acc = M16<T>::op(X[xr + r][xk + kk + g], Y[yr + r][yk + kk + g], acc);
 }
 
+// Broadcast of lane l's value to the whole wavefront (l uniform).
+__device__ __forceinline__ double bcast(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float bcast(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 // Cholesky of the 32 x 32 diagonal block at (o, o) of the LDS matrix by one
-// wavefront, left-looking: lane i < 32 owns row i; column j is
-// l_ij = (a_ij - sum_{k<j} l_ik l_jk) / l_jj with the pivot taken from lane j.
-// Returns 0, or j + 1 for the first pivot that is not positive (uniform).
+// wavefront, right-looking in registers: lane i < 32 holds row i; at column
+// j the pivot and the column entries l_cj are broadcast from their lanes
+// (readlane), l_jj = sqrt(a_jj), l_ij = a_ij / l_jj, and every row updates
+// a_ic -= l_ij l_cj for c > j.  Entries above the diagonal are never read.
+// Returns 0, or j + 1 for the first pivot that is not positive (uniform);
+// on success the factor is stored back to LDS.
 template <typename T>
 __device__ __forceinline__ int chol32(T (*L)[LP], int o, int lane)
 {
     const int i = lane;
+    T a[D];
+#pragma unroll
+    for (int j = 0; j < D; j++) a[j] = (i < D && j <= i) ? L[o + i][o + j] : T(0);
+#pragma unroll
     for (int j = 0; j < D; j++) {
-        T v = T(0);
-        if (i >= j && i < D) {
-            // independent partial sums keep several LDS loads in flight
-            T p0 = 0, p1 = 0, p2 = 0, p3 = 0;
-            int k = 0;
-            for (; k + 4 <= j; k += 4) {
-                p0 += L[o + i][o + k] * L[o + j][o + k];
-                p1 += L[o + i][o + k + 1] * L[o + j][o + k + 1];
-                p2 += L[o + i][o + k + 2] * L[o + j][o + k + 2];
-                p3 += L[o + i][o + k + 3] * L[o + j][o + k + 3];
-            }
-            for (; k < j; k++) p0 += L[o + i][o + k] * L[o + j][o + k];
-            v = L[o + i][o + j] - ((p0 + p1) + (p2 + p3));
-        }
-        const T d = __shfl(v, j);
+        const T d = bcast(a[j], j);
         if (!(d > T(0))) return j + 1;
-        const T l = sqrt(d);
-        if (i > j && i < D) L[o + i][o + j] = v / l;
-        if (i == j) L[o + j][o + j] = l;
-        wave_sync();
+        const T l = sqrt(d), rl = T(1) / l;
+        a[j] = (i == j) ? l : a[j] * rl;
+#pragma unroll
+        for (int c = j + 1; c < D; c++) a[c] -= a[j] * bcast(a[j], c);
     }
+#pragma unroll
+    for (int j = 0; j < D; j++)
+        if (i < D && j <= i) L[o + i][o + j] = a[j];
+    wave_sync();
     return 0;
 }
 
 // Inverse of the lower-triangular 32 x 32 block at (o, o): lane c < 32 forms
-// column c by forward substitution, W(r, c) = (delta_rc - sum_{c<=q<r} L(r, q)
-// W(q, c)) / L(r, r), directly in Wd (row-major; zero above the diagonal).
-// Each lane reads only its own column of Wd.
+// column c by forward substitution in registers, W(r, c) = (delta_rc -
+// sum_{q<r} L(r, q) W(q, c)) / L(r, r), with each L(r, q) broadcast from
+// lane r's copy of row r; the result goes to Wd (row-major, zero above the
+// diagonal).  rdg is unused (kept for the call signature).
 template <typename T>
 __device__ __forceinline__ void inv32(T (*L)[LP], int o, T (*Wd)[DP], T* rdg, int lane)
 {
-    if (lane < D) rdg[lane] = T(1) / L[o + lane][o + lane];
-    wave_sync();
+    (void)rdg;
     const int c = lane;
+    T a[D], w[D];
+#pragma unroll
+    for (int j = 0; j < D; j++) a[j] = (c < D && j <= c) ? L[o + c][o + j] : T(0);
+#pragma unroll
+    for (int r = 0; r < D; r++) {
+        T s = (r == c) ? T(1) : T(0);
+#pragma unroll
+        for (int q = 0; q < r; q++) s -= bcast(a[q], r) * w[q];
+        const T rr = T(1) / bcast(a[r], r);
+        w[r] = (r >= c) ? s * rr : T(0);
+    }
     if (c < D) {
-        for (int r = 0; r < D; r++) {
-            T p0 = 0, p1 = 0, p2 = 0, p3 = 0;
-            int q = c;
-            for (; q + 4 <= r; q += 4) {
-                p0 += L[o + r][o + q] * Wd[q][c];
-                p1 += L[o + r][o + q + 1] * Wd[q + 1][c];
-                p2 += L[o + r][o + q + 2] * Wd[q + 2][c];
-                p3 += L[o + r][o + q + 3] * Wd[q + 3][c];
-            }
-            for (; q < r; q++) p0 += L[o + r][o + q] * Wd[q][c];
-            const T s = ((r == c) ? T(1) : T(0)) - ((p0 + p1) + (p2 + p3));
-            Wd[r][c] = (r >= c) ? s * rdg[r] : T(0);
-        }
+#pragma unroll
+        for (int r = 0; r < D; r++) Wd[r][c] = w[r];
     }
     wave_sync();
 }
-
 
 template <typename T>
 struct Leaf128Smem {
@@ -201,20 +213,21 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
         // owns whole row blocks, so reading and overwriting them is race-free
         for (int rb = w; rb < nrb; rb += 4) {
             acc_t x0 = acc_t{0, 0, 0, 0}, x1 = acc_t{0, 0, 0, 0};
+            (void)x1;
             {
                 const int r = lane & 15, g = lane >> 4;
 #pragma unroll
                 for (int kk = 0; kk < D; kk += 4) {
                     const T av = L[r0 + rb * 16 + r][o + kk + g];
                     x0 = M16<T>::op(av, Wd[r][kk + g], x0);
-                    x1 = M16<T>::op(av, Wd[16 + r][kk + g], x1);
+                    if constexpr (TWO_HALVES) x1 = M16<T>::op(av, Wd[16 + r][kk + g], x1);
                 }
             }
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int i = r0 + rb * 16 + M16<T>::row(lane, q);
                 L[i][o + (lane & 15)] = x0[q];
-                L[i][o + 16 + (lane & 15)] = x1[q];
+                if constexpr (TWO_HALVES) L[i][o + 16 + (lane & 15)] = x1[q];
             }
         }
         __syncthreads();
@@ -263,7 +276,7 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
         __syncthreads();
         const int r0 = o + D, nrb = (N - r0) / 16;
         // T = W_RR L_Rj  (W_RR already in place, lower triangular).  A wave owns
-        // the row blocks w and w + 4 (at most six row blocks exist).
+        // the row blocks w and w + 4 (at most seven row blocks exist).
         acc_t tacc[2][2];
 #pragma unroll
         for (int q2 = 0; q2 < 2; q2++) {
@@ -276,7 +289,8 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
                 for (int kk = 0; kk < kend; kk += 4) {
                     const T av = L[r0 + rb * 16 + r][r0 + kk + g];
                     tacc[q2][0] = M16<T>::op(av, L[r0 + kk + g][o + r], tacc[q2][0]);
-                    tacc[q2][1] = M16<T>::op(av, L[r0 + kk + g][o + 16 + r], tacc[q2][1]);
+                    if constexpr (TWO_HALVES)
+                        tacc[q2][1] = M16<T>::op(av, L[r0 + kk + g][o + 16 + r], tacc[q2][1]);
                 }
             }
         }
@@ -289,7 +303,7 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
                 for (int q = 0; q < 4; q++) {
                     const int i = r0 + rb * 16 + M16<T>::row(lane, q);
                     L[i][o + (lane & 15)] = tacc[q2][0][q];
-                    L[i][o + 16 + (lane & 15)] = tacc[q2][1][q];
+                    if constexpr (TWO_HALVES) L[i][o + 16 + (lane & 15)] = tacc[q2][1][q];
                 }
             }
         }
@@ -305,14 +319,14 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
                 for (int kk = 0; kk < D; kk += 4) {
                     const T av = L[r0 + rb * 16 + r][o + kk + g];
                     y0 = M16<T>::op(av, Wd[kk + g][r], y0);
-                    y1 = M16<T>::op(av, Wd[kk + g][16 + r], y1);
+                    if constexpr (TWO_HALVES) y1 = M16<T>::op(av, Wd[kk + g][16 + r], y1);
                 }
                 wave_sync();
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     const int i = r0 + rb * 16 + M16<T>::row(lane, q);
                     L[i][o + (lane & 15)] = -y0[q];
-                    L[i][o + 16 + (lane & 15)] = -y1[q];
+                    if constexpr (TWO_HALVES) L[i][o + 16 + (lane & 15)] = -y1[q];
                 }
             }
         }
