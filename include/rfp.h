@@ -201,6 +201,35 @@ int rfp_dpfsv_batched(rfp_handle_t h, int mode, int64_t batch, const rfp_sys_t* 
                       hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Autotuner (not in the paper).  The handle can hold a table of kernel
+ * configurations, keyed by shape class (sizes rounded up to powers of two,
+ * operand orientation, precision): the GEMM tile (128x128, 64x128, 128x64,
+ * 64x64) with its split-K factor, and the right-hand-side slice width of the
+ * fused solve.  Without a table the library uses its built-in rules.  Every
+ * configuration computes the same result; only speed differs.
+ */
+enum { RFP_TUNE_FP64 = 1, RFP_TUNE_FP32 = 2, RFP_TUNE_FP16 = 4, RFP_TUNE_BF16 = 8 };
+
+/* Time every admissible configuration for the GEMM shapes that PFTRF (and,
+ * for FP64, PFTRI) of order n produce in the precisions `precs` (RFP_TUNE_*
+ * bits), and the solve's slice widths for nrhs right-hand sides (FP64; nrhs
+ * = 0 skips it), on scratch operands on this handle's device; keep the
+ * fastest.  Synchronises the stream; allocates scratch.  Argument order: N=1,
+ * NRHS=2, PRECS=3. */
+int rfp_autotune(rfp_handle_t h, int64_t n, int64_t nrhs, int precs, hipStream_t stream);
+/* Number of tuned entries; drop the table; force one GEMM configuration for
+ * every non-tuned shape (tile -1 switches forcing off; split 0 = built-in
+ * split-K rule, 1 = none, s = s-way) -- a testing aid. */
+int rfp_tune_count(rfp_handle_t h);
+int rfp_tune_clear(rfp_handle_t h);
+int rfp_tune_force(rfp_handle_t h, int tile, int split);
+/* Write / read the table as JSON text (one entry per line).  Load replaces
+ * the table; returns -1 when the file cannot be opened, -2 when it is not a
+ * table written by rfp_tune_save. */
+int rfp_tune_save(rfp_handle_t h, const char* path);
+int rfp_tune_load(rfp_handle_t h, const char* path);
+
+/* ------------------------------------------------------------------------
  * Kernel timing (introspection, used by the benchmark for its roofline).
  * While enabled, every kernel the handle's calls launch is bracketed by a pair
  * of HIP events on the call's stream.  rfp_profile_read waits for the device,

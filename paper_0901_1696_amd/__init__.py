@@ -54,6 +54,12 @@ _SIGS = {
     "rfp_spftrf_mp": [_vp, _int, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_dpfcast_s": [_vp, _chr, _chr, _i64, _vp, _int, ctypes.c_double, _vp, _vp, _vp],
     "rfp_dlansf": [_vp, _chr, _chr, _chr, _i64, _vp, _vp, _vp],
+    "rfp_autotune": [_vp, _i64, _i64, _int, _vp],
+    "rfp_tune_count": [_vp],
+    "rfp_tune_clear": [_vp],
+    "rfp_tune_force": [_vp, _int, _int],
+    "rfp_tune_save": [_vp, ctypes.c_char_p],
+    "rfp_tune_load": [_vp, ctypes.c_char_p],
     "rfp_dpfsv_batched": [_vp, _int, _i64, _vp, _vp, _vp, _int, ctypes.c_double, _int, _vp, _vp, _vp],
     "rfp_dpfsv_ir": [_vp, _int, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp, _i64, ctypes.c_double, _int,
                      ctypes.POINTER(_int), ctypes.POINTER(_int), _vp],
@@ -293,3 +299,33 @@ def rfp_dpfsv_batched(h, mode, batch, sys, arf_pool, b_pool, info, iter, do_pftr
     _check("rfp_dpfsv_batched", lib().rfp_dpfsv_batched(h.value, int(mode), int(batch), _ptr(sys), _ptr(arf_pool),
                                                         _ptr(b_pool), 1 if do_pftri else 0, float(tol), int(max_iter),
                                                         _ptr(info), _ptr(iter), _stream(stream)))
+
+
+TUNE_FP64, TUNE_FP32, TUNE_FP16, TUNE_BF16 = 1, 2, 4, 8
+
+
+def rfp_autotune(h, n, nrhs=0, precs=TUNE_FP64, stream=None):
+    _check("rfp_autotune", lib().rfp_autotune(h.value, int(n), int(nrhs), int(precs), _stream(stream)))
+
+
+def rfp_tune_count(h):
+    c = lib().rfp_tune_count(h.value)
+    if c < 0:
+        raise RfpError("rfp_tune_count", c)
+    return c
+
+
+def rfp_tune_clear(h):
+    _check("rfp_tune_clear", lib().rfp_tune_clear(h.value))
+
+
+def rfp_tune_force(h, tile, split=0):
+    _check("rfp_tune_force", lib().rfp_tune_force(h.value, int(tile), int(split)))
+
+
+def rfp_tune_save(h, path):
+    _check("rfp_tune_save", lib().rfp_tune_save(h.value, os.fsencode(path)))
+
+
+def rfp_tune_load(h, path):
+    _check("rfp_tune_load", lib().rfp_tune_load(h.value, os.fsencode(path)))

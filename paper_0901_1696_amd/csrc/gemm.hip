@@ -627,15 +627,43 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
     // low-precision operands for the bulk updates only: in-place products
     // (the leaf-level panel solves) stay in FP32
     const int lp = (sizeof(T) == 4 && !inplace) ? ex.lowp : 0;
-    const int tile = pick_tile(m, n, c_lower, inplace, &tm, &tn, lp != 0);
+    const bool amc0 = A.rs == 1, bnc0 = B.rs == 1, cmc0 = C.rs == 1;
+    // an autotuned (or forced) configuration for this shape class, if admissible
+    int tile = -1, tsplit = 0;
+    if (ex.tune && !inplace) {
+        const int sel0 = (amc0 ? 4 : 0) | (bnc0 ? 2 : 0) | (cmc0 ? 1 : 0);
+        auto it = ex.tune->gemm.find(
+            tune_gemm_key(sizeof(T) == 8 ? 0 : 1, lp, sel0, c_lower ? 1 : 0, m, n, k < 0 ? 0 : k));
+        if (it != ex.tune->gemm.end()) {
+            tile = it->second.tile;
+            tsplit = it->second.split;
+        } else if (ex.tune->force_tile >= 0) {
+            tile = ex.tune->force_tile;
+            tsplit = ex.tune->force_split;
+        }
+        if (tile < 0 || tile > 3 || (c_lower && m == n && TILE_BM[tile] != TILE_BN[tile]) ||
+            (lp && TILE_BM[tile] != TILE_BN[tile]))
+            tile = -1;
+    }
+    if (tile >= 0) {
+        tm = (m + TILE_BM[tile] - 1) / TILE_BM[tile];
+        tn = (n + TILE_BN[tile] - 1) / TILE_BN[tile];
+    } else {
+        tile = pick_tile(m, n, c_lower, inplace, &tm, &tn, lp != 0);
+    }
     p.tri_enum = (c_lower && m == n) ? 1 : 0;
     const int64_t ntiles = p.tri_enum ? tm * (tm + 1) / 2 : tm * tn;
     p.tiles_m = (int)tm;
     p.tiles_n = (int)tn;
 
-    // split K when the tile grid cannot fill the chip and K is long
+    // split K when the tile grid cannot fill the chip and K is long (or as tuned)
     int64_t nsplit = 1;
-    if (ntiles < 256 && p.k >= 1024 && ex.splitk_ws) {
+    if (tsplit > 1 && ex.splitk_ws) {
+        nsplit = tsplit;
+        if (nsplit > p.k / BK) nsplit = p.k / BK;
+        while (nsplit > 1 && (size_t)(nsplit * m * n) * sizeof(T) > ex.splitk_bytes) nsplit--;
+        if (nsplit < 1) nsplit = 1;
+    } else if (tsplit == 0 && ntiles < 256 && p.k >= 1024 && ex.splitk_ws) {
         nsplit = (512 + ntiles - 1) / ntiles;
         int64_t kmax = p.k / 256;
         if (nsplit > kmax) nsplit = kmax;

@@ -104,8 +104,10 @@ ProfScope::~ProfScope()
 
 struct rfp_context {
     int device;
-    void* splitk;
+    void* splitk;         // split-K partial sums of the caller's stream
     size_t splitk_bytes;
+    void* splitk2;        // ... and of the auxiliary stream (the two may run at once)
+    size_t splitk2_bytes;
     void* inv;
     size_t inv_bytes;
     rfp::Profiler* prof;
@@ -120,6 +122,7 @@ struct rfp_context {
     void* bat;            // batched-solver scratch (work counter + per-workgroup scratch)
     size_t bat_bytes;
     int cus;              // compute units of the device
+    rfp::TuneTable* tune; // autotuned kernel configurations (null: built-in rules)
 };
 
 namespace rfp {
@@ -433,6 +436,7 @@ static constexpr size_t SPLITK_BYTES = size_t(128) << 20;
 static hipError_t prepare(rfp_context* h, size_t inv_need)
 {
     hipError_t e = ensure(&h->splitk, &h->splitk_bytes, SPLITK_BYTES);
+    if (e == hipSuccess) e = ensure(&h->splitk2, &h->splitk2_bytes, SPLITK_BYTES);
     if (e != hipSuccess) return e;
     if (!h->aux) {
         e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
@@ -479,9 +483,12 @@ static Run<T> make_run(rfp_context* h, hipStream_t s, int* info)
     r.ex.prof = h->prof;
     r.ex2 = r.ex;
     r.ex2.stream = h->aux;
+    r.ex2.splitk_ws = h->splitk2;
+    r.ex2.splitk_bytes = h->splitk2_bytes;
     r.evs = h->nev ? h->ev : nullptr;
     r.nev = h->nev;
     r.evi = &h->evi;
+    r.ex.tune = r.ex2.tune = h->tune;
     return r;
 }
 
@@ -763,6 +770,7 @@ static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64
     Exec ex{};
     ex.stream = st;
     ex.prof = h->prof;
+    ex.tune = h->tune;
     const double mu = 1.0;
     hipError_t e = hipSuccess;
     auto ok = [&](hipError_t q) {
@@ -866,6 +874,195 @@ static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64
     return e == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
+
+// ------------------------------------------------------------- autotuner
+// Candidate configurations of one GEMM shape class are timed on scratch
+// operands of the class's largest recorded shape (same orientation, masks
+// and precision); the fastest is kept.  Every candidate computes the same
+// product, so any choice is correct; only speed differs.
+struct TuneShape {
+    int dt, lp, sel, clower, tri_a, tri_b;
+    int64_t m, n, k;
+};
+
+template <typename T>
+static float time_gemm(const Exec& ex0, const TuneShape& sh, int tile, int split, T* A, T* B, T* C)
+{
+    Exec ex = ex0;
+    TuneTable one;
+    one.force_tile = tile;
+    one.force_split = split;
+    ex.tune = &one;
+    const bool amc = sh.sel & 4, bnc = sh.sel & 2, cmc = sh.sel & 1;
+    Mat<const T> Am = amc ? Mat<const T>{A, 1, sh.m} : Mat<const T>{A, sh.k, 1};
+    Mat<const T> Bm = bnc ? Mat<const T>{B, 1, sh.n} : Mat<const T>{B, sh.k, 1};
+    Mat<T> Cm = cmc ? Mat<T>{C, 1, sh.m} : Mat<T>{C, sh.n, 1};
+    auto run = [&]() {
+        return gemm<T>(ex, sh.m, sh.n, sh.k, T(-1), Am, sh.tri_a, Bm, sh.tri_b, T(1), Cm, sh.clower != 0, false);
+    };
+    if (run() != hipSuccess) return -1.f;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.f;
+    }
+    constexpr int REPS = 3;
+    (void)hipEventRecord(e0, ex.stream);
+    for (int i = 0; i < REPS; i++) (void)run();
+    (void)hipEventRecord(e1, ex.stream);
+    float ms = -1.f;
+    if (hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms < 0 ? -1.f : ms * 1000.f / REPS;
+}
+
+static int tune_gemms(rfp_context* h, const std::vector<TuneShape>& shapes, hipStream_t st)
+{
+    // representative (largest) shape of every class
+    std::map<uint64_t, TuneShape> rep;
+    for (const TuneShape& sh : shapes) {
+        const uint64_t key = tune_gemm_key(sh.dt, sh.lp, sh.sel, sh.clower, sh.m, sh.n, sh.k);
+        auto it = rep.find(key);
+        if (it == rep.end() || (double)sh.m * sh.n * sh.k > (double)it->second.m * it->second.n * it->second.k)
+            rep[key] = sh;
+    }
+    size_t need = 0;
+    for (auto& kv : rep) {
+        const TuneShape& sh = kv.second;
+        const size_t es = sh.dt ? 4 : 8;
+        need = std::max(need, es * (size_t)(sh.m * sh.k + sh.n * sh.k + sh.m * sh.n) + 3 * 256);
+    }
+    void* buf = nullptr;
+    if (need && hipMalloc(&buf, need) != hipSuccess) return RFP_ERR_RUNTIME;
+    if (prepare(h, 0) != hipSuccess) {
+        (void)hipFree(buf);
+        return RFP_ERR_RUNTIME;
+    }
+    Exec ex{};
+    ex.stream = st;
+    ex.splitk_ws = h->splitk;
+    ex.splitk_bytes = h->splitk_bytes;
+    for (auto& kv : rep) {
+        const TuneShape& sh = kv.second;
+        ex.lowp = sh.lp;
+        const size_t es = sh.dt ? 4 : 8;
+        char* p = (char*)buf;
+        void* A = p;
+        void* B = p + ((es * (size_t)(sh.m * sh.k) + 255) & ~(size_t)255);
+        void* C = (char*)B + ((es * (size_t)(sh.n * sh.k) + 255) & ~(size_t)255);
+        // small finite operands (for FP32 two copies of 2^-7 per 8-byte word);
+        // the values do not change the work
+        const size_t total = need / 8;
+        const uint64_t two_f32 = ((uint64_t)0x3C000000u << 32) | 0x3C000000u;
+        double fillv = 1e-3;
+        if (sh.dt) std::memcpy(&fillv, &two_f32, sizeof fillv);
+        (void)fill_double(st, (double*)buf, (int64_t)total, fillv);
+        TuneGemm best{-1, 0, 0.f};
+        for (int tile = 0; tile < 4; tile++) {
+            for (int split : {0, 1, 2, 4, 8, 16}) {
+                if (split > 1 && (sh.k / split < 256 || (size_t)(split * sh.m * sh.n) * es > h->splitk_bytes))
+                    continue;
+                const float us = sh.dt ? time_gemm<float>(ex, sh, tile, split, (float*)A, (float*)B, (float*)C)
+                                       : time_gemm<double>(ex, sh, tile, split, (double*)A, (double*)B, (double*)C);
+                if (us > 0 && (best.tile < 0 || us < best.us)) best = TuneGemm{tile, split, us};
+            }
+        }
+        if (best.tile >= 0) h->tune->gemm[kv.first] = best;
+    }
+    (void)hipStreamSynchronize(st);
+    if (buf) (void)hipFree(buf);
+    return 0;
+}
+
+__global__ void tune_diag_kernel(Mat<double> t1, int64_t m1, Mat<double> t2, int64_t m2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m1) t1.at(i, i) = 1.0;
+    else if (i < m1 + m2) t2.at(i - m1, i - m1) = 1.0;
+}
+
+static int tune_solve(rfp_context* h, int64_t n, int64_t nrhs, hipStream_t st)
+{
+    // timing matrix: the identity in RFP (any data does the same work)
+    const size_t nt = (size_t)(n * (n + 1) / 2);
+    double *arf = nullptr, *b = nullptr;
+    if (hipMalloc(&arf, nt * 8) != hipSuccess) return RFP_ERR_RUNTIME;
+    if (hipMalloc(&b, (size_t)(n * nrhs) * 8) != hipSuccess) {
+        (void)hipFree(arf);
+        return RFP_ERR_RUNTIME;
+    }
+    (void)fill_double(st, arf, (int64_t)nt, 0.0);
+    (void)fill_double(st, b, n * nrhs, 1.0);
+    RfpBlocks blk;
+    rfp_blocks('N', 'L', n, &blk);
+    RfpView<double> v = rfp_view(blk, arf);
+    hipLaunchKernelGGL(tune_diag_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v.t1, v.m1, v.t2, v.m2);
+    int best = 0;
+    float best_us = 0.f;
+    for (int ncb : {1, 2, 4, 8}) {
+        if (ncb > 1 && 16 * (ncb / 2) >= nrhs) break;  // wider than the right-hand sides
+        h->tune->solve[tune_solve_key(0, n, nrhs)] = ncb;
+        hipEvent_t e0, e1;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        (void)pftrs_impl<double>(h, 'N', 'L', n, nrhs, arf, b, n, st);
+        (void)hipEventRecord(e0, st);
+        (void)pftrs_impl<double>(h, 'N', 'L', n, nrhs, arf, b, n, st);
+        (void)hipEventRecord(e1, st);
+        float ms = -1.f;
+        if (hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (ms > 0 && (best == 0 || ms * 1000.f < best_us)) {
+            best = ncb;
+            best_us = ms * 1000.f;
+        }
+    }
+    if (best) h->tune->solve[tune_solve_key(0, n, nrhs)] = best;
+    else h->tune->solve.erase(tune_solve_key(0, n, nrhs));
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(arf);
+    (void)hipFree(b);
+    return 0;
+}
+
+// GEMM shapes recorded from the drivers' plans (non-in-place products).
+static void plan_shapes(char routine, int64_t n, std::vector<TuneShape>& out, int dt, int lp)
+{
+    for (const char* lay : {"NL", "TU", "NU", "TL"}) {
+        int64_t cnt = 0;
+        std::vector<rfp_plan_op> ops;
+        PlanRec rec{nullptr, 0, 0, sizeof(double)};
+        double* arf = plan_base<double>(RFP_PLAN_BUF_ARF);
+        int* info = (int*)plan_base<int>(RFP_PLAN_BUF_INFO);
+        for (int pass = 0; pass < 2; pass++) {
+            rec.ops = pass ? ops.data() : nullptr;
+            rec.cap = pass ? cnt : 0;
+            rec.count = 0;
+            if (routine == 'F') (void)pftrf_impl<double>(nullptr, lay[0], lay[1], n, arf, info, nullptr, &rec);
+            else (void)pftri_impl<double>(nullptr, lay[0], lay[1], n, arf, info, nullptr, &rec);
+            cnt = rec.count;
+            if (!pass) ops.resize((size_t)cnt);
+        }
+        for (const rfp_plan_op& o : ops) {
+            if (o.kind != RFP_PLAN_GEMM || o.inplace || o.m <= 0 || o.n <= 0) continue;
+            TuneShape sh;
+            sh.dt = dt;
+            sh.lp = lp;
+            sh.sel = (o.a[2] == 1 ? 4 : 0) | (o.b[2] == 1 ? 2 : 0) | (o.c[2] == 1 ? 1 : 0);
+            sh.clower = o.c_lower;
+            sh.tri_a = o.tri_a;
+            sh.tri_b = o.tri_b;
+            sh.m = o.m;
+            sh.n = o.n;
+            sh.k = o.k;
+            out.push_back(sh);
+        }
+    }
+}
+
 }  // namespace rfp
 
 using namespace rfp;
@@ -893,10 +1090,12 @@ int rfp_destroy(rfp_handle_t h)
         DeviceGuard g(h->device);
         (void)hipDeviceSynchronize();
         if (h->splitk) (void)hipFree(h->splitk);
+        if (h->splitk2) (void)hipFree(h->splitk2);
         if (h->inv) (void)hipFree(h->inv);
         if (h->flags) (void)hipFree(h->flags);
         if (h->ir) (void)hipFree(h->ir);
         if (h->bat) (void)hipFree(h->bat);
+        delete h->tune;
         for (int i = 0; i < h->nev; i++) (void)hipEventDestroy(h->ev[i]);
         if (h->aux) (void)hipStreamDestroy(h->aux);
         delete h->prof;
@@ -1107,6 +1306,124 @@ int rfp_dpfsv_batched(rfp_handle_t h, int mode, int64_t batch, const rfp_sys_t* 
                                        do_pftri ? 1 : 0, tol, max_iter, info, iter, (int*)h->bat,
                                        (char*)h->bat + 256, wgs);
     return e == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+int rfp_autotune(rfp_handle_t h, int64_t n, int64_t nrhs, int precs, hipStream_t stream)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (n < 1) return -1;
+    if (nrhs < 0) return -2;
+    if (precs <= 0 || precs > 15) return -3;
+    DeviceGuard g(h->device);
+    if (!h->tune) h->tune = new TuneTable();
+    std::vector<TuneShape> shapes;
+    if (precs & RFP_TUNE_FP64) {
+        plan_shapes('F', n, shapes, 0, 0);
+        plan_shapes('I', n, shapes, 0, 0);
+    }
+    if (precs & RFP_TUNE_FP32) plan_shapes('F', n, shapes, 1, 0);
+    if (precs & RFP_TUNE_FP16) plan_shapes('F', n, shapes, 1, 1);
+    if (precs & RFP_TUNE_BF16) plan_shapes('F', n, shapes, 1, 2);
+    int rc = tune_gemms(h, shapes, stream);
+    if (rc == 0 && nrhs > 0 && (precs & RFP_TUNE_FP64)) rc = tune_solve(h, n, nrhs, stream);
+    return rc;
+}
+
+int rfp_tune_count(rfp_handle_t h)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    return h->tune ? (int)(h->tune->gemm.size() + h->tune->solve.size()) : 0;
+}
+
+int rfp_tune_clear(rfp_handle_t h)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    delete h->tune;
+    h->tune = nullptr;
+    return 0;
+}
+
+int rfp_tune_force(rfp_handle_t h, int tile, int split)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (tile < -1 || tile > 3) return -1;
+    if (split < 0 || split > 32) return -2;
+    if (!h->tune) h->tune = new TuneTable();
+    h->tune->force_tile = tile;
+    h->tune->force_split = split;
+    return 0;
+}
+
+int rfp_tune_save(rfp_handle_t h, const char* path)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (!path) return -1;
+    FILE* f = fopen(path, "w");
+    if (!f) return -1;
+    fprintf(f, "{\"rfp_tune\": 1,\n \"gemm\": [\n");
+    size_t i = 0;
+    if (h->tune)
+        for (auto& kv : h->tune->gemm) {
+            const uint64_t k = kv.first;
+            fprintf(f, "  {\"key\": %llu, \"dt\": %d, \"lp\": %d, \"sel\": %d, \"clower\": %d, \"mb\": %d, \"nb\": %d, "
+                       "\"kb\": %d, \"tile\": %d, \"split\": %d, \"us\": %.3f}%s\n",
+                    (unsigned long long)k, (int)(k >> 40), (int)((k >> 36) & 15), (int)((k >> 32) & 15),
+                    (int)((k >> 30) & 1), (int)((k >> 20) & 1023), (int)((k >> 10) & 1023), (int)(k & 1023),
+                    kv.second.tile, kv.second.split, kv.second.us, ++i < h->tune->gemm.size() ? "," : "");
+        }
+    fprintf(f, " ],\n \"solve\": [\n");
+    i = 0;
+    if (h->tune)
+        for (auto& kv : h->tune->solve)
+            fprintf(f, "  {\"key\": %llu, \"ncb\": %d}%s\n", (unsigned long long)kv.first, kv.second,
+                    ++i < h->tune->solve.size() ? "," : "");
+    fprintf(f, " ]\n}\n");
+    return fclose(f) == 0 ? 0 : -1;
+}
+
+int rfp_tune_load(rfp_handle_t h, const char* path)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (!path) return -1;
+    FILE* f = fopen(path, "r");
+    if (!f) return -1;
+    TuneTable* t = new TuneTable();
+    char line[512];
+    bool ok = true, in_solve = false;
+    while (fgets(line, sizeof line, f)) {
+        if (strstr(line, "\"solve\"")) in_solve = true;
+        const char* q = strstr(line, "{\"key\":");
+        if (!q) continue;
+        unsigned long long key;
+        if (!in_solve) {
+            int dt, lp, sel, cl, mb, nb, kb, tile, split;
+            float us;
+            if (sscanf(q, "{\"key\": %llu, \"dt\": %d, \"lp\": %d, \"sel\": %d, \"clower\": %d, \"mb\": %d, \"nb\": %d, "
+                          "\"kb\": %d, \"tile\": %d, \"split\": %d, \"us\": %f}",
+                       &key, &dt, &lp, &sel, &cl, &mb, &nb, &kb, &tile, &split, &us) != 11 ||
+                tile < 0 || tile > 3 || split < 0 || split > 32) {
+                ok = false;
+                break;
+            }
+            t->gemm[(uint64_t)key] = TuneGemm{tile, split, us};
+        } else {
+            int ncb;
+            if (sscanf(q, "{\"key\": %llu, \"ncb\": %d}", &key, &ncb) != 2 ||
+                !(ncb == 1 || ncb == 2 || ncb == 4 || ncb == 8)) {
+                ok = false;
+                break;
+            }
+            t->solve[(uint64_t)key] = ncb;
+        }
+    }
+    fclose(f);
+    if (!ok) {
+        delete t;
+        return -2;
+    }
+    delete h->tune;
+    h->tune = t;
+    return 0;
 }
 
 }  // extern "C"

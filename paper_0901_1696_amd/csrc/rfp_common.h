@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+
 #include "rfp.h"
 
 namespace rfp {
@@ -127,6 +129,36 @@ inline int64_t rec_split(int64_t n, int nb)
 struct Profiler;
 
 // Per-call execution context.
+// Tuning table (autotuner results): GEMM configurations per shape class and
+// right-hand-side slice widths of the fused solve per nrhs class.
+struct TuneGemm {
+    int tile;    // 0: 128 x 128, 1: 64 x 128, 2: 128 x 64, 3: 64 x 64
+    int split;   // 0: built-in rule, 1: no split-K, s > 1: s-way split-K
+    float us;    // measured time of the representative shape
+};
+struct TuneTable {
+    std::map<uint64_t, TuneGemm> gemm;
+    std::map<uint64_t, int> solve;  // key -> 16-column blocks per slice
+    int force_tile = -1, force_split = 0;  // testing: one configuration for every GEMM
+};
+// Shape classes: sizes by ceil(log2), precision (dt 0 FP64, 1 FP32; lp the
+// operand mode), operand orientation bits and the lower-output flag.
+__host__ inline int size_bucket(int64_t x)
+{
+    int b = 0;
+    while (b < 40 && ((int64_t)1 << b) < x) b++;
+    return b;
+}
+__host__ inline uint64_t tune_gemm_key(int dt, int lp, int sel, int clower, int64_t m, int64_t n, int64_t k)
+{
+    return ((uint64_t)dt << 40) | ((uint64_t)lp << 36) | ((uint64_t)sel << 32) | ((uint64_t)clower << 30) |
+           ((uint64_t)size_bucket(m) << 20) | ((uint64_t)size_bucket(n) << 10) | (uint64_t)size_bucket(k);
+}
+__host__ inline uint64_t tune_solve_key(int dt, int64_t n, int64_t nrhs)
+{
+    return ((uint64_t)dt << 20) | ((uint64_t)size_bucket(n) << 10) | (uint64_t)size_bucket(nrhs);
+}
+
 struct Exec {
     hipStream_t stream;
     int* info;          // device; kernels of a factorization exit early when *info != 0
@@ -134,6 +166,7 @@ struct Exec {
     size_t splitk_bytes;
     Profiler* prof;     // optional per-launch event timing
     int lowp = 0;       // FP32 GEMMs: 0 FP32 operands, 1 FP16, 2 BF16 (not for in-place products)
+    const TuneTable* tune = nullptr;  // autotuned configurations, if any
 };
 
 // Brackets one kernel launch with HIP events on the launch stream when

@@ -371,7 +371,12 @@ hipError_t block_solve(const Exec& ex, bool forward, Mat<const T> t1, Mat<const 
     a.spin_limit = 1 << 24;
     const int nblk = a.nb1 + a.nb2;
     if (nblk == 0 || nrhs <= 0) return hipSuccess;
-    const int ncb = block_solve_width(nrhs);
+    int ncb = block_solve_width(nrhs);
+    if (ex.tune && !getenv("RFP_SOLVE_COLS")) {
+        auto it = ex.tune->solve.find(tune_solve_key(sizeof(T) == 8 ? 0 : 1, m1 + m2, nrhs));
+        if (it != ex.tune->solve.end() && (it->second == 1 || it->second == 2 || it->second == 4 || it->second == 8))
+            ncb = it->second;
+    }
     a.nslices = (int)((nrhs + 16 * ncb - 1) / (16 * ncb));
     switch (ncb) {
         case 1: return launch_solve<T, 1>(ex, forward, a, nblk);
