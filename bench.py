@@ -102,6 +102,26 @@ def cpu_baseline(n=12000, nrhs=128):
                       f"matrix of the same recipe, nrhs={nrhs}; {dt:.1f} s"}
 
 
+def roofline_of(prof):
+    """Roofline object of the dominant kernel (largest summed event time) and
+    the top of the kernel table, from the library's per-launch event timing."""
+    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    total_kernel_ms = sum(v["total_ms"] for v in prof.values())
+    avg_ms = dom["total_ms"] / dom["launches"]
+    flops_per_launch = dom["flops"] / dom["launches"]
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
+                "traffic": traffic_for(dom_name), "kernel": dom_name, "launches": dom["launches"],
+                "avg_launch_ms": round(avg_ms, 5), "algorithmic_flops_per_launch": flops_per_launch,
+                "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"],
+                "share_of_kernel_time": round(dom["total_ms"] / total_kernel_ms, 4)}
+    kernels = sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])[:8]
+    table = [{"kernel": k, "launches": v["launches"], "total_ms": round(v["total_ms"], 3),
+              "tflops": round(v["flops"] / max(v["total_ms"], 1e-9) / 1e9, 2)} for k, v in kernels]
+    return roofline, table
+
+
 def backward_error_dense(A, B, X):
     """max over columns ||B - A X||_inf / (||A||_inf ||X||_inf + ||B||_inf), FP64 on the GPU."""
     R = B - A @ X
@@ -268,6 +288,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--mixed-n", type=int, default=40000)
+    ap.add_argument("--no-kernel-profile", action="store_true",
+                    help="skip the per-launch event timing (and the roofline); for counter collection runs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -333,14 +355,15 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] warmup step {i + 1}/{args.warmup} done")
 
-    rfp.rfp_profile_enable(h, True)
+    if not args.no_kernel_profile:
+        rfp.rfp_profile_enable(h, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = rfp.rfp_profile_read(h)
+    prof = rfp.rfp_profile_read(h) if not args.no_kernel_profile else {}
     rfp.rfp_profile_enable(h, False)
     if int(info.item()) != 0:
         raise SystemExit(f"PFTRF reported INFO={int(info.item())}")
@@ -350,20 +373,9 @@ def main():
     value = args.steps * work_flops / elapsed / 1e9
 
     # dominant kernel of the timed region (largest summed event time)
-    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
-    total_kernel_ms = sum(v["total_ms"] for v in prof.values())
-    avg_ms = dom["total_ms"] / dom["launches"]
-    flops_per_launch = dom["flops"] / dom["launches"]
-    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-    traffic = traffic_for(dom_name)
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
-                "traffic": traffic, "kernel": dom_name, "launches": dom["launches"],
-                "avg_launch_ms": round(avg_ms, 5), "algorithmic_flops_per_launch": flops_per_launch,
-                "share_of_kernel_time": round(dom["total_ms"] / total_kernel_ms, 4)}
-    kernels = sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"])[:8]
-    kernel_table = [{"kernel": k, "launches": v["launches"], "total_ms": round(v["total_ms"], 3),
-                     "tflops": round(v["flops"] / max(v["total_ms"], 1e-9) / 1e9, 2)} for k, v in kernels]
+    roofline, kernel_table = None, []
+    if prof:
+        roofline, kernel_table = roofline_of(prof)
 
     # ---- accuracy of every (n, layout) solve (independent check with torch)
     accuracy = None

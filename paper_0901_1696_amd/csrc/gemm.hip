@@ -443,12 +443,9 @@ template <typename T, bool AMC, bool BNC, bool CMC, int WMB, int WNB, int LP = 0
 static const char* kname()
 {
     static char buf[112];
-    if (!buf[0]) {
-        char lp[8] = "";
-        if (LP) snprintf(lp, sizeof lp, ", %d", LP);
-        snprintf(buf, sizeof buf, "rfp::gemm_kernel<%s, %s, %s, %s, %d, %d%s>(rfp::GemmParams<%s>)", tname<T>(),
-                 AMC ? "true" : "false", BNC ? "true" : "false", CMC ? "true" : "false", WMB, WNB, lp, tname<T>());
-    }
+    if (!buf[0])
+        snprintf(buf, sizeof buf, "rfp::gemm_kernel<%s, %s, %s, %s, %d, %d, %d>(rfp::GemmParams<%s>)", tname<T>(),
+                 AMC ? "true" : "false", BNC ? "true" : "false", CMC ? "true" : "false", WMB, WNB, LP, tname<T>());
     return buf;
 }
 

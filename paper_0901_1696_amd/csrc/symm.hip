@@ -35,7 +35,7 @@ struct SkinnyArgs {
     int64_t ldx;
     int r;
     int64_t kc;           // k per chunk
-    double* w;            // partials: slice (first_slice + chunk), column-major m x RMAX... see host
+    double* w;            // this product's first slice; chunk c writes slice c (w + c * wslice)
     int64_t wslice;       // doubles per slice
     int64_t wld;          // leading dimension of a slice (rows of the output half)
     int64_t row0;         // first output row of this product inside the slice
@@ -205,8 +205,8 @@ hipError_t symm_thin(const Exec& ex, const RfpView<const double>& v, const doubl
             a.row0 = 0;
             nsl[h] += nch;
             const dim3 grid((unsigned)((pr.m + TM - 1) / TM), (unsigned)nch);
-            ProfScope ps(ex, r > 16 ? "void rfp::skinny_kernel<2>(rfp::(anonymous namespace)::SkinnyArgs)"
-                                    : "void rfp::skinny_kernel<1>(rfp::(anonymous namespace)::SkinnyArgs)",
+            ProfScope ps(ex, r > 16 ? "rfp::skinny_kernel<2>(rfp::(anonymous namespace)::SkinnyArgs)"
+                                    : "rfp::skinny_kernel<1>(rfp::(anonymous namespace)::SkinnyArgs)",
                          2.0 * (double)pr.m * (double)pr.k * r, 8.0 * (double)pr.m * (double)pr.k);
             if (r > 16) hipLaunchKernelGGL(skinny_kernel<2>, grid, dim3(256), 0, ex.stream, a);
             else hipLaunchKernelGGL(skinny_kernel<1>, grid, dim3(256), 0, ex.stream, a);

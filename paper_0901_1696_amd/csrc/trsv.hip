@@ -320,7 +320,7 @@ static hipError_t launch_solve(const Exec& ex, bool forward, const SolveArgs<T>&
     char* nm = names[ti][di];
     if (!nm[0]) {
         const char* tn = ti ? "float" : "double";
-        snprintf(nm, sizeof names[ti][di], "void rfp::block_solve_kernel<%s, %d, %s>(rfp::SolveArgs<%s>)", tn, NCB,
+        snprintf(nm, sizeof names[ti][di], "rfp::block_solve_kernel<%s, %d, %s>(rfp::SolveArgs<%s>)", tn, NCB,
                  forward ? "true" : "false", tn);
     }
     const double mtot = (double)(a.m1 + a.m2);
