@@ -232,7 +232,10 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
 
     T ra[EA], rb[EB];
 
-    // Full slab [k0, k0 + BK) inside [kb, ke): no k bounds to test.
+    // Loads only issue the global reads; the masks (ragged rows, triangular
+    // bands, the ragged last slab) are applied when the slab is written to
+    // LDS, after the current slab's products, so the load latency overlaps
+    // the MFMAs.  Full slab [k0, k0 + BK) inside [kb, ke): no k bounds.
     auto load_fast = [&](int64_t k0) {
 #pragma unroll
         for (int r = 0; r < EA; r++) {
@@ -244,49 +247,47 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
             const int64_t kk = k0 + b_k + (BNC ? r * B_STEP : 0);
             rb[r] = BNC ? p.B[b_row[0] + kk * p.ldb] : p.B[b_row[r] * p.ldb + kk];
         }
-        if (!a_all_rows || !a_nomask) {
+    };
+    // Ragged last slab: k clamped into the operand (entries at or past ke are
+    // zeroed by the store).
+    auto load_tail = [&](int64_t k0) {
 #pragma unroll
-            for (int r = 0; r < EA; r++) {
-                const int64_t i = i0 + a_i + (AMC ? 0 : r * A_STEP);
-                const int64_t d = k0 + a_k + (AMC ? r * A_STEP : 0) - i;
-                const bool ok = ((a_valid >> (AMC ? 0 : r)) & 1u) && d >= ba.lo && d <= ba.hi;
-                ra[r] = ok ? ra[r] : T(0);
-            }
+        for (int r = 0; r < EA; r++) {
+            const int64_t kk = k0 + a_k + (AMC ? r * A_STEP : 0);
+            const int64_t kc = kk < kmax ? kk : kmax;
+            ra[r] = AMC ? p.A[a_row[0] + kc * p.lda] : p.A[a_row[r] * p.lda + kc];
         }
-        if (!b_all_rows || !b_nomask) {
 #pragma unroll
-            for (int r = 0; r < EB; r++) {
-                const int64_t j = j0 + b_j + (BNC ? 0 : r * B_STEP);
-                const int64_t d = k0 + b_k + (BNC ? r * B_STEP : 0) - j;
-                const bool ok = ((b_valid >> (BNC ? 0 : r)) & 1u) && d >= bb.lo && d <= bb.hi;
-                rb[r] = ok ? rb[r] : T(0);
-            }
+        for (int r = 0; r < EB; r++) {
+            const int64_t kk = k0 + b_k + (BNC ? r * B_STEP : 0);
+            const int64_t kc = kk < kmax ? kk : kmax;
+            rb[r] = BNC ? p.B[b_row[0] + kc * p.ldb] : p.B[b_row[r] * p.ldb + kc];
         }
     };
-    // Ragged last slab: k clamped into the operand, entries at or past ke zeroed.
-    auto load_tail = [&](int64_t k0) {
+    auto mask_a = [&](int64_t k0) {
 #pragma unroll
         for (int r = 0; r < EA; r++) {
             const int64_t i = i0 + a_i + (AMC ? 0 : r * A_STEP);
             const int64_t kk = k0 + a_k + (AMC ? r * A_STEP : 0);
-            const int64_t kc = kk < kmax ? kk : kmax;
-            const T v = AMC ? p.A[a_row[0] + kc * p.lda] : p.A[a_row[r] * p.lda + kc];
             const int64_t d = kk - i;
             const bool ok = ((a_valid >> (AMC ? 0 : r)) & 1u) && kk < ke && d >= ba.lo && d <= ba.hi;
-            ra[r] = ok ? v : T(0);
+            ra[r] = ok ? ra[r] : T(0);
         }
+    };
+    auto mask_b = [&](int64_t k0) {
 #pragma unroll
         for (int r = 0; r < EB; r++) {
             const int64_t j = j0 + b_j + (BNC ? 0 : r * B_STEP);
             const int64_t kk = k0 + b_k + (BNC ? r * B_STEP : 0);
-            const int64_t kc = kk < kmax ? kk : kmax;
-            const T v = BNC ? p.B[b_row[0] + kc * p.ldb] : p.B[b_row[r] * p.ldb + kc];
             const int64_t d = kk - j;
             const bool ok = ((b_valid >> (BNC ? 0 : r)) & 1u) && kk < ke && d >= bb.lo && d <= bb.hi;
-            rb[r] = ok ? v : T(0);
+            rb[r] = ok ? rb[r] : T(0);
         }
     };
-    auto store = [&](int buf) {
+    auto store = [&](int buf, int64_t k0, bool tail) {
+        // uniform per workgroup: the masks run only where a tile needs them
+        if (tail || !a_all_rows || !a_nomask) mask_a(k0);
+        if (tail || !b_all_rows || !b_nomask) mask_b(k0);
 #pragma unroll
         for (int r = 0; r < EA; r++) {
             if (AMC) As[buf][a_i][a_k + r * A_STEP] = to_lds<LP>(ra[r]);
@@ -359,20 +360,24 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
     if (nslab > 0) {
         if (nfull > 0) load_fast(kb);
         else load_tail(kb);
-        store(0);
+        store(0, kb, nfull == 0);
         __syncthreads();
         int64_t s = 0;
-        // steady state: the slab being prefetched is a full one
+        // steady state: the slab being prefetched is a full one.  The
+        // scheduling fence keeps the next slab's LDS stores (and the wait for
+        // its global loads that they imply) after this slab's products.
         for (; s + 1 < nfull; s++) {
             load_fast(kb + (s + 1) * BK);
             compute((int)(s & 1));
-            store((int)((s + 1) & 1));
+            __builtin_amdgcn_sched_barrier(0);
+            store((int)((s + 1) & 1), kb + (s + 1) * BK, false);
             __syncthreads();
         }
         if (s + 1 < nslab) {  // a ragged slab follows the last full one
             load_tail(kb + (s + 1) * BK);
             compute((int)(s & 1));
-            store((int)((s + 1) & 1));
+            __builtin_amdgcn_sched_barrier(0);
+            store((int)((s + 1) & 1), kb + (s + 1) * BK, true);
             __syncthreads();
             s++;
         }

@@ -189,9 +189,9 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
                     if (lane == 0) fail = o + f;
                     return;
                 }
-                RFP_LEAF_STAMP(16 + 3 * (o / D));
+                RFP_LEAF_STAMP(40 + 2 * (o / D));
                 inv32<T>(L, o, Wd, rdg, lane);
-                RFP_LEAF_STAMP(17 + 3 * (o / D));
+                RFP_LEAF_STAMP(41 + 2 * (o / D));
                 if (winv && lane < D) {
                     for (int r = 0; r < D; r++) winv[(o + r) * N + o + lane] = Wd[r][lane];
                 }
@@ -262,7 +262,7 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
         const int j = colmajor ? idx / N : idx % N;
         if (i < nb && j <= i) A.at(i, j) = L[i][j];
     }
-    RFP_LEAF_STAMP(13);
+    RFP_LEAF_STAMP(30);
     if (!winv) {
         __syncthreads();
         return 0;
@@ -338,7 +338,7 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
         }
     }
     __syncthreads();
-    RFP_LEAF_STAMP(14);
+    RFP_LEAF_STAMP(31);
     // W row-major into winv (zero above the diagonal, identity on padding)
     for (int idx = t; idx < N * N; idx += 256) {
         const int i = idx / N, j = idx % N;

@@ -252,36 +252,55 @@ struct Run {
         else chk(potrf_leaf<T>(ex, A, (int)order, winv, goff));
     }
 
+    // Cholesky of a diagonal block of order n <= panel width: the 2 x 2
+    // partition of Section 3 down to nb-row leaves, each leaf leaving the
+    // inverse of its factor in winv (consecutive nb x nb blocks).
+    void potrf_rec(int64_t n, Mat<T> A, int64_t goff, T* winv)
+    {
+        if (n <= 0) return;
+        if (n <= nb) {
+            leaf_potrf(n, A, goff, winv);
+            return;
+        }
+        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
+        potrf_rec(n1, A, goff, winv);
+        trsm_rlt(n2, n1, A.sub(n1, 0), A, winv);
+        mm(n2, n2, n1, T(-1), A.sub(n1, 0), TRI_NONE, A.sub(n1, 0), TRI_NONE, T(1), A.sub(n1, n1), true);
+        potrf_rec(n2, A.sub(n1, n1), goff + n1, winv + nleaves(n1, nb) * nb * nb);
+    }
+
     // Right-looking blocked Cholesky of the lower triangle of A (order n) in
-    // diagonal blocks of nb, with one step of lookahead: after the panel of
-    // step k, the critical stream updates only block column k + 1 and factors
-    // its diagonal block while the auxiliary stream applies step k's update
-    // to the rest of the trailing matrix.  Step k + 1's update of block
-    // column k + 2 waits for that bulk update (both write it).
+    // panels of pb = 2 nb columns, with one step of lookahead: after the
+    // panel of step k, the critical stream updates only panel column k + 1
+    // and factors its diagonal block while the auxiliary stream applies step
+    // k's update to the rest of the trailing matrix.  Step k + 1's update of
+    // panel column k + 2 waits for that bulk update (both write it).  Wider
+    // panels give the bulk update k = pb, where the GEMM runs faster than at
+    // k = nb, at the price of a longer diagonal chain per step.
     void potrf_la(int64_t n, Mat<T> A, int64_t goff, T* winv)
     {
         if (n <= 0) return;
-        const int64_t b = nb;
-        const int64_t K = nleaves(n, nb);
-        leaf_potrf(std::min<int64_t>(b, n), A, goff, winv);
+        const int64_t pb = 2 * nb;
+        const int64_t K = nleaves(n, pb);
+        auto winv_at = [&](int64_t o) { return winv + (o / nb) * nb * nb; };
+        potrf_rec(std::min<int64_t>(pb, n), A, goff, winv);
         hipEvent_t bulk_prev = nullptr;
         for (int64_t k = 0; k + 1 < K; k++) {
-            const int64_t o = k * b, bk = b, o1 = o + bk;
-            const int64_t b1 = std::min<int64_t>(b, n - o1), o2 = o1 + b1;
-            // panel: L(o1:, block k) = A(o1:, block k) W_k^T, in place
-            mm(n - o1, bk, bk, T(1), A.sub(o1, o), TRI_NONE, Mat<const T>{winv + k * b * b, nb, 1}, TRI_LOWER,
-               T(0), A.sub(o1, o), false, true);
+            const int64_t o = k * pb, o1 = o + pb;
+            const int64_t b1 = std::min<int64_t>(pb, n - o1), o2 = o1 + b1;
+            // panel: L(o1:, panel k) = A(o1:, panel k) L_kk^{-T}
+            trsm_rlt(n - o1, pb, A.sub(o1, o), A.sub(o, o), winv_at(o));
             hipEvent_t panel_done = record(0);
-            // lookahead: block column k + 1 (lower part of its diagonal tile), then its leaf
+            // lookahead: panel column k + 1 (lower part of its diagonal block), then that block
             wait(0, bulk_prev);
-            mm(n - o1, b1, bk, T(-1), A.sub(o1, o), TRI_NONE, A.sub(o1, o), TRI_NONE, T(1), A.sub(o1, o1), true);
-            leaf_potrf(b1, A.sub(o1, o1), goff + o1, winv + (k + 1) * b * b);
-            // bulk: columns beyond block k + 1
+            mm(n - o1, b1, pb, T(-1), A.sub(o1, o), TRI_NONE, A.sub(o1, o), TRI_NONE, T(1), A.sub(o1, o1), true);
+            potrf_rec(b1, A.sub(o1, o1), goff + o1, winv_at(o1));
+            // bulk: columns beyond panel k + 1
             bulk_prev = nullptr;
             if (o2 < n) {
                 wait(1, panel_done);
                 on_aux = two_streams();
-                mm(n - o2, n - o2, bk, T(-1), A.sub(o2, o), TRI_NONE, A.sub(o2, o), TRI_NONE, T(1), A.sub(o2, o2),
+                mm(n - o2, n - o2, pb, T(-1), A.sub(o2, o), TRI_NONE, A.sub(o2, o), TRI_NONE, T(1), A.sub(o2, o2),
                    true);
                 on_aux = false;
                 bulk_prev = record(1);

@@ -66,10 +66,10 @@ def test_pftri_plan(transr, uplo, n):
 def test_two_stream_schedule_is_checked():
     """The factorization uses the auxiliary stream; the replay's race check is
     active (a schedule without the bulk-update wait is flagged)."""
-    ops = rfp.rfp_plan("F", "N", "L", 1001)
+    n = 2001
+    ops = rfp.rfp_plan("F", "N", "L", n)
     assert any(o.stream == 1 for o in ops)
     assert any(o.kind == rfp.PLAN_WAIT for o in ops)
-    n = 1001
     A, _ = synth.spd(n, seed=9)
     arf = oracle.trttf("N", "L", A)
     # drop the waits of the critical stream: the next block column's update
@@ -114,3 +114,19 @@ def test_pftrs_plan_is_two_fused_solves():
         assert [o.tri_a for o in ops[2:]] == [0, 1]
         assert all(o.stream == 0 for o in ops)
         assert tuple(ops[2].d) == (rfp.PLAN_BUF_B, 0, 1, 1003)
+
+
+@pytest.mark.parametrize("transr,uplo", [("N", "L"), ("T", "U"), ("N", "U")])
+@pytest.mark.parametrize("n", [1100, 1537])
+def test_pftrf_plan_with_bulk_updates(transr, uplo, n):
+    """Sizes where the diagonal triangles have three or more 256-column panels,
+    so the auxiliary stream's bulk updates and the lookahead overlap: the
+    replay (race check included) matches the oracle."""
+    A, _ = synth.spd(n, seed=n + 3)
+    arf = oracle.trttf(transr, uplo, A)
+    want, _ = oracle.pftrf(transr, uplo, n, arf.copy())
+    ops = rfp.rfp_plan("F", transr, uplo, n)
+    assert any(o.stream == 1 for o in ops)
+    got = arf.copy()
+    Replayer(_bufs("F", uplo, n, got)).run(ops)
+    assert oracle.rel_fro(got, want) <= 1e-13 * n
