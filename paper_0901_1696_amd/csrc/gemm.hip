@@ -211,57 +211,59 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
     const Band ba = band_of(p.triA), bb = band_of(p.triB);
     const int64_t kmax = p.k > 0 ? p.k - 1 : 0;
     const bool a_nomask = p.triA == TRI_NONE, b_nomask = p.triB == TRI_NONE;
-    // Per-thread row pointers: rows are clamped into the operand once (a valid
-    // address even for the rows past the edge of a ragged tile, which are
-    // zeroed after the load), and the k position advances by pointer arithmetic.
-    int64_t a_row[AMC ? 1 : EA], b_row[BNC ? 1 : EB];
-    uint32_t a_valid = 0, b_valid = 0;
-#pragma unroll
-    for (int r = 0; r < (AMC ? 1 : EA); r++) {
-        const int64_t i = i0 + a_i + (AMC ? 0 : r * A_STEP);
-        a_row[r] = i < m ? i : m - 1;
-        a_valid |= (i < m ? 1u : 0u) << r;
-    }
-#pragma unroll
-    for (int r = 0; r < (BNC ? 1 : EB); r++) {
-        const int64_t j = j0 + b_j + (BNC ? 0 : r * B_STEP);
-        b_row[r] = j < n ? j : n - 1;
-        b_valid |= (j < n ? 1u : 0u) << r;
-    }
+    // Rows past the edge of a ragged tile are clamped to the last row of the
+    // operand (a valid address; the value is zeroed when the slab is stored).
+    // A column-major operand keeps one pointer per thread (its clamped row);
+    // a k-contiguous one recomputes each row's address at every load from an
+    // opaque copy of the thread's row, so that no per-row pointer (two
+    // registers each) stays live across the main loop.  With the scheduling
+    // fence between the two k groups of a slab (at most eight LDS fragments
+    // in flight), every FP64 tile fits two workgroups per CU, which the MFMA
+    // needs to hide HBM latency.
+    const int a_lim = (int)((m - 1 - i0) < (BM - 1) ? (m - 1 - i0) : (BM - 1));
+    const int b_lim = (int)((n - 1 - j0) < (BN - 1) ? (n - 1 - j0) : (BN - 1));
+    const T* a_org = AMC ? p.A + i0 + (a_i < a_lim ? a_i : a_lim) : p.A + i0 * p.lda;
+    const T* b_org = BNC ? p.B + j0 + (b_j < b_lim ? b_j : b_lim) : p.B + j0 * p.ldb;
     const bool a_all_rows = i0 + BM <= m, b_all_rows = j0 + BN <= n;
 
     T ra[EA], rb[EB];
 
-    // Loads only issue the global reads; the masks (ragged rows, triangular
-    // bands, the ragged last slab) are applied when the slab is written to
-    // LDS, after the current slab's products, so the load latency overlaps
-    // the MFMAs.  Full slab [k0, k0 + BK) inside [kb, ke): no k bounds.
+    // Element (row ai + r A_STEP or ai, k index kk) of each operand's tile.
+    auto ld_a = [&](int r, int ai, int64_t kk) -> T {
+        if constexpr (AMC) return a_org[kk * p.lda];
+        const int row = ai + r * A_STEP;
+        const int64_t i = row < a_lim ? row : a_lim;
+        return a_org[i * p.lda + kk];
+    };
+    auto ld_b = [&](int r, int bj, int64_t kk) -> T {
+        if constexpr (BNC) return b_org[kk * p.ldb];
+        const int row = bj + r * B_STEP;
+        const int64_t j = row < b_lim ? row : b_lim;
+        return b_org[j * p.ldb + kk];
+    };
+    // Full slab [k0, k0 + BK) inside [kb, ke): no k bounds.
     auto load_fast = [&](int64_t k0) {
+        int ai = a_i, ak = a_k, bj = b_j, bk = b_k;
+        asm volatile("" : "+v"(ai), "+v"(bj));
 #pragma unroll
-        for (int r = 0; r < EA; r++) {
-            const int64_t kk = k0 + a_k + (AMC ? r * A_STEP : 0);
-            ra[r] = AMC ? p.A[a_row[0] + kk * p.lda] : p.A[a_row[r] * p.lda + kk];
-        }
+        for (int r = 0; r < EA; r++) ra[r] = ld_a(r, ai, k0 + ak + (AMC ? r * A_STEP : 0));
 #pragma unroll
-        for (int r = 0; r < EB; r++) {
-            const int64_t kk = k0 + b_k + (BNC ? r * B_STEP : 0);
-            rb[r] = BNC ? p.B[b_row[0] + kk * p.ldb] : p.B[b_row[r] * p.ldb + kk];
-        }
+        for (int r = 0; r < EB; r++) rb[r] = ld_b(r, bj, k0 + bk + (BNC ? r * B_STEP : 0));
     };
     // Ragged last slab: k clamped into the operand (entries at or past ke are
     // zeroed by the store).
     auto load_tail = [&](int64_t k0) {
+        int ai = a_i, ak = a_k, bj = b_j, bk = b_k;
+        asm volatile("" : "+v"(ai), "+v"(bj));
 #pragma unroll
         for (int r = 0; r < EA; r++) {
-            const int64_t kk = k0 + a_k + (AMC ? r * A_STEP : 0);
-            const int64_t kc = kk < kmax ? kk : kmax;
-            ra[r] = AMC ? p.A[a_row[0] + kc * p.lda] : p.A[a_row[r] * p.lda + kc];
+            const int64_t kk = k0 + ak + (AMC ? r * A_STEP : 0);
+            ra[r] = ld_a(r, ai, kk < kmax ? kk : kmax);
         }
 #pragma unroll
         for (int r = 0; r < EB; r++) {
-            const int64_t kk = k0 + b_k + (BNC ? r * B_STEP : 0);
-            const int64_t kc = kk < kmax ? kk : kmax;
-            rb[r] = BNC ? p.B[b_row[0] + kc * p.ldb] : p.B[b_row[r] * p.ldb + kc];
+            const int64_t kk = k0 + bk + (BNC ? r * B_STEP : 0);
+            rb[r] = ld_b(r, bj, kk < kmax ? kk : kmax);
         }
     };
     auto mask_a = [&](int64_t k0) {
@@ -270,7 +272,7 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
             const int64_t i = i0 + a_i + (AMC ? 0 : r * A_STEP);
             const int64_t kk = k0 + a_k + (AMC ? r * A_STEP : 0);
             const int64_t d = kk - i;
-            const bool ok = ((a_valid >> (AMC ? 0 : r)) & 1u) && kk < ke && d >= ba.lo && d <= ba.hi;
+            const bool ok = i < m && kk < ke && d >= ba.lo && d <= ba.hi;
             ra[r] = ok ? ra[r] : T(0);
         }
     };
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
             const int64_t j = j0 + b_j + (BNC ? 0 : r * B_STEP);
             const int64_t kk = k0 + b_k + (BNC ? r * B_STEP : 0);
             const int64_t d = kk - j;
-            const bool ok = ((b_valid >> (BNC ? 0 : r)) & 1u) && kk < ke && d >= bb.lo && d <= bb.hi;
+            const bool ok = j < n && kk < ke && d >= bb.lo && d <= bb.hi;
             rb[r] = ok ? rb[r] : T(0);
         }
     };
@@ -351,6 +353,7 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
             for (int a = 0; a < WMB; a++)
 #pragma unroll
                 for (int b = 0; b < WNB; b++) acc[a][b] = Mfma<T>::op(af[a].y, bf[b].y, acc[a][b]);
+            __builtin_amdgcn_sched_barrier(0);
         }
         }
     };
