@@ -2,15 +2,19 @@
 // its factor, as a workgroup-level device routine (256 threads): used by the
 // leaf kernel of the blocked factorization and by the batched solver.
 //
-// The workgroup keeps the whole block in LDS (128 x 130 elements, rows
-// k-contiguous).  For each 32-column block column:
-//   1. one wavefront factors the 32 x 32 diagonal block (row per lane, the
-//      pivot column broadcast through LDS) and inverts it;
+// The workgroup keeps the lower triangle of the block in LDS, packed by
+// 16-row block rows (75.8 KB: small enough to share a CU with one workgroup
+// of the bulk-update GEMM, so that a leaf on a second stream starts as soon
+// as one GEMM workgroup retires instead of waiting for a whole CU).  For
+// each 16-column block column:
+//   1. one wavefront factors the 16 x 16 diagonal block and forms its
+//      inverse in the same register sweep (readlane broadcasts);
 //   2. all four wavefronts solve the panel below with MFMA, X = A_p W^T;
 //   3. all four wavefronts update the trailing lower triangle, A -= X X^T.
 // The factor is stored back (masked to the block's own lower triangle), then
 // W = L^{-1} is formed in place, block column by block column from the right:
-// W_RR is already inverted, so W_Rj = -(W_RR L_Rj) W_jj.
+// W_RR is already inverted, so W_Rj = -(W_RR L_Rj) W_jj (the diagonal
+// inverses wait in the output array between the two phases).
 #pragma once
 #include "rfp_common.h"
 
@@ -47,23 +51,21 @@ struct M16<float> {
 };
 
 // D: width of the block columns whose diagonal blocks are factored and
-// inverted by one wavefront (16 or 32; the sequential work per leaf grows
-// with D, the MFMA panel and trailing work does not).
-constexpr int N = 128, LP = N + 2, D = 16, DP = D + 2;
-constexpr bool TWO_HALVES = D > 16;
+// inverted by one wavefront.
+constexpr int N = 128, D = 16, DP = D + 2;
+
+// Packed lower-triangle layout: block row b (rows 16b .. 16b + 15) keeps
+// columns 0 .. 16b + 15 of each row, with a row pitch of 16b + 18 elements
+// (the padding shifts consecutive rows by 4 or 36 banks, so the 16 rows that
+// feed one MFMA operand hit distinct banks).  prow(i) is the offset of row i.
+__device__ __forceinline__ int prow(int i)
+{
+    const int b = i >> 4;
+    return 128 * b * b + 160 * b + (i & 15) * (16 * b + 18);
+}
+constexpr int NPACK = 128 * 8 * 8 + 160 * 8;  // prow(N): 9472 elements
 
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
-
-// acc(16 x 16) += sum_k X(xr + i, xk + k) * Y(yr + j, yk + k), k < K (multiple of 4),
-// X and Y rows k-contiguous in LDS with pitch P.  Lane l supplies k = kk + l/16.
-template <typename T, int P>
-__device__ __forceinline__ void mma_rows(typename M16<T>::acc& acc, const T (*X)[P], int xr, int xk,
-                                         const T (*Y)[P], int yr, int yk, int K, int lane)
-{
-    const int r = lane & 15, g = lane >> 4;
-    for (int kk = 0; kk < K; kk += 4)
-        acc = M16<T>::op(X[xr + r][xk + kk + g], Y[yr + r][yk + kk + g], acc);
-}
 
 // Broadcast of lane l's value to the whole wavefront (l uniform).
 __device__ __forceinline__ double bcast(double v, int l)
@@ -77,69 +79,101 @@ __device__ __forceinline__ float bcast(float v, int l)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// Cholesky of the 32 x 32 diagonal block at (o, o) of the LDS matrix by one
-// wavefront, right-looking in registers: lane i < 32 holds row i; at column
-// j the pivot and the column entries l_cj are broadcast from their lanes
-// (readlane), l_jj = sqrt(a_jj), l_ij = a_ij / l_jj, and every row updates
-// a_ic -= l_ij l_cj for c > j.  Entries above the diagonal are never read.
-// Returns 0, or j + 1 for the first pivot that is not positive (uniform);
-// on success the factor is stored back to LDS.
+// 1 / sqrt(d) and sqrt(d) of a positive pivot: the hardware reciprocal
+// square root estimate refined by two coupled Newton (Goldschmidt) steps on
+// g ~ sqrt(d) and h ~ 1 / (2 sqrt(d)) (each squares the relative error), then
+// one residual correction of the root; both results come out within about
+// one unit in the last place.  Pivots too small for the hardware estimate
+// take the library routines.
+__device__ __forceinline__ void rsqrt_sqrt(double d, double& rl, double& l)
+{
+    if (d < 1e-280) {
+        l = sqrt(d);
+        rl = 1.0 / l;
+        return;
+    }
+    const double y = __builtin_amdgcn_rsq(d);
+    double g = d * y, h = 0.5 * y;
+#pragma unroll
+    for (int it = 0; it < 2; it++) {
+        const double r = __builtin_fma(-g, h, 0.5);
+        g = __builtin_fma(g, r, g);
+        h = __builtin_fma(h, r, h);
+    }
+    const double e = __builtin_fma(-g, g, d);
+    l = __builtin_fma(e, h, g);
+    rl = 2.0 * h;
+}
+__device__ __forceinline__ void rsqrt_sqrt(float d, float& rl, float& l)
+{
+    if (d < 1e-30f) {
+        l = sqrtf(d);
+        rl = 1.0f / l;
+        return;
+    }
+    const float y = __builtin_amdgcn_rsqf(d);
+    const float h = 0.5f * y, g = d * y;
+    const float r = __builtin_fmaf(-g, h, 0.5f);
+    rl = 2.0f * __builtin_fmaf(h, r, h);
+    l = __builtin_fmaf(g, r, g);
+}
+
+// Cholesky factor and its inverse of the D x D diagonal block at (o, o) of
+// the LDS matrix, by one wavefront in registers, both right-looking.  Lane
+// i < D holds row i of the block (a), and lane c < D the running column c of
+// W = L^{-1} (s).  At column j: the pivot a_jj is broadcast (readlane),
+// l_jj = sqrt(a_jj), the column becomes l_ij = a_ij / l_jj; row j of W is
+// final, W(j, c) = s_j / l_jj; then every later row c takes the broadcast
+// l_cj = L(c, j) into both recurrences, a_ck -= l_cj l_kj for the factor and
+// s_c -= L(c, j) W(j, .) for the inverse (forward substitution of L W = I,
+// accumulated as the columns of L appear).  Entries above the diagonal are
+// never read.  Returns 0, or j + 1 for the first pivot that is not positive
+// (uniform; nothing is stored then).  On success the factor goes back to L
+// and the inverse to Wd (row-major, zero above the diagonal).
 template <typename T>
-__device__ __forceinline__ int chol32(T (*L)[LP], int o, int lane)
+__device__ __forceinline__ int chol_inv(T* L, int o, T (*Wd)[DP], int lane)
 {
     const int i = lane;
-    T a[D];
-#pragma unroll
-    for (int j = 0; j < D; j++) a[j] = (i < D && j <= i) ? L[o + i][o + j] : T(0);
+    T a[D], s[D];
 #pragma unroll
     for (int j = 0; j < D; j++) {
-        const T d = bcast(a[j], j);
-        if (!(d > T(0))) return j + 1;
-        const T l = sqrt(d), rl = T(1) / l;
-        a[j] = (i == j) ? l : a[j] * rl;
-#pragma unroll
-        for (int c = j + 1; c < D; c++) a[c] -= a[j] * bcast(a[j], c);
+        a[j] = (i < D && j <= i) ? L[prow(o + i) + o + j] : T(0);
+        s[j] = (j == i) ? T(1) : T(0);
     }
+    int fail = 0;
 #pragma unroll
-    for (int j = 0; j < D; j++)
-        if (i < D && j <= i) L[o + i][o + j] = a[j];
+    for (int j = 0; j < D; j++) {
+        T d = bcast(a[j], j);
+        if (!(d > T(0)) && !fail) fail = j + 1;
+        if (fail) d = T(1);  // keep the remaining steps finite; the result is discarded
+        T rl, l;
+        rsqrt_sqrt(d, rl, l);
+        a[j] = (i == j) ? l : a[j] * rl;
+        const T wj = (j >= i) ? s[j] * rl : T(0);
+        s[j] = wj;
+#pragma unroll
+        for (int c = j + 1; c < D; c++) {
+            const T lcj = bcast(a[j], c);
+            a[c] -= a[j] * lcj;
+            s[c] -= lcj * wj;
+        }
+    }
+    if (fail) return fail;
+    if (i < D) {
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            if (j <= i) L[prow(o + i) + o + j] = a[j];
+            Wd[j][i] = s[j];
+        }
+    }
     wave_sync();
     return 0;
 }
 
-// Inverse of the lower-triangular 32 x 32 block at (o, o): lane c < 32 forms
-// column c by forward substitution in registers, W(r, c) = (delta_rc -
-// sum_{q<r} L(r, q) W(q, c)) / L(r, r), with each L(r, q) broadcast from
-// lane r's copy of row r; the result goes to Wd (row-major, zero above the
-// diagonal).  rdg is unused (kept for the call signature).
-template <typename T>
-__device__ __forceinline__ void inv32(T (*L)[LP], int o, T (*Wd)[DP], T* rdg, int lane)
-{
-    (void)rdg;
-    const int c = lane;
-    T a[D], w[D];
-#pragma unroll
-    for (int j = 0; j < D; j++) a[j] = (c < D && j <= c) ? L[o + c][o + j] : T(0);
-#pragma unroll
-    for (int r = 0; r < D; r++) {
-        T s = (r == c) ? T(1) : T(0);
-#pragma unroll
-        for (int q = 0; q < r; q++) s -= bcast(a[q], r) * w[q];
-        const T rr = T(1) / bcast(a[r], r);
-        w[r] = (r >= c) ? s * rr : T(0);
-    }
-    if (c < D) {
-#pragma unroll
-        for (int r = 0; r < D; r++) Wd[r][c] = w[r];
-    }
-    wave_sync();
-}
-
 template <typename T>
 struct Leaf128Smem {
-    __attribute__((aligned(16))) T L[N][LP];
-    __attribute__((aligned(16))) T Wd[D][DP];
-    T rdg[D];
+    __attribute__((aligned(16))) T L[NPACK];
+    __attribute__((aligned(16))) T Wd[D][DP];  // inverse of the current diagonal block
     int fail;
 };
 
@@ -154,22 +188,26 @@ struct Leaf128Smem {
 template <typename T>
 __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int* info, int64_t info_base)
 {
-    T(&L)[N][LP] = sm.L;
+    T* L = sm.L;
     T(&Wd)[D][DP] = sm.Wd;  // Wd[r][c] = (L_jj^{-1})(r, c)
-    T* rdg = sm.rdg;
     int& fail = sm.fail;
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int r = lane & 15, g = lane >> 4;  // MFMA operand row and k offset of the lane
     if (t == 0) fail = 0;
     const bool colmajor = A.rs == 1;
+    // the packed triangle (and the rest of each diagonal block, as zeros);
+    // rows past nb are the identity
 #pragma unroll 16
     for (int it = 0; it < N * N / 256; it++) {
         const int idx = t + it * 256;
         const int i = colmajor ? idx % N : idx / N;
         const int j = colmajor ? idx / N : idx % N;
-        T v = (i == j) ? T(1) : T(0);
-        if (i < nb && j <= i) v = A.at(i, j);
-        L[i][j] = v;
+        if (j < 16 * ((i >> 4) + 1)) {
+            T v = (i == j) ? T(1) : T(0);
+            if (i < nb && j <= i) v = A.at(i, j);
+            L[prow(i) + j] = v;
+        }
     }
     __syncthreads();
     RFP_LEAF_STAMP(0);
@@ -177,34 +215,21 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
     const int nblk = (nb + D - 1) / D;
     typedef typename M16<T>::acc acc_t;
 
-    // factor the 32 x 32 diagonal block at offset o (wavefront 0) and leave
-    // its inverse in Wd; a failing pivot is recorded in `fail`
-    // (the inverse of each diagonal block is also parked in its final place in
-    // winv, where the inversion phase picks it up again)
-    auto diag = [&](int o, bool factor) {
-        if (factor) {
-            if (w == 0) {
-                const int f = chol32<T>(L, o, lane);
-                if (f) {
-                    if (lane == 0) fail = o + f;
-                    return;
-                }
-                RFP_LEAF_STAMP(40 + 2 * (o / D));
-                inv32<T>(L, o, Wd, rdg, lane);
-                RFP_LEAF_STAMP(41 + 2 * (o / D));
-                if (winv && lane < D) {
-                    for (int r = 0; r < D; r++) winv[(o + r) * N + o + lane] = Wd[r][lane];
-                }
-            }
-        } else {
-            for (int idx = t; idx < D * D; idx += 256) Wd[idx / D][idx % D] = winv[(o + idx / D) * N + o + idx % D];
-        }
-    };
-
     // ---------------------------------------------------------------- factor
     for (int kb = 0; kb < nblk; kb++) {
         const int o = kb * D;
-        diag(o, true);
+        // wavefront 0 factors and inverts the diagonal block (a failing pivot
+        // is recorded in `fail`); the inverse is parked in its final place in
+        // winv, where the inversion phase picks it up again
+        if (w == 0) {
+            const int f = chol_inv<T>(L, o, Wd, lane);
+            if (f) {
+                if (lane == 0) fail = o + f;
+            } else if (winv && lane < D) {
+                for (int q = 0; q < D; q++) winv[(o + q) * N + o + lane] = Wd[q][lane];
+            }
+            RFP_LEAF_STAMP(40 + 2 * kb);
+        }
         __syncthreads();
         RFP_LEAF_STAMP(1 + 3 * kb);
         if (fail) break;
@@ -212,23 +237,12 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
         // panel: X(i, c) = sum_k L(i, o + k) W(c, k), i.e. X = A_p W^T; a wave
         // owns whole row blocks, so reading and overwriting them is race-free
         for (int rb = w; rb < nrb; rb += 4) {
-            acc_t x0 = acc_t{0, 0, 0, 0}, x1 = acc_t{0, 0, 0, 0};
-            (void)x1;
-            {
-                const int r = lane & 15, g = lane >> 4;
+            acc_t x0 = acc_t{0, 0, 0, 0};
+            const T* Lr = L + prow(r0 + rb * 16 + r) + o;
 #pragma unroll
-                for (int kk = 0; kk < D; kk += 4) {
-                    const T av = L[r0 + rb * 16 + r][o + kk + g];
-                    x0 = M16<T>::op(av, Wd[r][kk + g], x0);
-                    if constexpr (TWO_HALVES) x1 = M16<T>::op(av, Wd[16 + r][kk + g], x1);
-                }
-            }
+            for (int kk = 0; kk < D; kk += 4) x0 = M16<T>::op(Lr[kk + g], Wd[r][kk + g], x0);
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const int i = r0 + rb * 16 + M16<T>::row(lane, q);
-                L[i][o + (lane & 15)] = x0[q];
-                if constexpr (TWO_HALVES) L[i][o + 16 + (lane & 15)] = x1[q];
-            }
+            for (int q = 0; q < 4; q++) L[prow(r0 + rb * 16 + M16<T>::row(lane, q)) + o + r] = x0[q];
         }
         __syncthreads();
         RFP_LEAF_STAMP(2 + 3 * kb);
@@ -239,11 +253,14 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
             while ((bi + 1) * (bi + 2) / 2 <= b) bi++;
             const int bj = b - bi * (bi + 1) / 2;
             acc_t s = acc_t{0, 0, 0, 0};
-            mma_rows<T, LP>(s, L, r0 + bi * 16, o, L, r0 + bj * 16, o, D, lane);
+            const T* X = L + prow(r0 + bi * 16 + r) + o;
+            const T* Y = L + prow(r0 + bj * 16 + r) + o;
+#pragma unroll
+            for (int kk = 0; kk < D; kk += 4) s = M16<T>::op(X[kk + g], Y[kk + g], s);
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                const int i = bi * 16 + M16<T>::row(lane, q), j = bj * 16 + (lane & 15);
-                if (i >= j) L[r0 + i][r0 + j] -= s[q];
+                const int i = bi * 16 + M16<T>::row(lane, q), j = bj * 16 + r;
+                if (i >= j) L[prow(r0 + i) + r0 + j] -= s[q];
             }
         }
         __syncthreads();
@@ -260,7 +277,7 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
     for (int idx = t; idx < N * N; idx += 256) {
         const int i = colmajor ? idx % N : idx / N;
         const int j = colmajor ? idx / N : idx % N;
-        if (i < nb && j <= i) A.at(i, j) = L[i][j];
+        if (i < nb && j <= i) A.at(i, j) = L[prow(i) + j];
     }
     RFP_LEAF_STAMP(30);
     if (!winv) {
@@ -272,26 +289,21 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
     for (int kb = nblk - 1; kb >= 0; kb--) {
         const int o = kb * D;
         __syncthreads();
-        diag(o, false);  // Wd = L_jj^{-1}, as parked in winv by the factor phase
+        for (int idx = t; idx < D * D; idx += 256) Wd[idx / D][idx % D] = winv[(o + idx / D) * N + o + idx % D];
         __syncthreads();
         const int r0 = o + D, nrb = (N - r0) / 16;
         // T = W_RR L_Rj  (W_RR already in place, lower triangular).  A wave owns
         // the row blocks w and w + 4 (at most seven row blocks exist).
-        acc_t tacc[2][2];
+        acc_t tacc[2];
 #pragma unroll
         for (int q2 = 0; q2 < 2; q2++) {
             const int rb = w + 4 * q2;
-            tacc[q2][0] = acc_t{0, 0, 0, 0};
-            tacc[q2][1] = acc_t{0, 0, 0, 0};
+            tacc[q2] = acc_t{0, 0, 0, 0};
             if (rb < nrb) {
-                const int r = lane & 15, g = lane >> 4;
+                const T* Xr = L + prow(r0 + rb * 16 + r) + r0;
                 const int kend = (rb + 1) * 16;  // W_RR(i, k) = 0 for k > i
-                for (int kk = 0; kk < kend; kk += 4) {
-                    const T av = L[r0 + rb * 16 + r][r0 + kk + g];
-                    tacc[q2][0] = M16<T>::op(av, L[r0 + kk + g][o + r], tacc[q2][0]);
-                    if constexpr (TWO_HALVES)
-                        tacc[q2][1] = M16<T>::op(av, L[r0 + kk + g][o + 16 + r], tacc[q2][1]);
-                }
+                for (int kk = 0; kk < kend; kk += 4)
+                    tacc[q2] = M16<T>::op(Xr[kk + g], L[prow(r0 + kk + g) + o + r], tacc[q2]);
             }
         }
         __syncthreads();  // every wave has read L_Rj
@@ -300,11 +312,7 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
             const int rb = w + 4 * q2;
             if (rb < nrb) {
 #pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int i = r0 + rb * 16 + M16<T>::row(lane, q);
-                    L[i][o + (lane & 15)] = tacc[q2][0][q];
-                    if constexpr (TWO_HALVES) L[i][o + 16 + (lane & 15)] = tacc[q2][1][q];
-                }
+                for (int q = 0; q < 4; q++) L[prow(r0 + rb * 16 + M16<T>::row(lane, q)) + o + r] = tacc[q2][q];
             }
         }
         // W_Rj = -T W_jj, in place on the wave's own rows
@@ -312,29 +320,21 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
         for (int q2 = 0; q2 < 2; q2++) {
             const int rb = w + 4 * q2;
             if (rb < nrb) {
-                acc_t y0 = acc_t{0, 0, 0, 0}, y1 = acc_t{0, 0, 0, 0};
-                const int r = lane & 15, g = lane >> 4;
+                acc_t y0 = acc_t{0, 0, 0, 0};
+                const T* Lr = L + prow(r0 + rb * 16 + r) + o;
                 wave_sync();
 #pragma unroll
-                for (int kk = 0; kk < D; kk += 4) {
-                    const T av = L[r0 + rb * 16 + r][o + kk + g];
-                    y0 = M16<T>::op(av, Wd[kk + g][r], y0);
-                    if constexpr (TWO_HALVES) y1 = M16<T>::op(av, Wd[kk + g][16 + r], y1);
-                }
+                for (int kk = 0; kk < D; kk += 4) y0 = M16<T>::op(Lr[kk + g], Wd[kk + g][r], y0);
                 wave_sync();
 #pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    const int i = r0 + rb * 16 + M16<T>::row(lane, q);
-                    L[i][o + (lane & 15)] = -y0[q];
-                    if constexpr (TWO_HALVES) L[i][o + 16 + (lane & 15)] = -y1[q];
-                }
+                for (int q = 0; q < 4; q++) L[prow(r0 + rb * 16 + M16<T>::row(lane, q)) + o + r] = -y0[q];
             }
         }
         // the diagonal block becomes its inverse
         if (w == 0 && lane < D) {
 #pragma unroll
-            for (int r = 0; r < D; r++)
-                if (r >= lane) L[o + r][o + lane] = Wd[r][lane];
+            for (int q = 0; q < D; q++)
+                if (q >= lane) L[prow(o + q) + o + lane] = Wd[q][lane];
         }
     }
     __syncthreads();
@@ -342,11 +342,10 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
     // W row-major into winv (zero above the diagonal, identity on padding)
     for (int idx = t; idx < N * N; idx += 256) {
         const int i = idx / N, j = idx % N;
-        winv[idx] = (j <= i) ? L[i][j] : T(0);
+        winv[idx] = (j <= i) ? L[prow(i) + j] : T(0);
     }
     __syncthreads();
     return 0;
 }
-
 
 }  // namespace rfp
