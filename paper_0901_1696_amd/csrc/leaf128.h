@@ -7,10 +7,12 @@
 // of the bulk-update GEMM, so that a leaf on a second stream starts as soon
 // as one GEMM workgroup retires instead of waiting for a whole CU).  For
 // each 16-column block column:
-//   1. one wavefront factors the 16 x 16 diagonal block and forms its
-//      inverse in the same register sweep (readlane broadcasts);
+//   1. one wavefront factors the 16 x 16 diagonal block (left-looking, rows
+//      in lanes) and inverts it (columns in lanes);
 //   2. all four wavefronts solve the panel below with MFMA, X = A_p W^T;
-//   3. all four wavefronts update the trailing lower triangle, A -= X X^T.
+//   3. the trailing lower triangle is updated, A -= X X^T: block column k + 1
+//      at once by all four wavefronts, the columns beyond it by wavefronts
+//      1-3 while wavefront 0 factors diagonal block k + 1.
 // The factor is stored back (masked to the block's own lower triangle), then
 // W = L^{-1} is formed in place, block column by block column from the right:
 // W_RR is already inverted, so W_Rj = -(W_RR L_Rj) W_jj (the diagonal
@@ -119,52 +121,80 @@ __device__ __forceinline__ void rsqrt_sqrt(float d, float& rl, float& l)
 }
 
 // Cholesky factor and its inverse of the D x D diagonal block at (o, o) of
-// the LDS matrix, by one wavefront in registers, both right-looking.  Lane
-// i < D holds row i of the block (a), and lane c < D the running column c of
-// W = L^{-1} (s).  At column j: the pivot a_jj is broadcast (readlane),
-// l_jj = sqrt(a_jj), the column becomes l_ij = a_ij / l_jj; row j of W is
-// final, W(j, c) = s_j / l_jj; then every later row c takes the broadcast
-// l_cj = L(c, j) into both recurrences, a_ck -= l_cj l_kj for the factor and
-// s_c -= L(c, j) W(j, .) for the inverse (forward substitution of L W = I,
-// accumulated as the columns of L appear).  Entries above the diagonal are
-// never read.  Returns 0, or j + 1 for the first pivot that is not positive
-// (uniform; nothing is stored then).  On success the factor goes back to L
-// and the inverse to Wd (row-major, zero above the diagonal).
+// the packed LDS matrix, by one wavefront (lane i = lane % 16 works on row i;
+// lanes 16..63 repeat lanes 0..15 and store nothing).
+//
+// Factor, left-looking: at column j every row forms
+//   t_i = a_ij - sum_{q<j} l_iq l_jq
+// from its own earlier entries l_iq (registers) and row j of L, which lane j
+// has written to LDS column by column (broadcast reads, issued ahead of
+// need); only the newest entry l_{j,j-1} comes by readlane from lane j, so
+// the step-to-step chain is that product, the pivot broadcast t_j and the
+// refined reciprocal square root: l_jj = sqrt(t_j), l_ij = t_i / l_jj.
+//
+// Inverse W = L^{-1}, by columns: lane c forms column c by forward
+// substitution, W(r, c) = (delta_rc - sum_{q<r} L(r, q) W(q, c)) / l_rr, with
+// L(r, q) read from LDS (broadcast) and 1 / l_rr kept from the factor.
+//
+// Entries above the diagonal are never read.  Returns 0, or j + 1 for the
+// first pivot that is not positive (uniform; the block is left partly
+// written then).  On success the factor is in L and the inverse in Wd
+// (row-major, zero above the diagonal).
 template <typename T>
 __device__ __forceinline__ int chol_inv(T* L, int o, T (*Wd)[DP], int lane)
 {
-    const int i = lane;
-    T a[D], s[D];
+    const int i = lane & 15;
+    const bool owner = lane < 16;
+    T* Lrow = L + prow(o + i) + o;  // row i of the block
+    T a[D], rl[D];
 #pragma unroll
-    for (int j = 0; j < D; j++) {
-        a[j] = (i < D && j <= i) ? L[prow(o + i) + o + j] : T(0);
-        s[j] = (j == i) ? T(1) : T(0);
-    }
+    for (int j = 0; j < D; j++) a[j] = (j <= i) ? Lrow[j] : T(0);
     int fail = 0;
+    // part = a_ij - sum_{q<j-1} l_iq l_jq, formed one column ahead (its
+    // operands are final one step early), so that it overlaps the previous
+    // pivot
+    T part = a[0];
 #pragma unroll
     for (int j = 0; j < D; j++) {
-        T d = bcast(a[j], j);
-        if (!(d > T(0)) && !fail) fail = j + 1;
-        if (fail) d = T(1);  // keep the remaining steps finite; the result is discarded
-        T rl, l;
-        rsqrt_sqrt(d, rl, l);
-        a[j] = (i == j) ? l : a[j] * rl;
-        const T wj = (j >= i) ? s[j] * rl : T(0);
-        s[j] = wj;
-#pragma unroll
-        for (int c = j + 1; c < D; c++) {
-            const T lcj = bcast(a[j], c);
-            a[c] -= a[j] * lcj;
-            s[c] -= lcj * wj;
+        // the pivot lane finishes its own t with its own l_{j,j-1}; the other
+        // rows need that entry by broadcast, off the pivot's chain
+        T d, t;
+        if (j > 0) {
+            d = bcast(part - a[j - 1] * a[j - 1], j);
+            t = part - a[j - 1] * bcast(a[j - 1], j);
+        } else {
+            d = bcast(part, 0);
+            t = part;
         }
+        if (!(d > T(0)) && !fail) fail = j + 1;  // a failed block is discarded
+        T nxt = T(0);
+        if (j + 1 < D) {
+            const T* Ln = L + prow(o + j + 1) + o;
+            nxt = a[j + 1];
+#pragma unroll
+            for (int q = 0; q < j; q++) nxt -= a[q] * Ln[q];
+        }
+        T r, l;
+        rsqrt_sqrt(d, r, l);
+        rl[j] = r;
+        a[j] = (i == j) ? l : t * r;  // rows above j: unused values, never stored
+        if (owner && i >= j) Lrow[j] = a[j];
+        part = nxt;
     }
     if (fail) return fail;
-    if (i < D) {
+    // inverse, column c = i
+    T w[D];
 #pragma unroll
-        for (int j = 0; j < D; j++) {
-            if (j <= i) L[prow(o + i) + o + j] = a[j];
-            Wd[j][i] = s[j];
-        }
+    for (int rr = 0; rr < D; rr++) {
+        const T* Lr = L + prow(o + rr) + o;
+        T s = (rr == i) ? T(1) : T(0);
+#pragma unroll
+        for (int q = 0; q < rr; q++) s -= Lr[q] * w[q];
+        w[rr] = (rr >= i) ? s * rl[rr] : T(0);
+    }
+    if (owner) {
+#pragma unroll
+        for (int rr = 0; rr < D; rr++) Wd[rr][i] = w[rr];
     }
     wave_sync();
     return 0;
@@ -215,13 +245,34 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
     const int nblk = (nb + D - 1) / D;
     typedef typename M16<T>::acc acc_t;
 
+    // Trailing update of step k, A -= X X^T over the 16 x 16 blocks (bi, bj),
+    // bi >= bj, of the lower triangle below diagonal block k (indices
+    // relative to block k + 1).  It is split by block column: column bj = 0
+    // (the next diagonal block and the panel below it) is needed at once;
+    // the columns bj >= 1 only one step later, so they are applied by
+    // wavefronts 1-3 while wavefront 0 factors the next diagonal block.  Each
+    // element still receives the updates of steps 0, 1, ... in order.
+    auto update_block = [&](int o, int bi, int bj) {
+        const int r0 = o + D;
+        acc_t s = acc_t{0, 0, 0, 0};
+        const T* X = L + prow(r0 + bi * 16 + r) + o;
+        const T* Y = L + prow(r0 + bj * 16 + r) + o;
+#pragma unroll
+        for (int kk = 0; kk < D; kk += 4) s = M16<T>::op(X[kk + g], Y[kk + g], s);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int i = bi * 16 + M16<T>::row(lane, q), j = bj * 16 + r;
+            if (i >= j) L[prow(r0 + i) + r0 + j] -= s[q];
+        }
+    };
+
     // ---------------------------------------------------------------- factor
     for (int kb = 0; kb < nblk; kb++) {
         const int o = kb * D;
-        // wavefront 0 factors and inverts the diagonal block (a failing pivot
-        // is recorded in `fail`); the inverse is parked in its final place in
-        // winv, where the inversion phase picks it up again
         if (w == 0) {
+            // wavefront 0 factors and inverts the diagonal block (a failing
+            // pivot is recorded in `fail`); the inverse is parked in its final
+            // place in winv, where the inversion phase picks it up again
             const int f = chol_inv<T>(L, o, Wd, lane);
             if (f) {
                 if (lane == 0) fail = o + f;
@@ -229,6 +280,17 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
                 for (int q = 0; q < D; q++) winv[(o + q) * N + o + lane] = Wd[q][lane];
             }
             RFP_LEAF_STAMP(40 + 2 * kb);
+        } else if (kb > 0) {
+            // the rest of step kb - 1's update: block columns bj >= 1 (the
+            // columns beyond diagonal block kb), as a triangle of
+            // (nrb - 1) x (nrb - 1) blocks
+            const int op = o - D, nrb = (N - o) / 16, cnt = nrb * (nrb - 1) / 2;
+            for (int b = w - 1; b < cnt; b += 3) {
+                int bi = 0;
+                while ((bi + 1) * (bi + 2) / 2 <= b) bi++;
+                const int bj = b - bi * (bi + 1) / 2;
+                update_block(op, bi + 1, bj + 1);
+            }
         }
         __syncthreads();
         RFP_LEAF_STAMP(1 + 3 * kb);
@@ -246,23 +308,9 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
         }
         __syncthreads();
         RFP_LEAF_STAMP(2 + 3 * kb);
-        // trailing update of the lower triangle of 16 x 16 blocks below/right
-        const int nt = nrb * (nrb + 1) / 2;
-        for (int b = w; b < nt; b += 4) {
-            int bi = 0;
-            while ((bi + 1) * (bi + 2) / 2 <= b) bi++;
-            const int bj = b - bi * (bi + 1) / 2;
-            acc_t s = acc_t{0, 0, 0, 0};
-            const T* X = L + prow(r0 + bi * 16 + r) + o;
-            const T* Y = L + prow(r0 + bj * 16 + r) + o;
-#pragma unroll
-            for (int kk = 0; kk < D; kk += 4) s = M16<T>::op(X[kk + g], Y[kk + g], s);
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const int i = bi * 16 + M16<T>::row(lane, q), j = bj * 16 + r;
-                if (i >= j) L[prow(r0 + i) + r0 + j] -= s[q];
-            }
-        }
+        // step kb's update of block column 0 (the next diagonal block and the
+        // blocks below it)
+        for (int bi = w; bi < nrb; bi += 4) update_block(o, bi, 0);
         __syncthreads();
         RFP_LEAF_STAMP(3 + 3 * kb);
     }
