@@ -334,48 +334,44 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
     }
 
     // --------------------------------------------------------------- inverse
+    // Step kb (right to left): T = W_RR L_Rj, then W_Rj = -T W_jj.  T is
+    // formed transposed (operands swapped), which leaves each lane holding
+    // T(lane % 16, kappa_q) with kappa_q the accumulator row index of
+    // register q: exactly the A operand of the second product when its B
+    // operand is read at the same kappa_q, so T never goes through LDS.  The
+    // parked W_jj is fetched one step ahead (one element per thread).  Row
+    // blocks per wave: {w, 6 - w} for w < 3, {3} for wave 3 (at most seven).
+    T wnext = nblk > 0 ? winv[((nblk - 1) * D + t / 16) * N + (nblk - 1) * D + t % 16] : T(0);
     for (int kb = nblk - 1; kb >= 0; kb--) {
         const int o = kb * D;
-        __syncthreads();
-        for (int idx = t; idx < D * D; idx += 256) Wd[idx / D][idx % D] = winv[(o + idx / D) * N + o + idx % D];
-        __syncthreads();
+        __syncthreads();  // the previous step is done with Wd and with L
+        Wd[t / 16][t % 16] = wnext;
+        if (kb > 0) wnext = winv[(o - D + t / 16) * N + o - D + t % 16];
         const int r0 = o + D, nrb = (N - r0) / 16;
-        // T = W_RR L_Rj  (W_RR already in place, lower triangular).  A wave owns
-        // the row blocks w and w + 4 (at most seven row blocks exist).
+        const int rbs[2] = {w, w < 3 ? 6 - w : 7};
         acc_t tacc[2];
 #pragma unroll
         for (int q2 = 0; q2 < 2; q2++) {
-            const int rb = w + 4 * q2;
+            const int rb = rbs[q2];
             tacc[q2] = acc_t{0, 0, 0, 0};
             if (rb < nrb) {
-                const T* Xr = L + prow(r0 + rb * 16 + r) + r0;
-                const int kend = (rb + 1) * 16;  // W_RR(i, k) = 0 for k > i
+                const T* Wr = L + prow(r0 + rb * 16 + r) + r0;  // W_RR, row r of block rb
+                const int kend = (rb + 1) * 16;                 // W_RR(i, k) = 0 for k > i
+#pragma unroll 4
                 for (int kk = 0; kk < kend; kk += 4)
-                    tacc[q2] = M16<T>::op(Xr[kk + g], L[prow(r0 + kk + g) + o + r], tacc[q2]);
+                    tacc[q2] = M16<T>::op(L[prow(r0 + kk + g) + o + r], Wr[kk + g], tacc[q2]);
             }
         }
-        __syncthreads();  // every wave has read L_Rj
+        __syncthreads();  // every wave has read L_Rj; W_jj is in Wd
 #pragma unroll
         for (int q2 = 0; q2 < 2; q2++) {
-            const int rb = w + 4 * q2;
+            const int rb = rbs[q2];
             if (rb < nrb) {
+                acc_t y = acc_t{0, 0, 0, 0};
 #pragma unroll
-                for (int q = 0; q < 4; q++) L[prow(r0 + rb * 16 + M16<T>::row(lane, q)) + o + r] = tacc[q2][q];
-            }
-        }
-        // W_Rj = -T W_jj, in place on the wave's own rows
+                for (int q = 0; q < 4; q++) y = M16<T>::op(tacc[q2][q], Wd[M16<T>::row(lane, q)][r], y);
 #pragma unroll
-        for (int q2 = 0; q2 < 2; q2++) {
-            const int rb = w + 4 * q2;
-            if (rb < nrb) {
-                acc_t y0 = acc_t{0, 0, 0, 0};
-                const T* Lr = L + prow(r0 + rb * 16 + r) + o;
-                wave_sync();
-#pragma unroll
-                for (int kk = 0; kk < D; kk += 4) y0 = M16<T>::op(Lr[kk + g], Wd[kk + g][r], y0);
-                wave_sync();
-#pragma unroll
-                for (int q = 0; q < 4; q++) L[prow(r0 + rb * 16 + M16<T>::row(lane, q)) + o + r] = -y0[q];
+                for (int q = 0; q < 4; q++) L[prow(r0 + rb * 16 + M16<T>::row(lane, q)) + o + r] = -y[q];
             }
         }
         // the diagonal block becomes its inverse

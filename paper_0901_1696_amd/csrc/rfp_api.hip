@@ -112,7 +112,9 @@ struct rfp_context {
     size_t inv_bytes;
     rfp::Profiler* prof;
     hipStream_t aux;      // second stream for the lookahead factorization (default priority)
-    hipEvent_t ev[64];    // ring of ordering events between the two streams
+    hipStream_t aux2;     // third stream: the off-diagonal solve overlapped with the first factor
+    hipEvent_t ev[64];    // ring of ordering events between the streams
+    hipEvent_t join;      // end of the third stream's work (waited much later than recorded)
     int nev, evi;
     int* flags;           // ready flags of the fused triangular solves
     size_t flags_bytes;
@@ -155,9 +157,11 @@ template <typename T>
 struct Run {
     Exec ex;             // the caller's stream: the critical path
     Exec ex2;            // auxiliary stream (bulk trailing updates), when available
+    Exec ex3;            // second auxiliary stream (no split-K), when available
     hipEvent_t* evs = nullptr;
     int nev = 0, *evi = nullptr;
-    bool on_aux = false;  // route the next GEMMs to ex2
+    hipEvent_t joinev = nullptr;
+    int on = 0;  // stream of the next GEMMs: 0 ex, 1 ex2, 2 ex3
     hipError_t err = hipSuccess;
     PlanRec* rec = nullptr;
     int nb = NB;  // leaf order of this call's recursion
@@ -185,7 +189,7 @@ struct Run {
             if (rfp_plan_op* o = next(RFP_PLAN_GEMM)) {
                 o->m = m; o->n = n; o->k = k;
                 o->inplace = inplace ? 1 : 0;
-                o->stream = on_aux ? 1 : 0;
+                o->stream = on;
                 o->alpha = (double)alpha; o->beta = (double)beta;
                 o->tri_a = ta; o->tri_b = tb; o->c_lower = lower ? 1 : 0;
                 plan_view(A.p, A.rs, A.cs, sizeof(T), o->a);
@@ -194,26 +198,38 @@ struct Run {
             }
             return;
         }
-        chk(gemm<T>(on_aux ? ex2 : ex, m, n, k, alpha, A, ta, B, tb, beta, C, lower, inplace));
+        chk(gemm<T>(on == 1 ? ex2 : on == 2 ? ex3 : ex, m, n, k, alpha, A, ta, B, tb, beta, C, lower, inplace));
     }
-    // Stream ordering.  Stream 0 is the caller's, stream 1 the auxiliary one.
-    // While recording a plan the two streams are virtual and every record and
-    // wait is logged, so the host replay can check the schedule for races.
+    // Stream ordering.  Stream 0 is the caller's, streams 1 and 2 the
+    // auxiliary ones.  While recording a plan the streams are virtual and
+    // every record and wait is logged, so the host replay can check the
+    // schedule for races.  Ring events are waited right after they are
+    // recorded; `join` (record_join) is the one event waited much later.
     int plan_events = 0;
     bool two_streams() const { return rec || (evs && ex2.stream != nullptr); }
+    bool three_streams() const { return rec || (evs && ex2.stream && ex3.stream && joinev); }
+    hipStream_t stream_of(int stream) const { return stream == 1 ? ex2.stream : stream == 2 ? ex3.stream : ex.stream; }
+    hipEvent_t plan_record(int stream)
+    {
+        if (rfp_plan_op* o = next(RFP_PLAN_RECORD)) {
+            o->stream = stream;
+            o->m = plan_events;
+        }
+        return (hipEvent_t)(uintptr_t)(++plan_events);
+    }
     hipEvent_t record(int stream)
     {
-        if (rec) {
-            if (rfp_plan_op* o = next(RFP_PLAN_RECORD)) {
-                o->stream = stream;
-                o->m = plan_events;
-            }
-            return (hipEvent_t)(uintptr_t)(++plan_events);
-        }
+        if (rec) return plan_record(stream);
         if (!two_streams()) return nullptr;
         hipEvent_t ev = evs[(*evi)++ % nev];
-        chk(hipEventRecord(ev, stream ? ex2.stream : ex.stream));
+        chk(hipEventRecord(ev, stream_of(stream)));
         return ev;
+    }
+    hipEvent_t record_join(int stream)
+    {
+        if (rec) return plan_record(stream);
+        chk(hipEventRecord(joinev, stream_of(stream)));
+        return joinev;
     }
     void wait(int stream, hipEvent_t ev)
     {
@@ -225,7 +241,7 @@ struct Run {
             }
             return;
         }
-        chk(hipStreamWaitEvent(stream ? ex2.stream : ex.stream, ev, 0));
+        chk(hipStreamWaitEvent(stream_of(stream), ev, 0));
     }
     // Fused triangular solve with the whole factor (see block_solve).
     int* flags = nullptr;
@@ -277,7 +293,12 @@ struct Run {
     // panel column k + 2 waits for that bulk update (both write it).  Wider
     // panels give the bulk update k = pb, where the GEMM runs faster than at
     // k = nb, at the price of a longer diagonal chain per step.
-    void potrf_la(int64_t n, Mat<T> A, int64_t goff, T* winv)
+    //
+    // fork_at / fork: after the panel solve of the first step whose solved
+    // columns [0, o1) reach fork_at, fork(o1, ev) is called with the event
+    // that marks those columns (and their leaf inverses) final on stream 0.
+    template <typename F = void (*)(int64_t, hipEvent_t)>
+    void potrf_la(int64_t n, Mat<T> A, int64_t goff, T* winv, int64_t fork_at = -1, F* fork = nullptr)
     {
         if (n <= 0) return;
         const int64_t pb = 2 * nb;
@@ -291,6 +312,10 @@ struct Run {
             // panel: L(o1:, panel k) = A(o1:, panel k) L_kk^{-T}
             trsm_rlt(n - o1, pb, A.sub(o1, o), A.sub(o, o), winv_at(o));
             hipEvent_t panel_done = record(0);
+            if (fork && fork_at >= 0 && o1 >= fork_at) {
+                (*fork)(o1, panel_done);
+                fork = nullptr;
+            }
             // lookahead: panel column k + 1 (lower part of its diagonal block), then that block
             wait(0, bulk_prev);
             mm(n - o1, b1, pb, T(-1), A.sub(o1, o), TRI_NONE, A.sub(o1, o), TRI_NONE, T(1), A.sub(o1, o1), true);
@@ -299,10 +324,10 @@ struct Run {
             bulk_prev = nullptr;
             if (o2 < n) {
                 wait(1, panel_done);
-                on_aux = two_streams();
+                on = two_streams() ? 1 : 0;
                 mm(n - o2, n - o2, pb, T(-1), A.sub(o2, o), TRI_NONE, A.sub(o2, o), TRI_NONE, T(1), A.sub(o2, o2),
                    true);
-                on_aux = false;
+                on = 0;
                 bulk_prev = record(1);
             }
         }
@@ -466,6 +491,16 @@ static hipError_t prepare(rfp_context* h, size_t inv_need)
             h->nev = i + 1;
         }
     }
+    if (!h->aux2) {
+        e = hipStreamCreateWithFlags(&h->aux2, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        e = hipEventCreateWithFlags(&h->join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(h->aux2);
+            h->aux2 = nullptr;
+            return e;
+        }
+    }
     return ensure(&h->inv, &h->inv_bytes, inv_need);
 }
 
@@ -508,6 +543,11 @@ static Run<T> make_run(rfp_context* h, hipStream_t s, int* info)
     r.nev = h->nev;
     r.evi = &h->evi;
     r.ex.tune = r.ex2.tune = h->tune;
+    r.ex3 = r.ex;
+    r.ex3.stream = h->aux2;
+    r.ex3.splitk_ws = nullptr;  // its GEMMs never split K: no workspace shared with the other streams
+    r.ex3.splitk_bytes = 0;
+    r.joinev = h->aux2 ? h->join : nullptr;
     return r;
 }
 
@@ -589,9 +629,33 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     RfpView<T> v = rfp_view(b, arf);
     r.setinfo(info);
     // step 1: L11 = chol(A11)              (Figure 4, factorization step 1)
-    r.potrf_la(b.m1, v.t1, 0, winv);
     // step 2: L21 = A21 L11^{-T}           (step 2, TRSM)
-    r.trsm_rlt(b.m2, b.m1, v.s, v.t1, winv);
+    // Step 2 is split at a column h of L11: the part that needs only the
+    // first h columns, L21(:, :h) = A21(:, :h) L11(:h, :h)^{-T} and the
+    // update A21(:, h:) -= L21(:, :h) L11(h:, :h)^T, runs on the second
+    // auxiliary stream as soon as the factorization of step 1 has passed
+    // column h, alongside its remaining (latency-bound) panels; the rest,
+    // L21(:, h:) = A21(:, h:) L11(h:, h:)^{-T}, follows step 1.
+    const int64_t pb = 2 * r.nb;
+    int64_t h0 = 0;
+    hipEvent_t joined = nullptr;
+    auto fork = [&](int64_t h, hipEvent_t ev) {
+        r.wait(2, ev);
+        r.on = 2;
+        r.trsm_rlt(b.m2, h, v.s, v.t1, winv);
+        r.mm(b.m2, b.m1 - h, h, T(-1), v.s, TRI_NONE, v.t1.sub(h, 0), TRI_NONE, T(1), v.s.sub(0, h));
+        r.on = 0;
+        joined = r.record_join(2);
+        h0 = h;
+    };
+    if (b.m2 > 0 && b.m1 >= 4 * pb && r.three_streams()) r.potrf_la(b.m1, v.t1, 0, winv, b.m1 / 2, &fork);
+    else r.potrf_la(b.m1, v.t1, 0, winv);
+    if (h0 > 0) {
+        r.wait(0, joined);
+        r.trsm_rlt(b.m2, b.m1 - h0, v.s.sub(0, h0), v.t1.sub(h0, h0), winv + nleaves(h0, r.nb) * r.nb * r.nb);
+    } else {
+        r.trsm_rlt(b.m2, b.m1, v.s, v.t1, winv);
+    }
     // step 3: A22 <- A22 - L21 L21^T       (step 3, SYRK on T2's triangle)
     r.mm(b.m2, b.m2, b.m1, T(-1), v.s, TRI_NONE, v.s, TRI_NONE, T(1), v.t2, true);
     // step 4: L22 = chol(A22), INFO offset by m1
@@ -1117,6 +1181,8 @@ int rfp_destroy(rfp_handle_t h)
         delete h->tune;
         for (int i = 0; i < h->nev; i++) (void)hipEventDestroy(h->ev[i]);
         if (h->aux) (void)hipStreamDestroy(h->aux);
+        if (h->join) (void)hipEventDestroy(h->join);
+        if (h->aux2) (void)hipStreamDestroy(h->aux2);
         delete h->prof;
     }
     std::free(h);

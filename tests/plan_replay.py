@@ -10,7 +10,7 @@ NumPy with the documented semantics and checks, for every access, that
     GEMM kernel supports (C and A the same view with all columns in one
     128-wide tile, or B the transpose view of C with all rows in one tile),
     and overlaps nothing else;
-  * the two-stream schedule is race-free: ops on different streams that the
+  * the multi-stream schedule is race-free: ops on different streams that the
     recorded events do not order (vector clocks) touch disjoint data, or only
     read the same data.
 
@@ -46,7 +46,7 @@ class Replayer:
     def __init__(self, bufs):
         self.bufs = bufs  # {buffer id: 1-D float64 array}
         self.nops = 0
-        self.vc = {0: [0, 0], 1: [0, 0]}  # vector clock of each stream
+        self.vc = {q: [0, 0, 0] for q in range(3)}  # vector clock of each stream
         self.events = {}
         self.log = []  # (stream, clock, reads, writes) per compute op
         self._r, self._w = [], []
@@ -191,16 +191,17 @@ class Replayer:
                 out.setdefault(buf, set()).update(sel)
             return out
         ops = [(s, vc, merge(r), merge(w)) for s, vc, r, w in self.log]
-        a_ops = [o for o in ops if o[0] == 0]
-        b_ops = [o for o in ops if o[0] == 1]
-        for sa, va, ra, wa in a_ops:
-            for sb, vb, rb, wb in b_ops:
-                if va[0] <= vb[0] or vb[1] <= va[1]:
-                    continue  # ordered by the events
-                for buf in set(wa) | set(wb):
-                    if (wa.get(buf, set()) & (rb.get(buf, set()) | wb.get(buf, set()))) or \
-                       (wb.get(buf, set()) & ra.get(buf, set())):
-                        raise PlanError(f"race between unordered ops on streams 0 and 1 (buffer {buf})")
+        by_stream = {q: [o for o in ops if o[0] == q] for q in range(3)}
+        for qa, qb in ((0, 1), (0, 2), (1, 2)):
+            for sa, va, ra, wa in by_stream[qa]:
+                for sb, vb, rb, wb in by_stream[qb]:
+                    if va[qa] <= vb[qa] or vb[qb] <= va[qb]:
+                        continue  # ordered by the events
+                    for buf in set(wa) | set(wb):
+                        if (wa.get(buf, set()) & (rb.get(buf, set()) | wb.get(buf, set()))) or \
+                           (wb.get(buf, set()) & ra.get(buf, set())):
+                            raise PlanError(f"race between unordered ops on streams {qa} and {qb} "
+                                            f"(buffer {buf})")
 
 
 NB2 = 128

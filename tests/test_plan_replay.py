@@ -130,3 +130,32 @@ def test_pftrf_plan_with_bulk_updates(transr, uplo, n):
     got = arf.copy()
     Replayer(_bufs("F", uplo, n, got)).run(ops)
     assert oracle.rel_fro(got, want) <= 1e-13 * n
+
+
+def _drop_waits_on(ops, waiter, recorder):
+    """The plan without stream `waiter`'s waits for events recorded on stream `recorder`."""
+    evs = {o.m for o in ops if o.kind == rfp.PLAN_RECORD and o.stream == recorder}
+    return [o for o in ops if not (o.kind == rfp.PLAN_WAIT and o.stream == waiter and o.m in evs)]
+
+
+@pytest.mark.parametrize("transr,uplo", [("N", "L"), ("T", "U")])
+def test_pftrf_plan_three_streams(transr, uplo):
+    """When the first diagonal triangle spans four or more panels, the first
+    part of the off-diagonal solve runs on the second auxiliary stream while
+    the factorization finishes: the replay matches the oracle, and dropping
+    either side of that fork (its start after the panel solve, or the join
+    before the rest of the solve) is flagged as a race."""
+    n = 2300
+    A, _ = synth.spd(n, seed=n + 4)
+    arf = oracle.trttf(transr, uplo, A)
+    want, _ = oracle.pftrf(transr, uplo, n, arf.copy())
+    ops = rfp.rfp_plan("F", transr, uplo, n)
+    assert any(o.stream == 2 and o.kind == rfp.PLAN_GEMM for o in ops)
+    got = arf.copy()
+    Replayer(_bufs("F", uplo, n, got)).run(ops)
+    assert oracle.rel_fro(got, want) <= 1e-13 * n
+    for waiter, recorder in ((0, 2), (2, 0)):
+        broken = _drop_waits_on(ops, waiter, recorder)
+        assert len(broken) < len(ops)
+        with pytest.raises(AssertionError):
+            Replayer(_bufs("F", uplo, n, arf.copy())).run(broken)
