@@ -294,11 +294,11 @@ struct Run {
     // panels give the bulk update k = pb, where the GEMM runs faster than at
     // k = nb, at the price of a longer diagonal chain per step.
     //
-    // fork_at / fork: after the panel solve of the first step whose solved
-    // columns [0, o1) reach fork_at, fork(o1, ev) is called with the event
-    // that marks those columns (and their leaf inverses) final on stream 0.
+    // fork: after the panel solve of every step, fork(o1, ev) is called with
+    // the event that marks columns [0, o1) (and their leaf inverses) final on
+    // stream 0.
     template <typename F = void (*)(int64_t, hipEvent_t)>
-    void potrf_la(int64_t n, Mat<T> A, int64_t goff, T* winv, int64_t fork_at = -1, F* fork = nullptr)
+    void potrf_la(int64_t n, Mat<T> A, int64_t goff, T* winv, F* fork = nullptr)
     {
         if (n <= 0) return;
         const int64_t pb = 2 * nb;
@@ -312,10 +312,7 @@ struct Run {
             // panel: L(o1:, panel k) = A(o1:, panel k) L_kk^{-T}
             trsm_rlt(n - o1, pb, A.sub(o1, o), A.sub(o, o), winv_at(o));
             hipEvent_t panel_done = record(0);
-            if (fork && fork_at >= 0 && o1 >= fork_at) {
-                (*fork)(o1, panel_done);
-                fork = nullptr;
-            }
+            if (fork) (*fork)(o1, panel_done);
             // lookahead: panel column k + 1 (lower part of its diagonal block), then that block
             wait(0, bulk_prev);
             mm(n - o1, b1, pb, T(-1), A.sub(o1, o), TRI_NONE, A.sub(o1, o), TRI_NONE, T(1), A.sub(o1, o1), true);
@@ -630,32 +627,31 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     r.setinfo(info);
     // step 1: L11 = chol(A11)              (Figure 4, factorization step 1)
     // step 2: L21 = A21 L11^{-T}           (step 2, TRSM)
-    // Step 2 is split at a column h of L11: the part that needs only the
-    // first h columns, L21(:, :h) = A21(:, :h) L11(:h, :h)^{-T} and the
-    // update A21(:, h:) -= L21(:, :h) L11(h:, :h)^T, runs on the second
-    // auxiliary stream as soon as the factorization of step 1 has passed
-    // column h, alongside its remaining (latency-bound) panels; the rest,
-    // L21(:, h:) = A21(:, h:) L11(h:, h:)^{-T}, follows step 1.
-    const int64_t pb = 2 * r.nb;
-    int64_t h0 = 0;
+    // Step 2 runs right-looking by chunks of about SCHUNK columns of L11,
+    // each on the second auxiliary stream as soon as the factorization of
+    // step 1 has passed it, alongside its remaining (latency-bound) panels:
+    //   L21(:, c0:c1) = A21(:, c0:c1) L11(c0:c1, c0:c1)^{-T}
+    //   A21(:, c1:)  -= L21(:, c0:c1) L11(c1:, c0:c1)^T
+    // The columns after the last chunk are solved on stream 0 after step 1.
+    constexpr int64_t SCHUNK = 1024;
+    int64_t done = 0;
     hipEvent_t joined = nullptr;
-    auto fork = [&](int64_t h, hipEvent_t ev) {
+    auto fork = [&](int64_t o1, hipEvent_t ev) {
+        if (o1 - done < SCHUNK || o1 >= b.m1) return;
         r.wait(2, ev);
         r.on = 2;
-        r.trsm_rlt(b.m2, h, v.s, v.t1, winv);
-        r.mm(b.m2, b.m1 - h, h, T(-1), v.s, TRI_NONE, v.t1.sub(h, 0), TRI_NONE, T(1), v.s.sub(0, h));
+        r.trsm_rlt(b.m2, o1 - done, v.s.sub(0, done), v.t1.sub(done, done),
+                   winv + nleaves(done, r.nb) * r.nb * r.nb);
+        r.mm(b.m2, b.m1 - o1, o1 - done, T(-1), v.s.sub(0, done), TRI_NONE, v.t1.sub(o1, done), TRI_NONE, T(1),
+             v.s.sub(0, o1));
         r.on = 0;
         joined = r.record_join(2);
-        h0 = h;
+        done = o1;
     };
-    if (b.m2 > 0 && b.m1 >= 4 * pb && r.three_streams()) r.potrf_la(b.m1, v.t1, 0, winv, b.m1 / 2, &fork);
+    if (b.m2 > 0 && b.m1 > SCHUNK && r.three_streams()) r.potrf_la(b.m1, v.t1, 0, winv, &fork);
     else r.potrf_la(b.m1, v.t1, 0, winv);
-    if (h0 > 0) {
-        r.wait(0, joined);
-        r.trsm_rlt(b.m2, b.m1 - h0, v.s.sub(0, h0), v.t1.sub(h0, h0), winv + nleaves(h0, r.nb) * r.nb * r.nb);
-    } else {
-        r.trsm_rlt(b.m2, b.m1, v.s, v.t1, winv);
-    }
+    r.wait(0, joined);
+    r.trsm_rlt(b.m2, b.m1 - done, v.s.sub(0, done), v.t1.sub(done, done), winv + nleaves(done, r.nb) * r.nb * r.nb);
     // step 3: A22 <- A22 - L21 L21^T       (step 3, SYRK on T2's triangle)
     r.mm(b.m2, b.m2, b.m1, T(-1), v.s, TRI_NONE, v.s, TRI_NONE, T(1), v.t2, true);
     // step 4: L22 = chol(A22), INFO offset by m1
