@@ -632,7 +632,9 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     // step 1 has passed it, alongside its remaining (latency-bound) panels:
     //   L21(:, c0:c1) = A21(:, c0:c1) L11(c0:c1, c0:c1)^{-T}
     //   A21(:, c1:)  -= L21(:, c0:c1) L11(c1:, c0:c1)^T
-    // The columns after the last chunk are solved on stream 0 after step 1.
+    //   A22          -= L21(:, c0:c1) L21(:, c0:c1)^T   (step 3's share of the chunk)
+    // The columns after the last chunk are solved, and their share of step 3
+    // applied, on stream 0 after step 1.
     constexpr int64_t SCHUNK = 1024;
     int64_t done = 0;
     hipEvent_t joined = nullptr;
@@ -644,6 +646,7 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
                    winv + nleaves(done, r.nb) * r.nb * r.nb);
         r.mm(b.m2, b.m1 - o1, o1 - done, T(-1), v.s.sub(0, done), TRI_NONE, v.t1.sub(o1, done), TRI_NONE, T(1),
              v.s.sub(0, o1));
+        r.mm(b.m2, b.m2, o1 - done, T(-1), v.s.sub(0, done), TRI_NONE, v.s.sub(0, done), TRI_NONE, T(1), v.t2, true);
         r.on = 0;
         joined = r.record_join(2);
         done = o1;
@@ -652,8 +655,9 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     else r.potrf_la(b.m1, v.t1, 0, winv);
     r.wait(0, joined);
     r.trsm_rlt(b.m2, b.m1 - done, v.s.sub(0, done), v.t1.sub(done, done), winv + nleaves(done, r.nb) * r.nb * r.nb);
-    // step 3: A22 <- A22 - L21 L21^T       (step 3, SYRK on T2's triangle)
-    r.mm(b.m2, b.m2, b.m1, T(-1), v.s, TRI_NONE, v.s, TRI_NONE, T(1), v.t2, true);
+    // step 3: A22 <- A22 - L21 L21^T       (step 3, SYRK on T2's triangle; the
+    // chunks' shares are already applied)
+    r.mm(b.m2, b.m2, b.m1 - done, T(-1), v.s.sub(0, done), TRI_NONE, v.s.sub(0, done), TRI_NONE, T(1), v.t2, true);
     // step 4: L22 = chol(A22), INFO offset by m1
     r.potrf_la(b.m2, v.t2, b.m1, winv);
     return r.err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
