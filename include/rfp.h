@@ -274,9 +274,10 @@ int rfp_profile_read(rfp_handle_t h, rfp_profile_entry* out, int cap, int* count
  *     w holds the inverses of the 64-row diagonal blocks of L11 then of L22,
  *     consecutive NB x NB row-major blocks (as RFP_PLAN_TRTRI_LEAVES writes).
  *   RFP_PLAN_RECORD / RFP_PLAN_WAIT: event m is recorded on / waited for by
- *     stream `stream` (0: the caller's stream, 1: the handle's auxiliary
- *     stream).  Every other record carries the stream it runs on; work on one
- *     stream runs in order, across streams only as the events order it.
+ *     stream `stream` (0: the caller's stream, 1 and 2: the handle's two
+ *     auxiliary streams).  Every other record carries the stream it runs on;
+ *     work on one stream runs in order, across streams only as the events
+ *     order it.
  * *count receives the number of records (even beyond cap).  Returns 0, -1 for
  * an unknown routine, -8 for bad output arguments, or the routine's own
  * argument error code. */
@@ -294,7 +295,7 @@ enum { RFP_PLAN_BUF_ARF = 0, RFP_PLAN_BUF_B = 1, RFP_PLAN_BUF_WORK = 2, RFP_PLAN
 typedef struct {
     int32_t kind, tri_a, tri_b, c_lower;
     int32_t inplace; /* GEMM: C aliases A or B (one tile spans the aliased dimension) */
-    int32_t stream;  /* 0: the caller's stream, 1: the handle's auxiliary stream */
+    int32_t stream;  /* 0: the caller's stream, 1 and 2: the handle's auxiliary streams */
     int64_t m, n, k;
     double alpha, beta;
     int64_t a[4], b[4], c[4]; /* buffer (-1: unused), offset, row stride, column stride */
