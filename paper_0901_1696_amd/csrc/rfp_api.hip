@@ -285,48 +285,51 @@ struct Run {
         potrf_rec(n2, A.sub(n1, n1), goff + n1, winv + nleaves(n1, nb) * nb * nb);
     }
 
-    // Right-looking blocked Cholesky of the lower triangle of A (order n) in
-    // panels of pb = 2 nb columns, with one step of lookahead: after the
-    // panel of step k, the critical stream updates only panel column k + 1
-    // and factors its diagonal block while the auxiliary stream applies step
-    // k's update to the rest of the trailing matrix.  Step k + 1's update of
-    // panel column k + 2 waits for that bulk update (both write it).  Wider
-    // panels give the bulk update k = pb, where the GEMM runs faster than at
-    // k = nb, at the price of a longer diagonal chain per step.
+    // Right-looking blocked Cholesky of the lower triangle of A (order n) with
+    // one step of lookahead: after the panel of step k, the critical stream
+    // updates only panel column k + 1 and factors its diagonal block while
+    // the auxiliary stream applies step k's update to the rest of the
+    // trailing matrix.  Step k + 1's update of panel column k + 2 waits for
+    // that bulk update (both write it).  Panels are 2 nb wide while the
+    // trailing matrix is large (the bulk update, at k = 2 nb, then runs faster
+    // than at k = nb and hides the diagonal chain) and nb wide once it is
+    // small (the chain per column is then shorter: fewer small products per
+    // leaf, and nothing large enough is left to hide it).
     //
     // fork: after the panel solve of every step, fork(o1, ev) is called with
     // the event that marks columns [0, o1) (and their leaf inverses) final on
     // stream 0.
+    static constexpr int64_t WIDE_PANELS_ABOVE = 6144;  // trailing order (best of 3072-8192 at n = 20000)
     template <typename F = void (*)(int64_t, hipEvent_t)>
     void potrf_la(int64_t n, Mat<T> A, int64_t goff, T* winv, F* fork = nullptr)
     {
         if (n <= 0) return;
-        const int64_t pb = 2 * nb;
-        const int64_t K = nleaves(n, pb);
         auto winv_at = [&](int64_t o) { return winv + (o / nb) * nb * nb; };
-        potrf_rec(std::min<int64_t>(pb, n), A, goff, winv);
+        auto width = [&](int64_t o) { return std::min<int64_t>(n - o > WIDE_PANELS_ABOVE ? 2 * nb : nb, n - o); };
+        int64_t o = 0, w = width(0);
+        potrf_rec(w, A, goff, winv);
         hipEvent_t bulk_prev = nullptr;
-        for (int64_t k = 0; k + 1 < K; k++) {
-            const int64_t o = k * pb, o1 = o + pb;
-            const int64_t b1 = std::min<int64_t>(pb, n - o1), o2 = o1 + b1;
-            // panel: L(o1:, panel k) = A(o1:, panel k) L_kk^{-T}
-            trsm_rlt(n - o1, pb, A.sub(o1, o), A.sub(o, o), winv_at(o));
+        while (o + w < n) {
+            const int64_t o1 = o + w, w1 = width(o1), o2 = o1 + w1;
+            // panel: L(o1:, panel) = A(o1:, panel) L_kk^{-T}
+            trsm_rlt(n - o1, w, A.sub(o1, o), A.sub(o, o), winv_at(o));
             hipEvent_t panel_done = record(0);
             if (fork) (*fork)(o1, panel_done);
-            // lookahead: panel column k + 1 (lower part of its diagonal block), then that block
+            // lookahead: the next panel column (lower part of its diagonal block), then that block
             wait(0, bulk_prev);
-            mm(n - o1, b1, pb, T(-1), A.sub(o1, o), TRI_NONE, A.sub(o1, o), TRI_NONE, T(1), A.sub(o1, o1), true);
-            potrf_rec(b1, A.sub(o1, o1), goff + o1, winv_at(o1));
-            // bulk: columns beyond panel k + 1
+            mm(n - o1, w1, w, T(-1), A.sub(o1, o), TRI_NONE, A.sub(o1, o), TRI_NONE, T(1), A.sub(o1, o1), true);
+            potrf_rec(w1, A.sub(o1, o1), goff + o1, winv_at(o1));
+            // bulk: columns beyond the next panel
             bulk_prev = nullptr;
             if (o2 < n) {
                 wait(1, panel_done);
                 on = two_streams() ? 1 : 0;
-                mm(n - o2, n - o2, pb, T(-1), A.sub(o2, o), TRI_NONE, A.sub(o2, o), TRI_NONE, T(1), A.sub(o2, o2),
-                   true);
+                mm(n - o2, n - o2, w, T(-1), A.sub(o2, o), TRI_NONE, A.sub(o2, o), TRI_NONE, T(1), A.sub(o2, o2), true);
                 on = 0;
                 bulk_prev = record(1);
             }
+            o = o1;
+            w = w1;
         }
         wait(0, bulk_prev);
     }
