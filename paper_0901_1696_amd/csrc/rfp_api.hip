@@ -630,7 +630,7 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     r.setinfo(info);
     // step 1: L11 = chol(A11)              (Figure 4, factorization step 1)
     // step 2: L21 = A21 L11^{-T}           (step 2, TRSM)
-    // Step 2 runs right-looking by chunks of about SCHUNK columns of L11,
+    // Step 2 runs right-looking by chunks of at least SCHUNK columns of L11,
     // each on the second auxiliary stream as soon as the factorization of
     // step 1 has passed it, alongside its remaining (latency-bound) panels:
     //   L21(:, c0:c1) = A21(:, c0:c1) L11(c0:c1, c0:c1)^{-T}
@@ -638,7 +638,9 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     //   A22          -= L21(:, c0:c1) L21(:, c0:c1)^T   (step 3's share of the chunk)
     // The columns after the last chunk are solved, and their share of step 3
     // applied, on stream 0 after step 1.
-    constexpr int64_t SCHUNK = 1024;
+    // chunk: 2048 columns (512-4096 measured at n = 20000: 1536-2048 best),
+    // at most half of T1 so that smaller triangles still get two chunks
+    const int64_t SCHUNK = std::min<int64_t>(2048, std::max<int64_t>(4 * r.nb, b.m1 / 2 / r.nb * r.nb));
     int64_t done = 0;
     hipEvent_t joined = nullptr;
     auto fork = [&](int64_t o1, hipEvent_t ev) {
