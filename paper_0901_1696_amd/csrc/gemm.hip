@@ -405,22 +405,67 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
             }
         return;
     }
+    // Element (a, b, r) of this thread's share of the tile: its address, and
+    // whether it is stored at all.
+    auto c_at = [&](int a, int b, int r, bool& ok) -> T* {
+        const int64_t j = j0 + wn * (BN / 2) + b * 16 + cl;
+        const int64_t i = i0 + wm * (BM / 2) + a * 16 + Mfma<T>::row(lane, r);
+        ok = i < m && j < n && (!p.c_lower || i >= j);
+        return CMC ? &p.C[i + j * p.ldc] : &p.C[i * p.ldc + j];
+    };
+    if (p.beta == T(0)) {
 #pragma unroll
-    for (int a = 0; a < WMB; a++)
+        for (int a = 0; a < WMB; a++)
 #pragma unroll
-        for (int b = 0; b < WNB; b++) {
-            const int64_t j = j0 + wn * (BN / 2) + b * 16 + cl;
+            for (int b = 0; b < WNB; b++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    bool ok;
+                    T* c = c_at(a, b, r, ok);
+                    if (ok) *c = p.alpha * acc[a][b][r];
+                }
+        return;
+    }
+    // C = alpha acc + beta C by block rows of 16: a block row's reads are all
+    // issued before any of its results is stored (written element by element,
+    // read-then-store would serialise one memory latency per element, since
+    // the compiler cannot prove the addresses distinct), and the next block
+    // row's reads before this one's stores.
+    T cv[2][WNB][4];
+    auto fetch = [&](int a, auto buf) {
+        constexpr int q = decltype(buf)::value;
+#pragma unroll
+        for (int b = 0; b < WNB; b++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int64_t i = i0 + wm * (BM / 2) + a * 16 + Mfma<T>::row(lane, r);
-                if (i < m && j < n && (!p.c_lower || i >= j)) {
-                    T* c = CMC ? &p.C[i + j * p.ldc] : &p.C[i * p.ldc + j];
-                    T v = p.alpha * acc[a][b][r];
-                    if (p.beta != T(0)) v += p.beta * *c;
-                    *c = v;
-                }
+                bool ok;
+                const T* c = c_at(a, b, r, ok);
+                cv[q][b][r] = ok ? *c : T(0);
             }
+    };
+    auto finish = [&](int a, auto buf) {
+        constexpr int q = decltype(buf)::value;
+#pragma unroll
+        for (int b = 0; b < WNB; b++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                bool ok;
+                T* c = c_at(a, b, r, ok);
+                if (ok) *c = p.alpha * acc[a][b][r] + p.beta * cv[q][b][r];
+            }
+    };
+    using B0 = std::integral_constant<int, 0>;
+    using B1 = std::integral_constant<int, 1>;
+    fetch(0, B0{});
+#pragma unroll
+    for (int a = 0; a < WMB; a += 2) {
+        if (a + 1 < WMB) fetch(a + 1, B1{});
+        finish(a, B0{});
+        if (a + 1 < WMB) {
+            if (a + 2 < WMB) fetch(a + 2, B0{});
+            finish(a + 1, B1{});
         }
+    }
 }
 
 // C = alpha * sum_z W[z] + beta * C over the (masked) m x n output.
