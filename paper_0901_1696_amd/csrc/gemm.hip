@@ -330,9 +330,11 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
 #pragma unroll
                 for (int b = 0; b < WNB; b++) {
                     if constexpr (LP == 1)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16f16(af[a], bf[b], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16f16(CMC ? bf[b] : af[a], CMC ? af[a] : bf[b],
+                                                                          acc[a][b], 0, 0, 0);
                     else
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bf[b], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(CMC ? bf[b] : af[a], CMC ? af[a] : bf[b],
+                                                                              acc[a][b], 0, 0, 0);
                 }
             return;
         } else {
@@ -348,11 +350,13 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
 #pragma unroll
             for (int a = 0; a < WMB; a++)
 #pragma unroll
-                for (int b = 0; b < WNB; b++) acc[a][b] = Mfma<T>::op(af[a].x, bf[b].x, acc[a][b]);
+                for (int b = 0; b < WNB; b++)
+                    acc[a][b] = Mfma<T>::op(CMC ? bf[b].x : af[a].x, CMC ? af[a].x : bf[b].x, acc[a][b]);
 #pragma unroll
             for (int a = 0; a < WMB; a++)
 #pragma unroll
-                for (int b = 0; b < WNB; b++) acc[a][b] = Mfma<T>::op(af[a].y, bf[b].y, acc[a][b]);
+                for (int b = 0; b < WNB; b++)
+                    acc[a][b] = Mfma<T>::op(CMC ? bf[b].y : af[a].y, CMC ? af[a].y : bf[b].y, acc[a][b]);
             __builtin_amdgcn_sched_barrier(0);
         }
         }
@@ -387,8 +391,11 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
         compute((int)(s & 1));
     }
 
-    // accumulator (a, b)[r] holds C(row, col) with
-    // row = wm*BM/2 + a*16 + Mfma<T>::row(lane, r), col = wn*BN/2 + b*16 + lane%16
+    // accumulator (a, b)[r] holds C(row, col) with row = wm*BM/2 + a*16 + x,
+    // col = wn*BN/2 + b*16 + y, where (x, y) = (Mfma<T>::row(lane, r), lane%16);
+    // for column-major C the products are formed transposed (operands swapped)
+    // and (x, y) = (lane%16, Mfma<T>::row(lane, r)), so that the 16 lanes of a
+    // row group store 16 consecutive elements of a column
     const int cl = lane & 15;
     if (p.W) {
         T* W = p.W + (int64_t)blockIdx.z * m * n;
@@ -396,10 +403,10 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
         for (int a = 0; a < WMB; a++)
 #pragma unroll
             for (int b = 0; b < WNB; b++) {
-                const int64_t j = j0 + wn * (BN / 2) + b * 16 + cl;
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const int64_t i = i0 + wm * (BM / 2) + a * 16 + Mfma<T>::row(lane, r);
+                    const int64_t i = i0 + wm * (BM / 2) + a * 16 + (CMC ? cl : Mfma<T>::row(lane, r));
+                    const int64_t j = j0 + wn * (BN / 2) + b * 16 + (CMC ? Mfma<T>::row(lane, r) : cl);
                     if (i < m && j < n) W[j * m + i] = acc[a][b][r];
                 }
             }
@@ -408,8 +415,8 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
     // Element (a, b, r) of this thread's share of the tile: its address, and
     // whether it is stored at all.
     auto c_at = [&](int a, int b, int r, bool& ok) -> T* {
-        const int64_t j = j0 + wn * (BN / 2) + b * 16 + cl;
-        const int64_t i = i0 + wm * (BM / 2) + a * 16 + Mfma<T>::row(lane, r);
+        const int64_t i = i0 + wm * (BM / 2) + a * 16 + (CMC ? cl : Mfma<T>::row(lane, r));
+        const int64_t j = j0 + wn * (BN / 2) + b * 16 + (CMC ? Mfma<T>::row(lane, r) : cl);
         ok = i < m && j < n && (!p.c_lower || i >= j);
         return CMC ? &p.C[i + j * p.ldc] : &p.C[i * p.ldc + j];
     };
@@ -429,9 +436,9 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
     // C = alpha acc + beta C by block rows of 16: a block row's reads are all
     // issued before any of its results is stored (written element by element,
     // read-then-store would serialise one memory latency per element, since
-    // the compiler cannot prove the addresses distinct), and the next block
-    // row's reads before this one's stores.
-    T cv[2][WNB][4];
+    // the compiler cannot prove the addresses distinct), and for row-major C
+    // the next block row's reads before this one's stores.
+    T cv[CMC ? 1 : 2][WNB][4];
     auto fetch = [&](int a, auto buf) {
         constexpr int q = decltype(buf)::value;
 #pragma unroll
@@ -456,14 +463,23 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
     };
     using B0 = std::integral_constant<int, 0>;
     using B1 = std::integral_constant<int, 1>;
-    fetch(0, B0{});
+    if constexpr (CMC) {
+        // (one buffer: the column-major address arithmetic leaves no room for two)
 #pragma unroll
-    for (int a = 0; a < WMB; a += 2) {
-        if (a + 1 < WMB) fetch(a + 1, B1{});
-        finish(a, B0{});
-        if (a + 1 < WMB) {
-            if (a + 2 < WMB) fetch(a + 2, B0{});
-            finish(a + 1, B1{});
+        for (int a = 0; a < WMB; a++) {
+            fetch(a, B0{});
+            finish(a, B0{});
+        }
+    } else {
+        fetch(0, B0{});
+#pragma unroll
+        for (int a = 0; a < WMB; a += 2) {
+            if (a + 1 < WMB) fetch(a + 1, B1{});
+            finish(a, B0{});
+            if (a + 1 < WMB) {
+                if (a + 2 < WMB) fetch(a + 2, B0{});
+                finish(a + 1, B1{});
+            }
         }
     }
 }
