@@ -47,6 +47,9 @@ struct Mfma<float> {
 };
 
 constexpr int BK = 16, NTH = 256;
+// global and LDS address spaces, for the global-to-LDS transfer builtin
+typedef __attribute__((address_space(1))) void gvoid_t;
+typedef __attribute__((address_space(3))) void lvoid_t;
 constexpr int KP = BK + 2;  // LDS row pitch (elements): k-contiguous rows, 16-byte aligned, conflict-free
 
 // Low-precision operand modes of the FP32 GEMM (LP): 0 FP32 MFMA; 1 operands
@@ -151,7 +154,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int total)
 // AMC: A's row index is contiguous (column-major A); else A's k index is.
 // BNC: B's row index (the n index of C) is contiguous; else its k index is.
 // CMC: C's row index is contiguous.
-template <typename T, bool AMC, bool BNC, bool CMC, int WMB, int WNB, int LP = 0>
+template <typename T, bool AMC, bool BNC, bool CMC, int WMB, int WNB, int LP = 0, bool DMA = false>
 __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(GemmParams<T> p)
 {
     constexpr int BM = 32 * WMB, BN = 32 * WNB;
@@ -363,32 +366,212 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
     };
 
     const int64_t span = ke > kb ? ke - kb : 0;
-    const int64_t nfull = span / BK, nslab = (span + BK - 1) / BK;
-    if (nslab > 0) {
-        if (nfull > 0) load_fast(kb);
-        else load_tail(kb);
-        store(0, kb, nfull == 0);
-        __syncthreads();
-        int64_t s = 0;
-        // steady state: the slab being prefetched is a full one.  The
-        // scheduling fence keeps the next slab's LDS stores (and the wait for
-        // its global loads that they imply) after this slab's products.
-        for (; s + 1 < nfull; s++) {
-            load_fast(kb + (s + 1) * BK);
-            compute((int)(s & 1));
+    if constexpr (DMA) {
+        // Direct staging (FP64, unmasked operands, whole slabs): each slab of
+        // A and B goes from global memory straight into LDS, four bytes per
+        // lane and instruction (any 8-byte-aligned pitch), with no register
+        // copy; the registers this frees hold a second set of MFMA fragments,
+        // so the next k group's LDS reads overlap the current one's products.
+        // A k-contiguous operand keeps 128-byte rows whose 16-byte chunks are
+        // permuted (chunk c of row r in slot c ^ (r & 7), and rows 8-15 of
+        // every 16 swapped in pairs), which makes the fragment reads
+        // conflict-free; an i-contiguous one keeps k rows padded by 64 bytes.
+        // Separate arrays per buffer let the compiler see that a transfer into
+        // one does not alias reads of the other.
+        static_assert(sizeof(T) == 8 && LP == 0, "direct staging is FP64 only");
+        constexpr int PA = AMC ? BM + 8 : BK, PB = BNC ? BN + 8 : BK;  // pitch (elements)
+        constexpr int SA = AMC ? BK * PA : BM * BK, SB = BNC ? BK * PB : BN * BK;
+        constexpr int QA = BM / 8, QB = BN / 8;  // transfers per thread and slab
+        __shared__ __attribute__((aligned(16))) double A0[SA], A1[SA], B0[SB], B1[SB];
+        const int wu = __builtin_amdgcn_readfirstlane(w);
+        // Source of each transfer, in bytes from the slab origin.  Rows past a
+        // ragged edge read the last row (their products are never stored).
+        // Only a few per-lane parts stay live; the offsets themselves are
+        // formed again at every slab (the parts are made opaque so that the
+        // compiler does not keep one register per transfer across the loop).
+        // i-contiguous: transfer q covers 32 rows of k column kq(q); the lane
+        // part is the row's byte offset.  k-contiguous: transfer q covers two
+        // rows, 8q + (rb ^ (q & 1)); the lane parts are rb and the chunk
+        // offset for even and odd q.
+        auto parts = [&](auto mc, auto bmx, int lim, int* rb, uint32_t* cb) {
+            constexpr bool MC = decltype(mc)::value;
+            constexpr int BX = decltype(bmx)::value;
+            if constexpr (MC) {
+                const int i = (BX == 128 ? wu : (wu & 1)) * 32 + (lane >> 1);
+                cb[0] = (uint32_t)((i < lim ? i : lim) * 8 + (lane & 1) * 4);
+            } else {
+#pragma unroll
+                for (int par = 0; par < 2; par++) {
+                    rb[par] = (2 * wu + (lane >> 5)) ^ par;
+                    const int c = ((lane & 31) >> 2) ^ (rb[par] & 7);
+                    cb[par] = (uint32_t)((2 * c + ((lane & 3) >> 1)) * 8 + (lane & 1) * 4);
+                }
+            }
+        };
+        int rba[2] = {0, 0}, rbb[2] = {0, 0};
+        uint32_t cba[2] = {0, 0}, cbb[2] = {0, 0};
+        parts(std::integral_constant<bool, AMC>{}, std::integral_constant<int, BM>{}, a_lim, rba, cba);
+        parts(std::integral_constant<bool, BNC>{}, std::integral_constant<int, BN>{}, b_lim, rbb, cbb);
+        auto issue = [&](auto mc, auto bmx, double* X, const char* src, int64_t ld, int lim, int* rb0,
+                         uint32_t* cb0) {
+            constexpr bool MC = decltype(mc)::value;
+            constexpr int BX = decltype(bmx)::value;
+            constexpr int P = MC ? BX + 8 : BK;
+            int rb[2] = {rb0[0], rb0[1]};
+            uint32_t cb[2] = {cb0[0], cb0[1]};
+            asm volatile("" : "+v"(rb[0]), "+v"(rb[1]), "+v"(cb[0]), "+v"(cb[1]));
+#pragma unroll
+            for (int q = 0; q < BX / 8; q++) {
+                const int u = 4 * q + wu;
+                const char* sp;
+                double* d;
+                if constexpr (MC) {
+                    const int kq = u / (BX / 32);
+                    sp = src + (int64_t)kq * ld * 8 + cb[0];
+                    d = X + kq * P + (u % (BX / 32)) * 32;
+                } else {
+                    const int r = 8 * q + rb[q & 1];
+                    sp = src + (uint32_t)((r < lim ? r : lim) * (uint32_t)ld) * 8u + cb[q & 1];
+                    d = X + u * 32;
+                }
+                __builtin_amdgcn_global_load_lds((gvoid_t*)sp, (lvoid_t*)d, 4, 0, 0);
+            }
+        };
+        auto dma = [&](double* XA, double* XB, int64_t k0) {
+            const char* sa = (const char*)(p.A + (AMC ? i0 + k0 * p.lda : i0 * p.lda + k0));
+            const char* sb = (const char*)(p.B + (BNC ? j0 + k0 * p.ldb : j0 * p.ldb + k0));
+            issue(std::integral_constant<bool, AMC>{}, std::integral_constant<int, BM>{}, XA, sa, p.lda, a_lim, rba,
+                  cba);
+            issue(std::integral_constant<bool, BNC>{}, std::integral_constant<int, BN>{}, XB, sb, p.ldb, b_lim, rbb,
+                  cbb);
+        };
+        // fragments of k group kg: lane (lrow, g) holds k = kg + 2g (.x) and kg + 2g + 1 (.y)
+        const int g = lane >> 4;
+        const int rsw = lrow ^ ((lrow >> 3) & 1);
+        const int sl0 = 2 * (g ^ (lrow & 7)), sl1 = 2 * ((4 + g) ^ (lrow & 7));
+        auto frag = [&](const double* XA, const double* XB, auto kgc, v2_t(&af)[WMB], v2_t(&bf)[WNB]) {
+            constexpr int kg = decltype(kgc)::value;
+#pragma unroll
+            for (int x = 0; x < WMB; x++) {
+                const int r = wm * (BM / 2) + x * 16;
+                if constexpr (AMC) {
+                    const double* c = XA + (kg + 2 * g) * PA + r + lrow;
+                    af[x] = v2_t{c[0], c[PA]};
+                } else {
+                    af[x] = *reinterpret_cast<const v2_t*>(XA + (r + rsw) * BK + (kg ? sl1 : sl0));
+                }
+            }
+#pragma unroll
+            for (int x = 0; x < WNB; x++) {
+                const int r = wn * (BN / 2) + x * 16;
+                if constexpr (BNC) {
+                    const double* c = XB + (kg + 2 * g) * PB + r + lrow;
+                    bf[x] = v2_t{c[0], c[PB]};
+                } else {
+                    bf[x] = *reinterpret_cast<const v2_t*>(XB + (r + rsw) * BK + (kg ? sl1 : sl0));
+                }
+            }
+        };
+        auto mma = [&](const v2_t(&af)[WMB], const v2_t(&bf)[WNB]) {
+#pragma unroll
+            for (int a = 0; a < WMB; a++)
+#pragma unroll
+                for (int b = 0; b < WNB; b++)
+                    acc[a][b] = Mfma<T>::op(CMC ? bf[b].x : af[a].x, CMC ? af[a].x : bf[b].x, acc[a][b]);
+#pragma unroll
+            for (int a = 0; a < WMB; a++)
+#pragma unroll
+                for (int b = 0; b < WNB; b++)
+                    acc[a][b] = Mfma<T>::op(CMC ? bf[b].y : af[a].y, CMC ? af[a].y : bf[b].y, acc[a][b]);
+        };
+        using K0 = std::integral_constant<int, 0>;
+        using K8 = std::integral_constant<int, 8>;
+        const int64_t ns = span / BK;  // whole slabs only (checked by the host)
+        v2_t fa[WMB], fb[WNB], ga[WMB], gb[WNB];
+        auto sync = [] {
             __builtin_amdgcn_sched_barrier(0);
-            store((int)((s + 1) & 1), kb + (s + 1) * BK, false);
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this thread's transfers have landed
             __syncthreads();
+        };
+        // One pass per slab s (buffer s % 2), entered after a barrier with k
+        // group 1 of slab s in (ga, gb) and slab s + 1 complete in the other
+        // buffer: start slab s + 2 into this buffer (slab s is no longer read;
+        // near the end the last slab again, never read from here), read k
+        // group 0 of slab s + 1, finish slab s, start slab s + 1, read its k
+        // group 1, and meet at the barrier with no transfer outstanding.  The
+        // transfers and LDS reads are spread over the products.
+        auto pass = [&](double* CA, double* CB, double* NA, double* NB, int64_t s) {
+            dma(CA, CB, kb + (s + 2 < ns ? s + 2 : ns - 1) * BK);
+            frag(NA, NB, K0{}, fa, fb);
+            mma(ga, gb);
+            mma(fa, fb);
+            frag(NA, NB, K8{}, ga, gb);
+            constexpr int NT = (BM + BN) / 8, NM = 2 * WMB * WNB, NF = WMB + WNB;
+            constexpr int M1 = NT / 2 < NM - NF ? NT / 2 : NM - NF;  // products carrying transfers
+#pragma unroll
+            for (int x = 0; x < M1; x++) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x010, (NT + M1 - 1) / M1, 0);
+            }
+#pragma unroll
+            for (int x = 0; x < NF; x++) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+            if constexpr (NM - M1 - NF > 0) __builtin_amdgcn_sched_group_barrier(0x008, NM - M1 - NF, 0);
+#pragma unroll
+            for (int x = 0; x < NF; x++) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, NM - NF, 0);
+            sync();
+        };
+        if (ns > 0) {
+            dma(A0, B0, kb);
+            if (ns > 1) dma(A1, B1, kb + BK);
+            sync();
+            frag(A0, B0, K0{}, fa, fb);
+            mma(fa, fb);
+            frag(A0, B0, K8{}, ga, gb);
+            sync();
+            int64_t s = 0;
+            while (s + 1 < ns) {
+                pass(A0, B0, A1, B1, s++);
+                if (s + 1 >= ns) break;
+                pass(A1, B1, A0, B0, s++);
+            }
+            mma(ga, gb);
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // the spare transfers of the last passes
         }
-        if (s + 1 < nslab) {  // a ragged slab follows the last full one
-            load_tail(kb + (s + 1) * BK);
+    } else {
+        const int64_t nfull = span / BK, nslab = (span + BK - 1) / BK;
+        if (nslab > 0) {
+            if (nfull > 0) load_fast(kb);
+            else load_tail(kb);
+            store(0, kb, nfull == 0);
+            __syncthreads();
+            int64_t s = 0;
+            // steady state: the slab being prefetched is a full one.  The
+            // scheduling fence keeps the next slab's LDS stores (and the wait for
+            // its global loads that they imply) after this slab's products.
+            for (; s + 1 < nfull; s++) {
+                load_fast(kb + (s + 1) * BK);
+                compute((int)(s & 1));
+                __builtin_amdgcn_sched_barrier(0);
+                store((int)((s + 1) & 1), kb + (s + 1) * BK, false);
+                __syncthreads();
+            }
+            if (s + 1 < nslab) {  // a ragged slab follows the last full one
+                load_tail(kb + (s + 1) * BK);
+                compute((int)(s & 1));
+                __builtin_amdgcn_sched_barrier(0);
+                store((int)((s + 1) & 1), kb + (s + 1) * BK, true);
+                __syncthreads();
+                s++;
+            }
             compute((int)(s & 1));
-            __builtin_amdgcn_sched_barrier(0);
-            store((int)((s + 1) & 1), kb + (s + 1) * BK, true);
-            __syncthreads();
-            s++;
         }
-        compute((int)(s & 1));
     }
 
     // accumulator (a, b)[r] holds C(row, col) with row = wm*BM/2 + a*16 + x,
@@ -508,13 +691,14 @@ template <typename T>
 static constexpr const char* tname() { return sizeof(T) == 8 ? "double" : "float"; }
 
 // Demangled kernel names as rocprofv3 prints them.
-template <typename T, bool AMC, bool BNC, bool CMC, int WMB, int WNB, int LP = 0>
+template <typename T, bool AMC, bool BNC, bool CMC, int WMB, int WNB, int LP = 0, bool DMA = false>
 static const char* kname()
 {
-    static char buf[112];
+    static char buf[120];
     if (!buf[0])
-        snprintf(buf, sizeof buf, "rfp::gemm_kernel<%s, %s, %s, %s, %d, %d, %d>(rfp::GemmParams<%s>)", tname<T>(),
-                 AMC ? "true" : "false", BNC ? "true" : "false", CMC ? "true" : "false", WMB, WNB, LP, tname<T>());
+        snprintf(buf, sizeof buf, "rfp::gemm_kernel<%s, %s, %s, %s, %d, %d, %d, %s>(rfp::GemmParams<%s>)", tname<T>(),
+                 AMC ? "true" : "false", BNC ? "true" : "false", CMC ? "true" : "false", WMB, WNB, LP,
+                 DMA ? "true" : "false", tname<T>());
     return buf;
 }
 
@@ -568,7 +752,7 @@ static double gemm_bytes(const GemmParams<T>& p)
 }
 
 template <typename T, bool AMC, bool BNC, bool CMC>
-static void launch(const GemmParams<T>& p, dim3 grid, int tile, const Exec& ex, int lp)
+static void launch(const GemmParams<T>& p, dim3 grid, int tile, const Exec& ex, int lp, bool dma)
 {
     if constexpr (sizeof(T) == 4) {
         // low-precision operand kernels: square tiles only (128 or 64)
@@ -586,6 +770,29 @@ static void launch(const GemmParams<T>& p, dim3 grid, int tile, const Exec& ex, 
             } else {
                 ProfScope ps(ex, kname<T, AMC, BNC, CMC, 2, 2, 2>(), gemm_flops(p), gemm_bytes(p));
                 hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC, 2, 2, 2>), grid, dim3(NTH), 0, ex.stream, p);
+            }
+            return;
+        }
+    }
+    if constexpr (sizeof(T) == 8) {
+        if (dma) {
+            switch (tile) {
+                case 0: {
+                    ProfScope ps(ex, kname<T, AMC, BNC, CMC, 4, 4, 0, true>(), gemm_flops(p), gemm_bytes(p));
+                    hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC, 4, 4, 0, true>), grid, dim3(NTH), 0, ex.stream, p);
+                } break;
+                case 1: {
+                    ProfScope ps(ex, kname<T, AMC, BNC, CMC, 2, 4, 0, true>(), gemm_flops(p), gemm_bytes(p));
+                    hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC, 2, 4, 0, true>), grid, dim3(NTH), 0, ex.stream, p);
+                } break;
+                case 2: {
+                    ProfScope ps(ex, kname<T, AMC, BNC, CMC, 4, 2, 0, true>(), gemm_flops(p), gemm_bytes(p));
+                    hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC, 4, 2, 0, true>), grid, dim3(NTH), 0, ex.stream, p);
+                } break;
+                default: {
+                    ProfScope ps(ex, kname<T, AMC, BNC, CMC, 2, 2, 0, true>(), gemm_flops(p), gemm_bytes(p));
+                    hipLaunchKernelGGL((gemm_kernel<T, AMC, BNC, CMC, 2, 2, 0, true>), grid, dim3(NTH), 0, ex.stream, p);
+                } break;
             }
             return;
         }
@@ -747,16 +954,24 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
         p.W = nullptr;
     }
     dim3 grid((unsigned)ntiles, 1, (unsigned)nsplit);
+    // direct global-to-LDS staging: FP64, unmasked operands, whole slabs, one
+    // pass over k, row offsets within 32 bits (the in-place leaf products
+    // keep the register path)
+#ifndef RFP_GEMM_DIRECT
+#define RFP_GEMM_DIRECT 1
+#endif
+    const bool dma = RFP_GEMM_DIRECT && sizeof(T) == 8 && lp == 0 && !inplace && triA == TRI_NONE &&
+                     triB == TRI_NONE && nsplit == 1 && p.k % BK == 0 && p.lda < (1 << 22) && p.ldb < (1 << 22);
     const int sel = (amc ? 4 : 0) | (bnc ? 2 : 0) | (cmc ? 1 : 0);
     switch (sel) {
-        case 0: launch<T, false, false, false>(p, grid, tile, ex, lp); break;
-        case 1: launch<T, false, false, true>(p, grid, tile, ex, lp); break;
-        case 2: launch<T, false, true, false>(p, grid, tile, ex, lp); break;
-        case 3: launch<T, false, true, true>(p, grid, tile, ex, lp); break;
-        case 4: launch<T, true, false, false>(p, grid, tile, ex, lp); break;
-        case 5: launch<T, true, false, true>(p, grid, tile, ex, lp); break;
-        case 6: launch<T, true, true, false>(p, grid, tile, ex, lp); break;
-        default: launch<T, true, true, true>(p, grid, tile, ex, lp); break;
+        case 0: launch<T, false, false, false>(p, grid, tile, ex, lp, dma); break;
+        case 1: launch<T, false, false, true>(p, grid, tile, ex, lp, dma); break;
+        case 2: launch<T, false, true, false>(p, grid, tile, ex, lp, dma); break;
+        case 3: launch<T, false, true, true>(p, grid, tile, ex, lp, dma); break;
+        case 4: launch<T, true, false, false>(p, grid, tile, ex, lp, dma); break;
+        case 5: launch<T, true, false, true>(p, grid, tile, ex, lp, dma); break;
+        case 6: launch<T, true, true, false>(p, grid, tile, ex, lp, dma); break;
+        default: launch<T, true, true, true>(p, grid, tile, ex, lp, dma); break;
     }
     if (nsplit > 1) {
         const int64_t total = m * n;
