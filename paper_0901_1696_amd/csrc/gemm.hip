@@ -420,21 +420,32 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
             int rb[2] = {rb0[0], rb0[1]};
             uint32_t cb[2] = {cb0[0], cb0[1]};
             asm volatile("" : "+v"(rb[0]), "+v"(rb[1]), "+v"(cb[0]), "+v"(cb[1]));
+            // likewise the uniform parts (each transfer's LDS base and column),
+            // which would otherwise take one scalar register each
+            int wq = wu;
+            int64_t ldq = ld;
+            asm volatile("" : "+s"(wq), "+s"(ldq));
+            ld = ldq;
+            if constexpr (MC) {
+                // transfer q of wave w: k column KS q + kq0, rows 32 part .. + 31
+                constexpr int KS = BX == 128 ? 1 : 2;
+                const int kq0 = BX == 128 ? 0 : (wq >> 1), part = BX == 128 ? wq : (wq & 1);
+                const int64_t step = (int64_t)KS * ld * 8;
+                const char* sp = src + (int64_t)kq0 * ld * 8 + cb[0];
+                double* d = X + kq0 * P + part * 32;
 #pragma unroll
-            for (int q = 0; q < BX / 8; q++) {
-                const int u = 4 * q + wu;
-                const char* sp;
-                double* d;
-                if constexpr (MC) {
-                    const int kq = u / (BX / 32);
-                    sp = src + (int64_t)kq * ld * 8 + cb[0];
-                    d = X + kq * P + (u % (BX / 32)) * 32;
-                } else {
-                    const int r = 8 * q + rb[q & 1];
-                    sp = src + (uint32_t)((r < lim ? r : lim) * (uint32_t)ld) * 8u + cb[q & 1];
-                    d = X + u * 32;
+                for (int q = 0; q < BX / 8; q++) {
+                    __builtin_amdgcn_global_load_lds((gvoid_t*)sp, (lvoid_t*)d, 4, 0, 0);
+                    sp += step;
+                    d += KS * P;
                 }
-                __builtin_amdgcn_global_load_lds((gvoid_t*)sp, (lvoid_t*)d, 4, 0, 0);
+            } else {
+#pragma unroll
+                for (int q = 0; q < BX / 8; q++) {
+                    const int r = 8 * q + rb[q & 1];
+                    const char* sp = src + (uint32_t)((r < lim ? r : lim) * (uint32_t)ld) * 8u + cb[q & 1];
+                    __builtin_amdgcn_global_load_lds((gvoid_t*)sp, (lvoid_t*)(X + (4 * q + wq) * 32), 4, 0, 0);
+                }
             }
         };
         auto dma = [&](double* XA, double* XB, int64_t k0) {
