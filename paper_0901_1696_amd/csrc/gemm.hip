@@ -440,11 +440,15 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
                     d += KS * P;
                 }
             } else {
+                // row offsets in bytes: rb ld 8 per lane, 8 q ld 8 per transfer,
+                // clamped at the last row with one min
+                const uint32_t ld8 = (uint32_t)ld * 8u, last = (uint32_t)lim * ld8;
+                const uint32_t ro[2] = {(uint32_t)rb[0] * ld8, (uint32_t)rb[1] * ld8};
 #pragma unroll
                 for (int q = 0; q < BX / 8; q++) {
-                    const int r = 8 * q + rb[q & 1];
-                    const char* sp = src + (uint32_t)((r < lim ? r : lim) * (uint32_t)ld) * 8u + cb[q & 1];
-                    __builtin_amdgcn_global_load_lds((gvoid_t*)sp, (lvoid_t*)(X + (4 * q + wq) * 32), 4, 0, 0);
+                    uint32_t o = ro[q & 1] + (uint32_t)(8 * q) * ld8;
+                    o = (o < last ? o : last) + cb[q & 1];
+                    __builtin_amdgcn_global_load_lds((gvoid_t*)(src + o), (lvoid_t*)(X + (4 * q + wq) * 32), 4, 0, 0);
                 }
             }
         };
