@@ -430,13 +430,13 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
                 // transfer q of wave w: k column KS q + kq0, rows 32 part .. + 31
                 constexpr int KS = BX == 128 ? 1 : 2;
                 const int kq0 = BX == 128 ? 0 : (wq >> 1), part = BX == 128 ? wq : (wq & 1);
-                const int64_t step = (int64_t)KS * ld * 8;
-                const char* sp = src + (int64_t)kq0 * ld * 8 + cb[0];
+                const uint32_t step = (uint32_t)(KS * ld * 8);
+                uint32_t o = (uint32_t)(kq0 * ld * 8) + cb[0];
                 double* d = X + kq0 * P + part * 32;
 #pragma unroll
                 for (int q = 0; q < BX / 8; q++) {
-                    __builtin_amdgcn_global_load_lds((gvoid_t*)sp, (lvoid_t*)d, 4, 0, 0);
-                    sp += step;
+                    __builtin_amdgcn_global_load_lds((gvoid_t*)(src + o), (lvoid_t*)d, 4, 0, 0);
+                    o += step;
                     d += KS * P;
                 }
             } else {
