@@ -107,6 +107,7 @@ struct GemmParams {
     int64_t kchunk;
     T* W;  // split-K partials, [split][n][m], or null
     const int* info;
+    int prio;  // raise the waves' issue priority
 };
 
 // A mask keeps (i, kk) when lo <= kk - i <= hi.
@@ -159,6 +160,7 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
 {
     constexpr int BM = 32 * WMB, BN = 32 * WNB;
     if (p.info && *p.info) return;
+    if (p.prio) __builtin_amdgcn_s_setprio(3);
 
     int64_t ti, tj;
     {
@@ -911,6 +913,7 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
     p.triB = triB;
     p.c_lower = c_lower ? 1 : 0;
     p.info = ex.info;
+    p.prio = ex.prio;
     int64_t tm, tn;
     // low-precision operands for the bulk updates only: in-place products
     // (the leaf-level panel solves) stay in FP32

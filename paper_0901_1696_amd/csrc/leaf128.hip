@@ -10,6 +10,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void potrf128_kernel(Mat<T> A, int nb, T* winv, int* info, int64_t info_base)
 {
     if (info && *info) return;
+    // always on the critical path: first in issue when sharing a compute unit with bulk work
+    __builtin_amdgcn_s_setprio(3);
     __shared__ Leaf128Smem<T> sm;
     (void)potrf128_block<T>(sm, A, nb, winv, info, info_base);
 }

@@ -547,6 +547,9 @@ static Run<T> make_run(rfp_context* h, hipStream_t s, int* info)
     r.ex3.stream = h->aux2;
     r.ex3.splitk_ws = nullptr;  // its GEMMs never split K: no workspace shared with the other streams
     r.ex3.splitk_bytes = 0;
+    // the caller's stream carries the critical path (panels and lookahead);
+    // the auxiliary streams' bulk work yields issue slots to it
+    r.ex.prio = 1;
     r.joinev = h->aux2 ? h->join : nullptr;
     return r;
 }

@@ -167,6 +167,8 @@ struct Exec {
     Profiler* prof;     // optional per-launch event timing
     int lowp = 0;       // FP32 GEMMs: 0 FP32 operands, 1 FP16, 2 BF16 (not for in-place products)
     const TuneTable* tune = nullptr;  // autotuned configurations, if any
+    int prio = 0;  // 1: the kernels' waves take the highest issue priority (the critical path, which
+                   // shares compute units with bulk work on the other streams)
 };
 
 // Brackets one kernel launch with HIP events on the launch stream when
