@@ -300,6 +300,11 @@ struct Run {
     // the event that marks columns [0, o1) (and their leaf inverses) final on
     // stream 0.
     static constexpr int64_t WIDE_PANELS_ABOVE = 6144;  // trailing order (best of 3072-8192 at n = 20000)
+#ifndef RFP_LOOKAHEAD_FIRST_BELOW
+#define RFP_LOOKAHEAD_FIRST_BELOW 6144
+#endif
+    // trailing order below which the bulk update waits for the lookahead
+    static constexpr int64_t LOOKAHEAD_FIRST_BELOW = RFP_LOOKAHEAD_FIRST_BELOW;
     template <typename F = void (*)(int64_t, hipEvent_t)>
     void potrf_la(int64_t n, Mat<T> A, int64_t goff, T* winv, F* fork = nullptr)
     {
@@ -318,11 +323,17 @@ struct Run {
             // lookahead: the next panel column (lower part of its diagonal block), then that block
             wait(0, bulk_prev);
             mm(n - o1, w1, w, T(-1), A.sub(o1, o), TRI_NONE, A.sub(o1, o), TRI_NONE, T(1), A.sub(o1, o1), true);
+            // Small trailing orders: the bulk update also waits for the
+            // lookahead, so that it overlaps the leaf chain (one workgroup at a
+            // time) instead of taking the compute units the lookahead needs;
+            // above, the bulk update is the longer stream and starts at once.
+            const hipEvent_t la_done = n - o1 <= LOOKAHEAD_FIRST_BELOW && o2 < n ? record(0) : nullptr;
             potrf_rec(w1, A.sub(o1, o1), goff + o1, winv_at(o1));
             // bulk: columns beyond the next panel
             bulk_prev = nullptr;
             if (o2 < n) {
                 wait(1, panel_done);
+                wait(1, la_done);
                 on = two_streams() ? 1 : 0;
                 mm(n - o2, n - o2, w, T(-1), A.sub(o2, o), TRI_NONE, A.sub(o2, o), TRI_NONE, T(1), A.sub(o2, o2), true);
                 on = 0;
