@@ -349,19 +349,34 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
         if (kb > 0) wnext = winv[(o - D + t / 16) * N + o - D + t % 16];
         const int r0 = o + D, nrb = (N - r0) / 16;
         const int rbs[2] = {w, w < 3 ? 6 - w : 7};
-        acc_t tacc[2];
-#pragma unroll
-        for (int q2 = 0; q2 < 2; q2++) {
-            const int rb = rbs[q2];
-            tacc[q2] = acc_t{0, 0, 0, 0};
-            if (rb < nrb) {
-                const T* Wr = L + prow(r0 + rb * 16 + r) + r0;  // W_RR, row r of block rb
-                const int kend = (rb + 1) * 16;                 // W_RR(i, k) = 0 for k > i
-#pragma unroll 4
-                for (int kk = 0; kk < kend; kk += 4)
-                    tacc[q2] = M16<T>::op(L[prow(r0 + kk + g) + o + r], Wr[kk + g], tacc[q2]);
-            }
+        // W_RR(i, k) = 0 for k past row i's block, so row block rb needs
+        // k < 16 (rb + 1).  The two row blocks share the L_Rj operand, and
+        // each sum is split over even and odd k steps: four independent
+        // accumulation chains instead of one or two long ones.
+        const int ke0 = rbs[0] < nrb ? (rbs[0] + 1) * 16 : 0, ke1 = rbs[1] < nrb ? (rbs[1] + 1) * 16 : 0;
+        const T* Wr0 = L + prow(r0 + rbs[0] * 16 + r) + r0;  // W_RR, row r of each block
+        const T* Wr1 = L + prow(r0 + rbs[1] * 16 + r) + r0;
+        acc_t t00 = acc_t{0, 0, 0, 0}, t01 = t00, t10 = t00, t11 = t00;
+        const int kboth = ke0 < ke1 ? ke0 : ke1;
+        int kk = 0;
+#pragma unroll 2
+        for (; kk < kboth; kk += 8) {
+            const T l0 = L[prow(r0 + kk + g) + o + r], l1 = L[prow(r0 + kk + 4 + g) + o + r];
+            t00 = M16<T>::op(l0, Wr0[kk + g], t00);
+            t10 = M16<T>::op(l0, Wr1[kk + g], t10);
+            t01 = M16<T>::op(l1, Wr0[kk + 4 + g], t01);
+            t11 = M16<T>::op(l1, Wr1[kk + 4 + g], t11);
         }
+        for (int k2 = kk; k2 < ke0; k2 += 8) {
+            t00 = M16<T>::op(L[prow(r0 + k2 + g) + o + r], Wr0[k2 + g], t00);
+            t01 = M16<T>::op(L[prow(r0 + k2 + 4 + g) + o + r], Wr0[k2 + 4 + g], t01);
+        }
+#pragma unroll 2
+        for (int k2 = kk; k2 < ke1; k2 += 8) {
+            t10 = M16<T>::op(L[prow(r0 + k2 + g) + o + r], Wr1[k2 + g], t10);
+            t11 = M16<T>::op(L[prow(r0 + k2 + 4 + g) + o + r], Wr1[k2 + 4 + g], t11);
+        }
+        const acc_t tacc[2] = {t00 + t01, t10 + t11};
         __syncthreads();  // every wave has read L_Rj; W_jj is in Wd
 #pragma unroll
         for (int q2 = 0; q2 < 2; q2++) {
