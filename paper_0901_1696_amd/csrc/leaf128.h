@@ -320,12 +320,22 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
         if (t == 0 && info) *info = (int)(info_base + f);
         return f;
     }
-    // store the factor: its own lower triangle only
-#pragma unroll 16
-    for (int idx = t; idx < N * N; idx += 256) {
-        const int i = colmajor ? idx % N : idx / N;
-        const int j = colmajor ? idx / N : idx % N;
-        if (i < nb && j <= i) A.at(i, j) = L[prow(i) + j];
+    // store the factor: its own lower triangle only, with stepped addresses
+    // (column-major: each thread one row, every other column; row-major: one
+    // row per wave and step, one column per lane)
+    if (colmajor) {
+        const int i = t & (N - 1), j0 = t >> 7;
+        if (i < nb) {
+            T* a = A.p + i + (int64_t)j0 * A.cs;
+            const T* l = L + prow(i) + j0;
+            const int64_t step = 2 * A.cs;
+            for (int j = j0; j <= i; j += 2, a += step, l += 2) *a = *l;
+        }
+    } else {
+        const int j = t & (N - 1);
+        const int64_t jo = (int64_t)j * A.cs;
+        for (int i = t >> 7; i < nb; i += 2)
+            if (j <= i) A.p[(int64_t)i * A.rs + jo] = L[prow(i) + j];
     }
     RFP_LEAF_STAMP(30);
     if (!winv) {
