@@ -224,19 +224,36 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int r = lane & 15, g = lane >> 4;  // MFMA operand row and k offset of the lane
+    RFP_LEAF_STAMP(32);
     if (t == 0) fail = 0;
     const bool colmajor = A.rs == 1;
     // the packed triangle (and the rest of each diagonal block, as zeros);
     // rows past nb are the identity
-#pragma unroll 16
-    for (int it = 0; it < N * N / 256; it++) {
-        const int idx = t + it * 256;
-        const int i = colmajor ? idx % N : idx / N;
-        const int j = colmajor ? idx / N : idx % N;
-        if (j < 16 * ((i >> 4) + 1)) {
-            T v = (i == j) ? T(1) : T(0);
-            if (i < nb && j <= i) v = A.at(i, j);
-            L[prow(i) + j] = v;
+    // In batches of 16 per thread: all loads first (each lane from its
+    // element clamped into the stored lower triangle, a valid address), then
+    // the LDS stores.  A's pointer is generic, so a load written after an LDS
+    // store could not be moved ahead of it: interleaved, every element would
+    // wait for its own load.
+    for (int it0 = 0; it0 < N * N / 256; it0 += 16) {
+        T a[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int idx = t + (it0 + u) * 256;
+            const int i = colmajor ? idx % N : idx / N;
+            const int j = colmajor ? idx / N : idx % N;
+            const int ic = i < nb ? i : nb - 1, jc = j < ic ? j : ic;
+            a[u] = nb > 0 ? A.at(ic, jc) : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int idx = t + (it0 + u) * 256;
+            const int i = colmajor ? idx % N : idx / N;
+            const int j = colmajor ? idx / N : idx % N;
+            if (j < 16 * ((i >> 4) + 1)) {
+                T v = (i == j) ? T(1) : T(0);
+                if (i < nb && j <= i) v = a[u];
+                L[prow(i) + j] = v;
+            }
         }
     }
     __syncthreads();
@@ -323,19 +340,38 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
     // store the factor: its own lower triangle only, with stepped addresses
     // (column-major: each thread one row, every other column; row-major: one
     // row per wave and step, one column per lane)
+    // (LDS reads batched ahead of the stores, as for the load; reads past a
+    // packed row stay inside L and are not stored)
     if (colmajor) {
         const int i = t & (N - 1), j0 = t >> 7;
         if (i < nb) {
             T* a = A.p + i + (int64_t)j0 * A.cs;
             const T* l = L + prow(i) + j0;
-            const int64_t step = 2 * A.cs;
-            for (int j = j0; j <= i; j += 2, a += step, l += 2) *a = *l;
+            for (int u0 = 0; u0 < N / 2 && j0 + 2 * u0 <= i; u0 += 16) {
+                T v[16];
+#pragma unroll
+                for (int u = 0; u < 16; u++) v[u] = l[2 * (u0 + u)];
+#pragma unroll
+                for (int u = 0; u < 16; u++)
+                    if (j0 + 2 * (u0 + u) <= i) a[2 * (int64_t)(u0 + u) * A.cs] = v[u];
+            }
         }
     } else {
         const int j = t & (N - 1);
         const int64_t jo = (int64_t)j * A.cs;
-        for (int i = t >> 7; i < nb; i += 2)
-            if (j <= i) A.p[(int64_t)i * A.rs + jo] = L[prow(i) + j];
+        for (int i0 = t >> 7; i0 < nb; i0 += 32) {
+            T v[16];
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const int i = i0 + 2 * u;
+                v[u] = L[prow(i < N ? i : N - 1) + j];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const int i = i0 + 2 * u;
+                if (i < nb && j <= i) A.p[(int64_t)i * A.rs + jo] = v[u];
+            }
+        }
     }
     RFP_LEAF_STAMP(30);
     if (!winv) {
@@ -408,11 +444,19 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
     }
     __syncthreads();
     RFP_LEAF_STAMP(31);
-    // W row-major into winv (zero above the diagonal, identity on padding)
-    for (int idx = t; idx < N * N; idx += 256) {
-        const int i = idx / N, j = idx % N;
-        winv[idx] = (j <= i) ? L[prow(i) + j] : T(0);
+    // W row-major into winv (zero above the diagonal, identity on padding),
+    // LDS reads batched ahead of the stores
+    for (int it0 = 0; it0 < N * N / 256; it0 += 16) {
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int idx = t + (it0 + u) * 256, i = idx / N, j = idx % N;
+            v[u] = (j <= i) ? L[prow(i) + j] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; u++) winv[t + (it0 + u) * 256] = v[u];
     }
+    RFP_LEAF_STAMP(33);
     __syncthreads();
     return 0;
 }
