@@ -229,15 +229,15 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
     const bool colmajor = A.rs == 1;
     // the packed triangle (and the rest of each diagonal block, as zeros);
     // rows past nb are the identity
-    // In batches of 16 per thread: all loads first (each lane from its
+    // In two batches of 32 per thread: all loads first (each lane from its
     // element clamped into the stored lower triangle, a valid address), then
     // the LDS stores.  A's pointer is generic, so a load written after an LDS
     // store could not be moved ahead of it: interleaved, every element would
     // wait for its own load.
-    for (int it0 = 0; it0 < N * N / 256; it0 += 16) {
-        T a[16];
+    for (int it0 = 0; it0 < N * N / 256; it0 += 32) {
+        T a[32];
 #pragma unroll
-        for (int u = 0; u < 16; u++) {
+        for (int u = 0; u < 32; u++) {
             const int idx = t + (it0 + u) * 256;
             const int i = colmajor ? idx % N : idx / N;
             const int j = colmajor ? idx / N : idx % N;
@@ -245,7 +245,7 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
             a[u] = nb > 0 ? A.at(ic, jc) : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < 16; u++) {
+        for (int u = 0; u < 32; u++) {
             const int idx = t + (it0 + u) * 256;
             const int i = colmajor ? idx % N : idx / N;
             const int j = colmajor ? idx / N : idx % N;
