@@ -654,7 +654,10 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     // applied, on stream 0 after step 1.
     // chunk: 2048 columns (512-4096 measured at n = 20000: 1536-2048 best),
     // at most half of T1 so that smaller triangles still get two chunks
-    const int64_t SCHUNK = std::min<int64_t>(2048, std::max<int64_t>(4 * r.nb, b.m1 / 2 / r.nb * r.nb));
+#ifndef RFP_SCHUNK_MAX
+#define RFP_SCHUNK_MAX 2048
+#endif
+    const int64_t SCHUNK = std::min<int64_t>(RFP_SCHUNK_MAX, std::max<int64_t>(4 * r.nb, b.m1 / 2 / r.nb * r.nb));
     int64_t done = 0;
     hipEvent_t joined = nullptr;
     auto fork = [&](int64_t o1, hipEvent_t ev) {
