@@ -300,10 +300,11 @@ struct Run {
     // the event that marks columns [0, o1) (and their leaf inverses) final on
     // stream 0.
     static constexpr int64_t WIDE_PANELS_ABOVE = 6144;  // trailing order (best of 3072-8192 at n = 20000)
+    // trailing order up to which the bulk update waits for the lookahead:
+    // every order by default (at n = 20000 better than 0, 2048-6144)
 #ifndef RFP_LOOKAHEAD_FIRST_BELOW
-#define RFP_LOOKAHEAD_FIRST_BELOW 6144
+#define RFP_LOOKAHEAD_FIRST_BELOW INT64_MAX
 #endif
-    // trailing order below which the bulk update waits for the lookahead
     static constexpr int64_t LOOKAHEAD_FIRST_BELOW = RFP_LOOKAHEAD_FIRST_BELOW;
     template <typename F = void (*)(int64_t, hipEvent_t)>
     void potrf_la(int64_t n, Mat<T> A, int64_t goff, T* winv, F* fork = nullptr)
@@ -323,10 +324,9 @@ struct Run {
             // lookahead: the next panel column (lower part of its diagonal block), then that block
             wait(0, bulk_prev);
             mm(n - o1, w1, w, T(-1), A.sub(o1, o), TRI_NONE, A.sub(o1, o), TRI_NONE, T(1), A.sub(o1, o1), true);
-            // Small trailing orders: the bulk update also waits for the
-            // lookahead, so that it overlaps the leaf chain (one workgroup at a
-            // time) instead of taking the compute units the lookahead needs;
-            // above, the bulk update is the longer stream and starts at once.
+            // The bulk update also waits for the lookahead, so that it overlaps
+            // the leaf chain (one workgroup at a time) instead of taking the
+            // compute units the lookahead (on the critical path) needs.
             const hipEvent_t la_done = n - o1 <= LOOKAHEAD_FIRST_BELOW && o2 < n ? record(0) : nullptr;
             potrf_rec(w1, A.sub(o1, o1), goff + o1, winv_at(o1));
             // bulk: columns beyond the next panel
@@ -652,10 +652,10 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     //   A22          -= L21(:, c0:c1) L21(:, c0:c1)^T   (step 3's share of the chunk)
     // The columns after the last chunk are solved, and their share of step 3
     // applied, on stream 0 after step 1.
-    // chunk: 2048 columns (512-4096 measured at n = 20000: 1536-2048 best),
+    // chunk: at most 1536 columns (512-4096 measured at n = 20000),
     // at most half of T1 so that smaller triangles still get two chunks
 #ifndef RFP_SCHUNK_MAX
-#define RFP_SCHUNK_MAX 2048
+#define RFP_SCHUNK_MAX 1536  // of 1024-2560 at n = 20000
 #endif
     const int64_t SCHUNK = std::min<int64_t>(RFP_SCHUNK_MAX, std::max<int64_t>(4 * r.nb, b.m1 / 2 / r.nb * r.nb));
     int64_t done = 0;
