@@ -299,7 +299,11 @@ struct Run {
     // fork: after the panel solve of every step, fork(o1, ev) is called with
     // the event that marks columns [0, o1) (and their leaf inverses) final on
     // stream 0.
-    static constexpr int64_t WIDE_PANELS_ABOVE = 6144;  // trailing order (best of 3072-8192 at n = 20000)
+#ifndef RFP_WIDE_PANELS_ABOVE
+#define RFP_WIDE_PANELS_ABOVE 6144
+#endif
+    // trailing order above which panels are 256 wide (best of 3072-8192 at n = 20000)
+    static constexpr int64_t WIDE_PANELS_ABOVE = RFP_WIDE_PANELS_ABOVE;
     // trailing order up to which the bulk update waits for the lookahead:
     // every order by default (at n = 20000 better than 0, 2048-6144)
 #ifndef RFP_LOOKAHEAD_FIRST_BELOW
