@@ -230,6 +230,39 @@ int rfp_tune_save(rfp_handle_t h, const char* path);
 int rfp_tune_load(rfp_handle_t h, const char* path);
 
 /* ------------------------------------------------------------------------
+ * Factorization schedule (not in the paper: the paper's four steps run one
+ * after the other; here they are overlapped on three streams).  These knobs
+ * change only the order and grouping of the same block operations of
+ * Section 3 (the 2 x 2 partition of Figure 3 applied to panels of the two
+ * diagonal triangles), never the arithmetic each block does, so every
+ * setting computes the same factor up to rounding.
+ *   wide_panels_above: a diagonal triangle's panels are 256 columns wide
+ *     while its trailing order exceeds this value, 128 wide after
+ *     (default 6144; 0 = always 256 wide; a value >= n = always 128 wide).
+ *   chunk_max: the off-diagonal solve (step 2) and its share of step 3 run
+ *     by chunks of at most this many columns on a third stream, overlapped
+ *     with step 1 (default 1536; at least 512 is used; 0 disables the
+ *     overlap, so steps 2 and 3 follow step 1).
+ *   lookahead_wait_below: trailing order up to which each bulk trailing
+ *     update waits for the critical stream's lookahead product (default
+ *     INT64_MAX: always; 0: never).
+ *   leaf_lds_pad: bytes of LDS the FP64 128-row diagonal leaf reserves
+ *     beyond what it uses, to keep large GEMM workgroups off its compute unit
+ *     (default 24576; 0 to 65536).
+ * rfp_set_schedule(h, NULL) restores the defaults; illegal values return
+ * -2 (a field < 0, or leaf_lds_pad > 65536) and leave the schedule as it
+ * was.  The schedule is host state of the handle; calls already enqueued are
+ * not affected.  Argument order: H=1, SCHED=2. */
+typedef struct {
+    int64_t wide_panels_above;
+    int64_t chunk_max;
+    int64_t lookahead_wait_below;
+    int64_t leaf_lds_pad;
+} rfp_schedule_t;
+int rfp_set_schedule(rfp_handle_t h, const rfp_schedule_t* sched);
+int rfp_get_schedule(rfp_handle_t h, rfp_schedule_t* sched);
+
+/* ------------------------------------------------------------------------
  * Kernel timing (introspection, used by the benchmark for its roofline).
  * While enabled, every kernel the handle's calls launch is bracketed by a pair
  * of HIP events on the call's stream.  rfp_profile_read waits for the device,
@@ -252,7 +285,8 @@ int rfp_profile_read(rfp_handle_t h, rfp_profile_entry* out, int cap, int* count
  * The drivers are the paper's 2 x 2 block algorithms (Figure 3, Sections 3-5)
  * applied recursively; rfp_plan records the sequence of primitives that
  * rfp_dpftrf ('F'), rfp_dpftrs ('S') or rfp_dpftri ('I') would enqueue for
- * the given arguments, without launching anything, so that the block
+ * the given arguments and schedule (sched: as rfp_set_schedule; NULL = the
+ * defaults), without launching anything, so that the block
  * algebra, the views into the RFP rectangle and the aliasing rules can be
  * checked on a machine without a GPU.  Each record names views as (buffer,
  * element offset, row stride, column stride) with buffer one of the
@@ -302,8 +336,8 @@ typedef struct {
     int64_t info_base;
     int64_t d[4], w[4];       /* RFP_PLAN_BLOCK_SOLVE: right-hand sides and block inverses */
 } rfp_plan_op;
-int rfp_plan(char routine, char transr, char uplo, int64_t n, int64_t nrhs, int64_t ldb, rfp_plan_op* ops,
-             int64_t cap, int64_t* count);
+int rfp_plan(char routine, char transr, char uplo, int64_t n, int64_t nrhs, int64_t ldb,
+             const rfp_schedule_t* sched, rfp_plan_op* ops, int64_t cap, int64_t* count);
 
 #ifdef __cplusplus
 }

@@ -70,6 +70,8 @@ def _declare(L):
     L.orc_norm_fro.restype = ctypes.c_double
     L.orc_pfcast_s.argtypes = [_chr, _chr, _i64, _dp, ctypes.c_int, ctypes.c_double, _dp, _vp]
     L.orc_backward_error.argtypes = [_chr, _chr, _i64, _i64, _dp, _dp, _i64, _dp, _i64]
+    L.orc_forward_error.restype = ctypes.c_double
+    L.orc_forward_error.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64]
     L.orc_factor_residual.restype = ctypes.c_double
     L.orc_factor_residual.argtypes = [_chr, _chr, _i64, _dp, _dp]
     L.orc_inverse_residual.restype = ctypes.c_double
@@ -209,6 +211,14 @@ def backward_error(transr, uplo, n, arf_a, b, x):
     arf_a = np.ascontiguousarray(arf_a, dtype=np.float64)
     return lib().orc_backward_error(_c(transr), _c(uplo), n, b.shape[1], _p(arf_a),
                                     _p(b), b.shape[0], _p(x), x.shape[0])
+
+
+def forward_error(x, x_ref):
+    """max over columns ||x - x_ref||_inf / ||x_ref||_inf."""
+    x = _f64(x if x.ndim == 2 else x.reshape(-1, 1))
+    x_ref = _f64(x_ref if x_ref.ndim == 2 else x_ref.reshape(-1, 1))
+    assert x.shape == x_ref.shape
+    return lib().orc_forward_error(x.shape[0], x.shape[1], _p(x), x.shape[0], _p(x_ref), x_ref.shape[0])
 
 
 def factor_residual(transr, uplo, n, arf_a, arf_l):

@@ -490,6 +490,26 @@ double orc_backward_error(char transr, char uplo, i64 n, i64 nrhs, const double 
     return worst;
 }
 
+/* Normwise forward error of a solve against a reference solution, max over
+ * columns: ||x - x_ref||_inf / ||x_ref||_inf (an exact zero column of x_ref
+ * gives ||x||_inf).  Differences accumulate in long double. */
+double orc_forward_error(i64 n, i64 nrhs, const double *x, i64 ldx, const double *xr, i64 ldr)
+{
+    double worst = 0.0;
+    for (i64 c = 0; c < nrhs; c++) {
+        long double dmax = 0.0L, rmax = 0.0L;
+        for (i64 i = 0; i < n; i++) {
+            long double d = fabsl((long double)x[i + c * ldx] - (long double)xr[i + c * ldr]);
+            long double r = fabsl((long double)xr[i + c * ldr]);
+            if (d > dmax) dmax = d;
+            if (r > rmax) rmax = r;
+        }
+        double e = rmax > 0 ? (double)(dmax / rmax) : (double)dmax;
+        if (e > worst) worst = e;
+    }
+    return worst;
+}
+
 /* ||L L^T - A||_F / ||A||_F, with L the PFTRF output for A (same layout). */
 double orc_factor_residual(char transr, char uplo, i64 n, const double *arf_a, const double *arf_l)
 {

@@ -63,7 +63,9 @@ _SIGS = {
     "rfp_dpfsv_batched": [_vp, _int, _i64, _vp, _vp, _vp, _int, ctypes.c_double, _int, _vp, _vp, _vp],
     "rfp_dpfsv_ir": [_vp, _int, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp, _i64, ctypes.c_double, _int,
                      ctypes.POINTER(_int), ctypes.POINTER(_int), _vp],
-    "rfp_plan": [_chr, _chr, _chr, _i64, _i64, _i64, _vp, _i64, ctypes.POINTER(_i64)],
+    "rfp_plan": [_chr, _chr, _chr, _i64, _i64, _i64, _vp, _vp, _i64, ctypes.POINTER(_i64)],
+    "rfp_set_schedule": [_vp, _vp],
+    "rfp_get_schedule": [_vp, _vp],
     "rfp_profile_enable": [_vp, _int],
     "rfp_profile_read": [_vp, _vp, _int, ctypes.POINTER(_int)],
 }
@@ -184,16 +186,56 @@ def rfp_profile_read(h):
             for e in list(buf)[:count.value]}
 
 
-def rfp_plan(routine, transr, uplo, n, nrhs=0, ldb=None):
+class Schedule(ctypes.Structure):
+    """Layout of ``rfp_schedule_t`` (include/rfp.h): the factorization schedule knobs."""
+    _fields_ = [("wide_panels_above", _i64), ("chunk_max", _i64), ("lookahead_wait_below", _i64),
+                ("leaf_lds_pad", _i64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+INT64_MAX = 2 ** 63 - 1
+DEFAULT_SCHEDULE = dict(wide_panels_above=6144, chunk_max=1536, lookahead_wait_below=INT64_MAX,
+                        leaf_lds_pad=24576)
+
+
+def _schedule(sched):
+    """A Schedule from None (the defaults), a Schedule, or a dict of fields
+    (missing fields take their defaults)."""
+    if sched is None or isinstance(sched, Schedule):
+        return sched
+    vals = dict(DEFAULT_SCHEDULE)
+    vals.update(sched)
+    return Schedule(**vals)
+
+
+def rfp_set_schedule(h, sched=None):
+    """Set the handle's factorization schedule (None restores the defaults)."""
+    sc = _schedule(sched)
+    _check("rfp_set_schedule", lib().rfp_set_schedule(h.value, None if sc is None else ctypes.byref(sc)))
+
+
+def rfp_get_schedule(h):
+    sc = Schedule()
+    _check("rfp_get_schedule", lib().rfp_get_schedule(h.value, ctypes.byref(sc)))
+    return sc.as_dict()
+
+
+def rfp_plan(routine, transr, uplo, n, nrhs=0, ldb=None, sched=None):
     """Primitive sequence of PFTRF ('F'), PFTRS ('S') or PFTRI ('I'), recorded
-    on the host without touching a device (see include/rfp.h)."""
+    on the host without touching a device (see include/rfp.h); sched as for
+    :func:`rfp_set_schedule`."""
     ldb = max(1, n) if ldb is None else ldb
+    sc = _schedule(sched)
+    psc = None if sc is None else ctypes.byref(sc)
     count = _i64(0)
-    rc = lib().rfp_plan(_c(routine), _c(transr), _c(uplo), n, nrhs, ldb, None, 0, ctypes.byref(count))
+    rc = lib().rfp_plan(_c(routine), _c(transr), _c(uplo), n, nrhs, ldb, psc, None, 0, ctypes.byref(count))
     if rc != 0:
         raise RfpError("rfp_plan", rc)
     ops = (PlanOp * max(1, count.value))()
-    rc = lib().rfp_plan(_c(routine), _c(transr), _c(uplo), n, nrhs, ldb, ops, count.value, ctypes.byref(count))
+    rc = lib().rfp_plan(_c(routine), _c(transr), _c(uplo), n, nrhs, ldb, psc, ops, count.value,
+                        ctypes.byref(count))
     if rc != 0:
         raise RfpError("rfp_plan", rc)
     return list(ops)[:count.value]

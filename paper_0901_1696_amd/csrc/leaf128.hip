@@ -25,13 +25,11 @@ hipError_t potrf128_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info
         snprintf(name[ti], sizeof name[ti], "rfp::potrf128_kernel<%s>(rfp::Mat<%s>, int, %s*, int*, long)",
                  ti ? "float" : "double", ti ? "float" : "double", ti ? "float" : "double");
     ProfScope ps(ex, name[ti], 2.0 * nb * nb * nb / 3.0, sizeof(T) * (double)nb * nb * 2.0);
-    // The FP64 leaf reserves LDS it does not use, so that no 128 x 128 GEMM
-    // workgroup (64-72 KB) of the bulk updates can share its compute unit
-    // (the smaller panel products still can): it is on the critical path.
-#ifndef RFP_LEAF_LDS_PAD
-#define RFP_LEAF_LDS_PAD (24 * 1024)
-#endif
-    const unsigned pad = sizeof(T) == 8 ? RFP_LEAF_LDS_PAD : 0;
+    // The FP64 leaf reserves LDS it does not use (ex.leaf_pad bytes, 24 KB by
+    // default), so that no 128 x 128 GEMM workgroup (64-72 KB) of the bulk
+    // updates can share its compute unit (the smaller panel products still
+    // can): it is on the critical path.
+    const unsigned pad = sizeof(T) == 8 ? (unsigned)ex.leaf_pad : 0;
     hipLaunchKernelGGL((potrf128_kernel<T>), dim3(1), dim3(256), pad, ex.stream, A, nb, winv, ex.info, info_base);
     return hipGetLastError();
 }

@@ -125,6 +125,7 @@ struct rfp_context {
     size_t bat_bytes;
     int cus;              // compute units of the device
     rfp::TuneTable* tune; // autotuned kernel configurations (null: built-in rules)
+    rfp_schedule_t sched; // factorization schedule knobs
 };
 
 namespace rfp {
@@ -299,23 +300,16 @@ struct Run {
     // fork: after the panel solve of every step, fork(o1, ev) is called with
     // the event that marks columns [0, o1) (and their leaf inverses) final on
     // stream 0.
-#ifndef RFP_WIDE_PANELS_ABOVE
-#define RFP_WIDE_PANELS_ABOVE 6144
-#endif
-    // trailing order above which panels are 256 wide (best of 3072-8192 at n = 20000)
-    static constexpr int64_t WIDE_PANELS_ABOVE = RFP_WIDE_PANELS_ABOVE;
-    // trailing order up to which the bulk update waits for the lookahead:
-    // every order by default (at n = 20000 better than 0, 2048-6144)
-#ifndef RFP_LOOKAHEAD_FIRST_BELOW
-#define RFP_LOOKAHEAD_FIRST_BELOW INT64_MAX
-#endif
-    static constexpr int64_t LOOKAHEAD_FIRST_BELOW = RFP_LOOKAHEAD_FIRST_BELOW;
+    // trailing order above which panels are 2 nb wide, and trailing order up
+    // to which the bulk update waits for the lookahead (the schedule knobs)
+    int64_t wide_panels_above = DEFAULT_WIDE_PANELS_ABOVE;
+    int64_t lookahead_wait_below = DEFAULT_LOOKAHEAD_WAIT_BELOW;
     template <typename F = void (*)(int64_t, hipEvent_t)>
     void potrf_la(int64_t n, Mat<T> A, int64_t goff, T* winv, F* fork = nullptr)
     {
         if (n <= 0) return;
         auto winv_at = [&](int64_t o) { return winv + (o / nb) * nb * nb; };
-        auto width = [&](int64_t o) { return std::min<int64_t>(n - o > WIDE_PANELS_ABOVE ? 2 * nb : nb, n - o); };
+        auto width = [&](int64_t o) { return std::min<int64_t>(n - o > wide_panels_above ? 2 * nb : nb, n - o); };
         int64_t o = 0, w = width(0);
         potrf_rec(w, A, goff, winv);
         hipEvent_t bulk_prev = nullptr;
@@ -331,7 +325,7 @@ struct Run {
             // The bulk update also waits for the lookahead, so that it overlaps
             // the leaf chain (one workgroup at a time) instead of taking the
             // compute units the lookahead (on the critical path) needs.
-            const hipEvent_t la_done = n - o1 <= LOOKAHEAD_FIRST_BELOW && o2 < n ? record(0) : nullptr;
+            const hipEvent_t la_done = n - o1 <= lookahead_wait_below && o2 < n ? record(0) : nullptr;
             potrf_rec(w1, A.sub(o1, o1), goff + o1, winv_at(o1));
             // bulk: columns beyond the next panel
             bulk_prev = nullptr;
@@ -541,8 +535,24 @@ static int next_epoch(rfp_context* h, hipStream_t s)
     return ++h->epoch;
 }
 
+static rfp_schedule_t default_schedule()
+{
+    rfp_schedule_t sc;
+    sc.wide_panels_above = DEFAULT_WIDE_PANELS_ABOVE;
+    sc.chunk_max = DEFAULT_CHUNK_MAX;
+    sc.lookahead_wait_below = DEFAULT_LOOKAHEAD_WAIT_BELOW;
+    sc.leaf_lds_pad = DEFAULT_LEAF_LDS_PAD;
+    return sc;
+}
+
+static bool bad_schedule(const rfp_schedule_t& sc)
+{
+    return sc.wide_panels_above < 0 || sc.chunk_max < 0 || sc.lookahead_wait_below < 0 || sc.leaf_lds_pad < 0 ||
+           sc.leaf_lds_pad > MAX_LEAF_LDS_PAD;
+}
+
 template <typename T>
-static Run<T> make_run(rfp_context* h, hipStream_t s, int* info)
+static Run<T> make_run(rfp_context* h, hipStream_t s, int* info, int lowp = 0)
 {
     Run<T> r;
     r.ex.stream = s;
@@ -558,6 +568,11 @@ static Run<T> make_run(rfp_context* h, hipStream_t s, int* info)
     r.nev = h->nev;
     r.evi = &h->evi;
     r.ex.tune = r.ex2.tune = h->tune;
+    // low-precision operands for every non-in-place product of all three streams
+    r.ex.lowp = r.ex2.lowp = lowp;
+    r.ex.leaf_pad = r.ex2.leaf_pad = (int)h->sched.leaf_lds_pad;
+    r.wide_panels_above = h->sched.wide_panels_above;
+    r.lookahead_wait_below = h->sched.lookahead_wait_below;
     r.ex3 = r.ex;
     r.ex3.stream = h->aux2;
     r.ex3.splitk_ws = nullptr;  // its GEMMs never split K: no workspace shared with the other streams
@@ -619,7 +634,7 @@ static T* plan_base(int buf)
 
 template <typename T>
 static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf, int* info, hipStream_t s,
-                      PlanRec* rec = nullptr, int lowp = 0)
+                      PlanRec* rec = nullptr, int lowp = 0, const rfp_schedule_t* plan_sched = nullptr)
 {
     if (!h && !rec) return RFP_ERR_HANDLE;
     if (bad_tr(transr)) return -1;
@@ -633,14 +648,19 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     Run<T> r;
     T* winv;
     DeviceGuard g(rec ? -1 : h->device);
+    rfp_schedule_t sc;
     if (rec) {
+        sc = plan_sched ? *plan_sched : default_schedule();
+        if (bad_schedule(sc)) return -8;
         r.rec = rec;
+        r.wide_panels_above = sc.wide_panels_above;
+        r.lookahead_wait_below = sc.lookahead_wait_below;
         winv = plan_base<T>(RFP_PLAN_BUF_WORK);
     } else {
         if (n == 0) return set_int(s, info, 0) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
         if (prepare(h, size_t(lv) * NB2 * NB2 * sizeof(T)) != hipSuccess) return RFP_ERR_RUNTIME;
-        r = make_run<T>(h, s, info);
-        r.ex.lowp = r.ex2.lowp = lowp;
+        sc = h->sched;
+        r = make_run<T>(h, s, info, lowp);
         winv = (T*)h->inv;
     }
     r.nb = NB2;
@@ -656,12 +676,11 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     //   A22          -= L21(:, c0:c1) L21(:, c0:c1)^T   (step 3's share of the chunk)
     // The columns after the last chunk are solved, and their share of step 3
     // applied, on stream 0 after step 1.
-    // chunk: at most 1536 columns (512-4096 measured at n = 20000),
-    // at most half of T1 so that smaller triangles still get two chunks
-#ifndef RFP_SCHUNK_MAX
-#define RFP_SCHUNK_MAX 1536  // of 1024-2560 at n = 20000
-#endif
-    const int64_t SCHUNK = std::min<int64_t>(RFP_SCHUNK_MAX, std::max<int64_t>(4 * r.nb, b.m1 / 2 / r.nb * r.nb));
+    // chunk: at most chunk_max columns (1536 by default), at least 4 leaves,
+    // at most half of T1 so that smaller triangles still get two chunks;
+    // chunk_max = 0: no overlap (steps 2 and 3 follow step 1)
+    const int64_t SCHUNK = std::max<int64_t>(
+        4 * r.nb, std::min<int64_t>(sc.chunk_max, std::max<int64_t>(4 * r.nb, b.m1 / 2 / r.nb * r.nb)));
     int64_t done = 0;
     hipEvent_t joined = nullptr;
     auto fork = [&](int64_t o1, hipEvent_t ev) {
@@ -677,7 +696,7 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
         joined = r.record_join(2);
         done = o1;
     };
-    if (b.m2 > 0 && b.m1 > SCHUNK && r.three_streams()) r.potrf_la(b.m1, v.t1, 0, winv, &fork);
+    if (sc.chunk_max > 0 && b.m2 > 0 && b.m1 > SCHUNK && r.three_streams()) r.potrf_la(b.m1, v.t1, 0, winv, &fork);
     else r.potrf_la(b.m1, v.t1, 0, winv);
     r.wait(0, joined);
     r.trsm_rlt(b.m2, b.m1 - done, v.s.sub(0, done), v.t1.sub(done, done), winv + nleaves(done, r.nb) * r.nb * r.nb);
@@ -1186,6 +1205,7 @@ int rfp_create(rfp_handle_t* h, int device)
     rfp_context* c = (rfp_context*)std::calloc(1, sizeof(rfp_context));
     if (!c) return RFP_ERR_RUNTIME;
     c->device = device;
+    c->sched = default_schedule();
     if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->cus <= 0)
         c->cus = 256;
     *h = c;
@@ -1315,17 +1335,18 @@ int rfp_spftri(rfp_handle_t h, char transr, char uplo, int64_t n, float* arf, in
     return pftri_impl<float>(h, transr, uplo, n, arf, info, stream);
 }
 
-int rfp_plan(char routine, char transr, char uplo, int64_t n, int64_t nrhs, int64_t ldb, rfp_plan_op* ops,
-             int64_t cap, int64_t* count)
+int rfp_plan(char routine, char transr, char uplo, int64_t n, int64_t nrhs, int64_t ldb,
+             const rfp_schedule_t* sched, rfp_plan_op* ops, int64_t cap, int64_t* count)
 {
     if (!count || cap < 0 || (cap > 0 && !ops)) return -8;
+    if (sched && bad_schedule(*sched)) return -7;
     PlanRec rec{ops, cap, 0, sizeof(double)};
     double* arf = plan_base<double>(RFP_PLAN_BUF_ARF);
     double* b = plan_base<double>(RFP_PLAN_BUF_B);
     int* info = (int*)plan_base<int>(RFP_PLAN_BUF_INFO);
     int rc;
     switch (upc(routine)) {
-        case 'F': rc = pftrf_impl<double>(nullptr, transr, uplo, n, arf, info, nullptr, &rec); break;
+        case 'F': rc = pftrf_impl<double>(nullptr, transr, uplo, n, arf, info, nullptr, &rec, 0, sched); break;
         case 'S': rc = pftrs_impl<double>(nullptr, transr, uplo, n, nrhs, arf, b, ldb, nullptr, &rec); break;
         case 'I': rc = pftri_impl<double>(nullptr, transr, uplo, n, arf, info, nullptr, &rec); break;
         default: return -1;
@@ -1438,6 +1459,23 @@ int rfp_autotune(rfp_handle_t h, int64_t n, int64_t nrhs, int precs, hipStream_t
     int rc = tune_gemms(h, shapes, stream);
     if (rc == 0 && nrhs > 0 && (precs & RFP_TUNE_FP64)) rc = tune_solve(h, n, nrhs, stream);
     return rc;
+}
+
+int rfp_set_schedule(rfp_handle_t h, const rfp_schedule_t* sched)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    const rfp_schedule_t sc = sched ? *sched : default_schedule();
+    if (bad_schedule(sc)) return -2;
+    h->sched = sc;
+    return 0;
+}
+
+int rfp_get_schedule(rfp_handle_t h, rfp_schedule_t* sched)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (!sched) return -2;
+    *sched = h->sched;
+    return 0;
 }
 
 int rfp_tune_count(rfp_handle_t h)

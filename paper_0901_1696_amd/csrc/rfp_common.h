@@ -118,6 +118,18 @@ __host__ __device__ inline RfpView<T> rfp_view(const RfpBlocks& b, T* arf)
 constexpr int NB = 64;
 constexpr int NB2 = 128;
 
+// Default factorization schedule (rfp_schedule_t).  Measured at n = 20000 on
+// all eight layouts: 256-column panels above a trailing order of 6144 (best of
+// 3072-8192), off-diagonal chunks of at most 1536 columns (of 512-4096), the
+// bulk update waiting for the lookahead at every order (better than 0 and
+// 2048-6144), and 24 KB of LDS reserved by the FP64 leaf (beside a 128 x 128
+// GEMM workgroup the leaf ran 1.5-1.8x slower).
+constexpr int64_t DEFAULT_WIDE_PANELS_ABOVE = 6144;
+constexpr int64_t DEFAULT_CHUNK_MAX = 1536;
+constexpr int64_t DEFAULT_LOOKAHEAD_WAIT_BELOW = INT64_MAX;
+constexpr int64_t DEFAULT_LEAF_LDS_PAD = 24 * 1024;
+constexpr int64_t MAX_LEAF_LDS_PAD = 64 * 1024;
+
 // Splits of the recursion are multiples of the leaf order measured from the
 // root, so the leaves of every sub-problem coincide with the leaves of its root.
 inline int64_t rec_split(int64_t n, int nb)
@@ -169,6 +181,7 @@ struct Exec {
     const TuneTable* tune = nullptr;  // autotuned configurations, if any
     int prio = 0;  // 1: the kernels' waves take the highest issue priority (the critical path, which
                    // shares compute units with bulk work on the other streams)
+    int leaf_pad = (int)DEFAULT_LEAF_LDS_PAD;  // LDS bytes the FP64 128-row leaf reserves beyond its own
 };
 
 // Brackets one kernel launch with HIP events on the launch stream when

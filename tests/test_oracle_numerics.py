@@ -191,3 +191,81 @@ def test_quick_returns():
     for t, u in LAYOUTS:
         f, info = oracle.pftrf(t, u, 0, np.zeros(0))
         assert info == 0 and f.size == 0
+
+
+# Closed-form pins of the metrics: small matrices whose backward error,
+# factor residual, inverse residual and forward error are hand-computed
+# rationals (or their square roots).  A dropped term of a denominator, a
+# missing weight of the off-diagonal entries, a transposed product or a norm
+# of the wrong kind each changes the value.
+
+def test_backward_error_closed_form():
+    """A = [[4, 1, -2], [1, 5, 0], [-2, 0, 6]] (||A||_inf = 8, the third row
+    sum).  Column 1: x = (1, -1, 0), b = A x + (0, 0, 1) = (3, -4, -1):
+    ||r|| = 1, ||x|| = 1, ||b|| = 4, eta = 1 / (8 + 4) = 1/12.  Column 2:
+    x = (0, 0, 1), b = 0: r = -A x = (2, 0, -6), eta = 6 / (8 * 1 + 0) = 3/4.
+    The metric is the max over columns; each column alone is checked too."""
+    A = np.array([[4.0, 1, -2], [1, 5, 0], [-2, 0, 6]])
+    assert np.all(np.linalg.eigvalsh(A) > 0)
+    X = np.array([[1.0, 0], [-1, 0], [0, 1]], order="F")
+    B = np.array([[3.0, 0], [-4, 0], [-1, 0]], order="F")
+    for t, u in LAYOUTS:
+        arf = oracle.trttf(t, u, A)
+        assert oracle.backward_error(t, u, 3, arf, B[:, :1], X[:, :1]) == pytest.approx(1 / 12, rel=1e-15)
+        assert oracle.backward_error(t, u, 3, arf, B[:, 1:], X[:, 1:]) == pytest.approx(3 / 4, rel=1e-15)
+        assert oracle.backward_error(t, u, 3, arf, B, X) == pytest.approx(3 / 4, rel=1e-15)
+    # leading dimensions beyond n are honoured
+    Bp = np.full((5, 1), 99.0, order="F")
+    Bp[:3, 0] = B[:, 0]
+    Xp = np.full((5, 1), -99.0, order="F")
+    Xp[:3, 0] = X[:, 0]
+    lib = oracle.lib()
+    arf = oracle.trttf("N", "L", A)
+    got = lib.orc_backward_error(b"N", b"L", 3, 1, oracle._p(arf), oracle._p(Bp), 5, oracle._p(Xp), 5)
+    assert got == pytest.approx(1 / 12, rel=1e-15)
+
+
+def test_factor_residual_closed_form():
+    """A = [[8, 4], [4, 5]] (||A||_F^2 = 64 + 2 * 16 + 25 = 121) and the
+    candidate factor L = [[3, 0], [2, 1]]: L L^T = [[9, 6], [6, 5]], so
+    L L^T - A = [[1, 2], [2, 0]] with squared norm 1 + 2 * 4 = 9: the residual
+    is 3/11 (both triangles counted).  The exact factor gives 0 up to
+    rounding; L^T L instead of L L^T would give sqrt(45) / 11."""
+    A = np.array([[8.0, 4], [4, 5]])
+    L = np.array([[3.0, 0], [2, 1]])
+    for t, u in LAYOUTS:
+        arf = oracle.trttf(t, u, A)
+        f = oracle.trttf(t, u, L if u == "L" else L.T)
+        assert oracle.factor_residual(t, u, 2, arf, f) == pytest.approx(3 / 11, rel=1e-15)
+        Le = np.linalg.cholesky(A)
+        fe = oracle.trttf(t, u, Le if u == "L" else Le.T)
+        assert oracle.factor_residual(t, u, 2, arf, fe) < 1e-15
+
+
+def test_inverse_residual_closed_form():
+    """A = [[2, 1], [1, 2]] with the candidate inverse V = I:
+    I - A V = -[[1, 1], [1, 1]], ||.||_F = 2; ||A||_F = sqrt(10),
+    ||V||_F = sqrt(2): the residual is 2 / sqrt(20) = 1/sqrt(5).  With
+    V = diag(1/2, 1/2): I - A/2 = [[0, -1/2], [-1/2, 0]], norm 1/sqrt(2),
+    ||V||_F = 1/sqrt(2): residual 1/sqrt(10).  The exact inverse
+    [[2, -1], [-1, 2]] / 3 gives 0 up to rounding."""
+    A = np.array([[2.0, 1], [1, 2]])
+    for t, u in LAYOUTS:
+        arf = oracle.trttf(t, u, A)
+        assert oracle.inverse_residual(t, u, 2, arf, oracle.trttf(t, u, np.eye(2))) == \
+            pytest.approx(1 / np.sqrt(5), rel=1e-15)
+        assert oracle.inverse_residual(t, u, 2, arf, oracle.trttf(t, u, 0.5 * np.eye(2))) == \
+            pytest.approx(1 / np.sqrt(10), rel=1e-15)
+        exact = np.array([[2.0, -1], [-1, 2]]) / 3
+        assert oracle.inverse_residual(t, u, 2, arf, oracle.trttf(t, u, exact)) < 1e-15
+
+
+def test_forward_error_closed_form():
+    """Column 1: x = (1, 2, 3), x_ref = (1, 4, -2): ||x - x_ref|| = 5,
+    ||x_ref|| = 4, error 5/4.  Column 2: x = x_ref = (0, 0, 8): 0.  Max 5/4;
+    column 2 alone 0; a reference column of zeros gives ||x||."""
+    X = np.array([[1.0, 0], [2, 0], [3, 8]], order="F")
+    R = np.array([[1.0, 0], [4, 0], [-2, 8]], order="F")
+    assert oracle.forward_error(X, R) == 5 / 4
+    assert oracle.forward_error(X[:, 1:], R[:, 1:]) == 0.0
+    assert oracle.forward_error(np.array([3.0, -7]), np.zeros(2)) == 7.0
