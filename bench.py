@@ -8,12 +8,22 @@ M n x n N(0,1) (seeded), B N(0,1).  The timed region holds exactly K steps
 (restores included) between device synchronisations; value = nominal FP64
 flops (PFTRF n^3/3 + PFTRS 2 n^2 nrhs) over the timed wall time.
 
+The headline is timed with the library's kernel profiler off.  A second,
+identical timed region with the profiler on gives the kernel table and the
+roofline.
+
 Also reported on the same JSON line:
   roofline      the dominant kernel's algorithmic FLOP/s over its event-timed
-                launches inside the timed region, against the FP64 MFMA peak;
+                launches inside the profiled timed region, against the FP64
+                MFMA peak;
   cpu_baseline  the CPU oracle timed on a bounded sample on the host cores;
   pftri         PFTRI GFLOP/s (nominal 2 n^3 / 3) on the same matrices;
-  accuracy      worst normwise backward error of the solves, all layouts;
+  accuracy      per layout: normwise backward error of the solve, forward
+                error against a known solution (B = A X_true), and
+                ||L L^T - A||_F / ||A||_F of the factor;
+  conversions   TRTTF / TFTTR times and bandwidth (excluded from the factor
+                times, as in the paper);
+  cfg1          n = 1001, TRANSR=N, UPLO=L, nrhs = 4: PFTRF, PFTRS, PFTRI;
   mixed         n = 40000 (TRANSR=N, UPLO=L), nrhs = 16, A = M M^T / k + alpha I
                 with M n x k (k = n/2) and alpha for cond ~1e3 and ~1e6: the
                 FP64 PFTRF+PFTRS time against the low-precision factor with
@@ -77,7 +87,18 @@ def traffic_for(kernel_name):
     return rec.get("kernels", {}).get(kernel_name, {}).get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(n=12000, nrhs=128):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n=12000, nrhs=128, full_sizes=(20000, 20001), layouts=8):
     """The oracle (definition-path PFTRF + PFTRS) on the host, bounded sample."""
     import numpy as np
     import oracle
@@ -96,10 +117,15 @@ def cpu_baseline(n=12000, nrhs=128):
     oracle.pftrs("N", "L", n, f, B)
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round((flops_trf(n) + flops_trs(n, nrhs)) / dt / 1e9, 3), "unit": "GFLOP/s",
-            "cores": threads, "kind": "oracle",
+    rate = (flops_trf(n) + flops_trs(n, nrhs)) / dt
+    full = sum(layouts / len(full_sizes) * (flops_trf(m) + flops_trs(m, nrhs)) for m in full_sizes)
+    return {"value": round(rate / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"oracle PFTRF+PFTRS (definition path, OpenMP rows) on one n={n} TRANSR=N UPLO=L "
-                      f"matrix of the same recipe, nrhs={nrhs}; {dt:.1f} s"}
+                      f"matrix of the same recipe, nrhs={nrhs}; {dt:.1f} s",
+            "full_step_estimate_s": round(full / rate, 1),
+            "scaling": "the rate of the n=12000 sample applied to the benchmark step's nominal flops "
+                       "(n=20000 and 20001, 8 layouts, nrhs=128); the oracle's cost grows as n^3"}
 
 
 def roofline_of(prof):
@@ -132,6 +158,52 @@ def backward_error_dense(A, B, X):
     R = B - A @ X
     anorm = A.abs().sum(dim=1).max()
     return (R.abs().amax(dim=0) / (anorm * X.abs().amax(dim=0) + B.abs().amax(dim=0))).max().item()
+
+
+def bench_cfg1(h, reps=10):
+    """n = 1001 (odd), TRANSR='N', UPLO='L', nrhs = 4, A = M M^T/n + I (seed
+    1001): median times of PFTRF, PFTRS and PFTRI (input restored outside the
+    timed events)."""
+    import statistics
+    import torch
+    import paper_0901_1696_amd as rfp
+    import synth
+
+    n, nrhs = 1001, 4
+    dev = torch.device("cuda:0")
+    A, B = synth.spd_device(n, nrhs=nrhs, seed=n, device=dev)
+    pristine = torch.empty(rfp.nt(n), dtype=torch.float64, device=dev)
+    rfp.rfp_dtrttf(h, "N", "L", n, A, pristine)
+    w = torch.empty_like(pristine)
+    x = B.clone()
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    times = {"pftrf": [], "pftrs": [], "pftri": []}
+    for r in range(reps + 1):
+        w.copy_(pristine)
+        x.copy_(B)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        rfp.rfp_dpftrf(h, "N", "L", n, w, info)
+        ev[1].record()
+        rfp.rfp_dpftrs(h, "N", "L", n, w, x)
+        ev[2].record()
+        rfp.rfp_dpftri(h, "N", "L", n, w, info)
+        ev[3].record()
+        ev[3].synchronize()
+        if r:
+            for k, (a, b) in zip(times, [(0, 1), (1, 2), (2, 3)]):
+                times[k].append(ev[a].elapsed_time(ev[b]))
+    if int(info.item()) != 0:
+        raise SystemExit(f"cfg1: INFO={int(info.item())}")
+    med = {k: statistics.median(v) for k, v in times.items()}
+    fl = {"pftrf": flops_trf(n), "pftrs": flops_trs(n, nrhs), "pftri": flops_tri(n)}
+    out = {"n": n, "layout": "NL", "nrhs": nrhs, "reps": reps}
+    for k in med:
+        out[k] = {"ms": round(med[k], 4), "gflops": round(fl[k] / (med[k] * 1e-3) / 1e9, 1)}
+    out["pftrf+pftrs_gflops"] = round((fl["pftrf"] + fl["pftrs"]) / ((med["pftrf"] + med["pftrs"]) * 1e-3) / 1e9, 1)
+    out["backward_error"] = backward_error_dense(A, B, x)
+    log(f"[bench] cfg1 {out}")
+    return out
 
 
 def bench_mixed(h, n, nrhs=16, kappas=(1e3, 1e6), reps=2):
@@ -175,12 +247,16 @@ def bench_mixed(h, n, nrhs=16, kappas=(1e3, 1e6), reps=2):
                 "fp64_gflops": round((flops_trf(n) + flops_trs(n, nrhs)) / t64 / 1e9, 1)}
         best = None
         for prec, name in [(rfp.PREC_FP16, "fp16"), (rfp.PREC_BF16, "bf16"), (rfp.PREC_FP32, "fp32")]:
+            codes = torch.zeros(2, dtype=torch.int32, device=dev)
+
             def mixed():
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                it, inf = rfp.rfp_dpfsv_ir(h, prec, "N", "L", n, arf, B, x, tol=1e-14, max_iter=40)
+                rfp.rfp_dpfsv_ir(h, prec, "N", "L", n, arf, B, x, codes[0:1], codes[1:2], tol=1e-14, max_iter=15)
                 torch.cuda.synchronize()
-                return time.perf_counter() - t0, it, inf
+                dt = time.perf_counter() - t0
+                it, inf = (int(v) for v in codes.cpu())
+                return dt, it, inf
             mixed()
             runs = [mixed() for _ in range(reps)]
             tm, it, inf = min(runs)
@@ -360,16 +436,13 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] warmup step {i + 1}/{args.warmup} done")
 
-    if not args.no_kernel_profile:
-        rfp.rfp_profile_enable(h, True)
+    # headline: K steps, kernel profiler off
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = rfp.rfp_profile_read(h) if not args.no_kernel_profile else {}
-    rfp.rfp_profile_enable(h, False)
     if int(info.item()) != 0:
         raise SystemExit(f"PFTRF reported INFO={int(info.item())}")
     elapsed = t1 - t0
@@ -377,22 +450,80 @@ def main():
     work_flops = sum(flops_trf(n) + flops_trs(n, nrhs) for n, _, _ in combos)
     value = args.steps * work_flops / elapsed / 1e9
 
-    # dominant kernel of the timed region (largest summed event time)
-    roofline, kernel_table = None, []
-    if prof:
+    # roofline: up to 3 of the same steps again, every kernel launch
+    # bracketed by HIP events on its own stream (the library creates its
+    # event pool when profiling is enabled, large enough for this region, so
+    # nothing is created or folded inside it)
+    roofline, kernel_table, prof_region = None, [], None
+    if not args.no_kernel_profile:
+        psteps = min(args.steps, 3)
+        rfp.rfp_profile_enable(h, True)
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for i in range(psteps):
+            step()
+        torch.cuda.synchronize()
+        p1 = time.perf_counter()
+        prof = rfp.rfp_profile_read(h)
+        rfp.rfp_profile_enable(h, False)
+        prof_region = {"steps": psteps, "ms_per_step": round((p1 - p0) / psteps * 1e3, 3)}
         roofline, kernel_table = roofline_of(prof)
+        log(f"[bench] profiled region {prof_region}")
 
     # ---- accuracy of every (n, layout) solve (independent check with torch)
     accuracy = None
     if not args.no_check:
-        worst, per = 0.0, {}
+        worst, per = {"backward_error": 0.0, "forward_error": 0.0, "factor_residual": 0.0}, {}
+        g = torch.Generator(device=dev).manual_seed(7)
         for n, t, u in combos:
+            A = dense[n]
             run_one(n, t, u)
-            eta = backward_error_dense(dense[n], rhs[n], bwork[:n])
-            per[f"{t}{u}{n}"] = eta
-            worst = max(worst, eta)
-        accuracy = {"max_backward_error": worst, "layouts_checked": len(combos), "per_layout": per}
-        log(f"[bench] worst backward error {worst:.3e}")
+            rec = {"backward_error": backward_error_dense(A, rhs[n], bwork[:n])}
+            # forward error against a known solution: B = A X_true
+            xt = torch.randn((n, 8), dtype=torch.float64, device=dev, generator=g)
+            bt = (A @ xt).t().contiguous().t()
+            w = work[:rfp.nt(n)]
+            rfp.rfp_dpftrs(h, t, u, n, w, bt)
+            rec["forward_error"] = ((bt - xt).abs().amax(0) / xt.abs().amax(0)).max().item()
+            # ||L L^T - A||_F / ||A||_F of the factor in w
+            L = torch.zeros((n, n), dtype=torch.float64, device=dev).t()
+            rfp.rfp_dtfttr(h, t, "L" if u == "L" else "U", n, w, L)
+            L = L if u == "L" else L.t()
+            L = torch.tril(L)
+            rec["factor_residual"] = (torch.linalg.matrix_norm(L @ L.t() - A) / torch.linalg.matrix_norm(A)).item()
+            del L, xt, bt
+            per[f"{t}{u}{n}"] = rec
+            for k in worst:
+                worst[k] = max(worst[k], rec[k])
+        accuracy = {"max_" + k: v for k, v in worst.items()}
+        accuracy.update({"layouts_checked": len(combos), "per_layout": per})
+        log(f"[bench] accuracy {accuracy['max_backward_error']:.3e} {accuracy['max_forward_error']:.3e} "
+            f"{accuracy['max_factor_residual']:.3e}")
+
+    # ---- TRTTF / TFTTR (not part of the factor times, as in the paper)
+    conversions = None
+    if not args.no_check:
+        rows = []
+        for n, t, u in combos:
+            A = dense[n]
+            w = work[:rfp.nt(n)]
+            full = torch.zeros((n, n), dtype=torch.float64, device=dev).t()
+            for name, fn in (("trttf", lambda: rfp.rfp_dtrttf(h, t, u, n, A, w)),
+                             ("tfttr", lambda: rfp.rfp_dtfttr(h, t, u, n, w, full))):
+                fn()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(3):
+                    fn()
+                e1.record()
+                e1.synchronize()
+                ms = e0.elapsed_time(e1) / 3
+                byts = 2.0 * 8 * rfp.nt(n)  # every stored entry read once and written once
+                rows.append({"routine": name, "layout": f"{t}{u}{n}", "ms": round(ms, 4),
+                             "GB/s": round(byts / ms / 1e6, 1), "hbm_frac": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4)})
+            del full
+        conversions = {"bytes_model": "16 n(n+1)/2 (each stored entry read and written once)", "runs": rows}
+        log(f"[bench] conversions {[(r['routine'], r['layout'], r['GB/s']) for r in rows]}")
 
     # ---- PFTRI (event timed, after its own PFTRF)
     pftri = None
@@ -418,6 +549,7 @@ def main():
 
     del pristine, rhs, dense, work, bwork
     torch.cuda.empty_cache()
+    cfg1 = bench_cfg1(h)
     mixed = None if args.no_mixed else bench_mixed(h, args.mixed_n)
     batched = None if args.no_batched else bench_batched(h)
 
@@ -434,7 +566,8 @@ def main():
         "config": {"workload": "FP64 PFTRF+PFTRS, n in {" + ",".join(map(str, sizes)) + "} x RFP layouts "
                    + ",".join(t + u for t, u in layouts) + f", nrhs={nrhs}, A=M M^T/n+I (seeded N(0,1))",
                    "n": sizes, "layouts": [t + u for t, u in layouts], "nrhs": nrhs},
-        "roofline": roofline, "cpu_baseline": cpu, "pftri": pftri, "accuracy": accuracy,
+        "roofline": roofline, "profiled_region": prof_region, "cpu_baseline": cpu, "pftri": pftri,
+        "accuracy": accuracy, "conversions": conversions, "cfg1": cfg1,
         "mixed": mixed, "batched": batched,
         "kernels": kernel_table,
         "paper_context": "PFTRF 90.7-93.0 GFLOP/s at n=20000 on a 16-core Intel Tigerton with MKL "

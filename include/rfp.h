@@ -87,6 +87,46 @@ int rfp_dpftrs(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, 
  * INFO=5. */
 int rfp_dpftri(rfp_handle_t h, char transr, char uplo, int64_t n, double* arf, int* info, hipStream_t stream);
 
+/* TFTRI (the paper's routine table, "Triangular inversion"): the inverse of
+ * the triangular matrix T held in arf (UPLO='L' lower, 'U' upper) overwrites
+ * it in the same layout, by the inversion stage of PFTRI (Section 5, Figure 4
+ * "Cholesky Inversion Algorithm" steps 1-4).  DIAG='U': T has a unit diagonal;
+ * the stored diagonal is not used and is left as it was.  *info (device int)
+ * becomes 0, or i > 0 when T(i,i) is exactly zero (DIAG='N').  Argument order:
+ * TRANSR=1, UPLO=2, DIAG=3, N=4, A=5, INFO=6. */
+int rfp_dtftri(rfp_handle_t h, char transr, char uplo, char diag, int64_t n, double* arf, int* info,
+               hipStream_t stream);
+
+/* TFSM (the paper's routine table, "Triangular solve"; Section 4 uses it as
+ * POTRS uses TRSM): B (m x n, column-major, ldb >= max(1,m)) is overwritten by
+ *   SIDE='L': X with op(A) X = alpha B (A of order m);
+ *   SIDE='R': X with X op(A) = alpha B (A of order n);
+ * op(A) = A (TRANS='N') or A^T ('T'); A triangular in arf (UPLO, DIAG as for
+ * rfp_dtftri).  alpha = 0 sets B to zero and does not read A.  Argument
+ * order: TRANSR=1, SIDE=2, UPLO=3, TRANS=4, DIAG=5, M=6, N=7, ALPHA=8, A=9,
+ * B=10, LDB=11. */
+int rfp_dtfsm(rfp_handle_t h, char transr, char side, char uplo, char trans, char diag, int64_t m, int64_t n,
+              double alpha, const double* arf, double* b, int64_t ldb, hipStream_t stream);
+
+/* SFRK (the paper's routine table, "Sym rank-k update"): C = alpha op(A)
+ * op(A)^T + beta C for the symmetric C of order n held in c (RFP), with
+ * op(A) = A (TRANS='N', A n x k) or A^T (TRANS='T', A k x n), A column-major
+ * with leading dimension lda (>= max(1, n) for 'N', >= max(1, k) for 'T').
+ * alpha = 0 or k = 0 does not read A; beta = 0 does not read C.  Argument
+ * order: TRANSR=1, UPLO=2, TRANS=3, N=4, K=5, ALPHA=6, A=7, LDA=8, BETA=9,
+ * C=10. */
+int rfp_dsfrk(rfp_handle_t h, char transr, char uplo, char trans, int64_t n, int64_t k, double alpha,
+              const double* a, int64_t lda, double beta, double* c, hipStream_t stream);
+
+/* TPTTF / TFTTP (the paper's routine table, "Conv. from TP to TF" and back):
+ * the standard packed array ap (n(n+1)/2 entries, Figure 2: the UPLO
+ * triangle column by column) to the RFP array arf of layout (TRANSR, UPLO),
+ * and back.  Argument order: TRANSR=1, UPLO=2, N=3, AP=4, ARF=5 (TPTTF);
+ * TRANSR=1, UPLO=2, N=3, ARF=4, AP=5 (TFTTP). */
+int rfp_dtpttf(rfp_handle_t h, char transr, char uplo, int64_t n, const double* ap, double* arf, hipStream_t stream);
+int rfp_dtfttp(rfp_handle_t h, char transr, char uplo, int64_t n, const double* arf, double* ap, hipStream_t stream);
+
+
 /* Single-precision counterparts (SPFTRF / SPFTRS / STRTTF / STFTTR in the
  * paper's routine table); same arguments and semantics with float arrays. */
 int rfp_strttf(rfp_handle_t h, char transr, char uplo, int64_t n, const float* a, int64_t lda, float* arf,
@@ -135,9 +175,11 @@ int rfp_dlansf(rfp_handle_t h, char norm, char transr, char uplo, int64_t n, con
 
 /* Solve A X = B for the FP64 SPD matrix in arf (left untouched) by a
  * low-precision Cholesky factor and FP64 iterative refinement:
- *   As = rfp_dpfcast_s(A, scale = 1, mu = 1) in FP32; Ls = PFTRF(As) with the
- *   updates in precision fprec (as rfp_spftrf_mp); the preconditioner
- *   is M^{-1} = D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2} (solves in FP32).
+ *   As = mu D^{-1/2} A D^{-1/2} rounded to FP32 (rfp_dpfcast_s with
+ *   scale = 1; mu = 2^25 for FPREC = RFP_PREC_FP16, so that the factor's
+ *   entries use the FP16 range, else 1); Ls = PFTRF(As) with the bulk
+ *   updates in precision fprec (as rfp_spftrf_mp); the preconditioner is
+ *   M^{-1} = mu D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2} (solves in FP32).
  *   X = 0, R = B; each sweep corrects X from R in FP64, then R = B - A X
  *   (FP64, from arf), until the normwise backward error
  *   max_c ||R_c||_inf / (||A||_inf ||X_c||_inf + ||B_c||_inf) is <= tol.
@@ -145,18 +187,23 @@ int rfp_dlansf(rfp_handle_t h, char norm, char transr, char uplo, int64_t n, con
  *   the backward error fourfold; later sweeps run 8 steps of conjugate
  *   gradients on A D = R preconditioned by M^{-1}, in FP64 (refinement with a
  *   CG inner solver), which converges where kappa(A) u_low is not small.
- * Falls back to the FP64 PFTRF + PFTRS on a copy of A when the low-precision
- * factor is not positive definite, when a conjugate-gradient sweep fails to
- * cut the backward error below 0.9 times the previous one, or after max_iter
- * sweeps.
- * Host outputs: *iter = number of sweeps when refinement converged, or the
- * fall-back reason: -1 max_iter reached, -2 stalled, -3 low-precision factor
- * not positive definite; *info = the FP64 PFTRF INFO of a fall-back (0
- * otherwise).  X (n x nrhs, ldx) receives the solution; b is only read.
- * The call synchronises with `stream` once per sweep (to read the backward
- * error) and returns when the solution is complete.  Argument order:
- * FPREC=1, TRANSR=2, UPLO=3, N=4, NRHS=5, A=6, B=7, LDB=8, X=9, LDX=10,
- * TOL=11 (positive), MAX_ITER=12 (>= 1), ITER=13, INFO=14. */
+ * Falls back to the FP64 PFTRF + PFTRS on a copy of A when the scaled copy
+ * is not finite, when the low-precision factor is not positive definite,
+ * when a conjugate-gradient sweep fails to cut the backward error below 0.9
+ * times the previous one, or after max_iter sweeps.
+ * Every decision is taken on the device: the call enqueues the setup,
+ * max_iter sweeps and the fall-back without waiting, and what is not needed
+ * exits at once.  It never synchronises; once the handle's workspace has been
+ * sized by an earlier call of the same n and nrhs, it allocates nothing and
+ * can be captured in a HIP graph.
+ * Device outputs (ints): *iter = number of sweeps when refinement converged,
+ * or the fall-back reason: -1 max_iter reached, -2 stalled, -3 low-precision
+ * factor not positive definite, -4 the scaled low-precision copy of A is not
+ * finite (a diagonal entry <= 0, or an entry out of range); *info = the FP64
+ * PFTRF INFO of a fall-back (0 otherwise).  X (n x nrhs, ldx) receives the
+ * solution; b is only read.  Argument order: FPREC=1, TRANSR=2, UPLO=3, N=4,
+ * NRHS=5, A=6, B=7, LDB=8, X=9, LDX=10, TOL=11 (positive), MAX_ITER=12
+ * (>= 1), ITER=13, INFO=14. */
 int rfp_dpfsv_ir(rfp_handle_t h, int fprec, char transr, char uplo, int64_t n, int64_t nrhs, const double* arf,
                  const double* b, int64_t ldb, double* x, int64_t ldx, double tol, int max_iter, int* iter, int* info,
                  hipStream_t stream);
@@ -229,6 +276,20 @@ int rfp_tune_force(rfp_handle_t h, int tile, int split);
 int rfp_tune_save(rfp_handle_t h, const char* path);
 int rfp_tune_load(rfp_handle_t h, const char* path);
 
+/* Fused-solve status (PFTRS and every solve inside the refinement and the
+ * FP64 fall-back).  The triangular solves pass solved rows between
+ * workgroups through flags; each wait for a flag is bounded (default 2^24
+ * polls).  A wait that runs out writes NaN into its block of the solution
+ * and sets bit 0 of the handle's device status word.  rfp_solve_status
+ * enqueues, on `stream`, a copy of that word into *status (device int) and
+ * clears it, so it reports every give-up since the previous call.
+ * rfp_set_solve_wait_limit sets the number of polls (0 = give up at the
+ * first poll that finds nothing new: a testing aid that makes every kernel
+ * still end normally); polls < 0 restores the default.  Argument order:
+ * H=1, STATUS=2 / POLLS=2. */
+int rfp_solve_status(rfp_handle_t h, int* status, hipStream_t stream);
+int rfp_set_solve_wait_limit(rfp_handle_t h, int64_t polls);
+
 /* ------------------------------------------------------------------------
  * Factorization schedule (not in the paper: the paper's four steps run one
  * after the other; here they are overlapped on three streams).  These knobs
@@ -265,7 +326,10 @@ int rfp_get_schedule(rfp_handle_t h, rfp_schedule_t* sched);
 /* ------------------------------------------------------------------------
  * Kernel timing (introspection, used by the benchmark for its roofline).
  * While enabled, every kernel the handle's calls launch is bracketed by a pair
- * of HIP events on the call's stream.  rfp_profile_read waits for the device,
+ * of HIP events on the call's stream.  Enabling creates a pool of 32768 event
+ * pairs up front; only when a region launches more kernels than that does a
+ * launch wait for the device to fold the finished pairs.  rfp_profile_read
+ * waits for the device,
  * folds the finished pairs into one entry per kernel (the kernel's demangled
  * name as rocprofv3 prints it: launches, summed event time, summed
  * algorithmic flops and bytes of those launches), and resets the totals

@@ -70,6 +70,12 @@ def _declare(L):
     L.orc_norm_fro.restype = ctypes.c_double
     L.orc_pfcast_s.argtypes = [_chr, _chr, _i64, _dp, ctypes.c_int, ctypes.c_double, _dp, _vp]
     L.orc_backward_error.argtypes = [_chr, _chr, _i64, _i64, _dp, _dp, _i64, _dp, _i64]
+    L.orc_tftri.restype = ctypes.c_int
+    L.orc_tftri.argtypes = [_chr, _chr, _chr, _i64, _dp]
+    L.orc_tfsm.restype = None
+    L.orc_tfsm.argtypes = [_chr, _chr, _chr, _chr, _chr, _i64, _i64, ctypes.c_double, _dp, _dp, _i64]
+    L.orc_sfrk.restype = None
+    L.orc_sfrk.argtypes = [_chr, _chr, _chr, _i64, _i64, ctypes.c_double, _dp, _i64, ctypes.c_double, _dp]
     L.orc_forward_error.restype = ctypes.c_double
     L.orc_forward_error.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64]
     L.orc_factor_residual.restype = ctypes.c_double
@@ -211,6 +217,32 @@ def backward_error(transr, uplo, n, arf_a, b, x):
     arf_a = np.ascontiguousarray(arf_a, dtype=np.float64)
     return lib().orc_backward_error(_c(transr), _c(uplo), n, b.shape[1], _p(arf_a),
                                     _p(b), b.shape[0], _p(x), x.shape[0])
+
+
+def tftri(transr, uplo, diag, n, arf):
+    """TFTRI: (inverse in RFP, info); the input array is not modified."""
+    out = np.ascontiguousarray(arf, dtype=np.float64).copy()
+    info = lib().orc_tftri(_c(transr), _c(uplo), _c(diag), n, _p(out))
+    return out, info
+
+
+def tfsm(transr, side, uplo, trans, diag, m, n, alpha, arf, b):
+    """TFSM: returns X (m x n, Fortran order); b is not modified."""
+    arf = np.ascontiguousarray(arf, dtype=np.float64)
+    x = np.array(b, dtype=np.float64, order="F", copy=True)
+    lib().orc_tfsm(_c(transr), _c(side), _c(uplo), _c(trans), _c(diag), m, n, float(alpha), _p(arf), _p(x),
+                   max(1, x.shape[0]))
+    return x
+
+
+def sfrk(transr, uplo, trans, n, k, alpha, a, beta, c):
+    """SFRK: returns the updated RFP array; c is not modified.  a is the
+    n x k (TRANS='N') or k x n (TRANS='T') column-major matrix."""
+    a = _f64(a)
+    out = np.ascontiguousarray(c, dtype=np.float64).copy()
+    lib().orc_sfrk(_c(transr), _c(uplo), _c(trans), n, k, float(alpha), _p(a), max(1, a.shape[0]), float(beta),
+                   _p(out))
+    return out
 
 
 def forward_error(x, x_ref):

@@ -457,6 +457,166 @@ void orc_pfcast_s(char transr, char uplo, i64 n, const double *arf, int scale, d
         }
 }
 
+/* ------------------------------------------------------------------------ */
+/* The rest of the routine table: TFTRI, TFSM, SFRK                          */
+/* ------------------------------------------------------------------------ */
+
+/* Dense triangular matrix T (row-major n x n, zero outside its triangle) of a
+ * triangular matrix held in RFP: UPLO='L' lower, 'U' upper; DIAG='U' puts ones
+ * on the diagonal (the stored diagonal is not read). */
+static void unpack_tri(char transr, char uplo, char diag, i64 n, const double *arf, double *T)
+{
+    int lower = up(uplo) == 'L';
+    memset(T, 0, sizeof(double) * (size_t)(n * n));
+    for (i64 i = 0; i < n; i++)
+        for (i64 j = 0; j < n; j++) {
+            if (lower ? j > i : j < i) continue;
+            T[i * n + j] = (i == j && up(diag) == 'U') ? 1.0 : arf[orc_rfp_pos(transr, uplo, n, i, j)];
+        }
+}
+
+/* TFTRI (the routine table, "Triangular inversion"): the inverse of the
+ * triangular matrix T held in RFP overwrites it, same layout.  By definition
+ * T X = I, column by column: forward substitution for a lower T, back
+ * substitution for an upper T.  Returns 0, or i+1 when T(i,i) is exactly zero
+ * (DIAG='N'); the array is then untouched.  DIAG='U' leaves the stored
+ * diagonal as it was. */
+int orc_tftri(char transr, char uplo, char diag, i64 n, double *arf)
+{
+    if (n <= 0) return 0;
+    int lower = up(uplo) == 'L', unit = up(diag) == 'U';
+    double *T = (double *)malloc(sizeof(double) * (size_t)(n * n));
+    double *X = (double *)malloc(sizeof(double) * (size_t)(n * n));
+    if (!T || !X) { free(T); free(X); return -100; }
+    unpack_tri(transr, uplo, diag, n, arf, T);
+    for (i64 i = 0; i < n; i++)
+        if (T[i * n + i] == 0.0) { free(T); free(X); return (int)(i + 1); }
+    memset(X, 0, sizeof(double) * (size_t)(n * n));
+    for (i64 c = 0; c < n; c++) {
+        if (lower) {
+            for (i64 i = 0; i < n; i++) {
+                double t = (i == c) ? 1.0 : 0.0;
+                for (i64 k = 0; k < i; k++) t -= T[i * n + k] * X[k * n + c];
+                X[i * n + c] = t / T[i * n + i];
+            }
+        } else {
+            for (i64 i = n - 1; i >= 0; i--) {
+                double t = (i == c) ? 1.0 : 0.0;
+                for (i64 k = i + 1; k < n; k++) t -= T[i * n + k] * X[k * n + c];
+                X[i * n + c] = t / T[i * n + i];
+            }
+        }
+    }
+    for (i64 i = 0; i < n; i++)
+        for (i64 j = 0; j < n; j++) {
+            if (lower ? j > i : j < i) continue;
+            if (i == j && unit) continue;
+            arf[orc_rfp_pos(transr, uplo, n, i, j)] = X[i * n + j];
+        }
+    free(T);
+    free(X);
+    return 0;
+}
+
+/* TFSM (the routine table, "Triangular solve"): B (m x n, column-major, ldb)
+ * becomes X with
+ *   SIDE='L': op(A) X = alpha B,   A of order m;
+ *   SIDE='R': X op(A) = alpha B,   A of order n;
+ * op(A) = A (TRANS='N') or A^T (TRANS='T'); A triangular in RFP (UPLO, DIAG).
+ * alpha = 0 sets B to zero without reading A.  Plain substitution on the
+ * dense op(A), one right-hand side (a column for SIDE='L', a row for
+ * SIDE='R') at a time. */
+void orc_tfsm(char transr, char side, char uplo, char trans, char diag, i64 m, i64 n, double alpha,
+              const double *arf, double *b, i64 ldb)
+{
+    if (m <= 0 || n <= 0) return;
+    int left = up(side) == 'L';
+    i64 k = left ? m : n;
+    if (alpha == 0.0) {
+        for (i64 j = 0; j < n; j++)
+            for (i64 i = 0; i < m; i++) b[i + j * ldb] = 0.0;
+        return;
+    }
+    double *T = (double *)malloc(sizeof(double) * (size_t)(k * k));
+    double *O = (double *)malloc(sizeof(double) * (size_t)(k * k));
+    double *v = (double *)malloc(sizeof(double) * (size_t)k);
+    if (!T || !O || !v) { free(T); free(O); free(v); return; }
+    unpack_tri(transr, uplo, diag, k, arf, T);
+    /* O = op(A), dense row-major */
+    for (i64 i = 0; i < k; i++)
+        for (i64 j = 0; j < k; j++) O[i * k + j] = (up(trans) == 'N') ? T[i * k + j] : T[j * k + i];
+    /* op(A) lower or upper */
+    int olow = (up(uplo) == 'L') == (up(trans) == 'N');
+    i64 nsys = left ? n : m;
+    for (i64 q = 0; q < nsys; q++) {
+        /* right-hand side q: column q of B (left) or row q of B (right) */
+        for (i64 i = 0; i < k; i++) v[i] = alpha * (left ? b[i + q * ldb] : b[q + i * ldb]);
+        if (left) {
+            /* op(A) x = v */
+            if (olow) {
+                for (i64 i = 0; i < k; i++) {
+                    double t = v[i];
+                    for (i64 c = 0; c < i; c++) t -= O[i * k + c] * v[c];
+                    v[i] = t / O[i * k + i];
+                }
+            } else {
+                for (i64 i = k - 1; i >= 0; i--) {
+                    double t = v[i];
+                    for (i64 c = i + 1; c < k; c++) t -= O[i * k + c] * v[c];
+                    v[i] = t / O[i * k + i];
+                }
+            }
+        } else {
+            /* x op(A) = v, i.e. op(A)^T x = v: column c of op(A) gives equation c */
+            if (olow) {
+                for (i64 c = k - 1; c >= 0; c--) {
+                    double t = v[c];
+                    for (i64 r = c + 1; r < k; r++) t -= O[r * k + c] * v[r];
+                    v[c] = t / O[c * k + c];
+                }
+            } else {
+                for (i64 c = 0; c < k; c++) {
+                    double t = v[c];
+                    for (i64 r = 0; r < c; r++) t -= O[r * k + c] * v[r];
+                    v[c] = t / O[c * k + c];
+                }
+            }
+        }
+        for (i64 i = 0; i < k; i++) {
+            if (left) b[i + q * ldb] = v[i];
+            else b[q + i * ldb] = v[i];
+        }
+    }
+    free(T);
+    free(O);
+    free(v);
+}
+
+/* SFRK (the routine table, "Sym rank-k update"): C = alpha op(A) op(A)^T +
+ * beta C on the stored triangle of the symmetric C (order n) in RFP, with
+ * op(A) = A (n x k, TRANS='N') or A^T (A k x n, TRANS='T'), A column-major
+ * with leading dimension lda.  beta = 0 does not read C; alpha = 0 (or
+ * k = 0) does not read A.  Every stored entry is the plain dot product. */
+void orc_sfrk(char transr, char uplo, char trans, i64 n, i64 k, double alpha, const double *a, i64 lda,
+              double beta, double *c)
+{
+    int notr = up(trans) == 'N';
+    for (i64 j = 0; j < n; j++)
+        for (i64 i = j; i < n; i++) {
+            i64 p = orc_rfp_pos(transr, uplo, n, i, j);
+            double t = 0.0;
+            if (alpha != 0.0)
+                for (i64 l = 0; l < k; l++) {
+                    double ail = notr ? a[i + l * lda] : a[l + i * lda];
+                    double ajl = notr ? a[j + l * lda] : a[l + j * lda];
+                    t += ail * ajl;
+                }
+            double v = alpha * t;
+            if (beta != 0.0) v += beta * c[p];
+            c[p] = v;
+        }
+}
+
 /* Normwise backward error of a solve, max over columns:
  *   eta = ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf).
  * A is the original matrix in RFP; residuals accumulate in long double. */

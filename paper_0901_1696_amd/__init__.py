@@ -45,6 +45,11 @@ _SIGS = {
     "rfp_dtfttr": [_vp, _chr, _chr, _i64, _vp, _vp, _i64, _vp],
     "rfp_dpftrf": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_dpftrs": [_vp, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp],
+    "rfp_dtftri": [_vp, _chr, _chr, _chr, _i64, _vp, _vp, _vp],
+    "rfp_dtfsm": [_vp, _chr, _chr, _chr, _chr, _chr, _i64, _i64, ctypes.c_double, _vp, _vp, _i64, _vp],
+    "rfp_dsfrk": [_vp, _chr, _chr, _chr, _i64, _i64, ctypes.c_double, _vp, _i64, ctypes.c_double, _vp, _vp],
+    "rfp_dtpttf": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
+    "rfp_dtfttp": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_dpftri": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_strttf": [_vp, _chr, _chr, _i64, _vp, _i64, _vp, _vp],
     "rfp_stfttr": [_vp, _chr, _chr, _i64, _vp, _vp, _i64, _vp],
@@ -62,7 +67,9 @@ _SIGS = {
     "rfp_tune_load": [_vp, ctypes.c_char_p],
     "rfp_dpfsv_batched": [_vp, _int, _i64, _vp, _vp, _vp, _int, ctypes.c_double, _int, _vp, _vp, _vp],
     "rfp_dpfsv_ir": [_vp, _int, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp, _i64, ctypes.c_double, _int,
-                     ctypes.POINTER(_int), ctypes.POINTER(_int), _vp],
+                     _vp, _vp, _vp],
+    "rfp_solve_status": [_vp, _vp, _vp],
+    "rfp_set_solve_wait_limit": [_vp, _i64],
     "rfp_plan": [_chr, _chr, _chr, _i64, _i64, _i64, _vp, _vp, _i64, ctypes.POINTER(_i64)],
     "rfp_set_schedule": [_vp, _vp],
     "rfp_get_schedule": [_vp, _vp],
@@ -267,6 +274,34 @@ def rfp_dpftri(h, transr, uplo, n, arf, info, stream=None):
                                           _stream(stream)))
 
 
+def rfp_dtftri(h, transr, uplo, diag, n, arf, info, stream=None):
+    _check("rfp_dtftri", lib().rfp_dtftri(h.value, _c(transr), _c(uplo), _c(diag), n, _ptr(arf), _ptr(info),
+                                          _stream(stream)))
+
+
+def rfp_dtfsm(h, transr, side, uplo, trans, diag, alpha, arf, b, stream=None):
+    """B (m x n, column-major tensor) <- X as in TFSM; m, n from b."""
+    pb, ldb, n = _colmajor(b, "b")
+    m = b.shape[0]
+    _check("rfp_dtfsm", lib().rfp_dtfsm(h.value, _c(transr), _c(side), _c(uplo), _c(trans), _c(diag), m, n,
+                                        float(alpha), _ptr(arf), pb, ldb, _stream(stream)))
+
+
+def rfp_dsfrk(h, transr, uplo, trans, n, k, alpha, a, beta, c, stream=None):
+    """C (RFP) <- alpha op(A) op(A)^T + beta C; a column-major (n x k or k x n)."""
+    pa, lda, _ = _colmajor(a, "a")
+    _check("rfp_dsfrk", lib().rfp_dsfrk(h.value, _c(transr), _c(uplo), _c(trans), n, k, float(alpha), pa, lda,
+                                        float(beta), _ptr(c), _stream(stream)))
+
+
+def rfp_dtpttf(h, transr, uplo, n, ap, arf, stream=None):
+    _check("rfp_dtpttf", lib().rfp_dtpttf(h.value, _c(transr), _c(uplo), n, _ptr(ap), _ptr(arf), _stream(stream)))
+
+
+def rfp_dtfttp(h, transr, uplo, n, arf, ap, stream=None):
+    _check("rfp_dtfttp", lib().rfp_dtfttp(h.value, _c(transr), _c(uplo), n, _ptr(arf), _ptr(ap), _stream(stream)))
+
+
 def rfp_strttf(h, transr, uplo, n, a, arf, stream=None):
     pa, lda, _ = _colmajor(a, "a")
     _check("rfp_strttf", lib().rfp_strttf(h.value, _c(transr), _c(uplo), n, pa, lda, _ptr(arf), _stream(stream)))
@@ -308,17 +343,27 @@ def rfp_dlansf(h, norm, transr, uplo, n, arf, out, stream=None):
                                           _stream(stream)))
 
 
-def rfp_dpfsv_ir(h, fprec, transr, uplo, n, arf, b, x, tol=1e-14, max_iter=50, stream=None):
-    """Mixed-precision solve with FP64 refinement; returns (iter, info) (host ints)."""
+def rfp_dpfsv_ir(h, fprec, transr, uplo, n, arf, b, x, iter, info, tol=1e-14, max_iter=20, stream=None):
+    """Mixed-precision solve with FP64 refinement.  iter and info are device
+    int32 tensors (one element each) that receive the sweep count or fall-back
+    reason and the fall-back's INFO; nothing synchronises."""
     pb, ldb, nrhs = _colmajor(b, "b")
     px, ldx, nx = _colmajor(x, "x")
     if nx != nrhs:
         raise ValueError("x and b must have the same number of columns")
-    it, info = _int(0), _int(0)
     _check("rfp_dpfsv_ir", lib().rfp_dpfsv_ir(h.value, int(fprec), _c(transr), _c(uplo), n, nrhs, _ptr(arf), pb, ldb,
-                                              px, ldx, float(tol), int(max_iter), ctypes.byref(it),
-                                              ctypes.byref(info), _stream(stream)))
-    return it.value, info.value
+                                              px, ldx, float(tol), int(max_iter), _ptr(iter), _ptr(info),
+                                              _stream(stream)))
+
+
+def rfp_solve_status(h, status, stream=None):
+    """Copy the handle's fused-solve status word into the device int32 tensor
+    `status` and clear it (bit 0: a bounded wait gave up)."""
+    _check("rfp_solve_status", lib().rfp_solve_status(h.value, _ptr(status), _stream(stream)))
+
+
+def rfp_set_solve_wait_limit(h, polls):
+    _check("rfp_set_solve_wait_limit", lib().rfp_set_solve_wait_limit(h.value, int(polls)))
 
 
 class SysDesc(ctypes.Structure):

@@ -360,13 +360,16 @@ __global__ __launch_bounds__(256) void batched_kernel(BatchArgs a)
                                 const double bq = fabs(bb[i + c * sd.ldb]);
                                 rm = (q > rm || q != q) ? q : rm;
                                 xm = (x > xm || x != x) ? x : xm;
-                                bmx = bq > bmx ? bq : bmx;
+                                bmx = (bq > bmx || bq != bq) ? bq : bmx;
                             }
                             rm = wg_max(rm, red);
                             xm = wg_max(xm, red);
                             bmx = wg_max(bmx, red);
                             const double den = anorm * xm + bmx;
-                            const double e = den > 0.0 ? rm / den : (rm > 0.0 ? __builtin_inf() : 0.0);
+                            const double e = (den != den || rm != rm) ? __builtin_nan("")
+                                             : den > 0.0              ? rm / den
+                                             : rm > 0.0               ? __builtin_inf()
+                                                                      : 0.0;
                             eta = (e > eta || e != e) ? e : eta;
                         }
                         if (eta <= a.tol) {

@@ -132,10 +132,14 @@ __global__ __launch_bounds__(64) void trtri_leaf_kernel(Mat<T> A, int nb, int* i
 }
 
 // Out-of-place inverses of all leaves of a lower-triangular matrix of order n
-// (one wavefront per leaf, blockIdx.x = leaf).  Used by PFTRS.
+// (one wavefront per leaf, blockIdx.x = leaf).  Used by PFTRS and TFSM.
+// unit: the diagonal is taken as ones (not read).  Does nothing while
+// *gate != 0 (gate may be null).
 template <typename T>
-__global__ __launch_bounds__(64) void trtri_leaves_kernel(Mat<const T> A, int64_t n, T* winv)
+__global__ __launch_bounds__(64) void trtri_leaves_kernel(Mat<const T> A, int64_t n, T* winv, const int* gate,
+                                                          int unit)
 {
+    if (gate && *gate) return;
     const int64_t b = blockIdx.x;
     const int64_t o = b * NB;
     const int nb = (int)((n - o) < NB ? (n - o) : NB);
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(64) void trtri_leaves_kernel(Mat<const T> A, int64_
     __shared__ T rdiag[NB];
 #pragma unroll
     for (int j = 0; j < NB; j++)
-        Ls[i][j] = (i < nb && j <= i) ? A.at(o + i, o + j) : (i == j ? T(1) : T(0));
+        Ls[i][j] = (i < nb && j < i) ? A.at(o + i, o + j) : (i == j ? ((i < nb && !unit) ? A.at(o + i, o + i) : T(1)) : T(0));
     __syncthreads();
     rdiag[i] = T(1) / Ls[i][i];
     __syncthreads();
@@ -210,14 +214,15 @@ hipError_t trtri_leaf(const Exec& ex, Mat<T> A, int nb, int64_t info_base)
 }
 
 template <typename T>
-hipError_t trtri_leaves(const Exec& ex, Mat<const T> A, int64_t n, T* winv)
+hipError_t trtri_leaves(const Exec& ex, Mat<const T> A, int64_t n, T* winv, bool unit)
 {
     if (n <= 0) return hipSuccess;
     const int64_t nl = (n + NB - 1) / NB;
-    ProfScope ps(ex, lname<T>("trtri_leaves_kernel", sizeof(T) == 8 ? "rfp::Mat<double const>, long, double*"
-                                                                    : "rfp::Mat<float const>, long, float*"),
+    ProfScope ps(ex, lname<T>("trtri_leaves_kernel", sizeof(T) == 8 ? "rfp::Mat<double const>, long, double*, int const*, int"
+                                                                    : "rfp::Mat<float const>, long, float*, int const*, int"),
                  (double)nl * NB * NB * NB / 3.0, sizeof(T) * (double)nl * NB * NB * 1.5);
-    hipLaunchKernelGGL((trtri_leaves_kernel<T>), dim3((unsigned)nl), dim3(64), 0, ex.stream, A, n, winv);
+    hipLaunchKernelGGL((trtri_leaves_kernel<T>), dim3((unsigned)nl), dim3(64), 0, ex.stream, A, n, winv, ex.gate,
+                       unit ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -234,7 +239,7 @@ hipError_t lauum_leaf(const Exec& ex, Mat<T> A, int nb)
 #define RFP_LEAF_INST(T)                                                               \
     template hipError_t potrf_leaf<T>(const Exec&, Mat<T>, int, T*, int64_t);          \
     template hipError_t trtri_leaf<T>(const Exec&, Mat<T>, int, int64_t);              \
-    template hipError_t trtri_leaves<T>(const Exec&, Mat<const T>, int64_t, T*);       \
+    template hipError_t trtri_leaves<T>(const Exec&, Mat<const T>, int64_t, T*, bool); \
     template hipError_t lauum_leaf<T>(const Exec&, Mat<T>, int);
 RFP_LEAF_INST(double)
 RFP_LEAF_INST(float)

@@ -7,6 +7,7 @@
 // Every RFP kernel walks the three blocks T1, S and T2 through their
 // canonical lower views; each view has one unit stride, and the 64 x 64 tile
 // of a workgroup is read with the fast thread index along it.
+#include <algorithm>
 #include <cstdio>
 
 #include "rfp_common.h"
@@ -34,7 +35,7 @@ __global__ void diag_scale_kernel(Mat<const double> t1, int64_t m1, Mat<const do
 // (lower triangle only if lower); src and dst have the same strides.
 __global__ __launch_bounds__(256) void cast_block_kernel(Mat<const double> src, Mat<float> dst, int64_t m, int64_t n,
                                                          int lower, const double* sr, const double* sc, double mu,
-                                                         int64_t tiles_m)
+                                                         int64_t tiles_m, int* nonfinite)
 {
     const int64_t ti = blockIdx.x % tiles_m, tj = blockIdx.x / tiles_m;
     const int64_t i0 = ti * TT, j0 = tj * TT;
@@ -50,13 +51,15 @@ __global__ __launch_bounds__(256) void cast_block_kernel(Mat<const double> src, 
             double v = src.at(i, j) * sr[i];
             v = v * sc[j];
             v = v * mu;
-            dst.at(i, j) = (float)v;
+            const float f = (float)v;
+            dst.at(i, j) = f;
+            if (nonfinite && !__builtin_isfinite(f)) *nonfinite = 1;
         }
     }
 }
 
 hipError_t pf_cast_scale(hipStream_t st, const RfpView<const double>& a, const RfpView<float>& o, int scale, double mu,
-                         double* s)
+                         double* s, int* nonfinite)
 {
     const int64_t n = a.m1 + a.m2;
     if (n == 0) return hipSuccess;
@@ -67,7 +70,7 @@ hipError_t pf_cast_scale(hipStream_t st, const RfpView<const double>& a, const R
         if (m <= 0 || nn <= 0) return;
         const int64_t tm = (m + TT - 1) / TT, tn = (nn + TT - 1) / TT;
         hipLaunchKernelGGL(cast_block_kernel, dim3((unsigned)(tm * tn)), dim3(256), 0, st, src, dst, m, nn,
-                           lower ? 1 : 0, sr, sc, mu, tm);
+                           lower ? 1 : 0, sr, sc, mu, tm, nonfinite);
     };
     blk(a.t1, o.t1, a.m1, a.m1, true, s, s);
     blk(a.s, o.s, a.m2, a.m1, false, s + a.m1, s);
@@ -197,8 +200,9 @@ hipError_t pf_norm(hipStream_t st, const RfpView<const double>& a, int which, do
 // ------------------------------------------------------- refinement sweep
 // out(i, c) = (float)(s[i] * r(i, c))
 __global__ void ir_scale_cast_kernel(const double* r, int64_t ldr, const double* s, float* out, int64_t ldo, int64_t n,
-                                     int64_t nrhs)
+                                     int64_t nrhs, const int* gate)
 {
+    if (gate && *gate) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t c = blockIdx.y;
     if (i < n && c < nrhs) out[i + c * ldo] = (float)(s[i] * r[i + c * ldr]);
@@ -206,8 +210,9 @@ __global__ void ir_scale_cast_kernel(const double* r, int64_t ldr, const double*
 
 // x(i, c) += (double)d(i, c) * s[i] * mu   (or x = ..., accumulate == 0)
 __global__ void ir_update_kernel(double* x, int64_t ldx, const double* s, double mu, const float* d, int64_t ldd,
-                                 int64_t n, int64_t nrhs, int accumulate)
+                                 int64_t n, int64_t nrhs, int accumulate, const int* gate)
 {
+    if (gate && *gate) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t c = blockIdx.y;
     if (i < n && c < nrhs) {
@@ -218,8 +223,9 @@ __global__ void ir_update_kernel(double* x, int64_t ldx, const double* s, double
 
 // out[c] = sum_i u(i, c) v(i, c), one workgroup per column (fixed order)
 __global__ __launch_bounds__(256) void col_dot_kernel(const double* u, const double* v, int64_t ld, int64_t n,
-                                                      double* out)
+                                                      double* out, const int* gate)
 {
+    if (gate && *gate) return;
     __shared__ double red[256];
     const int64_t c = blockIdx.x;
     double acc = 0.0;
@@ -235,8 +241,9 @@ __global__ __launch_bounds__(256) void col_dot_kernel(const double* u, const dou
 
 // alpha_c = rz[c] / pq[c] (0 when pq[c] = 0); d += alpha p; r -= alpha q
 __global__ void pcg_step_kernel(double* d, int64_t ldd, double* r, const double* p, const double* q, const double* rz,
-                                const double* pq, int64_t ld, int64_t n)
+                                const double* pq, int64_t ld, int64_t n, const int* gate)
 {
+    if (gate && *gate) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t c = blockIdx.y;
     if (i >= n) return;
@@ -248,8 +255,9 @@ __global__ void pcg_step_kernel(double* d, int64_t ldd, double* r, const double*
 
 // beta_c = rz_new[c] / rz_old[c] (0 when rz_old[c] = 0); p = z + beta p
 __global__ void pcg_dir_kernel(double* p, const double* z, const double* rz_new, const double* rz_old, int64_t ld,
-                               int64_t n)
+                               int64_t n, const int* gate)
 {
+    if (gate && *gate) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t c = blockIdx.y;
     if (i >= n) return;
@@ -259,8 +267,10 @@ __global__ void pcg_dir_kernel(double* p, const double* z, const double* rz_new,
 }
 
 // out[c] = max_i |v(i, c)|, one workgroup per column
-__global__ __launch_bounds__(256) void colmax_kernel(const double* v, int64_t ld, int64_t n, double* out)
+__global__ __launch_bounds__(256) void colmax_kernel(const double* v, int64_t ld, int64_t n, double* out,
+                                                     const int* gate)
 {
+    if (gate && *gate) return;
     __shared__ double red[256];
     const int64_t c = blockIdx.x;
     double m = 0.0;
@@ -282,13 +292,18 @@ __global__ __launch_bounds__(256) void colmax_kernel(const double* v, int64_t ld
 
 // eta = max_c rmax[c] / (anorm * xmax[c] + bmax[c])  (normwise backward error)
 __global__ __launch_bounds__(256) void eta_kernel(const double* rmax, const double* xmax, const double* bmax,
-                                                  const double* anorm, int64_t nrhs, double* eta)
+                                                  const double* anorm, int64_t nrhs, double* eta, const int* gate)
 {
+    if (gate && *gate) return;
     __shared__ double red[256];
     double m = 0.0;
     for (int64_t c = threadIdx.x; c < nrhs; c += 256) {
         const double den = *anorm * xmax[c] + bmax[c];
-        const double e = den > 0.0 ? rmax[c] / den : (rmax[c] > 0.0 ? __builtin_inf() : 0.0);
+        // a NaN anywhere (residual, solution, right-hand side, norm) gives NaN
+        const double e = (den != den || rmax[c] != rmax[c]) ? __builtin_nan("")
+                         : den > 0.0                        ? rmax[c] / den
+                         : rmax[c] > 0.0                    ? __builtin_inf()
+                                                            : 0.0;
         m = (e > m || e != e) ? e : m;
     }
     red[threadIdx.x] = m;
@@ -304,60 +319,197 @@ __global__ __launch_bounds__(256) void eta_kernel(const double* rmax, const doub
 }
 
 hipError_t ir_scale_cast(hipStream_t st, const double* r, int64_t ldr, const double* s, float* out, int64_t ldo,
-                         int64_t n, int64_t nrhs)
+                         int64_t n, int64_t nrhs, const int* gate)
 {
     if (n <= 0 || nrhs <= 0) return hipSuccess;
     hipLaunchKernelGGL(ir_scale_cast_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, r,
-                       ldr, s, out, ldo, n, nrhs);
+                       ldr, s, out, ldo, n, nrhs, gate);
     return hipGetLastError();
 }
 
 hipError_t ir_update(hipStream_t st, double* x, int64_t ldx, const double* s, double mu, const float* d, int64_t ldd,
-                     int64_t n, int64_t nrhs, bool accumulate)
+                     int64_t n, int64_t nrhs, bool accumulate, const int* gate)
 {
     if (n <= 0 || nrhs <= 0) return hipSuccess;
     hipLaunchKernelGGL(ir_update_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, x, ldx,
-                       s, mu, d, ldd, n, nrhs, accumulate ? 1 : 0);
+                       s, mu, d, ldd, n, nrhs, accumulate ? 1 : 0, gate);
     return hipGetLastError();
 }
 
-hipError_t col_dot(hipStream_t st, const double* u, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out)
+hipError_t col_dot(hipStream_t st, const double* u, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out,
+                   const int* gate)
 {
     if (nrhs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(col_dot_kernel, dim3((unsigned)nrhs), dim3(256), 0, st, u, v, ld, n, out);
+    hipLaunchKernelGGL(col_dot_kernel, dim3((unsigned)nrhs), dim3(256), 0, st, u, v, ld, n, out, gate);
     return hipGetLastError();
 }
 
 hipError_t pcg_step(hipStream_t st, double* d, int64_t ldd, double* r, const double* p, const double* q,
-                    const double* rz, const double* pq, int64_t ld, int64_t n, int64_t nrhs)
+                    const double* rz, const double* pq, int64_t ld, int64_t n, int64_t nrhs, const int* gate)
 {
     if (n <= 0 || nrhs <= 0) return hipSuccess;
     hipLaunchKernelGGL(pcg_step_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, d, ldd, r,
-                       p, q, rz, pq, ld, n);
+                       p, q, rz, pq, ld, n, gate);
     return hipGetLastError();
 }
 
 hipError_t pcg_dir(hipStream_t st, double* p, const double* z, const double* rz_new, const double* rz_old, int64_t ld,
-                   int64_t n, int64_t nrhs)
+                   int64_t n, int64_t nrhs, const int* gate)
 {
     if (n <= 0 || nrhs <= 0) return hipSuccess;
     hipLaunchKernelGGL(pcg_dir_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, p, z,
-                       rz_new, rz_old, ld, n);
+                       rz_new, rz_old, ld, n, gate);
     return hipGetLastError();
 }
 
-hipError_t col_max(hipStream_t st, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out)
+hipError_t col_max(hipStream_t st, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out, const int* gate)
 {
     if (nrhs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)nrhs), dim3(256), 0, st, v, ld, n, out);
+    hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)nrhs), dim3(256), 0, st, v, ld, n, out, gate);
     return hipGetLastError();
 }
 
 hipError_t backward_error(hipStream_t st, const double* rmax, const double* xmax, const double* bmax,
-                          const double* anorm, int64_t nrhs, double* eta)
+                          const double* anorm, int64_t nrhs, double* eta, const int* gate)
 {
-    hipLaunchKernelGGL(eta_kernel, dim3(1), dim3(256), 0, st, rmax, xmax, bmax, anorm, nrhs, eta);
+    hipLaunchKernelGGL(eta_kernel, dim3(1), dim3(256), 0, st, rmax, xmax, bmax, anorm, nrhs, eta, gate);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- refinement control
+// The refinement's decisions are taken on the device, by one-thread kernels
+// between the sweeps, and every sweep kernel reads a gate word: the host
+// enqueues the setup, max_iter sweeps and the fall-back once, without
+// waiting, and the sweeps after convergence (or the fall-back when it is not
+// needed) exit at their first instruction.
+__device__ __forceinline__ void ir_gates(IrCtl* c)
+{
+    c->g_ir = c->phase != IR_CLASSIC;
+    c->g_pcg = c->phase != IR_PCG;
+    c->g_run = c->phase >= IR_DONE;
+    c->g_fb = c->phase != IR_FALLBACK;
+    // the fall-back factor's INFO word doubles as its gate: nonzero skips it
+    c->fb_info = c->phase == IR_FALLBACK ? 0 : -1;
+}
+
+__global__ void ir_start_kernel(IrCtl* c)
+{
+    if (threadIdx.x != 0) return;
+    c->phase = IR_CLASSIC;
+    c->code = 0;
+    c->lp_info = 0;
+    c->nonfinite = 0;
+    c->eta = 0.0;
+    c->prev = 0.0;
+    ir_gates(c);
+}
+
+// after the scaled cast and the low-precision factor
+__global__ void ir_setup_decide_kernel(IrCtl* c)
+{
+    if (threadIdx.x != 0) return;
+    if (c->nonfinite) {
+        c->phase = IR_FALLBACK;
+        c->code = -4;
+    } else if (c->lp_info != 0) {
+        c->phase = IR_FALLBACK;
+        c->code = -3;
+    }
+    ir_gates(c);
+}
+
+// after sweep `it` (1-based) has left its backward error in c->eta: converged
+// at eta <= tol; a classical sweep that does not cut eta fourfold switches to
+// conjugate-gradient sweeps; a conjugate-gradient sweep that does not cut it
+// below 0.9 times the previous one stalls (-2); max_iter sweeps without
+// convergence give -1.  NaN compares false everywhere, so it ends in a stall.
+__global__ void ir_decide_kernel(IrCtl* c, int it, int max_iter, double tol)
+{
+    if (threadIdx.x != 0 || c->phase >= IR_DONE) return;
+    const double eta = c->eta;
+    if (eta <= tol) {
+        c->phase = IR_DONE;
+        c->code = it;
+    } else {
+        const bool swept_pcg = c->phase == IR_PCG;
+        if (it > 1 && swept_pcg && !(eta < 0.9 * c->prev)) {
+            c->phase = IR_FALLBACK;
+            c->code = -2;
+        } else if (it >= max_iter) {
+            c->phase = IR_FALLBACK;
+            c->code = -1;
+        } else if (it > 1 && !swept_pcg && !(eta < 0.25 * c->prev)) {
+            c->phase = IR_PCG;
+        }
+        c->prev = eta;
+    }
+    ir_gates(c);
+}
+
+__global__ void ir_finish_kernel(const IrCtl* c, int* iter, int* info)
+{
+    if (threadIdx.x != 0) return;
+    *iter = c->code;
+    *info = c->phase == IR_FALLBACK ? c->fb_info : 0;
+}
+
+hipError_t ir_start(hipStream_t st, IrCtl* c)
+{
+    hipLaunchKernelGGL(ir_start_kernel, dim3(1), dim3(64), 0, st, c);
+    return hipGetLastError();
+}
+
+hipError_t ir_setup_decide(hipStream_t st, IrCtl* c)
+{
+    hipLaunchKernelGGL(ir_setup_decide_kernel, dim3(1), dim3(64), 0, st, c);
+    return hipGetLastError();
+}
+
+hipError_t ir_decide(hipStream_t st, IrCtl* c, int it, int max_iter, double tol)
+{
+    hipLaunchKernelGGL(ir_decide_kernel, dim3(1), dim3(64), 0, st, c, it, max_iter, tol);
+    return hipGetLastError();
+}
+
+hipError_t ir_finish(hipStream_t st, IrCtl* c, int* iter, int* info)
+{
+    hipLaunchKernelGGL(ir_finish_kernel, dim3(1), dim3(64), 0, st, (const IrCtl*)c, iter, info);
+    return hipGetLastError();
+}
+
+__global__ void ir_copy_kernel(double* y, int64_t ldy, const double* x, int64_t ldx, int64_t n, const int* gate)
+{
+    if (gate && *gate) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (i < n) y[i + c * ldy] = x ? x[i + c * ldx] : 0.0;
+}
+
+hipError_t ir_copy(hipStream_t st, double* y, int64_t ldy, const double* x, int64_t ldx, int64_t n, int64_t nrhs,
+                   const int* gate)
+{
+    if (n <= 0 || nrhs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ir_copy_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, y, ldy, x,
+                       ldx, n, gate);
+    return hipGetLastError();
+}
+
+// grid-stride 1-D copy (two doubles per thread and step)
+__global__ __launch_bounds__(256) void gated_copy_kernel(double* dst, const double* src, int64_t count,
+                                                         const int* gate)
+{
+    if (gate && *gate) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) dst[i] = src[i];
+}
+
+hipError_t gated_copy(hipStream_t st, double* dst, const double* src, int64_t count, const int* gate)
+{
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 8192);
+    hipLaunchKernelGGL(gated_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dst, src, count, gate);
     return hipGetLastError();
 }
 
 }  // namespace rfp
+

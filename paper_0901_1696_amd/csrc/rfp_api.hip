@@ -39,13 +39,23 @@ struct Profiler {
         int64_t launches = 0;
         double ms = 0, flops = 0, bytes = 0;
     };
-    static constexpr int POOL_PAIRS = 16384;
+    static constexpr int POOL_PAIRS = 32768;
     std::vector<hipEvent_t> pool;
     std::vector<Rec> pending;
     std::map<std::string, Agg> agg;
     int used = 0;
     hipError_t err = hipSuccess;
 
+    // create the whole pool at once (called when profiling is enabled)
+    hipError_t reserve()
+    {
+        while ((int)pool.size() < 2 * POOL_PAIRS) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
+            pool.push_back(e);
+        }
+        return hipSuccess;
+    }
     int begin(const char* name, double flops, double bytes, hipStream_t s)
     {
         if (used == POOL_PAIRS) fold();
@@ -118,7 +128,8 @@ struct rfp_context {
     int nev, evi;
     int* flags;           // ready flags of the fused triangular solves
     size_t flags_bytes;
-    int epoch;            // last epoch handed to a fused solve
+    int* ctl;             // device words: [0] epoch of the flags, [1] solve status (bit 0: a wait gave up)
+    int spin_limit;       // polls of an unpublished block row before a fused-solve wait gives up
     void* ir;             // mixed-precision solve workspace
     size_t ir_bytes;
     void* bat;            // batched-solver scratch (work counter + per-workgroup scratch)
@@ -246,7 +257,10 @@ struct Run {
     }
     // Fused triangular solve with the whole factor (see block_solve).
     int* flags = nullptr;
-    void solve(bool forward, const RfpView<const T>& v, const T* winv, Mat<T> B, int64_t nrhs, int epoch)
+    int64_t nflags = 0;
+    int* ctl = nullptr;
+    int spin_limit = DEFAULT_SPIN_LIMIT;
+    void solve(bool forward, const RfpView<const T>& v, const T* winv, Mat<T> B, int64_t nrhs)
     {
         if (rec) {
             if (rfp_plan_op* o = next(RFP_PLAN_BLOCK_SOLVE)) {
@@ -260,7 +274,9 @@ struct Run {
             }
             return;
         }
-        chk(block_solve<T>(ex, forward, v.t1, v.s, v.t2, v.m1, v.m2, winv, B.p, B.cs, nrhs, flags, epoch));
+        chk(epoch_bump(ex.stream, flags, nflags, ctl));
+        chk(block_solve<T>(ex, forward, v.t1, v.s, v.t2, v.m1, v.m2, winv, B.p, B.cs, nrhs, flags, ctl, ctl + 1,
+                           spin_limit));
     }
     void leaf_potrf(int64_t order, Mat<T> A, int64_t goff, T* winv)
     {
@@ -367,6 +383,21 @@ struct Run {
         trsm_rlt(m, n2, B.sub(0, n1), L.sub(n1, n1), winv + nleaves(n1, nb) * nb * nb);
     }
 
+
+    // B (m x n) <- B L^{-1}; L lower of order n whose leaf inverses are in winv.
+    void trsm_rln(int64_t m, int64_t n, Mat<T> B, Mat<const T> L, const T* winv)
+    {
+        if (m <= 0 || n <= 0) return;
+        if (n <= nb) {
+            // B W with W = L^{-1} lower: the operand B(j, kk) = W(kk, j) is upper
+            mm(m, n, n, T(1), B, TRI_NONE, Mat<const T>{winv, 1, nb}, TRI_UPPER, T(0), B, false, true);
+            return;
+        }
+        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
+        trsm_rln(m, n2, B.sub(0, n1), L.sub(n1, n1), winv + nleaves(n1, nb) * nb * nb);
+        mm(m, n1, n2, T(-1), B.sub(0, n1), TRI_NONE, L.sub(n1, 0).tr(), TRI_NONE, T(1), B);
+        trsm_rln(m, n1, B, L, winv);
+    }
 
     // ---------------------------------------------------------------- solve
     void leaves_inv(Mat<const T> A, int64_t n, T* winv)
@@ -514,25 +545,41 @@ static hipError_t prepare(rfp_context* h, size_t inv_need)
 }
 
 // Ready flags for the fused solves: grown on demand and cleared once when
-// allocated; launches then tell stale flags apart by their epoch.
+// allocated; launches then tell stale flags apart by their epoch, a device
+// word (ctl[0]) that a one-thread kernel advances before every launch.  The
+// control words are allocated and cleared once, with the first flags.
 static hipError_t prepare_flags(rfp_context* h, int64_t count)
 {
-    const size_t need = size_t(count) * sizeof(int);
+    hipError_t e = hipSuccess;
+    if (!h->ctl) {
+        e = hipMalloc((void**)&h->ctl, 256);
+        if (e == hipSuccess) e = hipMemset(h->ctl, 0, 256);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) return e;
+    }
+    const size_t need = size_t(std::max<int64_t>(count, 1)) * sizeof(int);
     if (need <= h->flags_bytes) return hipSuccess;
-    hipError_t e = ensure((void**)&h->flags, &h->flags_bytes, need);
+    e = ensure((void**)&h->flags, &h->flags_bytes, need);
     if (e == hipSuccess) e = hipMemset(h->flags, 0, h->flags_bytes);
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    h->epoch = 0;
     return e;
 }
 
-static int next_epoch(rfp_context* h, hipStream_t s)
+// Both fused solves (forward, backward) over a factor whose 64-row diagonal
+// blocks' inverses are in w (those of T1, then of T2).
+template <typename T>
+static hipError_t solve_with_leaves(rfp_context* h, const Exec& ex, const RfpView<const T>& v, const T* w, T* b,
+                                    int64_t ldb, int64_t nrhs)
 {
-    if (h->epoch >= (1 << 30)) {
-        (void)fill_int(s, h->flags, (int64_t)(h->flags_bytes / sizeof(int)), 0);
-        h->epoch = 0;
+    const int64_t nf = (int64_t)(h->flags_bytes / sizeof(int));
+    for (int fwd = 1; fwd >= 0; fwd--) {
+        hipError_t e = epoch_bump(ex.stream, h->flags, nf, h->ctl);
+        if (e == hipSuccess)
+            e = block_solve<T>(ex, fwd == 1, v.t1, v.s, v.t2, v.m1, v.m2, w, b, ldb, nrhs, h->flags, h->ctl,
+                               h->ctl + 1, h->spin_limit);
+        if (e != hipSuccess) return e;
     }
-    return ++h->epoch;
+    return hipSuccess;
 }
 
 static rfp_schedule_t default_schedule()
@@ -634,8 +681,11 @@ static T* plan_base(int buf)
 
 template <typename T>
 static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf, int* info, hipStream_t s,
-                      PlanRec* rec = nullptr, int lowp = 0, const rfp_schedule_t* plan_sched = nullptr)
+                      PlanRec* rec = nullptr, int lowp = 0, const rfp_schedule_t* plan_sched = nullptr,
+                      bool gated = false)
 {
+    // gated: *info is not reset; the factorization runs only if the caller
+    // leaves it at 0 (every kernel of the factorization exits while it is not)
     if (!h && !rec) return RFP_ERR_HANDLE;
     if (bad_tr(transr)) return -1;
     if (bad_ul(uplo)) return -2;
@@ -665,7 +715,7 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     }
     r.nb = NB2;
     RfpView<T> v = rfp_view(b, arf);
-    r.setinfo(info);
+    if (!gated) r.setinfo(info);
     // step 1: L11 = chol(A11)              (Figure 4, factorization step 1)
     // step 2: L21 = A21 L11^{-T}           (step 2, TRSM)
     // Step 2 runs right-looking by chunks of at least SCHUNK columns of L11,
@@ -726,7 +776,6 @@ static int pftrs_impl(rfp_context* h, char transr, char uplo, int64_t n, int64_t
     const int64_t l1 = nleaves(b.m1, NB), l2 = nleaves(b.m2, NB);
     Run<T> r;
     T* w1;
-    int e_fwd = 1, e_bwd = 2;
     DeviceGuard g(rec ? -1 : h->device);
     if (rec) {
         r.rec = rec;
@@ -736,8 +785,9 @@ static int pftrs_impl(rfp_context* h, char transr, char uplo, int64_t n, int64_t
         if (prepare_flags(h, block_solve_flags(b.m1, b.m2, nrhs)) != hipSuccess) return RFP_ERR_RUNTIME;
         r = make_run<T>(h, s, nullptr);
         r.flags = h->flags;
-        e_fwd = next_epoch(h, s);
-        e_bwd = next_epoch(h, s);
+        r.nflags = (int64_t)(h->flags_bytes / sizeof(int));
+        r.ctl = h->ctl;
+        r.spin_limit = h->spin_limit;
         w1 = (T*)h->inv;
     }
     T* w2 = w1 + l1 * NB * NB;
@@ -749,8 +799,8 @@ static int pftrs_impl(rfp_context* h, char transr, char uplo, int64_t n, int64_t
     // L Y = B, then L^T X = Y (Figure 4, solution): the 2 x 2 block steps
     // (Y1 = L11^{-1} B1, B2 -= L21 Y1, Y2 = L22^{-1} B2 and back) run as one
     // blocked substitution per direction over all diagonal blocks of L11 and L22
-    r.solve(true, v, w1, B, nrhs, e_fwd);
-    r.solve(false, v, w1, B, nrhs, e_bwd);
+    r.solve(true, v, w1, B, nrhs);
+    r.solve(false, v, w1, B, nrhs);
     return r.err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
@@ -794,17 +844,19 @@ static int pftri_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
 // Workspace carve-up of the refinement driver (256-byte aligned pieces).
 struct IrSpace {
     float* a32;            // scaled FP32 copy of the matrix, same RFP layout
+    double* a64;           // FP64 copy of the matrix for the fall-back factor
+    float* w32;            // inverses of the 64-row diagonal blocks of the FP32 factor
     double* s;             // diagonal scaling D^{-1/2}
     double* r;             // residual, n x nrhs, leading dimension n
     float* r32;            // scaled residual / correction in FP32
-    double *bmax, *rmax, *xmax, *anorm, *eta, *normwork;
+    double *bmax, *rmax, *xmax, *anorm, *normwork;
     double *cr, *cz, *cp, *cq;  // conjugate-gradient vectors, n x nrhs each
     double *rz0, *rz1, *pq;     // their per-column scalars
     double* symm;               // partial products of A X
-    int* info;
+    IrCtl* ctl;                 // device-side decisions and gates
     size_t bytes;
 };
-static IrSpace ir_space(void* base, int64_t n, int64_t nrhs)
+static IrSpace ir_space(void* base, int64_t n, int64_t nrhs, int64_t nleaf64)
 {
     IrSpace w;
     size_t off = 0;
@@ -813,7 +865,10 @@ static IrSpace ir_space(void* base, int64_t n, int64_t nrhs)
         off += (bytes + 255) & ~(size_t)255;
         return (char*)base + o;
     };
-    w.a32 = (float*)take(sizeof(float) * (size_t)(n * (n + 1) / 2));
+    const size_t nt = (size_t)(n * (n + 1) / 2);
+    w.a32 = (float*)take(sizeof(float) * nt);
+    w.a64 = (double*)take(sizeof(double) * nt);
+    w.w32 = (float*)take(sizeof(float) * (size_t)nleaf64 * NB * NB);
     w.s = (double*)take(sizeof(double) * (size_t)n);
     w.r = (double*)take(sizeof(double) * (size_t)(n * nrhs));
     w.r32 = (float*)take(sizeof(float) * (size_t)(n * nrhs));
@@ -821,7 +876,6 @@ static IrSpace ir_space(void* base, int64_t n, int64_t nrhs)
     w.rmax = (double*)take(sizeof(double) * (size_t)nrhs);
     w.xmax = (double*)take(sizeof(double) * (size_t)nrhs);
     w.anorm = (double*)take(sizeof(double));
-    w.eta = (double*)take(sizeof(double));
     w.normwork = (double*)take(sizeof(double) * (size_t)(n + 3));
     w.cr = (double*)take(sizeof(double) * (size_t)(n * nrhs));
     w.cz = (double*)take(sizeof(double) * (size_t)(n * nrhs));
@@ -831,30 +885,14 @@ static IrSpace ir_space(void* base, int64_t n, int64_t nrhs)
     w.rz1 = (double*)take(sizeof(double) * (size_t)nrhs);
     w.pq = (double*)take(sizeof(double) * (size_t)nrhs);
     w.symm = (double*)take(symm_thin_workspace((n + 1) / 2, n / 2));
-    w.info = (int*)take(sizeof(int));
+    w.ctl = (IrCtl*)take(sizeof(IrCtl));
     w.bytes = off;
     return w;
 }
 
-// R = B - A X
-static hipError_t rfp_residual(const Exec& ex, const RfpView<const double>& v, const double* b, int64_t ldb,
-                               const double* x, int64_t ldx, double* r, int64_t nrhs, double* ws)
-{
-    const int64_t n = v.m1 + v.m2;
-    hipError_t e = copy2d<double, double>(ex.stream, Mat<double>{r, 1, n}, Mat<const double>{b, 1, ldb}, n, nrhs,
-                                          false);
-    return e != hipSuccess ? e : symm_thin(ex, v, x, ldx, -1.0, 1.0, r, n, nrhs, ws);
-}
-
-// Host copy of a few device words (the refinement decisions): one sync.
-template <typename V>
-static hipError_t fetch(hipStream_t s, const V* d, V* h)
-{
-    hipError_t e = hipMemcpyAsync(h, d, sizeof(V), hipMemcpyDeviceToHost, s);
-    return e == hipSuccess ? hipStreamSynchronize(s) : e;
-}
-
-// RFP_IR_TRACE=1 prints the backward error of every refinement sweep to stderr.
+// RFP_IR_TRACE=1 makes the refinement synchronise after every sweep and print
+// its backward error to stderr (a debugging aid; the call is then no longer
+// free of host synchronisation).
 static bool ir_trace()
 {
     static int on = -1;
@@ -864,6 +902,18 @@ static bool ir_trace()
     }
     return on == 1;
 }
+
+// Scaling of the low-precision copy: the unit-diagonal matrix D^{-1/2} A
+// D^{-1/2} has entries in [-1, 1] and so has its Cholesky factor, whose
+// entries are the only values rounded to the operand precision (the trailing
+// matrix stays FP32).  For FP16 the whole copy is multiplied by
+// mu = 2^25, so that the factor's entries (at most sqrt(mu) = 5793 in
+// magnitude) reach up to a tenth of the largest FP16 value (65504) and
+// small entries keep their precision instead of underflowing (the scaling
+// rule of Higham and Pranesh for squeezing a matrix into half precision,
+// applied to the factor); a power of two keeps the scaling exact.  BF16 and
+// FP32 have FP32's exponent range and take mu = 1.
+static double ir_mu(int fprec) { return fprec == RFP_PREC_FP16 ? 33554432.0 : 1.0; }
 
 static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64_t n, int64_t nrhs, const double* arf,
                         const double* b, int64_t ldb, double* x, int64_t ldx, double tol, int max_iter, int* iter,
@@ -884,124 +934,291 @@ static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64
     if (max_iter < 1) return -12;
     if (!iter) return -13;
     if (!info) return -14;
-    *iter = 0;
-    *info = 0;
-    if (n == 0 || nrhs == 0) return 0;
     DeviceGuard g(h->device);
-    const IrSpace probe = ir_space(nullptr, n, nrhs);
-    if (ensure(&h->ir, &h->ir_bytes, probe.bytes) != hipSuccess) return RFP_ERR_RUNTIME;
-    IrSpace w = ir_space(h->ir, n, nrhs);
+    if (n == 0 || nrhs == 0) {
+        const bool ok0 = set_int(st, iter, 0) == hipSuccess && set_int(st, info, 0) == hipSuccess;
+        return ok0 ? 0 : RFP_ERR_RUNTIME;
+    }
     RfpBlocks blk;
     rfp_blocks(transr, uplo, n, &blk);
+    const int64_t l1 = nleaves(blk.m1, NB), l2 = nleaves(blk.m2, NB);
+    const int64_t lv = std::max(nleaves(blk.m1, NB2), nleaves(blk.m2, NB2));
+    // Every workspace is sized before anything is enqueued, so that a call on
+    // sizes seen before allocates nothing and can be captured in a HIP graph.
+    if (prepare(h, std::max<size_t>(size_t(lv) * NB2 * NB2, size_t(l1 + l2) * NB * NB) * sizeof(double)) !=
+        hipSuccess)
+        return RFP_ERR_RUNTIME;
+    if (prepare_flags(h, block_solve_flags(blk.m1, blk.m2, nrhs)) != hipSuccess) return RFP_ERR_RUNTIME;
+    const IrSpace probe = ir_space(nullptr, n, nrhs, l1 + l2);
+    if (ensure(&h->ir, &h->ir_bytes, probe.bytes) != hipSuccess) return RFP_ERR_RUNTIME;
+    IrSpace w = ir_space(h->ir, n, nrhs, l1 + l2);
     RfpView<const double> v = rfp_view(blk, arf);
     RfpView<float> v32 = rfp_view(blk, w.a32);
+    RfpView<const float> v32c = rfp_view(blk, (const float*)w.a32);
+    IrCtl* c = w.ctl;
     Exec ex{};
     ex.stream = st;
     ex.prof = h->prof;
     ex.tune = h->tune;
-    const double mu = 1.0;
+    ex.splitk_ws = h->splitk;
+    ex.splitk_bytes = h->splitk_bytes;
+    Exec ex_run = ex, ex_ir = ex, ex_pcg = ex;
+    ex_run.gate = &c->g_run;
+    ex_ir.gate = &c->g_ir;
+    ex_pcg.gate = &c->g_pcg;
+    const double mu = ir_mu(fprec);
     hipError_t e = hipSuccess;
     auto ok = [&](hipError_t q) {
         if (q != hipSuccess && e == hipSuccess) e = q;
         return e == hipSuccess;
     };
     // scaled low-precision copy, its factor, and the norms that stay fixed
-    ok(pf_cast_scale(st, v, v32, 1, mu, w.s));
+    ok(ir_start(st, c));
+    ok(pf_cast_scale(st, v, v32, 1, mu, w.s, &c->nonfinite));
     ok(pf_norm(st, v, 1, w.normwork, w.anorm));
     ok(col_max(st, b, ldb, n, nrhs, w.bmax));
     if (!ok(hipGetLastError())) return RFP_ERR_RUNTIME;
-    int rc = pftrf_impl<float>(h, transr, uplo, n, w.a32, w.info, st, nullptr, fprec);
+    int rc = pftrf_impl<float>(h, transr, uplo, n, w.a32, &c->lp_info, st, nullptr, fprec);
     if (rc != 0) return rc;
-    int linfo = 0;
-    if (!ok(fetch(st, w.info, &linfo))) return RFP_ERR_RUNTIME;
-    int code = 0;  // 0 converged, else the fallback reason
-    if (linfo != 0) code = -3;
-    if (code == 0) {
-        ex.splitk_ws = h->splitk;
-        ex.splitk_bytes = h->splitk_bytes;
-        // M^{-1} = mu D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2}: the low-precision
-        // preconditioner, applied as a scaled cast, two FP32 triangular
-        // solves and an FP64 rescale into z (or added to z)
-        auto prec = [&](const double* v_in, double* z, int64_t ldz, bool accumulate) {
-            ok(ir_scale_cast(st, v_in, n, w.s, w.r32, n, n, nrhs));
-            if (e != hipSuccess) return false;
-            if (pftrs_impl<float>(h, transr, uplo, n, nrhs, w.a32, w.r32, n, st) != 0) return false;
-            return ok(ir_update(st, z, ldz, w.s, mu, w.r32, n, n, nrhs, accumulate));
-        };
-        // k steps of conjugate gradients on A d = r from d = 0, preconditioned
-        // by M^{-1}, with d added straight into x (FP64 throughout)
-        auto pcg = [&](int k) {
-            ok(copy2d<double, double>(st, Mat<double>{w.cr, 1, n}, Mat<const double>{w.r, 1, n}, n, nrhs, false));
-            if (!prec(w.cr, w.cz, n, false)) return false;
-            ok(copy2d<double, double>(st, Mat<double>{w.cp, 1, n}, Mat<const double>{w.cz, 1, n}, n, nrhs, false));
-            ok(col_dot(st, w.cr, w.cz, n, n, nrhs, w.rz0));
-            double *rz = w.rz0, *rzn = w.rz1;
-            for (int i = 0; i < k && e == hipSuccess; i++) {
-                ok(symm_thin(ex, v, w.cp, n, 1.0, 0.0, w.cq, n, nrhs, w.symm));
-                ok(col_dot(st, w.cp, w.cq, n, n, nrhs, w.pq));
-                ok(pcg_step(st, x, ldx, w.cr, w.cp, w.cq, rz, w.pq, n, n, nrhs));
-                if (i + 1 == k) break;
-                if (!prec(w.cr, w.cz, n, false)) return false;
-                ok(col_dot(st, w.cr, w.cz, n, n, nrhs, rzn));
-                ok(pcg_dir(st, w.cp, w.cz, rzn, rz, n, n, nrhs));
-                std::swap(rz, rzn);
-            }
-            return e == hipSuccess;
-        };
-        // x = 0, r = b; each sweep corrects x from r, then r = b - A x in FP64.
-        // A sweep first applies M^{-1} once (classical refinement); once that
-        // stops cutting the backward error by 4x per sweep, sweeps run
-        // PCG_STEPS preconditioned conjugate-gradient steps instead.
-        constexpr int PCG_STEPS = 8;
-        ok(copy2d<double, double>(st, Mat<double>{w.r, 1, n}, Mat<const double>{b, 1, ldb}, n, nrhs, false));
-        for (int64_t c = 0; c < nrhs; c++) ok(fill_double(st, x + c * ldx, n, 0.0));
-        double prev = 0.0;
-        bool use_pcg = false;
-        code = -1;
-        for (int it = 1; it <= max_iter; it++) {
-            const bool swept_pcg = use_pcg;
-            const bool good = swept_pcg ? pcg(PCG_STEPS) : prec(w.r, x, ldx, true);
-            if (!good) return RFP_ERR_RUNTIME;
-            ok(rfp_residual(ex, v, b, ldb, x, ldx, w.r, nrhs, w.symm));
-            ok(col_max(st, w.r, n, n, nrhs, w.rmax));
-            ok(col_max(st, x, ldx, n, nrhs, w.xmax));
-            ok(backward_error(st, w.rmax, w.xmax, w.bmax, w.anorm, nrhs, w.eta));
-            double eta = 0.0;
-            if (!ok(fetch(st, w.eta, &eta))) return RFP_ERR_RUNTIME;
-            if (ir_trace())
-                fprintf(stderr, "rfp_dpfsv_ir: sweep %d (%s) backward error %.3e\n", it, swept_pcg ? "pcg" : "ir",
-                        eta);
-            if (eta <= tol) {
-                code = it;
-                break;
-            }
-            if (it > 1 && !swept_pcg && !(eta < 0.25 * prev)) use_pcg = true;
-            // stalled: a conjugate-gradient sweep no longer cuts the backward error
-            if (it > 1 && swept_pcg && !(eta < 0.9 * prev)) {
-                code = -2;
-                break;
-            }
-            prev = eta;
+    ok(ir_setup_decide(st, c));  // -4 non-finite scaled copy, -3 factor not positive definite
+    // inverses of the low-precision factor's 64-row diagonal blocks, once
+    ok(trtri_leaves<float>(ex_run, v32c.t1, blk.m1, w.w32));
+    ok(trtri_leaves<float>(ex_run, v32c.t2, blk.m2, w.w32 + l1 * NB * NB));
+    // M^{-1} = mu D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2}: the low-precision
+    // preconditioner, applied as a scaled cast, the two FP32 fused solves and
+    // an FP64 rescale into z (or added to z)
+    auto prec = [&](const Exec& eg, const double* v_in, double* z, int64_t ldz, bool accumulate) {
+        ok(ir_scale_cast(st, v_in, n, w.s, w.r32, n, n, nrhs, eg.gate));
+        ok(solve_with_leaves<float>(h, eg, v32c, w.w32, w.r32, n, nrhs));
+        ok(ir_update(st, z, ldz, w.s, mu, w.r32, n, n, nrhs, accumulate, eg.gate));
+    };
+    // k steps of conjugate gradients on A d = r from d = 0, preconditioned
+    // by M^{-1}, with d added straight into x (FP64 throughout)
+    auto pcg = [&](int k) {
+        const int* gp = ex_pcg.gate;
+        ok(ir_copy(st, w.cr, n, w.r, n, n, nrhs, gp));
+        prec(ex_pcg, w.cr, w.cz, n, false);
+        ok(ir_copy(st, w.cp, n, w.cz, n, n, nrhs, gp));
+        ok(col_dot(st, w.cr, w.cz, n, n, nrhs, w.rz0, gp));
+        double *rz = w.rz0, *rzn = w.rz1;
+        for (int i = 0; i < k; i++) {
+            ok(symm_thin(ex_pcg, v, w.cp, n, 1.0, 0.0, w.cq, n, nrhs, w.symm));
+            ok(col_dot(st, w.cp, w.cq, n, n, nrhs, w.pq, gp));
+            ok(pcg_step(st, x, ldx, w.cr, w.cp, w.cq, rz, w.pq, n, n, nrhs, gp));
+            if (i + 1 == k) break;
+            prec(ex_pcg, w.cr, w.cz, n, false);
+            ok(col_dot(st, w.cr, w.cz, n, n, nrhs, rzn, gp));
+            ok(pcg_dir(st, w.cp, w.cz, rzn, rz, n, n, nrhs, gp));
+            std::swap(rz, rzn);
+        }
+    };
+    // x = 0, r = b; each sweep corrects x from r, then r = b - A x in FP64
+    // and the backward error goes to the decision kernel.  A sweep first
+    // applies M^{-1} once (classical refinement); once that stops cutting the
+    // backward error by 4x per sweep, sweeps run PCG_STEPS preconditioned
+    // conjugate-gradient steps instead.  Both kinds are enqueued for every
+    // sweep; the gates let exactly one of them run, and none after the
+    // refinement has ended.
+    constexpr int PCG_STEPS = 8;
+    ok(ir_copy(st, w.r, n, b, ldb, n, nrhs, ex_run.gate));
+    ok(ir_copy(st, x, ldx, nullptr, 0, n, nrhs, ex_run.gate));
+    for (int it = 1; it <= max_iter && e == hipSuccess; it++) {
+        prec(ex_ir, w.r, x, ldx, true);
+        pcg(PCG_STEPS);
+        ok(ir_copy(st, w.r, n, b, ldb, n, nrhs, ex_run.gate));
+        ok(symm_thin(ex_run, v, x, ldx, -1.0, 1.0, w.r, n, nrhs, w.symm));
+        ok(col_max(st, w.r, n, n, nrhs, w.rmax, ex_run.gate));
+        ok(col_max(st, x, ldx, n, nrhs, w.xmax, ex_run.gate));
+        ok(backward_error(st, w.rmax, w.xmax, w.bmax, w.anorm, nrhs, &c->eta, ex_run.gate));
+        ok(ir_decide(st, c, it, max_iter, tol));
+        if (ir_trace()) {
+            IrCtl hc;
+            if (hipMemcpyAsync(&hc, c, sizeof hc, hipMemcpyDeviceToHost, st) == hipSuccess &&
+                hipStreamSynchronize(st) == hipSuccess)
+                fprintf(stderr, "rfp_dpfsv_ir: sweep %d backward error %.3e phase %d code %d\n", it, hc.eta, hc.phase,
+                        hc.code);
         }
     }
-    *iter = code;
-    if (code > 0) return 0;
-    // fall-back: FP64 factor of a copy of A, then the FP64 solve
-    void* a64 = nullptr;
-    if (hipMalloc(&a64, sizeof(double) * (size_t)(n * (n + 1) / 2)) != hipSuccess) return RFP_ERR_RUNTIME;
-    ok(hipMemcpyAsync(a64, arf, sizeof(double) * (size_t)(n * (n + 1) / 2), hipMemcpyDeviceToDevice, st));
-    rc = pftrf_impl<double>(h, transr, uplo, n, (double*)a64, w.info, st);
-    if (rc == 0) ok(fetch(st, w.info, info));
-    if (rc == 0 && e == hipSuccess && *info == 0) {
-        ok(copy2d<double, double>(st, Mat<double>{x, 1, ldx}, Mat<const double>{b, 1, ldb}, n, nrhs, false));
-        rc = pftrs_impl<double>(h, transr, uplo, n, nrhs, (const double*)a64, x, ldx, st);
-    }
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(a64);
+    if (e != hipSuccess) return RFP_ERR_RUNTIME;
+    // fall-back, gated on the decision: FP64 factor of a copy of A (its INFO
+    // word is the gate, so a failing factor also skips the solve), then the
+    // FP64 solve
+    const int64_t nt = n * (n + 1) / 2;
+    ok(gated_copy(st, w.a64, arf, nt, &c->g_fb));
+    rc = pftrf_impl<double>(h, transr, uplo, n, w.a64, &c->fb_info, st, nullptr, 0, nullptr, true);
     if (rc != 0) return rc;
+    Exec ex_fb = ex;
+    ex_fb.gate = &c->fb_info;
+    RfpView<const double> v64 = rfp_view(blk, (const double*)w.a64);
+    double* w64 = (double*)h->inv;
+    ok(ir_copy(st, x, ldx, b, ldb, n, nrhs, ex_fb.gate));
+    ok(trtri_leaves<double>(ex_fb, v64.t1, blk.m1, w64));
+    ok(trtri_leaves<double>(ex_fb, v64.t2, blk.m2, w64 + l1 * NB * NB));
+    ok(solve_with_leaves<double>(h, ex_fb, v64, w64, x, ldx, nrhs));
+    ok(ir_finish(st, c, iter, info));
     return e == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
+
+// ------------------------------------------ the rest of the routine table
+// TFTRI (triangular inversion in RFP): the inverse of the lower view L
+// (UPLO='L': the matrix itself; 'U': the stored upper U = L^T, whose inverse
+// is the transpose of L's, in the same places) by the inversion stage of
+// PFTRI: W11 = L11^{-1}, S <- -S W11, W22 = L22^{-1}, S <- W22 S.
+// DIAG='U': the stored diagonal is saved, set to one for the inversion and
+// restored.
+template <typename T>
+static int tftri_impl(rfp_context* h, char transr, char uplo, char diag, int64_t n, T* arf, int* info, hipStream_t s)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (bad_tr(transr)) return -1;
+    if (bad_ul(uplo)) return -2;
+    if (upc(diag) != 'N' && upc(diag) != 'U') return -3;
+    if (n < 0) return -4;
+    if (n > 0 && !arf) return -5;
+    if (!info) return -6;
+    DeviceGuard g(h->device);
+    if (n == 0) return set_int(s, info, 0) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+    const bool unit = upc(diag) == 'U';
+    if (prepare(h, unit ? sizeof(T) * (size_t)n : 0) != hipSuccess) return RFP_ERR_RUNTIME;
+    RfpBlocks b;
+    rfp_blocks(transr, uplo, n, &b);
+    RfpView<T> v = rfp_view(b, arf);
+    Run<T> r = make_run<T>(h, s, info);
+    r.setinfo(info);
+    T* dbuf = (T*)h->inv;
+    if (unit) r.chk(unit_diag<T>(s, v, dbuf, false));
+    r.trtri_rec(b.m1, v.t1, 0);
+    r.trmm_rl(b.m2, b.m1, v.s, v.t1, T(-1));
+    r.trtri_rec(b.m2, v.t2, b.m1);
+    r.trmm_ll(b.m2, b.m1, v.t2, v.s);
+    if (unit) r.chk(unit_diag<T>(s, v, dbuf, true));
+    return r.err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+// TFSM (triangular solve with a triangular matrix in RFP).  Every case is a
+// solve from the right with the lower view L = [L11 0; L21 L22] (T1, S, T2)
+// on a strided view Bv of the right-hand sides:
+//   op(A) = L (UPLO='L', TRANS='N' or UPLO='U', TRANS='T') or L^T;
+//   SIDE='L': X = op(A)^{-1} B, i.e. Bv = B^T and Bv <- Bv op(A)^{-T};
+//   SIDE='R': X = B op(A)^{-1}, Bv = B and Bv <- Bv op(A)^{-1}.
+// Bv L^{-T}: X1 = B1 L11^{-T}, X2 = (B2 - X1 L21^T) L22^{-T};
+// Bv L^{-1}: X2 = B2 L22^{-1}, X1 = (B1 - X2 L21) L11^{-1};
+// each triangle's solve is the 2 x 2 partition down to 64-row leaves, whose
+// inverses (unit-diagonal ones for DIAG='U') turn the leaf solves into
+// products.  alpha scales B first (alpha = 0: B = 0, A not read).
+template <typename T>
+static int tfsm_impl(rfp_context* h, char transr, char side, char uplo, char trans, char diag, int64_t m, int64_t n,
+                     T alpha, const T* arf, T* bp, int64_t ldb, hipStream_t s)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (bad_tr(transr)) return -1;
+    if (upc(side) != 'L' && upc(side) != 'R') return -2;
+    if (bad_ul(uplo)) return -3;
+    if (bad_tr(trans)) return -4;
+    if (upc(diag) != 'N' && upc(diag) != 'U') return -5;
+    if (m < 0) return -6;
+    if (n < 0) return -7;
+    const bool left = upc(side) == 'L';
+    const int64_t k = left ? m : n;
+    if (k > 0 && alpha != T(0) && !arf) return -9;
+    if (m > 0 && n > 0 && !bp) return -10;
+    if (ldb < std::max<int64_t>(1, m)) return -11;
+    if (m == 0 || n == 0) return 0;
+    DeviceGuard g(h->device);
+    Mat<T> B{bp, 1, ldb};
+    if (alpha == T(0)) return scale2d<T>(s, B, m, n, T(0), false) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+    RfpBlocks b;
+    rfp_blocks(transr, uplo, k, &b);
+    const int64_t l1 = nleaves(b.m1, NB), l2 = nleaves(b.m2, NB);
+    if (prepare(h, size_t(l1 + l2) * NB * NB * sizeof(T)) != hipSuccess) return RFP_ERR_RUNTIME;
+    Run<T> r = make_run<T>(h, s, nullptr);
+    r.nb = NB;
+    RfpView<const T> v = rfp_view(b, arf);
+    T* w1 = (T*)h->inv;
+    T* w2 = w1 + l1 * NB * NB;
+    const bool unit = upc(diag) == 'U';
+    if (alpha != T(1)) r.chk(scale2d<T>(s, B, m, n, alpha, false));
+    r.chk(trtri_leaves<T>(r.ex, v.t1, b.m1, w1, unit));
+    r.chk(trtri_leaves<T>(r.ex, v.t2, b.m2, w2, unit));
+    const bool op_lower = (upc(uplo) == 'L') == (upc(trans) == 'N');
+    // right-solve with L^{-T} when (left and op(A) = L) or (right and op(A) = L^T)
+    const bool with_lt = left == op_lower;
+    Mat<T> Bv = left ? B.tr() : B;  // nsys x k
+    const int64_t ns = left ? n : m;
+    Mat<T> B1 = Bv, B2 = Bv.sub(0, b.m1);
+    const Mat<const T> T1 = v.t1, S = v.s, T2 = v.t2;
+    if (with_lt) {
+        r.trsm_rlt(ns, b.m1, B1, T1, w1);
+        r.mm(ns, b.m2, b.m1, T(-1), B1, TRI_NONE, S, TRI_NONE, T(1), B2);
+        r.trsm_rlt(ns, b.m2, B2, T2, w2);
+    } else {
+        r.trsm_rln(ns, b.m2, B2, T2, w2);
+        r.mm(ns, b.m1, b.m2, T(-1), B2, TRI_NONE, S.tr(), TRI_NONE, T(1), B1);
+        r.trsm_rln(ns, b.m1, B1, T1, w1);
+    }
+    return r.err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+// SFRK (symmetric rank-k update in RFP): C = alpha op(A) op(A)^T + beta C on
+// the three blocks of the lower view, op(A) split into rows [0, m1) and
+// [m1, n): T1 <- alpha A1 A1^T + beta T1 and T2 <- alpha A2 A2^T + beta T2
+// (lower triangles only), S <- alpha A2 A1^T + beta S.  alpha = 0 or k = 0
+// only scales C (A not read); beta = 0 does not read C.
+template <typename T>
+static int sfrk_impl(rfp_context* h, char transr, char uplo, char trans, int64_t n, int64_t k, T alpha, const T* a,
+                     int64_t lda, T beta, T* c, hipStream_t s)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (bad_tr(transr)) return -1;
+    if (bad_ul(uplo)) return -2;
+    if (bad_tr(trans)) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    const bool notr = upc(trans) == 'N';
+    if (n > 0 && k > 0 && alpha != T(0) && !a) return -7;
+    if (lda < std::max<int64_t>(1, notr ? n : k)) return -8;
+    if (n > 0 && !c) return -10;
+    if (n == 0) return 0;
+    DeviceGuard g(h->device);
+    RfpBlocks b;
+    rfp_blocks(transr, uplo, n, &b);
+    RfpView<T> v = rfp_view(b, c);
+    if (k == 0 || alpha == T(0)) {
+        if (beta == T(1)) return 0;
+        hipError_t e = scale2d<T>(s, v.t1, b.m1, b.m1, beta, true);
+        if (e == hipSuccess) e = scale2d<T>(s, v.s, b.m2, b.m1, beta, false);
+        if (e == hipSuccess) e = scale2d<T>(s, v.t2, b.m2, b.m2, beta, true);
+        return e == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+    }
+    if (prepare(h, 0) != hipSuccess) return RFP_ERR_RUNTIME;
+    Run<T> r = make_run<T>(h, s, nullptr);
+    Mat<const T> A = notr ? Mat<const T>{a, 1, lda} : Mat<const T>{a, lda, 1};  // op(A), n x k
+    Mat<const T> A1 = A, A2 = A.sub(b.m1, 0);
+    r.mm(b.m1, b.m1, k, alpha, A1, TRI_NONE, A1, TRI_NONE, beta, v.t1, true);
+    r.mm(b.m2, b.m1, k, alpha, A2, TRI_NONE, A1, TRI_NONE, beta, v.s);
+    r.mm(b.m2, b.m2, k, alpha, A2, TRI_NONE, A2, TRI_NONE, beta, v.t2, true);
+    return r.err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+// TPTTF / TFTTP (packed <-> RFP).
+template <typename T>
+static int tpttf_impl(rfp_context* h, char transr, char uplo, int64_t n, const T* ap, T* arf, hipStream_t s,
+                      bool to_rfp)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (bad_tr(transr)) return -1;
+    if (bad_ul(uplo)) return -2;
+    if (n < 0) return -3;
+    if (n > 0 && !(to_rfp ? (const void*)ap : (const void*)arf)) return -4;
+    if (n > 0 && !(to_rfp ? (const void*)arf : (const void*)ap)) return -5;
+    if (n == 0) return 0;
+    DeviceGuard g(h->device);
+    RfpBlocks b;
+    rfp_blocks(transr, uplo, n, &b);
+    return packed_copy<T>(s, rfp_view(b, arf), (T*)ap, upc(uplo) == 'U', to_rfp) == hipSuccess ? 0
+                                                                                              : RFP_ERR_RUNTIME;
+}
 
 // ------------------------------------------------------------- autotuner
 // Candidate configurations of one GEMM shape class are timed on scratch
@@ -1206,6 +1423,7 @@ int rfp_create(rfp_handle_t* h, int device)
     if (!c) return RFP_ERR_RUNTIME;
     c->device = device;
     c->sched = default_schedule();
+    c->spin_limit = DEFAULT_SPIN_LIMIT;
     if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->cus <= 0)
         c->cus = 256;
     *h = c;
@@ -1222,6 +1440,7 @@ int rfp_destroy(rfp_handle_t h)
         if (h->splitk2) (void)hipFree(h->splitk2);
         if (h->inv) (void)hipFree(h->inv);
         if (h->flags) (void)hipFree(h->flags);
+        if (h->ctl) (void)hipFree(h->ctl);
         if (h->ir) (void)hipFree(h->ir);
         if (h->bat) (void)hipFree(h->bat);
         delete h->tune;
@@ -1239,7 +1458,10 @@ int rfp_profile_enable(rfp_handle_t h, int on)
 {
     if (!h) return RFP_ERR_HANDLE;
     DeviceGuard g(h->device);
-    if (on && !h->prof) h->prof = new Profiler();
+    if (on && !h->prof) {
+        h->prof = new Profiler();
+        if (h->prof->reserve() != hipSuccess) return RFP_ERR_RUNTIME;
+    }
     if (!on && h->prof) {
         (void)hipDeviceSynchronize();
         delete h->prof;
@@ -1305,6 +1527,34 @@ int rfp_dpftrs(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, 
 int rfp_dpftri(rfp_handle_t h, char transr, char uplo, int64_t n, double* arf, int* info, hipStream_t stream)
 {
     return pftri_impl<double>(h, transr, uplo, n, arf, info, stream);
+}
+
+int rfp_dtftri(rfp_handle_t h, char transr, char uplo, char diag, int64_t n, double* arf, int* info,
+               hipStream_t stream)
+{
+    return tftri_impl<double>(h, transr, uplo, diag, n, arf, info, stream);
+}
+
+int rfp_dtfsm(rfp_handle_t h, char transr, char side, char uplo, char trans, char diag, int64_t m, int64_t n,
+              double alpha, const double* arf, double* b, int64_t ldb, hipStream_t stream)
+{
+    return tfsm_impl<double>(h, transr, side, uplo, trans, diag, m, n, alpha, arf, b, ldb, stream);
+}
+
+int rfp_dsfrk(rfp_handle_t h, char transr, char uplo, char trans, int64_t n, int64_t k, double alpha,
+              const double* a, int64_t lda, double beta, double* c, hipStream_t stream)
+{
+    return sfrk_impl<double>(h, transr, uplo, trans, n, k, alpha, a, lda, beta, c, stream);
+}
+
+int rfp_dtpttf(rfp_handle_t h, char transr, char uplo, int64_t n, const double* ap, double* arf, hipStream_t stream)
+{
+    return tpttf_impl<double>(h, transr, uplo, n, ap, arf, stream, true);
+}
+
+int rfp_dtfttp(rfp_handle_t h, char transr, char uplo, int64_t n, const double* arf, double* ap, hipStream_t stream)
+{
+    return tpttf_impl<double>(h, transr, uplo, n, ap, (double*)arf, stream, false);
 }
 
 int rfp_strttf(rfp_handle_t h, char transr, char uplo, int64_t n, const float* a, int64_t lda, float* arf,
@@ -1475,6 +1725,31 @@ int rfp_get_schedule(rfp_handle_t h, rfp_schedule_t* sched)
     if (!h) return RFP_ERR_HANDLE;
     if (!sched) return -2;
     *sched = h->sched;
+    return 0;
+}
+
+__global__ void take_status_kernel(int* word, int* out)
+{
+    if (threadIdx.x == 0) {
+        *out = *word;
+        *word = 0;
+    }
+}
+
+int rfp_solve_status(rfp_handle_t h, int* status, hipStream_t stream)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (!status) return -2;
+    DeviceGuard g(h->device);
+    if (!h->ctl && prepare_flags(h, 1) != hipSuccess) return RFP_ERR_RUNTIME;
+    hipLaunchKernelGGL(take_status_kernel, dim3(1), dim3(64), 0, stream, h->ctl + 1, status);
+    return hipGetLastError() == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+int rfp_set_solve_wait_limit(rfp_handle_t h, int64_t polls)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    h->spin_limit = polls < 0 ? DEFAULT_SPIN_LIMIT : (int)std::min<int64_t>(polls, INT32_MAX);
     return 0;
 }
 

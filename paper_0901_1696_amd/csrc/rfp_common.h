@@ -182,6 +182,8 @@ struct Exec {
     int prio = 0;  // 1: the kernels' waves take the highest issue priority (the critical path, which
                    // shares compute units with bulk work on the other streams)
     int leaf_pad = (int)DEFAULT_LEAF_LDS_PAD;  // LDS bytes the FP64 128-row leaf reserves beyond its own
+    const int* gate = nullptr;  // device, or null: the solve-side kernels (fused solve, leaf inverses,
+                                // thin symmetric multiply) do nothing while *gate != 0
 };
 
 // Brackets one kernel launch with HIP events on the launch stream when
@@ -219,9 +221,10 @@ hipError_t potrf_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info_ba
 template <typename T>
 hipError_t trtri_leaf(const Exec& ex, Mat<T> A, int nb, int64_t info_base);
 // Batched out-of-place inverses of every NB-leaf of a lower-triangular matrix
-// of order n: winv[b] = (diagonal block b)^{-1}.
+// of order n: winv[b] = (diagonal block b)^{-1} (unit: with a unit diagonal,
+// which is then not read).
 template <typename T>
-hipError_t trtri_leaves(const Exec& ex, Mat<const T> A, int64_t n, T* winv);
+hipError_t trtri_leaves(const Exec& ex, Mat<const T> A, int64_t n, T* winv, bool unit = false);
 // lauum: lower triangle of W^T W, in place.
 template <typename T>
 hipError_t lauum_leaf(const Exec& ex, Mat<T> A, int nb);
@@ -239,17 +242,23 @@ hipError_t potrf128_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info
 // column-major, leading dimension ldb) is overwritten by the solution.  flags
 // (block_solve_flags ints) are ready flags compared with epoch: every launch
 // on the same flags needs an epoch none of them holds.
+// epoch (device) is read at launch; status (device, or null) gets bit 0 when a
+// bounded wait gives up after spin_limit polls (that block of b becomes NaN).
 template <typename T>
 hipError_t block_solve(const Exec& ex, bool forward, Mat<const T> t1, Mat<const T> s, Mat<const T> t2, int64_t m1,
-                       int64_t m2, const T* winv, T* b, int64_t ldb, int64_t nrhs, int* flags, int epoch);
+                       int64_t m2, const T* winv, T* b, int64_t ldb, int64_t nrhs, int* flags, const int* epoch,
+                       int* status, int spin_limit);
 int64_t block_solve_flags(int64_t m1, int64_t m2, int64_t nrhs);
+// Advance the device epoch of a flag array (clearing the flags when it wraps).
+hipError_t epoch_bump(hipStream_t s, int* flags, int64_t nflags, int* epoch);
+constexpr int DEFAULT_SPIN_LIMIT = 1 << 24;
 hipError_t fill_int(hipStream_t s, int* p, int64_t n, int v);
 
 // Mixed-precision building blocks.
 // s[i] = 1/sqrt(a_ii) (scale) or 1, then o = (float)(((a_ij s_i) s_j) mu) on
 // every stored entry, o in the same RFP layout as a.
 hipError_t pf_cast_scale(hipStream_t st, const RfpView<const double>& a, const RfpView<float>& o, int scale, double mu,
-                         double* s);
+                         double* s, int* nonfinite = nullptr);
 // Norm of the symmetric matrix held in a: which = 0 max |a_ij|, 1 one- (=
 // infinity-) norm, 2 Frobenius; work holds n + 3 doubles; *out on the device.
 hipError_t pf_norm(hipStream_t st, const RfpView<const double>& a, int which, double* work, double* out);
@@ -260,17 +269,43 @@ size_t symm_thin_workspace(int64_t m1, int64_t m2);
 hipError_t symm_thin(const Exec& ex, const RfpView<const double>& v, const double* x, int64_t ldx, double alpha,
                      double beta, double* y, int64_t ldy, int64_t nrhs, double* ws);
 hipError_t ir_scale_cast(hipStream_t st, const double* r, int64_t ldr, const double* s, float* out, int64_t ldo,
-                         int64_t n, int64_t nrhs);
+                         int64_t n, int64_t nrhs, const int* gate = nullptr);
 hipError_t ir_update(hipStream_t st, double* x, int64_t ldx, const double* s, double mu, const float* d, int64_t ldd,
-                     int64_t n, int64_t nrhs, bool accumulate);
-hipError_t col_dot(hipStream_t st, const double* u, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out);
+                     int64_t n, int64_t nrhs, bool accumulate, const int* gate = nullptr);
+hipError_t col_dot(hipStream_t st, const double* u, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out,
+                   const int* gate = nullptr);
 hipError_t pcg_step(hipStream_t st, double* d, int64_t ldd, double* r, const double* p, const double* q,
-                    const double* rz, const double* pq, int64_t ld, int64_t n, int64_t nrhs);
+                    const double* rz, const double* pq, int64_t ld, int64_t n, int64_t nrhs, const int* gate = nullptr);
 hipError_t pcg_dir(hipStream_t st, double* p, const double* z, const double* rz_new, const double* rz_old, int64_t ld,
-                   int64_t n, int64_t nrhs);
-hipError_t col_max(hipStream_t st, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out);
+                   int64_t n, int64_t nrhs, const int* gate = nullptr);
+hipError_t col_max(hipStream_t st, const double* v, int64_t ld, int64_t n, int64_t nrhs, double* out,
+                   const int* gate = nullptr);
 hipError_t backward_error(hipStream_t st, const double* rmax, const double* xmax, const double* bmax,
-                          const double* anorm, int64_t nrhs, double* eta);
+                          const double* anorm, int64_t nrhs, double* eta, const int* gate = nullptr);
+// Device-side control of the refinement (no host synchronisation): see
+// pfsv_ir_impl.  IrCtl lives in device memory.
+struct IrCtl {
+    int phase;      // IR_CLASSIC, IR_PCG, IR_DONE, IR_FALLBACK
+    int code;       // sweeps on convergence, else the fall-back reason (< 0)
+    int g_ir, g_pcg, g_run;  // gates (0 = run) of classical sweeps, conjugate-gradient sweeps, any sweep
+    int g_fb;       // 0 = run the FP64 fall-back (factor and copy)
+    int g_fbsolve;  // 0 = run the fall-back solve (its factor succeeded)
+    int lp_info;    // INFO of the low-precision factor
+    int nonfinite;  // the scaled low-precision copy holds a non-finite entry
+    int fb_info;    // INFO of the fall-back factor (gated as the factor's info word)
+    int pad[6];
+    double eta, prev;
+};
+enum { IR_CLASSIC = 0, IR_PCG = 1, IR_DONE = 2, IR_FALLBACK = 3 };
+hipError_t ir_start(hipStream_t st, IrCtl* c);
+hipError_t ir_setup_decide(hipStream_t st, IrCtl* c);
+hipError_t ir_decide(hipStream_t st, IrCtl* c, int it, int max_iter, double tol);
+hipError_t ir_finish(hipStream_t st, IrCtl* c, int* iter, int* info);
+// y(i, c) = x(i, c) (n x nrhs), or 0 when x is null; nothing while *gate != 0
+hipError_t ir_copy(hipStream_t st, double* y, int64_t ldy, const double* x, int64_t ldx, int64_t n, int64_t nrhs,
+                   const int* gate);
+// 1-D copy of count doubles, nothing while *gate != 0
+hipError_t gated_copy(hipStream_t st, double* dst, const double* src, int64_t count, const int* gate);
 
 // Batched small systems (n <= 256): one persistent launch; scratch holds
 // batched_scratch_bytes(wgs) bytes, counter one int.
@@ -282,6 +317,18 @@ hipError_t batched_solve(const Exec& ex, const rfp_sys_t* sys, int64_t batch, do
 // 2-D strided copy dst = src (m x n), optionally only the lower triangle.
 template <typename Td, typename Ts>
 hipError_t copy2d(hipStream_t s, Mat<Td> dst, Mat<const Ts> src, int64_t m, int64_t n, bool lower);
+
+// Packed <-> RFP copy of every stored entry (to_rfp: packed -> RFP).
+template <typename T>
+hipError_t packed_copy(hipStream_t s, const RfpView<T>& v, T* ap, bool upper_packed, bool to_rfp);
+// X = alpha X on an m x n view (lower triangle only if lower); alpha = 0
+// writes zeros without reading X.
+template <typename T>
+hipError_t scale2d(hipStream_t s, Mat<T> x, int64_t m, int64_t n, T alpha, bool lower);
+// Save the diagonal of T1 and T2 into buf (n entries) and set it to one, or
+// (restore) write buf back.
+template <typename T>
+hipError_t unit_diag(hipStream_t s, const RfpView<T>& v, T* buf, bool restore);
 
 // Small utility kernels.
 hipError_t set_int(hipStream_t s, int* p, int v);

@@ -39,6 +39,7 @@ struct SkinnyArgs {
     int64_t wslice;       // doubles per slice
     int64_t wld;          // leading dimension of a slice (rows of the output half)
     int64_t row0;         // first output row of this product inside the slice
+    const int* gate;      // device, or null: nothing is done while *gate != 0
 };
 
 }  // namespace
@@ -48,6 +49,7 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyArgs p)
 {
     __shared__ __attribute__((aligned(16))) double As[TM][SP];
     __shared__ __attribute__((aligned(16))) double Xs[16 * NCB][SP];
+    if (p.gate && *p.gate) return;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int64_t i0 = (int64_t)blockIdx.x * TM;
@@ -125,8 +127,9 @@ __global__ __launch_bounds__(256) void skinny_kernel(SkinnyArgs p)
 
 // y(i, c) = beta y(i, c) + alpha sum_q w[q](i, c), q in slice order
 __global__ void skinny_reduce_kernel(const double* w, int nslices, int64_t wslice, int64_t wld, int64_t m, int r,
-                                     double alpha, double beta, double* y, int64_t ldy)
+                                     double alpha, double beta, double* y, int64_t ldy, const int* gate)
 {
+    if (gate && *gate) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (i >= m || c >= r) return;
@@ -203,6 +206,7 @@ hipError_t symm_thin(const Exec& ex, const RfpView<const double>& v, const doubl
             a.wslice = wslice;
             a.wld = half_rows[h];
             a.row0 = 0;
+            a.gate = ex.gate;
             nsl[h] += nch;
             const dim3 grid((unsigned)((pr.m + TM - 1) / TM), (unsigned)nch);
             ProfScope ps(ex, r > 16 ? "rfp::skinny_kernel<2>(rfp::(anonymous namespace)::SkinnyArgs)"
@@ -216,7 +220,7 @@ hipError_t symm_thin(const Exec& ex, const RfpView<const double>& v, const doubl
             double* yh = y + (h ? m1 : 0) + c0 * ldy;
             const dim3 grid((unsigned)((half_rows[h] + 255) / 256), (unsigned)r);
             hipLaunchKernelGGL(skinny_reduce_kernel, grid, dim3(256), 0, ex.stream, half_ws[h], nsl[h],
-                               half_rows[h] * RMAX, half_rows[h], half_rows[h], r, alpha, beta, yh, ldy);
+                               half_rows[h] * RMAX, half_rows[h], half_rows[h], r, alpha, beta, yh, ldy, ex.gate);
         }
     }
     return hipGetLastError();

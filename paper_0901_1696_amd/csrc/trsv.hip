@@ -15,13 +15,17 @@
 // numbers.  Dispatch is in order on every XCD, so the lowest unfinished
 // workgroup is always resident with all its inputs published: every wait
 // ends.  The waits are bounded spins all the same; a workgroup whose wait
-// runs out writes NaN into its block of the solution (and still raises its
-// flag, so that no other workgroup is held).
+// runs out writes NaN into its block of the solution, sets bit 0 of the
+// handle's device status word (the caller reads it with rfp_solve_status),
+// and still raises its flag, so that no other workgroup is held.
 //
-// Flags hold an epoch number that the host advances on every launch, so the
-// flag array is never cleared between calls.  Solved rows travel between
+// Flags hold an epoch number, so the flag array is never cleared between
+// calls.  The epoch lives in device memory: a one-thread kernel advances it
+// before every launch and the launch reads it, so a solve captured in a HIP
+// graph takes a fresh epoch on every replay.  Solved rows travel between
 // workgroups (and XCDs) through device-scope atomic stores and loads ordered
 // by the flags' release / acquire, never through plain cached accesses.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 
@@ -70,8 +74,10 @@ struct SolveArgs {
     int64_t ldb, nrhs;
     int nslices;             // slices of 16 * NCB columns
     int* flags;              // [block row][slice]
-    int epoch;
-    int spin_limit;
+    const int* epoch;        // device: this launch's epoch
+    const int* gate;         // device, or null: the launch does nothing while *gate != 0
+    int* status;             // device, or null: bit 0 set when a wait gives up
+    int spin_limit;          // polls of an unpublished dependency before giving up
 };
 
 namespace {
@@ -126,6 +132,8 @@ __global__ __launch_bounds__(256) void block_solve_kernel(SolveArgs<T> a)
     __shared__ __attribute__((aligned(16))) T Ls[BS][P];  // L block or W, Ls[i][kk]
     __shared__ __attribute__((aligned(16))) T Ys[CS][P];  // solved rows, Ys[column][row]
 
+    if (a.gate && *a.gate) return;
+    const int epoch = *a.epoch;
     const int nblk = a.nb1 + a.nb2;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int r = lane & 15, g = lane >> 4;
@@ -207,10 +215,10 @@ __global__ __launch_bounds__(256) void block_solve_kernel(SolveArgs<T> a)
                 int spins = 0, avail = 0;
                 for (;;) {
                     const bool rdy =
-                        dd < q && __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == a.epoch;
+                        dd < q && __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
                     const uint64_t m = __ballot(rdy);
                     avail = ~m ? __builtin_ctzll(~m) : 64;  // published run starting at d
-                    if (avail > 0 || spins > a.spin_limit) break;
+                    if (avail > 0 || spins >= a.spin_limit) break;
                     spins++;
                     __builtin_amdgcn_s_sleep(1);
                 }
@@ -284,13 +292,38 @@ __global__ __launch_bounds__(256) void block_solve_kernel(SolveArgs<T> a)
                 __hip_atomic_store(&a.b[(r0 + i) + c * a.ldb], ok ? out[cb][e] : nan, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         }
+    if (!ok && t == 0 && a.status) atomicOr(a.status, 1);
     // publish: every wavefront waits for its device-scope stores to complete,
     // then one thread raises the flag with a release store
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (t == 0)
-        __hip_atomic_store(a.flags + (int64_t)k * a.nslices + slice, a.epoch, __ATOMIC_RELEASE,
+        __hip_atomic_store(a.flags + (int64_t)k * a.nslices + slice, epoch, __ATOMIC_RELEASE,
                            __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Epoch of the next fused solve on a flag array: epoch + 1, wrapping to 1
+// once it reaches EPOCH_WRAP (the flags are then cleared first, by the grid
+// of the clear kernel, which reads the epoch but does not write it).
+constexpr int EPOCH_WRAP = 1 << 30;
+__global__ void epoch_clear_kernel(int* flags, int64_t n, const int* epoch)
+{
+    if (*epoch + 1 < EPOCH_WRAP) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) flags[i] = 0;
+}
+__global__ void epoch_bump_kernel(int* epoch)
+{
+    if (threadIdx.x == 0) *epoch = *epoch + 1 < EPOCH_WRAP ? *epoch + 1 : 1;
+}
+
+hipError_t epoch_bump(hipStream_t s, int* flags, int64_t nflags, int* epoch)
+{
+    if (nflags > 0)
+        hipLaunchKernelGGL(epoch_clear_kernel, dim3((unsigned)std::min<int64_t>((nflags + 255) / 256, 64)), dim3(256),
+                           0, s, flags, nflags, (const int*)epoch);
+    hipLaunchKernelGGL(epoch_bump_kernel, dim3(1), dim3(64), 0, s, epoch);
+    return hipGetLastError();
 }
 
 __global__ void fill_int_kernel(int* p, int64_t n, int v)
@@ -352,7 +385,8 @@ int block_solve_width(int64_t nrhs)
 
 template <typename T>
 hipError_t block_solve(const Exec& ex, bool forward, Mat<const T> t1, Mat<const T> s, Mat<const T> t2, int64_t m1,
-                       int64_t m2, const T* winv, T* b, int64_t ldb, int64_t nrhs, int* flags, int epoch)
+                       int64_t m2, const T* winv, T* b, int64_t ldb, int64_t nrhs, int* flags, const int* epoch,
+                       int* status, int spin_limit)
 {
     SolveArgs<T> a;
     a.t1 = t1;
@@ -368,7 +402,9 @@ hipError_t block_solve(const Exec& ex, bool forward, Mat<const T> t1, Mat<const 
     a.nrhs = nrhs;
     a.flags = flags;
     a.epoch = epoch;
-    a.spin_limit = 1 << 24;
+    a.gate = ex.gate;
+    a.status = status;
+    a.spin_limit = spin_limit;
     const int nblk = a.nb1 + a.nb2;
     if (nblk == 0 || nrhs <= 0) return hipSuccess;
     int ncb = block_solve_width(nrhs);
@@ -387,8 +423,10 @@ hipError_t block_solve(const Exec& ex, bool forward, Mat<const T> t1, Mat<const 
 }
 
 template hipError_t block_solve<double>(const Exec&, bool, Mat<const double>, Mat<const double>, Mat<const double>,
-                                        int64_t, int64_t, const double*, double*, int64_t, int64_t, int*, int);
+                                        int64_t, int64_t, const double*, double*, int64_t, int64_t, int*,
+                                        const int*, int*, int);
 template hipError_t block_solve<float>(const Exec&, bool, Mat<const float>, Mat<const float>, Mat<const float>,
-                                       int64_t, int64_t, const float*, float*, int64_t, int64_t, int*, int);
+                                       int64_t, int64_t, const float*, float*, int64_t, int64_t, int*, const int*,
+                                       int*, int);
 
 }  // namespace rfp

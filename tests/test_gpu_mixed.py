@@ -51,6 +51,14 @@ def test_lansf(h, transr, uplo, n):
     assert abs(got[2] - oracle.norm_fro(transr, uplo, n, arf)) <= 1e-13 * got[2]
 
 
+def _ir(h, fprec, transr, uplo, n, arf, b, x, **kw):
+    """rfp_dpfsv_ir with device outputs; returns them as host ints."""
+    out = torch.full((2,), -77, dtype=torch.int32, device="cuda")
+    rfp.rfp_dpfsv_ir(h, fprec, transr, uplo, n, arf, b, x, out[0:1], out[1:2], **kw)
+    it, info = (int(v) for v in host(out))
+    return it, info
+
+
 def _ir_case(n, kappa, nrhs, seed, transr="N", uplo="L"):
     k = max(1, n // 2)
     A, B = synth.spd(n, k=k, alpha=synth.cond_alpha(n, k, kappa), nrhs=nrhs, seed=seed)
@@ -64,7 +72,7 @@ def test_ir_fp32_converges_to_fp64_accuracy(h, transr, uplo, n, kappa):
     nrhs = 3
     A, B, arf = _ir_case(n, kappa, nrhs, seed=n + int(np.log10(kappa)), transr=transr, uplo=uplo)
     x = dev_colmajor(np.zeros((n, nrhs)))
-    it, info = rfp.rfp_dpfsv_ir(h, rfp.PREC_FP32, transr, uplo, n, dev(arf), dev_colmajor(B), x, tol=1e-14)
+    it, info = _ir(h, rfp.PREC_FP32, transr, uplo, n, dev(arf), dev_colmajor(B), x, tol=1e-14)
     X = host_colmajor(x)
     assert info == 0
     assert it > 0, f"refinement did not converge (code {it})"
@@ -80,12 +88,12 @@ def test_ir_fallbacks(h):
     d, bd = dev(arf), dev_colmajor(B)
     # one sweep allowed, unreachable tolerance: max_iter fall-back, FP64 answer
     x = dev_colmajor(np.zeros((n, nrhs)))
-    it, info = rfp.rfp_dpfsv_ir(h, rfp.PREC_FP32, "N", "L", n, d, bd, x, tol=1e-300, max_iter=1)
+    it, info = _ir(h, rfp.PREC_FP32, "N", "L", n, d, bd, x, tol=1e-300, max_iter=1)
     assert (it, info) == (-1, 0)
     assert oracle.backward_error("N", "L", n, arf, B, host_colmajor(x)) <= 1e-15
     # unreachable tolerance with room to iterate: the backward error stalls
     x = dev_colmajor(np.zeros((n, nrhs)))
-    it, info = rfp.rfp_dpfsv_ir(h, rfp.PREC_FP32, "N", "L", n, d, bd, x, tol=1e-300, max_iter=60)
+    it, info = _ir(h, rfp.PREC_FP32, "N", "L", n, d, bd, x, tol=1e-300, max_iter=60)
     assert (it, info) == (-2, 0)
     assert oracle.backward_error("N", "L", n, arf, B, host_colmajor(x)) <= 1e-15
     # b is only read, arf untouched
@@ -94,14 +102,24 @@ def test_ir_fallbacks(h):
 
 
 def test_ir_not_positive_definite(h):
+    """Leading minor 100 negative with a positive diagonal: the FP32 factor
+    fails (-3) and so does the FP64 fall-back (INFO = 100).  A negative
+    diagonal entry makes the scaled copy non-finite (-4); the fall-back's INFO
+    names that entry."""
     n = 130
-    A, B, arf = _ir_case(n, 1e2, 1, seed=3)
-    A[100, 100] = -1.0
+    A = synth.min_matrix(n)
+    A[99, 99] -= 2.0
+    B = synth.rhs(n, 1, seed=3)
     arf = oracle.trttf("T", "U", A)
+    assert oracle.pftrf("T", "U", n, arf)[1] == 100
     x = dev_colmajor(np.zeros((n, 1)))
-    it, info = rfp.rfp_dpfsv_ir(h, rfp.PREC_FP32, "T", "U", n, dev(arf), dev_colmajor(B), x)
-    assert it == -3
-    assert info == 101
+    assert _ir(h, rfp.PREC_FP32, "T", "U", n, dev(arf), dev_colmajor(B), x) == (-3, 100)
+    A2, B2, _ = _ir_case(n, 1e2, 1, seed=3)
+    A2[100, 100] = -1.0
+    arf2 = oracle.trttf("N", "U", A2)
+    x = dev_colmajor(np.zeros((n, 1)))
+    for fprec in (rfp.PREC_FP32, rfp.PREC_FP16):
+        assert _ir(h, fprec, "N", "U", n, dev(arf2), dev_colmajor(B2), x) == (-4, 101)
 
 
 def test_ir_argument_errors(h):
@@ -109,15 +127,16 @@ def test_ir_argument_errors(h):
     d = torch.zeros(rfp.nt(n), dtype=torch.float64, device="cuda")
     b = torch.zeros((n, 1), dtype=torch.float64, device="cuda")
     x = torch.zeros((n, 1), dtype=torch.float64, device="cuda")
+    out = torch.zeros(2, dtype=torch.int32, device="cuda")
     for kw, code in [(dict(fprec=9), -1), (dict(transr="X"), -2), (dict(tol=0.0), -11), (dict(max_iter=0), -12)]:
         args = dict(fprec=rfp.PREC_FP32, transr="N", tol=1e-14, max_iter=5)
         args.update(kw)
         with pytest.raises(rfp.RfpError) as e:
-            rfp.rfp_dpfsv_ir(h, args["fprec"], args["transr"], "L", n, d, b, x, tol=args["tol"],
+            rfp.rfp_dpfsv_ir(h, args["fprec"], args["transr"], "L", n, d, b, x, out[0:1], out[1:2], tol=args["tol"],
                              max_iter=args["max_iter"])
         assert e.value.code == code
-    # n = 0 and nrhs = 0 return at once
-    assert rfp.rfp_dpfsv_ir(h, rfp.PREC_FP32, "N", "L", 0, d, b[:0], x[:0]) == (0, 0)
+    # n = 0 and nrhs = 0 return at once, with both outputs 0
+    assert _ir(h, rfp.PREC_FP32, "N", "L", 0, d, b[:0], x[:0]) == (0, 0)
 
 
 @pytest.mark.parametrize("fprec", [rfp.PREC_FP32, rfp.PREC_FP16, rfp.PREC_BF16])
@@ -158,6 +177,89 @@ def test_ir_half_precision_updates(h, fprec, n, kappa):
     nrhs = 2
     A, B, arf = _ir_case(n, kappa, nrhs, seed=n + 17)
     x = dev_colmajor(np.zeros((n, nrhs)))
-    it, info = rfp.rfp_dpfsv_ir(h, fprec, "N", "L", n, dev(arf), dev_colmajor(B), x, tol=1e-14, max_iter=60)
+    it, info = _ir(h, fprec, "N", "L", n, dev(arf), dev_colmajor(B), x, tol=1e-14, max_iter=60)
     assert info == 0 and it > 0, f"code {it}"
     assert oracle.backward_error("N", "L", n, arf, B, host_colmajor(x)) <= 1e-14
+
+
+def test_ir_captured_in_graph_replays_like_eager(h):
+    """The refinement takes every decision on the device: captured once in a
+    HIP graph (after an eager call has sized the workspace), each replay with
+    new right-hand sides gives the eager result bit for bit, with the same
+    sweep count, and so does a replay whose right-hand sides hold a NaN,
+    which makes the refinement stall and take the FP64 fall-back."""
+    n, nrhs = 700, 3
+    A, B0, arf = _ir_case(n, 1e3, nrhs, seed=41)
+    d = dev(arf)
+    b = dev_colmajor(B0)
+    x = dev_colmajor(np.zeros((n, nrhs)))
+    out = torch.zeros(2, dtype=torch.int32, device="cuda")
+    kw = dict(tol=1e-14, max_iter=12)
+
+    def eager(Bv):
+        bb, xx = dev_colmajor(Bv), dev_colmajor(np.zeros((n, nrhs)))
+        oo = torch.zeros(2, dtype=torch.int32, device="cuda")
+        rfp.rfp_dpfsv_ir(h, rfp.PREC_FP16, "N", "L", n, d, bb, xx, oo[0:1], oo[1:2], **kw)
+        return host_colmajor(xx), tuple(int(v) for v in host(oo))
+
+    eager(B0)  # sizes every workspace
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rfp.rfp_dpfsv_ir(h, rfp.PREC_FP16, "N", "L", n, d, b, x, out[0:1], out[1:2], **kw)
+    torch.cuda.synchronize()
+    cases = [B0, synth.rhs(n, nrhs, seed=5), 1e-3 * synth.rhs(n, nrhs, seed=6), B0]
+    for Bv in cases:
+        want_x, want_code = eager(Bv)
+        b.copy_(dev_colmajor(Bv))
+        x.fill_(123.0)
+        out.fill_(-55)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = tuple(int(v) for v in host(out))
+        assert got == want_code and got[0] > 0
+        assert np.array_equal(host_colmajor(x), want_x)
+        assert oracle.backward_error("N", "L", n, arf, Bv, want_x) <= 1e-14
+        _ = torch.randn(1000, device="cuda").sum()  # other work between replays
+    # a replay that falls back: NaN in the right-hand sides stalls the refinement
+    Bn = B0.copy()
+    Bn[3, 1] = np.nan
+    want_x, want_code = eager(Bn)
+    assert want_code[0] < 0
+    b.copy_(dev_colmajor(Bn))
+    g.replay()
+    torch.cuda.synchronize()
+    assert tuple(int(v) for v in host(out)) == want_code
+    gx = host_colmajor(x)
+    assert np.array_equal(np.isnan(gx), np.isnan(want_x))
+    assert np.array_equal(gx[~np.isnan(gx)], want_x[~np.isnan(want_x)])
+
+
+def test_solve_wait_give_up_is_reported(h):
+    """With a wait limit of 0 polls, fused-solve workgroups whose dependencies
+    are not yet published give up at once: their blocks of X become NaN, every
+    kernel still ends, and the handle's status word reports it (then clears).
+    With the default limit the same solve is exact and the status stays 0."""
+    n, nrhs = 4000, 16
+    f = oracle.trttf("N", "L", np.tril(np.ones((n, n))))
+    X = synth.rng(1).integers(-3, 4, size=(n, nrhs)).astype(np.float64)
+    B = synth.min_matrix(n) @ X
+    st = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    rfp.rfp_solve_status(h, st)  # clear
+    rfp.rfp_set_solve_wait_limit(h, 0)
+    try:
+        bd = dev_colmajor(B)
+        rfp.rfp_dpftrs(h, "N", "L", n, dev(f), bd)
+        rfp.rfp_solve_status(h, st)
+        assert int(host(st)[0]) == 1
+        assert np.isnan(host_colmajor(bd)).any()
+        rfp.rfp_solve_status(h, st)
+        assert int(host(st)[0]) == 0  # cleared by the previous read
+    finally:
+        rfp.rfp_set_solve_wait_limit(h, -1)
+    bd = dev_colmajor(B)
+    rfp.rfp_dpftrs(h, "N", "L", n, dev(f), bd)
+    rfp.rfp_solve_status(h, st)
+    assert int(host(st)[0]) == 0
+    assert np.array_equal(host_colmajor(bd), X)
