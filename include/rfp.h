@@ -39,6 +39,7 @@ extern "C" {
 
 #define RFP_ERR_HANDLE (-101)
 #define RFP_ERR_RUNTIME (-102)
+#define RFP_ERR_SCRATCH (-103) /* rfp_dpftrs_noalloc: the problem exceeds its fixed scratch */
 
 typedef struct rfp_context* rfp_handle_t;
 
@@ -126,6 +127,24 @@ int rfp_dsfrk(rfp_handle_t h, char transr, char uplo, char trans, int64_t n, int
 int rfp_dtpttf(rfp_handle_t h, char transr, char uplo, int64_t n, const double* ap, double* arf, hipStream_t stream);
 int rfp_dtfttp(rfp_handle_t h, char transr, char uplo, int64_t n, const double* arf, double* ap, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): PFTRS
+ * exactly as rfp_dpftrs (same arguments and argument codes, same kernels,
+ * bit-identical results), without a handle.  Its scratch -- the inverses of
+ * the factor's 64-row diagonal blocks, the fused solves' ready flags and
+ * control words -- lives in a fixed 32 MiB device array of the library, one
+ * copy per GPU held until the process ends; the call allocates and frees
+ * nothing.  Limits: ceil(m1/64) + ceil(m2/64) <= 991 diagonal blocks (n up to
+ * about 63000) and (that count) x ceil(nrhs/16) <= 262144 ready flags;
+ * beyond them it returns RFP_ERR_SCRATCH and enqueues nothing.  Runs on the
+ * current device and `stream`.  All calls on one GPU share its scratch, so
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * and must not be issued; consecutive calls on one stream are safe.  The
+ * scratch keeps the last call's contents; the ready flags are told apart by
+ * an epoch kept in the scratch, so nothing needs clearing between calls.
+ * Argument order: TRANSR=1, UPLO=2, N=3, NR=4, A=5, B=6, LDB=7. */
+int rfp_dpftrs_noalloc(char transr, char uplo, int64_t n, int64_t nrhs, const double* arf, double* b, int64_t ldb,
+                       hipStream_t stream);
 
 /* Single-precision counterparts (SPFTRF / SPFTRS / STRTTF / STFTTR in the
  * paper's routine table); same arguments and semantics with float arrays. */

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librfp.so")
 
 RFP_ERR_HANDLE = -101
 RFP_ERR_RUNTIME = -102
+RFP_ERR_SCRATCH = -103
 LAYOUTS = [(t, u) for t in "NT" for u in "LU"]
 PREC_FP32, PREC_FP16, PREC_BF16, PREC_FP64 = 0, 1, 2, 3
 
@@ -28,7 +29,8 @@ _lib = None
 class RfpError(RuntimeError):
     def __init__(self, routine, code):
         self.code = code
-        what = {RFP_ERR_HANDLE: "bad handle", RFP_ERR_RUNTIME: "HIP runtime error"}.get(
+        what = {RFP_ERR_HANDLE: "bad handle", RFP_ERR_RUNTIME: "HIP runtime error",
+                RFP_ERR_SCRATCH: "problem exceeds the fixed scratch"}.get(
             code, f"illegal argument {-code}" if code < 0 else f"status {code}")
         super().__init__(f"{routine}: {what} (return code {code})")
 
@@ -45,6 +47,7 @@ _SIGS = {
     "rfp_dtfttr": [_vp, _chr, _chr, _i64, _vp, _vp, _i64, _vp],
     "rfp_dpftrf": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_dpftrs": [_vp, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp],
+    "rfp_dpftrs_noalloc": [_chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp],
     "rfp_dtftri": [_vp, _chr, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_dtfsm": [_vp, _chr, _chr, _chr, _chr, _chr, _i64, _i64, ctypes.c_double, _vp, _vp, _i64, _vp],
     "rfp_dsfrk": [_vp, _chr, _chr, _chr, _i64, _i64, ctypes.c_double, _vp, _i64, ctypes.c_double, _vp, _vp],
@@ -267,6 +270,13 @@ def rfp_dpftrs(h, transr, uplo, n, arf, b, stream=None):
     pb, ldb, nrhs = _colmajor(b, "b")
     _check("rfp_dpftrs", lib().rfp_dpftrs(h.value, _c(transr), _c(uplo), n, nrhs, _ptr(arf), pb, ldb,
                                           _stream(stream)))
+
+
+def rfp_dpftrs_noalloc(transr, uplo, n, arf, b, stream=None):
+    """PFTRS with the library's fixed scratch (no handle, no allocation)."""
+    pb, ldb, nrhs = _colmajor(b, "b")
+    _check("rfp_dpftrs_noalloc", lib().rfp_dpftrs_noalloc(_c(transr), _c(uplo), n, nrhs, _ptr(arf), pb, ldb,
+                                                          _stream(stream)))
 
 
 def rfp_dpftri(h, transr, uplo, n, arf, info, stream=None):
