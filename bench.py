@@ -30,6 +30,9 @@ Also reported on the same JSON line:
                 FP64 refinement (FP16, BF16 and FP32 factors tried; the fastest
                 that reaches the FP64 path's backward error bound of 1e-14),
                 each backward error measured with the dense FP64 A;
+  batched_medium 512 systems, n log-uniform in [256, 4096], cond 1e2..1e8,
+                PFTRI on every system, FP64 and FP16/BF16/FP32 factors with
+                FP64 refinement, in one persistent launch each;
   batched       20000 systems, n uniform in [16, 256], random layout, nrhs
                 uniform in [1, 8], A_i = M_i M_i^T / n_i + I: one persistent
                 launch in FP64 and with FP32 factors + FP64 refinement, with
@@ -303,7 +306,8 @@ def bench_batched(h, count=20000, seed=4, one_at_a_time=300, reps=3):
         A.diagonal().add_(1.0)
         rfp.rfp_dtrttf(h, t, u, n, A.t(), arf[a0:a0 + rfp.nt(n)])
         b[b0:b0 + n * nr] = torch.from_numpy(g.standard_normal(n * nr)).to(dev)
-    table = torch.frombuffer(bytearray(rfp.sys_table(systems)), dtype=torch.uint8).to(dev)
+    raw = rfp.sys_table(systems)
+    table = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
     info = torch.zeros(count, dtype=torch.int32, device=dev)
     it = torch.zeros_like(info)
     fl_f = sum(flops_trf(s[0]) for s in systems)
@@ -320,7 +324,7 @@ def bench_batched(h, count=20000, seed=4, one_at_a_time=300, reps=3):
                 b1.copy_(b)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                rfp.rfp_dpfsv_batched(h, mode, count, table, a1, b1, info, it, do_pftri=pftri)
+                rfp.rfp_pfsv_vbatched(h, mode, count, table, a1, b1, info, it, sys_host=raw, do_pftri=pftri)
                 torch.cuda.synchronize()
                 return time.perf_counter() - t0
             run()
@@ -355,6 +359,112 @@ def bench_batched(h, count=20000, seed=4, one_at_a_time=300, reps=3):
     return out
 
 
+def bench_batched_medium(h, count=512, seed=5, reps=2, one_at_a_time=24):
+    """512 systems, n log-uniform in [256, 4096], A_i = M_i M_i^T / k_i +
+    alpha_i I with k_i = ceil(n_i / 2) and alpha_i for cond 10^U(2, 8), random
+    layout, nrhs uniform in [1, 8]; PFTRI on every system; one persistent
+    launch per mode (FP64, and FP16 / BF16 / FP32 factors with FP64
+    refinement and FP64 fall-back), against the single-system routines
+    launched one system at a time (timed on the first systems)."""
+    import math
+    import numpy as np
+    import torch
+    import paper_0901_1696_amd as rfp
+    import synth
+
+    dev = torch.device("cuda:0")
+    ns, lays, nrs = synth.batch_sizes(count, 256, 4096, 1, 8, seed=seed, log_uniform=True)
+    g = synth.rng(seed + 1)
+    kap = 10.0 ** g.uniform(2.0, 8.0, size=count)
+    systems, ao, bo = [], 0, 0
+    for n, li, nr in zip(ns, lays, nrs):
+        n, nr = int(n), int(nr)
+        t, u = rfp.LAYOUTS[int(li)]
+        systems.append((n, ao, bo, n, nr, t, u))
+        ao += rfp.nt(n)
+        bo += n * nr
+    log(f"[bench] batched medium: generating {count} systems ({ao * 8 / 1e9:.2f} GB RFP)")
+    arf = torch.empty(ao, dtype=torch.float64, device=dev)
+    b = torch.empty(bo, dtype=torch.float64, device=dev)
+    for q, (n, a0, b0, ldb, nr, t, u) in enumerate(systems):
+        k = int(math.ceil(n / 2))
+        M = torch.from_numpy(g.standard_normal((n, k))).to(dev)
+        A = (M @ M.t()) / k
+        A.diagonal().add_(synth.cond_alpha(n, k, float(kap[q])))
+        rfp.rfp_dtrttf(h, t, u, n, A.t(), arf[a0:a0 + rfp.nt(n)])
+        b[b0:b0 + n * nr] = torch.from_numpy(g.standard_normal(n * nr)).to(dev)
+        del M, A
+    raw = rfp.sys_table(systems)
+    table = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+    info = torch.zeros(count, dtype=torch.int32, device=dev)
+    it = torch.zeros_like(info)
+    fl_f = sum(flops_trf(s[0]) for s in systems)
+    fl_s = sum(flops_trs(s[0], s[4]) for s in systems)
+    fl_i = sum(flops_tri(s[0]) for s in systems)
+    a1, b1 = arf.clone(), b.clone()
+    out = {"systems": count, "n_range": [256, 4096], "n_max": int(max(ns)), "nrhs_range": [1, 8],
+           "cond_range": [1e2, 1e8], "rfp_gb": round(ao * 8 / 1e9, 3),
+           "nominal_gflop": {"pftrf": round(fl_f / 1e9, 1), "pftrs": round(fl_s / 1e9, 1),
+                             "pftri": round(fl_i / 1e9, 1)}, "runs": []}
+    for mode, name in [(rfp.PREC_FP64, "fp64"), (rfp.PREC_FP16, "fp16_factor+fp64_ir"),
+                       (rfp.PREC_BF16, "bf16_factor+fp64_ir"), (rfp.PREC_FP32, "fp32_factor+fp64_ir")]:
+        def run():
+            a1.copy_(arf)
+            b1.copy_(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rfp.rfp_pfsv_vbatched(h, mode, count, table, a1, b1, info, it, sys_host=raw, do_pftri=True,
+                                  max_iter=30)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+        run()
+        tm = min(run() for _ in range(reps))
+        fl = fl_f + fl_s + fl_i
+        itc = it.cpu().numpy()
+        rec = {"mode": name, "pftri": True, "ms": round(tm * 1e3, 2), "gflops": round(fl / tm / 1e9, 1),
+               "info_nonzero": int((info != 0).sum().item()),
+               "refined": int((itc > 0).sum()), "fallback": {str(c): int((itc == c).sum()) for c in (-1, -2, -3, -4)},
+               "max_sweeps": int(itc.max())}
+        # backward error of the solves of a sample of systems (dense FP64 check)
+        worst = 0.0
+        for (n, a0, b0, ldb, nr, t, u) in systems[:16]:
+            A = torch.zeros((n, n), dtype=torch.float64, device=dev).t()
+            rfp.rfp_dtfttr(h, t, u, n, arf[a0:a0 + rfp.nt(n)], A)
+            A = A if u == "L" else A.t()
+            A = torch.tril(A) + torch.tril(A, -1).t()
+            B0 = b[b0:b0 + n * nr].view(nr, n).t()
+            X = b1[b0:b0 + n * nr].view(nr, n).t()
+            worst = max(worst, backward_error_dense(A, B0, X))
+            del A
+        rec["max_backward_error_16_systems"] = worst
+        out["runs"].append(rec)
+        log(f"[bench] batched medium {rec}")
+    # the FP64 path through the single-system routines, one system at a time
+    a1.copy_(arf)
+    b1.copy_(b)
+    inf1 = torch.zeros(1, dtype=torch.int32, device=dev)
+    sub = systems[:one_at_a_time]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (n, a0, b0, ldb, nr, t, u) in sub:
+        av = a1[a0:a0 + rfp.nt(n)]
+        bv = b1[b0:b0 + n * nr].view(nr, n).t()
+        rfp.rfp_dpftrf(h, t, u, n, av, inf1)
+        rfp.rfp_dpftrs(h, t, u, n, av, bv)
+        rfp.rfp_dpftri(h, t, u, n, av, inf1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter() - t0
+    fl_sub = sum(flops_trf(s[0]) + flops_trs(s[0], s[4]) + flops_tri(s[0]) for s in sub)
+    proj = t1 * (fl_f + fl_s + fl_i) / fl_sub
+    out["one_at_a_time_fp64"] = {"systems_timed": len(sub), "ms": round(t1 * 1e3, 2),
+                                 "projected_ms_all_by_flops": round(proj * 1e3, 1),
+                                 "batched_speedup": round(proj * 1e3 / out["runs"][0]["ms"], 2)}
+    log(f"[bench] batched medium one-at-a-time {out['one_at_a_time_fp64']}")
+    del arf, b, a1, b1
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -371,6 +481,8 @@ def main():
     ap.add_argument("--mixed-n", type=int, default=40000)
     ap.add_argument("--no-kernel-profile", action="store_true",
                     help="skip the per-launch event timing (and the roofline); for counter collection runs")
+    ap.add_argument("--only", choices=["pftri", "pftrs", "mixed", "batched", "batched_medium", "cfg1"],
+                    help="run one section alone (for profiler runs) and print its JSON")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -394,6 +506,14 @@ def main():
     import torch
     import paper_0901_1696_amd as rfp
     import synth
+
+    if args.only in ("mixed", "batched", "batched_medium", "cfg1"):
+        h = rfp.Handle(0)
+        fn = {"mixed": lambda: bench_mixed(h, args.mixed_n), "batched": lambda: bench_batched(h),
+              "batched_medium": lambda: bench_batched_medium(h), "cfg1": lambda: bench_cfg1(h)}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
+        h.close()
+        return
 
     sizes = [int(s) for s in args.sizes.split(",")]
     layouts = [(s[0], s[1]) for s in args.layouts.split(",")]
@@ -430,6 +550,33 @@ def main():
     def step():
         for c in combos:
             run_one(*c)
+
+    if args.only in ("pftri", "pftrs"):
+        # one section alone: PFTRF, then PFTRI or PFTRS (nrhs), per layout
+        tot_ms = 0.0
+        s = torch.cuda.current_stream()
+        for i in range(args.steps):
+            for n, t, u in combos:
+                w = work[:rfp.nt(n)]
+                w.copy_(pristine[(n, t, u)])
+                rfp.rfp_dpftrf(h, t, u, n, w, info)
+                b = bwork[:n]
+                b.copy_(rhs[n])
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                if args.only == "pftri":
+                    rfp.rfp_dpftri(h, t, u, n, w, info)
+                else:
+                    rfp.rfp_dpftrs(h, t, u, n, w, b)
+                e1.record(s)
+                e1.synchronize()
+                tot_ms += e0.elapsed_time(e1)
+            log(f"[bench] {args.only} step {i + 1}/{args.steps} done")
+        fl = args.steps * sum(flops_tri(n) if args.only == "pftri" else flops_trs(n, nrhs) for n, _, _ in combos)
+        print(json.dumps({args.only: {"gflops": round(fl / (tot_ms * 1e-3) / 1e9, 1),
+                                      "ms_per_call": round(tot_ms / (args.steps * len(combos)), 3)}}), flush=True)
+        h.close()
+        return
 
     for i in range(args.warmup):
         step()
@@ -552,6 +699,7 @@ def main():
     cfg1 = bench_cfg1(h)
     mixed = None if args.no_mixed else bench_mixed(h, args.mixed_n)
     batched = None if args.no_batched else bench_batched(h)
+    batched_medium = None if args.no_batched else bench_batched_medium(h)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -568,7 +716,7 @@ def main():
                    "n": sizes, "layouts": [t + u for t, u in layouts], "nrhs": nrhs},
         "roofline": roofline, "profiled_region": prof_region, "cpu_baseline": cpu, "pftri": pftri,
         "accuracy": accuracy, "conversions": conversions, "cfg1": cfg1,
-        "mixed": mixed, "batched": batched,
+        "mixed": mixed, "batched": batched, "batched_medium": batched_medium,
         "kernels": kernel_table,
         "paper_context": "PFTRF 90.7-93.0 GFLOP/s at n=20000 on a 16-core Intel Tigerton with MKL "
                          "(paper's zootfac_vendor table); another machine, not the target",

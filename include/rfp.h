@@ -228,14 +228,15 @@ int rfp_dpfsv_ir(rfp_handle_t h, int fprec, char transr, char uplo, int64_t n, i
                  hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * Batched small systems (not in the paper): many SPD systems of order
- * n <= 256, each in its own RFP layout, solved in one persistent launch.
- * Each workgroup takes systems from a work counter and runs the paper's
- * factorization (Section 3), solution (Section 4) and, if asked, inversion
- * (Section 5) for one system at a time, all inside the workgroup.
+ * Batched systems (not in the paper): many SPD systems of uneven order, each
+ * in its own RFP layout, in one persistent launch.  Each system goes through
+ * the paper's factorization (Section 3), solution (Section 4) and, if
+ * asked, inversion (Section 5).  A system of order n <= 256 is one task of
+ * one workgroup; a larger one is cut into 128-row tiles whose factorization,
+ * refinement and inversion steps run as tasks on many workgroups at once.
  */
 typedef struct {
-    int64_t n;       /* order, 0 <= n <= 256 */
+    int64_t n;       /* order, n >= 0 */
     int64_t arf_off; /* element offset of the system's RFP array in arf_pool */
     int64_t b_off;   /* element offset of its first right-hand side in b_pool */
     int64_t ldb;     /* leading dimension of its right-hand sides (>= max(1, n)) */
@@ -245,25 +246,32 @@ typedef struct {
 } rfp_sys_t;
 
 /* Solve every system of the batch.  sys (device, batch entries) describes
- * the systems; arf_pool and b_pool (device) hold their RFP arrays and
- * right-hand sides, which X overwrites.  mode:
+ * the systems; sys_host is the same table in host memory, read to size the
+ * handle's workspace for the systems with n > 256 (NULL: such systems are
+ * refused with info[i] = -1); arf_pool and b_pool (device) hold the RFP
+ * arrays and right-hand sides, which X overwrites.  fprec:
  *   RFP_PREC_FP64: PFTRF in place, then PFTRS (the factor stays in arf);
- *   RFP_PREC_FP32: FP32 factor of diag(A)^{-1/2} A diag(A)^{-1/2} and FP64
- *     refinement against the untouched FP64 matrix until the normwise
+ *   RFP_PREC_FP32, RFP_PREC_FP16, RFP_PREC_BF16: low-precision factor of
+ *     mu D^{-1/2} A D^{-1/2} (D = diag(A); mu = 2^25 for FP16, else 1) with
+ *     its bulk updates on operands rounded to fprec (FP32 accumulation), and
+ *     FP64 refinement against the untouched FP64 matrix until the normwise
  *     backward error is <= tol (at most max_iter sweeps; a sweep that fails to
- *     halve it counts as stalled); on failure the FP64 path runs on arf.
+ *     halve it counts as stalled); on failure the FP64 factor and solve run
+ *     on arf.
  * With do_pftri != 0, arf ends as the RFP array of A^{-1} (PFTRI after an
- * FP64 factor, in both modes).  Device outputs per system: info[i] = 0 or the
- * FP64 PFTRF INFO (first non-positive pivot, 1-based); iter[i] = 0 (FP64
- * mode), the number of refinement sweeps, or -1 (max_iter), -2 (stalled),
- * -3 (FP32 factor not positive definite) when the FP64 path was taken; a
- * system with n > 256 or a bad layout character gets info[i] = -1 and is not
- * touched.  No host synchronisation or allocation happens once the handle's
- * workspace has been sized by an earlier call, so the call can be captured
- * in a HIP graph.  Argument order: MODE=1, BATCH=2, SYS=3, ARF_POOL=4,
- * B_POOL=5, DO_PFTRI=6, TOL=7, MAX_ITER=8, INFO=9, ITER=10. */
-int rfp_dpfsv_batched(rfp_handle_t h, int mode, int64_t batch, const rfp_sys_t* sys, double* arf_pool,
-                      double* b_pool, int do_pftri, double tol, int max_iter, int* info, int* iter,
+ * FP64 factor, in every mode).  Device outputs per system: info[i] = 0 or the
+ * FP64 PFTRF INFO (first non-positive pivot, 1-based), -1 for a refused
+ * system (bad layout character or ldb, nrhs < 0, or n > 256 without sys_host),
+ * which is not touched; iter[i] = 0 (FP64 mode), the number of refinement
+ * sweeps, or the reason the FP64 path was taken: -1 max_iter, -2 stalled,
+ * -3 low-precision factor not positive definite, -4 scaled copy not finite.
+ * No host synchronisation, and no allocation once the handle's workspace has
+ * been sized by an earlier call on the same systems, so the call can be
+ * captured in a HIP graph.  Argument order: FPREC=1, BATCH=2, SYS=3,
+ * SYS_HOST=4, ARF_POOL=5, B_POOL=6, DO_PFTRI=7, TOL=8, MAX_ITER=9, INFO=10,
+ * ITER=11. */
+int rfp_pfsv_vbatched(rfp_handle_t h, int fprec, int64_t batch, const rfp_sys_t* sys, const rfp_sys_t* sys_host,
+                      double* arf_pool, double* b_pool, int do_pftri, double tol, int max_iter, int* info, int* iter,
                       hipStream_t stream);
 
 /* ------------------------------------------------------------------------
@@ -274,13 +282,18 @@ int rfp_dpfsv_batched(rfp_handle_t h, int mode, int64_t batch, const rfp_sys_t* 
  * fused solve.  Without a table the library uses its built-in rules.  Every
  * configuration computes the same result; only speed differs.
  */
-enum { RFP_TUNE_FP64 = 1, RFP_TUNE_FP32 = 2, RFP_TUNE_FP16 = 4, RFP_TUNE_BF16 = 8 };
+enum { RFP_TUNE_FP64 = 1, RFP_TUNE_FP32 = 2, RFP_TUNE_FP16 = 4, RFP_TUNE_BF16 = 8, RFP_TUNE_SCHEDULE = 16 };
 
 /* Time every admissible configuration for the GEMM shapes that PFTRF (and,
  * for FP64, PFTRI) of order n produce in the precisions `precs` (RFP_TUNE_*
  * bits), and the solve's slice widths for nrhs right-hand sides (FP64; nrhs
  * = 0 skips it), on scratch operands on this handle's device; keep the
- * fastest.  Synchronises the stream; allocates scratch.  Argument order: N=1,
+ * fastest.  With RFP_TUNE_SCHEDULE, also time the FP64 PFTRF of order n
+ * under a grid of factorization schedules (256-column panel threshold 3072,
+ * 6144, 12288 or never; chunk width 1024, 1536 or 2048; leaf LDS reservation
+ * 0 or 24 KB) and keep the fastest for n's size class (sizes rounded up to a
+ * power of two); factorizations of that class then use it unless the caller
+ * has set a schedule with rfp_set_schedule.  Synchronises the stream; allocates scratch.  Argument order: N=1,
  * NRHS=2, PRECS=3. */
 int rfp_autotune(rfp_handle_t h, int64_t n, int64_t nrhs, int precs, hipStream_t stream);
 /* Number of tuned entries; drop the table; force one GEMM configuration for
@@ -390,6 +403,8 @@ int rfp_profile_read(rfp_handle_t h, rfp_profile_entry* out, int cap, int* count
  *     factor held as a = L11 (order m), b = L21 (k x m), c = L22 (order k);
  *     w holds the inverses of the 64-row diagonal blocks of L11 then of L22,
  *     consecutive NB x NB row-major blocks (as RFP_PLAN_TRTRI_LEAVES writes).
+ *   RFP_PLAN_AXPY: C(m x n) += alpha * A (only C's lower triangle when
+ *     c_lower).
  *   RFP_PLAN_RECORD / RFP_PLAN_WAIT: event m is recorded on / waited for by
  *     stream `stream` (0: the caller's stream, 1 and 2: the handle's two
  *     auxiliary streams).  Every other record carries the stream it runs on;
@@ -406,7 +421,8 @@ enum {
     RFP_PLAN_LAUUM_LEAF = 5,
     RFP_PLAN_RECORD = 6,
     RFP_PLAN_WAIT = 7,
-    RFP_PLAN_BLOCK_SOLVE = 8
+    RFP_PLAN_BLOCK_SOLVE = 8,
+    RFP_PLAN_AXPY = 9
 };
 enum { RFP_PLAN_BUF_ARF = 0, RFP_PLAN_BUF_B = 1, RFP_PLAN_BUF_WORK = 2, RFP_PLAN_BUF_INFO = 3 };
 typedef struct {

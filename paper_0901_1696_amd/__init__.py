@@ -68,7 +68,7 @@ _SIGS = {
     "rfp_tune_force": [_vp, _int, _int],
     "rfp_tune_save": [_vp, ctypes.c_char_p],
     "rfp_tune_load": [_vp, ctypes.c_char_p],
-    "rfp_dpfsv_batched": [_vp, _int, _i64, _vp, _vp, _vp, _int, ctypes.c_double, _int, _vp, _vp, _vp],
+    "rfp_pfsv_vbatched": [_vp, _int, _i64, _vp, _vp, _vp, _vp, _int, ctypes.c_double, _int, _vp, _vp, _vp],
     "rfp_dpfsv_ir": [_vp, _int, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp, _i64, ctypes.c_double, _int,
                      _vp, _vp, _vp],
     "rfp_solve_status": [_vp, _vp, _vp],
@@ -87,7 +87,7 @@ class ProfileEntry(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 PLAN_GEMM, PLAN_POTRF_LEAF, PLAN_TRTRI_LEAF, PLAN_TRTRI_LEAVES, PLAN_LAUUM_LEAF = 1, 2, 3, 4, 5
-PLAN_RECORD, PLAN_WAIT, PLAN_BLOCK_SOLVE = 6, 7, 8
+PLAN_RECORD, PLAN_WAIT, PLAN_BLOCK_SOLVE, PLAN_AXPY = 6, 7, 8, 9
 PLAN_BUF_ARF, PLAN_BUF_B, PLAN_BUF_WORK = 0, 1, 2
 
 
@@ -390,15 +390,22 @@ def sys_table(systems):
     return bytes(arr)[:ctypes.sizeof(SysDesc) * len(systems)]
 
 
-def rfp_dpfsv_batched(h, mode, batch, sys, arf_pool, b_pool, info, iter, do_pftri=False, tol=1e-14, max_iter=20,
-                      stream=None):
-    """sys: device tensor holding the ``rfp_sys_t`` table (e.g. a uint8 tensor from :func:`sys_table`)."""
-    _check("rfp_dpfsv_batched", lib().rfp_dpfsv_batched(h.value, int(mode), int(batch), _ptr(sys), _ptr(arf_pool),
-                                                        _ptr(b_pool), 1 if do_pftri else 0, float(tol), int(max_iter),
-                                                        _ptr(info), _ptr(iter), _stream(stream)))
+def rfp_pfsv_vbatched(h, fprec, batch, sys, arf_pool, b_pool, info, iter, sys_host=None, do_pftri=False,
+                      tol=1e-14, max_iter=20, stream=None):
+    """sys: device tensor holding the ``rfp_sys_t`` table (e.g. a uint8 tensor
+    from :func:`sys_table`); sys_host: the same table as bytes on the host
+    (needed for systems with n > 256, which are refused without it)."""
+    hbuf = None
+    if sys_host is not None:
+        hbuf = (ctypes.c_char * max(1, len(sys_host))).from_buffer_copy(bytes(sys_host) or b"\0")
+    _check("rfp_pfsv_vbatched", lib().rfp_pfsv_vbatched(h.value, int(fprec), int(batch), _ptr(sys),
+                                                        None if hbuf is None else ctypes.addressof(hbuf),
+                                                        _ptr(arf_pool), _ptr(b_pool), 1 if do_pftri else 0,
+                                                        float(tol), int(max_iter), _ptr(info), _ptr(iter),
+                                                        _stream(stream)))
 
 
-TUNE_FP64, TUNE_FP32, TUNE_FP16, TUNE_BF16 = 1, 2, 4, 8
+TUNE_FP64, TUNE_FP32, TUNE_FP16, TUNE_BF16, TUNE_SCHEDULE = 1, 2, 4, 8, 16
 
 
 def rfp_autotune(h, n, nrhs=0, precs=TUNE_FP64, stream=None):

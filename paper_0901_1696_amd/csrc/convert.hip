@@ -134,6 +134,37 @@ hipError_t scale2d(hipStream_t s, Mat<T> x, int64_t m, int64_t n, T alpha, bool 
 template hipError_t scale2d<double>(hipStream_t, Mat<double>, int64_t, int64_t, double, bool);
 template hipError_t scale2d<float>(hipStream_t, Mat<float>, int64_t, int64_t, float, bool);
 
+// C += alpha A on an m x n view (lower triangle only if lower).
+template <typename T>
+__global__ __launch_bounds__(256) void axpy2d_kernel(Mat<T> c, Mat<const T> a, int64_t m, int64_t n, T alpha,
+                                                     int lower, int64_t tiles_m)
+{
+    const int64_t ti = blockIdx.x % tiles_m, tj = blockIdx.x / tiles_m;
+    const int64_t i0 = ti * CT, j0 = tj * CT;
+    if (lower && j0 > i0 + CT - 1) return;
+    const int t = threadIdx.x, fast = t % CT, slow = t / CT;
+    const bool rows = c.rs == 1;
+#pragma unroll 4
+    for (int r = 0; r < CT / 4; r++) {
+        const int li = rows ? fast : slow + 4 * r;
+        const int lj = rows ? slow + 4 * r : fast;
+        const int64_t i = i0 + li, j = j0 + lj;
+        if (i < m && j < n && (!lower || i >= j)) c.at(i, j) += alpha * a.at(i, j);
+    }
+}
+
+template <typename T>
+hipError_t axpy2d(hipStream_t s, Mat<T> c, Mat<const T> a, int64_t m, int64_t n, T alpha, bool lower)
+{
+    if (m <= 0 || n <= 0) return hipSuccess;
+    const int64_t tm = (m + CT - 1) / CT, tn = (n + CT - 1) / CT;
+    hipLaunchKernelGGL((axpy2d_kernel<T>), dim3((unsigned)(tm * tn)), dim3(256), 0, s, c, a, m, n, alpha,
+                       lower ? 1 : 0, tm);
+    return hipGetLastError();
+}
+template hipError_t axpy2d<double>(hipStream_t, Mat<double>, Mat<const double>, int64_t, int64_t, double, bool);
+template hipError_t axpy2d<float>(hipStream_t, Mat<float>, Mat<const float>, int64_t, int64_t, float, bool);
+
 // The diagonal of the two diagonal blocks: save it to buf and set it to one
 // (restore = 0), or write buf back (restore = 1).
 template <typename T>

@@ -137,6 +137,7 @@ struct rfp_context {
     int cus;              // compute units of the device
     rfp::TuneTable* tune; // autotuned kernel configurations (null: built-in rules)
     rfp_schedule_t sched; // factorization schedule knobs
+    int sched_user;       // 1: set by rfp_set_schedule (tuned schedules are then not used)
 };
 
 namespace rfp {
@@ -358,9 +359,12 @@ struct Run {
         }
         wait(0, bulk_prev);
     }
+    // the stream the next GEMMs and leaves go to
+    const Exec& cur() const { return on == 1 ? ex2 : on == 2 ? ex3 : ex; }
     void leaf(int kind, Mat<const T> A, int64_t order, const T* w, int64_t info_base)
     {
         if (rfp_plan_op* o = next(kind)) {
+            o->stream = on;
             o->m = order;
             o->info_base = info_base;
             plan_view(A.p, A.rs, A.cs, sizeof(T), o->a);
@@ -383,6 +387,25 @@ struct Run {
         trsm_rlt(m, n2, B.sub(0, n1), L.sub(n1, n1), winv + nleaves(n1, nb) * nb * nb);
     }
 
+
+    // C (m x n) += alpha A (lower triangles only when lower)
+    void axpy(int64_t m, int64_t n, T alpha, Mat<const T> A, Mat<T> C, bool lower)
+    {
+        if (m <= 0 || n <= 0) return;
+        if (rec) {
+            if (rfp_plan_op* o = next(RFP_PLAN_AXPY)) {
+                o->stream = on;
+                o->m = m;
+                o->n = n;
+                o->alpha = (double)alpha;
+                o->c_lower = lower ? 1 : 0;
+                plan_view(A.p, A.rs, A.cs, sizeof(T), o->a);
+                plan_view(C.p, C.rs, C.cs, sizeof(T), o->c);
+            }
+            return;
+        }
+        chk(axpy2d<T>(cur().stream, C, A, m, n, alpha, lower));
+    }
 
     // B (m x n) <- B L^{-1}; L lower of order n whose leaf inverses are in winv.
     void trsm_rln(int64_t m, int64_t n, Mat<T> B, Mat<const T> L, const T* winv)
@@ -456,7 +479,7 @@ struct Run {
         if (n <= 0) return;
         if (n <= nb) {
             if (rec) leaf(RFP_PLAN_TRTRI_LEAF, A, n, nullptr, goff);
-            else chk(trtri_leaf<T>(ex, A, (int)n, goff));
+            else chk(trtri_leaf<T>(cur(), A, (int)n, goff));
             return;
         }
         const int64_t n1 = rec_split(n, nb), n2 = n - n1;
@@ -471,7 +494,7 @@ struct Run {
         if (n <= 0) return;
         if (n <= nb) {
             if (rec) leaf(RFP_PLAN_LAUUM_LEAF, W, n, nullptr, 0);
-            else chk(lauum_leaf<T>(ex, W, (int)n));
+            else chk(lauum_leaf<T>(cur(), W, (int)n));
             return;
         }
         const int64_t n1 = rec_split(n, nb), n2 = n - n1;
@@ -598,9 +621,21 @@ static bool bad_schedule(const rfp_schedule_t& sc)
            sc.leaf_lds_pad > MAX_LEAF_LDS_PAD;
 }
 
-template <typename T>
-static Run<T> make_run(rfp_context* h, hipStream_t s, int* info, int lowp = 0)
+// The schedule of a factorization of order n: the caller's, else a tuned one
+// for n's size class, else the defaults.
+static rfp_schedule_t schedule_for(const rfp_context* h, int64_t n)
 {
+    if (!h->sched_user && h->tune) {
+        auto it = h->tune->sched.find(size_bucket(n));
+        if (it != h->tune->sched.end()) return it->second;
+    }
+    return h->sched;
+}
+
+template <typename T>
+static Run<T> make_run(rfp_context* h, hipStream_t s, int* info, int lowp = 0, const rfp_schedule_t* sc = nullptr)
+{
+    const rfp_schedule_t sched = sc ? *sc : h->sched;
     Run<T> r;
     r.ex.stream = s;
     r.ex.info = info;
@@ -617,9 +652,9 @@ static Run<T> make_run(rfp_context* h, hipStream_t s, int* info, int lowp = 0)
     r.ex.tune = r.ex2.tune = h->tune;
     // low-precision operands for every non-in-place product of all three streams
     r.ex.lowp = r.ex2.lowp = lowp;
-    r.ex.leaf_pad = r.ex2.leaf_pad = (int)h->sched.leaf_lds_pad;
-    r.wide_panels_above = h->sched.wide_panels_above;
-    r.lookahead_wait_below = h->sched.lookahead_wait_below;
+    r.ex.leaf_pad = r.ex2.leaf_pad = (int)sched.leaf_lds_pad;
+    r.wide_panels_above = sched.wide_panels_above;
+    r.lookahead_wait_below = sched.lookahead_wait_below;
     r.ex3 = r.ex;
     r.ex3.stream = h->aux2;
     r.ex3.splitk_ws = nullptr;  // its GEMMs never split K: no workspace shared with the other streams
@@ -709,8 +744,8 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     } else {
         if (n == 0) return set_int(s, info, 0) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
         if (prepare(h, size_t(lv) * NB2 * NB2 * sizeof(T)) != hipSuccess) return RFP_ERR_RUNTIME;
-        sc = h->sched;
-        r = make_run<T>(h, s, info, lowp);
+        sc = schedule_for(h, n);
+        r = make_run<T>(h, s, info, lowp, &sc);
         winv = (T*)h->inv;
     }
     r.nb = NB2;
@@ -817,26 +852,49 @@ static int pftri_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     RfpBlocks b;
     rfp_blocks(transr, uplo, n, &b);
     Run<T> r;
+    T* tmp;  // m1 x m1 column-major: W21^T W21 of stage 3, formed before S changes
     DeviceGuard g(rec ? -1 : h->device);
     if (rec) {
         r.rec = rec;
+        tmp = plan_base<T>(RFP_PLAN_BUF_WORK);
     } else {
         if (n == 0) return set_int(s, info, 0) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
-        if (prepare(h, 0) != hipSuccess) return RFP_ERR_RUNTIME;
+        if (prepare(h, sizeof(T) * (size_t)b.m1 * (size_t)b.m1) != hipSuccess) return RFP_ERR_RUNTIME;
         r = make_run<T>(h, s, info);
+        tmp = (T*)h->inv;
     }
     RfpView<T> v = rfp_view(b, arf);
+    Mat<T> Tmp{tmp, 1, b.m1};
     r.setinfo(info);
-    // stage 2 (TFTRI): W11 = L11^{-1}; S <- -S W11; W22 = L22^{-1}; S <- W22 S
+    const bool two = r.three_streams();
+    const int side = two ? 2 : 0;  // the stream of the T2 side
+    // stage 2 (TFTRI): W11 = L11^{-1}; S <- -S W11; W22 = L22^{-1}; S <- W22 S.
+    // W22 comes on the second stream while the first inverts L11 and scales S.
+    hipEvent_t start = two ? r.record(0) : nullptr;
+    r.wait(side, start);
+    r.on = side;
+    r.trtri_rec(b.m2, v.t2, b.m1);
+    r.on = 0;
+    hipEvent_t w22 = two ? r.record_join(side) : nullptr;
     r.trtri_rec(b.m1, v.t1, 0);
     r.trmm_rl(b.m2, b.m1, v.s, v.t1, T(-1));
-    r.trtri_rec(b.m2, v.t2, b.m1);
+    r.wait(0, w22);
     r.trmm_ll(b.m2, b.m1, v.t2, v.s);
-    // stage 3: T1 <- W11^T W11 + W21^T W21; S <- W22^T W21; T2 <- W22^T W22
-    r.lauum_rec(b.m1, v.t1);
-    r.mm(b.m1, b.m1, b.m2, T(1), v.s.tr(), TRI_NONE, v.s.tr(), TRI_NONE, T(1), v.t1, true);
+    // stage 3: T1 <- W11^T W11 + W21^T W21; S <- W22^T W21; T2 <- W22^T W22.
+    // W21^T W21 goes to a scratch triangle first, so that S can change on the
+    // second stream (S <- W22^T S, then LAUUM of T2) while the first stream
+    // forms W11^T W11 in T1 and adds the scratch triangle to it.
+    r.mm(b.m1, b.m1, b.m2, T(1), v.s.tr(), TRI_NONE, v.s.tr(), TRI_NONE, T(0), Tmp, true);
+    hipEvent_t syrk = two ? r.record(0) : nullptr;
+    r.wait(side, syrk);
+    r.on = side;
     r.trmm_llt(b.m2, b.m1, v.t2, v.s);
     r.lauum_rec(b.m2, v.t2);
+    r.on = 0;
+    hipEvent_t t2done = two ? r.record_join(side) : nullptr;
+    r.lauum_rec(b.m1, v.t1);
+    r.axpy(b.m1, b.m1, T(1), Tmp, v.t1, true);
+    r.wait(0, t2done);
     return r.err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
@@ -1373,6 +1431,64 @@ static int tune_solve(rfp_context* h, int64_t n, int64_t nrhs, hipStream_t st)
     return 0;
 }
 
+// Factorization schedule for order n: the FP64 PFTRF of the identity (the
+// same work as any matrix: no kernel depends on the values, and the factor of
+// the identity is the identity, so repeated calls need no restore) timed
+// under each candidate; the fastest is kept for n's size class.
+static int tune_schedule(rfp_context* h, int64_t n, hipStream_t st)
+{
+    const size_t nt = (size_t)(n * (n + 1) / 2);
+    double* arf = nullptr;
+    int* info = nullptr;
+    if (hipMalloc(&arf, nt * 8) != hipSuccess) return RFP_ERR_RUNTIME;
+    if (hipMalloc(&info, sizeof(int)) != hipSuccess) {
+        (void)hipFree(arf);
+        return RFP_ERR_RUNTIME;
+    }
+    (void)fill_double(st, arf, (int64_t)nt, 0.0);
+    RfpBlocks blk;
+    rfp_blocks('N', 'L', n, &blk);
+    RfpView<double> v = rfp_view(blk, arf);
+    hipLaunchKernelGGL(tune_diag_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v.t1, v.m1, v.t2, v.m2);
+    const rfp_schedule_t saved = h->sched;
+    const int saved_user = h->sched_user;
+    h->sched_user = 1;  // time exactly the candidate
+    rfp_schedule_t best = default_schedule();
+    float best_ms = -1.f;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    for (int64_t wide : {int64_t(3072), int64_t(6144), int64_t(12288), INT64_MAX})
+        for (int64_t chunk : {int64_t(1024), int64_t(1536), int64_t(2048)})
+            for (int64_t pad : {int64_t(0), DEFAULT_LEAF_LDS_PAD}) {
+                rfp_schedule_t sc = default_schedule();
+                sc.wide_panels_above = wide;
+                sc.chunk_max = chunk;
+                sc.leaf_lds_pad = pad;
+                h->sched = sc;
+                (void)pftrf_impl<double>(h, 'N', 'L', n, arf, info, st);
+                (void)hipEventRecord(e0, st);
+                (void)pftrf_impl<double>(h, 'N', 'L', n, arf, info, st);
+                (void)pftrf_impl<double>(h, 'N', 'L', n, arf, info, st);
+                (void)hipEventRecord(e1, st);
+                float ms = -1.f;
+                if (hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms > 0 && (best_ms < 0 || ms < best_ms)) {
+                    best_ms = ms;
+                    best = sc;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->sched = saved;
+    h->sched_user = saved_user;
+    if (best_ms > 0) h->tune->sched[size_bucket(n)] = best;
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(arf);
+    (void)hipFree(info);
+    return 0;
+}
+
 // GEMM shapes recorded from the drivers' plans (non-in-place products).
 static void plan_shapes(char routine, int64_t n, std::vector<TuneShape>& out, int dt, int lp)
 {
@@ -1662,31 +1778,53 @@ int rfp_dpfsv_ir(rfp_handle_t h, int fprec, char transr, char uplo, int64_t n, i
     return pfsv_ir_impl(h, fprec, transr, uplo, n, nrhs, arf, b, ldb, x, ldx, tol, max_iter, iter, info, stream);
 }
 
-int rfp_dpfsv_batched(rfp_handle_t h, int mode, int64_t batch, const rfp_sys_t* sys, double* arf_pool,
-                      double* b_pool, int do_pftri, double tol, int max_iter, int* info, int* iter,
+int rfp_pfsv_vbatched(rfp_handle_t h, int fprec, int64_t batch, const rfp_sys_t* sys, const rfp_sys_t* sys_host,
+                      double* arf_pool, double* b_pool, int do_pftri, double tol, int max_iter, int* info, int* iter,
                       hipStream_t stream)
 {
     if (!h) return RFP_ERR_HANDLE;
-    if (mode != RFP_PREC_FP64 && mode != RFP_PREC_FP32) return -1;
+    int mode;
+    switch (fprec) {
+        case RFP_PREC_FP64: mode = 0; break;
+        case RFP_PREC_FP32: mode = 1; break;
+        case RFP_PREC_FP16: mode = 2; break;
+        case RFP_PREC_BF16: mode = 3; break;
+        default: return -1;
+    }
     if (batch < 0) return -2;
     if (batch == 0) return 0;
     if (!sys) return -3;
-    if (!arf_pool) return -4;
-    if (!b_pool) return -5;
-    if (mode == RFP_PREC_FP32 && !(tol > 0.0)) return -7;
-    if (mode == RFP_PREC_FP32 && max_iter < 1) return -8;
-    if (!info) return -9;
-    if (!iter) return -10;
+    if (!arf_pool) return -5;
+    if (!b_pool) return -6;
+    if (mode != 0 && !(tol > 0.0)) return -8;
+    if (mode != 0 && max_iter < 1) return -9;
+    if (!info) return -10;
+    if (!iter) return -11;
     DeviceGuard g(h->device);
-    const int wgs = (int)std::min<int64_t>(batch, h->cus);  // one resident workgroup per CU (LDS-bound)
-    const size_t need = 256 + batched_scratch_bytes(wgs);
+    const int pftri = do_pftri ? 1 : 0;
+    const int mi = mode ? max_iter : 1;
+    // Sizes: the per-system scratch and the task count of the systems with
+    // n > 256 come from the host copy of the table (without it such systems
+    // are refused); the per-workgroup scratch is sized for two workgroups per
+    // compute unit, the most that run at once.
+    int64_t tasks = batch, sysbytes = 0;
+    if (sys_host) sysbytes = batched_plan_host(sys_host, batch, mode, pftri, mi, &tasks);
+    const int wgs = h->cus;  // one workgroup per compute unit (register-bound)
+    const size_t a_ctl = 256, a_st = batched_state_bytes(batch);
+    const size_t a_q = (sizeof(unsigned long long) * (size_t)(tasks + 1) + 255) & ~(size_t)255;
+    const size_t a_wg = (size_t)wgs * batched_wg_scratch_bytes();
+    const size_t need = a_ctl + a_st + a_q + a_wg + (size_t)sysbytes;
     if (ensure(&h->bat, &h->bat_bytes, need) != hipSuccess) return RFP_ERR_RUNTIME;
+    char* base = (char*)h->bat;
     Exec ex{};
     ex.stream = stream;
     ex.prof = h->prof;
-    const hipError_t e = batched_solve(ex, sys, batch, arf_pool, b_pool, mode == RFP_PREC_FP32 ? 1 : 0,
-                                       do_pftri ? 1 : 0, tol, max_iter, info, iter, (int*)h->bat,
-                                       (char*)h->bat + 256, wgs);
+    const hipError_t e = batched_solve(ex, sys, batch, arf_pool, b_pool, mode, pftri, tol, mi, info, iter,
+                                       base + a_ctl + a_st + a_q, wgs, base + a_ctl + a_st + a_q + a_wg,
+                                       sys_host ? (int64_t)(h->bat_bytes - (a_ctl + a_st + a_q + a_wg)) : 0,
+                                       base + a_ctl,
+                                       (unsigned long long*)(base + a_ctl + a_st), tasks + 1,
+                                       (unsigned long long*)base);
     return e == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
@@ -1695,7 +1833,7 @@ int rfp_autotune(rfp_handle_t h, int64_t n, int64_t nrhs, int precs, hipStream_t
     if (!h) return RFP_ERR_HANDLE;
     if (n < 1) return -1;
     if (nrhs < 0) return -2;
-    if (precs <= 0 || precs > 15) return -3;
+    if (precs <= 0 || precs > 31) return -3;
     DeviceGuard g(h->device);
     if (!h->tune) h->tune = new TuneTable();
     std::vector<TuneShape> shapes;
@@ -1708,6 +1846,7 @@ int rfp_autotune(rfp_handle_t h, int64_t n, int64_t nrhs, int precs, hipStream_t
     if (precs & RFP_TUNE_BF16) plan_shapes('F', n, shapes, 1, 2);
     int rc = tune_gemms(h, shapes, stream);
     if (rc == 0 && nrhs > 0 && (precs & RFP_TUNE_FP64)) rc = tune_solve(h, n, nrhs, stream);
+    if (rc == 0 && (precs & RFP_TUNE_SCHEDULE)) rc = tune_schedule(h, n, stream);
     return rc;
 }
 
@@ -1717,6 +1856,7 @@ int rfp_set_schedule(rfp_handle_t h, const rfp_schedule_t* sched)
     const rfp_schedule_t sc = sched ? *sched : default_schedule();
     if (bad_schedule(sc)) return -2;
     h->sched = sc;
+    h->sched_user = sched ? 1 : 0;
     return 0;
 }
 
@@ -1756,7 +1896,7 @@ int rfp_set_solve_wait_limit(rfp_handle_t h, int64_t polls)
 int rfp_tune_count(rfp_handle_t h)
 {
     if (!h) return RFP_ERR_HANDLE;
-    return h->tune ? (int)(h->tune->gemm.size() + h->tune->solve.size()) : 0;
+    return h->tune ? (int)(h->tune->gemm.size() + h->tune->solve.size() + h->tune->sched.size()) : 0;
 }
 
 int rfp_tune_clear(rfp_handle_t h)
@@ -1801,6 +1941,15 @@ int rfp_tune_save(rfp_handle_t h, const char* path)
         for (auto& kv : h->tune->solve)
             fprintf(f, "  {\"key\": %llu, \"ncb\": %d}%s\n", (unsigned long long)kv.first, kv.second,
                     ++i < h->tune->solve.size() ? "," : "");
+    fprintf(f, " ],\n \"sched\": [\n");
+    i = 0;
+    if (h->tune)
+        for (auto& kv : h->tune->sched)
+            fprintf(f, "  {\"bucket\": %d, \"wide_panels_above\": %lld, \"chunk_max\": %lld, "
+                       "\"lookahead_wait_below\": %lld, \"leaf_lds_pad\": %lld}%s\n",
+                    kv.first, (long long)kv.second.wide_panels_above, (long long)kv.second.chunk_max,
+                    (long long)kv.second.lookahead_wait_below, (long long)kv.second.leaf_lds_pad,
+                    ++i < h->tune->sched.size() ? "," : "");
     fprintf(f, " ]\n}\n");
     return fclose(f) == 0 ? 0 : -1;
 }
@@ -1816,6 +1965,27 @@ int rfp_tune_load(rfp_handle_t h, const char* path)
     bool ok = true, in_solve = false;
     while (fgets(line, sizeof line, f)) {
         if (strstr(line, "\"solve\"")) in_solve = true;
+        if (const char* qs = strstr(line, "{\"bucket\":")) {
+            int bucket;
+            long long w, c, l, p;
+            rfp_schedule_t sc;
+            if (sscanf(qs, "{\"bucket\": %d, \"wide_panels_above\": %lld, \"chunk_max\": %lld, "
+                           "\"lookahead_wait_below\": %lld, \"leaf_lds_pad\": %lld}",
+                       &bucket, &w, &c, &l, &p) != 5) {
+                ok = false;
+                break;
+            }
+            sc.wide_panels_above = w;
+            sc.chunk_max = c;
+            sc.lookahead_wait_below = l;
+            sc.leaf_lds_pad = p;
+            if (bad_schedule(sc)) {
+                ok = false;
+                break;
+            }
+            t->sched[bucket] = sc;
+            continue;
+        }
         const char* q = strstr(line, "{\"key\":");
         if (!q) continue;
         unsigned long long key;

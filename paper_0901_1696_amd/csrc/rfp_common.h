@@ -151,6 +151,7 @@ struct TuneGemm {
 struct TuneTable {
     std::map<uint64_t, TuneGemm> gemm;
     std::map<uint64_t, int> solve;  // key -> 16-column blocks per slice
+    std::map<int, rfp_schedule_t> sched;  // size_bucket(n) -> factorization schedule
     int force_tile = -1, force_split = 0;  // testing: one configuration for every GEMM
 };
 // Shape classes: sizes by ceil(log2), precision (dt 0 FP64, 1 FP32; lp the
@@ -307,12 +308,19 @@ hipError_t ir_copy(hipStream_t st, double* y, int64_t ldy, const double* x, int6
 // 1-D copy of count doubles, nothing while *gate != 0
 hipError_t gated_copy(hipStream_t st, double* dst, const double* src, int64_t count, const int* gate);
 
-// Batched small systems (n <= 256): one persistent launch; scratch holds
-// batched_scratch_bytes(wgs) bytes, counter one int.
-size_t batched_scratch_bytes(int wgs);
+// Batched systems in one persistent launch (csrc/batched.hip).  mode: 0 FP64,
+// 1 FP32, 2 FP16, 3 BF16 factor + FP64 refinement.  wgs_mem holds
+// batched_wg_scratch_bytes() per workgroup; sysmem the per-system scratch of
+// the systems with n > 256 (their total from batched_plan_host); st
+// batched_state_bytes(batch); q a task queue of qcap slots; ctl 4 words.
+size_t batched_wg_scratch_bytes();
+size_t batched_state_bytes(int64_t batch);
+int64_t batched_plan_host(const rfp_sys_t* sys_host, int64_t batch, int mode, int pftri, int max_iter,
+                          int64_t* tasks);
 hipError_t batched_solve(const Exec& ex, const rfp_sys_t* sys, int64_t batch, double* arf, double* b, int mode,
-                         int pftri, double tol, int max_iter, int* info, int* iter, int* counter, char* scratch,
-                         int wgs);
+                         int pftri, double tol, int max_iter, int* info, int* iter, char* wgs_mem, int wgs,
+                         char* sysmem, int64_t sysmem_bytes, void* st, unsigned long long* q, int64_t qcap,
+                         unsigned long long* ctl);
 
 // 2-D strided copy dst = src (m x n), optionally only the lower triangle.
 template <typename Td, typename Ts>
@@ -325,6 +333,9 @@ hipError_t packed_copy(hipStream_t s, const RfpView<T>& v, T* ap, bool upper_pac
 // writes zeros without reading X.
 template <typename T>
 hipError_t scale2d(hipStream_t s, Mat<T> x, int64_t m, int64_t n, T alpha, bool lower);
+// C += alpha A on an m x n view (lower triangle only if lower).
+template <typename T>
+hipError_t axpy2d(hipStream_t s, Mat<T> c, Mat<const T> a, int64_t m, int64_t n, T alpha, bool lower);
 // Save the diagonal of T1 and T2 into buf (n entries) and set it to one, or
 // (restore) write buf back.
 template <typename T>

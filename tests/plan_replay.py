@@ -101,6 +101,15 @@ class Replayer:
         R = op.alpha * (A @ B.T) + (op.beta * C if op.beta != 0 else 0.0)
         self.write(tuple(op.c), R, cmask, "gemm C")
 
+    def axpy(self, op):
+        m, n = op.m, op.n
+        mask = _mask(1 if op.c_lower else 0, m, n)
+        A, ra = self.read(tuple(op.a), m, n, 1 if op.c_lower else 0, "axpy A")
+        C, rc = self.read(tuple(op.c), m, n, 1 if op.c_lower else 0, "axpy C")
+        if ra[0] == rc[0] and ra[1] & rc[1]:
+            raise PlanError("axpy: A and C overlap")
+        self.write(tuple(op.c), C + op.alpha * A, mask, "axpy C")
+
     def leaf(self, op):
         nb = op.m
         low = _mask(1, nb, nb)
@@ -177,6 +186,8 @@ class Replayer:
                 self.leaves(op)
             elif op.kind == rfp.PLAN_BLOCK_SOLVE:
                 self.block_solve(op)
+            elif op.kind == rfp.PLAN_AXPY:
+                self.axpy(op)
             else:
                 self.leaf(op)
             s = op.stream
@@ -208,12 +219,15 @@ NB2 = 128
 
 
 def work_size(routine, uplo, n):
-    """Scratch the library allocates for the leaf inverses of each routine:
-    PFTRF reuses one set of 128-blocks sized for the larger diagonal block,
-    PFTRS keeps the 64-block inverses of both T1 and T2, PFTRI needs none."""
+    """Scratch the library allocates for each routine: PFTRF reuses one set of
+    128-block leaf inverses sized for the larger diagonal block, PFTRS keeps
+    the 64-block inverses of both T1 and T2, PFTRI one m1 x m1 square (the
+    product W21^T W21 formed before S changes)."""
     m1 = (n + 1) // 2 if uplo == "L" else n // 2
     m2 = n - m1
     nl = lambda m, b: (m + b - 1) // b
     if routine == "F":
         return max(nl(m1, NB2), nl(m2, NB2)) * NB2 * NB2
-    return {"S": nl(m1, NB) + nl(m2, NB), "I": 0}[routine] * NB * NB
+    if routine == "I":
+        return m1 * m1
+    return (nl(m1, NB) + nl(m2, NB)) * NB * NB

@@ -69,3 +69,28 @@ def test_every_forced_configuration_is_correct(tile, split):
     rfp.rfp_tune_force(h, tile, split)
     for t, u, n in [("N", "L", 513), ("T", "U", 300), ("N", "U", 1001)]:
         _check_all(h, n, t, u, seed=n + tile)
+
+
+def test_autotune_schedule(tmp_path):
+    """The factorization schedule is tuned per size class: the tuned entry is
+    saved and loaded with the table, factorizations of that class use it and
+    stay correct, and a schedule set by the caller takes precedence."""
+    h = rfp.Handle(0)
+    n = 2300
+    rfp.rfp_autotune(h, n, nrhs=0, precs=rfp.TUNE_SCHEDULE)
+    assert rfp.rfp_tune_count(h) == 1
+    path = tmp_path / "sched.json"
+    rfp.rfp_tune_save(h, str(path))
+    doc = json.loads(path.read_text())
+    assert len(doc["sched"]) == 1
+    e = doc["sched"][0]
+    assert e["wide_panels_above"] in (3072, 6144, 12288, 2 ** 63 - 1)
+    assert e["chunk_max"] in (1024, 1536, 2048) and e["leaf_lds_pad"] in (0, 24576)
+    for t, u in [("N", "L"), ("T", "U")]:
+        _check_all(h, n, t, u, seed=17)
+    rfp.rfp_tune_clear(h)
+    rfp.rfp_tune_load(h, str(path))
+    assert rfp.rfp_tune_count(h) == 1
+    rfp.rfp_set_schedule(h, dict(wide_panels_above=0))
+    _check_all(h, n, "N", "U", seed=18)
+    rfp.rfp_set_schedule(h, None)
