@@ -175,14 +175,29 @@ int rfp_spftrf_mp(rfp_handle_t h, int fprec, char transr, char uplo, int64_t n, 
                   hipStream_t stream);
 
 /* Scaled cast: s[i] = 1/sqrt(a_ii) when scale != 0 (else 1), and
- * arf32 = (float)(((a_ij * s_i) * s_j) * mu) on every stored entry, in the
- * same RFP layout (so diag(s) A diag(s) has a unit diagonal before mu).  Each
- * product is rounded in FP64 in that order, then rounded once to FP32.  A
- * diagonal entry that is not positive gives s_i = NaN.  s is a device array of
- * n doubles.  Argument order: TRANSR=1, UPLO=2, N=3, ARF=4, SCALE=5, MU=6
- * (positive, finite), S=7, ARF32=8. */
+ * arf32 = (float)(((a_ij * s_i) * s_j) * mu) on every stored off-diagonal
+ * entry, (float)((((a_ii * s_i) * s_i) + shift) * mu) on the diagonal, in the
+ * same RFP layout (so diag(s) A diag(s) has a unit diagonal before the shift
+ * and mu).  Each operation is rounded in FP64 in that order, then the result
+ * once to FP32.  A diagonal entry that is not positive gives s_i = NaN.  s is
+ * a device array of n doubles.  Argument order: TRANSR=1, UPLO=2, N=3,
+ * ARF=4, SCALE=5, MU=6 (positive, finite), SHIFT=7 (>= 0, finite), S=8,
+ * ARF32=9. */
 int rfp_dpfcast_s(rfp_handle_t h, char transr, char uplo, int64_t n, const double* arf, int scale, double mu,
-                  double* s, float* arf32, hipStream_t stream);
+                  double shift, double* s, float* arf32, hipStream_t stream);
+
+/* Diagonal shift of the low-precision factors of rfp_dpfsv_ir and
+ * rfp_pfsv_vbatched (not in the paper; the shift of Higham and Pranesh's
+ * low-precision Cholesky, SIAM J. Sci. Comput. 43 (2021)): they factor
+ * mu (D^{-1/2} A D^{-1/2} + c u I), u the unit roundoff of the factor's
+ * precision (2^-24 FP32, 2^-11 FP16, 2^-8 BF16), so that the factor's
+ * rounding cannot make an ill-conditioned matrix lose positive
+ * definiteness; refinement against the unshifted FP64 matrix removes the
+ * shift from the solution.  One c per precision FPREC (RFP_PREC_FP32,
+ * RFP_PREC_FP16 or RFP_PREC_BF16), c >= 0 (0: no shift; defaults 64 for
+ * FP32, 4 for FP16 and BF16).  Argument order: FPREC=2, C=3. */
+int rfp_set_lowp_shift(rfp_handle_t h, int fprec, double c);
+int rfp_get_lowp_shift(rfp_handle_t h, int fprec, double* c);
 
 /* LANSF (the paper's routine table, "Norm"): *out (device double) = the norm
  * of the symmetric matrix held in arf: 'M' max |a_ij|, '1', 'O' or 'I' the
@@ -194,9 +209,11 @@ int rfp_dlansf(rfp_handle_t h, char norm, char transr, char uplo, int64_t n, con
 
 /* Solve A X = B for the FP64 SPD matrix in arf (left untouched) by a
  * low-precision Cholesky factor and FP64 iterative refinement:
- *   As = mu D^{-1/2} A D^{-1/2} rounded to FP32 (rfp_dpfcast_s with
- *   scale = 1; mu = 2^25 for FPREC = RFP_PREC_FP16, so that the factor's
- *   entries use the FP16 range, else 1); Ls = PFTRF(As) with the bulk
+ *   As = mu (D^{-1/2} A D^{-1/2} + c u I) rounded to FP32 (rfp_dpfcast_s
+ *   with scale = 1 and the shift c u of rfp_set_lowp_shift; mu = 2^25 for
+ *   FPREC = RFP_PREC_FP16, so that the factor's entries and those of its
+ *   diagonal blocks' inverses both stay in the FP16 range, else 1);
+ *   Ls = PFTRF(As) with the bulk
  *   updates in precision fprec (as rfp_spftrf_mp); the preconditioner is
  *   M^{-1} = mu D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2} (solves in FP32).
  *   X = 0, R = B; each sweep corrects X from R in FP64, then R = B - A X
@@ -205,7 +222,9 @@ int rfp_dlansf(rfp_handle_t h, char norm, char transr, char uplo, int64_t n, con
  *   A sweep is X += M^{-1} R (classical refinement) until one fails to cut
  *   the backward error fourfold; later sweeps run 8 steps of conjugate
  *   gradients on A D = R preconditioned by M^{-1}, in FP64 (refinement with a
- *   CG inner solver), which converges where kappa(A) u_low is not small.
+ *   CG inner solver; M^{-1} is then applied in FP64 arithmetic from an FP64
+ *   copy of Ls, so that it is symmetric to FP64 rounding), which converges
+ *   where kappa(A) u_low is not small.
  * Falls back to the FP64 PFTRF + PFTRS on a copy of A when the scaled copy
  * is not finite, when the low-precision factor is not positive definite,
  * when a conjugate-gradient sweep fails to cut the backward error below 0.9
@@ -252,12 +271,15 @@ typedef struct {
  * arrays and right-hand sides, which X overwrites.  fprec:
  *   RFP_PREC_FP64: PFTRF in place, then PFTRS (the factor stays in arf);
  *   RFP_PREC_FP32, RFP_PREC_FP16, RFP_PREC_BF16: low-precision factor of
- *     mu D^{-1/2} A D^{-1/2} (D = diag(A); mu = 2^25 for FP16, else 1) with
+ *     mu (D^{-1/2} A D^{-1/2} + c u I) (D = diag(A); mu = 2^25 for FP16,
+ *     else 1; c u as in rfp_set_lowp_shift) with
  *     its bulk updates on operands rounded to fprec (FP32 accumulation), and
  *     FP64 refinement against the untouched FP64 matrix until the normwise
- *     backward error is <= tol (at most max_iter sweeps; a sweep that fails to
- *     halve it counts as stalled); on failure the FP64 factor and solve run
- *     on arf.
+ *     backward error is <= tol, with the sweeps of rfp_dpfsv_ir (classical,
+ *     then 8 preconditioned conjugate-gradient steps in FP64 once a sweep
+ *     fails to cut the backward error fourfold; stalled when such a sweep
+ *     fails to cut it below 0.9 times the previous one; at most max_iter
+ *     sweeps); on failure the FP64 factor and solve run on arf.
  * With do_pftri != 0, arf ends as the RFP array of A^{-1} (PFTRI after an
  * FP64 factor, in every mode).  Device outputs per system: info[i] = 0 or the
  * FP64 PFTRF INFO (first non-positive pivot, 1-based), -1 for a refused

@@ -68,7 +68,7 @@ def _declare(L):
     L.orc_norm_max.restype = ctypes.c_double
     L.orc_norm_fro.argtypes = [_chr, _chr, _i64, _dp]
     L.orc_norm_fro.restype = ctypes.c_double
-    L.orc_pfcast_s.argtypes = [_chr, _chr, _i64, _dp, ctypes.c_int, ctypes.c_double, _dp, _vp]
+    L.orc_pfcast_s.argtypes = [_chr, _chr, _i64, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _vp]
     L.orc_backward_error.argtypes = [_chr, _chr, _i64, _i64, _dp, _dp, _i64, _dp, _i64]
     L.orc_tftri.restype = ctypes.c_int
     L.orc_tftri.argtypes = [_chr, _chr, _chr, _i64, _dp]
@@ -201,12 +201,13 @@ def norm_fro(transr, uplo, n, arf):
     return lib().orc_norm_fro(_c(transr), _c(uplo), n, _p(arf))
 
 
-def pfcast_s(transr, uplo, n, arf, scale=True, mu=1.0):
-    """(s, arf32): diagonal scaling vector and the scaled FP32 RFP copy."""
+def pfcast_s(transr, uplo, n, arf, scale=True, mu=1.0, shift=0.0):
+    """(s, arf32): diagonal scaling vector and the scaled (and diagonally
+    shifted) FP32 RFP copy."""
     arf = np.ascontiguousarray(arf, dtype=np.float64)
     s = np.empty(n)
     out = np.zeros(arf.size, dtype=np.float32)
-    lib().orc_pfcast_s(_c(transr), _c(uplo), n, _p(arf), 1 if scale else 0, float(mu), _p(s),
+    lib().orc_pfcast_s(_c(transr), _c(uplo), n, _p(arf), 1 if scale else 0, float(mu), float(shift), _p(s),
                        out.ctypes.data_as(_vp))
     return s, out
 

@@ -437,11 +437,14 @@ double orc_norm_fro(char transr, char uplo, i64 n, const double *arf)
 
 /* Scaled cast of the mixed-precision solve (not part of the paper; the
  * scaling D^{-1/2} A D^{-1/2} with D = diag(A) is the classical symmetric
- * equilibration): s_i = 1 / sqrt(a_ii) when scale is set (NaN for a
- * non-positive a_ii), else 1; then every stored entry becomes
- * (float)(((a_ij * s_i) * s_j) * mu) with i >= j, each product rounded in
+ * equilibration, the diagonal shift that of Higham and Pranesh's
+ * low-precision Cholesky, SIAM J. Sci. Comput. 43 (2021)): s_i = 1 / sqrt(a_ii)
+ * when scale is set (NaN for a non-positive a_ii), else 1; then every stored
+ * entry becomes (float)(((a_ij * s_i) * s_j) * mu) with i > j, and a diagonal
+ * one (float)((((a_ii * s_i) * s_i) + shift) * mu), each operation rounded in
  * binary64 in that order. */
-void orc_pfcast_s(char transr, char uplo, i64 n, const double *arf, int scale, double mu, double *s, float *out)
+void orc_pfcast_s(char transr, char uplo, i64 n, const double *arf, int scale, double mu, double shift, double *s,
+                  float *out)
 {
     for (i64 i = 0; i < n; i++) {
         double d = sym_at(transr, uplo, n, arf, i, i);
@@ -452,6 +455,7 @@ void orc_pfcast_s(char transr, char uplo, i64 n, const double *arf, int scale, d
             i64 p = orc_rfp_pos(transr, uplo, n, i, j);
             double v = arf[p] * s[i];
             v = v * s[j];
+            if (i == j) v = v + shift;
             v = v * mu;
             out[p] = (float)v;
         }

@@ -60,7 +60,9 @@ _SIGS = {
     "rfp_spftrs": [_vp, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp],
     "rfp_spftri": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_spftrf_mp": [_vp, _int, _chr, _chr, _i64, _vp, _vp, _vp],
-    "rfp_dpfcast_s": [_vp, _chr, _chr, _i64, _vp, _int, ctypes.c_double, _vp, _vp, _vp],
+    "rfp_dpfcast_s": [_vp, _chr, _chr, _i64, _vp, _int, ctypes.c_double, ctypes.c_double, _vp, _vp, _vp],
+    "rfp_set_lowp_shift": [_vp, _int, ctypes.c_double],
+    "rfp_get_lowp_shift": [_vp, _int, _vp],
     "rfp_dlansf": [_vp, _chr, _chr, _chr, _i64, _vp, _vp, _vp],
     "rfp_autotune": [_vp, _i64, _i64, _int, _vp],
     "rfp_tune_count": [_vp],
@@ -343,9 +345,21 @@ def rfp_spftrf_mp(h, fprec, transr, uplo, n, arf, info, stream=None):
                                                 _stream(stream)))
 
 
-def rfp_dpfcast_s(h, transr, uplo, n, arf, scale, mu, s, arf32, stream=None):
+def rfp_dpfcast_s(h, transr, uplo, n, arf, scale, mu, s, arf32, shift=0.0, stream=None):
     _check("rfp_dpfcast_s", lib().rfp_dpfcast_s(h.value, _c(transr), _c(uplo), n, _ptr(arf), int(scale), float(mu),
-                                                _ptr(s), _ptr(arf32), _stream(stream)))
+                                                float(shift), _ptr(s), _ptr(arf32), _stream(stream)))
+
+
+def rfp_set_lowp_shift(h, fprec, c):
+    """Diagonal shift of the fprec low-precision factors, in units of that
+    precision's unit roundoff (0 switches it off)."""
+    _check("rfp_set_lowp_shift", lib().rfp_set_lowp_shift(h.value, int(fprec), float(c)))
+
+
+def rfp_get_lowp_shift(h, fprec):
+    out = ctypes.c_double()
+    _check("rfp_get_lowp_shift", lib().rfp_get_lowp_shift(h.value, int(fprec), ctypes.byref(out)))
+    return out.value
 
 
 def rfp_dlansf(h, norm, transr, uplo, n, arf, out, stream=None):

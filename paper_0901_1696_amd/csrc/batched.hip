@@ -63,10 +63,15 @@ constexpr double MU_FP16 = 33554432.0;  // 2^25, as in the single-system refinem
 // global memory (L2-resident for these sizes) under band masks; all products
 // are formed in registers first and stored after a barrier, so C may alias A
 // or B in any way.  Only i >= j is written when c_lower.  LPR rounds both
-// operands to FP16 (1) or BF16 (2) before the FP32 products.
-template <typename T, int NCB, int LPR = 0>
-__device__ void wg_mm(int m, int n, int k, T alpha, Mat<const T> A, int triA, Mat<const T> B, int triB, T beta,
-                      Mat<T> C, bool c_lower)
+// operands to FP16 (1) or BF16 (2) before the FP32 products.  A may be held
+// in a narrower type TA than the arithmetic (FP32 factors in FP64 products).
+template <typename X>
+struct NoDeduce {
+    typedef X type;
+};
+template <typename T, int NCB, int LPR = 0, typename TA = T>
+__device__ void wg_mm(int m, int n, int k, T alpha, Mat<const typename NoDeduce<TA>::type> A, int triA,
+                      Mat<const T> B, int triB, T beta, Mat<T> C, bool c_lower)
 {
     typedef typename M16<T>::acc acc_t;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -97,7 +102,7 @@ __device__ void wg_mm(int m, int n, int k, T alpha, Mat<const T> A, int triA, Ma
         for (int kk = 0; kk < k; kk += 4) {
             const int ka = kk + g;
             const int64_t da = ka - i;
-            const T av = (i < m && ka < k && da >= alo && da <= ahi) ? tile::lp_round<LPR>(A.at(i, ka)) : T(0);
+            const T av = (i < m && ka < k && da >= alo && da <= ahi) ? tile::lp_round<LPR>((T)A.at(i, ka)) : T(0);
 #pragma unroll
             for (int c = 0; c < NCB; c++) {
                 if (c >= ncb) break;
@@ -139,6 +144,8 @@ struct WgScratch {
     double *sv;               // diagonal scaling (NMAX)
     double *xv, *rv;          // refinement solution and residual (NMAX x RC, column-major)
     float* rf;                // FP32 correction (NMAX x RC)
+    double *pv, *qv;          // conjugate-gradient direction and its product with A (NMAX x RC)
+    double* rz;               // conjugate-gradient r . z per column (RC)
 };
 
 __host__ __device__ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -146,8 +153,8 @@ __host__ __device__ inline size_t align256(size_t b) { return (b + 255) & ~(size
 __host__ __device__ inline size_t wg_scratch_bytes()
 {
     return 2 * align256(sizeof(double) * BN * BN) + 5 * align256(sizeof(float) * BN * BN) +
-           align256(sizeof(double) * NMAX) + 2 * align256(sizeof(double) * NMAX * RC) +
-           align256(sizeof(float) * NMAX * RC);
+           align256(sizeof(double) * NMAX) + 4 * align256(sizeof(double) * NMAX * RC) +
+           align256(sizeof(float) * NMAX * RC) + align256(sizeof(double) * RC);
 }
 
 __device__ WgScratch wg_scratch(char* base)
@@ -170,6 +177,9 @@ __device__ WgScratch wg_scratch(char* base)
     s.xv = (double*)take(sizeof(double) * NMAX * RC);
     s.rv = (double*)take(sizeof(double) * NMAX * RC);
     s.rf = (float*)take(sizeof(float) * NMAX * RC);
+    s.pv = (double*)take(sizeof(double) * NMAX * RC);
+    s.qv = (double*)take(sizeof(double) * NMAX * RC);
+    s.rz = (double*)take(sizeof(double) * RC);
     return s;
 }
 
@@ -214,20 +224,22 @@ __device__ int factor64(BatchSmem& sm, const RfpView<double>& v, const WgScratch
 
 // X = A^{-1} B on an r-column slab B (rows m1 + m2, column-major, ld), with
 // the factor's inverses W1, W2 and L21 = S (Figure 4's solution steps with
-// the triangular solves done by the inverses).
-template <typename T>
-__device__ void solve_slab(int m1, int m2, Mat<const T> s, const T* w1, const T* w2, T* b, int64_t ld, int r)
+// the triangular solves done by the inverses).  The factor may be held in a
+// narrower type TF than the arithmetic T.
+template <typename T, typename TF = T>
+__device__ void solve_slab(int m1, int m2, Mat<const typename NoDeduce<TF>::type> s, const TF* w1, const TF* w2, T* b,
+                           int64_t ld, int r)
 {
     Mat<T> B1{b, 1, ld}, B2{b + m1, 1, ld};
-    Mat<const T> W1{w1, BN, 1}, W2{w2, BN, 1};
-    wg_mm<T, 1>(m1, r, m1, T(1), W1, TRI_LOWER, Mat<const T>(B1).tr(), TRI_NONE, T(0), B1, false);
+    Mat<const TF> W1{w1, BN, 1}, W2{w2, BN, 1};
+    wg_mm<T, 1, 0, TF>(m1, r, m1, T(1), W1, TRI_LOWER, Mat<const T>(B1).tr(), TRI_NONE, T(0), B1, false);
     if (m2 > 0) {
-        wg_mm<T, 1>(m2, r, m1, T(-1), s, TRI_NONE, Mat<const T>(B1).tr(), TRI_NONE, T(1), B2, false);
-        wg_mm<T, 1>(m2, r, m2, T(1), W2, TRI_LOWER, Mat<const T>(B2).tr(), TRI_NONE, T(0), B2, false);
-        wg_mm<T, 1>(m2, r, m2, T(1), W2.tr(), TRI_UPPER, Mat<const T>(B2).tr(), TRI_NONE, T(0), B2, false);
-        wg_mm<T, 1>(m1, r, m2, T(-1), s.tr(), TRI_NONE, Mat<const T>(B2).tr(), TRI_NONE, T(1), B1, false);
+        wg_mm<T, 1, 0, TF>(m2, r, m1, T(-1), s, TRI_NONE, Mat<const T>(B1).tr(), TRI_NONE, T(1), B2, false);
+        wg_mm<T, 1, 0, TF>(m2, r, m2, T(1), W2, TRI_LOWER, Mat<const T>(B2).tr(), TRI_NONE, T(0), B2, false);
+        wg_mm<T, 1, 0, TF>(m2, r, m2, T(1), W2.tr(), TRI_UPPER, Mat<const T>(B2).tr(), TRI_NONE, T(0), B2, false);
+        wg_mm<T, 1, 0, TF>(m1, r, m2, T(-1), s.tr(), TRI_NONE, Mat<const T>(B2).tr(), TRI_NONE, T(1), B1, false);
     }
-    wg_mm<T, 1>(m1, r, m1, T(1), W1.tr(), TRI_UPPER, Mat<const T>(B1).tr(), TRI_NONE, T(0), B1, false);
+    wg_mm<T, 1, 0, TF>(m1, r, m1, T(1), W1.tr(), TRI_UPPER, Mat<const T>(B1).tr(), TRI_NONE, T(0), B1, false);
 }
 
 // A^{-1} in place from the FP64 factor (Section 5): W21 = -W22 L21 W11 into
@@ -265,6 +277,29 @@ __device__ double wg_max(double v, double* red)
     return out;
 }
 
+// sum over the block's threads (same reduction tree as wg_max)
+__device__ double wg_sum(double v, double* red)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double out = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return out;
+}
+
+// Refinement: sweeps apply M^{-1} once (classical refinement) until one
+// fails to cut the backward error fourfold; later sweeps run PCG_STEPS steps
+// of preconditioned conjugate gradients in FP64, one recurrence continued
+// from sweep to sweep with the true residual replacing the recursive one at
+// each sweep's start; the refinement stalls after IR_STALE_SWEEPS such
+// sweeps in a row that fail to bring the backward error below 0.9 times its
+// best value (conjugate gradients minimise the error's A-norm, so the
+// residual need not fall every sweep).
+constexpr int PCG_STEPS = 8;
+
 // normwise backward error of one column from its maxima (NaN anywhere: NaN)
 __device__ __forceinline__ double col_eta(double rm, double xm, double bm, double anorm)
 {
@@ -290,16 +325,24 @@ struct SysState {
     int flags;
     int info, code;   // FP64 INFO; refinement sweeps or fall-back reason
     int cfail;        // first right-hand side left to the FP64 solve
-    int jump;         // refinement: local level that follows setup / a decision
+    int jump;         // refinement: local level that follows setup, a decision or a CG update
     int sweep;        // refinement: sweeps done
+    int pcg;          // refinement: sweeps run conjugate gradients
+    int cgstep;       // refinement: conjugate-gradient steps of the current sweep
+    int cgcont;       // refinement: the conjugate-gradient recurrence has started
+    int stale;        // refinement: conjugate-gradient sweeps in a row without a new best
+    double best;      // refinement: best backward error since the switch to conjugate gradients
     double prev;      // refinement: previous backward error
     double anorm;     // refinement: ||A||_inf
 };
 
 // Stages of a tiled system, in order.
 enum { ST_CAST = 0, ST_LPFAC, ST_IR, ST_F64FAC, ST_SOLVE, ST_TRTRI, ST_LAUUM, ST_END };
-// refinement stage, local levels: 0 setup, then per sweep 1 solve, 2 residual, 3 decision
-enum { IR_SETUP = 0, IR_SOLVE = 1, IR_RESID = 2, IR_DECIDE = 3, IR_LEVELS = 4 };
+// refinement stage, local levels: 0 setup; a classical sweep is 1 solve,
+// 2 residual, 3 decision; a conjugate-gradient sweep repeats 4 (z = M^{-1} r,
+// new direction p), 5 (q = A p, one task per block row), 6 (update of x and
+// r), then 2 and 3
+enum { IR_SETUP = 0, IR_SOLVE = 1, IR_RESID = 2, IR_DECIDE = 3, CG_Z = 4, CG_Q = 5, CG_UPD = 6, IR_LEVELS = 7 };
 
 struct BatchArgs {
     const rfp_sys_t* sys;
@@ -309,6 +352,7 @@ struct BatchArgs {
     int mode;       // 0 FP64; 1 FP32, 2 FP16, 3 BF16 factor + FP64 refinement
     int pftri;
     double tol;
+    double shift;   // added to the unit diagonal of the scaled matrix before the low-precision factor
     int max_iter;
     int* info;
     int* iter;
@@ -370,7 +414,7 @@ __host__ __device__ inline int64_t level_tasks(int stage, int64_t loc, int nb)
             const int64_t k = loc / 3, sub = loc % 3, rest = nb - 1 - k;
             return sub == 0 ? 1 : sub == 1 ? rest : rest * (rest + 1) / 2;
         }
-        case ST_IR: return loc == IR_RESID ? nb : 1;
+        case ST_IR: return (loc == IR_RESID || loc == CG_Q) ? nb : 1;
         case ST_SOLVE: return 1;
         case ST_TRTRI: {
             if (loc == 0) return nb;
@@ -395,6 +439,8 @@ struct TileScratch {
     double* rs;      // row sums of |A| (n)
     double *xv, *rv; // refinement solution and residual (n x nrhs, leading dimension n)
     float* rf;       // low-precision correction (n x nrhs)
+    double *pv, *qv; // conjugate-gradient direction and its product with A (n x nrhs)
+    double* rz;      // conjugate-gradient r . z per right-hand side
     double* bm;      // max |b| per right-hand side
     double* tmp;     // inversion: one column of tiles (nb x TB x TB)
     size_t bytes;
@@ -419,6 +465,9 @@ __host__ __device__ inline TileScratch tile_scratch(char* base, int64_t n, int64
     s.xv = mode ? (double*)take(sizeof(double) * n * nr) : nullptr;
     s.rv = mode ? (double*)take(sizeof(double) * n * nr) : nullptr;
     s.rf = mode ? (float*)take(sizeof(float) * n * nr) : nullptr;
+    s.pv = mode ? (double*)take(sizeof(double) * n * nr) : nullptr;
+    s.qv = mode ? (double*)take(sizeof(double) * n * nr) : nullptr;
+    s.rz = mode ? (double*)take(sizeof(double) * nr) : nullptr;
     s.bm = mode ? (double*)take(sizeof(double) * nr) : nullptr;
     s.tmp = pftri ? (double*)take(sizeof(double) * nb * t2) : nullptr;
     s.bytes = o;
@@ -449,11 +498,14 @@ __host__ __device__ inline SysPlan plan_of(const rfp_sys_t& sd, int mode, int pf
     p.bytes = (int64_t)tile_scratch(nullptr, sd.n, sd.nrhs, nb, mode, pftri).bytes;
     int64_t tasks = 0;
     for (int s = ST_CAST; s < ST_END; s++) {
-        const int64_t L = stage_levels(s, nb, mode);
-        for (int64_t l = 0; l < L; l++) {
-            const int64_t c = level_tasks(s, l, nb);
-            tasks += (s == ST_IR && l >= IR_SOLVE) ? c * (max_iter > 0 ? max_iter : 1) : c;
+        if (s == ST_IR) {
+            // setup, then per sweep at most PCG_STEPS conjugate-gradient
+            // steps (1 + nb + 1 tasks each), the residual and the decision
+            if (mode) tasks += 1 + (int64_t)(max_iter > 0 ? max_iter : 1) * (PCG_STEPS * (nb + 2) + nb + 1);
+            continue;
         }
+        const int64_t L = stage_levels(s, nb, mode);
+        for (int64_t l = 0; l < L; l++) tasks += level_tasks(s, l, nb);
     }
     p.tasks = tasks;
     return p;
@@ -521,6 +573,105 @@ __device__ __forceinline__ void release() { __builtin_amdgcn_fence(__ATOMIC_RELE
 __device__ __forceinline__ void acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 // --------------------------------------------------------- one-task systems
+// R (m1 + m2 rows, r <= RC columns, leading dimension NMAX) += alpha A X, A
+// the system's FP64 matrix through its lower views, its strict upper
+// triangle mirrored.
+__device__ void small_symm(const RfpView<double>& v, const double* x, double* rr, int r, double alpha)
+{
+    const int m1 = (int)v.m1, m2 = (int)v.m2;
+    Mat<const double> X1{x, 1, NMAX}, X2{x + m1, 1, NMAX};
+    Mat<double> R1{rr, 1, NMAX}, R2{rr + m1, 1, NMAX};
+    wg_mm<double, 1>(m1, r, m1, alpha, v.t1, TRI_LOWER, X1.tr(), TRI_NONE, 1.0, R1, false);
+    wg_mm<double, 1>(m1, r, m1, alpha, Mat<const double>(v.t1).tr(), TRI_SUPPER, X1.tr(), TRI_NONE, 1.0, R1, false);
+    if (m2 > 0) {
+        wg_mm<double, 1>(m1, r, m2, alpha, Mat<const double>(v.s).tr(), TRI_NONE, X2.tr(), TRI_NONE, 1.0, R1, false);
+        wg_mm<double, 1>(m2, r, m1, alpha, v.s, TRI_NONE, X1.tr(), TRI_NONE, 1.0, R2, false);
+        wg_mm<double, 1>(m2, r, m2, alpha, v.t2, TRI_LOWER, X2.tr(), TRI_NONE, 1.0, R2, false);
+        wg_mm<double, 1>(m2, r, m2, alpha, Mat<const double>(v.t2).tr(), TRI_SUPPER, X2.tr(), TRI_NONE, 1.0, R2,
+                         false);
+    }
+}
+
+// z = mu D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2} r on an r-column slab (leading
+// dimension NMAX): the low-precision preconditioner, solved with the factor's
+// FP32 values and inverses, in FP32 (added into z when add) or, for the
+// conjugate-gradient steps, in FP64 (so that the operator it applies is
+// symmetric to FP64 rounding: an FP32 solve's rounding would swamp the small
+// eigenvalues of the preconditioned matrix of an ill-conditioned system).
+__device__ void small_prec(int n, int m1, int m2, Mat<const float> FS, const WgScratch& ws, const double* rin,
+                           double* z, int r, double mu, bool add, bool fp64 = false)
+{
+    const int t = threadIdx.x;
+    if (fp64) {
+        for (int idx = t; idx < n * RC; idx += 256) {
+            const int i = idx % n, c = idx / n;
+            z[i + c * NMAX] = ws.sv[i] * rin[i + c * NMAX];
+        }
+        __syncthreads();
+        solve_slab<double, float>(m1, m2, FS, ws.w1f, ws.w2f, z, NMAX, r);
+        for (int idx = t; idx < n * RC; idx += 256) {
+            const int i = idx % n, c = idx / n;
+            z[i + c * NMAX] = (z[i + c * NMAX] * ws.sv[i]) * mu;
+        }
+        __syncthreads();
+        return;
+    }
+    for (int idx = t; idx < n * RC; idx += 256) {
+        const int i = idx % n, c = idx / n;
+        ws.rf[i + c * NMAX] = (float)(ws.sv[i] * rin[i + c * NMAX]);
+    }
+    __syncthreads();
+    solve_slab<float>(m1, m2, FS, ws.w1f, ws.w2f, ws.rf, NMAX, r);
+    for (int idx = t; idx < n * RC; idx += 256) {
+        const int i = idx % n, c = idx / n;
+        const double d = ((double)ws.rf[i + c * NMAX] * ws.sv[i]) * mu;
+        z[i + c * NMAX] = add ? z[i + c * NMAX] + d : d;
+    }
+    __syncthreads();
+}
+
+// PCG_STEPS steps of preconditioned conjugate gradients on A x = b (FP64
+// throughout) from the true residual r of x (in ws.rv, updated to the
+// recursive residual), x in ws.xv; the recurrence starts (p = z) unless cont,
+// when it continues the previous sweep's (p = z + beta p).
+__device__ void small_pcg(const RfpView<double>& v, Mat<const float> FS, const WgScratch& ws, int r, double mu,
+                          double* red, bool cont)
+{
+    const int t = threadIdx.x, m1 = (int)v.m1, m2 = (int)v.m2, n = m1 + m2;
+    for (int k = 0; k < PCG_STEPS; k++) {
+        small_prec(n, m1, m2, FS, ws, ws.rv, ws.qv, r, mu, false, true);  // z into qv
+        const bool first = k == 0 && !cont;
+        for (int c = 0; c < r; c++) {
+            double s = 0.0;
+            for (int i = t; i < n; i += 256) s += ws.rv[i + c * NMAX] * ws.qv[i + c * NMAX];
+            s = wg_sum(s, red);
+            const double rz = ws.rz[c];
+            const double beta = (!first && rz != 0.0) ? s / rz : 0.0;
+            for (int i = t; i < n; i += 256) {
+                const int o = i + c * NMAX;
+                ws.pv[o] = first ? ws.qv[o] : ws.qv[o] + beta * ws.pv[o];
+            }
+            __syncthreads();
+            if (t == 0) ws.rz[c] = s;
+        }
+        for (int idx = t; idx < n * RC; idx += 256) ws.qv[idx % n + (idx / n) * NMAX] = 0.0;
+        __syncthreads();
+        small_symm(v, ws.pv, ws.qv, r, 1.0);  // q = A p
+        for (int c = 0; c < r; c++) {
+            double s = 0.0;
+            for (int i = t; i < n; i += 256) s += ws.pv[i + c * NMAX] * ws.qv[i + c * NMAX];
+            s = wg_sum(s, red);
+            const double al = s != 0.0 ? ws.rz[c] / s : 0.0;
+            for (int i = t; i < n; i += 256) {
+                const int o = i + c * NMAX;
+                ws.xv[o] += al * ws.pv[o];
+                ws.rv[o] -= al * ws.qv[o];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Everything for a system with n <= 256 in this workgroup.
 __device__ __attribute__((noinline)) void small_system(const BatchArgs& a, int64_t id, BatchSmem& sm, double* red, const WgScratch& ws)
 {
@@ -547,8 +698,9 @@ __device__ __attribute__((noinline)) void small_system(const BatchArgs& a, int64
         for (int idx = t; idx < BN * BN; idx += 256) {
             const int i = idx % BN, j = idx / BN;
             float f;
+            const double dg = i == j ? a.shift : 0.0;
             if (i < m1 && j <= i) {
-                ws.f1[idx] = f = (float)(((v.t1.at(i, j) * ws.sv[i]) * ws.sv[j]) * mu);
+                ws.f1[idx] = f = (float)((((v.t1.at(i, j) * ws.sv[i]) * ws.sv[j]) + dg) * mu);
                 nonfinite |= !__builtin_isfinite(f);
             }
             if (i < m2 && j < m1) {
@@ -556,7 +708,7 @@ __device__ __attribute__((noinline)) void small_system(const BatchArgs& a, int64
                 nonfinite |= !__builtin_isfinite(f);
             }
             if (i < m2 && j <= i) {
-                ws.f2[idx] = f = (float)(((v.t2.at(i, j) * ws.sv[m1 + i]) * ws.sv[m1 + j]) * mu);
+                ws.f2[idx] = f = (float)((((v.t2.at(i, j) * ws.sv[m1 + i]) * ws.sv[m1 + j]) + dg) * mu);
                 nonfinite |= !__builtin_isfinite(f);
             }
         }
@@ -598,39 +750,19 @@ __device__ __attribute__((noinline)) void small_system(const BatchArgs& a, int64
                     ws.rv[i + c * NMAX] = bv;
                 }
                 __syncthreads();
-                double prev = 0.0;
-                int done = -1;
+                double prev = 0.0, best = 0.0;
+                int done = -1, stale = 0, pcg_sweeps = 0;
+                bool pcg = false;
                 for (int it = 1; it <= a.max_iter; it++) {
-                    for (int idx = t; idx < n * RC; idx += 256) {
-                        const int i = idx % n, c = idx / n;
-                        ws.rf[i + c * NMAX] = (float)(ws.sv[i] * ws.rv[i + c * NMAX]);
-                    }
-                    __syncthreads();
-                    solve_slab<float>(m1, m2, FS, ws.w1f, ws.w2f, ws.rf, NMAX, r);
-                    for (int idx = t; idx < n * RC; idx += 256) {
-                        const int i = idx % n, c = idx / n;
-                        ws.xv[i + c * NMAX] += ((double)ws.rf[i + c * NMAX] * ws.sv[i]) * mu;
-                    }
-                    __syncthreads();
+                    if (pcg) small_pcg(v, FS, ws, r, mu, red, pcg_sweeps++ > 0);
+                    else small_prec(n, m1, m2, FS, ws, ws.rv, ws.xv, r, mu, true);
                     // r = b - A x in FP64 from the untouched RFP matrix
                     for (int idx = t; idx < n * RC; idx += 256) {
                         const int i = idx % n, c = idx / n;
                         ws.rv[i + c * NMAX] = c < r ? bb[i + c * sd.ldb] : 0.0;
                     }
                     __syncthreads();
-                    Mat<const double> X1{ws.xv, 1, NMAX}, X2{ws.xv + m1, 1, NMAX};
-                    Mat<double> R1{ws.rv, 1, NMAX}, R2{ws.rv + m1, 1, NMAX};
-                    wg_mm<double, 1>(m1, r, m1, -1.0, v.t1, TRI_LOWER, X1.tr(), TRI_NONE, 1.0, R1, false);
-                    wg_mm<double, 1>(m1, r, m1, -1.0, Mat<const double>(v.t1).tr(), TRI_SUPPER, X1.tr(), TRI_NONE,
-                                     1.0, R1, false);
-                    if (m2 > 0) {
-                        wg_mm<double, 1>(m1, r, m2, -1.0, Mat<const double>(v.s).tr(), TRI_NONE, X2.tr(), TRI_NONE,
-                                         1.0, R1, false);
-                        wg_mm<double, 1>(m2, r, m1, -1.0, v.s, TRI_NONE, X1.tr(), TRI_NONE, 1.0, R2, false);
-                        wg_mm<double, 1>(m2, r, m2, -1.0, v.t2, TRI_LOWER, X2.tr(), TRI_NONE, 1.0, R2, false);
-                        wg_mm<double, 1>(m2, r, m2, -1.0, Mat<const double>(v.t2).tr(), TRI_SUPPER, X2.tr(),
-                                         TRI_NONE, 1.0, R2, false);
-                    }
+                    small_symm(v, ws.xv, ws.rv, r, -1.0);
                     // normwise backward error, max over the slab's columns
                     double eta = 0.0;
                     for (int c = 0; c < r; c++) {
@@ -649,9 +781,18 @@ __device__ __attribute__((noinline)) void small_system(const BatchArgs& a, int64
                         done = it;
                         break;
                     }
-                    if (it > 1 && !(eta < 0.5 * prev)) {
-                        done = -2;
-                        break;
+                    if (pcg) {
+                        if (eta < 0.9 * best) {
+                            best = eta;
+                            stale = 0;
+                        } else if (++stale >= IR_STALE_SWEEPS) {
+                            done = -2;
+                            break;
+                        }
+                    }
+                    if (it > 1 && !pcg && !(eta < 0.25 * prev)) {
+                        pcg = true;
+                        best = eta < prev ? eta : prev;
                     }
                     prev = eta;
                 }
@@ -781,7 +922,9 @@ __device__ __attribute__((noinline)) void cast_task(const BatchArgs& a, SysState
     for (int e = th; e < TB * TB; e += 256) {
         const int r = rfast ? e % TB : e / TB, c = rfast ? e / TB : e % TB;
         if (r < ci && c < cj && (i != j || r >= c)) {
-            const float f = (float)(((A.at(r, c) * sdiag[r]) * sdiag[TB + c]) * mu);
+            double v = (A.at(r, c) * sdiag[r]) * sdiag[TB + c];
+            if (i == j && r == c) v = v + a.shift;
+            const float f = (float)(v * mu);
             L.at(r, c) = f;
             bad |= !__builtin_isfinite(f);
         }
@@ -791,34 +934,102 @@ __device__ __attribute__((noinline)) void cast_task(const BatchArgs& a, SysState
 }
 
 // Forward (L Y = B) then backward (L^T X = Y) substitution over the block
-// rows with the tile inverses, on an n x r slab (column-major, ld).
-template <typename T>
+// rows with the tile inverses, on an n x r slab (column-major, ld): with the
+// FP64 tiles (T = double, LPT false) or the low-precision tiles (LPT), in
+// FP32 or FP64 arithmetic.
+template <typename T, bool LPT>
 __device__ void tile_solve(const Tiles& tl, const TileScratch& ts, T* b, int64_t ld, int r)
 {
+    // TF: the factor's storage (the low-precision tiles for an FP32 solve or
+    // an FP64 solve with FP32 tiles, else the FP64 array)
+    typedef typename std::conditional<LPT, float, T>::type TF;
     const int nb = tl.nb;
-    T* w;
-    if constexpr (sizeof(T) == 4) w = ts.w32;
+    TF* w;
+    if constexpr (LPT) w = ts.w32;
     else w = ts.w64;
-    auto tileT = [&](int i, int j) -> Mat<const T> {
-        if constexpr (sizeof(T) == 4) return lp_tile(ts, i, j);
+    auto tileT = [&](int i, int j) -> Mat<const TF> {
+        if constexpr (LPT) return lp_tile(ts, i, j);
         else return tl.t64(i, j);
     };
     auto slab = [&](int k) { return Mat<T>{b + tl.r0(k), 1, ld}; };
     for (int k = 0; k < nb; k++) {
         const Mat<T> Bk = slab(k);
         for (int j = 0; j < k; j++)
-            wg_mm<T, 1>(tl.cnt(k), r, tl.cnt(j), T(-1), tileT(k, j), TRI_NONE, Mat<const T>(slab(j)).tr(), TRI_NONE,
-                        T(1), Bk, false);
-        wg_mm<T, 1>(tl.cnt(k), r, tl.cnt(k), T(1), diag_inv(w, k), TRI_LOWER, Mat<const T>(Bk).tr(), TRI_NONE, T(0),
-                    Bk, false);
+            wg_mm<T, 1, 0, TF>(tl.cnt(k), r, tl.cnt(j), T(-1), tileT(k, j), TRI_NONE, Mat<const T>(slab(j)).tr(),
+                               TRI_NONE, T(1), Bk, false);
+        wg_mm<T, 1, 0, TF>(tl.cnt(k), r, tl.cnt(k), T(1), diag_inv(w, k), TRI_LOWER, Mat<const T>(Bk).tr(), TRI_NONE,
+                           T(0), Bk, false);
     }
     for (int k = nb - 1; k >= 0; k--) {
         const Mat<T> Bk = slab(k);
         for (int j = k + 1; j < nb; j++)
-            wg_mm<T, 1>(tl.cnt(k), r, tl.cnt(j), T(-1), tileT(j, k).tr(), TRI_NONE, Mat<const T>(slab(j)).tr(),
-                        TRI_NONE, T(1), Bk, false);
-        wg_mm<T, 1>(tl.cnt(k), r, tl.cnt(k), T(1), Mat<const T>(diag_inv(w, k)).tr(), TRI_UPPER,
-                    Mat<const T>(Bk).tr(), TRI_NONE, T(0), Bk, false);
+            wg_mm<T, 1, 0, TF>(tl.cnt(k), r, tl.cnt(j), T(-1), tileT(j, k).tr(), TRI_NONE,
+                               Mat<const T>(slab(j)).tr(), TRI_NONE, T(1), Bk, false);
+        wg_mm<T, 1, 0, TF>(tl.cnt(k), r, tl.cnt(k), T(1), Mat<const TF>(diag_inv(w, k)).tr(), TRI_UPPER,
+                           Mat<const T>(Bk).tr(), TRI_NONE, T(0), Bk, false);
+    }
+}
+
+// Block row i of R += alpha A X (n x nrhs pairs, leading dimension n): the
+// tiles (i, j), j <= i, and the mirrored (j, i)^T, j > i, of the FP64 array.
+__device__ void rowblock_symm(const Tiles& tl, int i, const double* x, double* rr, int64_t n, int64_t nrhs,
+                              double alpha)
+{
+    const int ci = tl.cnt(i);
+    for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
+        const int r = (int)(nrhs - c0 < RC ? nrhs - c0 : RC);
+        const Mat<double> R{rr + tl.r0(i) + c0 * n, 1, n};
+        for (int j = 0; j < tl.nb; j++) {
+            const Mat<const double> X{x + tl.r0(j) + c0 * n, 1, n};
+            if (j < i) {
+                wg_mm<double, 1>(ci, r, tl.cnt(j), alpha, tl.t64(i, j), TRI_NONE, X.tr(), TRI_NONE, 1.0, R, false);
+            } else if (j == i) {
+                wg_mm<double, 1>(ci, r, ci, alpha, tl.t64(i, i), TRI_LOWER, X.tr(), TRI_NONE, 1.0, R, false);
+                wg_mm<double, 1>(ci, r, ci, alpha, Mat<const double>(tl.t64(i, i)).tr(), TRI_SUPPER, X.tr(),
+                                 TRI_NONE, 1.0, R, false);
+            } else {
+                wg_mm<double, 1>(ci, r, tl.cnt(j), alpha, Mat<const double>(tl.t64(j, i)).tr(), TRI_NONE, X.tr(),
+                                 TRI_NONE, 1.0, R, false);
+            }
+        }
+    }
+}
+
+// z = mu D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2} r over all right-hand sides (the
+// low-precision preconditioner, solved with the FP32 tiles and tile
+// inverses), in FP32 into z or added into it, or (fp64, for the
+// conjugate-gradient steps) in FP64 arithmetic, which keeps the operator it
+// applies symmetric to FP64 rounding.
+__device__ void tile_prec(const BatchArgs& a, const Tiles& tl, const TileScratch& ts, int64_t n, int64_t nrhs,
+                          const double* rin, double* z, bool add, bool fp64 = false)
+{
+    const int th = threadIdx.x;
+    const double mu = a.mode == 2 ? MU_FP16 : 1.0;
+    if (fp64) {
+        for (int64_t e = th; e < n * nrhs; e += 256) z[e] = ts.sv[e % n] * rin[e];
+        __syncthreads();
+        for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
+            const int r = (int)(nrhs - c0 < RC ? nrhs - c0 : RC);
+            tile_solve<double, true>(tl, ts, z + c0 * n, n, r);
+        }
+        for (int64_t e = th; e < n * nrhs; e += 256) z[e] = (z[e] * ts.sv[e % n]) * mu;
+        __syncthreads();
+        return;
+    }
+    for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
+        const int r = (int)(nrhs - c0 < RC ? nrhs - c0 : RC);
+        for (int64_t e = th; e < n * r; e += 256) {
+            const int64_t i = e % n, c = c0 + e / n;
+            ts.rf[i + c * n] = (float)(ts.sv[i] * rin[i + c * n]);
+        }
+        __syncthreads();
+        tile_solve<float, true>(tl, ts, ts.rf + c0 * n, n, r);
+        for (int64_t e = th; e < n * r; e += 256) {
+            const int64_t i = e % n, c = c0 + e / n;
+            const double d = ((double)ts.rf[i + c * n] * ts.sv[i]) * mu;
+            z[i + c * n] = add ? z[i + c * n] + d : d;
+        }
+        __syncthreads();
     }
 }
 
@@ -828,7 +1039,6 @@ __device__ __attribute__((noinline)) void ir_task(const BatchArgs& a, SysState& 
 {
     const int th = threadIdx.x;
     const int64_t n = sd.n, nrhs = sd.nrhs;
-    const double mu = a.mode == 2 ? MU_FP16 : 1.0;
     double* b = a.b + sd.b_off;
     if (loc == IR_SETUP) {
         if (S.flags & (F_LPFAIL | F_NONFINITE)) {
@@ -885,6 +1095,11 @@ __device__ __attribute__((noinline)) void ir_task(const BatchArgs& a, SysState& 
         if (th == 0) {
             S.anorm = m;
             S.sweep = 0;
+            S.pcg = 0;
+            S.cgstep = 0;
+            S.cgcont = 0;
+            S.stale = 0;
+            S.best = 0.0;
             S.prev = 0.0;
             S.code = 0;
             S.jump = nrhs > 0 ? IR_SOLVE : IR_LEVELS;
@@ -892,49 +1107,70 @@ __device__ __attribute__((noinline)) void ir_task(const BatchArgs& a, SysState& 
         return;
     }
     if (loc == IR_SOLVE) {
-        // x += mu D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2} r, slab by slab
-        for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
-            const int r = (int)(nrhs - c0 < RC ? nrhs - c0 : RC);
-            for (int64_t e = th; e < n * r; e += 256) {
-                const int64_t i = e % n, c = c0 + e / n;
-                ts.rf[i + c * n] = (float)(ts.sv[i] * ts.rv[i + c * n]);
-            }
-            __syncthreads();
-            tile_solve<float>(tl, ts, ts.rf + c0 * n, n, r);
-            for (int64_t e = th; e < n * r; e += 256) {
-                const int64_t i = e % n, c = c0 + e / n;
-                ts.xv[i + c * n] += ((double)ts.rf[i + c * n] * ts.sv[i]) * mu;
-            }
-            __syncthreads();
-        }
+        // x += mu D^{-1/2} (Ls Ls^T)^{-1} D^{-1/2} r
+        tile_prec(a, tl, ts, n, nrhs, ts.rv, ts.xv, true);
         return;
     }
-    if (loc == IR_RESID) {
-        // block row i of r = b - A x: the tiles (i, j), j <= i, and the
-        // mirrored (j, i)^T, j > i, of the FP64 array
+    if (loc == IR_RESID || loc == CG_Q) {
+        // block row i of r = b - A x, or of q = A p
         const int i = (int)t;
         const int ci = tl.cnt(i);
-        for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
-            const int r = (int)(nrhs - c0 < RC ? nrhs - c0 : RC);
-            const Mat<double> R{ts.rv + tl.r0(i) + c0 * n, 1, n};
-            for (int e = th; e < ci * r; e += 256) {
-                const int q = e % ci, c = e / ci;
-                R.at(q, c) = b[tl.r0(i) + q + (c0 + c) * sd.ldb];
+        const bool res = loc == IR_RESID;
+        double* out = res ? ts.rv : ts.qv;
+        for (int64_t e = th; e < ci * nrhs; e += 256) {
+            const int64_t q = e % ci, c = e / ci;
+            out[tl.r0(i) + q + c * n] = res ? b[tl.r0(i) + q + c * sd.ldb] : 0.0;
+        }
+        __syncthreads();
+        rowblock_symm(tl, i, res ? ts.xv : ts.pv, out, n, nrhs, res ? -1.0 : 1.0);
+        return;
+    }
+    if (loc == CG_Z) {
+        // z = M^{-1} r into q's storage; rz' = r . z; p = z + (rz' / rz) p
+        // (p = z when the recurrence starts)
+        tile_prec(a, tl, ts, n, nrhs, ts.rv, ts.qv, false, true);
+        const bool first = S.cgcont == 0;
+        for (int64_t c = 0; c < nrhs; c++) {
+            double s = 0.0;
+            for (int64_t i = th; i < n; i += 256) s += ts.rv[i + c * n] * ts.qv[i + c * n];
+            s = wg_sum(s, red);
+            const double rz = ts.rz[c];
+            const double beta = (!first && rz != 0.0) ? s / rz : 0.0;
+            for (int64_t i = th; i < n; i += 256) {
+                const int64_t o = i + c * n;
+                ts.pv[o] = first ? ts.qv[o] : ts.qv[o] + beta * ts.pv[o];
             }
             __syncthreads();
-            for (int j = 0; j < tl.nb; j++) {
-                const Mat<const double> X{ts.xv + tl.r0(j) + c0 * n, 1, n};
-                if (j < i) {
-                    wg_mm<double, 1>(ci, r, tl.cnt(j), -1.0, tl.t64(i, j), TRI_NONE, X.tr(), TRI_NONE, 1.0, R, false);
-                } else if (j == i) {
-                    wg_mm<double, 1>(ci, r, ci, -1.0, tl.t64(i, i), TRI_LOWER, X.tr(), TRI_NONE, 1.0, R, false);
-                    wg_mm<double, 1>(ci, r, ci, -1.0, Mat<const double>(tl.t64(i, i)).tr(), TRI_SUPPER, X.tr(),
-                                     TRI_NONE, 1.0, R, false);
-                } else {
-                    wg_mm<double, 1>(ci, r, tl.cnt(j), -1.0, Mat<const double>(tl.t64(j, i)).tr(), TRI_NONE, X.tr(),
-                                     TRI_NONE, 1.0, R, false);
-                }
+            if (th == 0) ts.rz[c] = s;
+        }
+        if (th == 0) S.cgcont = 1;
+        return;
+    }
+    if (loc == CG_UPD) {
+        // alpha = rz / (p . q); x += alpha p; r -= alpha q (the recursive
+        // residual); a sweep ends after PCG_STEPS steps, or earlier once the
+        // recursive residual meets the tolerance
+        double eta = 0.0;
+        for (int64_t c = 0; c < nrhs; c++) {
+            double s = 0.0;
+            for (int64_t i = th; i < n; i += 256) s += ts.pv[i + c * n] * ts.qv[i + c * n];
+            s = wg_sum(s, red);
+            const double al = s != 0.0 ? ts.rz[c] / s : 0.0;
+            double rm = 0.0, xm = 0.0;
+            for (int64_t i = th; i < n; i += 256) {
+                const int64_t o = i + c * n;
+                ts.xv[o] += al * ts.pv[o];
+                ts.rv[o] -= al * ts.qv[o];
+                rm = nanmax(rm, fabs(ts.rv[o]));
+                xm = nanmax(xm, fabs(ts.xv[o]));
             }
+            rm = wg_max(rm, red);
+            xm = wg_max(xm, red);
+            eta = nanmax(eta, col_eta(rm, xm, ts.bm[c], S.anorm));
+        }
+        if (th == 0) {
+            S.cgstep++;
+            S.jump = (S.cgstep >= PCG_STEPS || eta <= a.tol) ? IR_RESID : CG_Z;
         }
         return;
     }
@@ -951,9 +1187,12 @@ __device__ __attribute__((noinline)) void ir_task(const BatchArgs& a, SysState& 
         eta = nanmax(eta, col_eta(rm, xm, ts.bm[c], S.anorm));
     }
     const int it = S.sweep + 1;
+    const bool swept_pcg = S.pcg != 0;
+    const bool better = eta < 0.9 * S.best;
+    const int stale = swept_pcg ? (better ? 0 : S.stale + 1) : 0;
     int done = 0;  // 1 converged, -1 max_iter, -2 stalled
     if (eta <= a.tol) done = 1;
-    else if (it > 1 && !(eta < 0.5 * S.prev)) done = -2;
+    else if (swept_pcg && stale >= IR_STALE_SWEEPS) done = -2;
     else if (it >= a.max_iter) done = -1;
     if (done == 1) {
         for (int64_t e = th; e < n * nrhs; e += 256) {
@@ -963,6 +1202,7 @@ __device__ __attribute__((noinline)) void ir_task(const BatchArgs& a, SysState& 
     }
     __syncthreads();
     if (th == 0) {
+        const double prev = S.prev;
         S.sweep = it;
         S.prev = eta;
         if (done == 1) {
@@ -974,7 +1214,16 @@ __device__ __attribute__((noinline)) void ir_task(const BatchArgs& a, SysState& 
             S.cfail = 0;
             S.jump = IR_LEVELS;
         } else {
-            S.jump = IR_SOLVE;
+            if (swept_pcg) {
+                S.stale = stale;
+                if (better) S.best = eta;
+            } else if (it > 1 && !(eta < 0.25 * prev)) {
+                S.pcg = 1;
+                S.best = eta < prev ? eta : prev;
+                S.stale = 0;
+            }
+            S.cgstep = 0;
+            S.jump = S.pcg ? CG_Z : IR_SOLVE;
         }
     }
 }
@@ -1067,7 +1316,7 @@ __device__ __attribute__((noinline)) void solve_task(const BatchArgs& a, const S
 {
     for (int64_t c0 = S.cfail; c0 < sd.nrhs; c0 += RC) {
         const int r = (int)(sd.nrhs - c0 < RC ? sd.nrhs - c0 : RC);
-        tile_solve<double>(tl, ts, a.b + sd.b_off + c0 * sd.ldb, sd.ldb, r);
+        tile_solve<double, false>(tl, ts, a.b + sd.b_off + c0 * sd.ldb, sd.ldb, r);
     }
 }
 
@@ -1120,7 +1369,8 @@ __device__ void advance(const BatchArgs& a, int64_t s, SysState& S, const rfp_sy
     int stage;
     int64_t loc;
     int64_t ell = S.level + 1;
-    if (locate(S.level, nb, a.mode, &stage, &loc) && stage == ST_IR && (loc == IR_SETUP || loc == IR_DECIDE))
+    if (locate(S.level, nb, a.mode, &stage, &loc) && stage == ST_IR &&
+        (loc == IR_SETUP || loc == IR_DECIDE || loc == CG_UPD))
         ell = stage_start(ST_IR, nb, a.mode) + S.jump;
     for (;; ell++) {
         if (!locate(ell, nb, a.mode, &stage, &loc)) {
@@ -1180,6 +1430,11 @@ __global__ __launch_bounds__(256) void batched_setup_kernel(BatchArgs a)
             S.cfail = 0;
             S.jump = 0;
             S.sweep = 0;
+            S.pcg = 0;
+            S.cgstep = 0;
+            S.cgcont = 0;
+            S.stale = 0;
+            S.best = 0.0;
             S.prev = 0.0;
             S.anorm = 0.0;
             if (S.kind == K_NONE) {
@@ -1336,12 +1591,12 @@ __global__ __launch_bounds__(256, 1) void batched_kernel(BatchArgs a)
 }
 
 hipError_t batched_solve(const Exec& ex, const rfp_sys_t* sys, int64_t batch, double* arf, double* b, int mode,
-                         int pftri, double tol, int max_iter, int* info, int* iter, char* wgs_mem, int wgs,
-                         char* sysmem, int64_t sysmem_bytes, void* st, unsigned long long* q, int64_t qcap,
+                         int pftri, double tol, double shift, int max_iter, int* info, int* iter, char* wgs_mem,
+                         int wgs, char* sysmem, int64_t sysmem_bytes, void* st, unsigned long long* q, int64_t qcap,
                          unsigned long long* ctl)
 {
     if (batch <= 0) return hipSuccess;
-    BatchArgs a{sys, batch, arf, b, mode, pftri, tol, max_iter, info, iter, wgs_mem, sysmem, sysmem_bytes,
+    BatchArgs a{sys, batch, arf, b, mode, pftri, tol, shift, max_iter, info, iter, wgs_mem, sysmem, sysmem_bytes,
                 (SysState*)st, q, qcap, ctl, (int64_t)1 << 26};
     hipLaunchKernelGGL(batched_setup_kernel, dim3(1), dim3(256), 0, ex.stream, a);
     const int64_t zb = std::min<int64_t>((qcap + 255) / 256, 4096);

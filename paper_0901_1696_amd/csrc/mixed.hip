@@ -32,10 +32,11 @@ __global__ void diag_scale_kernel(Mat<const double> t1, int64_t m1, Mat<const do
 }
 
 // dst(i, j) = (float)(((src(i, j) * sr[i]) * sc[j]) * mu) over an m x n block
-// (lower triangle only if lower); src and dst have the same strides.
+// (lower triangle only if lower, a diagonal block: then shift is added to
+// each diagonal entry before mu); src and dst have the same strides.
 __global__ __launch_bounds__(256) void cast_block_kernel(Mat<const double> src, Mat<float> dst, int64_t m, int64_t n,
                                                          int lower, const double* sr, const double* sc, double mu,
-                                                         int64_t tiles_m, int* nonfinite)
+                                                         double shift, int64_t tiles_m, int* nonfinite)
 {
     const int64_t ti = blockIdx.x % tiles_m, tj = blockIdx.x / tiles_m;
     const int64_t i0 = ti * TT, j0 = tj * TT;
@@ -50,6 +51,7 @@ __global__ __launch_bounds__(256) void cast_block_kernel(Mat<const double> src, 
         if (i < m && j < n && (!lower || i >= j)) {
             double v = src.at(i, j) * sr[i];
             v = v * sc[j];
+            if (lower && i == j) v = v + shift;
             v = v * mu;
             const float f = (float)v;
             dst.at(i, j) = f;
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(256) void cast_block_kernel(Mat<const double> src, 
 }
 
 hipError_t pf_cast_scale(hipStream_t st, const RfpView<const double>& a, const RfpView<float>& o, int scale, double mu,
-                         double* s, int* nonfinite)
+                         double shift, double* s, int* nonfinite)
 {
     const int64_t n = a.m1 + a.m2;
     if (n == 0) return hipSuccess;
@@ -70,7 +72,7 @@ hipError_t pf_cast_scale(hipStream_t st, const RfpView<const double>& a, const R
         if (m <= 0 || nn <= 0) return;
         const int64_t tm = (m + TT - 1) / TT, tn = (nn + TT - 1) / TT;
         hipLaunchKernelGGL(cast_block_kernel, dim3((unsigned)(tm * tn)), dim3(256), 0, st, src, dst, m, nn,
-                           lower ? 1 : 0, sr, sc, mu, tm, nonfinite);
+                           lower ? 1 : 0, sr, sc, mu, shift, tm, nonfinite);
     };
     blk(a.t1, o.t1, a.m1, a.m1, true, s, s);
     blk(a.s, o.s, a.m2, a.m1, false, s + a.m1, s);
@@ -384,6 +386,8 @@ hipError_t backward_error(hipStream_t st, const double* rmax, const double* xmax
 // needed) exit at their first instruction.
 __device__ __forceinline__ void ir_gates(IrCtl* c)
 {
+    c->g_cvt = 1;
+    c->g_cont = 1;
     c->g_ir = c->phase != IR_CLASSIC;
     c->g_pcg = c->phase != IR_PCG;
     c->g_run = c->phase >= IR_DONE;
@@ -401,6 +405,8 @@ __global__ void ir_start_kernel(IrCtl* c)
     c->nonfinite = 0;
     c->eta = 0.0;
     c->prev = 0.0;
+    c->best = 0.0;
+    c->stale = 0;
     ir_gates(c);
 }
 
@@ -420,19 +426,32 @@ __global__ void ir_setup_decide_kernel(IrCtl* c)
 
 // after sweep `it` (1-based) has left its backward error in c->eta: converged
 // at eta <= tol; a classical sweep that does not cut eta fourfold switches to
-// conjugate-gradient sweeps; a conjugate-gradient sweep that does not cut it
-// below 0.9 times the previous one stalls (-2); max_iter sweeps without
-// convergence give -1.  NaN compares false everywhere, so it ends in a stall.
+// conjugate-gradient sweeps, which continue one recurrence from sweep to
+// sweep (each restarts it from the true residual); conjugate gradients
+// minimise the error's A-norm, so the residual need not fall every sweep,
+// and the refinement stalls (-2) only after IR_STALE_SWEEPS of them in a row
+// that do not bring eta below 0.9 times its best value; max_iter sweeps
+// without convergence give -1.  NaN compares false everywhere, so it ends in
+// a stall.
 __global__ void ir_decide_kernel(IrCtl* c, int it, int max_iter, double tol)
 {
     if (threadIdx.x != 0 || c->phase >= IR_DONE) return;
+    const int before = c->phase;
     const double eta = c->eta;
     if (eta <= tol) {
         c->phase = IR_DONE;
         c->code = it;
     } else {
         const bool swept_pcg = c->phase == IR_PCG;
-        if (it > 1 && swept_pcg && !(eta < 0.9 * c->prev)) {
+        if (swept_pcg) {
+            if (eta < 0.9 * c->best) {
+                c->best = eta;
+                c->stale = 0;
+            } else {
+                c->stale++;
+            }
+        }
+        if (swept_pcg && c->stale >= IR_STALE_SWEEPS) {
             c->phase = IR_FALLBACK;
             c->code = -2;
         } else if (it >= max_iter) {
@@ -440,10 +459,16 @@ __global__ void ir_decide_kernel(IrCtl* c, int it, int max_iter, double tol)
             c->code = -1;
         } else if (it > 1 && !swept_pcg && !(eta < 0.25 * c->prev)) {
             c->phase = IR_PCG;
+            c->best = eta < c->prev ? eta : c->prev;
+            c->stale = 0;
         }
         c->prev = eta;
     }
     ir_gates(c);
+    // open exactly when this decision starts, or continues, the
+    // conjugate-gradient sweeps
+    c->g_cvt = !(before == IR_CLASSIC && c->phase == IR_PCG);
+    c->g_cont = !(before == IR_PCG && c->phase == IR_PCG);
 }
 
 __global__ void ir_finish_kernel(const IrCtl* c, int* iter, int* info)
@@ -508,6 +533,42 @@ hipError_t gated_copy(hipStream_t st, double* dst, const double* src, int64_t co
     if (count <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((count + 255) / 256, 8192);
     hipLaunchKernelGGL(gated_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dst, src, count, gate);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void widen_copy_kernel(double* dst, const float* src, int64_t count,
+                                                         const int* gate)
+{
+    if (gate && *gate) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        dst[i] = (double)src[i];
+}
+
+hipError_t widen_copy(hipStream_t st, double* dst, const float* src, int64_t count, const int* gate)
+{
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 8192);
+    hipLaunchKernelGGL(widen_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dst, src, count, gate);
+    return hipGetLastError();
+}
+
+// y(i, c) = (x(i, c) * s[i]) * mul
+__global__ void row_scale_kernel(double* y, int64_t ldy, const double* x, int64_t ldx, const double* s, double mul,
+                                 int64_t n, const int* gate)
+{
+    if (gate && *gate) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = blockIdx.y;
+    if (i < n) y[i + c * ldy] = (x[i + c * ldx] * s[i]) * mul;
+}
+
+hipError_t row_scale(hipStream_t st, double* y, int64_t ldy, const double* x, int64_t ldx, const double* s, double mul,
+                     int64_t n, int64_t nrhs, const int* gate)
+{
+    if (n <= 0 || nrhs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(row_scale_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, y, ldy,
+                       x, ldx, s, mul, n, gate);
     return hipGetLastError();
 }
 

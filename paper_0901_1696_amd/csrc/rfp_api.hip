@@ -130,6 +130,7 @@ struct rfp_context {
     size_t flags_bytes;
     int* ctl;             // device words: [0] epoch of the flags, [1] solve status (bit 0: a wait gave up)
     int spin_limit;       // polls of an unpublished block row before a fused-solve wait gives up
+    double lowp_shift[3]; // diagonal shift of a FP32, FP16, BF16 factor, in units of its unit roundoff
     void* ir;             // mixed-precision solve workspace
     size_t ir_bytes;
     void* bat;            // batched-solver scratch (work counter + per-workgroup scratch)
@@ -972,6 +973,12 @@ static bool ir_trace()
 // applied to the factor); a power of two keeps the scaling exact.  BF16 and
 // FP32 have FP32's exponent range and take mu = 1.
 static double ir_mu(int fprec) { return fprec == RFP_PREC_FP16 ? 33554432.0 : 1.0; }
+// c u of the handle's setting for fprec (FP32, FP16 or BF16)
+static double lowp_shift(const rfp_context* h, int fprec)
+{
+    const int k = fprec == RFP_PREC_FP32 ? 0 : fprec == RFP_PREC_FP16 ? 1 : 2;
+    return h->lowp_shift[k] * unit_roundoff(fprec);
+}
 
 static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64_t n, int64_t nrhs, const double* arf,
                         const double* b, int64_t ldb, double* x, int64_t ldx, double tol, int max_iter, int* iter,
@@ -1032,7 +1039,7 @@ static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64
     };
     // scaled low-precision copy, its factor, and the norms that stay fixed
     ok(ir_start(st, c));
-    ok(pf_cast_scale(st, v, v32, 1, mu, w.s, &c->nonfinite));
+    ok(pf_cast_scale(st, v, v32, 1, mu, lowp_shift(h, fprec), w.s, &c->nonfinite));
     ok(pf_norm(st, v, 1, w.normwork, w.anorm));
     ok(col_max(st, b, ldb, n, nrhs, w.bmax));
     if (!ok(hipGetLastError())) return RFP_ERR_RUNTIME;
@@ -1050,21 +1057,49 @@ static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64
         ok(solve_with_leaves<float>(h, eg, v32c, w.w32, w.r32, n, nrhs));
         ok(ir_update(st, z, ldz, w.s, mu, w.r32, n, n, nrhs, accumulate, eg.gate));
     };
-    // k steps of conjugate gradients on A d = r from d = 0, preconditioned
-    // by M^{-1}, with d added straight into x (FP64 throughout)
+    // The conjugate-gradient steps apply M^{-1} in FP64 arithmetic, with an
+    // FP64 copy of the low-precision factor and FP64 inverses of its leaves:
+    // the operator is then symmetric to FP64 rounding, where an FP32 solve's
+    // rounding (about u_32 / shift relative) would swamp the small eigenvalues
+    // of the preconditioned matrix of an ill-conditioned system.  The copy is
+    // made once, when the sweeps switch to conjugate gradients, in the
+    // fall-back's buffers (not used before the refinement has ended).
+    const int64_t nt = n * (n + 1) / 2;
+    double* w64 = (double*)h->inv;
+    RfpView<const double> v64 = rfp_view(blk, (const double*)w.a64);
+    Exec ex_cvt = ex;
+    ex_cvt.gate = &c->g_cvt;
+    auto widen = [&]() {
+        ok(widen_copy(st, w.a64, w.a32, nt, ex_cvt.gate));
+        ok(trtri_leaves<double>(ex_cvt, v64.t1, blk.m1, w64));
+        ok(trtri_leaves<double>(ex_cvt, v64.t2, blk.m2, w64 + l1 * NB * NB));
+    };
+    auto prec64 = [&](const Exec& eg, const double* v_in, double* z) {
+        ok(row_scale(st, z, n, v_in, n, w.s, 1.0, n, nrhs, eg.gate));
+        ok(solve_with_leaves<double>(h, eg, v64, w64, z, n, nrhs));
+        ok(row_scale(st, z, n, z, n, w.s, mu, n, nrhs, eg.gate));
+    };
+    // k steps of preconditioned conjugate gradients on A x = b (FP64
+    // throughout), from the true residual r of the current x: the first
+    // conjugate-gradient sweep starts the recurrence (p = z), later ones
+    // continue it (p = z + beta p, the true residual replacing the recursive
+    // one).  rz / rzn name the buffers of r.z across sweeps (every sweep
+    // enqueues the same number of swaps, so the names stay consistent).
+    double *rz = w.rz0, *rzn = w.rz1;
     auto pcg = [&](int k) {
         const int* gp = ex_pcg.gate;
         ok(ir_copy(st, w.cr, n, w.r, n, n, nrhs, gp));
-        prec(ex_pcg, w.cr, w.cz, n, false);
-        ok(ir_copy(st, w.cp, n, w.cz, n, n, nrhs, gp));
-        ok(col_dot(st, w.cr, w.cz, n, n, nrhs, w.rz0, gp));
-        double *rz = w.rz0, *rzn = w.rz1;
+        prec64(ex_pcg, w.cr, w.cz);
+        ok(col_dot(st, w.cr, w.cz, n, n, nrhs, rzn, gp));
+        ok(ir_copy(st, w.cp, n, w.cz, n, n, nrhs, &c->g_cvt));
+        ok(pcg_dir(st, w.cp, w.cz, rzn, rz, n, n, nrhs, &c->g_cont));
+        std::swap(rz, rzn);
         for (int i = 0; i < k; i++) {
             ok(symm_thin(ex_pcg, v, w.cp, n, 1.0, 0.0, w.cq, n, nrhs, w.symm));
             ok(col_dot(st, w.cp, w.cq, n, n, nrhs, w.pq, gp));
             ok(pcg_step(st, x, ldx, w.cr, w.cp, w.cq, rz, w.pq, n, n, nrhs, gp));
             if (i + 1 == k) break;
-            prec(ex_pcg, w.cr, w.cz, n, false);
+            prec64(ex_pcg, w.cr, w.cz);
             ok(col_dot(st, w.cr, w.cz, n, n, nrhs, rzn, gp));
             ok(pcg_dir(st, w.cp, w.cz, rzn, rz, n, n, nrhs, gp));
             std::swap(rz, rzn);
@@ -1082,6 +1117,7 @@ static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64
     ok(ir_copy(st, x, ldx, nullptr, 0, n, nrhs, ex_run.gate));
     for (int it = 1; it <= max_iter && e == hipSuccess; it++) {
         prec(ex_ir, w.r, x, ldx, true);
+        widen();
         pcg(PCG_STEPS);
         ok(ir_copy(st, w.r, n, b, ldb, n, nrhs, ex_run.gate));
         ok(symm_thin(ex_run, v, x, ldx, -1.0, 1.0, w.r, n, nrhs, w.symm));
@@ -1101,14 +1137,11 @@ static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64
     // fall-back, gated on the decision: FP64 factor of a copy of A (its INFO
     // word is the gate, so a failing factor also skips the solve), then the
     // FP64 solve
-    const int64_t nt = n * (n + 1) / 2;
     ok(gated_copy(st, w.a64, arf, nt, &c->g_fb));
     rc = pftrf_impl<double>(h, transr, uplo, n, w.a64, &c->fb_info, st, nullptr, 0, nullptr, true);
     if (rc != 0) return rc;
     Exec ex_fb = ex;
     ex_fb.gate = &c->fb_info;
-    RfpView<const double> v64 = rfp_view(blk, (const double*)w.a64);
-    double* w64 = (double*)h->inv;
     ok(ir_copy(st, x, ldx, b, ldb, n, nrhs, ex_fb.gate));
     ok(trtri_leaves<double>(ex_fb, v64.t1, blk.m1, w64));
     ok(trtri_leaves<double>(ex_fb, v64.t2, blk.m2, w64 + l1 * NB * NB));
@@ -1540,6 +1573,9 @@ int rfp_create(rfp_handle_t* h, int device)
     c->device = device;
     c->sched = default_schedule();
     c->spin_limit = DEFAULT_SPIN_LIMIT;
+    c->lowp_shift[0] = DEFAULT_LOWP_SHIFT_FP32;
+    c->lowp_shift[1] = DEFAULT_LOWP_SHIFT_HALF;
+    c->lowp_shift[2] = DEFAULT_LOWP_SHIFT_HALF;
     if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->cus <= 0)
         c->cus = 256;
     *h = c;
@@ -1722,7 +1758,7 @@ int rfp_plan(char routine, char transr, char uplo, int64_t n, int64_t nrhs, int6
 }
 
 int rfp_dpfcast_s(rfp_handle_t h, char transr, char uplo, int64_t n, const double* arf, int scale, double mu,
-                  double* s, float* arf32, hipStream_t stream)
+                  double shift, double* s, float* arf32, hipStream_t stream)
 {
     if (!h) return RFP_ERR_HANDLE;
     if (bad_tr(transr)) return -1;
@@ -1730,13 +1766,14 @@ int rfp_dpfcast_s(rfp_handle_t h, char transr, char uplo, int64_t n, const doubl
     if (n < 0) return -3;
     if (n > 0 && !arf) return -4;
     if (!(mu > 0.0) || mu > 1e300) return -6;
-    if (n > 0 && !s) return -7;
-    if (n > 0 && !arf32) return -8;
+    if (!(shift >= 0.0) || shift > 1e300) return -7;
+    if (n > 0 && !s) return -8;
+    if (n > 0 && !arf32) return -9;
     if (n == 0) return 0;
     DeviceGuard g(h->device);
     RfpBlocks b;
     rfp_blocks(transr, uplo, n, &b);
-    return pf_cast_scale(stream, rfp_view(b, arf), rfp_view(b, arf32), scale, mu, s) == hipSuccess ? 0
+    return pf_cast_scale(stream, rfp_view(b, arf), rfp_view(b, arf32), scale, mu, shift, s) == hipSuccess ? 0
                                                                                                  : RFP_ERR_RUNTIME;
 }
 
@@ -1819,7 +1856,8 @@ int rfp_pfsv_vbatched(rfp_handle_t h, int fprec, int64_t batch, const rfp_sys_t*
     Exec ex{};
     ex.stream = stream;
     ex.prof = h->prof;
-    const hipError_t e = batched_solve(ex, sys, batch, arf_pool, b_pool, mode, pftri, tol, mi, info, iter,
+    const double shift = mode ? lowp_shift(h, fprec) : 0.0;
+    const hipError_t e = batched_solve(ex, sys, batch, arf_pool, b_pool, mode, pftri, tol, shift, mi, info, iter,
                                        base + a_ctl + a_st + a_q, wgs, base + a_ctl + a_st + a_q + a_wg,
                                        sys_host ? (int64_t)(h->bat_bytes - (a_ctl + a_st + a_q + a_wg)) : 0,
                                        base + a_ctl,
@@ -1884,6 +1922,31 @@ int rfp_solve_status(rfp_handle_t h, int* status, hipStream_t stream)
     if (!h->ctl && prepare_flags(h, 1) != hipSuccess) return RFP_ERR_RUNTIME;
     hipLaunchKernelGGL(take_status_kernel, dim3(1), dim3(64), 0, stream, h->ctl + 1, status);
     return hipGetLastError() == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+static int shift_slot(int fprec)
+{
+    return fprec == RFP_PREC_FP32 ? 0 : fprec == RFP_PREC_FP16 ? 1 : fprec == RFP_PREC_BF16 ? 2 : -1;
+}
+
+int rfp_set_lowp_shift(rfp_handle_t h, int fprec, double c)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    const int k = shift_slot(fprec);
+    if (k < 0) return -2;
+    if (!(c >= 0.0) || c > 1e6) return -3;
+    h->lowp_shift[k] = c;
+    return 0;
+}
+
+int rfp_get_lowp_shift(rfp_handle_t h, int fprec, double* c)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    const int k = shift_slot(fprec);
+    if (k < 0) return -2;
+    if (!c) return -3;
+    *c = h->lowp_shift[k];
+    return 0;
 }
 
 int rfp_set_solve_wait_limit(rfp_handle_t h, int64_t polls)

@@ -257,9 +257,20 @@ hipError_t fill_int(hipStream_t s, int* p, int64_t n, int v);
 
 // Mixed-precision building blocks.
 // s[i] = 1/sqrt(a_ii) (scale) or 1, then o = (float)(((a_ij s_i) s_j) mu) on
-// every stored entry, o in the same RFP layout as a.
+// every stored entry (shift added to (a_ii s_i) s_i before mu), o in the same
+// RFP layout as a.
 hipError_t pf_cast_scale(hipStream_t st, const RfpView<const double>& a, const RfpView<float>& o, int scale, double mu,
-                         double* s, int* nonfinite = nullptr);
+                         double shift, double* s, int* nonfinite = nullptr);
+// Default multiples c of the factor precision's unit roundoff u added to the
+// unit diagonal of the scaled matrix before a low-precision factor: the FP32
+// factor's own rounding (FP32 accumulation over long inner products) needs a
+// larger multiple of its small u than FP16 / BF16 operands do of theirs.
+constexpr double DEFAULT_LOWP_SHIFT_FP32 = 64.0;
+constexpr double DEFAULT_LOWP_SHIFT_HALF = 4.0;
+inline double unit_roundoff(int fprec)
+{
+    return fprec == RFP_PREC_FP16 ? 0x1p-11 : fprec == RFP_PREC_BF16 ? 0x1p-8 : 0x1p-24;
+}
 // Norm of the symmetric matrix held in a: which = 0 max |a_ij|, 1 one- (=
 // infinity-) norm, 2 Frobenius; work holds n + 3 doubles; *out on the device.
 hipError_t pf_norm(hipStream_t st, const RfpView<const double>& a, int which, double* work, double* out);
@@ -294,9 +305,15 @@ struct IrCtl {
     int lp_info;    // INFO of the low-precision factor
     int nonfinite;  // the scaled low-precision copy holds a non-finite entry
     int fb_info;    // INFO of the fall-back factor (gated as the factor's info word)
-    int pad[6];
-    double eta, prev;
+    int g_cvt;      // 0 = first conjugate-gradient sweep (widen the factor for the FP64 preconditioner, p = z)
+    int g_cont;     // 0 = a conjugate-gradient sweep that continues the previous one's recurrence
+    int stale;      // conjugate-gradient sweeps in a row without a new best backward error
+    int pad[3];
+    double eta, prev, best;
 };
+// conjugate-gradient sweeps in a row that may fail to bring the backward
+// error below 0.9 times its best value before the refinement counts as stalled
+constexpr int IR_STALE_SWEEPS = 3;
 enum { IR_CLASSIC = 0, IR_PCG = 1, IR_DONE = 2, IR_FALLBACK = 3 };
 hipError_t ir_start(hipStream_t st, IrCtl* c);
 hipError_t ir_setup_decide(hipStream_t st, IrCtl* c);
@@ -307,6 +324,11 @@ hipError_t ir_copy(hipStream_t st, double* y, int64_t ldy, const double* x, int6
                    const int* gate);
 // 1-D copy of count doubles, nothing while *gate != 0
 hipError_t gated_copy(hipStream_t st, double* dst, const double* src, int64_t count, const int* gate);
+// dst = (double)src over count entries, nothing while *gate != 0
+hipError_t widen_copy(hipStream_t st, double* dst, const float* src, int64_t count, const int* gate);
+// y(i, c) = (x(i, c) * s[i]) * mul (n x nrhs), nothing while *gate != 0
+hipError_t row_scale(hipStream_t st, double* y, int64_t ldy, const double* x, int64_t ldx, const double* s, double mul,
+                     int64_t n, int64_t nrhs, const int* gate);
 
 // Batched systems in one persistent launch (csrc/batched.hip).  mode: 0 FP64,
 // 1 FP32, 2 FP16, 3 BF16 factor + FP64 refinement.  wgs_mem holds
@@ -318,8 +340,8 @@ size_t batched_state_bytes(int64_t batch);
 int64_t batched_plan_host(const rfp_sys_t* sys_host, int64_t batch, int mode, int pftri, int max_iter,
                           int64_t* tasks);
 hipError_t batched_solve(const Exec& ex, const rfp_sys_t* sys, int64_t batch, double* arf, double* b, int mode,
-                         int pftri, double tol, int max_iter, int* info, int* iter, char* wgs_mem, int wgs,
-                         char* sysmem, int64_t sysmem_bytes, void* st, unsigned long long* q, int64_t qcap,
+                         int pftri, double tol, double shift, int max_iter, int* info, int* iter, char* wgs_mem,
+                         int wgs, char* sysmem, int64_t sysmem_bytes, void* st, unsigned long long* q, int64_t qcap,
                          unsigned long long* ctl);
 
 // 2-D strided copy dst = src (m x n), optionally only the lower triangle.

@@ -228,7 +228,8 @@ def test_batched_tiled_low_precision(h, mode, pftri):
     with condition numbers 1e2 .. 1e6: every solution reaches the backward
     error bound (refinement converged, or the FP64 fall-back, whose factor is
     then left in the array), and with PFTRI the array holds the inverse of the
-    FP64 matrix.  FP32 factors refine every one of these systems."""
+    FP64 matrix.  With the diagonal shift and the conjugate-gradient sweeps,
+    every factor precision refines every one of these systems."""
     ns = [300, 513, 700, 1001, 100, 256]
     lays = [0, 1, 2, 3, 1, 2]
     nrs = [2, 1, 3, 2, 1, 4]
@@ -254,9 +255,7 @@ def test_batched_tiled_low_precision(h, mode, pftri):
     for (n, a0, b0, ldb, nr, t, u), arf, q in zip(systems, arfs, range(len(systems))):
         B = b_pool[b0:b0 + ldb * nr].reshape(nr, ldb).T[:n]
         X = bp[b0:b0 + ldb * nr].reshape(nr, ldb).T[:n]
-        assert it[q] != 0
-        if mode == rfp.PREC_FP32:
-            assert it[q] > 0, (n, it[q])
+        assert it[q] > 0, (n, it[q])
         assert oracle.backward_error(t, u, n, arf, B, X) <= 1e-14, (n, t, u, it[q])
         if pftri:
             f, _ = oracle.pftrf(t, u, n, arf.copy())
@@ -267,3 +266,44 @@ def test_batched_tiled_low_precision(h, mode, pftri):
         else:
             f, _ = oracle.pftrf(t, u, n, arf.copy())  # fell back: the FP64 factor is in place
             assert oracle.rel_fro(ap[a0:a0 + arf.size], f) <= 1e-12 * n
+
+
+@pytest.mark.parametrize("mode", [rfp.PREC_FP16, rfp.PREC_BF16, rfp.PREC_FP32])
+def test_batched_ill_conditioned_refines_without_fallback(h, mode):
+    """Condition numbers 1e7 and 1e8 (kappa u_low >> 1 for FP16 and BF16):
+    the shifted low-precision factor stays positive definite, and the
+    conjugate-gradient sweeps bring every system (tiled and one-task) to the
+    FP64 backward error without the FP64 fall-back; with the shift switched
+    off, the FP16 and BF16 factors (and the FP32 factors at 1e8) are not
+    positive definite (-3) and the FP64 fall-back answers."""
+    ns, lays, nrs = [700, 1300, 256, 400], [0, 3, 1, 2], [2, 3, 1, 4]
+    res = {}
+    c_default = rfp.rfp_get_lowp_shift(h, mode)
+    for c in (c_default, 0.0):
+        systems, arfs, As, arf_pool, b_pool = [], [], [], [], []
+        ao = bo = 0
+        for q, (n, li, nr) in enumerate(zip(ns, lays, nrs)):
+            s_q, a_q, _, ap_q, bp_q = make_batch([n], [li], [nr], seed=900 + q, kappa=1e7 if q % 2 else 1e8)
+            n_, _, _, ldb, nr_, t, u = s_q[0]
+            systems.append((n_, ao, bo, ldb, nr_, t, u))
+            arfs.append(a_q[0])
+            arf_pool.append(ap_q)
+            b_pool.append(bp_q)
+            ao += ap_q.size
+            bo += bp_q.size
+        arf_pool, b_pool = np.concatenate(arf_pool), np.concatenate(b_pool)
+        rfp.rfp_set_lowp_shift(h, mode, c)
+        try:
+            ap, bp, info, it = run_batch(h, mode, systems, arf_pool, b_pool, max_iter=30)
+        finally:
+            rfp.rfp_set_lowp_shift(h, mode, c_default)
+        assert np.all(info == 0), info
+        for (n, a0, b0, ldb, nr, t, u), arf in zip(systems, arfs):
+            B = b_pool[b0:b0 + ldb * nr].reshape(nr, ldb).T[:n]
+            X = bp[b0:b0 + ldb * nr].reshape(nr, ldb).T[:n]
+            assert oracle.backward_error(t, u, n, arf, B, X) <= 1e-14, (c, n, t, u)
+        res[c] = it
+    assert np.all(res[c_default] > 0), res[c_default]
+    # unshifted: FP16 / BF16 fail on every system, FP32 on the kappa = 1e8 ones
+    lost = res[0.0] if mode != rfp.PREC_FP32 else res[0.0][0::2]
+    assert np.all(lost == -3), res[0.0]

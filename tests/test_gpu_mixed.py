@@ -22,14 +22,15 @@ def h():
 
 @pytest.mark.parametrize("transr,uplo", LAYOUTS)
 @pytest.mark.parametrize("n", [1, 2, 3, 64, 65, 129, 300, 1001])
-@pytest.mark.parametrize("scale,mu", [(0, 1.0), (1, 1.0), (1, 4096.0)])
-def test_cast_scale_bit_exact(h, transr, uplo, n, scale, mu):
+@pytest.mark.parametrize("scale,mu,shift", [(0, 1.0, 0.0), (1, 1.0, 0.0), (1, 4096.0, 0.0), (1, 2.0 ** 25, 4 * 2.0 ** -11),
+                                            (1, 1.0, 3.3e-7)])
+def test_cast_scale_bit_exact(h, transr, uplo, n, scale, mu, shift):
     A, _ = synth.spd(n, seed=n + 31)
     arf = oracle.trttf(transr, uplo, A)
-    s_want, out_want = oracle.pfcast_s(transr, uplo, n, arf, scale=bool(scale), mu=mu)
+    s_want, out_want = oracle.pfcast_s(transr, uplo, n, arf, scale=bool(scale), mu=mu, shift=shift)
     s = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
     out = torch.full((rfp.nt(n),), -7.0, dtype=torch.float32, device="cuda")
-    rfp.rfp_dpfcast_s(h, transr, uplo, n, dev(arf), scale, mu, s, out)
+    rfp.rfp_dpfcast_s(h, transr, uplo, n, dev(arf), scale, mu, s, out, shift=shift)
     assert np.array_equal(host(s), s_want)
     assert np.array_equal(host(out), out_want)
 
@@ -263,3 +264,43 @@ def test_solve_wait_give_up_is_reported(h):
     rfp.rfp_solve_status(h, st)
     assert int(host(st)[0]) == 0
     assert np.array_equal(host_colmajor(bd), X)
+
+
+def test_lowp_shift_setting(h):
+    assert rfp.rfp_get_lowp_shift(h, rfp.PREC_FP32) == 64.0
+    assert rfp.rfp_get_lowp_shift(h, rfp.PREC_FP16) == 4.0
+    assert rfp.rfp_get_lowp_shift(h, rfp.PREC_BF16) == 4.0
+    rfp.rfp_set_lowp_shift(h, rfp.PREC_BF16, 0.0)
+    assert rfp.rfp_get_lowp_shift(h, rfp.PREC_BF16) == 0.0
+    assert rfp.rfp_get_lowp_shift(h, rfp.PREC_FP16) == 4.0
+    with pytest.raises(RuntimeError):
+        rfp.rfp_set_lowp_shift(h, rfp.PREC_FP16, -1.0)
+    with pytest.raises(RuntimeError):
+        rfp.rfp_set_lowp_shift(h, rfp.PREC_FP64, 1.0)
+    rfp.rfp_set_lowp_shift(h, rfp.PREC_BF16, 4.0)
+
+
+@pytest.mark.parametrize("fprec", [rfp.PREC_FP16, rfp.PREC_BF16, rfp.PREC_FP32])
+@pytest.mark.parametrize("kappa", [1e6, 1e8])
+def test_ir_shifted_factor_refines_ill_conditioned(h, fprec, kappa):
+    """kappa(A) u_low >> 1: the shifted low-precision factor stays positive
+    definite and, as the preconditioner of the conjugate-gradient sweeps,
+    brings the solution to the FP64 backward error.  Without the shift, the
+    FP16 / BF16 factor of the kappa = 1e8 matrix is not positive definite."""
+    n, nrhs = 1001, 2
+    A, B, arf = _ir_case(n, kappa, nrhs, seed=n + int(np.log10(kappa)))
+    x = dev_colmajor(np.zeros((n, nrhs)))
+    it, info = _ir(h, fprec, "N", "L", n, dev(arf), dev_colmajor(B), x, tol=1e-14, max_iter=30)
+    assert info == 0 and it > 0, f"code {it}"
+    assert oracle.backward_error("N", "L", n, arf, B, host_colmajor(x)) <= 1e-14
+    if fprec == rfp.PREC_FP32 or kappa < 1e8:
+        return
+    c0 = rfp.rfp_get_lowp_shift(h, fprec)
+    rfp.rfp_set_lowp_shift(h, fprec, 0.0)
+    try:
+        x = dev_colmajor(np.zeros((n, nrhs)))
+        it0, info0 = _ir(h, fprec, "N", "L", n, dev(arf), dev_colmajor(B), x, tol=1e-14, max_iter=30)
+    finally:
+        rfp.rfp_set_lowp_shift(h, fprec, c0)
+    assert (it0, info0) == (-3, 0)
+    assert oracle.backward_error("N", "L", n, arf, B, host_colmajor(x)) <= 1e-14

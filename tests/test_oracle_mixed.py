@@ -47,6 +47,29 @@ def test_cast_undoes_power_of_two_scaling_exactly(transr, uplo, n, mu):
     assert np.array_equal(out, want)
 
 
+@pytest.mark.parametrize("transr,uplo", LAYOUTS)
+@pytest.mark.parametrize("n", [1, 7, 129])
+@pytest.mark.parametrize("shift", [2.0 ** -9, 2.0 ** -6])
+def test_cast_shift_adds_to_the_unit_diagonal(transr, uplo, n, shift):
+    """Same exact setting as above: the scaled matrix is mu (C + shift I),
+    and with shift and mu powers of two and C's diagonal 1 every stored
+    value is still exact (1 + shift fits in FP32's 24 bits)."""
+    C = _unit_diag_spd(n, seed=n + 3)
+    e = synth.rng(n + 5).integers(-10, 11, size=n)
+    d0 = np.ldexp(1.0, e)
+    A = np.asfortranarray(d0[:, None] * C * d0[None, :])
+    mu = 4096.0
+    arf = oracle.trttf(transr, uplo, A)
+    s, out = oracle.pfcast_s(transr, uplo, n, arf, scale=True, mu=mu, shift=shift)
+    want = oracle.trttf(transr, uplo, np.asfortranarray(mu * (C + shift * np.eye(n)))).astype(np.float32)
+    assert np.array_equal(out, want)
+    # the off-diagonal entries are those of the unshifted cast
+    _, out0 = oracle.pfcast_s(transr, uplo, n, arf, scale=True, mu=mu)
+    diag = oracle.trttf(transr, uplo, np.asfortranarray(np.eye(n))) != 0
+    assert np.array_equal(out[~diag], out0[~diag])
+    assert np.all(out[diag] == np.float32(mu * (1.0 + shift)))
+
+
 def test_cast_marks_non_positive_diagonal():
     n = 9
     A, _ = synth.spd(n, seed=2)
