@@ -207,6 +207,18 @@ int rfp_get_lowp_shift(rfp_handle_t h, int fprec, double* c);
 int rfp_dlansf(rfp_handle_t h, char norm, char transr, char uplo, int64_t n, const double* arf, double* out,
                hipStream_t stream);
 
+/* Symmetric product with a thin matrix (not in the paper's routine table;
+ * the residual and conjugate-gradient product of rfp_dpfsv_ir):
+ * Y = alpha A X + beta Y for the symmetric A of order n held in arf (RFP,
+ * only the stored triangle is read, each entry once), X and Y n x nrhs
+ * column-major (ldx, ldy >= max(1, n)); Y must not overlap X.  beta = 0 does
+ * not read Y.  The summation order is fixed, so the result is the same on
+ * every call.  Uses handle scratch (about 3 (n/256) n 16 doubles).  Argument
+ * order: TRANSR=1, UPLO=2, N=3, NRHS=4, ALPHA=5, A=6, X=7, LDX=8, BETA=9,
+ * Y=10, LDY=11. */
+int rfp_dsfmv(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, double alpha, const double* arf,
+              const double* x, int64_t ldx, double beta, double* y, int64_t ldy, hipStream_t stream);
+
 /* Solve A X = B for the FP64 SPD matrix in arf (left untouched) by a
  * low-precision Cholesky factor and FP64 iterative refinement:
  *   As = mu (D^{-1/2} A D^{-1/2} + c u I) rounded to FP32 (rfp_dpfcast_s
@@ -351,9 +363,9 @@ int rfp_set_solve_wait_limit(rfp_handle_t h, int64_t polls);
  * Section 3 (the 2 x 2 partition of Figure 3 applied to panels of the two
  * diagonal triangles), never the arithmetic each block does, so every
  * setting computes the same factor up to rounding.
- *   wide_panels_above: a diagonal triangle's panels are 256 columns wide
- *     while its trailing order exceeds this value, 128 wide after
- *     (default 6144; 0 = always 256 wide; a value >= n = always 128 wide).
+ *   wide_panels_above: a diagonal triangle's panels are wide_panel_cols
+ *     columns wide while its trailing order exceeds this value, 128 wide
+ *     after (default 6144; 0 = always wide; a value >= n = always 128 wide).
  *   chunk_max: the off-diagonal solve (step 2) and its share of step 3 run
  *     by chunks of at most this many columns on a third stream, overlapped
  *     with step 1 (default 1536; at least 512 is used; 0 disables the
@@ -364,15 +376,22 @@ int rfp_set_solve_wait_limit(rfp_handle_t h, int64_t polls);
  *   leaf_lds_pad: bytes of LDS the FP64 128-row diagonal leaf reserves
  *     beyond what it uses, to keep large GEMM workgroups off its compute unit
  *     (default 24576; 0 to 65536).
+ *   wide_panel_cols: width of the wide panels, a multiple of 128 (default
+ *     256).  A wide panel's diagonal block is factored by the 2 x 2 partition
+ *     down to 128-row leaves; a width at least the triangle's order factors
+ *     the whole triangle that way (a fully recursive factorization, whose
+ *     trailing updates have the largest inner dimensions and so the least
+ *     traffic per flop).
  * rfp_set_schedule(h, NULL) restores the defaults; illegal values return
- * -2 (a field < 0, or leaf_lds_pad > 65536) and leave the schedule as it
- * was.  The schedule is host state of the handle; calls already enqueued are
+ * -2 (a field < 0, leaf_lds_pad > 65536, or wide_panel_cols not a positive
+ * multiple of 128) and leave the schedule as it was.  The schedule is host state of the handle; calls already enqueued are
  * not affected.  Argument order: H=1, SCHED=2. */
 typedef struct {
     int64_t wide_panels_above;
     int64_t chunk_max;
     int64_t lookahead_wait_below;
     int64_t leaf_lds_pad;
+    int64_t wide_panel_cols;
 } rfp_schedule_t;
 int rfp_set_schedule(rfp_handle_t h, const rfp_schedule_t* sched);
 int rfp_get_schedule(rfp_handle_t h, rfp_schedule_t* sched);

@@ -66,6 +66,7 @@ def _declare(L):
     L.orc_backward_error.restype = ctypes.c_double
     L.orc_norm_max.argtypes = [_chr, _chr, _i64, _dp]
     L.orc_norm_max.restype = ctypes.c_double
+    L.orc_sfmv.argtypes = [_chr, _chr, _i64, _i64, ctypes.c_double, _dp, _dp, _i64, ctypes.c_double, _dp, _i64]
     L.orc_norm_fro.argtypes = [_chr, _chr, _i64, _dp]
     L.orc_norm_fro.restype = ctypes.c_double
     L.orc_pfcast_s.argtypes = [_chr, _chr, _i64, _dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _vp]
@@ -194,6 +195,17 @@ def norm_inf(transr, uplo, n, arf):
 def norm_max(transr, uplo, n, arf):
     arf = np.ascontiguousarray(arf, dtype=np.float64)
     return lib().orc_norm_max(_c(transr), _c(uplo), n, _p(arf))
+
+
+def sfmv(transr, uplo, n, alpha, arf, x, beta, y):
+    """alpha A X + beta Y for the symmetric A in RFP (x, y: n x nrhs)."""
+    arf = np.ascontiguousarray(arf, dtype=np.float64)
+    x = np.asfortranarray(np.asarray(x, dtype=np.float64).reshape(n, -1))
+    y = np.asfortranarray(np.array(y, dtype=np.float64).reshape(n, -1))
+    nrhs = x.shape[1]
+    lib().orc_sfmv(_c(transr), _c(uplo), n, nrhs, float(alpha), _p(arf), _p(x), max(1, n), float(beta), _p(y),
+                   max(1, n))
+    return y
 
 
 def norm_fro(transr, uplo, n, arf):

@@ -435,6 +435,22 @@ double orc_norm_fro(char transr, char uplo, i64 n, const double *arf)
     return (double)sqrtl(s);
 }
 
+/* Y = alpha A X + beta Y for the symmetric A held in RFP (X, Y n x nrhs
+ * column-major), by the definition of the product over the full symmetric
+ * matrix, each sum in long double; beta = 0 does not read Y. */
+void orc_sfmv(char transr, char uplo, i64 n, i64 nrhs, double alpha, const double *arf, const double *x, i64 ldx,
+              double beta, double *y, i64 ldy)
+{
+    for (i64 c = 0; c < nrhs; c++)
+        for (i64 i = 0; i < n; i++) {
+            long double s = 0.0L;
+            for (i64 j = 0; j < n; j++) s += (long double)sym_at(transr, uplo, n, arf, i, j) * x[j + c * ldx];
+            double v = (double)((long double)alpha * s);
+            if (beta != 0.0) v += beta * y[i + c * ldy];
+            y[i + c * ldy] = v;
+        }
+}
+
 /* Scaled cast of the mixed-precision solve (not part of the paper; the
  * scaling D^{-1/2} A D^{-1/2} with D = diag(A) is the classical symmetric
  * equilibration, the diagonal shift that of Higham and Pranesh's

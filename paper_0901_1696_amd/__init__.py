@@ -64,6 +64,7 @@ _SIGS = {
     "rfp_set_lowp_shift": [_vp, _int, ctypes.c_double],
     "rfp_get_lowp_shift": [_vp, _int, _vp],
     "rfp_dlansf": [_vp, _chr, _chr, _chr, _i64, _vp, _vp, _vp],
+    "rfp_dsfmv": [_vp, _chr, _chr, _i64, _i64, ctypes.c_double, _vp, _vp, _i64, ctypes.c_double, _vp, _i64, _vp],
     "rfp_autotune": [_vp, _i64, _i64, _int, _vp],
     "rfp_tune_count": [_vp],
     "rfp_tune_clear": [_vp],
@@ -201,7 +202,7 @@ def rfp_profile_read(h):
 class Schedule(ctypes.Structure):
     """Layout of ``rfp_schedule_t`` (include/rfp.h): the factorization schedule knobs."""
     _fields_ = [("wide_panels_above", _i64), ("chunk_max", _i64), ("lookahead_wait_below", _i64),
-                ("leaf_lds_pad", _i64)]
+                ("leaf_lds_pad", _i64), ("wide_panel_cols", _i64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -209,7 +210,7 @@ class Schedule(ctypes.Structure):
 
 INT64_MAX = 2 ** 63 - 1
 DEFAULT_SCHEDULE = dict(wide_panels_above=6144, chunk_max=1536, lookahead_wait_below=INT64_MAX,
-                        leaf_lds_pad=24576)
+                        leaf_lds_pad=24576, wide_panel_cols=256)
 
 
 def _schedule(sched):
@@ -360,6 +361,17 @@ def rfp_get_lowp_shift(h, fprec):
     out = ctypes.c_double()
     _check("rfp_get_lowp_shift", lib().rfp_get_lowp_shift(h.value, int(fprec), ctypes.byref(out)))
     return out.value
+
+
+def rfp_dsfmv(h, transr, uplo, n, alpha, arf, x, beta, y, stream=None):
+    """Y = alpha A X + beta Y, A symmetric in RFP; x and y column-major
+    (n x nrhs) device tensors."""
+    px, ldx, nrhs = _colmajor(x, "x")
+    py, ldy, ny = _colmajor(y, "y")
+    if ny != nrhs:
+        raise ValueError("x and y must have the same number of columns")
+    _check("rfp_dsfmv", lib().rfp_dsfmv(h.value, _c(transr), _c(uplo), n, nrhs, float(alpha), _ptr(arf), px, ldx,
+                                        float(beta), py, ldy, _stream(stream)))
 
 
 def rfp_dlansf(h, norm, transr, uplo, n, arf, out, stream=None):

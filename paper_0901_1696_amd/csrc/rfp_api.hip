@@ -321,13 +321,16 @@ struct Run {
     // trailing order above which panels are 2 nb wide, and trailing order up
     // to which the bulk update waits for the lookahead (the schedule knobs)
     int64_t wide_panels_above = DEFAULT_WIDE_PANELS_ABOVE;
+    int64_t wide_panel_cols = DEFAULT_WIDE_PANEL_COLS;
     int64_t lookahead_wait_below = DEFAULT_LOOKAHEAD_WAIT_BELOW;
     template <typename F = void (*)(int64_t, hipEvent_t)>
     void potrf_la(int64_t n, Mat<T> A, int64_t goff, T* winv, F* fork = nullptr)
     {
         if (n <= 0) return;
         auto winv_at = [&](int64_t o) { return winv + (o / nb) * nb * nb; };
-        auto width = [&](int64_t o) { return std::min<int64_t>(n - o > wide_panels_above ? 2 * nb : nb, n - o); };
+        auto width = [&](int64_t o) {
+            return std::min<int64_t>(n - o > wide_panels_above ? wide_panel_cols : nb, n - o);
+        };
         int64_t o = 0, w = width(0);
         potrf_rec(w, A, goff, winv);
         hipEvent_t bulk_prev = nullptr;
@@ -613,13 +616,14 @@ static rfp_schedule_t default_schedule()
     sc.chunk_max = DEFAULT_CHUNK_MAX;
     sc.lookahead_wait_below = DEFAULT_LOOKAHEAD_WAIT_BELOW;
     sc.leaf_lds_pad = DEFAULT_LEAF_LDS_PAD;
+    sc.wide_panel_cols = DEFAULT_WIDE_PANEL_COLS;
     return sc;
 }
 
 static bool bad_schedule(const rfp_schedule_t& sc)
 {
     return sc.wide_panels_above < 0 || sc.chunk_max < 0 || sc.lookahead_wait_below < 0 || sc.leaf_lds_pad < 0 ||
-           sc.leaf_lds_pad > MAX_LEAF_LDS_PAD;
+           sc.leaf_lds_pad > MAX_LEAF_LDS_PAD || sc.wide_panel_cols < NB2 || sc.wide_panel_cols % NB2 != 0;
 }
 
 // The schedule of a factorization of order n: the caller's, else a tuned one
@@ -655,6 +659,7 @@ static Run<T> make_run(rfp_context* h, hipStream_t s, int* info, int lowp = 0, c
     r.ex.lowp = r.ex2.lowp = lowp;
     r.ex.leaf_pad = r.ex2.leaf_pad = (int)sched.leaf_lds_pad;
     r.wide_panels_above = sched.wide_panels_above;
+    r.wide_panel_cols = sched.wide_panel_cols;
     r.lookahead_wait_below = sched.lookahead_wait_below;
     r.ex3 = r.ex;
     r.ex3.stream = h->aux2;
@@ -740,6 +745,7 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
         if (bad_schedule(sc)) return -8;
         r.rec = rec;
         r.wide_panels_above = sc.wide_panels_above;
+        r.wide_panel_cols = sc.wide_panel_cols;
         r.lookahead_wait_below = sc.lookahead_wait_below;
         winv = plan_base<T>(RFP_PLAN_BUF_WORK);
     } else {
@@ -1799,6 +1805,33 @@ int rfp_dlansf(rfp_handle_t h, char norm, char transr, char uplo, int64_t n, con
     return pf_norm(stream, rfp_view(b, arf), which, (double*)h->ir, out) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
+int rfp_dsfmv(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, double alpha, const double* arf,
+              const double* x, int64_t ldx, double beta, double* y, int64_t ldy, hipStream_t stream)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (bad_tr(transr)) return -1;
+    if (bad_ul(uplo)) return -2;
+    if (n < 0) return -3;
+    if (nrhs < 0) return -4;
+    if (n > 0 && nrhs > 0 && !arf) return -6;
+    if (n > 0 && nrhs > 0 && !x) return -7;
+    if (ldx < std::max<int64_t>(1, n)) return -8;
+    if (n > 0 && nrhs > 0 && !y) return -10;
+    if (ldy < std::max<int64_t>(1, n)) return -11;
+    if (n == 0 || nrhs == 0) return 0;
+    DeviceGuard g(h->device);
+    RfpBlocks b;
+    rfp_blocks(transr, uplo, n, &b);
+    // the product's partial sums live in the refinement workspace
+    if (ensure(&h->ir, &h->ir_bytes, symm_thin_workspace(b.m1, b.m2)) != hipSuccess) return RFP_ERR_RUNTIME;
+    Exec ex{};
+    ex.stream = stream;
+    ex.prof = h->prof;
+    return symm_thin(ex, rfp_view(b, arf), x, ldx, alpha, beta, y, ldy, nrhs, (double*)h->ir) == hipSuccess
+               ? 0
+               : RFP_ERR_RUNTIME;
+}
+
 int rfp_spftrf_mp(rfp_handle_t h, int fprec, char transr, char uplo, int64_t n, float* arf, int* info,
                   hipStream_t stream)
 {
@@ -2009,10 +2042,10 @@ int rfp_tune_save(rfp_handle_t h, const char* path)
     if (h->tune)
         for (auto& kv : h->tune->sched)
             fprintf(f, "  {\"bucket\": %d, \"wide_panels_above\": %lld, \"chunk_max\": %lld, "
-                       "\"lookahead_wait_below\": %lld, \"leaf_lds_pad\": %lld}%s\n",
+                       "\"lookahead_wait_below\": %lld, \"leaf_lds_pad\": %lld, \"wide_panel_cols\": %lld}%s\n",
                     kv.first, (long long)kv.second.wide_panels_above, (long long)kv.second.chunk_max,
                     (long long)kv.second.lookahead_wait_below, (long long)kv.second.leaf_lds_pad,
-                    ++i < h->tune->sched.size() ? "," : "");
+                    (long long)kv.second.wide_panel_cols, ++i < h->tune->sched.size() ? "," : "");
     fprintf(f, " ]\n}\n");
     return fclose(f) == 0 ? 0 : -1;
 }
@@ -2030,11 +2063,11 @@ int rfp_tune_load(rfp_handle_t h, const char* path)
         if (strstr(line, "\"solve\"")) in_solve = true;
         if (const char* qs = strstr(line, "{\"bucket\":")) {
             int bucket;
-            long long w, c, l, p;
+            long long w, c, l, p, pc;
             rfp_schedule_t sc;
             if (sscanf(qs, "{\"bucket\": %d, \"wide_panels_above\": %lld, \"chunk_max\": %lld, "
-                           "\"lookahead_wait_below\": %lld, \"leaf_lds_pad\": %lld}",
-                       &bucket, &w, &c, &l, &p) != 5) {
+                           "\"lookahead_wait_below\": %lld, \"leaf_lds_pad\": %lld, \"wide_panel_cols\": %lld}",
+                       &bucket, &w, &c, &l, &p, &pc) != 6) {
                 ok = false;
                 break;
             }
@@ -2042,6 +2075,7 @@ int rfp_tune_load(rfp_handle_t h, const char* path)
             sc.chunk_max = c;
             sc.lookahead_wait_below = l;
             sc.leaf_lds_pad = p;
+            sc.wide_panel_cols = pc;
             if (bad_schedule(sc)) {
                 ok = false;
                 break;

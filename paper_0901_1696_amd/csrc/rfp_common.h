@@ -125,6 +125,7 @@ constexpr int NB2 = 128;
 // 2048-6144), and 24 KB of LDS reserved by the FP64 leaf (beside a 128 x 128
 // GEMM workgroup the leaf ran 1.5-1.8x slower).
 constexpr int64_t DEFAULT_WIDE_PANELS_ABOVE = 6144;
+constexpr int64_t DEFAULT_WIDE_PANEL_COLS = 256;
 constexpr int64_t DEFAULT_CHUNK_MAX = 1536;
 constexpr int64_t DEFAULT_LOOKAHEAD_WAIT_BELOW = INT64_MAX;
 constexpr int64_t DEFAULT_LEAF_LDS_PAD = 24 * 1024;

@@ -123,71 +123,132 @@ __device__ __forceinline__ const T* dep_block(const SolveArgs<T>& a, int k, int6
 // workgroup.  The grid is padded to whole groups of XCD_COUNT block rows.
 constexpr int XCD_COUNT = 8;
 
-template <typename T, int NCB, bool FWD>
+// R consecutive block rows per workgroup (R = 1 or 2): the workgroup
+// accumulates the products of every earlier block row for all R of them,
+// then solves them one after the other inside the workgroup (the second
+// also subtracts the product with the first through LDS), publishing each as
+// soon as it is solved.  With R = 2 half as many results cross between
+// workgroups on the dependency chain, whose per-step latency (flag, device-
+// scope loads and stores) is what bounds the solve for few right-hand sides.
+template <typename T, int NCB, bool FWD, int R>
 __global__ __launch_bounds__(256) void block_solve_kernel(SolveArgs<T> a)
 {
     constexpr int CS = 16 * NCB;
     constexpr int LPT = BS * BS / 256;  // factor-block elements per thread
     constexpr int YPT = CS * BS / 256;  // solution-block elements per thread
-    __shared__ __attribute__((aligned(16))) T Ls[BS][P];  // L block or W, Ls[i][kk]
-    __shared__ __attribute__((aligned(16))) T Ys[CS][P];  // solved rows, Ys[column][row]
+    __shared__ __attribute__((aligned(16))) T Ls[BS][P];  // L block (or W, R = 1), Ls[i][kk]
+    __shared__ __attribute__((aligned(16))) T Ys[CS][P];  // rows of a dependency or own rows, Ys[column][row]
+    // R = 2: both diagonal inverses and the coupling block, staged once
+    constexpr int RB = R == 2 ? BS : 1;
+    __shared__ __attribute__((aligned(16))) T Wd[R][RB][R == 2 ? P : 1];
+    __shared__ __attribute__((aligned(16))) T Cd[RB][R == 2 ? P : 1];
 
     if (a.gate && *a.gate) return;
     const int epoch = *a.epoch;
     const int nblk = a.nb1 + a.nb2;
+    const int nsup = (nblk + R - 1) / R;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int grp = blockIdx.x / (XCD_COUNT * a.nslices), rem = blockIdx.x % (XCD_COUNT * a.nslices);
     const int slice = rem / XCD_COUNT;
-    const int q = grp * XCD_COUNT + rem % XCD_COUNT;
-    if (q >= nblk) return;  // padding of the last group: nobody waits for it
-    const int k = FWD ? q : nblk - 1 - q;
+    const int sq = grp * XCD_COUNT + rem % XCD_COUNT;
+    if (sq >= nsup) return;  // padding of the last group: nobody waits for it
+    const int q = sq * R;    // position of the first own block row in dependency order
     const int64_t c0 = (int64_t)slice * CS;
-    int64_t r0;
-    int cnt;
-    block_rows(a, k, &r0, &cnt);
-
-    // the diagonal block's inverse, needed last: fetch it now
-    const T* wk = a.w + (int64_t)k * BS * BS;
-    T wreg[LPT];
+    // own block rows: position q + x in dependency order (present when < nblk)
+    int kx[R], cntx[R];
+    int64_t r0x[R];
 #pragma unroll
-    for (int e = 0; e < LPT; e++) {
-        const int idx = t + 256 * e, i = idx / BS, kk = idx % BS;
-        wreg[e] = (i < cnt && kk < cnt) ? (FWD ? wk[i * BS + kk] : wk[kk * BS + i]) : T(0);
+    for (int x = 0; x < R; x++) {
+        const int qx = q + x < nblk ? q + x : q;
+        kx[x] = FWD ? qx : nblk - 1 - qx;
+        block_rows(a, kx[x], &r0x[x], &cntx[x]);
+    }
+    const bool has2 = R == 2 && q + 1 < nblk;
+
+    // the diagonal block's inverse, needed last (R = 1: fetched into
+    // registers now; R = 2: both inverses and the block coupling the two rows
+    // staged in LDS before the dependency loop)
+    T wreg[R == 1 ? LPT : 1];
+    auto fetch_w = [&](int x, T (&dst)[LPT]) {
+        const T* wk = a.w + (int64_t)kx[x] * BS * BS;
+        const int cnt = cntx[x];
+#pragma unroll
+        for (int e = 0; e < LPT; e++) {
+            const int idx = t + 256 * e, i = idx / BS, kk = idx % BS;
+            dst[e] = (i < cnt && kk < cnt) ? (FWD ? wk[i * BS + kk] : wk[kk * BS + i]) : T(0);
+        }
+    };
+    if constexpr (R == 1) {
+        fetch_w(0, wreg);
+    } else {
+        T tmp[LPT];
+#pragma unroll
+        for (int x = 0; x < R; x++) {
+            fetch_w(x, tmp);
+#pragma unroll
+            for (int e = 0; e < LPT; e++) {
+                const int idx = t + 256 * e;
+                Wd[x][idx / BS][idx % BS] = tmp[e];
+            }
+        }
+        if (has2) {
+            int64_t si, sk;
+            const T* lp = dep_block<T, FWD>(a, kx[1], r0x[1], kx[0], r0x[0], &si, &sk);
+#pragma unroll
+            for (int e = 0; e < LPT; e++) {
+                const int idx = t + 256 * e, i = idx / BS, kk = idx % BS;  // L(i, kk) of the coupling block
+                Cd[i][kk] = (i < cntx[1] && kk < cntx[0]) ? lp[i * si + kk * sk] : T(0);
+            }
+        }
+        __syncthreads();
     }
 
     typedef typename MT<T>::acc acc_t;
-    acc_t acc[NCB];
+    acc_t acc[R][NCB];
     // B_k in the MFMA result layout: wave w holds rows 16w .. 16w + 15
 #pragma unroll
-    for (int cb = 0; cb < NCB; cb++)
+    for (int x = 0; x < R; x++)
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const int i = 16 * w + MT<T>::row(lane, e);
-            const int64_t c = c0 + cb * 16 + r;
-            acc[cb][e] = (i < cnt && c < a.nrhs) ? a.b[(r0 + i) + c * a.ldb] : T(0);
-        }
+        for (int cb = 0; cb < NCB; cb++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int i = 16 * w + MT<T>::row(lane, e);
+                const int64_t c = c0 + cb * 16 + r;
+                const bool in = x == 0 || has2;
+                acc[x][cb][e] = (in && i < cntx[x] && c < a.nrhs) ? a.b[(r0x[x] + i) + c * a.ldb] : T(0);
+            }
 
-    // factor block of dependency d into registers (all loads in flight at once);
-    // the thread's element e is (i, kk) = (idx % BS, idx / BS) when i runs along
-    // the unit stride, else (idx / BS, idx % BS), idx = t + 256 e
-    T lreg[LPT];
-    bool i_fast = true;
-    auto fetch_l = [&](int d) {
+    // Factor blocks stream through a ring of PD register buffers, PD - 1
+    // blocks ahead of the products: a workgroup behind the front of published
+    // rows is otherwise bound by one memory latency per block.  Step s applies
+    // dependency s / R to own row s % R.  The thread's element e of a block is
+    // (i, kk) = (idx % BS, idx / BS) when i runs along the unit stride, else
+    // (idx / BS, idx % BS), idx = t + 256 e.
+    constexpr int PD = NCB == 1 ? 4 : 2;
+    static_assert(PD % R == 0, "ring slots map to fixed own rows");
+    const int nsteps = q * R;
+    T lreg[PD][LPT];
+    bool ifast[PD];
+    auto fetch_s = [&](int st, T (&dst)[LPT], bool& i_fast) {
+        const int d = st / R, x = st % R;
         const int j = FWD ? d : nblk - 1 - d;
         int64_t rj, si, sk;
         int cntj;
         block_rows(a, j, &rj, &cntj);
-        const T* lp = dep_block<T, FWD>(a, k, r0, j, rj, &si, &sk);
+        const T* lp = dep_block<T, FWD>(a, kx[x], r0x[x], j, rj, &si, &sk);
         i_fast = si == 1;
+        const int cnt = (x == 0 || has2) ? cntx[x] : 0;
 #pragma unroll
         for (int e = 0; e < LPT; e++) {
             const int idx = t + 256 * e;
             const int i = i_fast ? idx % BS : idx / BS, kk = i_fast ? idx / BS : idx % BS;
-            lreg[e] = (i < cnt && kk < cntj) ? lp[i * si + kk * sk] : T(0);
+            dst[e] = (i < cnt && kk < cntj) ? lp[i * si + kk * sk] : T(0);
         }
     };
-    if (q > 0) fetch_l(0);
+#pragma unroll
+    for (int p = 0; p < PD - 1; p++)
+        if (p < nsteps) fetch_s(p, lreg[p], ifast[p]);
 
     // Readiness is learnt in batches: wave 0 reads the flags of up to 64
     // upcoming dependencies at once and one acquire covers every dependency
@@ -196,110 +257,163 @@ __global__ __launch_bounds__(256) void block_solve_kernel(SolveArgs<T> a)
     bool ok = true;
     int ready = 0;  // dependencies 0 .. ready-1 are known to be published
     __shared__ int ready_sh;
-    for (int d = 0; d < q; d++) {
+    auto wait_ready = [&](int d) {  // workgroup-uniform; false when a wait gave up
+        if (w == 0) {
+            const int dd = d + lane;
+            const int jj = FWD ? dd : nblk - 1 - dd;
+            const int* f = a.flags + (int64_t)jj * a.nslices + slice;
+            int spins = 0, avail = 0;
+            for (;;) {
+                const bool rdy =
+                    dd < q && __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
+                const uint64_t m = __ballot(rdy);
+                avail = ~m ? __builtin_ctzll(~m) : 64;  // published run starting at d
+                if (avail > 0 || spins >= a.spin_limit) break;
+                spins++;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (lane == 0) ready_sh = avail > 0 ? d + avail : -1;
+        }
+        __syncthreads();
+        ready = ready_sh;
+        return ready >= 0;
+    };
+    // Rows solved by other workgroups are read with device-scope loads:
+    // when block rows share cache lines (an unaligned m1 or ldb), this
+    // workgroup's own first read of B_k may have cached a neighbour's
+    // unsolved rows, and a plain load could be served that stale copy.
+    // The rows of dependencies already known to be published go through a
+    // ring of YD register buffers, up to YD - 1 dependencies ahead.
+    constexpr int YD = PD / R;
+    T yreg[YD][YPT];
+    int yfetched = 0;  // dependencies whose rows have been loaded into the ring
+    auto fetch_y = [&](int d, T (&dst)[YPT]) {
         const int j = FWD ? d : nblk - 1 - d;
         int64_t rj;
         int cntj;
         block_rows(a, j, &rj, &cntj);
 #pragma unroll
-        for (int e = 0; e < LPT; e++) {
-            const int idx = t + 256 * e;
-            const int i = i_fast ? idx % BS : idx / BS, kk = i_fast ? idx / BS : idx % BS;
-            Ls[i][kk] = lreg[e];
-        }
-        if (d >= ready) {
-            if (w == 0) {
-                const int dd = d + lane;
-                const int jj = FWD ? dd : nblk - 1 - dd;
-                const int* f = a.flags + (int64_t)jj * a.nslices + slice;
-                int spins = 0, avail = 0;
-                for (;;) {
-                    const bool rdy =
-                        dd < q && __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch;
-                    const uint64_t m = __ballot(rdy);
-                    avail = ~m ? __builtin_ctzll(~m) : 64;  // published run starting at d
-                    if (avail > 0 || spins >= a.spin_limit) break;
-                    spins++;
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                if (lane == 0) ready_sh = avail > 0 ? d + avail : -1;
-            }
-            __syncthreads();
-            ready = ready_sh;
-            if (ready < 0) {
-                ok = false;
-                break;
-            }
-        }
-        // Rows solved by other workgroups are read with device-scope loads:
-        // when block rows share cache lines (an unaligned m1 or ldb), this
-        // workgroup's own first read of B_k may have cached a neighbour's
-        // unsolved rows, and a plain load could be served that stale copy.
-        T yreg[YPT];
-#pragma unroll
         for (int e = 0; e < YPT; e++) {
             const int idx = t + 256 * e, kk = idx % BS, c = idx / BS;
-            yreg[e] = (kk < cntj && c0 + c < a.nrhs)
+            dst[e] = (kk < cntj && c0 + c < a.nrhs)
                           ? __hip_atomic_load(&a.b[(rj + kk) + (c0 + c) * a.ldb], __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT)
                           : T(0);
         }
-        if (d + 1 < q) fetch_l(d + 1);  // overlaps this step's products
-#pragma unroll
-        for (int e = 0; e < YPT; e++) {
-            const int idx = t + 256 * e;
-            Ys[idx / BS][idx % BS] = yreg[e];
-        }
-        __syncthreads();
+    };
+    // ac -= M Ys (M: Ls, or the coupling block)
+    auto product = [&](acc_t (&ac)[NCB], T (&M)[BS][P]) {
 #pragma unroll 4
         for (int kk = 0; kk < BS; kk += 4) {
-            const T av = -Ls[16 * w + r][kk + g];
+            const T av = -M[16 * w + r][kk + g];
 #pragma unroll
-            for (int cb = 0; cb < NCB; cb++) acc[cb] = MT<T>::op(av, Ys[cb * 16 + r][kk + g], acc[cb]);
+            for (int cb = 0; cb < NCB; cb++) ac[cb] = MT<T>::op(av, Ys[cb * 16 + r][kk + g], ac[cb]);
         }
-        __syncthreads();
+    };
+    for (int s0 = 0; s0 < nsteps && ok; s0 += PD) {
+#pragma unroll
+        for (int p = 0; p < PD; p++) {
+            const int st = s0 + p, x = p % R, d = st / R, ys = (p / R) % YD;  // d % YD == ys
+            if (st < nsteps && ok) {
+#pragma unroll
+                for (int e = 0; e < LPT; e++) {
+                    const int idx = t + 256 * e;
+                    const int i = ifast[p] ? idx % BS : idx / BS, kk = ifast[p] ? idx / BS : idx % BS;
+                    Ls[i][kk] = lreg[p][e];
+                }
+                if (x == 0) {
+                    if (yfetched <= d) {
+                        if (d >= ready && !wait_ready(d)) ok = false;
+                        if (ok) fetch_y(d, yreg[ys]);
+                        yfetched = d + 1;
+                    }
+#pragma unroll
+                    for (int e = 0; e < YPT; e++) {
+                        const int idx = t + 256 * e;
+                        Ys[idx / BS][idx % BS] = yreg[ys][e];
+                    }
+                }
+                if (ok) {
+                    __syncthreads();
+                    const int sn = st + PD - 1;  // the ring slot just freed
+                    if (sn < nsteps) fetch_s(sn, lreg[(p + PD - 1) % PD], ifast[(p + PD - 1) % PD]);
+                    if (x == R - 1) {
+#pragma unroll
+                        for (int u = 1; u < YD; u++) {
+                            const int dd = d + u;
+                            if (dd >= yfetched && dd < q && dd < ready) {
+                                fetch_y(dd, yreg[(ys + u) % YD]);
+                                yfetched = dd + 1;
+                            }
+                        }
+                    }
+                    product(acc[x], Ls);
+                    __syncthreads();
+                }
+            }
+        }
     }
 
-    // X_k = W_k acc (forward) or W_k^T acc (backward)
-#pragma unroll
-    for (int e = 0; e < LPT; e++) {
-        const int idx = t + 256 * e;
-        Ls[idx / BS][idx % BS] = wreg[e];
-    }
-#pragma unroll
-    for (int cb = 0; cb < NCB; cb++)
-#pragma unroll
-        for (int e = 0; e < 4; e++) Ys[cb * 16 + r][16 * w + MT<T>::row(lane, e)] = acc[cb][e];
-    __syncthreads();
-    acc_t out[NCB];
-#pragma unroll
-    for (int cb = 0; cb < NCB; cb++) out[cb] = acc_t{0, 0, 0, 0};
-#pragma unroll 4
-    for (int kk = 0; kk < BS; kk += 4) {
-        const T av = Ls[16 * w + r][kk + g];
-#pragma unroll
-        for (int cb = 0; cb < NCB; cb++) out[cb] = MT<T>::op(av, Ys[cb * 16 + r][kk + g], out[cb]);
-    }
+    // Own row x: X_k = W_k acc (forward) or W_k^T acc (backward), stored and
+    // published; for a pair, the second row first subtracts the coupling
+    // block times the first row's solution (through LDS).
     const T nan = T(__builtin_nan(""));
+    auto solve_own = [&](int x) {
+        if constexpr (R == 1) {
 #pragma unroll
-    for (int cb = 0; cb < NCB; cb++)
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const int i = 16 * w + MT<T>::row(lane, e);
-            const int64_t c = c0 + cb * 16 + r;
-            if (i < cnt && c < a.nrhs)
-                __hip_atomic_store(&a.b[(r0 + i) + c * a.ldb], ok ? out[cb][e] : nan, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            for (int e = 0; e < LPT; e++) {
+                const int idx = t + 256 * e;
+                Ls[idx / BS][idx % BS] = wreg[e];
+            }
         }
-    if (!ok && t == 0 && a.status) atomicOr(a.status, 1);
-    // publish: every wavefront waits for its device-scope stores to complete,
-    // then one thread raises the flag with a release store
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (t == 0)
-        __hip_atomic_store(a.flags + (int64_t)k * a.nslices + slice, epoch, __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        T(&Wm)[BS][P] = R == 1 ? Ls : reinterpret_cast<T(&)[BS][P]>(Wd[x]);
+#pragma unroll
+        for (int cb = 0; cb < NCB; cb++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) Ys[cb * 16 + r][16 * w + MT<T>::row(lane, e)] = acc[x][cb][e];
+        __syncthreads();
+        acc_t out[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; cb++) out[cb] = acc_t{0, 0, 0, 0};
+#pragma unroll 4
+        for (int kk = 0; kk < BS; kk += 4) {
+            const T av = Wm[16 * w + r][kk + g];
+#pragma unroll
+            for (int cb = 0; cb < NCB; cb++) out[cb] = MT<T>::op(av, Ys[cb * 16 + r][kk + g], out[cb]);
+        }
+        __syncthreads();  // every wave is done with Ys
+#pragma unroll
+        for (int cb = 0; cb < NCB; cb++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int i = 16 * w + MT<T>::row(lane, e);
+                const int64_t c = c0 + cb * 16 + r;
+                const T v = ok ? out[cb][e] : nan;
+                Ys[cb * 16 + r][i] = v;  // the solved rows, for the second row of a pair
+                if (i < cntx[x] && c < a.nrhs)
+                    __hip_atomic_store(&a.b[(r0x[x] + i) + c * a.ldb], v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        if (!ok && t == 0 && a.status) atomicOr(a.status, 1);
+        // publish: every wavefront waits for its device-scope stores to
+        // complete, then one thread raises the flag with a release store
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (t == 0)
+            __hip_atomic_store(a.flags + (int64_t)kx[x] * a.nslices + slice, epoch, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    };
+    solve_own(0);
+    if constexpr (R == 2) {
+        if (has2) {
+            // acc_1 -= L(k1, k0) X_k0, with X_k0 in Ys
+            __syncthreads();
+            product(acc[1], reinterpret_cast<T(&)[BS][P]>(Cd));
+            __syncthreads();
+            solve_own(1);
+        }
+    }
 }
 
 // Epoch of the next fused solve on a flag array: epoch + 1, wrapping to 1
@@ -345,25 +459,49 @@ hipError_t fill_int(hipStream_t s, int* p, int64_t n, int v)
     return hipGetLastError();
 }
 
-template <typename T, int NCB>
-static hipError_t launch_solve(const Exec& ex, bool forward, const SolveArgs<T>& a, int nblk)
+// Block rows per workgroup for 16-column slices: 2, or 1 with RFP_SOLVE_PAIR=0.
+static int solve_rows_per_group()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("RFP_SOLVE_PAIR");
+        v = (e && e[0] == '0') ? 1 : 2;
+    }
+    return v;
+}
+
+template <typename T, int NCB, int R>
+static hipError_t launch_solve_r(const Exec& ex, bool forward, const SolveArgs<T>& a, int nblk)
 {
     static char names[2][2][112];
     const int ti = sizeof(T) == 8 ? 0 : 1, di = forward ? 0 : 1;
     char* nm = names[ti][di];
     if (!nm[0]) {
         const char* tn = ti ? "float" : "double";
-        snprintf(nm, sizeof names[ti][di], "rfp::block_solve_kernel<%s, %d, %s>(rfp::SolveArgs<%s>)", tn, NCB,
-                 forward ? "true" : "false", tn);
+        snprintf(nm, sizeof names[ti][di], "rfp::block_solve_kernel<%s, %d, %s, %d>(rfp::SolveArgs<%s>)", tn, NCB,
+                 forward ? "true" : "false", R, tn);
     }
     const double mtot = (double)(a.m1 + a.m2);
     ProfScope ps(ex, nm, mtot * mtot * (double)a.nrhs,
                  sizeof(T) * (mtot * mtot / 2 * a.nslices + 2.0 * mtot * (double)a.nrhs));
-    const int groups = (nblk + XCD_COUNT - 1) / XCD_COUNT;
+    const int nsup = (nblk + R - 1) / R;
+    const int groups = (nsup + XCD_COUNT - 1) / XCD_COUNT;
     const dim3 grid((unsigned)(groups * XCD_COUNT * a.nslices));
-    if (forward) hipLaunchKernelGGL((block_solve_kernel<T, NCB, true>), grid, dim3(256), 0, ex.stream, a);
-    else hipLaunchKernelGGL((block_solve_kernel<T, NCB, false>), grid, dim3(256), 0, ex.stream, a);
+    if (forward) hipLaunchKernelGGL((block_solve_kernel<T, NCB, true, R>), grid, dim3(256), 0, ex.stream, a);
+    else hipLaunchKernelGGL((block_solve_kernel<T, NCB, false, R>), grid, dim3(256), 0, ex.stream, a);
     return hipGetLastError();
+}
+
+template <typename T, int NCB>
+static hipError_t launch_solve(const Exec& ex, bool forward, const SolveArgs<T>& a, int nblk)
+{
+    // pairs (and the deeper ring) for 16-column slices, where a workgroup
+    // streams the most factor blocks per right-hand side; wider slices keep
+    // one block row per workgroup and a ring of two (more resident
+    // workgroups measured faster there: n = 20000, 128 right-hand sides)
+    if constexpr (NCB == 1)
+        if (solve_rows_per_group() == 2) return launch_solve_r<T, NCB, 2>(ex, forward, a, nblk);
+    return launch_solve_r<T, NCB, 1>(ex, forward, a, nblk);
 }
 
 // Slice width in 16-column blocks: narrow slices shorten each block row's

@@ -151,3 +151,48 @@ def test_packed_conversions_bit_exact(h, transr, uplo, n):
     rfp.rfp_dtfttp(h, transr, uplo, n, arf, back)
     assert np.array_equal(host(back), ap)
     assert np.array_equal(oracle.tfttp(transr, uplo, n, want), ap)
+
+
+def _sfmv(h, transr, uplo, n, alpha, arf, X, beta, Y):
+    x = dev_colmajor(X)
+    y = dev_colmajor(Y)
+    rfp.rfp_dsfmv(h, transr, uplo, n, alpha, dev(arf), x, beta, y)
+    return host_colmajor(y)
+
+
+@pytest.mark.parametrize("transr,uplo", LAYOUTS)
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 300, 513, 1001])
+@pytest.mark.parametrize("nrhs", [1, 16, 17])
+def test_sfmv(h, transr, uplo, n, nrhs):
+    """Symmetric product against the oracle: every element within the bound
+    of a reordered FP64 sum, 4 n u (|alpha| |A| |X| + |beta| |Y|)."""
+    A, _ = synth.spd(n, seed=n + 80)
+    arf = oracle.trttf(transr, uplo, A)
+    g = synth.rng(n + nrhs)
+    X = g.standard_normal((n, nrhs))
+    Y = g.standard_normal((n, nrhs))
+    for alpha, beta in [(-1.0, 1.0), (2.5, 0.0)]:
+        Yin = Y if beta != 0.0 else np.full((n, nrhs), np.nan)
+        got = _sfmv(h, transr, uplo, n, alpha, arf, X, beta, Yin)
+        want = oracle.sfmv(transr, uplo, n, alpha, arf, X, beta, Yin if beta != 0.0 else np.zeros((n, nrhs)))
+        bound = 4 * n * 2.0 ** -53 * (abs(alpha) * (np.abs(A) @ np.abs(X)) + abs(beta) * np.abs(Y))
+        assert np.all(np.abs(got - want) <= bound + 1e-300), (alpha, beta)
+
+
+@pytest.mark.parametrize("transr,uplo", LAYOUTS)
+@pytest.mark.parametrize("n", [257, 1000, 3001])
+def test_sfmv_exact_and_repeatable(h, transr, uplo, n):
+    """Integer data (the min matrix, integer columns; every partial sum an
+    integer below 2^53) gives the exact product; a second call gives the same
+    bits for random data."""
+    A = synth.min_matrix(n)
+    arf = oracle.trttf(transr, uplo, A)
+    X = synth.rng(n).integers(-3, 4, size=(n, 20)).astype(np.float64)
+    got = _sfmv(h, transr, uplo, n, 1.0, arf, X, 0.0, np.zeros((n, 20)))
+    assert np.array_equal(got, A @ X)
+    B, _ = synth.spd(n, seed=n + 5)
+    brf = oracle.trttf(transr, uplo, B)
+    Xr = synth.rng(n + 1).standard_normal((n, 16))
+    y1 = _sfmv(h, transr, uplo, n, 1.0, brf, Xr, 0.0, np.zeros((n, 16)))
+    y2 = _sfmv(h, transr, uplo, n, 1.0, brf, Xr, 0.0, np.zeros((n, 16)))
+    assert np.array_equal(y1, y2)

@@ -139,3 +139,30 @@ def test_sfrk_closed_form(transr, uplo):
     C2 = oracle.trttf(transr, uplo, np.full((n, n), 2.0))
     got = oracle.sfrk(transr, uplo, "T", n, k, 0.0, np.full((k, n), np.nan, order="F"), -1.5, C2)
     assert np.array_equal(got, np.full(oracle.nt(n), -3.0))
+
+
+@pytest.mark.parametrize("transr,uplo", LAYOUTS)
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 65, 130])
+def test_sfmv_against_numpy(transr, uplo, n):
+    """The symmetric product against numpy's dense product of the unpacked
+    matrix (alpha, beta, several right-hand sides)."""
+    A, _ = synth.spd(n, seed=n + 70)
+    arf = oracle.trttf(transr, uplo, A)
+    g = synth.rng(n + 71)
+    X = g.standard_normal((n, 5))
+    Y = g.standard_normal((n, 5))
+    got = oracle.sfmv(transr, uplo, n, -1.5, arf, X, 0.25, Y)
+    want = -1.5 * (A @ X) + 0.25 * Y
+    assert np.abs(got - want).max() <= 1e-14 * (np.abs(A) @ np.abs(X) + np.abs(Y)).max()
+
+
+@pytest.mark.parametrize("transr,uplo", LAYOUTS)
+def test_sfmv_min_matrix_exact(transr, uplo):
+    """Integers throughout: the min matrix times integer columns is exact, and
+    beta = 0 ignores a NaN-filled Y."""
+    n = 33
+    A = synth.min_matrix(n)
+    arf = oracle.trttf(transr, uplo, A)
+    X = synth.rng(3).integers(-4, 5, size=(n, 3)).astype(np.float64)
+    got = oracle.sfmv(transr, uplo, n, 1.0, arf, X, 0.0, np.full((n, 3), np.nan))
+    assert np.array_equal(got, A @ X)
