@@ -232,15 +232,18 @@ int rfp_dsfmv(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, d
  *   (FP64, from arf), until the normwise backward error
  *   max_c ||R_c||_inf / (||A||_inf ||X_c||_inf + ||B_c||_inf) is <= tol.
  *   A sweep is X += M^{-1} R (classical refinement) until one fails to cut
- *   the backward error fourfold; later sweeps run 8 steps of conjugate
- *   gradients on A D = R preconditioned by M^{-1}, in FP64 (refinement with a
- *   CG inner solver; M^{-1} is then applied in FP64 arithmetic from an FP64
- *   copy of Ls, so that it is symmetric to FP64 rounding), which converges
- *   where kappa(A) u_low is not small.
+ *   the backward error fourfold; later sweeps run 4 steps of conjugate
+ *   gradients on A X = B preconditioned by M^{-1}, in FP64, one recurrence
+ *   continued from sweep to sweep and restarted from the true residual R at
+ *   each sweep (refinement with a CG inner solver; M^{-1} is then applied in
+ *   FP64 arithmetic from an FP64 copy of Ls, so that it is symmetric to FP64
+ *   rounding), which converges where kappa(A) u_low is not small.
  * Falls back to the FP64 PFTRF + PFTRS on a copy of A when the scaled copy
  * is not finite, when the low-precision factor is not positive definite,
- * when a conjugate-gradient sweep fails to cut the backward error below 0.9
- * times the previous one, or after max_iter sweeps.
+ * when 3 conjugate-gradient sweeps in a row fail to bring the backward error
+ * below 0.9 times its best value (conjugate gradients minimise the error's
+ * A-norm, so the residual need not fall every sweep), or after max_iter
+ * sweeps.
  * Every decision is taken on the device: the call enqueues the setup,
  * max_iter sweeps and the fall-back without waiting, and what is not needed
  * exits at once.  It never synchronises; once the handle's workspace has been
@@ -287,11 +290,12 @@ typedef struct {
  *     else 1; c u as in rfp_set_lowp_shift) with
  *     its bulk updates on operands rounded to fprec (FP32 accumulation), and
  *     FP64 refinement against the untouched FP64 matrix until the normwise
- *     backward error is <= tol, with the sweeps of rfp_dpfsv_ir (classical,
- *     then 8 preconditioned conjugate-gradient steps in FP64 once a sweep
- *     fails to cut the backward error fourfold; stalled when such a sweep
- *     fails to cut it below 0.9 times the previous one; at most max_iter
- *     sweeps); on failure the FP64 factor and solve run on arf.
+ *     backward error is <= tol, with sweeps as in rfp_dpfsv_ir (classical,
+ *     then sweeps of up to 8 preconditioned conjugate-gradient steps in FP64
+ *     once a sweep fails to cut the backward error fourfold; stalled after 3
+ *     such sweeps in a row that do not bring it below 0.9 times its best
+ *     value; at most max_iter sweeps); on failure the FP64 factor and solve
+ *     run on arf.
  * With do_pftri != 0, arf ends as the RFP array of A^{-1} (PFTRI after an
  * FP64 factor, in every mode).  Device outputs per system: info[i] = 0 or the
  * FP64 PFTRF INFO (first non-positive pivot, 1-based), -1 for a refused
@@ -377,7 +381,8 @@ int rfp_set_solve_wait_limit(rfp_handle_t h, int64_t polls);
  *     beyond what it uses, to keep large GEMM workgroups off its compute unit
  *     (default 24576; 0 to 65536).
  *   wide_panel_cols: width of the wide panels, a multiple of 128 (default
- *     256).  A wide panel's diagonal block is factored by the 2 x 2 partition
+ *     256; FP16 and BF16-operand factorizations use 1024 unless a schedule
+ *     was set or tuned).  A wide panel's diagonal block is factored by the 2 x 2 partition
  *     down to 128-row leaves; a width at least the triangle's order factors
  *     the whole triangle that way (a fully recursive factorization, whose
  *     trailing updates have the largest inner dimensions and so the least

@@ -752,6 +752,9 @@ static int pftrf_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
         if (n == 0) return set_int(s, info, 0) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
         if (prepare(h, size_t(lv) * NB2 * NB2 * sizeof(T)) != hipSuccess) return RFP_ERR_RUNTIME;
         sc = schedule_for(h, n);
+        const bool tuned = h->tune && h->tune->sched.count(size_bucket(n));
+        if ((lowp == RFP_PREC_FP16 || lowp == RFP_PREC_BF16) && !h->sched_user && !tuned)
+            sc.wide_panel_cols = DEFAULT_LOWP_WIDE_PANEL_COLS;
         r = make_run<T>(h, s, info, lowp, &sc);
         winv = (T*)h->inv;
     }
@@ -1118,7 +1121,7 @@ static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64
     // conjugate-gradient steps instead.  Both kinds are enqueued for every
     // sweep; the gates let exactly one of them run, and none after the
     // refinement has ended.
-    constexpr int PCG_STEPS = 8;
+    constexpr int PCG_STEPS = 4;
     ok(ir_copy(st, w.r, n, b, ldb, n, nrhs, ex_run.gate));
     ok(ir_copy(st, x, ldx, nullptr, 0, n, nrhs, ex_run.gate));
     for (int it = 1; it <= max_iter && e == hipSuccess; it++) {

@@ -55,6 +55,8 @@ inline int64_t regions(int64_t len) { return (len + RS - 1) / RS; }
 
 }  // namespace
 
+__device__ double g_symv_zero = 0.0;  // never written
+
 __global__ __launch_bounds__(256) void symv_region_kernel(RegionArgs p)
 {
     __shared__ __attribute__((aligned(16))) double As[TT][SP];       // tile, As[row][col]
@@ -101,7 +103,10 @@ __global__ __launch_bounds__(256) void symv_region_kernel(RegionArgs p)
             const int li = rows_fast ? idx % TT : idx / TT, lk = rows_fast ? idx / TT : idx % TT;
             const int64_t i = ti + li, kk = tj + lk;
             const bool ok = i < p.m && kk < p.k && (!dtile || li >= lk);
-            ra[e] = ok ? p.a.at(i, kk) : 0.0;
+            // a masked-off element is loaded from a zero in device memory:
+            // every load is issued (no branch), so the wait for this tile
+            // does not wait for the loads issued after it
+            ra[e] = *(ok ? &p.a.at(i, kk) : &g_symv_zero);
         }
     };
     auto next_of = [&](int q) {  // first present tile at or after position q, else RG * RG

@@ -59,6 +59,20 @@ struct MT<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+// One zero of each type in device memory: a masked-off element is loaded
+// from here instead of being skipped, so that every load of a block is
+// issued unconditionally (no branch around it) and the compiler can count
+// the loads still in flight (a wait for one ring slot then leaves the later
+// slots' loads outstanding).  Never written.
+__device__ double g_zero_d = 0.0;
+__device__ float g_zero_f = 0.0f;
+template <typename T>
+__device__ __forceinline__ const T* zero_ptr()
+{
+    if constexpr (sizeof(T) == 8) return (const T*)&g_zero_d;
+    else return (const T*)&g_zero_f;
+}
+
 constexpr int BS = NB;     // rows per block row
 constexpr int P = BS + 4;  // LDS row pitch
 
@@ -176,7 +190,7 @@ __global__ __launch_bounds__(256) void block_solve_kernel(SolveArgs<T> a)
 #pragma unroll
         for (int e = 0; e < LPT; e++) {
             const int idx = t + 256 * e, i = idx / BS, kk = idx % BS;
-            dst[e] = (i < cnt && kk < cnt) ? (FWD ? wk[i * BS + kk] : wk[kk * BS + i]) : T(0);
+            dst[e] = *((i < cnt && kk < cnt) ? wk + (FWD ? i * BS + kk : kk * BS + i) : zero_ptr<T>());
         }
     };
     if constexpr (R == 1) {
@@ -243,7 +257,7 @@ __global__ __launch_bounds__(256) void block_solve_kernel(SolveArgs<T> a)
         for (int e = 0; e < LPT; e++) {
             const int idx = t + 256 * e;
             const int i = i_fast ? idx % BS : idx / BS, kk = i_fast ? idx / BS : idx % BS;
-            dst[e] = (i < cnt && kk < cntj) ? lp[i * si + kk * sk] : T(0);
+            dst[e] = *((i < cnt && kk < cntj) ? lp + i * si + kk * sk : zero_ptr<T>());
         }
     };
 #pragma unroll
@@ -296,10 +310,8 @@ __global__ __launch_bounds__(256) void block_solve_kernel(SolveArgs<T> a)
 #pragma unroll
         for (int e = 0; e < YPT; e++) {
             const int idx = t + 256 * e, kk = idx % BS, c = idx / BS;
-            dst[e] = (kk < cntj && c0 + c < a.nrhs)
-                          ? __hip_atomic_load(&a.b[(rj + kk) + (c0 + c) * a.ldb], __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT)
-                          : T(0);
+            const T* src = (kk < cntj && c0 + c < a.nrhs) ? &a.b[(rj + kk) + (c0 + c) * a.ldb] : zero_ptr<T>();
+            dst[e] = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     };
     // ac -= M Ys (M: Ls, or the coupling block)
