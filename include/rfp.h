@@ -232,7 +232,7 @@ int rfp_dsfmv(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, d
  *   (FP64, from arf), until the normwise backward error
  *   max_c ||R_c||_inf / (||A||_inf ||X_c||_inf + ||B_c||_inf) is <= tol.
  *   A sweep is X += M^{-1} R (classical refinement) until one fails to cut
- *   the backward error fourfold; later sweeps run 4 steps of conjugate
+ *   the backward error fourfold; later sweeps run 8 steps of conjugate
  *   gradients on A X = B preconditioned by M^{-1}, in FP64, one recurrence
  *   continued from sweep to sweep and restarted from the true residual R at
  *   each sweep (refinement with a CG inner solver; M^{-1} is then applied in

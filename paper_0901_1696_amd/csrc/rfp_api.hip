@@ -1121,7 +1121,7 @@ static int pfsv_ir_impl(rfp_context* h, int fprec, char transr, char uplo, int64
     // conjugate-gradient steps instead.  Both kinds are enqueued for every
     // sweep; the gates let exactly one of them run, and none after the
     // refinement has ended.
-    constexpr int PCG_STEPS = 4;
+    constexpr int PCG_STEPS = 8;
     ok(ir_copy(st, w.r, n, b, ldb, n, nrhs, ex_run.gate));
     ok(ir_copy(st, x, ldx, nullptr, 0, n, nrhs, ex_run.gate));
     for (int it = 1; it <= max_iter && e == hipSuccess; it++) {
