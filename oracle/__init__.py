@@ -83,6 +83,24 @@ def _declare(L):
     L.orc_factor_residual.argtypes = [_chr, _chr, _i64, _dp, _dp]
     L.orc_inverse_residual.restype = ctypes.c_double
     L.orc_inverse_residual.argtypes = [_chr, _chr, _i64, _dp, _dp]
+    # complex Hermitian (zrfp_oracle.c): complex arrays as interleaved doubles
+    L.orc_zrfp_pos.restype = _i64
+    L.orc_zrfp_pos.argtypes = [_chr, _chr, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_int)]
+    L.orc_ztrttf.restype = None
+    L.orc_ztrttf.argtypes = [_chr, _chr, _i64, _dp, _i64, _dp]
+    L.orc_ztfttr.restype = None
+    L.orc_ztfttr.argtypes = [_chr, _chr, _i64, _dp, _dp, _i64]
+    for name in ("orc_zpftrf", "orc_zpftrf_srpa", "orc_zpftri"):
+        getattr(L, name).restype = ctypes.c_int
+        getattr(L, name).argtypes = [_chr, _chr, _i64, _dp]
+    L.orc_zpftrs.restype = None
+    L.orc_zpftrs.argtypes = [_chr, _chr, _i64, _i64, _dp, _dp, _i64]
+    L.orc_zbackward_error.restype = ctypes.c_double
+    L.orc_zbackward_error.argtypes = [_chr, _chr, _i64, _i64, _dp, _dp, _i64, _dp, _i64]
+    L.orc_zfactor_residual.restype = ctypes.c_double
+    L.orc_zfactor_residual.argtypes = [_chr, _chr, _i64, _dp, _dp]
+    L.orc_zinverse_residual.restype = ctypes.c_double
+    L.orc_zinverse_residual.argtypes = [_chr, _chr, _i64, _dp, _dp]
 
 
 def _c(ch):
@@ -288,3 +306,85 @@ def rel_fro(x, ref):
 
 
 LAYOUTS = [(t, u) for t in "NT" for u in "LU"]
+
+
+# ------------------------------------------------- complex Hermitian (zrfp)
+ZLAYOUTS = [(t, u) for t in "NC" for u in "LU"]
+
+
+def _zp(a):
+    assert a.dtype == np.complex128 and (a.flags["C_CONTIGUOUS"] or a.flags["F_CONTIGUOUS"])
+    return a.ctypes.data_as(_dp)
+
+
+def _z(a, order="F"):
+    return np.array(a, dtype=np.complex128, order=order, copy=True)
+
+
+def zrfp_pos(transr, uplo, n, i, j):
+    """(offset, stored number is the conjugate) of stored-triangle element (i, j)."""
+    c = ctypes.c_int(0)
+    p = lib().orc_zrfp_pos(_c(transr), _c(uplo), n, i, j, ctypes.byref(c))
+    return p, bool(c.value)
+
+
+def ztrttf(transr, uplo, a):
+    """Full complex (column-major) -> complex RFP array of n(n+1)/2."""
+    a = _z(a)
+    n = a.shape[1]
+    arf = np.zeros(nt(n), dtype=np.complex128)
+    lib().orc_ztrttf(_c(transr), _c(uplo), n, _zp(a), a.shape[0], _zp(arf))
+    return arf
+
+
+def ztfttr(transr, uplo, n, arf, fill=0.0):
+    a = np.full((n, n), fill, dtype=np.complex128, order="F")
+    arf = np.ascontiguousarray(arf, dtype=np.complex128)
+    lib().orc_ztfttr(_c(transr), _c(uplo), n, _zp(arf), _zp(a), max(n, 1))
+    return a
+
+
+def zpftrf(transr, uplo, n, arf):
+    """Definition-path complex factor.  Returns (factor array, info)."""
+    out = np.array(arf, dtype=np.complex128, copy=True)
+    return out, lib().orc_zpftrf(_c(transr), _c(uplo), n, _zp(out))
+
+
+def zpftrf_srpa(transr, uplo, n, arf):
+    """The paper's four steps, complex Hermitian.  Returns (factor array, info)."""
+    out = np.array(arf, dtype=np.complex128, copy=True)
+    return out, lib().orc_zpftrf_srpa(_c(transr), _c(uplo), n, _zp(out))
+
+
+def zpftrs(transr, uplo, n, arf_factor, b):
+    x = np.array(b, dtype=np.complex128, order="F", copy=True)
+    if x.ndim == 1:
+        x = x.reshape(-1, 1, order="F")
+    arf_factor = np.ascontiguousarray(arf_factor, dtype=np.complex128)
+    lib().orc_zpftrs(_c(transr), _c(uplo), n, x.shape[1], _zp(arf_factor), _zp(x), x.shape[0])
+    return x
+
+
+def zpftri(transr, uplo, n, arf_factor):
+    out = np.array(arf_factor, dtype=np.complex128, copy=True)
+    return out, lib().orc_zpftri(_c(transr), _c(uplo), n, _zp(out))
+
+
+def zbackward_error(transr, uplo, n, arf_a, b, x):
+    b = _z(b if b.ndim == 2 else b.reshape(-1, 1))
+    x = _z(x if x.ndim == 2 else x.reshape(-1, 1))
+    arf_a = np.ascontiguousarray(arf_a, dtype=np.complex128)
+    return lib().orc_zbackward_error(_c(transr), _c(uplo), n, b.shape[1], _zp(arf_a), _zp(b), b.shape[0],
+                                     _zp(x), x.shape[0])
+
+
+def zfactor_residual(transr, uplo, n, arf_a, arf_l):
+    arf_a = np.ascontiguousarray(arf_a, dtype=np.complex128)
+    arf_l = np.ascontiguousarray(arf_l, dtype=np.complex128)
+    return lib().orc_zfactor_residual(_c(transr), _c(uplo), n, _zp(arf_a), _zp(arf_l))
+
+
+def zinverse_residual(transr, uplo, n, arf_a, arf_inv):
+    arf_a = np.ascontiguousarray(arf_a, dtype=np.complex128)
+    arf_inv = np.ascontiguousarray(arf_inv, dtype=np.complex128)
+    return lib().orc_zinverse_residual(_c(transr), _c(uplo), n, _zp(arf_a), _zp(arf_inv))
