@@ -88,6 +88,54 @@ int rfp_dpftrs(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, 
  * INFO=5. */
 int rfp_dpftri(rfp_handle_t h, char transr, char uplo, int64_t n, double* arf, int* info, hipStream_t stream);
 
+/* ---------------------------------------------------------------------
+ * Complex Hermitian positive definite matrices (the Hermitian case of
+ * Sections 3-5 and the complex rows of the routine table: ZPFTRF, ZPFTRS,
+ * ZPFTRI; A = L L^H or U^H U).
+ *  - Complex arrays are interleaved (re, im) pairs of doubles: element k
+ *    of a complex array p is (p[2k], p[2k+1]); leading dimensions and sizes
+ *    count complex elements.  A torch.complex128 tensor has this layout.
+ *  - TRANSR is 'N' or 'C'.  The RFP array has the positions of the real
+ *    format of the same layout (TRANSR 'C' where the real one has 'T');
+ *    every part that the real format keeps transposed is kept conjugate-
+ *    transposed here (the paper's convention for the complex case).
+ *  - Scratch comes from the handle: leaf inverses of the 64-row diagonal
+ *    blocks plus 64 x max(n, nrhs) complex temporaries.
+ * --------------------------------------------------------------------- */
+
+/* ZTRTTF: the UPLO triangle of the full Hermitian matrix a (column-major,
+ * lda >= max(1,n)) into the RFP array arf.  Argument order: TRANSR=1,
+ * UPLO=2, N=3, A=4, LDA=5, ARF=6. */
+int rfp_ztrttf(rfp_handle_t h, char transr, char uplo, int64_t n, const double* a, int64_t lda, double* arf,
+               hipStream_t stream);
+
+/* ZTFTTR: the RFP array into the UPLO triangle of a (the other triangle is
+ * left untouched).  Argument order: TRANSR=1, UPLO=2, N=3, ARF=4, A=5,
+ * LDA=6. */
+int rfp_ztfttr(rfp_handle_t h, char transr, char uplo, int64_t n, const double* arf, double* a, int64_t lda,
+               hipStream_t stream);
+
+/* ZPFTRF (Section 3, Hermitian case): A = L L^H (UPLO='L') or U^H U ('U')
+ * by the four steps on the blocks of the rectangle (POTRF on T1, TRSM
+ * S <- S L11^{-H}, HERK T2 <- T2 - S S^H, POTRF on T2).  *info (device int)
+ * becomes 0, or p > 0 when the leading minor of order p is not positive
+ * definite (the factorization then stops; arf is partly overwritten).
+ * Argument order: TRANSR=1, UPLO=2, N=3, A=4, INFO=5. */
+int rfp_zpftrf(rfp_handle_t h, char transr, char uplo, int64_t n, double* arf, int* info, hipStream_t stream);
+
+/* ZPFTRS (Section 4, Hermitian case): solve A X = B with the ZPFTRF factor
+ * (L Y = B, then L^H X = Y); X overwrites b (n x nrhs complex, column-major,
+ * ldb >= max(1,n)).  Argument order: TRANSR=1, UPLO=2, N=3, NR=4, A=5, B=6,
+ * LDB=7. */
+int rfp_zpftrs(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, const double* arf, double* b,
+               int64_t ldb, hipStream_t stream);
+
+/* ZPFTRI (Section 5, Hermitian case): from the ZPFTRF factor, the same
+ * triangle of A^{-1} = W^H W, W = L^{-1}, overwrites arf.  *info (device
+ * int) becomes 0, or i > 0 when the factor's diagonal entry i is zero.
+ * Argument order: TRANSR=1, UPLO=2, N=3, A=4, INFO=5. */
+int rfp_zpftri(rfp_handle_t h, char transr, char uplo, int64_t n, double* arf, int* info, hipStream_t stream);
+
 /* TFTRI (the paper's routine table, "Triangular inversion"): the inverse of
  * the triangular matrix T held in arf (UPLO='L' lower, 'U' upper) overwrites
  * it in the same layout, by the inversion stage of PFTRI (Section 5, Figure 4

@@ -81,6 +81,11 @@ _SIGS = {
     "rfp_get_schedule": [_vp, _vp],
     "rfp_profile_enable": [_vp, _int],
     "rfp_profile_read": [_vp, _vp, _int, ctypes.POINTER(_int)],
+    "rfp_ztrttf": [_vp, _chr, _chr, _i64, _vp, _i64, _vp, _vp],
+    "rfp_ztfttr": [_vp, _chr, _chr, _i64, _vp, _vp, _i64, _vp],
+    "rfp_zpftrf": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
+    "rfp_zpftrs": [_vp, _chr, _chr, _i64, _i64, _vp, _vp, _i64, _vp],
+    "rfp_zpftri": [_vp, _chr, _chr, _i64, _vp, _vp, _vp],
 }
 
 
@@ -284,6 +289,47 @@ def rfp_dpftrs_noalloc(transr, uplo, n, arf, b, stream=None):
 
 def rfp_dpftri(h, transr, uplo, n, arf, info, stream=None):
     _check("rfp_dpftri", lib().rfp_dpftri(h.value, _c(transr), _c(uplo), n, _ptr(arf), _ptr(info),
+                                          _stream(stream)))
+
+
+def _zcheck(t, name):
+    import torch
+    if t.dtype != torch.complex128:
+        raise ValueError(f"{name}: expected a torch.complex128 tensor")
+
+
+def rfp_ztrttf(h, transr, uplo, n, a, arf, stream=None):
+    """Complex: full Hermitian (column-major complex128) -> complex RFP (TRANSR 'N' or 'C')."""
+    _zcheck(a, "a")
+    _zcheck(arf, "arf")
+    pa, lda, _ = _colmajor(a, "a")
+    _check("rfp_ztrttf", lib().rfp_ztrttf(h.value, _c(transr), _c(uplo), n, pa, lda, _ptr(arf), _stream(stream)))
+
+
+def rfp_ztfttr(h, transr, uplo, n, arf, a, stream=None):
+    _zcheck(a, "a")
+    _zcheck(arf, "arf")
+    pa, lda, _ = _colmajor(a, "a")
+    _check("rfp_ztfttr", lib().rfp_ztfttr(h.value, _c(transr), _c(uplo), n, _ptr(arf), pa, lda, _stream(stream)))
+
+
+def rfp_zpftrf(h, transr, uplo, n, arf, info, stream=None):
+    _zcheck(arf, "arf")
+    _check("rfp_zpftrf", lib().rfp_zpftrf(h.value, _c(transr), _c(uplo), n, _ptr(arf), _ptr(info),
+                                          _stream(stream)))
+
+
+def rfp_zpftrs(h, transr, uplo, n, arf, b, stream=None):
+    _zcheck(arf, "arf")
+    _zcheck(b, "b")
+    pb, ldb, nrhs = _colmajor(b, "b")
+    _check("rfp_zpftrs", lib().rfp_zpftrs(h.value, _c(transr), _c(uplo), n, nrhs, _ptr(arf), pb, ldb,
+                                          _stream(stream)))
+
+
+def rfp_zpftri(h, transr, uplo, n, arf, info, stream=None):
+    _zcheck(arf, "arf")
+    _check("rfp_zpftri", lib().rfp_zpftri(h.value, _c(transr), _c(uplo), n, _ptr(arf), _ptr(info),
                                           _stream(stream)))
 
 

@@ -135,6 +135,8 @@ struct rfp_context {
     size_t ir_bytes;
     void* bat;            // batched-solver scratch (work counter + per-workgroup scratch)
     size_t bat_bytes;
+    void* zwork;          // complex path: leaf inverses and block temporaries
+    size_t zwork_bytes;
     int cus;              // compute units of the device
     rfp::TuneTable* tune; // autotuned kernel configurations (null: built-in rules)
     rfp_schedule_t sched; // factorization schedule knobs
@@ -1603,6 +1605,7 @@ int rfp_destroy(rfp_handle_t h)
         if (h->flags) (void)hipFree(h->flags);
         if (h->ctl) (void)hipFree(h->ctl);
         if (h->ir) (void)hipFree(h->ir);
+        if (h->zwork) (void)hipFree(h->zwork);
         if (h->bat) (void)hipFree(h->bat);
         delete h->tune;
         for (int i = 0; i < h->nev; i++) (void)hipEventDestroy(h->ev[i]);
@@ -1688,6 +1691,104 @@ int rfp_dpftrs(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, 
 int rfp_dpftri(rfp_handle_t h, char transr, char uplo, int64_t n, double* arf, int* info, hipStream_t stream)
 {
     return pftri_impl<double>(h, transr, uplo, n, arf, info, stream);
+}
+
+// ------------------------------------------------- complex Hermitian path
+static bool zbad_tr(char c) { return upc(c) != 'N' && upc(c) != 'C'; }
+
+static int zconvert_impl(rfp_context* h, char transr, char uplo, int64_t n, double* a, int64_t lda, double* arf,
+                         hipStream_t s, bool to_rfp)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (zbad_tr(transr)) return -1;
+    if (bad_ul(uplo)) return -2;
+    if (n < 0) return -3;
+    if (n == 0) return 0;
+    // TRTTF (.., A=4, LDA=5, ARF=6); TFTTR (.., ARF=4, A=5, LDA=6)
+    if (to_rfp) {
+        if (!a) return -4;
+        if (lda < std::max<int64_t>(1, n)) return -5;
+        if (!arf) return -6;
+    } else {
+        if (!arf) return -4;
+        if (!a) return -5;
+        if (lda < std::max<int64_t>(1, n)) return -6;
+    }
+    DeviceGuard g(h->device);
+    ZRfpViews v;
+    zrfp_views(transr, uplo, n, (double2*)arf, &v);
+    return zconvert(s, v, upc(uplo) == 'U', (double2*)a, lda, to_rfp) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+static hipError_t zensure(rfp_context* h, int64_t n, int64_t nrhs)
+{
+    return ensure(&h->zwork, &h->zwork_bytes, zwork_elems(n, nrhs) * sizeof(double2));
+}
+
+int rfp_ztrttf(rfp_handle_t h, char transr, char uplo, int64_t n, const double* a, int64_t lda, double* arf,
+               hipStream_t stream)
+{
+    return zconvert_impl(h, transr, uplo, n, (double*)a, lda, arf, stream, true);
+}
+
+int rfp_ztfttr(rfp_handle_t h, char transr, char uplo, int64_t n, const double* arf, double* a, int64_t lda,
+               hipStream_t stream)
+{
+    return zconvert_impl(h, transr, uplo, n, a, lda, (double*)arf, stream, false);
+}
+
+int rfp_zpftrf(rfp_handle_t h, char transr, char uplo, int64_t n, double* arf, int* info, hipStream_t stream)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (zbad_tr(transr)) return -1;
+    if (bad_ul(uplo)) return -2;
+    if (n < 0) return -3;
+    if (n > 0 && !arf) return -4;
+    if (!info) return -5;
+    DeviceGuard g(h->device);
+    if (set_int(stream, info, 0) != hipSuccess) return RFP_ERR_RUNTIME;
+    if (n == 0) return 0;
+    if (zensure(h, n, 0) != hipSuccess) return RFP_ERR_RUNTIME;
+    ZRfpViews v;
+    zrfp_views(transr, uplo, n, (double2*)arf, &v);
+    return zpftrf_run(stream, v, (double2*)h->zwork, info) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
+}
+
+int rfp_zpftrs(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, const double* arf, double* b,
+               int64_t ldb, hipStream_t stream)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (zbad_tr(transr)) return -1;
+    if (bad_ul(uplo)) return -2;
+    if (n < 0) return -3;
+    if (nrhs < 0) return -4;
+    if (n > 0 && !arf) return -5;
+    if (n > 0 && nrhs > 0 && !b) return -6;
+    if (ldb < std::max<int64_t>(1, n)) return -7;
+    if (n == 0 || nrhs == 0) return 0;
+    DeviceGuard g(h->device);
+    if (zensure(h, n, nrhs) != hipSuccess) return RFP_ERR_RUNTIME;
+    ZRfpViews v;
+    zrfp_views(transr, uplo, n, (double2*)arf, &v);
+    return zpftrs_run(stream, v, (double2*)b, ldb, nrhs, (double2*)h->zwork, nullptr) == hipSuccess ? 0
+                                                                                                  : RFP_ERR_RUNTIME;
+}
+
+int rfp_zpftri(rfp_handle_t h, char transr, char uplo, int64_t n, double* arf, int* info, hipStream_t stream)
+{
+    if (!h) return RFP_ERR_HANDLE;
+    if (zbad_tr(transr)) return -1;
+    if (bad_ul(uplo)) return -2;
+    if (n < 0) return -3;
+    if (n > 0 && !arf) return -4;
+    if (!info) return -5;
+    DeviceGuard g(h->device);
+    if (set_int(stream, info, 0) != hipSuccess) return RFP_ERR_RUNTIME;
+    if (n == 0) return 0;
+    if (zensure(h, n, 0) != hipSuccess) return RFP_ERR_RUNTIME;
+    ZRfpViews v;
+    zrfp_views(transr, uplo, n, (double2*)arf, &v);
+    return zpftri_run(stream, v, (double2*)h->zwork, info) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
 int rfp_dtftri(rfp_handle_t h, char transr, char uplo, char diag, int64_t n, double* arf, int* info,

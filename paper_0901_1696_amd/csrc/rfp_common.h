@@ -371,4 +371,28 @@ hipError_t unit_diag(hipStream_t s, const RfpView<T>& v, T* buf, bool restore);
 // Small utility kernels.
 hipError_t set_int(hipStream_t s, int* p, int v);
 
+// Complex Hermitian path (zpf.hip).  A view reads the canonical lower
+// element (i, j) at p[i rs + j cs], conjugated when conj.  Masks: operand
+// element (r, c) counts only when r - c >= md; ZMASK_NONE keeps all.
+constexpr int64_t ZMASK_NONE = -(int64_t(1) << 62);
+struct ZView {
+    double2* p;
+    int64_t rs, cs;
+    bool conj;
+};
+struct ZRfpViews {
+    int64_t n, m1, m2;
+    ZView t1, s, t2;  // L11, L21, L22
+};
+// Views of a complex RFP array (TRANSR 'N' or 'C'); false for an illegal
+// TRANSR / UPLO.
+bool zrfp_views(char transr, char uplo, int64_t n, double2* arf, ZRfpViews* v);
+// Scratch (complex elements) of the drivers for order n and nrhs columns.
+size_t zwork_elems(int64_t n, int64_t nrhs);
+hipError_t zconvert(hipStream_t s, const ZRfpViews& v, bool upper, double2* a, int64_t lda, bool to_rfp);
+hipError_t zpftrf_run(hipStream_t s, const ZRfpViews& v, double2* work, int* info);
+hipError_t zpftrs_run(hipStream_t s, const ZRfpViews& v, double2* b, int64_t ldb, int64_t nrhs, double2* work,
+                      int* info);
+hipError_t zpftri_run(hipStream_t s, const ZRfpViews& v, double2* work, int* info);
+
 }  // namespace rfp

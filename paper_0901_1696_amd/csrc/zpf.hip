@@ -1,0 +1,639 @@
+// Complex Hermitian (Z) RFP Cholesky: factorization, solution and inversion
+// of a Hermitian positive definite matrix held in complex Rectangular Full
+// Packed Format (Section 3, A = L L^H; Section 4, L Y = B and L^H X = Y;
+// Section 5, A^{-1} = W^H W with W = L^{-1}; the complex rows of the routine
+// table: ZPFTRF, ZPFTRS, ZPFTRI with TRANSR = 'N' or 'C').
+//
+// Format: the element positions are those of the real format of the same
+// TRANSR/UPLO; wherever the real format keeps a part transposed, the complex
+// one keeps its conjugate transpose, and TRANSR = 'C' keeps the conjugate
+// transpose of the whole rectangle.  Each of the three blocks (L11, L21, L22
+// of the canonical lower matrix) is therefore a strided view whose numbers
+// are either the canonical elements or their conjugates (ZView::conj).
+//
+// Arithmetic: complex numbers are interleaved (re, im) doubles.  Every block
+// product goes through one MFMA kernel: a 64 x 64 tile of C per workgroup,
+// operands staged in LDS as separate real and imaginary planes (conjugation,
+// transposition and triangular masks applied while staging), and each complex
+// multiply-add of a 16 x 16 x 4 step formed by four FP64 MFMAs
+// (re += ar br - ai bi, im += ar bi + ai br).  Diagonal blocks of at most 64
+// rows are factored and inverted by one workgroup in LDS.  The blocked
+// drivers below follow the paper's steps with 64-column blocks.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rfp_common.h"
+
+namespace rfp {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int ZT = 64;  // C tile (rows and columns) and leaf order
+constexpr int ZK = 16;  // K step of the product
+
+__device__ __forceinline__ double2 zconj_if(double2 v, bool c)
+{
+    if (c) v.y = -v.y;
+    return v;
+}
+
+// C = alpha op(A) op(B) + beta C on views (real alpha, beta).
+//   op(A) is M x K: A (ta = 0) or A^H (ta = 1); an element (r, c) of A's view
+//   (before op) counts only when r - c >= mda (else it is zero);
+//   likewise B (N columns) with tb, mdb; C(i, j) is written only when
+//   i - j >= mdc.  beta = 0: C is not read.  gate: nothing runs while *gate.
+struct ZGemm {
+    int64_t M, N, K;
+    ZView A, B, C;
+    int ta, tb;
+    int64_t mda, mdb, mdc;
+    double alpha, beta;
+    const int* gate;
+};
+
+__global__ __launch_bounds__(256) void zgemm_kernel(ZGemm g)
+{
+    if (g.gate && *g.gate) return;
+    const int64_t i0 = (int64_t)blockIdx.x * ZT, j0 = (int64_t)blockIdx.y * ZT;
+    if (i0 + ZT - 1 - j0 < g.mdc) return;  // the whole tile lies outside C's mask
+    constexpr int PA = ZT + 8;
+    __shared__ double Ar[ZK][PA], Ai[ZK][PA], Br[ZK][PA], Bi[ZK][PA];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;
+
+    // K range where both operands can be nonzero for this tile
+    int64_t klo = 0, khi = g.K;
+    if (g.mda > ZMASK_NONE) {
+        if (!g.ta) khi = std::min<int64_t>(khi, i0 + ZT - 1 - g.mda + 1);  // A(i, k): k <= i - mda
+        else klo = std::max<int64_t>(klo, i0 + g.mda);                     // A(k, i): k >= i + mda
+    }
+    if (g.mdb > ZMASK_NONE) {
+        if (!g.tb) klo = std::max<int64_t>(klo, j0 + g.mdb);               // B(k, j): k >= j + mdb
+        else khi = std::min<int64_t>(khi, j0 + ZT - 1 - g.mdb + 1);        // B(j, k): k <= j - mdb
+    }
+
+    // staging maps: the element index e = t + 256 q runs along the operand's
+    // unit stride (coalesced loads)
+    const bool a_fast_i = (g.ta ? g.A.cs : g.A.rs) == 1;
+    const bool b_fast_j = (g.tb ? g.B.rs : g.B.cs) == 1;
+    const bool aconj = g.A.conj != (g.ta != 0), bconj = g.B.conj != (g.tb != 0);
+    double2 ra[4], rb[4];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int e = t + 256 * q;
+            {
+                const int i = a_fast_i ? e % ZT : e / ZK, k = a_fast_i ? e / ZT : e % ZK;
+                const int64_t gi = i0 + i, gk = k0 + k;
+                const int64_t r = g.ta ? gk : gi, c = g.ta ? gi : gk;
+                const bool in = gi < g.M && gk < khi && r - c >= g.mda;
+                ra[q] = in ? zconj_if(g.A.p[r * g.A.rs + c * g.A.cs], aconj) : make_double2(0.0, 0.0);
+            }
+            {
+                const int j = b_fast_j ? e % ZT : e / ZK, k = b_fast_j ? e / ZT : e % ZK;
+                const int64_t gj = j0 + j, gk = k0 + k;
+                const int64_t r = g.tb ? gj : gk, c = g.tb ? gk : gj;
+                const bool in = gj < g.N && gk < khi && r - c >= g.mdb;
+                rb[q] = in ? zconj_if(g.B.p[r * g.B.rs + c * g.B.cs], bconj) : make_double2(0.0, 0.0);
+            }
+        }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int e = t + 256 * q;
+            const int ia = a_fast_i ? e % ZT : e / ZK, ka = a_fast_i ? e / ZT : e % ZK;
+            Ar[ka][ia] = ra[q].x;
+            Ai[ka][ia] = ra[q].y;
+            const int jb = b_fast_j ? e % ZT : e / ZK, kb = b_fast_j ? e / ZT : e % ZK;
+            Br[kb][jb] = rb[q].x;
+            Bi[kb][jb] = rb[q].y;
+        }
+    };
+
+    v4d cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) cr[a][b] = ci[a][b] = v4d{0, 0, 0, 0};
+
+    int64_t k0 = klo / ZK * ZK;  // K steps aligned to ZK (elements below klo are masked)
+    if (k0 < khi) load(k0);
+    for (; k0 < khi; k0 += ZK) {
+        __syncthreads();  // the previous step's reads of the planes are done
+        stage();
+        __syncthreads();
+        if (k0 + ZK < khi) load(k0 + ZK);  // in flight during this step's products
+#pragma unroll
+        for (int kk = 0; kk < ZK; kk += 4) {
+            const int k = kk + (lane >> 4);
+            double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+            for (int a = 0; a < 2; a++) {
+                ar[a] = Ar[k][32 * wr + 16 * a + (lane & 15)];
+                ai[a] = Ai[k][32 * wr + 16 * a + (lane & 15)];
+            }
+#pragma unroll
+            for (int b = 0; b < 2; b++) {
+                br[b] = Br[k][32 * wc + 16 * b + (lane & 15)];
+                bi[b] = Bi[k][32 * wc + 16 * b + (lane & 15)];
+            }
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int b = 0; b < 2; b++) {
+                    cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
+                    cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], bi[b], cr[a][b], 0, 0, 0);
+                    ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], ci[a][b], 0, 0, 0);
+                    ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], ci[a][b], 0, 0, 0);
+                }
+        }
+    }
+
+    // result element r of a lane: row (lane / 16) + 4 r, column lane % 16
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int64_t i = i0 + 32 * wr + 16 * a + (lane >> 4) + 4 * r;
+                const int64_t j = j0 + 32 * wc + 16 * b + (lane & 15);
+                if (i < g.M && j < g.N && i - j >= g.mdc) {
+                    double2* cp = g.C.p + i * g.C.rs + j * g.C.cs;
+                    double2 v = make_double2(g.alpha * cr[a][b][r], g.alpha * ci[a][b][r]);
+                    if (g.beta != 0.0) {
+                        const double2 o = zconj_if(*cp, g.C.conj);
+                        v.x += g.beta * o.x;
+                        v.y += g.beta * o.y;
+                    }
+                    *cp = zconj_if(v, g.C.conj);
+                }
+            }
+}
+
+// C(i, j) = alpha A(i, j) + beta C(i, j) for i - j >= mdc (beta = 0: C not read).
+struct ZAxpby {
+    int64_t M, N;
+    ZView A, C;
+    int64_t mdc;
+    double alpha, beta;
+    const int* gate;
+};
+
+__global__ __launch_bounds__(256) void zaxpby_kernel(ZAxpby g)
+{
+    if (g.gate && *g.gate) return;
+    const int64_t i0 = (int64_t)blockIdx.x * ZT, j0 = (int64_t)blockIdx.y * ZT;
+    const bool fast_i = g.C.rs == 1;
+    for (int e = threadIdx.x; e < ZT * ZT; e += 256) {
+        const int64_t i = i0 + (fast_i ? e % ZT : e / ZT), j = j0 + (fast_i ? e / ZT : e % ZT);
+        if (i >= g.M || j >= g.N || i - j < g.mdc) continue;
+        double2 v = zconj_if(g.A.p[i * g.A.rs + j * g.A.cs], g.A.conj);
+        v.x *= g.alpha;
+        v.y *= g.alpha;
+        double2* cp = g.C.p + i * g.C.rs + j * g.C.cs;
+        if (g.beta != 0.0) {
+            const double2 o = zconj_if(*cp, g.C.conj);
+            v.x += g.beta * o.x;
+            v.y += g.beta * o.y;
+        }
+        *cp = zconj_if(v, g.C.conj);
+    }
+}
+
+// Diagonal blocks of at most 64 rows, one workgroup each: block b is the
+// diagonal block at (b * 64, b * 64) of the view (order min(64, m - 64 b)).
+//   ZLEAF_FACTOR: Cholesky in place (lower triangle written back, real
+//                 diagonal), then W = L^{-1} into w[b];
+//   ZLEAF_INV:    W = L^{-1} of the factor already in the view, into w[b];
+//   ZLEAF_INV_INPLACE: as ZLEAF_INV, and W also replaces the block's lower
+//                 triangle.
+// w[b] is a dense 64 x 64 column-major block (zero above the diagonal).
+// INFO: FACTOR, first non-positive pivot p (1-based in the block) ->
+// info_off + 64 b + p; INV modes, first zero diagonal entry likewise.
+enum { ZLEAF_FACTOR = 0, ZLEAF_INV = 1, ZLEAF_INV_INPLACE = 2 };
+
+// *info = v unless it already holds a smaller nonzero position (blocks may
+// report in any order; INFO is the first failing position).
+__device__ void info_first(int* info, int v)
+{
+    int old = __hip_atomic_load(info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (old == 0 || v < old) {
+        const int prev = atomicCAS(info, old, v);
+        if (prev == old) break;
+        old = prev;
+    }
+}
+
+__global__ __launch_bounds__(256) void zleaf_kernel(ZView A, int64_t m, int mode, double2* w, int* info,
+                                                    int64_t info_off, const int* gate)
+{
+    if (gate && *gate) return;
+    constexpr int P = ZT + 1;
+    __shared__ double Lr[ZT][P], Li[ZT][P], Wr[ZT][P], Wi[ZT][P];
+    __shared__ int fail_sh, zero_sh;
+    const int t = threadIdx.x;
+    const int64_t b = blockIdx.x, k0 = b * ZT;
+    const int nb = (int)std::min<int64_t>(ZT, m - k0);
+    if (nb <= 0) return;
+    for (int e = t; e < ZT * ZT; e += 256) {
+        const int i = e % ZT, j = e / ZT;
+        double2 v = make_double2(0.0, 0.0);
+        if (i >= j && i < nb) v = zconj_if(A.p[(k0 + i) * A.rs + (k0 + j) * A.cs], A.conj);
+        if (i == j) v.y = 0.0;  // the diagonal of a Hermitian matrix and of its factor is real
+        Lr[i][j] = v.x;
+        Li[i][j] = v.y;
+    }
+    if (t == 0) {
+        fail_sh = 0;
+        zero_sh = 1 << 30;  // first zero on the diagonal (INV modes)
+    }
+    __syncthreads();
+    if (mode == ZLEAF_FACTOR) {
+        for (int j = 0; j < nb; j++) {
+            const double d = Lr[j][j];
+            if (!(d > 0.0)) {  // uniform: every thread reads the same LDS word
+                if (t == 0) {
+                    info_first(info, (int)(info_off + k0 + j + 1));
+                    fail_sh = 1;
+                }
+                break;
+            }
+            const double l = sqrt(d);
+            __syncthreads();  // every thread has read L(j, j)
+            if (t < ZT) {
+                if (t == j) Lr[j][j] = l;
+                else if (t > j && t < nb) {
+                    Lr[t][j] /= l;
+                    Li[t][j] /= l;
+                }
+            }
+            __syncthreads();
+            // trailing lower triangle: L(i, c) -= L(i, j) conj(L(c, j)), j < c <= i
+            for (int e = t; e < ZT * ZT; e += 256) {
+                const int i = e % ZT, c = e / ZT;
+                if (c > j && i >= c && i < nb) {
+                    const double xr = Lr[i][j], xi = Li[i][j], yr = Lr[c][j], yi = Li[c][j];
+                    Lr[i][c] -= xr * yr + xi * yi;
+                    Li[i][c] -= xi * yr - xr * yi;
+                }
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+        if (fail_sh) return;
+        // the factor back into the view (lower triangle of the block)
+        for (int e = t; e < ZT * ZT; e += 256) {
+            const int i = e % ZT, j = e / ZT;
+            if (i >= j && i < nb)
+                A.p[(k0 + i) * A.rs + (k0 + j) * A.cs] = zconj_if(make_double2(Lr[i][j], Li[i][j]), A.conj);
+        }
+    } else {
+        if (info && t < nb && Lr[t][t] == 0.0) atomicMin(&zero_sh, t + 1);
+        __syncthreads();
+        if (zero_sh < (1 << 30)) {
+            if (t == 0) info_first(info, (int)(info_off + k0 + zero_sh));
+            return;
+        }
+    }
+    // W = L^{-1}: thread c forms column c by forward substitution,
+    // W(i, c) = -(sum_{k = c}^{i-1} L(i, k) W(k, c)) / L(i, i)
+    if (t < ZT) {
+        const int c = t;
+        for (int i = 0; i < ZT; i++) {
+            Wr[i][c] = 0.0;
+            Wi[i][c] = 0.0;
+        }
+        if (c < nb) {
+            Wr[c][c] = 1.0 / Lr[c][c];
+            for (int i = c + 1; i < nb; i++) {
+                double sr = 0.0, si = 0.0;
+                for (int k = c; k < i; k++) {
+                    sr += Lr[i][k] * Wr[k][c] - Li[i][k] * Wi[k][c];
+                    si += Lr[i][k] * Wi[k][c] + Li[i][k] * Wr[k][c];
+                }
+                Wr[i][c] = -sr / Lr[i][i];
+                Wi[i][c] = -si / Lr[i][i];
+            }
+        }
+    }
+    __syncthreads();
+    double2* wb = w + b * ZT * ZT;
+    for (int e = t; e < ZT * ZT; e += 256) {
+        const int i = e % ZT, j = e / ZT;
+        wb[i + j * ZT] = make_double2(Wr[i][j], Wi[i][j]);
+        if (mode == ZLEAF_INV_INPLACE && i >= j && i < nb)
+            A.p[(k0 + i) * A.rs + (k0 + j) * A.cs] = zconj_if(make_double2(Wr[i][j], Wi[i][j]), A.conj);
+    }
+}
+
+// ZTRTTF / ZTFTTR on one block of the RFP array: element (i, j) of the view
+// (i >= j on a diagonal block) is canonical element (ro + i, co + j) of A.
+__global__ void zconvert_kernel(ZView v, int64_t rows, int64_t cols, bool diag, int64_t ro, int64_t co, bool upper,
+                                double2* a, int64_t lda, bool to_rfp)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows * cols) return;
+    const int64_t i = v.rs == 1 ? idx % rows : idx / cols, j = v.rs == 1 ? idx / rows : idx % cols;
+    if (diag && i < j) return;
+    const int64_t gi = ro + i, gj = co + j;
+    double2* p = v.p + i * v.rs + j * v.cs;
+    // canonical lower element L(gi, gj): UPLO='L' A(gi, gj); 'U' conj(A(gj, gi))
+    double2* ap = upper ? a + gj + gi * lda : a + gi + gj * lda;
+    if (to_rfp) {
+        const double2 l = zconj_if(*ap, upper);
+        *p = zconj_if(l, v.conj);
+    } else {
+        const double2 l = zconj_if(*p, v.conj);
+        *ap = zconj_if(l, upper);
+    }
+}
+
+inline unsigned tiles(int64_t x) { return (unsigned)((x + ZT - 1) / ZT); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+ZView zview_sub(const ZView& v, int64_t i, int64_t j)
+{
+    return ZView{v.p + i * v.rs + j * v.cs, v.rs, v.cs, v.conj};
+}
+
+hipError_t zgemm(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const ZView& A, int ta, int64_t mda,
+                 const ZView& B, int tb, int64_t mdb, double beta, const ZView& C, int64_t mdc, const int* gate)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    ZGemm g{M, N, K, A, B, C, ta, tb, mda, mdb, mdc, alpha, beta, gate};
+    if (K <= 0) {  // C = beta C
+        if (beta == 1.0) return hipSuccess;
+        ZAxpby c{M, N, C, C, mdc, beta, 0.0, gate};
+        hipLaunchKernelGGL(zaxpby_kernel, dim3(tiles(M), tiles(N)), dim3(256), 0, s, c);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(zgemm_kernel, dim3(tiles(M), tiles(N)), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t zaxpby(hipStream_t s, int64_t M, int64_t N, double alpha, const ZView& A, double beta, const ZView& C,
+                  int64_t mdc, const int* gate)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    ZAxpby c{M, N, A, C, mdc, alpha, beta, gate};
+    hipLaunchKernelGGL(zaxpby_kernel, dim3(tiles(M), tiles(N)), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t zleaf(hipStream_t s, const ZView& A, int64_t m, int64_t first, int64_t count, int mode, double2* w,
+                 int* info, int64_t info_off, const int* gate)
+{
+    if (count <= 0) return hipSuccess;
+    // blocks first .. first + count - 1: shift the view so that block 0 is `first`
+    const ZView a = zview_sub(A, first * ZT, first * ZT);
+    hipLaunchKernelGGL(zleaf_kernel, dim3((unsigned)count), dim3(256), 0, s, a, m - first * ZT, mode, w, info,
+                       info_off + first * ZT, gate);
+    return hipGetLastError();
+}
+
+hipError_t zconvert(hipStream_t s, const ZRfpViews& v, bool upper, double2* a, int64_t lda, bool to_rfp)
+{
+    struct Blk {
+        ZView v;
+        int64_t rows, cols, ro, co;
+        bool diag;
+    } blks[3] = {{v.t1, v.m1, v.m1, 0, 0, true}, {v.s, v.m2, v.m1, v.m1, 0, false}, {v.t2, v.m2, v.m2, v.m1, v.m1, true}};
+    for (const Blk& b : blks) {
+        const int64_t cnt = b.rows * b.cols;
+        if (cnt <= 0) continue;
+        hipLaunchKernelGGL(zconvert_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, b.v, b.rows, b.cols,
+                           b.diag, b.ro, b.co, upper, a, lda, to_rfp);
+    }
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- drivers
+
+#define ZCK(x)                                  \
+    do {                                        \
+        hipError_t e_ = (x);                    \
+        if (e_ != hipSuccess) return e_;        \
+    } while (0)
+
+// Cholesky of the m x m lower view A in place (64-column blocks, right-
+// looking): leaf (factor + inverse W_kk into w[k]), panel P = A_{>k,k} W_kk^H
+// (through tmp, at least (m - 64) x 64), trailing A_{>k,>k} -= P P^H.
+static hipError_t zpotrf_view(hipStream_t s, const ZView& A, int64_t m, double2* w, double2* tmp, int* info,
+                              int64_t info_off)
+{
+    for (int64_t k0 = 0; k0 < m; k0 += ZT) {
+        const int64_t nb = std::min<int64_t>(ZT, m - k0), r = m - k0 - nb;
+        const int64_t kb = k0 / ZT;
+        ZCK(zleaf(s, A, m, kb, 1, ZLEAF_FACTOR, w + kb * ZT * ZT, info, info_off, info));
+        if (r <= 0) break;
+        const ZView P = zview_sub(A, k0 + nb, k0);
+        const ZView W{w + kb * ZT * ZT, 1, ZT, 0};
+        const ZView T{tmp, 1, r, 0};
+        ZCK(zgemm(s, r, nb, nb, 1.0, P, 0, ZMASK_NONE, W, 1, ZMASK_NONE, 0.0, T, ZMASK_NONE, info));
+        ZCK(zaxpby(s, r, nb, 1.0, T, 0.0, P, ZMASK_NONE, info));
+        ZCK(zgemm(s, r, r, nb, -1.0, P, 0, ZMASK_NONE, P, 1, ZMASK_NONE, 1.0, zview_sub(A, k0 + nb, k0 + nb), 0,
+                  info));
+    }
+    return hipSuccess;
+}
+
+int64_t zleaves(int64_t m) { return (m + ZT - 1) / ZT; }
+
+size_t zwork_elems(int64_t n, int64_t nrhs)
+{
+    const int64_t m1 = (n + 1) / 2;  // the larger block order of every layout
+    const int64_t leaves = 2 * zleaves(m1);
+    return (size_t)(leaves * ZT * ZT) + (size_t)ZT * (size_t)std::max<int64_t>(std::max<int64_t>(n, nrhs), 1);
+}
+
+hipError_t zpftrf_run(hipStream_t s, const ZRfpViews& v, double2* work, int* info)
+{
+    double2* w1 = work;
+    double2* w2 = w1 + zleaves(v.m1) * ZT * ZT;
+    double2* tmp = w2 + zleaves(v.m2) * ZT * ZT;
+    // step 1: POTRF on T1
+    ZCK(zpotrf_view(s, v.t1, v.m1, w1, tmp, info, 0));
+    if (v.m2 == 0) return hipSuccess;
+    // step 2: TRSM, S <- S L11^{-H}, block column by block column
+    for (int64_t j0 = 0; j0 < v.m1; j0 += ZT) {
+        const int64_t nb = std::min<int64_t>(ZT, v.m1 - j0), rest = v.m1 - j0 - nb;
+        const ZView Sj = zview_sub(v.s, 0, j0);
+        const ZView W{w1 + (j0 / ZT) * ZT * ZT, 1, ZT, 0};
+        const ZView T{tmp, 1, v.m2, 0};
+        ZCK(zgemm(s, v.m2, nb, nb, 1.0, Sj, 0, ZMASK_NONE, W, 1, ZMASK_NONE, 0.0, T, ZMASK_NONE, info));
+        ZCK(zaxpby(s, v.m2, nb, 1.0, T, 0.0, Sj, ZMASK_NONE, info));
+        if (rest > 0)
+            ZCK(zgemm(s, v.m2, rest, nb, -1.0, Sj, 0, ZMASK_NONE, zview_sub(v.t1, j0 + nb, j0), 1, ZMASK_NONE, 1.0,
+                      zview_sub(v.s, 0, j0 + nb), ZMASK_NONE, info));
+    }
+    // step 3: HERK, T2 <- T2 - S S^H (lower triangle)
+    ZCK(zgemm(s, v.m2, v.m2, v.m1, -1.0, v.s, 0, ZMASK_NONE, v.s, 1, ZMASK_NONE, 1.0, v.t2, 0, info));
+    // step 4: POTRF on T2, INFO counted from the start of A
+    return zpotrf_view(s, v.t2, v.m2, w2, tmp, info, v.m1);
+}
+
+hipError_t zpftrs_run(hipStream_t s, const ZRfpViews& v, double2* b, int64_t ldb, int64_t nrhs, double2* work,
+                      int* info)
+{
+    (void)info;  // a zero on the factor's diagonal yields infinities, as in LAPACK
+    const int64_t l1 = zleaves(v.m1), l2 = zleaves(v.m2);
+    double2* w1 = work;
+    double2* w2 = w1 + l1 * ZT * ZT;
+    double2* tmp = w2 + l2 * ZT * ZT;
+    ZCK(zleaf(s, v.t1, v.m1, 0, l1, ZLEAF_INV, w1, nullptr, 0, nullptr));
+    ZCK(zleaf(s, v.t2, v.m2, 0, l2, ZLEAF_INV, w2, nullptr, v.m1, nullptr));
+    const ZView B{b, 1, ldb, 0};
+    const ZView T{tmp, 1, ZT, 0};
+    struct Part {
+        ZView L;
+        int64_t m, row0;
+        double2* w;
+    } parts[2] = {{v.t1, v.m1, 0, w1}, {v.t2, v.m2, v.m1, w2}};
+    // forward, L Y = B: T1's rows, then B2 -= S Y1, then T2's rows
+    for (int p = 0; p < 2; p++) {
+        const Part& q = parts[p];
+        if (p == 1 && v.m2 > 0)
+            ZCK(zgemm(s, v.m2, nrhs, v.m1, -1.0, v.s, 0, ZMASK_NONE, B, 0, ZMASK_NONE, 1.0, zview_sub(B, v.m1, 0),
+                      ZMASK_NONE, nullptr));
+        for (int64_t k0 = 0; k0 < q.m; k0 += ZT) {
+            const int64_t nb = std::min<int64_t>(ZT, q.m - k0), rest = q.m - k0 - nb;
+            const ZView Bk = zview_sub(B, q.row0 + k0, 0);
+            const ZView W{q.w + (k0 / ZT) * ZT * ZT, 1, ZT, 0};
+            ZCK(zgemm(s, nb, nrhs, nb, 1.0, W, 0, ZMASK_NONE, Bk, 0, ZMASK_NONE, 0.0, T, ZMASK_NONE, nullptr));
+            ZCK(zaxpby(s, nb, nrhs, 1.0, T, 0.0, Bk, ZMASK_NONE, nullptr));
+            if (rest > 0)
+                ZCK(zgemm(s, rest, nrhs, nb, -1.0, zview_sub(q.L, k0 + nb, k0), 0, ZMASK_NONE, Bk, 0, ZMASK_NONE, 1.0,
+                          zview_sub(B, q.row0 + k0 + nb, 0), ZMASK_NONE, nullptr));
+        }
+    }
+    // backward, L^H X = Y: T2's rows from the last, then B1 -= S^H X2, then T1's
+    for (int p = 1; p >= 0; p--) {
+        const Part& q = parts[p];
+        if (p == 0 && v.m2 > 0)
+            ZCK(zgemm(s, v.m1, nrhs, v.m2, -1.0, v.s, 1, ZMASK_NONE, zview_sub(B, v.m1, 0), 0, ZMASK_NONE, 1.0, B,
+                      ZMASK_NONE, nullptr));
+        for (int64_t k0 = (q.m - 1) / ZT * ZT; q.m > 0 && k0 >= 0; k0 -= ZT) {
+            const int64_t nb = std::min<int64_t>(ZT, q.m - k0);
+            const ZView Bk = zview_sub(B, q.row0 + k0, 0);
+            const ZView W{q.w + (k0 / ZT) * ZT * ZT, 1, ZT, 0};
+            ZCK(zgemm(s, nb, nrhs, nb, 1.0, W, 1, ZMASK_NONE, Bk, 0, ZMASK_NONE, 0.0, T, ZMASK_NONE, nullptr));
+            ZCK(zaxpby(s, nb, nrhs, 1.0, T, 0.0, Bk, ZMASK_NONE, nullptr));
+            if (k0 > 0)  // rows above: B(0:k0) -= L(k, 0:k0)^H X_k
+                ZCK(zgemm(s, k0, nrhs, nb, -1.0, zview_sub(q.L, k0, 0), 1, ZMASK_NONE, Bk, 0, ZMASK_NONE, 1.0,
+                          zview_sub(B, q.row0, 0), ZMASK_NONE, nullptr));
+        }
+    }
+    return hipSuccess;
+}
+
+// W = L^{-1} in place on the m x m lower view (block columns from the last):
+// W_{>j,j} = -W_{>j,>j} L_{>j,j} W_jj, then W_jj into the diagonal block.
+static hipError_t ztrtri_view(hipStream_t s, const ZView& A, int64_t m, double2* w, double2* tmp, int* info,
+                              int64_t info_off)
+{
+    const int64_t l = zleaves(m);
+    ZCK(zleaf(s, A, m, 0, l, ZLEAF_INV, w, info, info_off, info));
+    for (int64_t j0 = (l - 1) * ZT; l > 0 && j0 >= 0; j0 -= ZT) {
+        const int64_t nb = std::min<int64_t>(ZT, m - j0), r = m - j0 - nb;
+        const ZView W{w + (j0 / ZT) * ZT * ZT, 1, ZT, 0};
+        if (r > 0) {
+            const ZView T{tmp, 1, r, 0};
+            ZCK(zgemm(s, r, nb, r, 1.0, zview_sub(A, j0 + nb, j0 + nb), 0, 0, zview_sub(A, j0 + nb, j0), 0, ZMASK_NONE,
+                      0.0, T, ZMASK_NONE, info));
+            ZCK(zgemm(s, r, nb, nb, -1.0, T, 0, ZMASK_NONE, W, 0, ZMASK_NONE, 0.0, zview_sub(A, j0 + nb, j0),
+                      ZMASK_NONE, info));
+        }
+        ZCK(zaxpby(s, nb, nb, 1.0, W, 0.0, zview_sub(A, j0, j0), 0, info));
+    }
+    return hipSuccess;
+}
+
+// W^H W in place on the m x m lower view holding W (row blocks from the
+// first): C(I, 0:i0+nb) = W(i0:m, I)^H W(i0:m, 0:i0+nb).
+static hipError_t zlauum_view(hipStream_t s, const ZView& A, int64_t m, double2* tmp, const int* gate)
+{
+    for (int64_t i0 = 0; i0 < m; i0 += ZT) {
+        const int64_t nb = std::min<int64_t>(ZT, m - i0);
+        const ZView T{tmp, 1, ZT, 0};
+        ZCK(zgemm(s, nb, i0 + nb, m - i0, 1.0, zview_sub(A, i0, i0), 1, 0, zview_sub(A, i0, 0), 0, -i0, 0.0, T,
+                  ZMASK_NONE, gate));
+        ZCK(zaxpby(s, nb, i0 + nb, 1.0, T, 0.0, zview_sub(A, i0, 0), -i0, gate));
+    }
+    return hipSuccess;
+}
+
+hipError_t zpftri_run(hipStream_t s, const ZRfpViews& v, double2* work, int* info)
+{
+    const int64_t l1 = zleaves(v.m1), l2 = zleaves(v.m2);
+    double2* w1 = work;
+    double2* w2 = w1 + l1 * ZT * ZT;
+    double2* tmp = w2 + l2 * ZT * ZT;
+    // stage A: W = L^{-1} on the three blocks
+    ZCK(ztrtri_view(s, v.t1, v.m1, w1, tmp, info, 0));
+    if (v.m2 > 0) {
+        // S <- -S W11, block columns from the first (column block j reads
+        // columns >= j only)
+        for (int64_t j0 = 0; j0 < v.m1; j0 += ZT) {
+            const int64_t nb = std::min<int64_t>(ZT, v.m1 - j0);
+            const ZView T{tmp, 1, v.m2, 0};
+            ZCK(zgemm(s, v.m2, nb, v.m1 - j0, 1.0, zview_sub(v.s, 0, j0), 0, ZMASK_NONE, zview_sub(v.t1, j0, j0), 0, 0,
+                      0.0, T, ZMASK_NONE, info));
+            ZCK(zaxpby(s, v.m2, nb, -1.0, T, 0.0, zview_sub(v.s, 0, j0), ZMASK_NONE, info));
+        }
+        ZCK(ztrtri_view(s, v.t2, v.m2, w2, tmp, info, v.m1));
+        // S <- W22 S, row blocks from the last (row block i reads rows <= i)
+        for (int64_t i0 = (l2 - 1) * ZT; i0 >= 0; i0 -= ZT) {
+            const int64_t nb = std::min<int64_t>(ZT, v.m2 - i0);
+            const ZView T{tmp, 1, ZT, 0};
+            ZCK(zgemm(s, nb, v.m1, i0 + nb, 1.0, zview_sub(v.t2, i0, 0), 0, -i0, v.s, 0, ZMASK_NONE, 0.0, T,
+                      ZMASK_NONE, info));
+            ZCK(zaxpby(s, nb, v.m1, 1.0, T, 0.0, zview_sub(v.s, i0, 0), ZMASK_NONE, info));
+        }
+    }
+    // stage B: A^{-1} = W^H W
+    ZCK(zlauum_view(s, v.t1, v.m1, tmp, info));
+    if (v.m2 > 0) {
+        ZCK(zgemm(s, v.m1, v.m1, v.m2, 1.0, v.s, 1, ZMASK_NONE, v.s, 0, ZMASK_NONE, 1.0, v.t1, 0, info));
+        // S <- W22^H S, row blocks from the first (row block i reads rows >= i)
+        for (int64_t i0 = 0; i0 < v.m2; i0 += ZT) {
+            const int64_t nb = std::min<int64_t>(ZT, v.m2 - i0);
+            const ZView T{tmp, 1, ZT, 0};
+            ZCK(zgemm(s, nb, v.m1, v.m2 - i0, 1.0, zview_sub(v.t2, i0, i0), 1, 0, zview_sub(v.s, i0, 0), 0,
+                      ZMASK_NONE, 0.0, T, ZMASK_NONE, info));
+            ZCK(zaxpby(s, nb, v.m1, 1.0, T, 0.0, zview_sub(v.s, i0, 0), ZMASK_NONE, info));
+        }
+        ZCK(zlauum_view(s, v.t2, v.m2, tmp, info));
+    }
+    return hipSuccess;
+}
+
+bool zrfp_views(char transr, char uplo, int64_t n, double2* arf, ZRfpViews* v)
+{
+    const int t = (transr >= 'a' && transr <= 'z') ? transr - 'a' + 'A' : transr;
+    const int u = (uplo >= 'a' && uplo <= 'z') ? uplo - 'a' + 'A' : uplo;
+    if ((t != 'N' && t != 'C') || (u != 'L' && u != 'U')) return false;
+    RfpBlocks b;
+    if (!rfp_blocks(t == 'N' ? 'N' : 'T', (char)u, n, &b)) return false;
+    // the blocks the real format keeps transposed hold conjugates: for 'L'
+    // L22, for 'U' L21 and L22 (the canonical lower view reads the stored
+    // upper triangle); TRANSR = 'C' conjugates the whole rectangle
+    const bool c = t == 'C';
+    const bool x11 = false, x21 = u == 'U', x22 = true;
+    v->n = n;
+    v->m1 = b.m1;
+    v->m2 = b.m2;
+    v->t1 = ZView{arf + b.off11, b.rs11, b.cs11, x11 != c};
+    v->s = ZView{arf + b.off21, b.rs21, b.cs21, x21 != c};
+    v->t2 = ZView{arf + b.off22, b.rs22, b.cs22, x22 != c};
+    return true;
+}
+
+}  // namespace rfp

@@ -57,6 +57,45 @@ def spd_device(n, k=None, alpha=1.0, nrhs=0, seed=0, device="cuda"):
     return A, B
 
 
+def hpd(n, k=None, alpha=1.0, nrhs=0, seed=0):
+    """Complex Hermitian A = M M^H / k + alpha I, M with N(0,1) real and
+    imaginary parts (n x n complex128, Fortran order, real diagonal), and
+    complex B (n x nrhs)."""
+    k = n if k is None else k
+    g = rng(seed)
+    M = g.standard_normal((n, k)) + 1j * g.standard_normal((n, k))
+    B = None
+    if nrhs:
+        B = np.asfortranarray(g.standard_normal((n, nrhs)) + 1j * g.standard_normal((n, nrhs)))
+    A = M @ M.conj().T
+    A /= k
+    A = 0.5 * (A + A.conj().T)
+    A[np.diag_indices(n)] = A[np.diag_indices(n)].real + alpha
+    return np.asfortranarray(A), B
+
+
+def hpd_device(n, k=None, alpha=1.0, nrhs=0, seed=0, device="cuda"):
+    """Same recipe as :func:`hpd` with the product formed by torch on
+    ``device``; complex128 tensors, column-major."""
+    import torch
+
+    k = n if k is None else k
+    g = rng(seed)
+    M = torch.from_numpy(g.standard_normal((n, k)) + 1j * g.standard_normal((n, k))).to(device)
+    B = None
+    if nrhs:
+        B = torch.from_numpy(np.asfortranarray(g.standard_normal((n, nrhs)) + 1j * g.standard_normal((n, nrhs))))
+        B = B.to(device).t().contiguous().t()
+    Mh = M.conj().t().contiguous()
+    A = M @ Mh
+    del M, Mh
+    A.div_(k)
+    A = 0.5 * (A + A.conj().t())
+    A.diagonal().copy_(A.diagonal().real + alpha)
+    A = A.t().contiguous().t()
+    return A, B
+
+
 def rhs(n, nrhs, seed):
     """Standalone right-hand sides N(0,1), column-major."""
     return np.asfortranarray(rng(seed).standard_normal((n, nrhs)))
