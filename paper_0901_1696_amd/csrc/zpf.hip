@@ -45,6 +45,10 @@ __device__ __forceinline__ double2 zconj_if(double2 v, bool c)
 //   (before op) counts only when r - c >= mda (else it is zero);
 //   likewise B (N columns) with tb, mdb; C(i, j) is written only when
 //   i - j >= mdc.  beta = 0: C is not read.  gate: nothing runs while *gate.
+//   Split K (part != null): workgroup z of a tile sums only K range
+//   [z kchunk, (z + 1) kchunk) and stores its raw sums in part (one 64 x 64
+//   block per tile and z); zsplit_reduce_kernel then adds the nsplit blocks
+//   of a tile in order of z and applies alpha, beta and the mask.
 struct ZGemm {
     int64_t M, N, K;
     ZView A, B, C;
@@ -52,6 +56,9 @@ struct ZGemm {
     int64_t mda, mdb, mdc;
     double alpha, beta;
     const int* gate;
+    int64_t kchunk;
+    int nsplit;
+    double2* part;
 };
 
 __global__ __launch_bounds__(256) void zgemm_kernel(ZGemm g)
@@ -66,6 +73,10 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemm g)
 
     // K range where both operands can be nonzero for this tile
     int64_t klo = 0, khi = g.K;
+    if (g.part) {
+        klo = (int64_t)blockIdx.z * g.kchunk;
+        khi = std::min<int64_t>(khi, klo + g.kchunk);
+    }
     if (g.mda > ZMASK_NONE) {
         if (!g.ta) khi = std::min<int64_t>(khi, i0 + ZT - 1 - g.mda + 1);  // A(i, k): k <= i - mda
         else klo = std::max<int64_t>(klo, i0 + g.mda);                     // A(k, i): k >= i + mda
@@ -89,14 +100,14 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemm g)
                 const int i = a_fast_i ? e % ZT : e / ZK, k = a_fast_i ? e / ZT : e % ZK;
                 const int64_t gi = i0 + i, gk = k0 + k;
                 const int64_t r = g.ta ? gk : gi, c = g.ta ? gi : gk;
-                const bool in = gi < g.M && gk < khi && r - c >= g.mda;
+                const bool in = gi < g.M && gk >= klo && gk < khi && r - c >= g.mda;
                 ra[q] = in ? zconj_if(g.A.p[r * g.A.rs + c * g.A.cs], aconj) : make_double2(0.0, 0.0);
             }
             {
                 const int j = b_fast_j ? e % ZT : e / ZK, k = b_fast_j ? e / ZT : e % ZK;
                 const int64_t gj = j0 + j, gk = k0 + k;
                 const int64_t r = g.tb ? gj : gk, c = g.tb ? gk : gj;
-                const bool in = gj < g.N && gk < khi && r - c >= g.mdb;
+                const bool in = gj < g.N && gk >= klo && gk < khi && r - c >= g.mdb;
                 rb[q] = in ? zconj_if(g.B.p[r * g.B.rs + c * g.B.cs], bconj) : make_double2(0.0, 0.0);
             }
         }
@@ -154,6 +165,19 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemm g)
     }
 
     // result element r of a lane: row (lane / 16) + 4 r, column lane % 16
+    if (g.part) {
+        double2* pb = g.part + (((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * g.nsplit + blockIdx.z) * ZT * ZT;
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int li = 32 * wr + 16 * a + (lane >> 4) + 4 * r, lj = 32 * wc + 16 * b + (lane & 15);
+                    pb[li + lj * ZT] = make_double2(cr[a][b][r], ci[a][b][r]);
+                }
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
@@ -173,6 +197,32 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemm g)
                     *cp = zconj_if(v, g.C.conj);
                 }
             }
+}
+
+__global__ __launch_bounds__(256) void zsplit_reduce_kernel(ZGemm g)
+{
+    if (g.gate && *g.gate) return;
+    const int64_t i0 = (int64_t)blockIdx.x * ZT, j0 = (int64_t)blockIdx.y * ZT;
+    if (i0 + ZT - 1 - j0 < g.mdc) return;
+    const double2* pb = g.part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * g.nsplit * ZT * ZT;
+    for (int e = threadIdx.x; e < ZT * ZT; e += 256) {
+        const int64_t i = i0 + e % ZT, j = j0 + e / ZT;
+        if (i >= g.M || j >= g.N || i - j < g.mdc) continue;
+        double sr = 0.0, si = 0.0;
+        for (int z = 0; z < g.nsplit; z++) {
+            const double2 v = pb[(int64_t)z * ZT * ZT + e];
+            sr += v.x;
+            si += v.y;
+        }
+        double2* cp = g.C.p + i * g.C.rs + j * g.C.cs;
+        double2 v = make_double2(g.alpha * sr, g.alpha * si);
+        if (g.beta != 0.0) {
+            const double2 o = zconj_if(*cp, g.C.conj);
+            v.x += g.beta * o.x;
+            v.y += g.beta * o.y;
+        }
+        *cp = zconj_if(v, g.C.conj);
+    }
 }
 
 // C(i, j) = alpha A(i, j) + beta C(i, j) for i - j >= mdc (beta = 0: C not read).
@@ -364,11 +414,31 @@ ZView zview_sub(const ZView& v, int64_t i, int64_t j)
     return ZView{v.p + i * v.rs + j * v.cs, v.rs, v.cs, v.conj};
 }
 
+// Split-K scratch of the driver running on this thread (set by each
+// z*_run entry from its work array; one handle serves one thread at a time).
+constexpr int64_t ZPART_TILES = 1024;  // 64 x 64 partial blocks (64 MB)
+constexpr int ZCUS = 256;
+thread_local double2* z_part = nullptr;
+
 hipError_t zgemm(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, const ZView& A, int ta, int64_t mda,
                  const ZView& B, int tb, int64_t mdb, double beta, const ZView& C, int64_t mdc, const int* gate)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
-    ZGemm g{M, N, K, A, B, C, ta, tb, mda, mdb, mdc, alpha, beta, gate};
+    ZGemm g{M, N, K, A, B, C, ta, tb, mda, mdb, mdc, alpha, beta, gate, 0, 1, nullptr};
+    // few tiles and a long K: split K so that about two workgroups per CU run
+    const int64_t nt = (int64_t)tiles(M) * tiles(N);
+    if (z_part && nt < ZCUS && K >= 512) {
+        int64_t sp = std::min<int64_t>((2 * ZCUS + nt - 1) / nt, K / 256);
+        sp = std::min<int64_t>(sp, ZPART_TILES / nt);
+        if (sp >= 2) {
+            g.kchunk = ((K + sp - 1) / sp + ZK - 1) / ZK * ZK;
+            g.nsplit = (int)((K + g.kchunk - 1) / g.kchunk);
+            g.part = z_part;
+            hipLaunchKernelGGL(zgemm_kernel, dim3(tiles(M), tiles(N), (unsigned)g.nsplit), dim3(256), 0, s, g);
+            hipLaunchKernelGGL(zsplit_reduce_kernel, dim3(tiles(M), tiles(N)), dim3(256), 0, s, g);
+            return hipGetLastError();
+        }
+    }
     if (K <= 0) {  // C = beta C
         if (beta == 1.0) return hipSuccess;
         ZAxpby c{M, N, C, C, mdc, beta, 0.0, gate};
@@ -423,112 +493,162 @@ hipError_t zconvert(hipStream_t s, const ZRfpViews& v, bool upper, double2* a, i
         if (e_ != hipSuccess) return e_;        \
     } while (0)
 
-// Cholesky of the m x m lower view A in place (64-column blocks, right-
-// looking): leaf (factor + inverse W_kk into w[k]), panel P = A_{>k,k} W_kk^H
-// (through tmp, at least (m - 64) x 64), trailing A_{>k,>k} -= P P^H.
-static hipError_t zpotrf_view(hipStream_t s, const ZView& A, int64_t m, double2* w, double2* tmp, int* info,
-                              int64_t info_off)
-{
-    for (int64_t k0 = 0; k0 < m; k0 += ZT) {
-        const int64_t nb = std::min<int64_t>(ZT, m - k0), r = m - k0 - nb;
-        const int64_t kb = k0 / ZT;
-        ZCK(zleaf(s, A, m, kb, 1, ZLEAF_FACTOR, w + kb * ZT * ZT, info, info_off, info));
-        if (r <= 0) break;
-        const ZView P = zview_sub(A, k0 + nb, k0);
-        const ZView W{w + kb * ZT * ZT, 1, ZT, 0};
-        const ZView T{tmp, 1, r, 0};
-        ZCK(zgemm(s, r, nb, nb, 1.0, P, 0, ZMASK_NONE, W, 1, ZMASK_NONE, 0.0, T, ZMASK_NONE, info));
-        ZCK(zaxpby(s, r, nb, 1.0, T, 0.0, P, ZMASK_NONE, info));
-        ZCK(zgemm(s, r, r, nb, -1.0, P, 0, ZMASK_NONE, P, 1, ZMASK_NONE, 1.0, zview_sub(A, k0 + nb, k0 + nb), 0,
-                  info));
-    }
-    return hipSuccess;
-}
+// Block width of the products that are not tied to a leaf (trailing
+// updates, triangular products by whole block columns or rows).
+constexpr int64_t ZB = 256;
 
 int64_t zleaves(int64_t m) { return (m + ZT - 1) / ZT; }
 
+// Work array of the drivers: leaf inverses of both diagonal blocks, the
+// split-K partial blocks, and ZB x max(n, nrhs) temporaries.
 size_t zwork_elems(int64_t n, int64_t nrhs)
 {
     const int64_t m1 = (n + 1) / 2;  // the larger block order of every layout
     const int64_t leaves = 2 * zleaves(m1);
-    return (size_t)(leaves * ZT * ZT) + (size_t)ZT * (size_t)std::max<int64_t>(std::max<int64_t>(n, nrhs), 1);
+    return (size_t)(leaves * ZT * ZT) + (size_t)(ZPART_TILES * ZT * ZT) +
+           (size_t)ZB * (size_t)std::max<int64_t>(std::max<int64_t>(n, nrhs), 1);
+}
+
+struct ZWork {
+    double2 *w1, *w2, *tmp;
+};
+static ZWork zwork_split(const ZRfpViews& v, double2* work)
+{
+    ZWork z;
+    z.w1 = work;
+    z.w2 = z.w1 + zleaves(v.m1) * ZT * ZT;
+    z_part = z.w2 + zleaves(v.m2) * ZT * ZT;
+    z.tmp = z_part + ZPART_TILES * ZT * ZT;
+    return z;
+}
+
+// Cholesky of the m x m lower view A in place, right-looking in panels of ZB
+// columns, each factored in 64-column steps: leaf (factor and W_kk = L_kk^{-1}
+// into w[k]), P = A_{>k,k} W_kk^H (through tmp, up to m x 64), the panel's
+// remaining columns -= P P^H; after the panel, the trailing matrix -= the
+// panel times its conjugate transpose (K = ZB).
+static hipError_t zpotrf_view(hipStream_t s, const ZView& A, int64_t m, double2* w, double2* tmp, int* info,
+                              int64_t info_off)
+{
+    for (int64_t p0 = 0; p0 < m; p0 += ZB) {
+        const int64_t pe = std::min<int64_t>(m, p0 + ZB);
+        for (int64_t k0 = p0; k0 < pe; k0 += ZT) {
+            const int64_t nb = std::min<int64_t>(ZT, pe - k0), r = m - k0 - nb, cols = pe - k0 - nb;
+            const int64_t kb = k0 / ZT;
+            ZCK(zleaf(s, A, m, kb, 1, ZLEAF_FACTOR, w + kb * ZT * ZT, info, info_off, info));
+            if (r <= 0) break;
+            const ZView P = zview_sub(A, k0 + nb, k0);
+            const ZView W{w + kb * ZT * ZT, 1, ZT, 0};
+            const ZView T{tmp, 1, r, 0};
+            ZCK(zgemm(s, r, nb, nb, 1.0, P, 0, ZMASK_NONE, W, 1, ZMASK_NONE, 0.0, T, ZMASK_NONE, info));
+            ZCK(zaxpby(s, r, nb, 1.0, T, 0.0, P, ZMASK_NONE, info));
+            if (cols > 0)
+                ZCK(zgemm(s, r, cols, nb, -1.0, P, 0, ZMASK_NONE, P, 1, ZMASK_NONE, 1.0,
+                          zview_sub(A, k0 + nb, k0 + nb), 0, info));
+        }
+        if (pe < m)
+            ZCK(zgemm(s, m - pe, m - pe, pe - p0, -1.0, zview_sub(A, pe, p0), 0, ZMASK_NONE, zview_sub(A, pe, p0), 1,
+                      ZMASK_NONE, 1.0, zview_sub(A, pe, pe), 0, info));
+    }
+    return hipSuccess;
 }
 
 hipError_t zpftrf_run(hipStream_t s, const ZRfpViews& v, double2* work, int* info)
 {
-    double2* w1 = work;
-    double2* w2 = w1 + zleaves(v.m1) * ZT * ZT;
-    double2* tmp = w2 + zleaves(v.m2) * ZT * ZT;
+    const ZWork z = zwork_split(v, work);
     // step 1: POTRF on T1
-    ZCK(zpotrf_view(s, v.t1, v.m1, w1, tmp, info, 0));
+    ZCK(zpotrf_view(s, v.t1, v.m1, z.w1, z.tmp, info, 0));
     if (v.m2 == 0) return hipSuccess;
-    // step 2: TRSM, S <- S L11^{-H}, block column by block column
-    for (int64_t j0 = 0; j0 < v.m1; j0 += ZT) {
-        const int64_t nb = std::min<int64_t>(ZT, v.m1 - j0), rest = v.m1 - j0 - nb;
-        const ZView Sj = zview_sub(v.s, 0, j0);
-        const ZView W{w1 + (j0 / ZT) * ZT * ZT, 1, ZT, 0};
-        const ZView T{tmp, 1, v.m2, 0};
-        ZCK(zgemm(s, v.m2, nb, nb, 1.0, Sj, 0, ZMASK_NONE, W, 1, ZMASK_NONE, 0.0, T, ZMASK_NONE, info));
-        ZCK(zaxpby(s, v.m2, nb, 1.0, T, 0.0, Sj, ZMASK_NONE, info));
-        if (rest > 0)
-            ZCK(zgemm(s, v.m2, rest, nb, -1.0, Sj, 0, ZMASK_NONE, zview_sub(v.t1, j0 + nb, j0), 1, ZMASK_NONE, 1.0,
-                      zview_sub(v.s, 0, j0 + nb), ZMASK_NONE, info));
+    // step 2: TRSM, S <- S L11^{-H}: panels of ZB columns, 64-column steps
+    // inside a panel (X_j = S_j W_jj^H, then the panel's later columns), then
+    // the columns after the panel at once
+    for (int64_t p0 = 0; p0 < v.m1; p0 += ZB) {
+        const int64_t pe = std::min<int64_t>(v.m1, p0 + ZB);
+        for (int64_t j0 = p0; j0 < pe; j0 += ZT) {
+            const int64_t nb = std::min<int64_t>(ZT, pe - j0), cols = pe - j0 - nb;
+            const ZView Sj = zview_sub(v.s, 0, j0);
+            const ZView W{z.w1 + (j0 / ZT) * ZT * ZT, 1, ZT, 0};
+            const ZView T{z.tmp, 1, v.m2, 0};
+            ZCK(zgemm(s, v.m2, nb, nb, 1.0, Sj, 0, ZMASK_NONE, W, 1, ZMASK_NONE, 0.0, T, ZMASK_NONE, info));
+            ZCK(zaxpby(s, v.m2, nb, 1.0, T, 0.0, Sj, ZMASK_NONE, info));
+            if (cols > 0)
+                ZCK(zgemm(s, v.m2, cols, nb, -1.0, Sj, 0, ZMASK_NONE, zview_sub(v.t1, j0 + nb, j0), 1, ZMASK_NONE, 1.0,
+                          zview_sub(v.s, 0, j0 + nb), ZMASK_NONE, info));
+        }
+        if (pe < v.m1)
+            ZCK(zgemm(s, v.m2, v.m1 - pe, pe - p0, -1.0, zview_sub(v.s, 0, p0), 0, ZMASK_NONE,
+                      zview_sub(v.t1, pe, p0), 1, ZMASK_NONE, 1.0, zview_sub(v.s, 0, pe), ZMASK_NONE, info));
     }
     // step 3: HERK, T2 <- T2 - S S^H (lower triangle)
     ZCK(zgemm(s, v.m2, v.m2, v.m1, -1.0, v.s, 0, ZMASK_NONE, v.s, 1, ZMASK_NONE, 1.0, v.t2, 0, info));
     // step 4: POTRF on T2, INFO counted from the start of A
-    return zpotrf_view(s, v.t2, v.m2, w2, tmp, info, v.m1);
+    return zpotrf_view(s, v.t2, v.m2, z.w2, z.tmp, info, v.m1);
 }
 
 hipError_t zpftrs_run(hipStream_t s, const ZRfpViews& v, double2* b, int64_t ldb, int64_t nrhs, double2* work,
                       int* info)
 {
     (void)info;  // a zero on the factor's diagonal yields infinities, as in LAPACK
+    const ZWork z = zwork_split(v, work);
     const int64_t l1 = zleaves(v.m1), l2 = zleaves(v.m2);
-    double2* w1 = work;
-    double2* w2 = w1 + l1 * ZT * ZT;
-    double2* tmp = w2 + l2 * ZT * ZT;
-    ZCK(zleaf(s, v.t1, v.m1, 0, l1, ZLEAF_INV, w1, nullptr, 0, nullptr));
-    ZCK(zleaf(s, v.t2, v.m2, 0, l2, ZLEAF_INV, w2, nullptr, v.m1, nullptr));
+    ZCK(zleaf(s, v.t1, v.m1, 0, l1, ZLEAF_INV, z.w1, nullptr, 0, nullptr));
+    ZCK(zleaf(s, v.t2, v.m2, 0, l2, ZLEAF_INV, z.w2, nullptr, v.m1, nullptr));
     const ZView B{b, 1, ldb, 0};
-    const ZView T{tmp, 1, ZT, 0};
+    const ZView T{z.tmp, 1, ZT, 0};
     struct Part {
         ZView L;
         int64_t m, row0;
         double2* w;
-    } parts[2] = {{v.t1, v.m1, 0, w1}, {v.t2, v.m2, v.m1, w2}};
-    // forward, L Y = B: T1's rows, then B2 -= S Y1, then T2's rows
+    } parts[2] = {{v.t1, v.m1, 0, z.w1}, {v.t2, v.m2, v.m1, z.w2}};
+    // forward, L Y = B: T1's rows, then B2 -= S Y1, then T2's rows; inside a
+    // part, ZB-row panels of 64-row steps (the panel's later rows updated per
+    // step, the rows after the panel once per panel)
     for (int p = 0; p < 2; p++) {
         const Part& q = parts[p];
         if (p == 1 && v.m2 > 0)
             ZCK(zgemm(s, v.m2, nrhs, v.m1, -1.0, v.s, 0, ZMASK_NONE, B, 0, ZMASK_NONE, 1.0, zview_sub(B, v.m1, 0),
                       ZMASK_NONE, nullptr));
-        for (int64_t k0 = 0; k0 < q.m; k0 += ZT) {
-            const int64_t nb = std::min<int64_t>(ZT, q.m - k0), rest = q.m - k0 - nb;
-            const ZView Bk = zview_sub(B, q.row0 + k0, 0);
-            const ZView W{q.w + (k0 / ZT) * ZT * ZT, 1, ZT, 0};
-            ZCK(zgemm(s, nb, nrhs, nb, 1.0, W, 0, ZMASK_NONE, Bk, 0, ZMASK_NONE, 0.0, T, ZMASK_NONE, nullptr));
-            ZCK(zaxpby(s, nb, nrhs, 1.0, T, 0.0, Bk, ZMASK_NONE, nullptr));
-            if (rest > 0)
-                ZCK(zgemm(s, rest, nrhs, nb, -1.0, zview_sub(q.L, k0 + nb, k0), 0, ZMASK_NONE, Bk, 0, ZMASK_NONE, 1.0,
-                          zview_sub(B, q.row0 + k0 + nb, 0), ZMASK_NONE, nullptr));
+        for (int64_t p0 = 0; p0 < q.m; p0 += ZB) {
+            const int64_t pe = std::min<int64_t>(q.m, p0 + ZB);
+            for (int64_t k0 = p0; k0 < pe; k0 += ZT) {
+                const int64_t nb = std::min<int64_t>(ZT, pe - k0), rest = pe - k0 - nb;
+                const ZView Bk = zview_sub(B, q.row0 + k0, 0);
+                const ZView W{q.w + (k0 / ZT) * ZT * ZT, 1, ZT, 0};
+                ZCK(zgemm(s, nb, nrhs, nb, 1.0, W, 0, ZMASK_NONE, Bk, 0, ZMASK_NONE, 0.0, T, ZMASK_NONE, nullptr));
+                ZCK(zaxpby(s, nb, nrhs, 1.0, T, 0.0, Bk, ZMASK_NONE, nullptr));
+                if (rest > 0)
+                    ZCK(zgemm(s, rest, nrhs, nb, -1.0, zview_sub(q.L, k0 + nb, k0), 0, ZMASK_NONE, Bk, 0, ZMASK_NONE,
+                              1.0, zview_sub(B, q.row0 + k0 + nb, 0), ZMASK_NONE, nullptr));
+            }
+            if (pe < q.m)
+                ZCK(zgemm(s, q.m - pe, nrhs, pe - p0, -1.0, zview_sub(q.L, pe, p0), 0, ZMASK_NONE,
+                          zview_sub(B, q.row0 + p0, 0), 0, ZMASK_NONE, 1.0, zview_sub(B, q.row0 + pe, 0), ZMASK_NONE,
+                          nullptr));
         }
     }
-    // backward, L^H X = Y: T2's rows from the last, then B1 -= S^H X2, then T1's
+    // backward, L^H X = Y: T2's rows from the last, then B1 -= S^H X2, then
+    // T1's; ZB-row panels from the last, 64-row steps from the panel's last
     for (int p = 1; p >= 0; p--) {
         const Part& q = parts[p];
         if (p == 0 && v.m2 > 0)
             ZCK(zgemm(s, v.m1, nrhs, v.m2, -1.0, v.s, 1, ZMASK_NONE, zview_sub(B, v.m1, 0), 0, ZMASK_NONE, 1.0, B,
                       ZMASK_NONE, nullptr));
-        for (int64_t k0 = (q.m - 1) / ZT * ZT; q.m > 0 && k0 >= 0; k0 -= ZT) {
-            const int64_t nb = std::min<int64_t>(ZT, q.m - k0);
-            const ZView Bk = zview_sub(B, q.row0 + k0, 0);
-            const ZView W{q.w + (k0 / ZT) * ZT * ZT, 1, ZT, 0};
-            ZCK(zgemm(s, nb, nrhs, nb, 1.0, W, 1, ZMASK_NONE, Bk, 0, ZMASK_NONE, 0.0, T, ZMASK_NONE, nullptr));
-            ZCK(zaxpby(s, nb, nrhs, 1.0, T, 0.0, Bk, ZMASK_NONE, nullptr));
-            if (k0 > 0)  // rows above: B(0:k0) -= L(k, 0:k0)^H X_k
-                ZCK(zgemm(s, k0, nrhs, nb, -1.0, zview_sub(q.L, k0, 0), 1, ZMASK_NONE, Bk, 0, ZMASK_NONE, 1.0,
-                          zview_sub(B, q.row0, 0), ZMASK_NONE, nullptr));
+        for (int64_t p0 = (q.m - 1) / ZB * ZB; q.m > 0 && p0 >= 0; p0 -= ZB) {
+            const int64_t pe = std::min<int64_t>(q.m, p0 + ZB);
+            for (int64_t k0 = (pe - 1) / ZT * ZT; k0 >= p0; k0 -= ZT) {
+                const int64_t nb = std::min<int64_t>(ZT, pe - k0);
+                const ZView Bk = zview_sub(B, q.row0 + k0, 0);
+                const ZView W{q.w + (k0 / ZT) * ZT * ZT, 1, ZT, 0};
+                ZCK(zgemm(s, nb, nrhs, nb, 1.0, W, 1, ZMASK_NONE, Bk, 0, ZMASK_NONE, 0.0, T, ZMASK_NONE, nullptr));
+                ZCK(zaxpby(s, nb, nrhs, 1.0, T, 0.0, Bk, ZMASK_NONE, nullptr));
+                if (k0 > p0)  // the panel's rows above: B(p0:k0) -= L(k, p0:k0)^H X_k
+                    ZCK(zgemm(s, k0 - p0, nrhs, nb, -1.0, zview_sub(q.L, k0, p0), 1, ZMASK_NONE, Bk, 0, ZMASK_NONE,
+                              1.0, zview_sub(B, q.row0 + p0, 0), ZMASK_NONE, nullptr));
+            }
+            if (p0 > 0)  // rows before the panel: B(0:p0) -= L(p0:pe, 0:p0)^H X_panel
+                ZCK(zgemm(s, p0, nrhs, pe - p0, -1.0, zview_sub(q.L, p0, 0), 1, ZMASK_NONE,
+                          zview_sub(B, q.row0 + p0, 0), 0, ZMASK_NONE, 1.0, zview_sub(B, q.row0, 0), ZMASK_NONE,
+                          nullptr));
         }
     }
     return hipSuccess;
@@ -556,13 +676,13 @@ static hipError_t ztrtri_view(hipStream_t s, const ZView& A, int64_t m, double2*
     return hipSuccess;
 }
 
-// W^H W in place on the m x m lower view holding W (row blocks from the
-// first): C(I, 0:i0+nb) = W(i0:m, I)^H W(i0:m, 0:i0+nb).
+// W^H W in place on the m x m lower view holding W (row blocks of ZB from
+// the first): C(I, 0:i0+nb) = W(i0:m, I)^H W(i0:m, 0:i0+nb).
 static hipError_t zlauum_view(hipStream_t s, const ZView& A, int64_t m, double2* tmp, const int* gate)
 {
-    for (int64_t i0 = 0; i0 < m; i0 += ZT) {
-        const int64_t nb = std::min<int64_t>(ZT, m - i0);
-        const ZView T{tmp, 1, ZT, 0};
+    for (int64_t i0 = 0; i0 < m; i0 += ZB) {
+        const int64_t nb = std::min<int64_t>(ZB, m - i0);
+        const ZView T{tmp, 1, ZB, 0};
         ZCK(zgemm(s, nb, i0 + nb, m - i0, 1.0, zview_sub(A, i0, i0), 1, 0, zview_sub(A, i0, 0), 0, -i0, 0.0, T,
                   ZMASK_NONE, gate));
         ZCK(zaxpby(s, nb, i0 + nb, 1.0, T, 0.0, zview_sub(A, i0, 0), -i0, gate));
@@ -572,45 +692,44 @@ static hipError_t zlauum_view(hipStream_t s, const ZView& A, int64_t m, double2*
 
 hipError_t zpftri_run(hipStream_t s, const ZRfpViews& v, double2* work, int* info)
 {
-    const int64_t l1 = zleaves(v.m1), l2 = zleaves(v.m2);
-    double2* w1 = work;
-    double2* w2 = w1 + l1 * ZT * ZT;
-    double2* tmp = w2 + l2 * ZT * ZT;
+    const ZWork z = zwork_split(v, work);
+    const int64_t l2 = zleaves(v.m2);
+    (void)l2;
     // stage A: W = L^{-1} on the three blocks
-    ZCK(ztrtri_view(s, v.t1, v.m1, w1, tmp, info, 0));
+    ZCK(ztrtri_view(s, v.t1, v.m1, z.w1, z.tmp, info, 0));
     if (v.m2 > 0) {
-        // S <- -S W11, block columns from the first (column block j reads
-        // columns >= j only)
-        for (int64_t j0 = 0; j0 < v.m1; j0 += ZT) {
-            const int64_t nb = std::min<int64_t>(ZT, v.m1 - j0);
-            const ZView T{tmp, 1, v.m2, 0};
+        // S <- -S W11, block columns of ZB from the first (column block j
+        // reads columns >= j only)
+        for (int64_t j0 = 0; j0 < v.m1; j0 += ZB) {
+            const int64_t nb = std::min<int64_t>(ZB, v.m1 - j0);
+            const ZView T{z.tmp, 1, v.m2, 0};
             ZCK(zgemm(s, v.m2, nb, v.m1 - j0, 1.0, zview_sub(v.s, 0, j0), 0, ZMASK_NONE, zview_sub(v.t1, j0, j0), 0, 0,
                       0.0, T, ZMASK_NONE, info));
             ZCK(zaxpby(s, v.m2, nb, -1.0, T, 0.0, zview_sub(v.s, 0, j0), ZMASK_NONE, info));
         }
-        ZCK(ztrtri_view(s, v.t2, v.m2, w2, tmp, info, v.m1));
-        // S <- W22 S, row blocks from the last (row block i reads rows <= i)
-        for (int64_t i0 = (l2 - 1) * ZT; i0 >= 0; i0 -= ZT) {
-            const int64_t nb = std::min<int64_t>(ZT, v.m2 - i0);
-            const ZView T{tmp, 1, ZT, 0};
+        ZCK(ztrtri_view(s, v.t2, v.m2, z.w2, z.tmp, info, v.m1));
+        // S <- W22 S, row blocks of ZB from the last (row block i reads rows <= i)
+        for (int64_t i0 = (v.m2 - 1) / ZB * ZB; i0 >= 0; i0 -= ZB) {
+            const int64_t nb = std::min<int64_t>(ZB, v.m2 - i0);
+            const ZView T{z.tmp, 1, ZB, 0};
             ZCK(zgemm(s, nb, v.m1, i0 + nb, 1.0, zview_sub(v.t2, i0, 0), 0, -i0, v.s, 0, ZMASK_NONE, 0.0, T,
                       ZMASK_NONE, info));
             ZCK(zaxpby(s, nb, v.m1, 1.0, T, 0.0, zview_sub(v.s, i0, 0), ZMASK_NONE, info));
         }
     }
     // stage B: A^{-1} = W^H W
-    ZCK(zlauum_view(s, v.t1, v.m1, tmp, info));
+    ZCK(zlauum_view(s, v.t1, v.m1, z.tmp, info));
     if (v.m2 > 0) {
         ZCK(zgemm(s, v.m1, v.m1, v.m2, 1.0, v.s, 1, ZMASK_NONE, v.s, 0, ZMASK_NONE, 1.0, v.t1, 0, info));
-        // S <- W22^H S, row blocks from the first (row block i reads rows >= i)
-        for (int64_t i0 = 0; i0 < v.m2; i0 += ZT) {
-            const int64_t nb = std::min<int64_t>(ZT, v.m2 - i0);
-            const ZView T{tmp, 1, ZT, 0};
+        // S <- W22^H S, row blocks of ZB from the first (row block i reads rows >= i)
+        for (int64_t i0 = 0; i0 < v.m2; i0 += ZB) {
+            const int64_t nb = std::min<int64_t>(ZB, v.m2 - i0);
+            const ZView T{z.tmp, 1, ZB, 0};
             ZCK(zgemm(s, nb, v.m1, v.m2 - i0, 1.0, zview_sub(v.t2, i0, i0), 1, 0, zview_sub(v.s, i0, 0), 0,
                       ZMASK_NONE, 0.0, T, ZMASK_NONE, info));
             ZCK(zaxpby(s, nb, v.m1, 1.0, T, 0.0, zview_sub(v.s, i0, 0), ZMASK_NONE, info));
         }
-        ZCK(zlauum_view(s, v.t2, v.m2, tmp, info));
+        ZCK(zlauum_view(s, v.t2, v.m2, z.tmp, info));
     }
     return hipSuccess;
 }

@@ -224,3 +224,37 @@ def test_zargument_codes(h):
     with pytest.raises(rfp.RfpError) as e:
         rfp.rfp_zpftrf(h, "N", "L", -1, t, info)
     assert e.value.code == -3
+
+
+@pytest.mark.parametrize("transr,uplo", [("N", "U"), ("C", "L")])
+def test_zsplit_k_products_n1100(h, transr, uplo):
+    """n = 1100: block products with K >= 512 and fewer than 256 tiles take the
+    split-K form (partial sums added in a fixed order): the HERK of ZPFTRF,
+    S Y1 and S^H X2 of ZPFTRS, and the triangular products of ZPFTRI."""
+    n, nrhs = 1100, 8
+    a, b = synth.hpd(n, nrhs=nrhs, seed=1100)
+    arf = oracle.ztrttf(transr, uplo, a)
+    t = dev(arf)
+    info = info_tensor()
+    rfp.rfp_zpftrf(h, transr, uplo, n, t, info)
+    assert read_info(info) == 0
+    ref, _ = oracle.zpftrf(transr, uplo, n, arf)
+    got = host(t)
+    assert rel(got, ref) <= 1e-12 * n
+    assert np.abs(got - ref).max() <= 8 * n * U * np.abs(ref).max()
+    tb = dev_colmajor(b)
+    rfp.rfp_zpftrs(h, transr, uplo, n, t, tb)
+    x = host_colmajor(tb)
+    assert rel(x, oracle.zpftrs(transr, uplo, n, ref, b)) <= 1e-12 * n
+    assert oracle.zbackward_error(transr, uplo, n, arf, b, x) < 1e-15
+    rfp.rfp_zpftri(h, transr, uplo, n, t, info)
+    assert read_info(info) == 0
+    inv = oracle.ztfttr(transr, uplo, n, host(t))
+    dense = np.linalg.inv(a)
+    tri = np.tril if uplo == "L" else np.triu
+    m = tri(np.ones((n, n), bool))
+    assert rel(inv[m], dense[m]) <= 1e-12 * n
+    # the same products again: identical bits (the split sums are ordered)
+    t2 = dev(arf)
+    rfp.rfp_zpftrf(h, transr, uplo, n, t2, info)
+    assert np.array_equal(host(t2), got)
