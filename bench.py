@@ -209,6 +209,59 @@ def bench_cfg1(h, reps=10):
     return out
 
 
+def bench_complex(h, sizes=(20000, 20001), layouts=("NL", "NU", "CL", "CU"), nrhs=128):
+    """Complex Hermitian path: ZPFTRF, ZPFTRS and ZPFTRI on A = M M^H/n + I
+    (M with N(0,1) real and imaginary parts, seed n), each layout timed once
+    with events (the input restored outside the timed events).  Flops count a
+    complex multiply-add as 8 real flops: 4n^3/3, 8n^2 nrhs, 8n^3/3."""
+    import torch
+    import paper_0901_1696_amd as rfp
+    import synth
+
+    dev = torch.device("cuda:0")
+    tot = {"zpftrf": [0.0, 0.0], "zpftrs": [0.0, 0.0], "zpftri": [0.0, 0.0]}
+    worst = 0.0
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    for n in sizes:
+        A, B = synth.hpd_device(n, nrhs=nrhs, seed=n, device=dev)
+        w = torch.empty(rfp.nt(n), dtype=torch.complex128, device=dev)
+        for lay in layouts:
+            t, u = lay[0], lay[1]
+            rfp.rfp_ztrttf(h, t, u, n, A, w)
+            x = B.clone()
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[0].record()
+            rfp.rfp_zpftrf(h, t, u, n, w, info)
+            ev[1].record()
+            rfp.rfp_zpftrs(h, t, u, n, w, x)
+            ev[2].record()
+            rfp.rfp_zpftri(h, t, u, n, w, info)
+            ev[3].record()
+            ev[3].synchronize()
+            if int(info.item()) != 0:
+                raise SystemExit(f"complex {lay}{n}: INFO={int(info.item())}")
+            fl = {"zpftrf": 4 * n ** 3 / 3, "zpftrs": 8.0 * n * n * nrhs, "zpftri": 8 * n ** 3 / 3}
+            for k, (a, b) in zip(tot, [(0, 1), (1, 2), (2, 3)]):
+                tot[k][0] += ev[a].elapsed_time(ev[b])
+                tot[k][1] += fl[k]
+            r = B - A @ x
+            eta = (r.abs().amax(0) / (torch.linalg.matrix_norm(A, ord=float("inf")) * x.abs().amax(0)
+                                      + B.abs().amax(0))).max().item()
+            worst = max(worst, eta)
+            del x, r
+        del A, B, w
+        torch.cuda.empty_cache()
+    runs = len(sizes) * len(layouts)
+    out = {"n": list(sizes), "layouts": list(layouts), "nrhs": nrhs,
+           "flop_model": "complex multiply-add = 8 flops: ZPFTRF 4n^3/3, ZPFTRS 8n^2 nrhs, ZPFTRI 8n^3/3"}
+    for k, (ms, fl) in tot.items():
+        out[k] = {"gflops": round(fl / (ms * 1e-3) / 1e9, 1), "ms_per_call": round(ms / runs, 2)}
+    out["max_backward_error"] = worst
+    log(f"[bench] complex {out}")
+    return out
+
+
 def bench_mixed(h, n, nrhs=16, kappas=(1e3, 1e6), reps=2):
     """FP64 PFTRF+PFTRS vs low-precision factor + FP64 refinement at equal backward error."""
     import torch
@@ -481,7 +534,8 @@ def main():
     ap.add_argument("--mixed-n", type=int, default=40000)
     ap.add_argument("--no-kernel-profile", action="store_true",
                     help="skip the per-launch event timing (and the roofline); for counter collection runs")
-    ap.add_argument("--only", choices=["pftri", "pftrs", "mixed", "batched", "batched_medium", "cfg1"],
+    ap.add_argument("--no-complex", action="store_true")
+    ap.add_argument("--only", choices=["pftri", "pftrs", "mixed", "batched", "batched_medium", "cfg1", "complex"],
                     help="run one section alone (for profiler runs) and print its JSON")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
@@ -507,10 +561,11 @@ def main():
     import paper_0901_1696_amd as rfp
     import synth
 
-    if args.only in ("mixed", "batched", "batched_medium", "cfg1"):
+    if args.only in ("mixed", "batched", "batched_medium", "cfg1", "complex"):
         h = rfp.Handle(0)
         fn = {"mixed": lambda: bench_mixed(h, args.mixed_n), "batched": lambda: bench_batched(h),
-              "batched_medium": lambda: bench_batched_medium(h), "cfg1": lambda: bench_cfg1(h)}[args.only]
+              "batched_medium": lambda: bench_batched_medium(h), "cfg1": lambda: bench_cfg1(h),
+              "complex": lambda: bench_complex(h)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         h.close()
         return
@@ -700,6 +755,7 @@ def main():
     mixed = None if args.no_mixed else bench_mixed(h, args.mixed_n)
     batched = None if args.no_batched else bench_batched(h)
     batched_medium = None if args.no_batched else bench_batched_medium(h)
+    complex_ = None if args.no_complex else bench_complex(h)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -716,7 +772,7 @@ def main():
                    "n": sizes, "layouts": [t + u for t, u in layouts], "nrhs": nrhs},
         "roofline": roofline, "profiled_region": prof_region, "cpu_baseline": cpu, "pftri": pftri,
         "accuracy": accuracy, "conversions": conversions, "cfg1": cfg1,
-        "mixed": mixed, "batched": batched, "batched_medium": batched_medium,
+        "mixed": mixed, "batched": batched, "batched_medium": batched_medium, "complex": complex_,
         "kernels": kernel_table,
         "paper_context": "PFTRF 90.7-93.0 GFLOP/s at n=20000 on a 16-core Intel Tigerton with MKL "
                          "(paper's zootfac_vendor table); another machine, not the target",

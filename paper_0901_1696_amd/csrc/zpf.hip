@@ -33,6 +33,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int ZT = 64;  // C tile (rows and columns) and leaf order
 constexpr int ZK = 16;  // K step of the product
+constexpr int ZQ = ZT * ZK / 256;  // operand elements per thread and K step
 
 __device__ __forceinline__ double2 zconj_if(double2 v, bool c)
 {
@@ -61,7 +62,7 @@ struct ZGemm {
     double2* part;
 };
 
-__global__ __launch_bounds__(256) void zgemm_kernel(ZGemm g)
+__global__ __launch_bounds__(256, 2) void zgemm_kernel(ZGemm g)
 {
     if (g.gate && *g.gate) return;
     const int64_t i0 = (int64_t)blockIdx.x * ZT, j0 = (int64_t)blockIdx.y * ZT;
@@ -87,41 +88,43 @@ __global__ __launch_bounds__(256) void zgemm_kernel(ZGemm g)
     }
 
     // staging maps: the element index e = t + 256 q runs along the operand's
-    // unit stride (coalesced loads)
+    // unit stride (coalesced loads): element q of a thread is (i0 + i, k) with
+    // i = i_0 + q di, k = k_0 + q dk (di, dk: 0 and 8, or 4 and 0), so its
+    // address is base + q step + k0 times the stride along K.
     const bool a_fast_i = (g.ta ? g.A.cs : g.A.rs) == 1;
     const bool b_fast_j = (g.tb ? g.B.rs : g.B.cs) == 1;
     const bool aconj = g.A.conj != (g.ta != 0), bconj = g.B.conj != (g.tb != 0);
-    double2 ra[4], rb[4];
+    const int64_t a_is = g.ta ? g.A.cs : g.A.rs, a_ks = g.ta ? g.A.rs : g.A.cs;  // strides along i and K
+    const int64_t b_js = g.tb ? g.B.rs : g.B.cs, b_ks = g.tb ? g.B.cs : g.B.rs;  // along j and K
+    const int ai_0 = a_fast_i ? (t & (ZT - 1)) : t / ZK, ak_0 = a_fast_i ? t / ZT : (t & (ZK - 1));
+    const int a_di = a_fast_i ? 0 : 256 / ZK, a_dk = a_fast_i ? 256 / ZT : 0;
+    const int bj_0 = b_fast_j ? (t & (ZT - 1)) : t / ZK, bk_0 = b_fast_j ? t / ZT : (t & (ZK - 1));
+    const int b_dj = b_fast_j ? 0 : 256 / ZK, b_dk = b_fast_j ? 256 / ZT : 0;
+    const double2* a_base = g.A.p + (i0 + ai_0) * a_is + ak_0 * a_ks;
+    const double2* b_base = g.B.p + (j0 + bj_0) * b_js + bk_0 * b_ks;
+    const int64_t a_step = a_di * a_is + a_dk * a_ks, b_step = b_dj * b_js + b_dk * b_ks;
+    double2 ra[ZQ], rb[ZQ];
     auto load = [&](int64_t k0) {
+        const double2* pa = a_base + k0 * a_ks;
+        const double2* pb = b_base + k0 * b_ks;
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const int e = t + 256 * q;
-            {
-                const int i = a_fast_i ? e % ZT : e / ZK, k = a_fast_i ? e / ZT : e % ZK;
-                const int64_t gi = i0 + i, gk = k0 + k;
-                const int64_t r = g.ta ? gk : gi, c = g.ta ? gi : gk;
-                const bool in = gi < g.M && gk >= klo && gk < khi && r - c >= g.mda;
-                ra[q] = in ? zconj_if(g.A.p[r * g.A.rs + c * g.A.cs], aconj) : make_double2(0.0, 0.0);
-            }
-            {
-                const int j = b_fast_j ? e % ZT : e / ZK, k = b_fast_j ? e / ZT : e % ZK;
-                const int64_t gj = j0 + j, gk = k0 + k;
-                const int64_t r = g.tb ? gj : gk, c = g.tb ? gk : gj;
-                const bool in = gj < g.N && gk >= klo && gk < khi && r - c >= g.mdb;
-                rb[q] = in ? zconj_if(g.B.p[r * g.B.rs + c * g.B.cs], bconj) : make_double2(0.0, 0.0);
-            }
+        for (int q = 0; q < ZQ; q++) {
+            const int64_t gi = i0 + ai_0 + q * a_di, gka = k0 + ak_0 + q * a_dk;
+            const int64_t gj = j0 + bj_0 + q * b_dj, gkb = k0 + bk_0 + q * b_dk;
+            // masks on the stored (row - column): A(gi, k) or A(k, gi); B(k, gj) or B(gj, k)
+            const bool ia = gi < g.M && gka >= klo && gka < khi && (g.ta ? gka - gi : gi - gka) >= g.mda;
+            const bool ib = gj < g.N && gkb >= klo && gkb < khi && (g.tb ? gj - gkb : gkb - gj) >= g.mdb;
+            ra[q] = ia ? zconj_if(pa[q * a_step], aconj) : make_double2(0.0, 0.0);
+            rb[q] = ib ? zconj_if(pb[q * b_step], bconj) : make_double2(0.0, 0.0);
         }
     };
     auto stage = [&]() {
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const int e = t + 256 * q;
-            const int ia = a_fast_i ? e % ZT : e / ZK, ka = a_fast_i ? e / ZT : e % ZK;
-            Ar[ka][ia] = ra[q].x;
-            Ai[ka][ia] = ra[q].y;
-            const int jb = b_fast_j ? e % ZT : e / ZK, kb = b_fast_j ? e / ZT : e % ZK;
-            Br[kb][jb] = rb[q].x;
-            Bi[kb][jb] = rb[q].y;
+        for (int q = 0; q < ZQ; q++) {
+            Ar[ak_0 + q * a_dk][ai_0 + q * a_di] = ra[q].x;
+            Ai[ak_0 + q * a_dk][ai_0 + q * a_di] = ra[q].y;
+            Br[bk_0 + q * b_dk][bj_0 + q * b_dj] = rb[q].x;
+            Bi[bk_0 + q * b_dk][bj_0 + q * b_dj] = rb[q].y;
         }
     };
 
