@@ -262,6 +262,67 @@ def bench_complex(h, sizes=(20000, 20001), layouts=("NL", "NU", "CL", "CU"), nrh
     return out
 
 
+def bench_pf_vs_po(h, sizes=(20000, 40000), nrhs=128, hbm_bytes=288e9):
+    """The paper's central comparison (PF against PO, Section 8) on this GPU:
+    FP64 PFTRF and PFTRS on the RFP array against the vendor's full-storage
+    Cholesky and solve as torch calls them (ROCm's LAPACK-style potrf/potrs on
+    the n x n array; PFTRI is timed alone), on the same matrix at equal n,
+    each event-timed once after a warm-up; plus the storage each needs and
+    the largest n whose matrix fits in the GPU's memory."""
+    import torch
+    import paper_0901_1696_amd as rfp
+    import synth
+
+    dev = torch.device("cuda:0")
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    rows = []
+    for n in sizes:
+        A, B = synth.spd_device(n, nrhs=nrhs, seed=n, device=dev)
+        w = torch.empty(rfp.nt(n), dtype=torch.float64, device=dev)
+        pf, po = {}, {}
+
+        def timed(fn):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            out = fn()
+            e1.record()
+            e1.synchronize()
+            return e0.elapsed_time(e1), out
+
+        for rep in range(2):
+            rfp.rfp_dtrttf(h, "N", "L", n, A, w)
+            x = B.clone()
+            pf["trf"], _ = timed(lambda: rfp.rfp_dpftrf(h, "N", "L", n, w, info))
+            pf["trs"], _ = timed(lambda: rfp.rfp_dpftrs(h, "N", "L", n, w, x))
+            pf["tri"], _ = timed(lambda: rfp.rfp_dpftri(h, "N", "L", n, w, info))
+            del x
+            po["trf"], L = timed(lambda: torch.linalg.cholesky(A))
+            po["trs"], y = timed(lambda: torch.cholesky_solve(B, L))
+            del L, y
+            torch.cuda.empty_cache()
+        if int(info.item()) != 0:
+            raise SystemExit(f"pf_vs_po n={n}: INFO={int(info.item())}")
+        fl = {"trf": flops_trf(n), "trs": flops_trs(n, nrhs), "tri": flops_tri(n)}
+        row = {"n": n, "nrhs": nrhs, "layout": "NL"}
+        for k in fl:
+            row[f"pf_{k}_gflops"] = round(fl[k] / (pf[k] * 1e-3) / 1e9, 1)
+            if k in po:
+                row[f"po_{k}_gflops"] = round(fl[k] / (po[k] * 1e-3) / 1e9, 1)
+                row[f"pf_over_po_{k}"] = round(po[k] / pf[k], 3)
+        row["pf_bytes"] = 8 * rfp.nt(n)
+        row["po_bytes"] = 8 * n * n
+        rows.append(row)
+        del A, B, w
+        torch.cuda.empty_cache()
+    nmax_pf = int(((1 + hbm_bytes) ** 0.5 - 1) / 2)  # 8 n (n + 1) / 2 = 4 n (n + 1) <= bytes
+    nmax_po = int((hbm_bytes / 8) ** 0.5)
+    out = {"runs": rows, "po": "torch.linalg.cholesky / cholesky_solve (FP64, n x n storage); the vendor inverse "
+                                "through torch (cholesky_inverse) fails at these n, so PO inversion is not compared",
+           "largest_n_fitting_288GB": {"pf": nmax_pf, "po": nmax_po}}
+    log(f"[bench] pf_vs_po {out}")
+    return out
+
+
 def bench_mixed(h, n, nrhs=16, kappas=(1e3, 1e6), reps=2):
     """FP64 PFTRF+PFTRS vs low-precision factor + FP64 refinement at equal backward error."""
     import torch
@@ -535,7 +596,9 @@ def main():
     ap.add_argument("--no-kernel-profile", action="store_true",
                     help="skip the per-launch event timing (and the roofline); for counter collection runs")
     ap.add_argument("--no-complex", action="store_true")
-    ap.add_argument("--only", choices=["pftri", "pftrs", "mixed", "batched", "batched_medium", "cfg1", "complex"],
+    ap.add_argument("--no-pf-vs-po", action="store_true")
+    ap.add_argument("--only", choices=["pftri", "pftrs", "mixed", "batched", "batched_medium", "cfg1", "complex",
+                                       "pf_vs_po"],
                     help="run one section alone (for profiler runs) and print its JSON")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
@@ -561,11 +624,11 @@ def main():
     import paper_0901_1696_amd as rfp
     import synth
 
-    if args.only in ("mixed", "batched", "batched_medium", "cfg1", "complex"):
+    if args.only in ("mixed", "batched", "batched_medium", "cfg1", "complex", "pf_vs_po"):
         h = rfp.Handle(0)
         fn = {"mixed": lambda: bench_mixed(h, args.mixed_n), "batched": lambda: bench_batched(h),
               "batched_medium": lambda: bench_batched_medium(h), "cfg1": lambda: bench_cfg1(h),
-              "complex": lambda: bench_complex(h)}[args.only]
+              "complex": lambda: bench_complex(h), "pf_vs_po": lambda: bench_pf_vs_po(h)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         h.close()
         return
@@ -756,6 +819,7 @@ def main():
     batched = None if args.no_batched else bench_batched(h)
     batched_medium = None if args.no_batched else bench_batched_medium(h)
     complex_ = None if args.no_complex else bench_complex(h)
+    pf_vs_po = None if args.no_pf_vs_po else bench_pf_vs_po(h)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -773,6 +837,7 @@ def main():
         "roofline": roofline, "profiled_region": prof_region, "cpu_baseline": cpu, "pftri": pftri,
         "accuracy": accuracy, "conversions": conversions, "cfg1": cfg1,
         "mixed": mixed, "batched": batched, "batched_medium": batched_medium, "complex": complex_,
+        "pf_vs_po": pf_vs_po,
         "kernels": kernel_table,
         "paper_context": "PFTRF 90.7-93.0 GFLOP/s at n=20000 on a 16-core Intel Tigerton with MKL "
                          "(paper's zootfac_vendor table); another machine, not the target",
