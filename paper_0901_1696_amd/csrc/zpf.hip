@@ -35,6 +35,8 @@ constexpr int ZT = 64;  // C tile (rows and columns) and leaf order
 constexpr int ZK = 16;  // K step of the product
 constexpr int ZQ = ZT * ZK / 256;  // operand elements per thread and K step
 
+__device__ __forceinline__ void wave_sync_z() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
 __device__ __forceinline__ double2 zconj_if(double2 v, bool c)
 {
     if (c) v.y = -v.y;
@@ -306,38 +308,38 @@ __global__ __launch_bounds__(256) void zleaf_kernel(ZView A, int64_t m, int mode
         zero_sh = 1 << 30;  // first zero on the diagonal (INV modes)
     }
     __syncthreads();
+    const int ti = t & (ZT - 1), tq = t >> 6;  // trailing update: row ti, columns tq, tq + 4, ...
     if (mode == ZLEAF_FACTOR) {
+        // right-looking, one column per step, two barriers per step
         for (int j = 0; j < nb; j++) {
-            const double d = Lr[j][j];
-            if (!(d > 0.0)) {  // uniform: every thread reads the same LDS word
+            const double d = Lr[j][j];  // final since the previous step's barrier
+            if (!(d > 0.0)) {           // uniform: every thread reads the same LDS word
                 if (t == 0) {
                     info_first(info, (int)(info_off + k0 + j + 1));
                     fail_sh = 1;
                 }
                 break;
             }
-            const double l = sqrt(d);
-            __syncthreads();  // every thread has read L(j, j)
-            if (t < ZT) {
-                if (t == j) Lr[j][j] = l;
-                else if (t > j && t < nb) {
-                    Lr[t][j] /= l;
-                    Li[t][j] /= l;
-                }
+            const double l = sqrt(d), rl = 1.0 / l;
+            if (t > j && t < nb) {
+                Lr[t][j] *= rl;
+                Li[t][j] *= rl;
             }
             __syncthreads();
+            // L(j, j) is not read again in this step (every thread has d)
+            if (t == 0) Lr[j][j] = l;
             // trailing lower triangle: L(i, c) -= L(i, j) conj(L(c, j)), j < c <= i
-            for (int e = t; e < ZT * ZT; e += 256) {
-                const int i = e % ZT, c = e / ZT;
-                if (c > j && i >= c && i < nb) {
-                    const double xr = Lr[i][j], xi = Li[i][j], yr = Lr[c][j], yi = Li[c][j];
+            const int i = j + 1 + ti;
+            if (i < nb) {
+                const double xr = Lr[i][j], xi = Li[i][j];
+                for (int c = j + 1 + tq; c <= i; c += 4) {
+                    const double yr = Lr[c][j], yi = Li[c][j];
                     Lr[i][c] -= xr * yr + xi * yi;
                     Li[i][c] -= xi * yr - xr * yi;
                 }
             }
             __syncthreads();
         }
-        __syncthreads();
         if (fail_sh) return;
         // the factor back into the view (lower triangle of the block)
         for (int e = t; e < ZT * ZT; e += 256) {
@@ -353,25 +355,34 @@ __global__ __launch_bounds__(256) void zleaf_kernel(ZView A, int64_t m, int mode
             return;
         }
     }
-    // W = L^{-1}: thread c forms column c by forward substitution,
-    // W(i, c) = -(sum_{k = c}^{i-1} L(i, k) W(k, c)) / L(i, i)
-    if (t < ZT) {
-        const int c = t;
-        for (int i = 0; i < ZT; i++) {
+    // W = L^{-1} by forward substitution down each column,
+    // W(i, c) = -(sum_{k = c}^{i-1} L(i, k) W(k, c)) / L(i, i): four lanes of
+    // one wavefront per column (lane part p sums k = c + p, c + p + 4, ...),
+    // so a column never waits on another wavefront
+    {
+        const int c = t >> 2, part = t & 3;
+        for (int i = part; i < ZT; i += 4) {
             Wr[i][c] = 0.0;
             Wi[i][c] = 0.0;
         }
-        if (c < nb) {
-            Wr[c][c] = 1.0 / Lr[c][c];
-            for (int i = c + 1; i < nb; i++) {
-                double sr = 0.0, si = 0.0;
-                for (int k = c; k < i; k++) {
+        wave_sync_z();
+        for (int i = 0; i < nb; i++) {
+            double sr = 0.0, si = 0.0;
+            if (c < i && c < nb)
+                for (int k = c + part; k < i; k += 4) {
                     sr += Lr[i][k] * Wr[k][c] - Li[i][k] * Wi[k][c];
                     si += Lr[i][k] * Wi[k][c] + Li[i][k] * Wr[k][c];
                 }
-                Wr[i][c] = -sr / Lr[i][i];
-                Wi[i][c] = -si / Lr[i][i];
+            sr += __shfl_xor(sr, 1);
+            si += __shfl_xor(si, 1);
+            sr += __shfl_xor(sr, 2);
+            si += __shfl_xor(si, 2);
+            if (part == 0 && c <= i && c < nb) {
+                const double rd = 1.0 / Lr[i][i];
+                Wr[i][c] = i == c ? rd : -sr * rd;
+                Wi[i][c] = i == c ? 0.0 : -si * rd;
             }
+            wave_sync_z();  // row i of the column is visible to its four lanes
         }
     }
     __syncthreads();
