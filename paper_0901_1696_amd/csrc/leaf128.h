@@ -209,26 +209,14 @@ struct Leaf128Smem {
 
 }  // namespace
 
-// Factor the lower triangle of A (order nb <= 128) in place; when winv is not
-// null, write W = L^{-1} to it (128 x 128 row-major, zero above the diagonal,
-// identity on the padding).  Returns 0, or j + 1 for the first pivot j that
-// is not positive (then *info = info_base + j + 1 when info is not null and
-// A is left partly updated).  All 256 threads must call it; it ends with a
-// barrier.
+// The packed lower triangle of A (order nb <= 128) into L (and the rest of
+// each diagonal block, as zeros); rows past nb are the identity.  All 256
+// threads; no barrier at the end.
 template <typename T>
-__device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int* info, int64_t info_base)
+__device__ __forceinline__ void leaf128_load(T* L, Mat<T> A, int nb)
 {
-    T* L = sm.L;
-    T(&Wd)[D][DP] = sm.Wd;  // Wd[r][c] = (L_jj^{-1})(r, c)
-    int& fail = sm.fail;
-
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int r = lane & 15, g = lane >> 4;  // MFMA operand row and k offset of the lane
-    RFP_LEAF_STAMP(32);
-    if (t == 0) fail = 0;
+    const int t = threadIdx.x;
     const bool colmajor = A.rs == 1;
-    // the packed triangle (and the rest of each diagonal block, as zeros);
-    // rows past nb are the identity
     // In two batches of 32 per thread: all loads first (each lane from its
     // element clamped into the stored lower triangle, a valid address), then
     // the LDS stores.  A's pointer is generic, so a load written after an LDS
@@ -256,6 +244,163 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
             }
         }
     }
+}
+
+// L's own lower triangle (order nb) back into A (the other triangle of A is
+// another block's data).  All 256 threads; no barrier.
+template <typename T>
+__device__ __forceinline__ void leaf128_store(const T* L, Mat<T> A, int nb)
+{
+    const int t = threadIdx.x;
+    const bool colmajor = A.rs == 1;
+    // its own lower triangle only, with stepped addresses
+    // (column-major: each thread one row, every other column; row-major: one
+    // row per wave and step, one column per lane)
+    // (LDS reads batched ahead of the stores, as for the load; reads past a
+    // packed row stay inside L and are not stored)
+    if (colmajor) {
+        const int i = t & (N - 1), j0 = t >> 7;
+        if (i < nb) {
+            T* a = A.p + i + (int64_t)j0 * A.cs;
+            const T* l = L + prow(i) + j0;
+            for (int u0 = 0; u0 < N / 2 && j0 + 2 * u0 <= i; u0 += 16) {
+                T v[16];
+#pragma unroll
+                for (int u = 0; u < 16; u++) v[u] = l[2 * (u0 + u)];
+#pragma unroll
+                for (int u = 0; u < 16; u++)
+                    if (j0 + 2 * (u0 + u) <= i) a[2 * (int64_t)(u0 + u) * A.cs] = v[u];
+            }
+        }
+    } else {
+        const int j = t & (N - 1);
+        const int64_t jo = (int64_t)j * A.cs;
+        for (int i0 = t >> 7; i0 < nb; i0 += 32) {
+            T v[16];
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const int i = i0 + 2 * u;
+                v[u] = L[prow(i < N ? i : N - 1) + j];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const int i = i0 + 2 * u;
+                if (i < nb && j <= i) A.p[(int64_t)i * A.rs + jo] = v[u];
+            }
+        }
+    }
+}
+
+// W = L^{-1} in place in L, from the factor in L and the inverses W_jj of its
+// nblk diagonal 16 x 16 blocks parked in winv (128 x 128 row-major, at their
+// final places); with write_winv the whole W then goes to winv (zero above
+// the diagonal).  All 256 threads; ends with a barrier.
+template <typename T>
+__device__ __forceinline__ void leaf128_invert(Leaf128Smem<T>& sm, int nblk, T* winv, bool write_winv)
+{
+    T* L = sm.L;
+    T(&Wd)[D][DP] = sm.Wd;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    typedef typename M16<T>::acc acc_t;
+    // --------------------------------------------------------------- inverse
+    // Step kb (right to left): T = W_RR L_Rj, then W_Rj = -T W_jj.  T is
+    // formed transposed (operands swapped), which leaves each lane holding
+    // T(lane % 16, kappa_q) with kappa_q the accumulator row index of
+    // register q: exactly the A operand of the second product when its B
+    // operand is read at the same kappa_q, so T never goes through LDS.  The
+    // parked W_jj is fetched one step ahead (one element per thread).  Row
+    // blocks per wave: {w, 6 - w} for w < 3, {3} for wave 3 (at most seven).
+    T wnext = nblk > 0 ? winv[((nblk - 1) * D + t / 16) * N + (nblk - 1) * D + t % 16] : T(0);
+    for (int kb = nblk - 1; kb >= 0; kb--) {
+        const int o = kb * D;
+        __syncthreads();  // the previous step is done with Wd and with L
+        Wd[t / 16][t % 16] = wnext;
+        if (kb > 0) wnext = winv[(o - D + t / 16) * N + o - D + t % 16];
+        const int r0 = o + D, nrb = (N - r0) / 16;
+        const int rbs[2] = {w, w < 3 ? 6 - w : 7};
+        // W_RR(i, k) = 0 for k past row i's block, so row block rb needs
+        // k < 16 (rb + 1).  The two row blocks share the L_Rj operand, and
+        // each sum is split over even and odd k steps: four independent
+        // accumulation chains instead of one or two long ones.
+        const int ke0 = rbs[0] < nrb ? (rbs[0] + 1) * 16 : 0, ke1 = rbs[1] < nrb ? (rbs[1] + 1) * 16 : 0;
+        const T* Wr0 = L + prow(r0 + rbs[0] * 16 + r) + r0;  // W_RR, row r of each block
+        const T* Wr1 = L + prow(r0 + rbs[1] * 16 + r) + r0;
+        acc_t t00 = acc_t{0, 0, 0, 0}, t01 = t00, t10 = t00, t11 = t00;
+        const int kboth = ke0 < ke1 ? ke0 : ke1;
+        int kk = 0;
+#pragma unroll 2
+        for (; kk < kboth; kk += 8) {
+            const T l0 = L[prow(r0 + kk + g) + o + r], l1 = L[prow(r0 + kk + 4 + g) + o + r];
+            t00 = M16<T>::op(l0, Wr0[kk + g], t00);
+            t10 = M16<T>::op(l0, Wr1[kk + g], t10);
+            t01 = M16<T>::op(l1, Wr0[kk + 4 + g], t01);
+            t11 = M16<T>::op(l1, Wr1[kk + 4 + g], t11);
+        }
+        for (int k2 = kk; k2 < ke0; k2 += 8) {
+            t00 = M16<T>::op(L[prow(r0 + k2 + g) + o + r], Wr0[k2 + g], t00);
+            t01 = M16<T>::op(L[prow(r0 + k2 + 4 + g) + o + r], Wr0[k2 + 4 + g], t01);
+        }
+#pragma unroll 2
+        for (int k2 = kk; k2 < ke1; k2 += 8) {
+            t10 = M16<T>::op(L[prow(r0 + k2 + g) + o + r], Wr1[k2 + g], t10);
+            t11 = M16<T>::op(L[prow(r0 + k2 + 4 + g) + o + r], Wr1[k2 + 4 + g], t11);
+        }
+        const acc_t tacc[2] = {t00 + t01, t10 + t11};
+        __syncthreads();  // every wave has read L_Rj; W_jj is in Wd
+#pragma unroll
+        for (int q2 = 0; q2 < 2; q2++) {
+            const int rb = rbs[q2];
+            if (rb < nrb) {
+                acc_t y = acc_t{0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < 4; q++) y = M16<T>::op(tacc[q2][q], Wd[M16<T>::row(lane, q)][r], y);
+#pragma unroll
+                for (int q = 0; q < 4; q++) L[prow(r0 + rb * 16 + M16<T>::row(lane, q)) + o + r] = -y[q];
+            }
+        }
+        // the diagonal block becomes its inverse
+        if (w == 0 && lane < D) {
+#pragma unroll
+            for (int q = 0; q < D; q++)
+                if (q >= lane) L[prow(o + q) + o + lane] = Wd[q][lane];
+        }
+    }
+    __syncthreads();
+    RFP_LEAF_STAMP(31);
+    // W row-major into winv (zero above the diagonal, identity on padding),
+    // LDS reads batched ahead of the stores
+    for (int it0 = 0; write_winv && it0 < N * N / 256; it0 += 16) {
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int idx = t + (it0 + u) * 256, i = idx / N, j = idx % N;
+            v[u] = (j <= i) ? L[prow(i) + j] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; u++) winv[t + (it0 + u) * 256] = v[u];
+    }
+    __syncthreads();
+}
+
+// Factor the lower triangle of A (order nb <= 128) in place; when winv is not
+// null, write W = L^{-1} to it (128 x 128 row-major, zero above the diagonal,
+// identity on the padding).  Returns 0, or j + 1 for the first pivot j that
+// is not positive (then *info = info_base + j + 1 when info is not null and
+// A is left partly updated).  All 256 threads must call it; it ends with a
+// barrier.
+template <typename T>
+__device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int* info, int64_t info_base)
+{
+    T* L = sm.L;
+    T(&Wd)[D][DP] = sm.Wd;  // Wd[r][c] = (L_jj^{-1})(r, c)
+    int& fail = sm.fail;
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int r = lane & 15, g = lane >> 4;  // MFMA operand row and k offset of the lane
+    RFP_LEAF_STAMP(32);
+    if (t == 0) fail = 0;
+    leaf128_load<T>(L, A, nb);
     __syncthreads();
     RFP_LEAF_STAMP(0);
 
@@ -337,126 +482,65 @@ __device__ int potrf128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* winv, int
         if (t == 0 && info) *info = (int)(info_base + f);
         return f;
     }
-    // store the factor: its own lower triangle only, with stepped addresses
-    // (column-major: each thread one row, every other column; row-major: one
-    // row per wave and step, one column per lane)
-    // (LDS reads batched ahead of the stores, as for the load; reads past a
-    // packed row stay inside L and are not stored)
-    if (colmajor) {
-        const int i = t & (N - 1), j0 = t >> 7;
-        if (i < nb) {
-            T* a = A.p + i + (int64_t)j0 * A.cs;
-            const T* l = L + prow(i) + j0;
-            for (int u0 = 0; u0 < N / 2 && j0 + 2 * u0 <= i; u0 += 16) {
-                T v[16];
-#pragma unroll
-                for (int u = 0; u < 16; u++) v[u] = l[2 * (u0 + u)];
-#pragma unroll
-                for (int u = 0; u < 16; u++)
-                    if (j0 + 2 * (u0 + u) <= i) a[2 * (int64_t)(u0 + u) * A.cs] = v[u];
-            }
-        }
-    } else {
-        const int j = t & (N - 1);
-        const int64_t jo = (int64_t)j * A.cs;
-        for (int i0 = t >> 7; i0 < nb; i0 += 32) {
-            T v[16];
-#pragma unroll
-            for (int u = 0; u < 16; u++) {
-                const int i = i0 + 2 * u;
-                v[u] = L[prow(i < N ? i : N - 1) + j];
-            }
-#pragma unroll
-            for (int u = 0; u < 16; u++) {
-                const int i = i0 + 2 * u;
-                if (i < nb && j <= i) A.p[(int64_t)i * A.rs + jo] = v[u];
-            }
-        }
-    }
+    leaf128_store<T>(L, A, nb);
     RFP_LEAF_STAMP(30);
     if (!winv) {
         __syncthreads();
         return 0;
     }
 
-    // --------------------------------------------------------------- inverse
-    // Step kb (right to left): T = W_RR L_Rj, then W_Rj = -T W_jj.  T is
-    // formed transposed (operands swapped), which leaves each lane holding
-    // T(lane % 16, kappa_q) with kappa_q the accumulator row index of
-    // register q: exactly the A operand of the second product when its B
-    // operand is read at the same kappa_q, so T never goes through LDS.  The
-    // parked W_jj is fetched one step ahead (one element per thread).  Row
-    // blocks per wave: {w, 6 - w} for w < 3, {3} for wave 3 (at most seven).
-    T wnext = nblk > 0 ? winv[((nblk - 1) * D + t / 16) * N + (nblk - 1) * D + t % 16] : T(0);
-    for (int kb = nblk - 1; kb >= 0; kb--) {
-        const int o = kb * D;
-        __syncthreads();  // the previous step is done with Wd and with L
-        Wd[t / 16][t % 16] = wnext;
-        if (kb > 0) wnext = winv[(o - D + t / 16) * N + o - D + t % 16];
-        const int r0 = o + D, nrb = (N - r0) / 16;
-        const int rbs[2] = {w, w < 3 ? 6 - w : 7};
-        // W_RR(i, k) = 0 for k past row i's block, so row block rb needs
-        // k < 16 (rb + 1).  The two row blocks share the L_Rj operand, and
-        // each sum is split over even and odd k steps: four independent
-        // accumulation chains instead of one or two long ones.
-        const int ke0 = rbs[0] < nrb ? (rbs[0] + 1) * 16 : 0, ke1 = rbs[1] < nrb ? (rbs[1] + 1) * 16 : 0;
-        const T* Wr0 = L + prow(r0 + rbs[0] * 16 + r) + r0;  // W_RR, row r of each block
-        const T* Wr1 = L + prow(r0 + rbs[1] * 16 + r) + r0;
-        acc_t t00 = acc_t{0, 0, 0, 0}, t01 = t00, t10 = t00, t11 = t00;
-        const int kboth = ke0 < ke1 ? ke0 : ke1;
-        int kk = 0;
-#pragma unroll 2
-        for (; kk < kboth; kk += 8) {
-            const T l0 = L[prow(r0 + kk + g) + o + r], l1 = L[prow(r0 + kk + 4 + g) + o + r];
-            t00 = M16<T>::op(l0, Wr0[kk + g], t00);
-            t10 = M16<T>::op(l0, Wr1[kk + g], t10);
-            t01 = M16<T>::op(l1, Wr0[kk + 4 + g], t01);
-            t11 = M16<T>::op(l1, Wr1[kk + 4 + g], t11);
-        }
-        for (int k2 = kk; k2 < ke0; k2 += 8) {
-            t00 = M16<T>::op(L[prow(r0 + k2 + g) + o + r], Wr0[k2 + g], t00);
-            t01 = M16<T>::op(L[prow(r0 + k2 + 4 + g) + o + r], Wr0[k2 + 4 + g], t01);
-        }
-#pragma unroll 2
-        for (int k2 = kk; k2 < ke1; k2 += 8) {
-            t10 = M16<T>::op(L[prow(r0 + k2 + g) + o + r], Wr1[k2 + g], t10);
-            t11 = M16<T>::op(L[prow(r0 + k2 + 4 + g) + o + r], Wr1[k2 + 4 + g], t11);
-        }
-        const acc_t tacc[2] = {t00 + t01, t10 + t11};
-        __syncthreads();  // every wave has read L_Rj; W_jj is in Wd
-#pragma unroll
-        for (int q2 = 0; q2 < 2; q2++) {
-            const int rb = rbs[q2];
-            if (rb < nrb) {
-                acc_t y = acc_t{0, 0, 0, 0};
-#pragma unroll
-                for (int q = 0; q < 4; q++) y = M16<T>::op(tacc[q2][q], Wd[M16<T>::row(lane, q)][r], y);
-#pragma unroll
-                for (int q = 0; q < 4; q++) L[prow(r0 + rb * 16 + M16<T>::row(lane, q)) + o + r] = -y[q];
-            }
-        }
-        // the diagonal block becomes its inverse
-        if (w == 0 && lane < D) {
-#pragma unroll
-            for (int q = 0; q < D; q++)
-                if (q >= lane) L[prow(o + q) + o + lane] = Wd[q][lane];
-        }
-    }
-    __syncthreads();
-    RFP_LEAF_STAMP(31);
-    // W row-major into winv (zero above the diagonal, identity on padding),
-    // LDS reads batched ahead of the stores
-    for (int it0 = 0; it0 < N * N / 256; it0 += 16) {
-        T v[16];
-#pragma unroll
-        for (int u = 0; u < 16; u++) {
-            const int idx = t + (it0 + u) * 256, i = idx / N, j = idx % N;
-            v[u] = (j <= i) ? L[prow(i) + j] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < 16; u++) winv[t + (it0 + u) * 256] = v[u];
-    }
+    leaf128_invert<T>(sm, nblk, winv, true);
     RFP_LEAF_STAMP(33);
+    __syncthreads();
+    return 0;
+}
+
+// In-place inverse W = L^{-1} of the lower-triangular A (order nb <= 128):
+// the four wavefronts invert the diagonal 16 x 16 blocks (two each, lane c
+// forming column c by forward substitution) and park them in scratch (128 x
+// 128 row-major), then the block columns are formed from the right as in the
+// factorization leaf (W_Rj = -(W_RR L_Rj) W_jj on MFMA).  Returns 0, or i + 1
+// for the first exactly zero diagonal entry i (then *info = info_base + i + 1
+// when info is not null, and A is unchanged).  All 256 threads must call it;
+// it ends with a barrier.
+template <typename T>
+__device__ int trtri128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* scratch, int* info, int64_t info_base)
+{
+    T* L = sm.L;
+    int& fail = sm.fail;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (t == 0) fail = 1 << 30;
+    leaf128_load<T>(L, A, nb);
+    __syncthreads();
+    if (t < nb && L[prow(t) + t] == T(0)) atomicMin(&fail, t + 1);
+    __syncthreads();
+    if (fail < (1 << 30)) {
+        const int f = fail;
+        __syncthreads();
+        if (t == 0 && info) *info = (int)(info_base + f);
+        return f;
+    }
+    const int nblk = (nb + D - 1) / D;
+    for (int kb = w; kb < nblk; kb += 4) {
+        const int o = kb * D;
+        if (lane < D) {
+            const int c = lane;
+            T wv[D];
+#pragma unroll
+            for (int rr = 0; rr < D; rr++) {
+                const T* Lr = L + prow(o + rr) + o;
+                T sum = (rr == c) ? T(1) : T(0);
+#pragma unroll
+                for (int q = 0; q < rr; q++) sum -= Lr[q] * wv[q];
+                wv[rr] = (rr >= c) ? sum / Lr[rr] : T(0);
+            }
+#pragma unroll
+            for (int rr = 0; rr < D; rr++) scratch[(o + rr) * N + o + c] = wv[rr];
+        }
+    }
+    __syncthreads();  // the parked inverses are visible to the whole workgroup
+    leaf128_invert<T>(sm, nblk, scratch, false);
+    leaf128_store<T>(L, A, nb);
     __syncthreads();
     return 0;
 }

@@ -37,4 +37,30 @@ hipError_t potrf128_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info
 template hipError_t potrf128_leaf<double>(const Exec&, Mat<double>, int, double*, int64_t);
 template hipError_t potrf128_leaf<float>(const Exec&, Mat<float>, int, float*, int64_t);
 
+template <typename T>
+__global__ __launch_bounds__(256) void trtri128_kernel(Mat<T> A, int nb, T* scratch, int* info, int64_t info_base)
+{
+    if (info && *info) return;
+    // on the critical path of the inversion: first in issue on a shared compute unit
+    __builtin_amdgcn_s_setprio(3);
+    __shared__ Leaf128Smem<T> sm;
+    (void)trtri128_block<T>(sm, A, nb, scratch, info, info_base);
+}
+
+template <typename T>
+hipError_t trtri128_leaf(const Exec& ex, Mat<T> A, int nb, T* scratch, int64_t info_base)
+{
+    static char name[2][96];
+    const int ti = sizeof(T) == 8 ? 0 : 1;
+    if (!name[ti][0])
+        snprintf(name[ti], sizeof name[ti], "rfp::trtri128_kernel<%s>(rfp::Mat<%s>, int, %s*, int*, long)",
+                 ti ? "float" : "double", ti ? "float" : "double", ti ? "float" : "double");
+    ProfScope ps(ex, name[ti], (double)nb * nb * nb / 3.0, sizeof(T) * (double)nb * nb);
+    hipLaunchKernelGGL((trtri128_kernel<T>), dim3(1), dim3(256), 0, ex.stream, A, nb, scratch, ex.info, info_base);
+    return hipGetLastError();
+}
+
+template hipError_t trtri128_leaf<double>(const Exec&, Mat<double>, int, double*, int64_t);
+template hipError_t trtri128_leaf<float>(const Exec&, Mat<float>, int, float*, int64_t);
+
 }  // namespace rfp

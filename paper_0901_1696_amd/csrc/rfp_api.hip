@@ -181,6 +181,8 @@ struct Run {
     hipError_t err = hipSuccess;
     PlanRec* rec = nullptr;
     int nb = NB;  // leaf order of this call's recursion
+    bool tri128 = false;         // triangular inverses of blocks up to NB2 rows by the 128-row leaf
+    T* tri_scratch = nullptr;    // its scratch: NB2 x NB2 per stream (index `on`)
     void chk(hipError_t e)
     {
         if (e != hipSuccess && err == hipSuccess) err = e;
@@ -483,8 +485,11 @@ struct Run {
     void trtri_rec(int64_t n, Mat<T> A, int64_t goff)
     {
         if (n <= 0) return;
-        if (n <= nb) {
+        // blocks up to 128 rows: one workgroup's MFMA leaf (a scratch block
+        // per stream), else the one-wavefront 64-row leaf
+        if (n <= nb || (tri128 && n <= NB2)) {
             if (rec) leaf(RFP_PLAN_TRTRI_LEAF, A, n, nullptr, goff);
+            else if (tri128) chk(trtri128_leaf<T>(cur(), A, (int)n, tri_scratch + (int64_t)on * NB2 * NB2, goff));
             else chk(trtri_leaf<T>(cur(), A, (int)n, goff));
             return;
         }
@@ -871,10 +876,13 @@ static int pftri_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
         tmp = plan_base<T>(RFP_PLAN_BUF_WORK);
     } else {
         if (n == 0) return set_int(s, info, 0) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
-        if (prepare(h, sizeof(T) * (size_t)b.m1 * (size_t)b.m1) != hipSuccess) return RFP_ERR_RUNTIME;
+        const size_t tri = (size_t)3 * NB2 * NB2;  // the 128-row inverse leaf's scratch, one block per stream
+        if (prepare(h, sizeof(T) * ((size_t)b.m1 * (size_t)b.m1 + tri)) != hipSuccess) return RFP_ERR_RUNTIME;
         r = make_run<T>(h, s, info);
         tmp = (T*)h->inv;
+        r.tri_scratch = tmp + (size_t)b.m1 * (size_t)b.m1;
     }
+    r.tri128 = true;
     RfpView<T> v = rfp_view(b, arf);
     Mat<T> Tmp{tmp, 1, b.m1};
     r.setinfo(info);
@@ -1182,13 +1190,16 @@ static int tftri_impl(rfp_context* h, char transr, char uplo, char diag, int64_t
     DeviceGuard g(h->device);
     if (n == 0) return set_int(s, info, 0) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
     const bool unit = upc(diag) == 'U';
-    if (prepare(h, unit ? sizeof(T) * (size_t)n : 0) != hipSuccess) return RFP_ERR_RUNTIME;
+    const size_t dn = unit ? (size_t)n : 0, tri = (size_t)3 * NB2 * NB2;
+    if (prepare(h, sizeof(T) * (dn + tri)) != hipSuccess) return RFP_ERR_RUNTIME;
     RfpBlocks b;
     rfp_blocks(transr, uplo, n, &b);
     RfpView<T> v = rfp_view(b, arf);
     Run<T> r = make_run<T>(h, s, info);
     r.setinfo(info);
     T* dbuf = (T*)h->inv;
+    r.tri128 = true;
+    r.tri_scratch = dbuf + dn;
     if (unit) r.chk(unit_diag<T>(s, v, dbuf, false));
     r.trtri_rec(b.m1, v.t1, 0);
     r.trmm_rl(b.m2, b.m1, v.s, v.t1, T(-1));

@@ -239,6 +239,12 @@ hipError_t lauum_leaf(const Exec& ex, Mat<T> A, int nb);
 // written to winv; INFO as for potrf_leaf.
 template <typename T>
 hipError_t potrf128_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info_base);
+// In-place inverse of a lower-triangular diagonal block of order nb <= 128 by
+// one workgroup (MFMA block columns); scratch: 128 x 128 elements of device
+// memory owned by the caller's stream.  *ex.info = info_base + i + 1 for the
+// first exactly zero diagonal entry i.
+template <typename T>
+hipError_t trtri128_leaf(const Exec& ex, Mat<T> A, int nb, T* scratch, int64_t info_base);
 
 // Fused blocked triangular solve with the whole factor of an RFP matrix
 // (Section 4): forward L Y = B, else L^T X = B, over the views L11 (order m1),

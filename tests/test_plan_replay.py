@@ -89,9 +89,9 @@ def test_plan_argument_errors():
 
 
 def test_plan_leaf_counts():
-    """The factorization recursion reaches diagonal blocks of at most 128 rows
-    (the solve and inversion ones 64), aligned from the start of T1 and T2,
-    one leaf per block."""
+    """The factorization recursion reaches diagonal blocks of at most 128 rows,
+    aligned from the start of T1 and T2, one leaf per block; the inversion's
+    recursion stops at blocks of at most 128 rows that tile both triangles."""
     for n in [100, 1001, 4097]:
         for t, u in LAYOUTS:
             m1 = (n + 1) // 2 if u == "L" else n // 2
@@ -102,7 +102,9 @@ def test_plan_leaf_counts():
             assert all(o.m <= 128 for o in leaves)
             ops = rfp.rfp_plan("I", t, u, n)
             leaves = [o for o in ops if o.kind == rfp.PLAN_TRTRI_LEAF]
-            assert len(leaves) == -(-m1 // 64) + -(-m2 // 64)
+            assert all(o.m <= 128 for o in leaves)
+            assert sum(o.m for o in leaves) == m1 + m2
+            assert len(leaves) >= -(-m1 // 128) + -(-m2 // 128)
 
 
 def test_pftrs_plan_is_two_fused_solves():
