@@ -545,4 +545,60 @@ __device__ int trtri128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb, T* scratch, 
     return 0;
 }
 
+// In place, the lower triangle of W^T W for the lower-triangular A = W of
+// order nb <= 128 (the LAUUM step of the inversion): the 36 output blocks
+// C_ij = sum_{k >= i} W_ki^T W_kj (i >= j, 16 x 16 each) are shared out over
+// the four wavefronts and formed on MFMA from W in LDS (rows past nb are the
+// identity and add nothing to the stored part), then written over W.  All
+// 256 threads must call it; it ends with a barrier.
+template <typename T>
+__device__ void lauum128_block(Leaf128Smem<T>& sm, Mat<T> A, int nb)
+{
+    T* L = sm.L;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    typedef typename M16<T>::acc acc_t;
+    leaf128_load<T>(L, A, nb);
+    __syncthreads();
+    const int nblk = (nb + D - 1) / D, nout = nblk * (nblk + 1) / 2;
+    constexpr int PER = (8 * 9 / 2 + 3) / 4;  // output blocks per wavefront at most
+    acc_t c[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        c[q] = acc_t{0, 0, 0, 0};
+        const int b = w + 4 * q;
+        if (b < nout) {
+            int bi = 0;
+            while ((bi + 1) * (bi + 2) / 2 <= b) bi++;
+            const int bj = b - bi * (bi + 1) / 2;
+            // A operand: W_ki^T (row r, k index); B operand: W_kj (k index, column r)
+            for (int bk = bi; bk < nblk; bk++) {
+#pragma unroll
+                for (int kk = 0; kk < D; kk += 4) {
+                    const T* row = L + prow(bk * D + kk + g);
+                    c[q] = M16<T>::op(row[bi * D + r], row[bj * D + r], c[q]);
+                }
+            }
+        }
+    }
+    __syncthreads();  // every wavefront is done reading W
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int b = w + 4 * q;
+        if (b < nout) {
+            int bi = 0;
+            while ((bi + 1) * (bi + 2) / 2 <= b) bi++;
+            const int bj = b - bi * (bi + 1) / 2;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int i = bi * D + M16<T>::row(lane, e), j = bj * D + r;
+                if (i >= j) L[prow(i) + j] = c[q][e];
+            }
+        }
+    }
+    __syncthreads();
+    leaf128_store<T>(L, A, nb);
+    __syncthreads();
+}
+
 }  // namespace rfp

@@ -63,4 +63,29 @@ hipError_t trtri128_leaf(const Exec& ex, Mat<T> A, int nb, T* scratch, int64_t i
 template hipError_t trtri128_leaf<double>(const Exec&, Mat<double>, int, double*, int64_t);
 template hipError_t trtri128_leaf<float>(const Exec&, Mat<float>, int, float*, int64_t);
 
+template <typename T>
+__global__ __launch_bounds__(256) void lauum128_kernel(Mat<T> A, int nb, const int* info)
+{
+    if (info && *info) return;
+    __builtin_amdgcn_s_setprio(3);
+    __shared__ Leaf128Smem<T> sm;
+    lauum128_block<T>(sm, A, nb);
+}
+
+template <typename T>
+hipError_t lauum128_leaf(const Exec& ex, Mat<T> A, int nb)
+{
+    static char name[2][96];
+    const int ti = sizeof(T) == 8 ? 0 : 1;
+    if (!name[ti][0])
+        snprintf(name[ti], sizeof name[ti], "rfp::lauum128_kernel<%s>(rfp::Mat<%s>, int, int const*)",
+                 ti ? "float" : "double", ti ? "float" : "double");
+    ProfScope ps(ex, name[ti], (double)nb * nb * nb / 3.0, sizeof(T) * (double)nb * nb);
+    hipLaunchKernelGGL((lauum128_kernel<T>), dim3(1), dim3(256), 0, ex.stream, A, nb, (const int*)ex.info);
+    return hipGetLastError();
+}
+
+template hipError_t lauum128_leaf<double>(const Exec&, Mat<double>, int);
+template hipError_t lauum128_leaf<float>(const Exec&, Mat<float>, int);
+
 }  // namespace rfp

@@ -503,8 +503,9 @@ struct Run {
     void lauum_rec(int64_t n, Mat<T> W)
     {
         if (n <= 0) return;
-        if (n <= nb) {
+        if (n <= nb || (tri128 && n <= NB2)) {
             if (rec) leaf(RFP_PLAN_LAUUM_LEAF, W, n, nullptr, 0);
+            else if (tri128) chk(lauum128_leaf<T>(cur(), W, (int)n));
             else chk(lauum_leaf<T>(cur(), W, (int)n));
             return;
         }

@@ -245,6 +245,10 @@ hipError_t potrf128_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info
 // first exactly zero diagonal entry i.
 template <typename T>
 hipError_t trtri128_leaf(const Exec& ex, Mat<T> A, int nb, T* scratch, int64_t info_base);
+// In place, the lower triangle of W^T W for a lower-triangular diagonal block
+// W of order nb <= 128, by one workgroup on MFMA.
+template <typename T>
+hipError_t lauum128_leaf(const Exec& ex, Mat<T> A, int nb);
 
 // Fused blocked triangular solve with the whole factor of an RFP matrix
 // (Section 4): forward L Y = B, else L^T X = B, over the views L11 (order m1),
