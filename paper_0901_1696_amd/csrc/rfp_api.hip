@@ -442,15 +442,19 @@ struct Run {
     }
 
     // ------------------------------------------------------------ inversion
+    // Leaf order of the inversion recursion: 128 rows when the 128-row
+    // inverse and LAUUM leaves run, so that the in-place base products of the
+    // triangular multiplies (one tile across the aliased side) are 128 wide too.
+    int64_t tb() const { return tri128 ? NB2 : nb; }
     // B (m x n) <- alpha B W, W lower of order n
     void trmm_rl(int64_t m, int64_t n, Mat<T> B, Mat<const T> W, T alpha)
     {
         if (m <= 0 || n <= 0) return;
-        if (n <= nb) {
+        if (n <= tb()) {
             mm(m, n, n, alpha, B, TRI_NONE, W.tr(), TRI_UPPER, T(0), B, false, true);
             return;
         }
-        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
+        const int64_t n1 = rec_split(n, tb()), n2 = n - n1;
         trmm_rl(m, n1, B, W, alpha);
         mm(m, n1, n2, alpha, B.sub(0, n1), TRI_NONE, W.sub(n1, 0).tr(), TRI_NONE, T(1), B);
         trmm_rl(m, n2, B.sub(0, n1), W.sub(n1, n1), alpha);
@@ -459,11 +463,11 @@ struct Run {
     void trmm_ll(int64_t m, int64_t n, Mat<const T> W, Mat<T> B)
     {
         if (m <= 0 || n <= 0) return;
-        if (m <= nb) {
+        if (m <= tb()) {
             mm(m, n, m, T(1), W, TRI_LOWER, B.tr(), TRI_NONE, T(0), B, false, true);
             return;
         }
-        const int64_t m1 = rec_split(m, nb), m2 = m - m1;
+        const int64_t m1 = rec_split(m, tb()), m2 = m - m1;
         trmm_ll(m2, n, W.sub(m1, m1), B.sub(m1, 0));
         mm(m2, n, m1, T(1), W.sub(m1, 0), TRI_NONE, B.tr(), TRI_NONE, T(1), B.sub(m1, 0));
         trmm_ll(m1, n, W, B);
@@ -472,11 +476,11 @@ struct Run {
     void trmm_llt(int64_t m, int64_t n, Mat<const T> W, Mat<T> B)
     {
         if (m <= 0 || n <= 0) return;
-        if (m <= nb) {
+        if (m <= tb()) {
             mm(m, n, m, T(1), W.tr(), TRI_UPPER, B.tr(), TRI_NONE, T(0), B, false, true);
             return;
         }
-        const int64_t m1 = rec_split(m, nb), m2 = m - m1;
+        const int64_t m1 = rec_split(m, tb()), m2 = m - m1;
         trmm_llt(m1, n, W, B);
         mm(m1, n, m2, T(1), W.sub(m1, 0).tr(), TRI_NONE, B.sub(m1, 0).tr(), TRI_NONE, T(1), B);
         trmm_llt(m2, n, W.sub(m1, m1), B.sub(m1, 0));
@@ -485,15 +489,15 @@ struct Run {
     void trtri_rec(int64_t n, Mat<T> A, int64_t goff)
     {
         if (n <= 0) return;
-        // blocks up to 128 rows: one workgroup's MFMA leaf (a scratch block
-        // per stream), else the one-wavefront 64-row leaf
-        if (n <= nb || (tri128 && n <= NB2)) {
+        // 128-row blocks: one workgroup's MFMA leaf (a scratch block per
+        // stream); 64-row blocks: the one-wavefront leaf
+        if (n <= tb()) {
             if (rec) leaf(RFP_PLAN_TRTRI_LEAF, A, n, nullptr, goff);
             else if (tri128) chk(trtri128_leaf<T>(cur(), A, (int)n, tri_scratch + (int64_t)on * NB2 * NB2, goff));
             else chk(trtri_leaf<T>(cur(), A, (int)n, goff));
             return;
         }
-        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
+        const int64_t n1 = rec_split(n, tb()), n2 = n - n1;
         trtri_rec(n1, A, goff);
         trmm_rl(n2, n1, A.sub(n1, 0), A, T(-1));
         trtri_rec(n2, A.sub(n1, n1), goff + n1);
@@ -503,13 +507,13 @@ struct Run {
     void lauum_rec(int64_t n, Mat<T> W)
     {
         if (n <= 0) return;
-        if (n <= nb || (tri128 && n <= NB2)) {
+        if (n <= tb()) {
             if (rec) leaf(RFP_PLAN_LAUUM_LEAF, W, n, nullptr, 0);
             else if (tri128) chk(lauum128_leaf<T>(cur(), W, (int)n));
             else chk(lauum_leaf<T>(cur(), W, (int)n));
             return;
         }
-        const int64_t n1 = rec_split(n, nb), n2 = n - n1;
+        const int64_t n1 = rec_split(n, tb()), n2 = n - n1;
         lauum_rec(n1, W);
         mm(n1, n1, n2, T(1), W.sub(n1, 0).tr(), TRI_NONE, W.sub(n1, 0).tr(), TRI_NONE, T(1), W, true);
         trmm_llt(n2, n1, W.sub(n1, n1), W.sub(n1, 0));
