@@ -101,6 +101,18 @@ struct GemmParams {
     int64_t ldc;
     T alpha, beta;
     int triA, triB;
+    // With one triangular operand the k-range of a tile splits into slabs
+    // that cross the operand's diagonal next to the tile and slabs it keeps
+    // whole: part 0 runs all of them, part 1 only the whole ones (no masks),
+    // part 2 only the crossing ones (masked).
+    int part;
+    int band;  // the tile's extent along the triangular operand's rows (parts 1, 2; work accounting)
+    // Tile order (not with tri_enum): bit 0 deals GROUP tile columns at a
+    // time instead of GROUP tile rows; bits 1 and 2 reverse the tile rows and
+    // columns.  With one triangular operand the tiles' k-ranges vary along
+    // one direction of the grid; each XCD then gets a contiguous range along
+    // the other one (an even share of the work) and the longest tiles first.
+    int order;
     int c_lower;   // write only C(i, j) with i >= j
     int tri_enum;  // square lower output: the grid enumerates lower tiles only
     int tiles_m, tiles_n;
@@ -173,7 +185,7 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
             while (r * (r + 1) / 2 > bid) r--;
             ti = r;
             tj = bid - r * (r + 1) / 2;
-        } else {
+        } else if (!(p.order & 1)) {
             const int per_group = GROUP * p.tiles_n;
             const int g = bid / per_group;
             const int first = g * GROUP;
@@ -181,7 +193,18 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
             const int in = bid - g * per_group;
             ti = first + in % rows;
             tj = in / rows;
+        } else {
+            // GROUP tile columns at a time
+            const int per_group = GROUP * p.tiles_m;
+            const int g = bid / per_group;
+            const int first = g * GROUP;
+            const int cols = (p.tiles_n - first) < GROUP ? (p.tiles_n - first) : GROUP;
+            const int in = bid - g * per_group;
+            tj = first + in % cols;
+            ti = in / cols;
         }
+        if (p.order & 2) ti = p.tiles_m - 1 - ti;
+        if (p.order & 4) tj = p.tiles_n - 1 - tj;
     }
     const int64_t i0 = ti * BM, j0 = tj * BN;
     const int64_t m = p.m, n = p.n;
@@ -190,10 +213,27 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
     int64_t kb = (int64_t)blockIdx.z * p.kchunk;
     int64_t ke = kb + p.kchunk < p.k ? kb + p.kchunk : p.k;
     // skip k slabs that a triangular operand zeroes for this whole tile
-    if (p.triA == TRI_LOWER || p.triA == TRI_SLOWER) ke = ke < i0 + BM ? ke : i0 + BM;
-    if (p.triA == TRI_UPPER || p.triA == TRI_SUPPER) kb = kb > i0 ? kb : i0;
-    if (p.triB == TRI_LOWER || p.triB == TRI_SLOWER) ke = ke < j0 + BN ? ke : j0 + BN;
-    if (p.triB == TRI_UPPER || p.triB == TRI_SUPPER) kb = kb > j0 ? kb : j0;
+    if (p.part == 0) {
+        if (p.triA == TRI_LOWER || p.triA == TRI_SLOWER) ke = ke < i0 + BM ? ke : i0 + BM;
+        if (p.triA == TRI_UPPER || p.triA == TRI_SUPPER) kb = kb > i0 ? kb : i0;
+        if (p.triB == TRI_LOWER || p.triB == TRI_SLOWER) ke = ke < j0 + BN ? ke : j0 + BN;
+        if (p.triB == TRI_UPPER || p.triB == TRI_SUPPER) kb = kb > j0 ? kb : j0;
+    } else {
+        // the crossing slabs [lo, hi): the tile's own rows of the operand;
+        // below them a lower operand keeps every entry, above them an upper one
+        const bool onA = p.triA != TRI_NONE;
+        const int tri = onA ? p.triA : p.triB;
+        const int64_t lo = onA ? i0 : j0, hi = lo + (onA ? BM : BN);
+        const bool lower = tri == TRI_LOWER || tri == TRI_SLOWER;
+        if (p.part == 2) {
+            kb = kb > lo ? kb : lo;
+            ke = ke < hi ? ke : hi;
+        } else if (lower) {
+            ke = ke < lo ? ke : lo;
+        } else {
+            kb = kb > hi ? kb : hi;
+        }
+    }
 
     typedef typename Lds<T, LP>::type LT;
     constexpr int KPL = Lds<T, LP>::pitch;
@@ -215,7 +255,7 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
 
     const Band ba = band_of(p.triA), bb = band_of(p.triB);
     const int64_t kmax = p.k > 0 ? p.k - 1 : 0;
-    const bool a_nomask = p.triA == TRI_NONE, b_nomask = p.triB == TRI_NONE;
+    const bool a_nomask = p.triA == TRI_NONE || p.part == 1, b_nomask = p.triB == TRI_NONE || p.part == 1;
     // Rows past the edge of a ragged tile are clamped to the last row of the
     // operand (a valid address; the value is zeroed when the slab is stored).
     // A column-major operand keeps one pointer per thread (its clamped row);
@@ -749,14 +789,43 @@ static double out_cells(const GemmParams<T>& p)
     return p.c_lower ? (double)p.m * p.n - 0.5 * (double)p.n * (double)(p.n - 1) : (double)p.m * (double)p.n;
 }
 
+// Kept (row, kk) pairs of a triangular operand inside the slabs that cross
+// its diagonal next to each row's tile (tiles of `band` rows).
+static double band_pairs(int tri, int64_t rows, int64_t k, int band)
+{
+    double s = 0;
+    for (int64_t i = 0; i < rows; i++) {
+        const int64_t t0 = i / band * band, t1 = t0 + band < k ? t0 + band : k;
+        int64_t lo = t0, hi = t1;  // kept kk in [lo, hi)
+        switch (tri) {
+            case TRI_LOWER: hi = hi < i + 1 ? hi : i + 1; break;
+            case TRI_SLOWER: hi = hi < i ? hi : i; break;
+            case TRI_UPPER: lo = lo > i ? lo : i; break;
+            case TRI_SUPPER: lo = lo > i + 1 ? lo : i + 1; break;
+            default: break;
+        }
+        if (hi > lo) s += (double)(hi - lo);
+    }
+    return s;
+}
+
 template <typename T>
 static double gemm_flops(const GemmParams<T>& p)
 {
     double cells = out_cells(p);
     double kfrac = 1.0;
     if (p.k > 0) {
-        if (p.triA) kfrac *= tri_pairs(p.triA, p.m, p.k) / ((double)p.m * p.k);
-        if (p.triB) kfrac *= tri_pairs(p.triB, p.n, p.k) / ((double)p.n * p.k);
+        if (p.part != 0) {
+            const bool onA = p.triA != TRI_NONE;
+            const int tri = onA ? p.triA : p.triB;
+            const int64_t rows = onA ? p.m : p.n;
+            const double band = band_pairs(tri, rows, p.k, p.band);
+            const double kept = p.part == 2 ? band : tri_pairs(tri, rows, p.k) - band;
+            kfrac = kept / ((double)rows * p.k);
+        } else {
+            if (p.triA) kfrac *= tri_pairs(p.triA, p.m, p.k) / ((double)p.m * p.k);
+            if (p.triB) kfrac *= tri_pairs(p.triB, p.n, p.k) / ((double)p.n * p.k);
+        }
     }
     return 2.0 * cells * (double)p.k * kfrac;
 }
@@ -943,6 +1012,10 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
         tile = pick_tile(m, n, c_lower, inplace, &tm, &tn, lp != 0);
     }
     p.tri_enum = (c_lower && m == n) ? 1 : 0;
+    if (!p.tri_enum && (triA != TRI_NONE) != (triB != TRI_NONE)) {
+        const bool lowA = triA == TRI_LOWER || triA == TRI_SLOWER, lowB = triB == TRI_LOWER || triB == TRI_SLOWER;
+        p.order = triA != TRI_NONE ? (1 | (lowA ? 2 : 0)) : (lowB ? 4 : 0);
+    }
     const int64_t ntiles = p.tri_enum ? tm * (tm + 1) / 2 : tm * tn;
     p.tiles_m = (int)tm;
     p.tiles_n = (int)tn;
@@ -978,9 +1051,36 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
 #ifndef RFP_GEMM_DIRECT
 #define RFP_GEMM_DIRECT 1
 #endif
-    const bool dma = RFP_GEMM_DIRECT && sizeof(T) == 8 && lp == 0 && !inplace && triA == TRI_NONE &&
-                     triB == TRI_NONE && nsplit == 1 && p.k % BK == 0 && p.lda < (1 << 22) && p.ldb < (1 << 22);
+    const bool direct_ok = RFP_GEMM_DIRECT && sizeof(T) == 8 && lp == 0 && !inplace && nsplit == 1 &&
+                           p.k % BK == 0 && p.lda < (1 << 22) && p.ldb < (1 << 22);
+    const bool dma = direct_ok && triA == TRI_NONE && triB == TRI_NONE;
     const int sel = (amc ? 4 : 0) | (bnc ? 2 : 0) | (cmc ? 1 : 0);
+    // One triangular operand and a long k-range: the slabs the operand keeps
+    // whole go through the direct-staging kernel without masks, then the
+    // slabs crossing its diagonal (one tile's worth of k) are added by the
+    // masked kernel.
+    if (direct_ok && (triA != TRI_NONE) != (triB != TRI_NONE) && p.k > 2 * TILE_BM[0]) {
+        GemmParams<T> q = p;
+        q.part = 1;
+        q.band = triA != TRI_NONE ? TILE_BM[tile] : TILE_BN[tile];
+        auto go = [&](const GemmParams<T>& g, bool direct) {
+            switch (sel) {
+                case 0: launch<T, false, false, false>(g, grid, tile, ex, lp, direct); break;
+                case 1: launch<T, false, false, true>(g, grid, tile, ex, lp, direct); break;
+                case 2: launch<T, false, true, false>(g, grid, tile, ex, lp, direct); break;
+                case 3: launch<T, false, true, true>(g, grid, tile, ex, lp, direct); break;
+                case 4: launch<T, true, false, false>(g, grid, tile, ex, lp, direct); break;
+                case 5: launch<T, true, false, true>(g, grid, tile, ex, lp, direct); break;
+                case 6: launch<T, true, true, false>(g, grid, tile, ex, lp, direct); break;
+                default: launch<T, true, true, true>(g, grid, tile, ex, lp, direct); break;
+            }
+        };
+        go(q, true);
+        q.part = 2;
+        q.beta = T(1);
+        go(q, false);
+        return hipGetLastError();
+    }
     switch (sel) {
         case 0: launch<T, false, false, false>(p, grid, tile, ex, lp, dma); break;
         case 1: launch<T, false, false, true>(p, grid, tile, ex, lp, dma); break;
