@@ -499,6 +499,7 @@ int rfp_profile_read(rfp_handle_t h, rfp_profile_entry* out, int cap, int* count
  *     consecutive NB x NB row-major blocks (as RFP_PLAN_TRTRI_LEAVES writes).
  *   RFP_PLAN_AXPY: C(m x n) += alpha * A (only C's lower triangle when
  *     c_lower).
+ *   RFP_PLAN_COPY: C(m x n) = A (A and C do not overlap).
  *   RFP_PLAN_RECORD / RFP_PLAN_WAIT: event m is recorded on / waited for by
  *     stream `stream` (0: the caller's stream, 1 and 2: the handle's two
  *     auxiliary streams).  Every other record carries the stream it runs on;
@@ -516,7 +517,8 @@ enum {
     RFP_PLAN_RECORD = 6,
     RFP_PLAN_WAIT = 7,
     RFP_PLAN_BLOCK_SOLVE = 8,
-    RFP_PLAN_AXPY = 9
+    RFP_PLAN_AXPY = 9,
+    RFP_PLAN_COPY = 10
 };
 enum { RFP_PLAN_BUF_ARF = 0, RFP_PLAN_BUF_B = 1, RFP_PLAN_BUF_WORK = 2, RFP_PLAN_BUF_INFO = 3 };
 typedef struct {

@@ -95,7 +95,7 @@ class ProfileEntry(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 PLAN_GEMM, PLAN_POTRF_LEAF, PLAN_TRTRI_LEAF, PLAN_TRTRI_LEAVES, PLAN_LAUUM_LEAF = 1, 2, 3, 4, 5
-PLAN_RECORD, PLAN_WAIT, PLAN_BLOCK_SOLVE, PLAN_AXPY = 6, 7, 8, 9
+PLAN_RECORD, PLAN_WAIT, PLAN_BLOCK_SOLVE, PLAN_AXPY, PLAN_COPY = 6, 7, 8, 9, 10
 PLAN_BUF_ARF, PLAN_BUF_B, PLAN_BUF_WORK = 0, 1, 2
 
 

@@ -183,6 +183,29 @@ struct Run {
     int nb = NB;  // leaf order of this call's recursion
     bool tri128 = false;         // triangular inverses of blocks up to NB2 rows by the 128-row leaf
     T* tri_scratch = nullptr;    // its scratch: NB2 x NB2 per stream (index `on`)
+    // Scratch of the out-of-place triangular multiplies, one per stream: an
+    // r x c product fits when r <= rows and c <= cols (column-major with
+    // leading dimension ld), or, with ld == 0, when r * c <= elems (leading
+    // dimension r).  Without one (or when it is too small) the multiplies
+    // recurse in place.
+    struct Scratch {
+        T* p = nullptr;
+        int64_t ld = 0, rows = 0, cols = 0, elems = 0;
+    };
+    Scratch tsc[3];
+    bool scratch_for(int64_t r, int64_t c, Mat<T>* X) const
+    {
+        const Scratch& q = tsc[on];
+        if (!q.p || r <= 0 || c <= 0) return false;
+        if (q.ld) {
+            if (r > q.rows || c > q.cols) return false;
+            *X = Mat<T>{q.p, 1, q.ld};
+            return true;
+        }
+        if (r * c > q.elems) return false;
+        *X = Mat<T>{q.p, 1, r};
+        return true;
+    }
     void chk(hipError_t e)
     {
         if (e != hipSuccess && err == hipSuccess) err = e;
@@ -442,6 +465,23 @@ struct Run {
     }
 
     // ------------------------------------------------------------ inversion
+    // C (m x n) <- A
+    void copy(int64_t m, int64_t n, Mat<const T> A, Mat<T> C)
+    {
+        if (m <= 0 || n <= 0) return;
+        if (rec) {
+            if (rfp_plan_op* o = next(RFP_PLAN_COPY)) {
+                o->stream = on;
+                o->m = m;
+                o->n = n;
+                plan_view(A.p, A.rs, A.cs, sizeof(T), o->a);
+                plan_view(C.p, C.rs, C.cs, sizeof(T), o->c);
+            }
+            return;
+        }
+        chk(copy2d<T, T>(cur().stream, C, A, m, n, false));
+    }
+
     // Leaf order of the inversion recursion: 128 rows when the 128-row
     // inverse and LAUUM leaves run, so that the in-place base products of the
     // triangular multiplies (one tile across the aliased side) are 128 wide too.
@@ -452,6 +492,12 @@ struct Run {
         if (m <= 0 || n <= 0) return;
         if (n <= tb()) {
             mm(m, n, n, alpha, B, TRI_NONE, W.tr(), TRI_UPPER, T(0), B, false, true);
+            return;
+        }
+        Mat<T> X;
+        if (scratch_for(m, n, &X)) {  // one product into the scratch, copied back
+            mm(m, n, n, alpha, B, TRI_NONE, W.tr(), TRI_UPPER, T(0), X);
+            copy(m, n, X, B);
             return;
         }
         const int64_t n1 = rec_split(n, tb()), n2 = n - n1;
@@ -467,6 +513,12 @@ struct Run {
             mm(m, n, m, T(1), W, TRI_LOWER, B.tr(), TRI_NONE, T(0), B, false, true);
             return;
         }
+        Mat<T> X;
+        if (scratch_for(m, n, &X)) {
+            mm(m, n, m, T(1), W, TRI_LOWER, B.tr(), TRI_NONE, T(0), X);
+            copy(m, n, X, B);
+            return;
+        }
         const int64_t m1 = rec_split(m, tb()), m2 = m - m1;
         trmm_ll(m2, n, W.sub(m1, m1), B.sub(m1, 0));
         mm(m2, n, m1, T(1), W.sub(m1, 0), TRI_NONE, B.tr(), TRI_NONE, T(1), B.sub(m1, 0));
@@ -480,10 +532,32 @@ struct Run {
             mm(m, n, m, T(1), W.tr(), TRI_UPPER, B.tr(), TRI_NONE, T(0), B, false, true);
             return;
         }
+        Mat<T> X;
+        if (scratch_for(m, n, &X)) {
+            mm(m, n, m, T(1), W.tr(), TRI_UPPER, B.tr(), TRI_NONE, T(0), X);
+            copy(m, n, X, B);
+            return;
+        }
         const int64_t m1 = rec_split(m, tb()), m2 = m - m1;
         trmm_llt(m1, n, W, B);
         mm(m1, n, m2, T(1), W.sub(m1, 0).tr(), TRI_NONE, B.sub(m1, 0).tr(), TRI_NONE, T(1), B);
         trmm_llt(m2, n, W.sub(m1, m1), B.sub(m1, 0));
+    }
+    // B (m x n) <- alpha W2 B W1 (W1 lower of order n, W2 lower of order m):
+    // with scratch, B W1 goes there and W2 times it straight back into B;
+    // stream `on` waits for ev (W2 ready) before the second product.
+    void trmm_both(int64_t m, int64_t n, Mat<T> B, Mat<const T> W1, Mat<const T> W2, T alpha, hipEvent_t ev)
+    {
+        Mat<T> X;
+        if (m > 0 && n > 0 && scratch_for(m, n, &X)) {
+            mm(m, n, n, alpha, B, TRI_NONE, W1.tr(), TRI_UPPER, T(0), X);
+            wait(on, ev);
+            mm(m, n, m, T(1), W2, TRI_LOWER, X.tr(), TRI_NONE, T(0), B);
+            return;
+        }
+        trmm_rl(m, n, B, W1, alpha);
+        wait(on, ev);
+        trmm_ll(m, n, W2, B);
     }
     // in-place inverse of the lower triangle of A (order n)
     void trtri_rec(int64_t n, Mat<T> A, int64_t goff)
@@ -498,10 +572,11 @@ struct Run {
             return;
         }
         const int64_t n1 = rec_split(n, tb()), n2 = n - n1;
+        // both diagonal inverses first, so that the scratch is free for the
+        // off-diagonal block W21 = -W22 A21 W11
         trtri_rec(n1, A, goff);
-        trmm_rl(n2, n1, A.sub(n1, 0), A, T(-1));
         trtri_rec(n2, A.sub(n1, n1), goff + n1);
-        trmm_ll(n2, n1, A.sub(n1, n1), A.sub(n1, 0));
+        trmm_both(n2, n1, A.sub(n1, 0), A, A.sub(n1, n1), T(-1), nullptr);
     }
     // lower triangle of W^T W in place (order n)
     void lauum_rec(int64_t n, Mat<T> W)
@@ -861,6 +936,25 @@ static int pftrs_impl(rfp_context* h, char transr, char uplo, int64_t n, int64_t
     return r.err == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
+// PFTRI's workspace (elements): the m1 x m1 square, the 128-row leaf's
+// scratch at `tri`, the second stream's multiply scratch at `side`
+// (side_elems: the off-diagonal block of T2's top split).
+struct PftriWork {
+    int64_t tri, side, side_elems, total, q;
+};
+static PftriWork pftri_work(int64_t m1, int64_t m2)
+{
+    auto up = [](int64_t x) { return (x + 31) / 32 * 32; };  // 256-byte pieces
+    PftriWork w;
+    w.tri = up(m1 * m1);
+    w.side = up(w.tri + 3 * (int64_t)NB2 * NB2);
+    const int64_t s2 = m2 > NB2 ? rec_split(m2, NB2) : m2;
+    w.side_elems = s2 * (m2 - s2);
+    w.total = w.side + w.side_elems;
+    w.q = m1 > NB2 ? m1 - rec_split(m1, NB2) : 0;
+    return w;
+}
+
 template <typename T>
 static int pftri_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf, int* info, hipStream_t s,
                       PlanRec* rec = nullptr)
@@ -874,20 +968,28 @@ static int pftri_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     RfpBlocks b;
     rfp_blocks(transr, uplo, n, &b);
     Run<T> r;
-    T* tmp;  // m1 x m1 column-major: W21^T W21 of stage 3, formed before S changes
+    // Workspace: tmp, m1 x m1 column-major (the multiplies' scratch of the
+    // first stream in stage 2, then W21^T W21 of stage 3, formed before S
+    // changes); the 128-row leaf's scratch; the second stream's multiply
+    // scratch, one off-diagonal block of T2's recursion.
+    const PftriWork pw = pftri_work(b.m1, b.m2);
+    T* tmp;
     DeviceGuard g(rec ? -1 : h->device);
     if (rec) {
         r.rec = rec;
         tmp = plan_base<T>(RFP_PLAN_BUF_WORK);
     } else {
         if (n == 0) return set_int(s, info, 0) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
-        const size_t tri = (size_t)3 * NB2 * NB2;  // the 128-row inverse leaf's scratch, one block per stream
-        if (prepare(h, sizeof(T) * ((size_t)b.m1 * (size_t)b.m1 + tri)) != hipSuccess) return RFP_ERR_RUNTIME;
+        if (prepare(h, sizeof(T) * (size_t)pw.total) != hipSuccess) return RFP_ERR_RUNTIME;
         r = make_run<T>(h, s, info);
         tmp = (T*)h->inv;
-        r.tri_scratch = tmp + (size_t)b.m1 * (size_t)b.m1;
     }
+    r.tri_scratch = tmp + pw.tri;
     r.tri128 = true;
+    r.tsc[0].p = tmp;
+    r.tsc[0].elems = (int64_t)b.m1 * b.m1;
+    r.tsc[2].p = tmp + pw.side;
+    r.tsc[2].elems = pw.side_elems;
     RfpView<T> v = rfp_view(b, arf);
     Mat<T> Tmp{tmp, 1, b.m1};
     r.setinfo(info);
@@ -902,14 +1004,23 @@ static int pftri_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
     r.on = 0;
     hipEvent_t w22 = two ? r.record_join(side) : nullptr;
     r.trtri_rec(b.m1, v.t1, 0);
-    r.trmm_rl(b.m2, b.m1, v.s, v.t1, T(-1));
-    r.wait(0, w22);
-    r.trmm_ll(b.m2, b.m1, v.t2, v.s);
+    r.trmm_both(b.m2, b.m1, v.s, v.t1, v.t2, T(-1), w22);
     // stage 3: T1 <- W11^T W11 + W21^T W21; S <- W22^T W21; T2 <- W22^T W22.
     // W21^T W21 goes to a scratch triangle first, so that S can change on the
     // second stream (S <- W22^T S, then LAUUM of T2) while the first stream
     // forms W11^T W11 in T1 and adds the scratch triangle to it.
     r.mm(b.m1, b.m1, b.m2, T(1), v.s.tr(), TRI_NONE, v.s.tr(), TRI_NONE, T(0), Tmp, true);
+    // from here the first stream's multiply scratch is the block of tmp
+    // strictly above its diagonal: rows [0, q), columns [q, m1), q the order
+    // of the second diagonal block of T1's top split
+    if (pw.q > 0) {
+        r.tsc[0].p = tmp + (size_t)pw.q * b.m1;
+        r.tsc[0].ld = b.m1;
+        r.tsc[0].rows = pw.q;
+        r.tsc[0].cols = b.m1 - pw.q;
+    } else {
+        r.tsc[0] = typename Run<T>::Scratch{};
+    }
     hipEvent_t syrk = two ? r.record(0) : nullptr;
     r.wait(side, syrk);
     r.on = side;

@@ -110,6 +110,14 @@ class Replayer:
             raise PlanError("axpy: A and C overlap")
         self.write(tuple(op.c), C + op.alpha * A, mask, "axpy C")
 
+    def copy(self, op):
+        m, n = op.m, op.n
+        A, ra = self.read(tuple(op.a), m, n, 0, "copy A")
+        cbuf, cidx = _idx(tuple(op.c), m, n)
+        if ra[0] == cbuf and ra[1] & set(cidx.ravel().tolist()):
+            raise PlanError("copy: A and C overlap")
+        self.write(tuple(op.c), A, np.ones((m, n), bool), "copy C")
+
     def leaf(self, op):
         nb = op.m
         low = _mask(1, nb, nb)
@@ -188,6 +196,8 @@ class Replayer:
                 self.block_solve(op)
             elif op.kind == rfp.PLAN_AXPY:
                 self.axpy(op)
+            elif op.kind == rfp.PLAN_COPY:
+                self.copy(op)
             else:
                 self.leaf(op)
             s = op.stream
@@ -222,12 +232,17 @@ def work_size(routine, uplo, n):
     """Scratch the library allocates for each routine: PFTRF reuses one set of
     128-block leaf inverses sized for the larger diagonal block, PFTRS keeps
     the 64-block inverses of both T1 and T2, PFTRI one m1 x m1 square (the
-    product W21^T W21 formed before S changes)."""
+    product W21^T W21 formed before S changes), the 128-row inverse leaf's
+    scratch and the second stream's multiply scratch (one off-diagonal block
+    of T2's top split), each piece starting at a multiple of 32 elements."""
     m1 = (n + 1) // 2 if uplo == "L" else n // 2
     m2 = n - m1
     nl = lambda m, b: (m + b - 1) // b
     if routine == "F":
         return max(nl(m1, NB2), nl(m2, NB2)) * NB2 * NB2
     if routine == "I":
-        return m1 * m1
+        up = lambda x: (x + 31) // 32 * 32
+        split = lambda m: (nl(m, NB2) + 1) // 2 * NB2
+        s2 = split(m2) if m2 > NB2 else m2
+        return up(up(m1 * m1) + 3 * NB2 * NB2) + s2 * (m2 - s2)
     return (nl(m1, NB) + nl(m2, NB)) * NB * NB

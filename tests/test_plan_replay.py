@@ -52,7 +52,7 @@ def test_pftrs_plan(transr, uplo, n):
 
 
 @pytest.mark.parametrize("transr,uplo", LAYOUTS)
-@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("n", SIZES + [800, 1100])  # 800, 1100: copied-back products in the LAUUM recursion
 def test_pftri_plan(transr, uplo, n):
     A, _ = synth.spd(n, seed=n + 2)
     f, _ = oracle.pftrf(transr, uplo, n, oracle.trttf(transr, uplo, A))
