@@ -107,12 +107,14 @@ struct GemmParams {
     // part 2 only the crossing ones (masked).
     int part;
     int band;  // the tile's extent along the triangular operand's rows (parts 1, 2; work accounting)
-    // Tile order (not with tri_enum): bit 0 deals GROUP tile columns at a
-    // time instead of GROUP tile rows; bits 1 and 2 reverse the tile rows and
-    // columns.  With one triangular operand the tiles' k-ranges vary along
-    // one direction of the grid; each XCD then gets a contiguous range along
-    // the other one (an even share of the work) and the longest tiles first.
-    int order;
+    // Tile order (not with tri_enum): 0 deals GROUP tile rows at a time;
+    // otherwise (bit 3 set) `group` tile rows (bit 0 clear) or columns (bit 0
+    // set) at a time, and bits 1 and 2 reverse the tile rows and columns.  With one
+    // triangular operand the tiles' k-ranges vary along one direction of the
+    // grid: the groups run across it, and there are at least as many groups
+    // as XCDs, so that each XCD's contiguous range of groups holds an even
+    // share of the work, longest tiles first.
+    int order, group;
     int c_lower;   // write only C(i, j) with i >= j
     int tri_enum;  // square lower output: the grid enumerates lower tiles only
     int tiles_m, tiles_n;
@@ -186,19 +188,21 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
             ti = r;
             tj = bid - r * (r + 1) / 2;
         } else if (!(p.order & 1)) {
-            const int per_group = GROUP * p.tiles_n;
+            const int G = p.order ? p.group : GROUP;
+            const int per_group = G * p.tiles_n;
             const int g = bid / per_group;
-            const int first = g * GROUP;
-            const int rows = (p.tiles_m - first) < GROUP ? (p.tiles_m - first) : GROUP;
+            const int first = g * G;
+            const int rows = (p.tiles_m - first) < G ? (p.tiles_m - first) : G;
             const int in = bid - g * per_group;
             ti = first + in % rows;
             tj = in / rows;
         } else {
-            // GROUP tile columns at a time
-            const int per_group = GROUP * p.tiles_m;
+            // p.group tile columns at a time
+            const int G = p.group;
+            const int per_group = G * p.tiles_m;
             const int g = bid / per_group;
-            const int first = g * GROUP;
-            const int cols = (p.tiles_n - first) < GROUP ? (p.tiles_n - first) : GROUP;
+            const int first = g * G;
+            const int cols = (p.tiles_n - first) < G ? (p.tiles_n - first) : G;
             const int in = bid - g * per_group;
             tj = first + in % cols;
             ti = in / cols;
@@ -1014,7 +1018,9 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
     p.tri_enum = (c_lower && m == n) ? 1 : 0;
     if (!p.tri_enum && (triA != TRI_NONE) != (triB != TRI_NONE)) {
         const bool lowA = triA == TRI_LOWER || triA == TRI_SLOWER, lowB = triB == TRI_LOWER || triB == TRI_SLOWER;
-        p.order = triA != TRI_NONE ? (1 | (lowA ? 2 : 0)) : (lowB ? 4 : 0);
+        p.order = 8 | (triA != TRI_NONE ? (1 | (lowA ? 2 : 0)) : (lowB ? 4 : 0));
+        const int64_t across = (p.order & 1) ? tn : tm;  // tiles the groups are cut from
+        p.group = (int)std::min<int64_t>(GROUP, std::max<int64_t>(1, across / NXCD));
     }
     const int64_t ntiles = p.tri_enum ? tm * (tm + 1) / 2 : tm * tn;
     p.tiles_m = (int)tm;
