@@ -1,7 +1,7 @@
-// Diagonal-block ("leaf") kernels of the recursive RFP algorithms: Cholesky
-// (POTRF, Section 3), triangular inverse (TRTRI, Section 5 stage 2) and the
-// triangular product W^T W (LAUUM, Section 5 stage 3) on blocks of order at
-// most NB = 64.  One wavefront handles one block; rows or columns live in
+// 64-row diagonal-block ("leaf") kernels: Cholesky with the inverse of the
+// factor (POTRF, Section 3) and the batched inverses of every diagonal block
+// of a triangle (the fused solves, TFSM), on blocks of order at most NB = 64.
+// One wavefront handles one block; rows or columns live in
 // lanes and the block is broadcast through LDS, so the only synchronisation
 // is within the wavefront.  Every store back into the RFP array is masked to
 // the block's own lower triangle: the other triangle of a diagonal block is
@@ -97,40 +97,6 @@ __device__ __forceinline__ void inv_columns(const T (*Ls)[NB + 1], const T* rdia
     }
 }
 
-// In-place inverse of one lower-triangular leaf (PFTRI stage 2).
-template <typename T>
-__global__ __launch_bounds__(64) void trtri_leaf_kernel(Mat<T> A, int nb, int* info, int64_t info_base)
-{
-    if (info && *info) return;
-    const int i = threadIdx.x;
-    __shared__ T Ls[NB][NB + 1];
-    __shared__ T rdiag[NB];
-#pragma unroll
-    for (int j = 0; j < NB; j++) Ls[i][j] = (i < nb && j <= i) ? A.at(i, j) : (i == j ? T(1) : T(0));
-    __syncthreads();
-    // first exactly-zero diagonal entry (uniform decision)
-    for (int r = 0; r < nb; r++) {
-        if (Ls[r][r] == T(0)) {
-            if (i == 0) *info = (int)(info_base + r + 1);
-            return;
-        }
-    }
-    rdiag[i] = T(1) / Ls[i][i];
-    __syncthreads();
-    T w[NB];
-    inv_columns<T>(Ls, rdiag, i, w);
-    __syncthreads();
-    // lane c holds column c of W; transpose through LDS, then lane i stores row i
-#pragma unroll
-    for (int r = 0; r < NB; r++) Ls[r][i] = w[r];
-    __syncthreads();
-    if (i < nb) {
-#pragma unroll
-        for (int j = 0; j < NB; j++)
-            if (j <= i) A.at(i, j) = Ls[i][j];
-    }
-}
-
 // Out-of-place inverses of all leaves of a lower-triangular matrix of order n
 // (one wavefront per leaf, blockIdx.x = leaf).  Used by PFTRS and TFSM.
 // unit: the diagonal is taken as ones (not read).  Does nothing while
@@ -159,31 +125,6 @@ __global__ __launch_bounds__(64) void trtri_leaves_kernel(Mat<const T> A, int64_
     for (int r = 0; r < NB; r++) out[r * NB + i] = w[r];
 }
 
-// In-place lower triangle of W^T W for one leaf: (W^T W)(r, c) =
-// sum_{k >= r} W(k, r) W(k, c) for r >= c; lane c keeps column c of W.
-template <typename T>
-__global__ __launch_bounds__(64) void lauum_leaf_kernel(Mat<T> A, int nb, const int* info)
-{
-    if (info && *info) return;
-    const int i = threadIdx.x;
-    __shared__ T Ls[NB][NB + 1];
-#pragma unroll
-    for (int j = 0; j < NB; j++) Ls[i][j] = (i < nb && j <= i) ? A.at(i, j) : T(0);
-    __syncthreads();
-    const int c = i;
-    T w[NB];
-#pragma unroll
-    for (int k = 0; k < NB; k++) w[k] = Ls[k][c];
-#pragma unroll
-    for (int r = 0; r < NB; r++) {
-        T acc = 0;
-#pragma unroll
-        for (int k = r; k < NB; k++) acc += Ls[k][r] * w[k];
-        if (r >= c && r < nb) A.at(r, c) = acc;
-        __builtin_amdgcn_sched_barrier(0);
-    }
-}
-
 template <typename T>
 static const char* lname(const char* kern, const char* args)
 {
@@ -204,16 +145,6 @@ hipError_t potrf_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info_ba
 }
 
 template <typename T>
-hipError_t trtri_leaf(const Exec& ex, Mat<T> A, int nb, int64_t info_base)
-{
-    ProfScope ps(ex, lname<T>("trtri_leaf_kernel", sizeof(T) == 8 ? "rfp::Mat<double>, int, int*, long"
-                                                                  : "rfp::Mat<float>, int, int*, long"),
-                 (double)nb * nb * nb / 3.0, sizeof(T) * (double)nb * nb);
-    hipLaunchKernelGGL((trtri_leaf_kernel<T>), dim3(1), dim3(64), 0, ex.stream, A, nb, ex.info, info_base);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t trtri_leaves(const Exec& ex, Mat<const T> A, int64_t n, T* winv, bool unit)
 {
     if (n <= 0) return hipSuccess;
@@ -226,21 +157,9 @@ hipError_t trtri_leaves(const Exec& ex, Mat<const T> A, int64_t n, T* winv, bool
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t lauum_leaf(const Exec& ex, Mat<T> A, int nb)
-{
-    ProfScope ps(ex, lname<T>("lauum_leaf_kernel", sizeof(T) == 8 ? "rfp::Mat<double>, int, int const*"
-                                                                  : "rfp::Mat<float>, int, int const*"),
-                 (double)nb * nb * nb / 3.0, sizeof(T) * (double)nb * nb);
-    hipLaunchKernelGGL((lauum_leaf_kernel<T>), dim3(1), dim3(64), 0, ex.stream, A, nb, (const int*)ex.info);
-    return hipGetLastError();
-}
-
 #define RFP_LEAF_INST(T)                                                               \
     template hipError_t potrf_leaf<T>(const Exec&, Mat<T>, int, T*, int64_t);          \
-    template hipError_t trtri_leaf<T>(const Exec&, Mat<T>, int, int64_t);              \
-    template hipError_t trtri_leaves<T>(const Exec&, Mat<const T>, int64_t, T*, bool); \
-    template hipError_t lauum_leaf<T>(const Exec&, Mat<T>, int);
+    template hipError_t trtri_leaves<T>(const Exec&, Mat<const T>, int64_t, T*, bool);
 RFP_LEAF_INST(double)
 RFP_LEAF_INST(float)
 

@@ -181,8 +181,7 @@ struct Run {
     hipError_t err = hipSuccess;
     PlanRec* rec = nullptr;
     int nb = NB;  // leaf order of this call's recursion
-    bool tri128 = false;         // triangular inverses of blocks up to NB2 rows by the 128-row leaf
-    T* tri_scratch = nullptr;    // its scratch: NB2 x NB2 per stream (index `on`)
+    T* tri_scratch = nullptr;    // the 128-row inverse leaf's scratch: NB2 x NB2 per stream (index `on`)
     // Scratch of the out-of-place triangular multiplies, one per stream: an
     // r x c product fits when r <= rows and c <= cols (column-major with
     // leading dimension ld), or, with ld == 0, when r * c <= elems (leading
@@ -482,10 +481,10 @@ struct Run {
         chk(copy2d<T, T>(cur().stream, C, A, m, n, false));
     }
 
-    // Leaf order of the inversion recursion: 128 rows when the 128-row
-    // inverse and LAUUM leaves run, so that the in-place base products of the
-    // triangular multiplies (one tile across the aliased side) are 128 wide too.
-    int64_t tb() const { return tri128 ? NB2 : nb; }
+    // Leaf order of the inversion recursion: the 128-row inverse and LAUUM
+    // leaves, and in-place base products of the triangular multiplies 128
+    // wide (one tile across the aliased side).
+    static constexpr int64_t tb() { return NB2; }
     // B (m x n) <- alpha B W, W lower of order n
     void trmm_rl(int64_t m, int64_t n, Mat<T> B, Mat<const T> W, T alpha)
     {
@@ -563,12 +562,10 @@ struct Run {
     void trtri_rec(int64_t n, Mat<T> A, int64_t goff)
     {
         if (n <= 0) return;
-        // 128-row blocks: one workgroup's MFMA leaf (a scratch block per
-        // stream); 64-row blocks: the one-wavefront leaf
+        // one workgroup's MFMA leaf (a scratch block per stream)
         if (n <= tb()) {
             if (rec) leaf(RFP_PLAN_TRTRI_LEAF, A, n, nullptr, goff);
-            else if (tri128) chk(trtri128_leaf<T>(cur(), A, (int)n, tri_scratch + (int64_t)on * NB2 * NB2, goff));
-            else chk(trtri_leaf<T>(cur(), A, (int)n, goff));
+            else chk(trtri128_leaf<T>(cur(), A, (int)n, tri_scratch + (int64_t)on * NB2 * NB2, goff));
             return;
         }
         const int64_t n1 = rec_split(n, tb()), n2 = n - n1;
@@ -584,8 +581,7 @@ struct Run {
         if (n <= 0) return;
         if (n <= tb()) {
             if (rec) leaf(RFP_PLAN_LAUUM_LEAF, W, n, nullptr, 0);
-            else if (tri128) chk(lauum128_leaf<T>(cur(), W, (int)n));
-            else chk(lauum_leaf<T>(cur(), W, (int)n));
+            else chk(lauum128_leaf<T>(cur(), W, (int)n));
             return;
         }
         const int64_t n1 = rec_split(n, tb()), n2 = n - n1;
@@ -985,7 +981,6 @@ static int pftri_impl(rfp_context* h, char transr, char uplo, int64_t n, T* arf,
         tmp = (T*)h->inv;
     }
     r.tri_scratch = tmp + pw.tri;
-    r.tri128 = true;
     r.tsc[0].p = tmp;
     r.tsc[0].elems = (int64_t)b.m1 * b.m1;
     r.tsc[2].p = tmp + pw.side;
@@ -1314,7 +1309,6 @@ static int tftri_impl(rfp_context* h, char transr, char uplo, char diag, int64_t
     Run<T> r = make_run<T>(h, s, info);
     r.setinfo(info);
     T* dbuf = (T*)h->inv;
-    r.tri128 = true;
     r.tri_scratch = dbuf + dn;
     if (unit) r.chk(unit_diag<T>(s, v, dbuf, false));
     r.trtri_rec(b.m1, v.t1, 0);

@@ -222,18 +222,11 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
 // the first non-positive pivot j.
 template <typename T>
 hipError_t potrf_leaf(const Exec& ex, Mat<T> A, int nb, T* winv, int64_t info_base);
-// trtri: in-place inverse of the lower triangle of A.  info as above for an
-// exactly zero diagonal entry.
-template <typename T>
-hipError_t trtri_leaf(const Exec& ex, Mat<T> A, int nb, int64_t info_base);
 // Batched out-of-place inverses of every NB-leaf of a lower-triangular matrix
 // of order n: winv[b] = (diagonal block b)^{-1} (unit: with a unit diagonal,
 // which is then not read).
 template <typename T>
 hipError_t trtri_leaves(const Exec& ex, Mat<const T> A, int64_t n, T* winv, bool unit = false);
-// lauum: lower triangle of W^T W, in place.
-template <typename T>
-hipError_t lauum_leaf(const Exec& ex, Mat<T> A, int nb);
 // Fused Cholesky of a diagonal block of order nb <= NB2 with the inverse of
 // its factor (NB2 x NB2, row-major, zero above the diagonal, identity-padded)
 // written to winv; INFO as for potrf_leaf.
