@@ -1841,9 +1841,9 @@ static int zconvert_impl(rfp_context* h, char transr, char uplo, int64_t n, doub
     return zconvert(s, v, upc(uplo) == 'U', (double2*)a, lda, to_rfp) == hipSuccess ? 0 : RFP_ERR_RUNTIME;
 }
 
-static hipError_t zensure(rfp_context* h, int64_t n, int64_t nrhs)
+static hipError_t zensure(rfp_context* h, int64_t n, int64_t nrhs, bool inverse = false)
 {
-    return ensure(&h->zwork, &h->zwork_bytes, zwork_elems(n, nrhs) * sizeof(double2));
+    return ensure(&h->zwork, &h->zwork_bytes, zwork_elems(n, nrhs, inverse) * sizeof(double2));
 }
 
 int rfp_ztrttf(rfp_handle_t h, char transr, char uplo, int64_t n, const double* a, int64_t lda, double* arf,
@@ -1906,7 +1906,7 @@ int rfp_zpftri(rfp_handle_t h, char transr, char uplo, int64_t n, double* arf, i
     DeviceGuard g(h->device);
     if (set_int(stream, info, 0) != hipSuccess) return RFP_ERR_RUNTIME;
     if (n == 0) return 0;
-    if (zensure(h, n, 0) != hipSuccess) return RFP_ERR_RUNTIME;
+    if (zensure(h, n, 0, true) != hipSuccess) return RFP_ERR_RUNTIME;
     ZRfpViews v;
     zrfp_views(transr, uplo, n, (double2*)arf, &v);
     return zpftri_run(stream, v, (double2*)h->zwork, info) == hipSuccess ? 0 : RFP_ERR_RUNTIME;

@@ -391,7 +391,7 @@ struct ZRfpViews {
 // TRANSR / UPLO.
 bool zrfp_views(char transr, char uplo, int64_t n, double2* arf, ZRfpViews* v);
 // Scratch (complex elements) of the drivers for order n and nrhs columns.
-size_t zwork_elems(int64_t n, int64_t nrhs);
+size_t zwork_elems(int64_t n, int64_t nrhs, bool inverse = false);
 hipError_t zconvert(hipStream_t s, const ZRfpViews& v, bool upper, double2* a, int64_t lda, bool to_rfp);
 hipError_t zpftrf_run(hipStream_t s, const ZRfpViews& v, double2* work, int* info);
 hipError_t zpftrs_run(hipStream_t s, const ZRfpViews& v, double2* b, int64_t ldb, int64_t nrhs, double2* work,

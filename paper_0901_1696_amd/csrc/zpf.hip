@@ -514,17 +514,19 @@ constexpr int64_t ZB = 256;
 int64_t zleaves(int64_t m) { return (m + ZT - 1) / ZT; }
 
 // Work array of the drivers: leaf inverses of both diagonal blocks, the
-// split-K partial blocks, and ZB x max(n, nrhs) temporaries.
-size_t zwork_elems(int64_t n, int64_t nrhs)
+// split-K partial blocks, ZB x max(n, nrhs) temporaries, and for the
+// inversion an m1 x m2 block (the out-of-place products).
+size_t zwork_elems(int64_t n, int64_t nrhs, bool inverse)
 {
-    const int64_t m1 = (n + 1) / 2;  // the larger block order of every layout
+    const int64_t m1 = (n + 1) / 2, m2 = n / 2;  // the block orders of every layout
     const int64_t leaves = 2 * zleaves(m1);
     return (size_t)(leaves * ZT * ZT) + (size_t)(ZPART_TILES * ZT * ZT) +
-           (size_t)ZB * (size_t)std::max<int64_t>(std::max<int64_t>(n, nrhs), 1);
+           (size_t)ZB * (size_t)std::max<int64_t>(std::max<int64_t>(n, nrhs), 1) +
+           (inverse ? (size_t)m1 * (size_t)m2 : 0);
 }
 
 struct ZWork {
-    double2 *w1, *w2, *tmp;
+    double2 *w1, *w2, *tmp, *big;
 };
 static ZWork zwork_split(const ZRfpViews& v, double2* work)
 {
@@ -533,6 +535,7 @@ static ZWork zwork_split(const ZRfpViews& v, double2* work)
     z.w2 = z.w1 + zleaves(v.m1) * ZT * ZT;
     z_part = z.w2 + zleaves(v.m2) * ZT * ZT;
     z.tmp = z_part + ZPART_TILES * ZT * ZT;
+    z.big = z.tmp + ZB * std::max<int64_t>(v.m1 + v.m2, 1);
     return z;
 }
 
@@ -668,82 +671,74 @@ hipError_t zpftrs_run(hipStream_t s, const ZRfpViews& v, double2* b, int64_t ldb
     return hipSuccess;
 }
 
-// W = L^{-1} in place on the m x m lower view (block columns from the last):
-// W_{>j,j} = -W_{>j,>j} L_{>j,j} W_jj, then W_jj into the diagonal block.
-static hipError_t ztrtri_view(hipStream_t s, const ZView& A, int64_t m, double2* w, double2* tmp, int* info,
-                              int64_t info_off)
+// W = L^{-1} in place on the m x m lower view whose 64-row diagonal blocks
+// already hold their inverses: the 2 x 2 partition at splits that are
+// multiples of 64 from the view's start, both diagonal inverses first, then
+// W21 = -W22 (L21 W11) through the scratch X (at least n2 x n1 elements).
+static hipError_t ztrtri_rec(hipStream_t s, const ZView& A, int64_t m, double2* X, int* info)
 {
-    const int64_t l = zleaves(m);
-    ZCK(zleaf(s, A, m, 0, l, ZLEAF_INV, w, info, info_off, info));
-    for (int64_t j0 = (l - 1) * ZT; l > 0 && j0 >= 0; j0 -= ZT) {
-        const int64_t nb = std::min<int64_t>(ZT, m - j0), r = m - j0 - nb;
-        const ZView W{w + (j0 / ZT) * ZT * ZT, 1, ZT, 0};
-        if (r > 0) {
-            const ZView T{tmp, 1, r, 0};
-            ZCK(zgemm(s, r, nb, r, 1.0, zview_sub(A, j0 + nb, j0 + nb), 0, 0, zview_sub(A, j0 + nb, j0), 0, ZMASK_NONE,
-                      0.0, T, ZMASK_NONE, info));
-            ZCK(zgemm(s, r, nb, nb, -1.0, T, 0, ZMASK_NONE, W, 0, ZMASK_NONE, 0.0, zview_sub(A, j0 + nb, j0),
-                      ZMASK_NONE, info));
-        }
-        ZCK(zaxpby(s, nb, nb, 1.0, W, 0.0, zview_sub(A, j0, j0), 0, info));
-    }
+    if (m <= ZT) return hipSuccess;
+    const int64_t n1 = rec_split(m, ZT), n2 = m - n1;
+    ZCK(ztrtri_rec(s, A, n1, X, info));
+    ZCK(ztrtri_rec(s, zview_sub(A, n1, n1), n2, X, info));
+    const ZView Xv{X, 1, n2, false};
+    ZCK(zgemm(s, n2, n1, n1, 1.0, zview_sub(A, n1, 0), 0, ZMASK_NONE, A, 0, 0, 0.0, Xv, ZMASK_NONE, info));
+    ZCK(zgemm(s, n2, n1, n2, -1.0, zview_sub(A, n1, n1), 0, 0, Xv, 0, ZMASK_NONE, 0.0, zview_sub(A, n1, 0),
+              ZMASK_NONE, info));
     return hipSuccess;
 }
 
-// W^H W in place on the m x m lower view holding W (row blocks of ZB from
-// the first): C(I, 0:i0+nb) = W(i0:m, I)^H W(i0:m, 0:i0+nb).
-static hipError_t zlauum_view(hipStream_t s, const ZView& A, int64_t m, double2* tmp, const int* gate)
+// W^H W in place on the m x m lower view holding W: the 2 x 2 partition,
+// C11 = LAUUM(W11) + W21^H W21, C21 = W22^H W21 (through the scratch X,
+// copied back), C22 = LAUUM(W22); blocks of at most ZB rows by row blocks
+// (C(I, 0:i0+nb) = W(i0:m, I)^H W(i0:m, 0:i0+nb) into tmp, then copied).
+static hipError_t zlauum_rec(hipStream_t s, const ZView& A, int64_t m, double2* tmp, double2* X, const int* gate)
 {
-    for (int64_t i0 = 0; i0 < m; i0 += ZB) {
-        const int64_t nb = std::min<int64_t>(ZB, m - i0);
-        const ZView T{tmp, 1, ZB, 0};
-        ZCK(zgemm(s, nb, i0 + nb, m - i0, 1.0, zview_sub(A, i0, i0), 1, 0, zview_sub(A, i0, 0), 0, -i0, 0.0, T,
-                  ZMASK_NONE, gate));
-        ZCK(zaxpby(s, nb, i0 + nb, 1.0, T, 0.0, zview_sub(A, i0, 0), -i0, gate));
+    if (m <= 0) return hipSuccess;
+    if (m <= ZB) {
+        for (int64_t i0 = 0; i0 < m; i0 += ZT) {
+            const int64_t nb = std::min<int64_t>(ZT, m - i0);
+            const ZView T{tmp, 1, ZT, 0};
+            ZCK(zgemm(s, nb, i0 + nb, m - i0, 1.0, zview_sub(A, i0, i0), 1, 0, zview_sub(A, i0, 0), 0, -i0, 0.0, T,
+                      ZMASK_NONE, gate));
+            ZCK(zaxpby(s, nb, i0 + nb, 1.0, T, 0.0, zview_sub(A, i0, 0), -i0, gate));
+        }
+        return hipSuccess;
     }
-    return hipSuccess;
+    const int64_t n1 = rec_split(m, ZT), n2 = m - n1;
+    const ZView A21 = zview_sub(A, n1, 0), A22 = zview_sub(A, n1, n1);
+    ZCK(zlauum_rec(s, A, n1, tmp, X, gate));
+    ZCK(zgemm(s, n1, n1, n2, 1.0, A21, 1, ZMASK_NONE, A21, 0, ZMASK_NONE, 1.0, A, 0, gate));
+    const ZView Xv{X, 1, n2, false};
+    ZCK(zgemm(s, n2, n1, n2, 1.0, A22, 1, 0, A21, 0, ZMASK_NONE, 0.0, Xv, ZMASK_NONE, gate));
+    ZCK(zaxpby(s, n2, n1, 1.0, Xv, 0.0, A21, ZMASK_NONE, gate));
+    return zlauum_rec(s, A22, n2, tmp, X, gate);
 }
 
 hipError_t zpftri_run(hipStream_t s, const ZRfpViews& v, double2* work, int* info)
 {
     const ZWork z = zwork_split(v, work);
-    const int64_t l2 = zleaves(v.m2);
-    (void)l2;
-    // stage A: W = L^{-1} on the three blocks
-    ZCK(ztrtri_view(s, v.t1, v.m1, z.w1, z.tmp, info, 0));
+    // stage A: W = L^{-1} on the three blocks.  Every 64-row diagonal block
+    // of both triangles is inverted in place at once, then the recursion
+    // fills the off-diagonal blocks; S <- -W22 S W11 through the scratch.
+    ZCK(zleaf(s, v.t1, v.m1, 0, zleaves(v.m1), ZLEAF_INV_INPLACE, z.w1, info, 0, info));
+    ZCK(zleaf(s, v.t2, v.m2, 0, zleaves(v.m2), ZLEAF_INV_INPLACE, z.w2, info, v.m1, info));
+    ZCK(ztrtri_rec(s, v.t1, v.m1, z.big, info));
+    ZCK(ztrtri_rec(s, v.t2, v.m2, z.big, info));
     if (v.m2 > 0) {
-        // S <- -S W11, block columns of ZB from the first (column block j
-        // reads columns >= j only)
-        for (int64_t j0 = 0; j0 < v.m1; j0 += ZB) {
-            const int64_t nb = std::min<int64_t>(ZB, v.m1 - j0);
-            const ZView T{z.tmp, 1, v.m2, 0};
-            ZCK(zgemm(s, v.m2, nb, v.m1 - j0, 1.0, zview_sub(v.s, 0, j0), 0, ZMASK_NONE, zview_sub(v.t1, j0, j0), 0, 0,
-                      0.0, T, ZMASK_NONE, info));
-            ZCK(zaxpby(s, v.m2, nb, -1.0, T, 0.0, zview_sub(v.s, 0, j0), ZMASK_NONE, info));
-        }
-        ZCK(ztrtri_view(s, v.t2, v.m2, z.w2, z.tmp, info, v.m1));
-        // S <- W22 S, row blocks of ZB from the last (row block i reads rows <= i)
-        for (int64_t i0 = (v.m2 - 1) / ZB * ZB; i0 >= 0; i0 -= ZB) {
-            const int64_t nb = std::min<int64_t>(ZB, v.m2 - i0);
-            const ZView T{z.tmp, 1, ZB, 0};
-            ZCK(zgemm(s, nb, v.m1, i0 + nb, 1.0, zview_sub(v.t2, i0, 0), 0, -i0, v.s, 0, ZMASK_NONE, 0.0, T,
-                      ZMASK_NONE, info));
-            ZCK(zaxpby(s, nb, v.m1, 1.0, T, 0.0, zview_sub(v.s, i0, 0), ZMASK_NONE, info));
-        }
+        const ZView Xv{z.big, 1, v.m2, false};
+        ZCK(zgemm(s, v.m2, v.m1, v.m1, 1.0, v.s, 0, ZMASK_NONE, v.t1, 0, 0, 0.0, Xv, ZMASK_NONE, info));
+        ZCK(zgemm(s, v.m2, v.m1, v.m2, -1.0, v.t2, 0, 0, Xv, 0, ZMASK_NONE, 0.0, v.s, ZMASK_NONE, info));
     }
-    // stage B: A^{-1} = W^H W
-    ZCK(zlauum_view(s, v.t1, v.m1, z.tmp, info));
+    // stage B: A^{-1} = W^H W: T1 <- LAUUM(W11) + W21^H W21, S <- W22^H W21
+    // (through the scratch, copied back), T2 <- LAUUM(W22)
+    ZCK(zlauum_rec(s, v.t1, v.m1, z.tmp, z.big, info));
     if (v.m2 > 0) {
         ZCK(zgemm(s, v.m1, v.m1, v.m2, 1.0, v.s, 1, ZMASK_NONE, v.s, 0, ZMASK_NONE, 1.0, v.t1, 0, info));
-        // S <- W22^H S, row blocks of ZB from the first (row block i reads rows >= i)
-        for (int64_t i0 = 0; i0 < v.m2; i0 += ZB) {
-            const int64_t nb = std::min<int64_t>(ZB, v.m2 - i0);
-            const ZView T{z.tmp, 1, ZB, 0};
-            ZCK(zgemm(s, nb, v.m1, v.m2 - i0, 1.0, zview_sub(v.t2, i0, i0), 1, 0, zview_sub(v.s, i0, 0), 0,
-                      ZMASK_NONE, 0.0, T, ZMASK_NONE, info));
-            ZCK(zaxpby(s, nb, v.m1, 1.0, T, 0.0, zview_sub(v.s, i0, 0), ZMASK_NONE, info));
-        }
-        ZCK(zlauum_view(s, v.t2, v.m2, z.tmp, info));
+        const ZView Xv{z.big, 1, v.m2, false};
+        ZCK(zgemm(s, v.m2, v.m1, v.m2, 1.0, v.t2, 1, 0, v.s, 0, ZMASK_NONE, 0.0, Xv, ZMASK_NONE, info));
+        ZCK(zaxpby(s, v.m2, v.m1, 1.0, Xv, 0.0, v.s, ZMASK_NONE, info));
+        ZCK(zlauum_rec(s, v.t2, v.m2, z.tmp, z.big, info));
     }
     return hipSuccess;
 }

@@ -165,6 +165,24 @@ def test_zpftri_parity(h, transr, uplo, n):
 
 
 @pytest.mark.parametrize("transr,uplo", LAYOUTS)
+@pytest.mark.parametrize("n", [600, 1100])
+def test_zpftri_parity_recursive(h, transr, uplo, n):
+    """Triangles of 300 and 550 rows: the W^H W recursion splits blocks above
+    256 rows (at 550 twice), the inverse recursion down to 64-row blocks."""
+    a, _ = synth.hpd(n, seed=5 * n)
+    arf = oracle.ztrttf(transr, uplo, a)
+    f, _ = oracle.zpftrf(transr, uplo, n, arf)
+    want, rinfo = oracle.zpftri(transr, uplo, n, f)
+    t = dev(f)
+    info = info_tensor()
+    rfp.rfp_zpftri(h, transr, uplo, n, t, info)
+    assert read_info(info) == rinfo == 0
+    got = host(t)
+    assert rel(got, want) <= 1e-12 * n
+    assert np.abs(got - want).max() <= 1e-11 * n * np.abs(want).max()
+
+
+@pytest.mark.parametrize("transr,uplo", LAYOUTS)
 @pytest.mark.parametrize("n", [2, 9, 65, 130])
 def test_zpftri_gaussian_integer_exact(h, transr, uplo, n):
     L, _ = gauss_int_factor(n)
