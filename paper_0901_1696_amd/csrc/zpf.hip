@@ -105,10 +105,16 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(ZGemm g)
     const double2* a_base = g.A.p + (i0 + ai_0) * a_is + ak_0 * a_ks;
     const double2* b_base = g.B.p + (j0 + bj_0) * b_js + bk_0 * b_ks;
     const int64_t a_step = a_di * a_is + a_dk * a_ks, b_step = b_dj * b_js + b_dk * b_ks;
+    // Raw operand values of the next step and their keep masks (bit q):
+    // every lane loads (a masked element reads the view's first element,
+    // always valid), and the mask and conjugation are applied only when the
+    // values are staged, so the loads stay in flight during the products.
     double2 ra[ZQ], rb[ZQ];
+    unsigned ma = 0, mb = 0;
     auto load = [&](int64_t k0) {
         const double2* pa = a_base + k0 * a_ks;
         const double2* pb = b_base + k0 * b_ks;
+        ma = mb = 0;
 #pragma unroll
         for (int q = 0; q < ZQ; q++) {
             const int64_t gi = i0 + ai_0 + q * a_di, gka = k0 + ak_0 + q * a_dk;
@@ -116,17 +122,21 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(ZGemm g)
             // masks on the stored (row - column): A(gi, k) or A(k, gi); B(k, gj) or B(gj, k)
             const bool ia = gi < g.M && gka >= klo && gka < khi && (g.ta ? gka - gi : gi - gka) >= g.mda;
             const bool ib = gj < g.N && gkb >= klo && gkb < khi && (g.tb ? gj - gkb : gkb - gj) >= g.mdb;
-            ra[q] = ia ? zconj_if(pa[q * a_step], aconj) : make_double2(0.0, 0.0);
-            rb[q] = ib ? zconj_if(pb[q * b_step], bconj) : make_double2(0.0, 0.0);
+            ra[q] = *(ia ? pa + q * a_step : g.A.p);
+            rb[q] = *(ib ? pb + q * b_step : g.B.p);
+            ma |= (ia ? 1u : 0u) << q;
+            mb |= (ib ? 1u : 0u) << q;
         }
     };
     auto stage = [&]() {
 #pragma unroll
         for (int q = 0; q < ZQ; q++) {
-            Ar[ak_0 + q * a_dk][ai_0 + q * a_di] = ra[q].x;
-            Ai[ak_0 + q * a_dk][ai_0 + q * a_di] = ra[q].y;
-            Br[bk_0 + q * b_dk][bj_0 + q * b_dj] = rb[q].x;
-            Bi[bk_0 + q * b_dk][bj_0 + q * b_dj] = rb[q].y;
+            const double2 va = (ma >> q) & 1 ? zconj_if(ra[q], aconj) : make_double2(0.0, 0.0);
+            const double2 vb = (mb >> q) & 1 ? zconj_if(rb[q], bconj) : make_double2(0.0, 0.0);
+            Ar[ak_0 + q * a_dk][ai_0 + q * a_di] = va.x;
+            Ai[ak_0 + q * a_dk][ai_0 + q * a_di] = va.y;
+            Br[bk_0 + q * b_dk][bj_0 + q * b_dj] = vb.x;
+            Bi[bk_0 + q * b_dk][bj_0 + q * b_dj] = vb.y;
         }
     };
 
@@ -183,8 +193,23 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(ZGemm g)
                 }
         return;
     }
+    // by halves of the wave's rows: all reads of C first (a masked element
+    // reads C's first element), then the stores, so that the reads are not
+    // each waited for inside a branch
 #pragma unroll
-    for (int a = 0; a < 2; a++)
+    for (int a = 0; a < 2; a++) {
+        double2 o[2][4];
+        if (g.beta != 0.0) {
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int64_t i = i0 + 32 * wr + 16 * a + (lane >> 4) + 4 * r;
+                    const int64_t j = j0 + 32 * wc + 16 * b + (lane & 15);
+                    const bool ok = i < g.M && j < g.N && i - j >= g.mdc;
+                    o[b][r] = *(ok ? g.C.p + i * g.C.rs + j * g.C.cs : g.C.p);
+                }
+        }
 #pragma unroll
         for (int b = 0; b < 2; b++)
 #pragma unroll
@@ -192,16 +217,16 @@ __global__ __launch_bounds__(256, 2) void zgemm_kernel(ZGemm g)
                 const int64_t i = i0 + 32 * wr + 16 * a + (lane >> 4) + 4 * r;
                 const int64_t j = j0 + 32 * wc + 16 * b + (lane & 15);
                 if (i < g.M && j < g.N && i - j >= g.mdc) {
-                    double2* cp = g.C.p + i * g.C.rs + j * g.C.cs;
                     double2 v = make_double2(g.alpha * cr[a][b][r], g.alpha * ci[a][b][r]);
                     if (g.beta != 0.0) {
-                        const double2 o = zconj_if(*cp, g.C.conj);
-                        v.x += g.beta * o.x;
-                        v.y += g.beta * o.y;
+                        const double2 c = zconj_if(o[b][r], g.C.conj);
+                        v.x += g.beta * c.x;
+                        v.y += g.beta * c.y;
                     }
-                    *cp = zconj_if(v, g.C.conj);
+                    *(g.C.p + i * g.C.rs + j * g.C.cs) = zconj_if(v, g.C.conj);
                 }
             }
+    }
 }
 
 __global__ __launch_bounds__(256) void zsplit_reduce_kernel(ZGemm g)
