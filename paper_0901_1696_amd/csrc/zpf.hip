@@ -320,13 +320,25 @@ __global__ __launch_bounds__(256) void zleaf_kernel(ZView A, int64_t m, int mode
     const int64_t b = blockIdx.x, k0 = b * ZT;
     const int nb = (int)std::min<int64_t>(ZT, m - k0);
     if (nb <= 0) return;
-    for (int e = t; e < ZT * ZT; e += 256) {
-        const int i = e % ZT, j = e / ZT;
-        double2 v = make_double2(0.0, 0.0);
-        if (i >= j && i < nb) v = zconj_if(A.p[(k0 + i) * A.rs + (k0 + j) * A.cs], A.conj);
-        if (i == j) v.y = 0.0;  // the diagonal of a Hermitian matrix and of its factor is real
-        Lr[i][j] = v.x;
-        Li[i][j] = v.y;
+    {
+        // all 16 loads of a thread in flight together (an element outside the
+        // lower triangle reads the block's first element and is dropped)
+        constexpr int PER = ZT * ZT / 256;
+        double2 v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int e = t + 256 * u, i = e % ZT, j = e / ZT;
+            const bool in = i >= j && i < nb;
+            v[u] = *(in ? A.p + (k0 + i) * A.rs + (k0 + j) * A.cs : A.p + k0 * A.rs + k0 * A.cs);
+        }
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int e = t + 256 * u, i = e % ZT, j = e / ZT;
+            double2 x = (i >= j && i < nb) ? zconj_if(v[u], A.conj) : make_double2(0.0, 0.0);
+            if (i == j) x.y = 0.0;  // the diagonal of a Hermitian matrix and of its factor is real
+            Lr[i][j] = x.x;
+            Li[i][j] = x.y;
+        }
     }
     if (t == 0) {
         fail_sh = 0;
