@@ -22,12 +22,23 @@ __global__ __launch_bounds__(256) void copy2d_kernel(Mat<Td> dst, Mat<const Ts> 
     const int t = threadIdx.x;
     const int fast = t % CT, slow = t / CT;
     const bool src_rows = src.rs == 1;  // source row index contiguous
+    // all loads of a thread in flight together: an element outside the block
+    // (or its triangle) reads the view's first element and is not kept
+    Ts v[CT / 4];
 #pragma unroll
     for (int r = 0; r < CT / 4; r++) {
         const int li = src_rows ? fast : slow + 4 * r;
         const int lj = src_rows ? slow + 4 * r : fast;
         const int64_t i = i0 + li, j = j0 + lj;
-        if (i < m && j < n && (!lower || i >= j)) tile[li][lj] = src.at(i, j);
+        const bool ok = i < m && j < n && (!lower || i >= j);
+        v[r] = *(ok ? &src.at(i, j) : src.p);
+    }
+#pragma unroll
+    for (int r = 0; r < CT / 4; r++) {
+        const int li = src_rows ? fast : slow + 4 * r;
+        const int lj = src_rows ? slow + 4 * r : fast;
+        const int64_t i = i0 + li, j = j0 + lj;
+        if (i < m && j < n && (!lower || i >= j)) tile[li][lj] = v[r];
     }
     __syncthreads();
     const bool dst_rows = dst.rs == 1;
@@ -144,12 +155,30 @@ __global__ __launch_bounds__(256) void axpy2d_kernel(Mat<T> c, Mat<const T> a, i
     if (lower && j0 > i0 + CT - 1) return;
     const int t = threadIdx.x, fast = t % CT, slow = t / CT;
     const bool rows = c.rs == 1;
-#pragma unroll 4
-    for (int r = 0; r < CT / 4; r++) {
-        const int li = rows ? fast : slow + 4 * r;
-        const int lj = rows ? slow + 4 * r : fast;
-        const int64_t i = i0 + li, j = j0 + lj;
-        if (i < m && j < n && (!lower || i >= j)) c.at(i, j) += alpha * a.at(i, j);
+    // in groups of four rows: the group's loads issued together (an element
+    // outside the block or its triangle reads the first element of each view
+    // and is not stored)
+#pragma unroll
+    for (int r0 = 0; r0 < CT / 4; r0 += 4) {
+        T av[4], cv[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int r = r0 + u;
+            const int li = rows ? fast : slow + 4 * r;
+            const int lj = rows ? slow + 4 * r : fast;
+            const int64_t i = i0 + li, j = j0 + lj;
+            const bool ok = i < m && j < n && (!lower || i >= j);
+            av[u] = *(ok ? &a.at(i, j) : a.p);
+            cv[u] = *(ok ? &c.at(i, j) : c.p);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int r = r0 + u;
+            const int li = rows ? fast : slow + 4 * r;
+            const int lj = rows ? slow + 4 * r : fast;
+            const int64_t i = i0 + li, j = j0 + lj;
+            if (i < m && j < n && (!lower || i >= j)) c.at(i, j) = cv[u] + alpha * av[u];
+        }
     }
 }
 

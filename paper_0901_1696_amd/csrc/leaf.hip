@@ -112,9 +112,23 @@ __global__ __launch_bounds__(64) void trtri_leaves_kernel(Mat<const T> A, int64_
     const int i = threadIdx.x;
     __shared__ T Ls[NB][NB + 1];
     __shared__ T rdiag[NB];
+    // row i of the block, sixteen loads in flight at a time (an entry that is
+    // not read takes the block's first element and is replaced)
 #pragma unroll
-    for (int j = 0; j < NB; j++)
-        Ls[i][j] = (i < nb && j < i) ? A.at(o + i, o + j) : (i == j ? ((i < nb && !unit) ? A.at(o + i, o + i) : T(1)) : T(0));
+    for (int j0 = 0; j0 < NB; j0 += 16) {
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int j = j0 + u;
+            const bool rd = i < nb && (j < i || (j == i && !unit));
+            v[u] = *(rd ? &A.at(o + i, o + j) : &A.at(o, o));
+        }
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int j = j0 + u;
+            Ls[i][j] = (i < nb && j < i) ? v[u] : (i == j ? ((i < nb && !unit) ? v[u] : T(1)) : T(0));
+        }
+    }
     __syncthreads();
     rdiag[i] = T(1) / Ls[i][i];
     __syncthreads();

@@ -106,12 +106,23 @@ __global__ __launch_bounds__(256) void sym_norm_kernel(Mat<const double> a, int6
     __syncthreads();
     const bool rows = a.rs == 1;
     double sq = 0.0, mx = 0.0;
+    // all loads of a thread in flight together (an element outside the block
+    // or its triangle reads the view's first element and is skipped)
+    double av[TT / 4];
+#pragma unroll
+    for (int r = 0; r < TT / 4; r++) {
+        const int li = rows ? fast : slow + 4 * r;
+        const int lj = rows ? slow + 4 * r : fast;
+        const int64_t i = i0 + li, j = j0 + lj;
+        av[r] = *((i < m && j < n && (!lower || i >= j)) ? &a.at(i, j) : a.p);
+    }
+#pragma unroll
     for (int r = 0; r < TT / 4; r++) {
         const int li = rows ? fast : slow + 4 * r;
         const int lj = rows ? slow + 4 * r : fast;
         const int64_t i = i0 + li, j = j0 + lj;
         if (i < m && j < n && (!lower || i >= j)) {
-            const double v = fabs(a.at(i, j));
+            const double v = fabs(av[r]);
             const bool diag = gi0 + i == gj0 + j;
             atomicAdd(&rs[li], v);
             if (!diag) atomicAdd(&cs[lj], v);
