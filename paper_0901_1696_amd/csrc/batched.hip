@@ -99,17 +99,44 @@ __device__ void wg_mm(int m, int n, int k, T alpha, Mat<const typename NoDeduce<
         const int strip = w + 4 * s;
         if (strip >= nstrip) continue;
         const int i = strip * 16 + r;
-        for (int kk = 0; kk < k; kk += 4) {
+        // Each step's loads are issued together, with no branch around them
+        // (an entry outside the masks reads the operand's first element and is
+        // replaced by zero), one step ahead of the products that use them.
+        TA araw;
+        T braw[NCB];
+        unsigned oka = 0, okb = 0;
+        auto fetch = [&](int kk, TA& a, T (&b)[NCB], unsigned& ma, unsigned& mb) {
             const int ka = kk + g;
             const int64_t da = ka - i;
-            const T av = (i < m && ka < k && da >= alo && da <= ahi) ? tile::lp_round<LPR>((T)A.at(i, ka)) : T(0);
+            const bool ok = i < m && ka < k && da >= alo && da <= ahi;
+            a = *(ok ? &A.at(i, ka) : A.p);
+            ma = ok ? 1u : 0u;
+            mb = 0;
+#pragma unroll
+            for (int c = 0; c < NCB; c++) {
+                const int j = c * 16 + r;
+                const int64_t db = ka - j;
+                const bool okc = c < ncb && j < n && ka < k && db >= blo && db <= bhi;
+                b[c] = *(okc ? &B.at(j, ka) : B.p);
+                mb |= (okc ? 1u : 0u) << c;
+            }
+        };
+        fetch(0, araw, braw, oka, okb);
+        for (int kk = 0; kk < k; kk += 4) {
+            // this step's values are needed here (one wait for all of them) ...
+            asm volatile("" : "+v"(araw));
+#pragma unroll
+            for (int c = 0; c < NCB; c++) asm volatile("" : "+v"(braw[c]));
+            const T av = oka ? tile::lp_round<LPR>((T)araw) : T(0);
+            T bv[NCB];
+#pragma unroll
+            for (int c = 0; c < NCB; c++) bv[c] = (okb >> c) & 1 ? tile::lp_round<LPR>(braw[c]) : T(0);
+            // ... and the next step's are in flight during the products
+            if (kk + 4 < k) fetch(kk + 4, araw, braw, oka, okb);
 #pragma unroll
             for (int c = 0; c < NCB; c++) {
                 if (c >= ncb) break;
-                const int j = c * 16 + r;
-                const int64_t db = ka - j;
-                const T bv = (j < n && ka < k && db >= blo && db <= bhi) ? tile::lp_round<LPR>(B.at(j, ka)) : T(0);
-                acc[s][c] = M16<T>::op(av, bv, acc[s][c]);
+                acc[s][c] = M16<T>::op(av, bv[c], acc[s][c]);
             }
         }
     }
@@ -121,12 +148,21 @@ __device__ void wg_mm(int m, int n, int k, T alpha, Mat<const typename NoDeduce<
 #pragma unroll
         for (int c = 0; c < NCB; c++) {
             if (c >= ncb) break;
+            T cv[4] = {T(0), T(0), T(0), T(0)};
+            if (beta != T(0)) {  // the block's reads of C together, then its stores
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int i = strip * 16 + M16<T>::row(lane, e), j = c * 16 + r;
+                    const bool ok = i < m && j < n && (!c_lower || i >= j);
+                    cv[e] = *(ok ? &C.at(i, j) : C.p);
+                }
+            }
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const int i = strip * 16 + M16<T>::row(lane, e), j = c * 16 + r;
                 if (i < m && j < n && (!c_lower || i >= j)) {
                     T v = alpha * acc[s][c][e];
-                    if (beta != T(0)) v += beta * C.at(i, j);
+                    if (beta != T(0)) v += beta * cv[e];
                     C.at(i, j) = v;
                 }
             }
