@@ -101,21 +101,29 @@ __device__ __forceinline__ double lp_round(double v)
 
 // Each thread stages 8 elements of each operand per slab: the 128 x 16 slab
 // is read along the operand's unit stride (rows when rs == 1, k otherwise).
-template <typename T, int LPR>
-__device__ __forceinline__ void load_slab(const Mat<const T>& X, int rows, int64_t k0, int64_t K, int tri, T (&r)[8])
+// Every lane loads (an entry outside the slab or the mask reads the operand's
+// first element, always valid) and keeps the mask in bit e of `mk`; the mask
+// and the rounding are applied when the slab is stored, so the loads stay in
+// flight during the previous slab's products.
+template <typename T>
+__device__ __forceinline__ void load_slab(const Mat<const T>& X, int rows, int64_t k0, int64_t K, int tri, T (&r)[8],
+                                          unsigned& mk)
 {
     const int t = threadIdx.x;
     const bool rfast = X.rs == 1;
+    mk = 0;
 #pragma unroll
     for (int e = 0; e < 8; e++) {
         const int idx = t + 256 * e;
         const int i = rfast ? idx % TB : idx / KS, kk = rfast ? idx / TB : idx % KS;
         const int64_t k = k0 + kk;
-        r[e] = (i < rows && k < K && keep(tri, i, k)) ? lp_round<LPR>(X.at(i, k)) : T(0);
+        const bool ok = i < rows && k < K && keep(tri, i, k);
+        r[e] = *(ok ? &X.at(i, k) : X.p);
+        mk |= (ok ? 1u : 0u) << e;
     }
 }
-template <typename T>
-__device__ __forceinline__ void store_slab(const Mat<const T>& X, T (&S)[TB][KP], const T (&r)[8])
+template <typename T, int LPR>
+__device__ __forceinline__ void store_slab(const Mat<const T>& X, T (&S)[TB][KP], const T (&r)[8], unsigned mk)
 {
     const int t = threadIdx.x;
     const bool rfast = X.rs == 1;
@@ -123,7 +131,7 @@ __device__ __forceinline__ void store_slab(const Mat<const T>& X, T (&S)[TB][KP]
     for (int e = 0; e < 8; e++) {
         const int idx = t + 256 * e;
         const int i = rfast ? idx % TB : idx / KS, kk = rfast ? idx / TB : idx % KS;
-        S[i][kk] = r[e];
+        S[i][kk] = (mk >> e) & 1 ? lp_round<LPR>(r[e]) : T(0);
     }
 }
 
@@ -136,18 +144,19 @@ __device__ void mma(Smem<T>& sm, Acc<T>& acc, int m, int n, int64_t K, Mat<const
     const int wm = w >> 1, wn = w & 1;
     const int r = lane & 15, g = lane >> 4;
     T ra[8], rb[8];
+    unsigned ma = 0, mb = 0;
     if (K > 0) {
-        load_slab<T, LPR>(A, m, 0, K, triA, ra);
-        load_slab<T, LPR>(B, n, 0, K, triB, rb);
+        load_slab<T>(A, m, 0, K, triA, ra, ma);
+        load_slab<T>(B, n, 0, K, triB, rb, mb);
     }
     for (int64_t k0 = 0; k0 < K; k0 += KS) {
         __syncthreads();  // the previous slab's products are done with the LDS
-        store_slab<T>(A, sm.A, ra);
-        store_slab<T>(B, sm.B, rb);
+        store_slab<T, LPR>(A, sm.A, ra, ma);
+        store_slab<T, LPR>(B, sm.B, rb, mb);
         __syncthreads();
         if (k0 + KS < K) {
-            load_slab<T, LPR>(A, m, k0 + KS, K, triA, ra);
-            load_slab<T, LPR>(B, n, k0 + KS, K, triB, rb);
+            load_slab<T>(A, m, k0 + KS, K, triA, ra, ma);
+            load_slab<T>(B, n, k0 + KS, K, triB, rb, mb);
         }
 #pragma unroll
         for (int kk = 0; kk < KS; kk += 4) {
@@ -176,17 +185,28 @@ __device__ void store(const Acc<T>& acc, int m, int n, T alpha, T beta, Mat<T> C
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++)
+        for (int b = 0; b < 4; b++) {
+            T cv[4] = {T(0), T(0), T(0), T(0)};
+            if (beta != T(0)) {  // the block's reads of C together, then its stores
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int i = 64 * wm + 16 * a + Mfma<T>::row(lane, e);
+                    const int j = 64 * wn + 16 * b + (lane & 15);
+                    const bool ok = i < m && j < n && (!c_lower || i >= j);
+                    cv[e] = *(ok ? &C.at(i, j) : C.p);
+                }
+            }
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const int i = 64 * wm + 16 * a + Mfma<T>::row(lane, e);
                 const int j = 64 * wn + 16 * b + (lane & 15);
                 if (i < m && j < n && (!c_lower || i >= j)) {
                     T v = alpha * acc.v[a][b][e];
-                    if (beta != T(0)) v += beta * C.at(i, j);
+                    if (beta != T(0)) v += beta * cv[e];
                     C.at(i, j) = v;
                 }
             }
+        }
 }
 
 }  // namespace tile
