@@ -296,7 +296,8 @@ int rfp_dsfmv(rfp_handle_t h, char transr, char uplo, int64_t n, int64_t nrhs, d
  * max_iter sweeps and the fall-back without waiting, and what is not needed
  * exits at once.  It never synchronises; once the handle's workspace has been
  * sized by an earlier call of the same n and nrhs, it allocates nothing and
- * can be captured in a HIP graph.
+ * can be captured in a HIP graph (a later call that grows the workspace
+ * invalidates graphs captured before it).
  * Device outputs (ints): *iter = number of sweeps when refinement converged,
  * or the fall-back reason: -1 max_iter reached, -2 stalled, -3 low-precision
  * factor not positive definite, -4 the scaled low-precision copy of A is not
@@ -353,7 +354,10 @@ typedef struct {
  * -3 low-precision factor not positive definite, -4 scaled copy not finite.
  * No host synchronisation, and no allocation once the handle's workspace has
  * been sized by an earlier call on the same systems, so the call can be
- * captured in a HIP graph.  Argument order: FPREC=1, BATCH=2, SYS=3,
+ * captured in a HIP graph.  A later call on the same handle that needs a
+ * larger workspace (more systems, or larger ones) replaces it, and a graph
+ * captured before then replays into freed memory: capture after the largest
+ * call, or give graphs a handle of their own.  Argument order: FPREC=1, BATCH=2, SYS=3,
  * SYS_HOST=4, ARF_POOL=5, B_POOL=6, DO_PFTRI=7, TOL=8, MAX_ITER=9, INFO=10,
  * ITER=11. */
 int rfp_pfsv_vbatched(rfp_handle_t h, int fprec, int64_t batch, const rfp_sys_t* sys, const rfp_sys_t* sys_host,

@@ -53,12 +53,16 @@ typedef __attribute__((address_space(3))) void lvoid_t;
 constexpr int KP = BK + 2;  // LDS row pitch (elements): k-contiguous rows, 16-byte aligned, conflict-free
 
 // Low-precision operand modes of the FP32 GEMM (LP): 0 FP32 MFMA; 1 operands
-// rounded to FP16 and 2 to BF16 when staged in LDS, products on the
-// 16x16x16 MFMA with FP32 accumulation.  The 16x16x16 instructions take four
-// consecutive k values per lane: lane l supplies A(l % 16, 4 (l / 16) + j)
-// and B(4 (l / 16) + j, l % 16), j = 0..3; the result layout is the FP32 one.
-typedef _Float16 v4h __attribute__((ext_vector_type(4)));
-typedef short v4s __attribute__((ext_vector_type(4)));
+// rounded to FP16 and 2 to BF16 when staged in LDS, products on gfx950's
+// 16x16x32 MFMA with FP32 accumulation.  Each lane supplies eight k values of
+// its row of A (row l % 16) and the same eight k values of its column of B
+// (column l % 16), the k group 8 (l / 16) .. 8 (l / 16) + 7 of a 32-deep
+// slab; since A and B use the same assignment every k of the slab is summed
+// exactly once, whatever order the instruction takes its k slots in.  The
+// result layout is the FP32 one.
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 template <typename T, int LP>
 struct Lds {
     typedef T type;
@@ -67,12 +71,12 @@ struct Lds {
 template <>
 struct Lds<float, 1> {
     typedef _Float16 type;
-    static constexpr int pitch = BK + 4;  // 40-byte rows: 8-byte aligned k groups
+    static constexpr int pitch = 40;  // 32-deep slabs in 80-byte rows: 16-byte aligned k groups
 };
 template <>
 struct Lds<float, 2> {
     typedef short type;  // BF16 bit pattern
-    static constexpr int pitch = BK + 4;
+    static constexpr int pitch = 40;
 };
 // FP32 -> BF16, round to nearest even (a NaN stays a quiet NaN)
 __device__ __forceinline__ short f32_to_bf16(float f)
@@ -248,14 +252,17 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
     const int lane = t & 63, w = t >> 6;
     const int wm = w & 1, wn = w >> 1;
 
-    constexpr int EA = BM * BK / NTH;  // elements of each operand tile per thread
-    constexpr int EB = BN * BK / NTH;
-    const int a_i = AMC ? (t % BM) : (t / BK);
-    const int a_k = AMC ? (t / BM) : (t % BK);
-    const int b_j = BNC ? (t % BN) : (t / BK);
-    const int b_k = BNC ? (t / BN) : (t % BK);
-    constexpr int A_STEP = AMC ? NTH / BM : NTH / BK;  // along k (AMC) or i
-    constexpr int B_STEP = BNC ? NTH / BN : NTH / BK;
+    // slab depth of the register-staged path: 32 k values for FP16/BF16
+    // operands (one 16x16x32 MFMA per fragment pair), 16 otherwise
+    constexpr int SK = LP != 0 ? 32 : BK;
+    constexpr int EA = BM * SK / NTH;  // elements of each operand tile per thread
+    constexpr int EB = BN * SK / NTH;
+    const int a_i = AMC ? (t % BM) : (t / SK);
+    const int a_k = AMC ? (t / BM) : (t % SK);
+    const int b_j = BNC ? (t % BN) : (t / SK);
+    const int b_k = BNC ? (t / BN) : (t % SK);
+    constexpr int A_STEP = AMC ? NTH / BM : NTH / SK;  // along k (AMC) or i
+    constexpr int B_STEP = BNC ? NTH / BN : NTH / SK;
 
     const Band ba = band_of(p.triA), bb = band_of(p.triB);
     const int64_t kmax = p.k > 0 ? p.k - 1 : 0;
@@ -290,7 +297,7 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
         const int64_t j = row < b_lim ? row : b_lim;
         return b_org[j * p.ldb + kk];
     };
-    // Full slab [k0, k0 + BK) inside [kb, ke): no k bounds.
+    // Full slab [k0, k0 + SK) inside [kb, ke): no k bounds.
     auto load_fast = [&](int64_t k0) {
         int ai = a_i, ak = a_k, bj = b_j, bk = b_k;
         asm volatile("" : "+v"(ai), "+v"(bj));
@@ -365,25 +372,26 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
     const int lrow = lane & 15, lk = 2 * (lane >> 4);
     auto compute = [&](int buf) {
         if constexpr (LP != 0) {
-            typedef typename std::conditional<LP == 1, v4h, v4s>::type v4l;
-            const int lk4 = 4 * (lane >> 4);
-            v4l af[WMB], bf[WNB];
+            typedef typename std::conditional<LP == 1, v8h, v8s>::type v8l;
+            const int lk8 = 8 * (lane >> 4);
+            v8l af[WMB], bf[WNB];
 #pragma unroll
             for (int x = 0; x < WMB; x++)
-                af[x] = *reinterpret_cast<const v4l*>(&As[buf][wm * (BM / 2) + x * 16 + lrow][lk4]);
+                af[x] = *reinterpret_cast<const v8l*>(&As[buf][wm * (BM / 2) + x * 16 + lrow][lk8]);
 #pragma unroll
             for (int x = 0; x < WNB; x++)
-                bf[x] = *reinterpret_cast<const v4l*>(&Bs[buf][wn * (BN / 2) + x * 16 + lrow][lk4]);
+                bf[x] = *reinterpret_cast<const v8l*>(&Bs[buf][wn * (BN / 2) + x * 16 + lrow][lk8]);
 #pragma unroll
             for (int a = 0; a < WMB; a++)
 #pragma unroll
                 for (int b = 0; b < WNB; b++) {
                     if constexpr (LP == 1)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16f16(CMC ? bf[b] : af[a], CMC ? af[a] : bf[b],
-                                                                          acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(CMC ? bf[b] : af[a], CMC ? af[a] : bf[b],
+                                                                           acc[a][b], 0, 0, 0);
                     else
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(CMC ? bf[b] : af[a], CMC ? af[a] : bf[b],
-                                                                              acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(v8bf, CMC ? bf[b] : af[a]), __builtin_bit_cast(v8bf, CMC ? af[a] : bf[b]),
+                            acc[a][b], 0, 0, 0);
                 }
             return;
         } else {
@@ -606,7 +614,7 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
             __builtin_amdgcn_s_waitcnt(0x0F70);  // the spare transfers of the last passes
         }
     } else {
-        const int64_t nfull = span / BK, nslab = (span + BK - 1) / BK;
+        const int64_t nfull = span / SK, nslab = (span + SK - 1) / SK;
         if (nslab > 0) {
             if (nfull > 0) load_fast(kb);
             else load_tail(kb);
@@ -617,17 +625,17 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
             // scheduling fence keeps the next slab's LDS stores (and the wait for
             // its global loads that they imply) after this slab's products.
             for (; s + 1 < nfull; s++) {
-                load_fast(kb + (s + 1) * BK);
+                load_fast(kb + (s + 1) * SK);
                 compute((int)(s & 1));
                 __builtin_amdgcn_sched_barrier(0);
-                store((int)((s + 1) & 1), kb + (s + 1) * BK, false);
+                store((int)((s + 1) & 1), kb + (s + 1) * SK, false);
                 __syncthreads();
             }
             if (s + 1 < nslab) {  // a ragged slab follows the last full one
-                load_tail(kb + (s + 1) * BK);
+                load_tail(kb + (s + 1) * SK);
                 compute((int)(s & 1));
                 __builtin_amdgcn_sched_barrier(0);
-                store((int)((s + 1) & 1), kb + (s + 1) * BK, true);
+                store((int)((s + 1) & 1), kb + (s + 1) * SK, true);
                 __syncthreads();
                 s++;
             }
@@ -1041,8 +1049,9 @@ hipError_t gemm(const Exec& ex, int64_t m, int64_t n, int64_t k, T alpha, Mat<co
         while (nsplit > 1 && (size_t)(nsplit * m * n) * sizeof(T) > ex.splitk_bytes) nsplit--;
     }
     if (nsplit > 1) {
+        const int64_t sk = lp != 0 ? 32 : BK;  // the kernel's slab depth
         int64_t chunk = (p.k + nsplit - 1) / nsplit;
-        chunk = (chunk + BK - 1) / BK * BK;
+        chunk = (chunk + sk - 1) / sk * sk;
         nsplit = (p.k + chunk - 1) / chunk;
         p.kchunk = chunk;
         p.W = (T*)ex.splitk_ws;
