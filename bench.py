@@ -394,6 +394,16 @@ def bench_mixed(h, n, nrhs=16, kappas=(1e3, 1e6), reps=2):
     return out
 
 
+def batch_fractions(fl, tm, ao, bo):
+    """A batched run against both of its bounds: the FP64 MFMA peak, and HBM
+    at its least traffic (every RFP array and right-hand side read once and
+    written once, 8 bytes an entry)."""
+    byt = 2 * 8 * (ao + bo)
+    return {"frac_fp64_peak": round(fl / tm / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
+            "hbm_min_bytes": byt, "hbm_gbs_at_min_bytes": round(byt / tm / 1e9, 1),
+            "frac_hbm": round(byt / tm / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def bench_batched(h, count=20000, seed=4, one_at_a_time=300, reps=3):
     """Persistent batched launch vs the single-system routines one system at a time."""
     import numpy as np
@@ -447,6 +457,7 @@ def bench_batched(h, count=20000, seed=4, one_at_a_time=300, reps=3):
             bad = int((info != 0).sum().item())
             rec = {"mode": name, "pftri": pftri, "ms": round(tm * 1e3, 2), "gflops": round(fl / tm / 1e9, 1),
                    "info_nonzero": bad, "max_sweeps": int(it.max().item()), "min_code": int(it.min().item())}
+            rec.update(batch_fractions(fl, tm, ao, bo))
             out["runs"].append(rec)
             log(f"[bench] batched {rec}")
     # the same work through the single-system routines, one system at a time
@@ -539,6 +550,7 @@ def bench_batched_medium(h, count=512, seed=5, reps=2, one_at_a_time=24):
                "info_nonzero": int((info != 0).sum().item()),
                "refined": int((itc > 0).sum()), "fallback": {str(c): int((itc == c).sum()) for c in (-1, -2, -3, -4)},
                "max_sweeps": int(itc.max())}
+        rec.update(batch_fractions(fl, tm, ao, bo))
         # backward error of the solves of a sample of systems (dense FP64 check)
         worst = 0.0
         for (n, a0, b0, ldb, nr, t, u) in systems[:16]:
