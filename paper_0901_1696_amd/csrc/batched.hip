@@ -547,6 +547,7 @@ __host__ __device__ inline SysPlan plan_of(const rfp_sys_t& sd, int mode, int pf
     return p;
 }
 
+#ifndef RFP_BATCHED_X2
 size_t batched_wg_scratch_bytes() { return wg_scratch_bytes(); }
 size_t batched_state_bytes(int64_t batch) { return align256(sizeof(SysState) * (size_t)batch); }
 
@@ -562,6 +563,7 @@ int64_t batched_plan_host(const rfp_sys_t* sys_host, int64_t batch, int mode, in
     *tasks = t;
     return bytes;
 }
+#endif
 
 namespace {
 
@@ -1427,6 +1429,7 @@ __device__ void advance(const BatchArgs& a, int64_t s, SysState& S, const rfp_sy
 
 }  // namespace
 
+#ifndef RFP_BATCHED_X2
 // Setup: per-system plan and scratch offsets (one workgroup, scan over the
 // systems in chunks of 256); the control words.
 __global__ __launch_bounds__(256) void batched_setup_kernel(BatchArgs a)
@@ -1536,7 +1539,17 @@ __global__ void batched_finish_kernel(BatchArgs a)
     }
 }
 
-__global__ __launch_bounds__(256, 1) void batched_kernel(BatchArgs a)
+#endif
+
+// The persistent loop, built twice: batched_kernel runs one workgroup per
+// compute unit, which leaves the tile tasks of systems with n > 256 their
+// full register budget; batched_kernel_x2 runs two (at most 256 registers a
+// lane, some spilled, and two 78 KB LDS blocks per CU), which hides more of
+// the per-system latency of a batch that holds only one-task systems.  The
+// second is built in its own translation unit (batched_x2.hip includes this
+// file with RFP_BATCHED_X2 defined): the loop's callees are compiled once
+// per unit, and only there do they all get the smaller register budget.
+__device__ __forceinline__ void batched_loop(const BatchArgs& a)
 {
     __shared__ BatchSmem sm;
     __shared__ double red[4];
@@ -1626,10 +1639,24 @@ __global__ __launch_bounds__(256, 1) void batched_kernel(BatchArgs a)
     }
 }
 
+#ifdef RFP_BATCHED_X2
+__global__ __launch_bounds__(256, 2) void batched_kernel_x2(BatchArgs a) { batched_loop(a); }
+
+hipError_t launch_batched_x2(unsigned wgs, hipStream_t stream, const BatchArgs& a)
+{
+    hipLaunchKernelGGL(batched_kernel_x2, dim3(wgs), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+#else
+__global__ __launch_bounds__(256, 1) void batched_kernel(BatchArgs a) { batched_loop(a); }
+
+// batched_x2.hip: the same loop built for two workgroups per compute unit
+hipError_t launch_batched_x2(unsigned wgs, hipStream_t stream, const BatchArgs& a);
+
 hipError_t batched_solve(const Exec& ex, const rfp_sys_t* sys, int64_t batch, double* arf, double* b, int mode,
                          int pftri, double tol, double shift, int max_iter, int* info, int* iter, char* wgs_mem,
-                         int wgs, char* sysmem, int64_t sysmem_bytes, void* st, unsigned long long* q, int64_t qcap,
-                         unsigned long long* ctl)
+                         int wgs, int occ, char* sysmem, int64_t sysmem_bytes, void* st, unsigned long long* q,
+                         int64_t qcap, unsigned long long* ctl)
 {
     if (batch <= 0) return hipSuccess;
     BatchArgs a{sys, batch, arf, b, mode, pftri, tol, shift, max_iter, info, iter, wgs_mem, sysmem, sysmem_bytes,
@@ -1639,12 +1666,17 @@ hipError_t batched_solve(const Exec& ex, const rfp_sys_t* sys, int64_t batch, do
     hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)std::max<int64_t>(zb, 1)), dim3(256), 0, ex.stream, q, qcap);
     const unsigned sb = (unsigned)((batch + 255) / 256);
     hipLaunchKernelGGL(batched_queue_kernel, dim3(sb), dim3(256), 0, ex.stream, a);
-    {
+    if (occ == 2) {
+        ProfScope ps(ex, "rfp::batched_kernel_x2(rfp::BatchArgs)", 0.0, 0.0);
+        const hipError_t e = launch_batched_x2((unsigned)wgs, ex.stream, a);
+        if (e != hipSuccess) return e;
+    } else {
         ProfScope ps(ex, "rfp::batched_kernel(rfp::BatchArgs)", 0.0, 0.0);
         hipLaunchKernelGGL(batched_kernel, dim3((unsigned)wgs), dim3(256), 0, ex.stream, a);
     }
     hipLaunchKernelGGL(batched_finish_kernel, dim3(sb), dim3(256), 0, ex.stream, a);
     return hipGetLastError();
 }
+#endif
 
 }  // namespace rfp

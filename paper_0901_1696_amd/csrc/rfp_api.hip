@@ -2100,14 +2100,22 @@ int rfp_pfsv_vbatched(rfp_handle_t h, int fprec, int64_t batch, const rfp_sys_t*
     const int mi = mode ? max_iter : 1;
     // Sizes: the per-system scratch and the task count of the systems with
     // n > 256 come from the host copy of the table (without it such systems
-    // are refused); the per-workgroup scratch is sized for two workgroups per
-    // compute unit, the most that run at once.
+    // are refused); the per-workgroup scratch is always sized for two
+    // workgroups per compute unit, the most that run at once, so it does not
+    // change with the batch's make-up.  A batch of one-task systems only
+    // (n <= 256) runs two workgroups per compute unit; one with larger
+    // systems runs one, whose tile tasks need the full register budget.
     int64_t tasks = batch, sysbytes = 0;
-    if (sys_host) sysbytes = batched_plan_host(sys_host, batch, mode, pftri, mi, &tasks);
-    const int wgs = h->cus;  // one workgroup per compute unit (register-bound)
+    bool all_small = true;
+    if (sys_host) {
+        sysbytes = batched_plan_host(sys_host, batch, mode, pftri, mi, &tasks);
+        for (int64_t i = 0; i < batch && all_small; i++) all_small = sys_host[i].n <= 256;
+    }
+    const int occ = all_small ? 2 : 1;
+    const int wgs = occ * h->cus;
     const size_t a_ctl = 256, a_st = batched_state_bytes(batch);
     const size_t a_q = (sizeof(unsigned long long) * (size_t)(tasks + 1) + 255) & ~(size_t)255;
-    const size_t a_wg = (size_t)wgs * batched_wg_scratch_bytes();
+    const size_t a_wg = (size_t)(2 * h->cus) * batched_wg_scratch_bytes();
     const size_t need = a_ctl + a_st + a_q + a_wg + (size_t)sysbytes;
     if (ensure(&h->bat, &h->bat_bytes, need) != hipSuccess) return RFP_ERR_RUNTIME;
     char* base = (char*)h->bat;
@@ -2116,7 +2124,7 @@ int rfp_pfsv_vbatched(rfp_handle_t h, int fprec, int64_t batch, const rfp_sys_t*
     ex.prof = h->prof;
     const double shift = mode ? lowp_shift(h, fprec) : 0.0;
     const hipError_t e = batched_solve(ex, sys, batch, arf_pool, b_pool, mode, pftri, tol, shift, mi, info, iter,
-                                       base + a_ctl + a_st + a_q, wgs, base + a_ctl + a_st + a_q + a_wg,
+                                       base + a_ctl + a_st + a_q, wgs, occ, base + a_ctl + a_st + a_q + a_wg,
                                        sys_host ? (int64_t)(h->bat_bytes - (a_ctl + a_st + a_q + a_wg)) : 0,
                                        base + a_ctl,
                                        (unsigned long long*)(base + a_ctl + a_st), tasks + 1,

@@ -342,15 +342,17 @@ hipError_t row_scale(hipStream_t st, double* y, int64_t ldy, const double* x, in
 // 1 FP32, 2 FP16, 3 BF16 factor + FP64 refinement.  wgs_mem holds
 // batched_wg_scratch_bytes() per workgroup; sysmem the per-system scratch of
 // the systems with n > 256 (their total from batched_plan_host); st
-// batched_state_bytes(batch); q a task queue of qcap slots; ctl 4 words.
+// batched_state_bytes(batch); q a task queue of qcap slots; ctl 4 words;
+// wgs persistent workgroups of the kernel built for occ (1 or 2) of them per
+// compute unit.
 size_t batched_wg_scratch_bytes();
 size_t batched_state_bytes(int64_t batch);
 int64_t batched_plan_host(const rfp_sys_t* sys_host, int64_t batch, int mode, int pftri, int max_iter,
                           int64_t* tasks);
 hipError_t batched_solve(const Exec& ex, const rfp_sys_t* sys, int64_t batch, double* arf, double* b, int mode,
                          int pftri, double tol, double shift, int max_iter, int* info, int* iter, char* wgs_mem,
-                         int wgs, char* sysmem, int64_t sysmem_bytes, void* st, unsigned long long* q, int64_t qcap,
-                         unsigned long long* ctl);
+                         int wgs, int occ, char* sysmem, int64_t sysmem_bytes, void* st, unsigned long long* q,
+                         int64_t qcap, unsigned long long* ctl);
 
 // 2-D strided copy dst = src (m x n), optionally only the lower triangle.
 template <typename Td, typename Ts>
