@@ -307,3 +307,39 @@ def test_batched_ill_conditioned_refines_without_fallback(h, mode):
     # unshifted: FP16 / BF16 fail on every system, FP32 on the kappa = 1e8 ones
     lost = res[0.0] if mode != rfp.PREC_FP32 else res[0.0][0::2]
     assert np.all(lost == -3), res[0.0]
+
+
+def test_batched_two_workgroups_per_cu_build(h):
+    """A batch of one-task systems only (n <= 256) runs the two-per-CU build
+    of the persistent loop; one tiled system (n = 257) added to the same
+    batch switches the launch to the one-per-CU build.  The one-task systems
+    come out bit for bit the same from both builds (one workgroup does all of
+    a system's arithmetic, in the same order), and match the oracle."""
+    ns = [1, 17, 64, 128, 200, 255, 256]
+    lays = [i % 4 for i in range(len(ns))]
+    nrs = [1, 2, 3, 4, 5, 6, 7]
+    runs = {}
+    for name, extra in (("small", []), ("with_tiled", [257])):
+        systems, arfs, As, arf_pool, b_pool = make_batch(ns + extra, lays + [1] * len(extra),
+                                                         nrs + [2] * len(extra), seed=700)
+        torch.cuda.synchronize()
+        rfp.rfp_profile_enable(h, True)
+        try:
+            ap, bp, info, it = run_batch(h, rfp.PREC_FP64, systems, arf_pool, b_pool)
+            prof = rfp.rfp_profile_read(h)
+        finally:
+            rfp.rfp_profile_enable(h, False)
+        assert np.all(info == 0) and np.all(it == 0), (name, info, it)
+        runs[name] = (systems, arfs, b_pool, ap, bp, {k for k in prof if k.startswith("rfp::batched_kernel")})
+    assert runs["small"][5] == {"rfp::batched_kernel_x2(rfp::BatchArgs)"}
+    assert runs["with_tiled"][5] == {"rfp::batched_kernel(rfp::BatchArgs)"}
+    systems, arfs, b_pool, ap, bp, _ = runs["small"]
+    ap2, bp2 = runs["with_tiled"][3], runs["with_tiled"][4]
+    for sysd, arf in zip(systems, arfs):
+        n, a0, b0, ldb, nr, t, u = sysd
+        assert np.array_equal(ap[a0:a0 + arf.size], ap2[a0:a0 + arf.size]), (n, t, u)
+        assert np.array_equal(_sys_b(bp, sysd), _sys_b(bp2, sysd)), (n, t, u)
+        f, _ = oracle.pftrf(t, u, n, arf.copy())
+        want = oracle.pftrs(t, u, n, f, np.asfortranarray(_sys_b(b_pool, sysd)[:n]))
+        assert oracle.rel_fro(ap[a0:a0 + arf.size], f) <= 1e-12 * n, (n, t, u)
+        assert oracle.rel_fro(_sys_b(bp, sysd)[:n], want) <= 1e-12 * n, (n, t, u)
