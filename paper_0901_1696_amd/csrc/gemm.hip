@@ -297,14 +297,22 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
         const int64_t j = row < b_lim ? row : b_lim;
         return b_org[j * p.ldb + kk];
     };
+    // k offset within the slab of element r of a column-major operand's
+    // thread (row fixed, k varying).  FP16/BF16 operands take runs of eight
+    // consecutive k (group g + STEP (r / 8), element r % 8), so that a run
+    // goes to LDS as one 16-byte store along its row; FP32/FP64 ones take
+    // every STEP-th k.
+    constexpr bool PACK = LP != 0;
+    static_assert(!PACK || ((!AMC || EA % 8 == 0) && (!BNC || EB % 8 == 0)), "runs of eight k per thread");
+    auto kofs = [&](int g, int step, int r) -> int { return PACK ? 8 * (g + step * (r / 8)) + (r % 8) : g + r * step; };
     // Full slab [k0, k0 + SK) inside [kb, ke): no k bounds.
     auto load_fast = [&](int64_t k0) {
         int ai = a_i, ak = a_k, bj = b_j, bk = b_k;
         asm volatile("" : "+v"(ai), "+v"(bj));
 #pragma unroll
-        for (int r = 0; r < EA; r++) ra[r] = ld_a(r, ai, k0 + ak + (AMC ? r * A_STEP : 0));
+        for (int r = 0; r < EA; r++) ra[r] = ld_a(r, ai, k0 + (AMC ? kofs(ak, A_STEP, r) : ak));
 #pragma unroll
-        for (int r = 0; r < EB; r++) rb[r] = ld_b(r, bj, k0 + bk + (BNC ? r * B_STEP : 0));
+        for (int r = 0; r < EB; r++) rb[r] = ld_b(r, bj, k0 + (BNC ? kofs(bk, B_STEP, r) : bk));
     };
     // Ragged last slab: k clamped into the operand (entries at or past ke are
     // zeroed by the store).
@@ -313,12 +321,12 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
         asm volatile("" : "+v"(ai), "+v"(bj));
 #pragma unroll
         for (int r = 0; r < EA; r++) {
-            const int64_t kk = k0 + ak + (AMC ? r * A_STEP : 0);
+            const int64_t kk = k0 + (AMC ? kofs(ak, A_STEP, r) : ak);
             ra[r] = ld_a(r, ai, kk < kmax ? kk : kmax);
         }
 #pragma unroll
         for (int r = 0; r < EB; r++) {
-            const int64_t kk = k0 + bk + (BNC ? r * B_STEP : 0);
+            const int64_t kk = k0 + (BNC ? kofs(bk, B_STEP, r) : bk);
             rb[r] = ld_b(r, bj, kk < kmax ? kk : kmax);
         }
     };
@@ -326,7 +334,7 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
 #pragma unroll
         for (int r = 0; r < EA; r++) {
             const int64_t i = i0 + a_i + (AMC ? 0 : r * A_STEP);
-            const int64_t kk = k0 + a_k + (AMC ? r * A_STEP : 0);
+            const int64_t kk = k0 + (AMC ? kofs(a_k, A_STEP, r) : a_k);
             const int64_t d = kk - i;
             const bool ok = i < m && kk < ke && d >= ba.lo && d <= ba.hi;
             ra[r] = ok ? ra[r] : T(0);
@@ -336,7 +344,7 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
 #pragma unroll
         for (int r = 0; r < EB; r++) {
             const int64_t j = j0 + b_j + (BNC ? 0 : r * B_STEP);
-            const int64_t kk = k0 + b_k + (BNC ? r * B_STEP : 0);
+            const int64_t kk = k0 + (BNC ? kofs(b_k, B_STEP, r) : b_k);
             const int64_t d = kk - j;
             const bool ok = j < n && kk < ke && d >= bb.lo && d <= bb.hi;
             rb[r] = ok ? rb[r] : T(0);
@@ -346,15 +354,37 @@ __global__ __launch_bounds__(NTH, (WMB * WNB >= 16) ? 1 : 2) void gemm_kernel(Ge
         // uniform per workgroup: the masks run only where a tile needs them
         if (tail || !a_all_rows || !a_nomask) mask_a(k0);
         if (tail || !b_all_rows || !b_nomask) mask_b(k0);
+        if constexpr (PACK && AMC) {
+            typedef LT v8t __attribute__((ext_vector_type(8)));
 #pragma unroll
-        for (int r = 0; r < EA; r++) {
-            if (AMC) As[buf][a_i][a_k + r * A_STEP] = to_lds<LP>(ra[r]);
-            else As[buf][a_i + r * A_STEP][a_k] = to_lds<LP>(ra[r]);
+            for (int q = 0; q < EA / 8; q++) {
+                v8t v;
+#pragma unroll
+                for (int e = 0; e < 8; e++) v[e] = to_lds<LP>(ra[8 * q + e]);
+                *reinterpret_cast<v8t*>(&As[buf][a_i][8 * (a_k + A_STEP * q)]) = v;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < EA; r++) {
+                if (AMC) As[buf][a_i][a_k + r * A_STEP] = to_lds<LP>(ra[r]);
+                else As[buf][a_i + r * A_STEP][a_k] = to_lds<LP>(ra[r]);
+            }
         }
+        if constexpr (PACK && BNC) {
+            typedef LT v8t __attribute__((ext_vector_type(8)));
 #pragma unroll
-        for (int r = 0; r < EB; r++) {
-            if (BNC) Bs[buf][b_j][b_k + r * B_STEP] = to_lds<LP>(rb[r]);
-            else Bs[buf][b_j + r * B_STEP][b_k] = to_lds<LP>(rb[r]);
+            for (int q = 0; q < EB / 8; q++) {
+                v8t v;
+#pragma unroll
+                for (int e = 0; e < 8; e++) v[e] = to_lds<LP>(rb[8 * q + e]);
+                *reinterpret_cast<v8t*>(&Bs[buf][b_j][8 * (b_k + B_STEP * q)]) = v;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < EB; r++) {
+                if (BNC) Bs[buf][b_j][b_k + r * B_STEP] = to_lds<LP>(rb[r]);
+                else Bs[buf][b_j + r * B_STEP][b_k] = to_lds<LP>(rb[r]);
+            }
         }
     };
 
